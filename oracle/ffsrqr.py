@@ -1,0 +1,431 @@
+"""Plain FP64 CPU oracle of the Flip-Flop SRQR hot path.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import or run anything under ``oracle/``.
+It shares no code with the GPU library and never imports it.
+
+Every step follows the paper's text in the paper's order, written for a reader
+to check by eye; numpy matmul is used as a library primitive and nothing is
+blocked, fused or reordered.  All arithmetic is FP64.
+
+Steps (Feng, Xiao & Gu, "Low-Rank Matrix Approximations with Flip-Flop
+Spectrum-Revealing QR Factorization"):
+
+  sketch       Algorithm 2 (TRQRCP), first two steps: B = Omega A.
+  qrcp_sketch  Algorithm 1 (Partial QRCP) run for l steps on B; pivots only.
+  qr_panel     Householder QR without pivoting of A(:, S) (Algorithm 2, the
+               "QR on the pivoted block" step; compact-WY form in Section 2.1),
+               returned as explicit Q1 and R11.
+  project      R = Q1^T A Pi: the (R11 R12) block of the partial QR
+               factorization (Section 2.1, block form; Section 3.1, partial
+               QRCP on A to l steps).
+  srqr_rho     g2 of Section 2.2 (definitions of R-tilde, g1, g2), computed
+               exactly (no random probe).
+  ffsrqr       Algorithm 4 (SRQR) swap loop around the above, then Section
+               3.1: QR without pivoting of (R11 R12)^T, L = Rhat11^T,
+               V = Pi Qhat1, and sigma(L) by one-sided Jacobi.
+
+Readings of the paper taken here (each is listed with its reason in the
+design notes):
+  * Omega has l = min(k+p, m, n) rows and QRCP on B runs all l steps (one
+    block: the block size b only tiles work, it does not change results).
+  * Column norms on B are recomputed from scratch at every step (no
+    downdating), ties go to the smallest original column index.
+  * Residual norms gamma_j of the trailing columns are exact,
+    ||(I - Q1 Q1^T) a_j||, not the sketch estimate of Algorithm 4.
+  * g2 is exact: |alpha| * max row norm of R-tilde^{-1}.
+  * A swap (Algorithm 4's round-robin rotation) replaces S[i*] by j*: the new
+    ordered leading set is S without S[i*], followed by j*.  The factorization
+    of the new set is recomputed from scratch instead of Givens updates; thin
+    QR is unique up to row signs, and signs are normalised.
+  * The swap loop is capped at max_swaps (default 4 l); the flag SWAPCAP
+    records when the cap stops it.
+  * Outputs are normalised to diag(R11) > 0 and diag(L) >= 0.
+  * sigma_j := sigma_j(L), L the whole l x l factor.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+from .philox import omega as _omega
+
+FLAG_RANK_DEFICIENT = 1
+FLAG_SWAPCAP = 2
+FLAG_NONFINITE = 4
+FLAG_L_CLAMPED = 8
+
+
+# ---------------------------------------------------------------------------
+# Householder reflector (LAPACK xLARFG convention)
+# ---------------------------------------------------------------------------
+def _norm2(x: np.ndarray) -> float:
+    """Euclidean norm, scaled by max |x_i| so that tiny entries do not underflow."""
+    s = float(np.max(np.abs(x))) if x.size else 0.0
+    if s == 0.0 or not math.isfinite(s):
+        return s
+    y = x / s
+    return s * math.sqrt(float(y @ y))
+
+
+def householder(x: np.ndarray):
+    """Reflector H = I - tau v v^T with v[0] = 1 and H x = beta e_1.
+
+    beta = -sign(x[0]) ||x|| (sign(0) = +), tau = (beta - x[0]) / beta.
+    When x[1:] is zero, H = I (tau = 0, beta = x[0]).
+    """
+    alpha = float(x[0])
+    xnorm = _norm2(x[1:]) if x.shape[0] > 1 else 0.0
+    v = np.zeros_like(x, dtype=np.float64)
+    v[0] = 1.0
+    if xnorm == 0.0:
+        return v, 0.0, alpha
+    beta = -math.copysign(math.hypot(alpha, xnorm), alpha)
+    tau = (beta - alpha) / beta
+    v[1:] = x[1:] / (alpha - beta)
+    return v, tau, beta
+
+
+# ---------------------------------------------------------------------------
+# a1: sketch
+# ---------------------------------------------------------------------------
+def omega(seed: int, l: int, m: int) -> np.ndarray:
+    return _omega(seed, l, m)
+
+
+def sketch(Omega: np.ndarray, A: np.ndarray) -> np.ndarray:
+    """B = Omega A (Algorithm 2: form the initial sample matrix)."""
+    return Omega @ np.asarray(A, dtype=np.float64)
+
+
+# ---------------------------------------------------------------------------
+# a2: partial QRCP on the sketch
+# ---------------------------------------------------------------------------
+def qrcp_sketch(B: np.ndarray, l: int):
+    """Algorithm 1 (Partial QRCP) on B for l steps.
+
+    Returns (perm, margins, Bout): perm is the full column order (the first l
+    entries are the pivots in the order chosen, the rest is where the swaps
+    left them), margins[j] = (r_max - r_second) / r_max at step j, and Bout
+    the transformed B (upper trapezoidal in its leading l columns).
+    """
+    B = np.array(B, dtype=np.float64, copy=True)
+    rows, n = B.shape
+    perm = np.arange(n)
+    margins = np.zeros(l)
+    for j in range(l):
+        # residual column norms of the trailing matrix, recomputed from scratch
+        r = np.sum(B[j:, j:] ** 2, axis=0)
+        rmax = r.max()
+        cands = np.flatnonzero(r == rmax)
+        s = int(cands[np.argmin(perm[j + cands])])       # tie -> smallest original index
+        if r.shape[0] > 1:
+            rest = np.delete(r, s)
+            margins[j] = (rmax - rest.max()) / rmax if rmax > 0 else 0.0
+        else:
+            margins[j] = 1.0
+        # exchange columns j and j+s in B and Pi
+        if s:
+            B[:, [j, j + s]] = B[:, [j + s, j]]
+            perm[[j, j + s]] = perm[[j + s, j]]
+        if j < rows:
+            v, tau, beta = householder(B[j:, j])
+            if j + 1 < n and tau != 0.0:
+                w = v @ B[j:, j + 1:]
+                B[j:, j + 1:] -= tau * np.outer(v, w)
+            B[j, j] = beta
+            B[j + 1:, j] = 0.0
+    return perm, margins, B
+
+
+# ---------------------------------------------------------------------------
+# a3: Householder QR (no pivoting) of a tall panel, explicit Q1
+# ---------------------------------------------------------------------------
+def householder_qr(P: np.ndarray):
+    """Householder QR of P (m x c), m >= c: P = Q1 R, Q1 explicit (m x c).
+
+    Reflectors are applied one column at a time (Algorithm 1 without the
+    pivot search); Q1 = H_1 ... H_c [I; 0] is accumulated backwards.
+    Signs are normalised so that diag(R) >= 0.
+    """
+    W = np.array(P, dtype=np.float64, copy=True)
+    m, c = W.shape
+    if m < c:
+        raise ValueError("householder_qr needs a tall panel")
+    vs, taus = [], []
+    for j in range(c):
+        v, tau, beta = householder(W[j:, j])
+        if j + 1 < c and tau != 0.0:
+            W[j:, j + 1:] -= tau * np.outer(v, v @ W[j:, j + 1:])
+        W[j, j] = beta
+        W[j + 1:, j] = 0.0
+        vs.append(v)
+        taus.append(tau)
+    R = np.triu(W[:c, :])
+    Q = np.zeros((m, c))
+    Q[:c, :c] = np.eye(c)
+    for j in range(c - 1, -1, -1):
+        # H_j only touches rows j:, and columns < j of the partial product are
+        # still e_i there (zero in rows j:), so only Q[j:, j:] changes.
+        v, tau = vs[j], taus[j]
+        if tau != 0.0:
+            Q[j:, j:] -= tau * np.outer(v, v @ Q[j:, j:])
+    d = np.where(np.diag(R) < 0, -1.0, 1.0)
+    return Q * d, R * d[:, None]
+
+
+# ---------------------------------------------------------------------------
+# a4: projection and residual norms
+# ---------------------------------------------------------------------------
+def project(Q1: np.ndarray, A: np.ndarray) -> np.ndarray:
+    """W = Q1^T A for every column of A, in the original column order."""
+    return Q1.T @ np.asarray(A, dtype=np.float64)
+
+
+def residual_norms(A: np.ndarray, Q1: np.ndarray, W: np.ndarray, cols) -> np.ndarray:
+    """gamma_j = ||a_j - Q1 W(:, j)|| for j in cols (exact, column by column)."""
+    A = np.asarray(A)
+    cols = np.asarray(cols)
+    out = np.empty(cols.shape[0])
+    step = 256
+    for s in range(0, cols.shape[0], step):
+        c = cols[s:s + step]
+        E = np.asarray(A[:, c], dtype=np.float64) - Q1 @ W[:, c]
+        out[s:s + step] = np.sqrt(np.sum(E * E, axis=0))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# a5: SRQR quantities
+# ---------------------------------------------------------------------------
+def back_substitute(U: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """Solve U x = b for upper-triangular U, one row at a time."""
+    n = U.shape[0]
+    x = np.zeros(n)
+    for i in range(n - 1, -1, -1):
+        x[i] = (b[i] - U[i, i + 1:] @ x[i + 1:]) / U[i, i]
+    return x
+
+
+def upper_inverse(U: np.ndarray) -> np.ndarray:
+    """Inverse of an upper-triangular matrix, column by column."""
+    n = U.shape[0]
+    X = np.zeros((n, n))
+    e = np.zeros(n)
+    for j in range(n):
+        e[:] = 0.0
+        e[j] = 1.0
+        X[: j + 1, j] = back_substitute(U[: j + 1, : j + 1], e[: j + 1])
+    return X
+
+
+def srqr_rho(R11: np.ndarray, a: np.ndarray, alpha: float) -> np.ndarray:
+    """rho_i = |alpha| * ||row i of R-tilde^{-1}||, i = 1..l+1 (Section 2.2).
+
+    R-tilde = [[R11, a], [0, alpha]] is the leading (l+1) x (l+1) block of R;
+    g2 = |alpha| ||R-tilde^{-T}||_{1,2} is the largest rho_i (the largest
+    column norm of R-tilde^{-T} is the largest row norm of R-tilde^{-1}).
+    """
+    l = R11.shape[0]
+    Rt = np.zeros((l + 1, l + 1))
+    Rt[:l, :l] = R11
+    Rt[:l, l] = a
+    Rt[l, l] = alpha
+    X = upper_inverse(Rt)
+    return abs(alpha) * np.sqrt(np.sum(X * X, axis=1))
+
+
+# ---------------------------------------------------------------------------
+# a6: flip-flop LQ and right factor
+# ---------------------------------------------------------------------------
+def flip_flop_lq(R: np.ndarray, perm: np.ndarray):
+    """QR without pivoting of R^T = (R11 R12)^T (Section 3.1).
+
+    Returns (L, Qhat1, V): L = Rhat11^T (lower triangular, diag >= 0),
+    Qhat1 (n x l) explicit, V = Pi Qhat1, i.e. V[perm[i], :] = Qhat1[i, :].
+    """
+    Qh, Rh = householder_qr(R.T)
+    L = Rh.T
+    V = np.empty_like(Qh)
+    V[np.asarray(perm), :] = Qh
+    return L, Qh, V
+
+
+# ---------------------------------------------------------------------------
+# a7: one-sided Jacobi singular values
+# ---------------------------------------------------------------------------
+def jacobi_svd(M: np.ndarray, tol: float = 1e-14, max_sweeps: int = 60,
+               want_vectors: bool = False):
+    """One-sided (Hestenes) Jacobi on the columns of M, cyclic by rows.
+
+    Each pair (p, q) with |c_p . c_q| > tol ||c_p|| ||c_q|| is rotated so that
+    the two columns become orthogonal (Rutishauser's formulas).  Stops after a
+    sweep with no rotation.  Returns sigma descending (and U, V if asked;
+    M V = U diag(sigma)).
+    """
+    G = np.array(M, dtype=np.float64, copy=True)
+    n = G.shape[1]
+    V = np.eye(n) if want_vectors else None
+    sweeps = 0
+    for sweeps in range(1, max_sweeps + 1):
+        rotated = False
+        for p in range(n - 1):
+            for q in range(p + 1, n):
+                cp = G[:, p]
+                cq = G[:, q]
+                a = float(cp @ cp)
+                b = float(cq @ cq)
+                g = float(cp @ cq)
+                if a == 0.0 or b == 0.0 or abs(g) <= tol * math.sqrt(a * b):
+                    continue
+                rotated = True
+                zeta = (b - a) / (2.0 * g)
+                t = math.copysign(1.0, zeta) / (abs(zeta) + math.sqrt(1.0 + zeta * zeta))
+                c = 1.0 / math.sqrt(1.0 + t * t)
+                s = c * t
+                new_p = c * cp - s * cq
+                new_q = s * cp + c * cq
+                G[:, p] = new_p
+                G[:, q] = new_q
+                if V is not None:
+                    vp = V[:, p].copy()
+                    vq = V[:, q].copy()
+                    V[:, p] = c * vp - s * vq
+                    V[:, q] = s * vp + c * vq
+        if not rotated:
+            break
+    norms = np.sqrt(np.sum(G * G, axis=0))
+    order = np.argsort(-norms, kind="stable")
+    sigma = norms[order]
+    if not want_vectors:
+        return sigma, sweeps
+    U = np.zeros_like(G)
+    nz = sigma > 0
+    U[:, nz] = G[:, order[nz]] / sigma[nz]
+    return sigma, U, V[:, order], sweeps
+
+
+# ---------------------------------------------------------------------------
+# The whole path
+# ---------------------------------------------------------------------------
+@dataclasses.dataclass
+class Result:
+    perm: np.ndarray        # [n] pivots first (in order), the rest ascending
+    Q: np.ndarray           # m x l, orthonormal columns, diag(R11) > 0
+    R: np.ndarray           # l x n = [R11 R12] in perm order
+    L: np.ndarray           # l x l lower triangular, diag >= 0
+    V: np.ndarray           # n x l, Pi Qhat1
+    sigma: np.ndarray       # [l] singular values of L, descending
+    l: int
+    swaps: int
+    g2: float               # g2 of the final leading set
+    alpha: float            # residual norm of the (l+1)-st column
+    jstar: int              # original index of that column
+    margins: np.ndarray     # QRCP-on-B margins per step
+    flags: int
+    numerical_rank: int
+    B: np.ndarray           # sketch (l x n)
+    history: list           # [(S, g2, jstar, alpha)] per SRQR test
+
+
+def _full_perm(S, n):
+    S = list(int(s) for s in S)
+    chosen = np.zeros(n, dtype=bool)
+    chosen[S] = True
+    rest = np.flatnonzero(~chosen)
+    return np.concatenate([np.asarray(S, dtype=np.int64), rest.astype(np.int64)])
+
+
+def factor_leading_set(A: np.ndarray, S):
+    """QR of A(:, S) and the projection for a given ordered leading set S."""
+    A = np.asarray(A)
+    n = A.shape[1]
+    perm = _full_perm(S, n)
+    P = np.asarray(A[:, perm[: len(S)]], dtype=np.float64)
+    Q1, R11 = householder_qr(P)
+    W = project(Q1, A)
+    R = W[:, perm]
+    R[:, : len(S)] = R11
+    return perm, Q1, R11, R, W
+
+
+def ffsrqr(A: np.ndarray, k: int, p: int, seed: int, g: float = 2.0,
+           max_swaps: int | None = None, Omega: np.ndarray | None = None) -> Result:
+    """Flip-Flop SRQR hot path, FP64 (Algorithm 9 up to the LQ, Algorithm 4 inside)."""
+    A = np.asarray(A)
+    m, n = A.shape
+    if not (1 <= k <= min(m, n)) or p < 0 or not g > 1.0:
+        raise ValueError("bad arguments")
+    flags = 0
+    l = min(k + p, m, n)
+    if l < k + p:
+        flags |= FLAG_L_CLAMPED
+    if max_swaps is None:
+        max_swaps = 4 * l
+    Af = np.asarray(A, dtype=np.float64)
+    if not np.all(np.isfinite(Af)):
+        # a non-finite entry poisons every step: report it, factor nothing
+        flags |= FLAG_NONFINITE
+        nan = np.nan
+        return Result(perm=np.arange(n, dtype=np.int64), Q=np.full((m, l), nan),
+                      R=np.full((l, n), nan), L=np.full((l, l), nan), V=np.full((n, l), nan),
+                      sigma=np.full(l, nan), l=l, swaps=0, g2=nan, alpha=nan, jstar=-1,
+                      margins=np.zeros(l), flags=flags, numerical_rank=0,
+                      B=np.full((l, n), nan), history=[])
+    colnorm = np.sqrt(np.sum(Af * Af, axis=0))
+    tau_r = max(m, n) * 2.0 ** -52 * float(colnorm.max())
+
+    # a1
+    Om = omega(seed, l, m) if Omega is None else Omega
+    B = sketch(Om, Af)
+    # a2
+    pivots, margins, _ = qrcp_sketch(B, l)
+    S = [int(s) for s in pivots[:l]]
+
+    swaps = 0
+    history = []
+    numerical_rank = l
+    while True:
+        # a3 + a4
+        perm, Q1, R11, R, W = factor_leading_set(Af, S)
+        # a5
+        if l < n:
+            trailing = perm[l:]
+            gam = residual_norms(Af, Q1, W, trailing)
+            gmax = gam.max()
+            cands = np.flatnonzero(gam == gmax)
+            jpos = int(cands[np.argmin(trailing[cands])])
+            jstar = int(trailing[jpos])
+            alpha = float(gmax)
+            dR = np.abs(np.diag(R11))
+            if alpha <= tau_r or dR.min() <= tau_r:
+                flags |= FLAG_RANK_DEFICIENT
+                numerical_rank = int(np.sum(dR > tau_r))
+                g2 = 1.0
+                history.append((list(S), g2, jstar, alpha))
+                break
+            rho = srqr_rho(R11, W[:, jstar], alpha)
+            g2 = float(rho.max())
+            history.append((list(S), g2, jstar, alpha))
+            if g2 <= g:
+                break
+            if swaps >= max_swaps:
+                flags |= FLAG_SWAPCAP
+                break
+            istar = int(np.argmax(rho[:l]))
+            S = S[:istar] + S[istar + 1:] + [jstar]
+            swaps += 1
+        else:
+            jstar, alpha, g2 = -1, 0.0, 1.0
+            history.append((list(S), g2, jstar, alpha))
+            break
+
+    # a6
+    L, Qhat1, V = flip_flop_lq(R, perm)
+    # a7
+    sigma, _ = jacobi_svd(L)
+    return Result(perm=perm, Q=Q1, R=R, L=L, V=V, sigma=sigma, l=l, swaps=swaps,
+                  g2=g2, alpha=alpha, jstar=jstar, margins=margins, flags=flags,
+                  numerical_rank=numerical_rank, B=B, history=history)

@@ -1,0 +1,122 @@
+"""Seeded synthetic inputs for the Flip-Flop SRQR hot path.
+
+Test and benchmark infrastructure. This module holds no step of the
+method: it only builds input matrices with prescribed singular spectra,
+shaped like the paper's test problems (Section 4.1, "Type 1" matrices
+U*D*V^T plus Gaussian noise).  Both the oracle and the GPU path consume the
+bytes it returns; neither imports the other.
+
+Recipes (all seeded, FP64 arithmetic, optionally rounded to FP32 storage):
+
+* ``spectrum_matrix(m, n, sigma, seed, noise)``:
+  A = U diag(sigma) V^T + noise * G, with U (m x r) and V (n x r) the
+  explicit Q factors of LAPACK Householder QR of i.i.d. N(0,1) matrices
+  (numpy.linalg.qr), G i.i.d. N(0,1), r = len(sigma).
+* named workloads:
+  - ``small_fp64``  : m=1000, n=800, sigma_j = j^-2 (r = 800),
+    k=20, p=10, sketch seed 0.
+  - ``mid``         : m=16384, n=8192, r=1024, sigma_j = exp(-j/50),
+    noise 1e-6, k=256, p=16, sketch seed 0.
+"""
+from __future__ import annotations
+
+import dataclasses
+import numpy as np
+
+__all__ = [
+    "Workload",
+    "WORKLOADS",
+    "spectrum_matrix",
+    "separated_columns_matrix",
+    "random_matrix",
+    "make_workload",
+]
+
+
+def _rng(seed: int, stream: int) -> np.random.Generator:
+    # One independent numpy generator per (seed, stream) pair.
+    return np.random.Generator(np.random.Philox(key=[int(seed), int(stream) + 1]))
+
+
+def _orthonormal(rows: int, cols: int, rng: np.random.Generator) -> np.ndarray:
+    g = rng.standard_normal((rows, cols))
+    q, r = np.linalg.qr(g)
+    # Fix the column signs so that the factor is a function of the seed only.
+    s = np.sign(np.diag(r))
+    s[s == 0] = 1.0
+    return q * s
+
+
+def spectrum_matrix(m: int, n: int, sigma, seed: int, noise: float = 0.0,
+                    dtype=np.float64) -> np.ndarray:
+    """A = U diag(sigma) V^T + noise*G, Fortran (column-major) order."""
+    sigma = np.asarray(sigma, dtype=np.float64)
+    r = sigma.shape[0]
+    if r > min(m, n):
+        raise ValueError("spectrum longer than min(m, n)")
+    u = _orthonormal(m, r, _rng(seed, 1))
+    v = _orthonormal(n, r, _rng(seed, 2))
+    a = np.asfortranarray((u * sigma) @ v.T)
+    if noise:
+        a += noise * _rng(seed, 3).standard_normal((m, n))
+    return np.asfortranarray(a.astype(dtype, copy=False))
+
+
+def separated_columns_matrix(m: int, n: int, seed: int, ratio: float = 1.5,
+                             dtype=np.float64) -> np.ndarray:
+    """Orthogonal columns whose norms are spaced by ``ratio``, in shuffled order.
+
+    With orthogonal columns the greedy pivot order is the descending-norm order,
+    so it is known in closed form (see ``column_norm_order``).
+    """
+    if n > m:
+        raise ValueError("need m >= n for orthogonal columns")
+    rng = _rng(seed, 4)
+    q = _orthonormal(m, n, rng)
+    norms = ratio ** (-np.arange(n, dtype=np.float64))
+    order = rng.permutation(n)
+    a = q * norms[order]
+    return np.asfortranarray(a.astype(dtype, copy=False))
+
+
+def random_matrix(m: int, n: int, seed: int, dtype=np.float64) -> np.ndarray:
+    """i.i.d. N(0,1) entries."""
+    a = _rng(seed, 5).standard_normal((m, n))
+    return np.asfortranarray(a.astype(dtype, copy=False))
+
+
+@dataclasses.dataclass(frozen=True)
+class Workload:
+    name: str
+    m: int
+    n: int
+    k: int
+    p: int
+    seed: int          # sketch (Omega) seed
+    fixture_seed: int  # seed of the matrix generator
+    spectrum: str
+    noise: float
+
+    @property
+    def l(self) -> int:
+        return min(self.k + self.p, self.m, self.n)
+
+    def sigma(self) -> np.ndarray:
+        if self.spectrum == "inv_square":
+            r = min(self.m, self.n)
+            return np.arange(1, r + 1, dtype=np.float64) ** -2.0
+        if self.spectrum == "exp50_r1024":
+            j = np.arange(1, 1025, dtype=np.float64)
+            return np.exp(-j / 50.0)
+        raise KeyError(self.spectrum)
+
+
+WORKLOADS = {
+    "small_fp64": Workload("small_fp64", 1000, 800, 20, 10, 0, 1, "inv_square", 0.0),
+    "mid": Workload("mid", 16384, 8192, 256, 16, 0, 2, "exp50_r1024", 1e-6),
+}
+
+
+def make_workload(name: str, dtype=np.float64) -> np.ndarray:
+    w = WORKLOADS[name]
+    return spectrum_matrix(w.m, w.n, w.sigma(), w.fixture_seed, w.noise, dtype=dtype)

@@ -1,0 +1,112 @@
+"""Planted mistakes: each mutant is the oracle's own source with one plausible
+slip (a dropped term, a wrong sign or index, a transposed operand).  The test
+compiles the mutant in the oracle's namespace, patches it in, and checks that
+at least one of the pins fails.  This shows that the pins can tell a wrong
+oracle from a right one.  Everything here runs on the CPU."""
+import inspect
+import sys
+import textwrap
+
+import numpy as np
+import pytest
+
+import oracle
+import test_oracle_linalg as LIN
+import test_oracle_path as PATH
+
+MOD = sys.modules["oracle.ffsrqr"]
+
+
+def _mutant(func, old, new):
+    src = textwrap.dedent(inspect.getsource(func))
+    assert src.count(old) >= 1, f"snippet not found in {func.__name__}: {old!r}"
+    src = src.replace(old, new, 1)
+    ns = dict(MOD.__dict__)
+    exec(compile(src, f"<mutant {func.__name__}>", "exec"), ns)
+    return ns[func.__name__]
+
+
+def _small():
+    import synth
+    w = synth.WORKLOADS["small_fp64"]
+    A = synth.make_workload("small_fp64")
+    return w, A, oracle.ffsrqr(A, w.k, w.p, w.seed)
+
+
+def _pins():
+    """The pins, run in order; returns the name of the first one that fails."""
+    checks = [
+        ("householder", lambda: [LIN.test_householder_maps_to_beta_e1(x) for x in
+                                 ([3.0, 4.0], [-3.0, 4.0, 12.0], [0.0, 1.0, 1.0])]),
+        ("qr_lapack", lambda: [LIN.test_householder_qr_matches_lapack(s) for s in ((50, 13), (300, 40))]),
+        ("qrcp_dgeqp3", lambda: LIN.test_qrcp_pivots_match_dgeqp3(3, (20, 300), 20)),
+        ("qrcp_ties", LIN.test_qrcp_ties_go_to_smallest_index),
+        ("rho_closed_form", LIN.test_srqr_rho_matches_block_inverse_closed_form),
+        ("backsub", LIN.test_upper_inverse_and_back_substitution),
+        ("jacobi_2x2", LIN.test_jacobi_2x2_closed_form),
+        ("jacobi_lapack", lambda: LIN.test_jacobi_matches_lapack_svd((30, 30), "gauss")),
+        ("full_rank", PATH.test_full_rank_reconstruction),
+        ("structure", lambda: PATH.test_small_outputs_structure(_small())),
+        ("bounds", lambda: PATH.test_singular_value_bounds(_small(), "small")),
+        ("kahan_swaps", PATH.test_srqr_swaps_kahan),
+        ("tight_g", PATH.test_tighter_g_swaps_until_satisfied),
+    ]
+    for name, fn in checks:
+        try:
+            with np.errstate(all="ignore"):
+                fn()
+        except Exception:          # an assertion or a crash both count as caught
+            return name
+    return None
+
+
+MUTANTS = [
+    # reflector
+    ("householder", "tau = (beta - alpha) / beta", "tau = (beta + alpha) / beta"),
+    ("householder", "v[1:] = x[1:] / (alpha - beta)", "v[1:] = x[1:] / (alpha + beta)"),
+    ("householder", "beta = -math.copysign(", "beta = math.copysign("),
+    # QRCP on the sketch
+    ("qrcp_sketch", "r = np.sum(B[j:, j:] ** 2, axis=0)", "r = np.sum(B[:, j:] ** 2, axis=0)"),
+    ("qrcp_sketch", "s = int(cands[np.argmin(perm[j + cands])])", "s = int(cands[np.argmax(perm[j + cands])])"),
+    ("qrcp_sketch", "B[j:, j + 1:] -= tau * np.outer(v, w)", "B[j:, j + 1:] -= np.outer(v, w)"),
+    ("qrcp_sketch", "perm[[j, j + s]] = perm[[j + s, j]]", "perm[[j, j + s]] = perm[[j, j + s]]"),
+    # Householder QR of the panel
+    ("householder_qr", "W[j:, j + 1:] -= tau * np.outer(v, v @ W[j:, j + 1:])",
+     "W[j:, j + 1:] -= 0.5 * tau * np.outer(v, v @ W[j:, j + 1:])"),
+    ("householder_qr", "for j in range(c - 1, -1, -1):", "for j in range(c):"),
+    ("householder_qr", "return Q * d, R * d[:, None]", "return Q, R * d[:, None]"),
+    # projection and residual norms
+    ("factor_leading_set", "R = W[:, perm]", "R = W[:, np.argsort(perm)]"),
+    ("residual_norms", "E = np.asarray(A[:, c], dtype=np.float64) - Q1 @ W[:, c]",
+     "E = np.asarray(A[:, c], dtype=np.float64) - Q1 @ W[:, c[::-1]]"),
+    # SRQR test
+    ("srqr_rho", "Rt[:l, l] = a", "Rt[:l, l] = 0.0 * a"),
+    ("srqr_rho", "Rt[l, l] = alpha", "Rt[l, l] = 1.0"),
+    ("srqr_rho", "np.sum(X * X, axis=1)", "np.sum(X * X, axis=0)"),
+    ("back_substitute", "x[i] = (b[i] - U[i, i + 1:] @ x[i + 1:]) / U[i, i]",
+     "x[i] = (b[i] + U[i, i + 1:] @ x[i + 1:]) / U[i, i]"),
+    ("ffsrqr", "S = S[:istar] + S[istar + 1:] + [jstar]", "S = S[:istar] + S[istar + 1:] + [S[istar]]"),
+    ("ffsrqr", "if g2 <= g:", "if True:"),
+    # flip-flop LQ
+    ("flip_flop_lq", "V[np.asarray(perm), :] = Qh", "V[:, :] = Qh"),
+    ("flip_flop_lq", "L = Rh.T", "L = Rh"),
+    # Jacobi
+    ("jacobi_svd", "new_p = c * cp - s * cq", "new_p = c * cp + s * cq"),
+    ("jacobi_svd", "zeta = (b - a) / (2.0 * g)", "zeta = (a - b) / (2.0 * g)"),
+    ("jacobi_svd", "for q in range(p + 1, n):", "for q in range(p + 2, n):"),
+]
+
+
+def test_unmutated_oracle_passes_every_pin():
+    assert _pins() is None
+
+
+@pytest.mark.parametrize("fname,old,new", MUTANTS, ids=[f"{m[0]}-{i}" for i, m in enumerate(MUTANTS)])
+def test_mutant_is_caught(monkeypatch, fname, old, new):
+    orig = getattr(MOD, fname)
+    mut = _mutant(orig, old, new)
+    monkeypatch.setattr(MOD, fname, mut)
+    if hasattr(oracle, fname) and getattr(oracle, fname) is orig:
+        monkeypatch.setattr(oracle, fname, mut)
+    caught = _pins()
+    assert caught is not None, f"no pin caught the mutant {fname}: {old!r} -> {new!r}"
