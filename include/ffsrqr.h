@@ -1,0 +1,233 @@
+/*
+ * ffsrqr.h - C ABI of the MI355X (gfx950) Flip-Flop SRQR hot path.
+ *
+ * Method: Feng, Xiao & Gu, "Low-Rank Matrix Approximations with Flip-Flop
+ * Spectrum-Revealing QR Factorization".  Given A (m x n), a target rank k and
+ * an oversampling size p, the library computes, with l = min(k+p, m, n):
+ *
+ *   Omega  l x m i.i.d. N(0,1)                    (Algorithm 2, first step)
+ *   B      = Omega A                              (Algorithm 2, sample matrix)
+ *   S      l pivots of partial QRCP on B          (Algorithm 1 applied to B)
+ *   Q1,R11 Householder QR of A(:, S)              (Algorithm 2, QR of the block;
+ *                                                  compact WY, Section 2.1)
+ *   R      = Q1^T A Pi = [R11 R12]                (partial QRCP block form,
+ *                                                  Sections 2.1 and 3.1)
+ *   g2     SRQR test and round-robin swaps        (Section 2.2, definitions of
+ *                                                  R-tilde, g1, g2; Algorithm 4)
+ *   L, V   QR without pivoting of R^T: R^T = Qhat1 Rhat11, L = Rhat11^T,
+ *          V = Pi Qhat1                           (Section 3.1, flip-flop step)
+ *   sigma  singular values of L                   (Section 3.1; Algorithm 9)
+ *
+ * so that A ~ Q1 L V^T, and the diagonal of L tracks the singular values.
+ *
+ * Conventions for every entry point:
+ *  - Matrices are column-major with an explicit leading dimension.
+ *  - Pointers named A, B, Q, R, L, V, W, omega, perm, cols, piv, margins,
+ *    anorm2, gamma2, sigma and work are DEVICE pointers (hipMalloc'd memory
+ *    of the current device); info and bytes are HOST pointers.
+ *  - The caller owns every buffer.  A is read-only.  No entry point allocates
+ *    device memory: scratch lives in the caller's workspace.
+ *  - precision: FFSRQR_FP64 means double storage and arithmetic everywhere;
+ *    FFSRQR_FP32 means float storage of A and of the float outputs (Q, L, V,
+ *    B, R, W), FP32 MFMA GEMMs and FP32 Householder panels, FP64 column
+ *    norms, residual norms, SRQR test and singular values.
+ *  - stream is a hipStream_t (NULL = the default stream).  Stage entry points
+ *    only enqueue work; ffsrqr_factor synchronises the stream once per SRQR
+ *    test (the swap decision is read back on the host) and on return.
+ *  - Errors: argument checks return FFSRQR_EINVAL, a too-small workspace
+ *    FFSRQR_EWORKSPACE, a HIP failure FFSRQR_EHIP, no usable gfx950 device
+ *    FFSRQR_ENODEV; nothing is enqueued when a check fails.
+ *    ffsrqr_last_error() returns a thread-local message for the last failure.
+ *    Conditions found on the device are reported through ffsrqr_info.flags.
+ *  - Calls on one workspace must not overlap; distinct workspaces may be used
+ *    concurrently on distinct streams.
+ */
+#ifndef FFSRQR_H
+#define FFSRQR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* ffsrqr_stream_t; /* the same type as hipStream_t */
+
+typedef enum {
+  FFSRQR_OK = 0,
+  FFSRQR_EINVAL = 1,
+  FFSRQR_EWORKSPACE = 2,
+  FFSRQR_EHIP = 3,
+  FFSRQR_ENODEV = 4
+} ffsrqr_status;
+
+typedef enum { FFSRQR_FP64 = 0, FFSRQR_FP32 = 1 } ffsrqr_precision;
+
+/* ffsrqr_info.flags bits */
+enum {
+  FFSRQR_FLAG_RANK_DEFICIENT = 1u, /* alpha or a diagonal of R11 <= max(m,n) eps max_j ||a_j|| */
+  FFSRQR_FLAG_SWAPCAP = 2u,        /* the swap loop stopped at max_swaps with g2 > g            */
+  FFSRQR_FLAG_NONFINITE = 4u,      /* A holds a NaN or Inf; outputs are NaN                     */
+  FFSRQR_FLAG_L_CLAMPED = 8u,      /* k + p > min(m, n); l was clamped to min(m, n)             */
+  FFSRQR_FLAG_TIMEOUT = 16u        /* a device-wide wait exceeded its spin limit (never expected) */
+};
+
+typedef struct {
+  int32_t precision; /* ffsrqr_precision                                          */
+  int32_t max_swaps; /* cap of the SRQR swap loop; < 0 selects the default 4*l     */
+  double g;          /* SRQR tolerance for g2 (Section 2.2: g > 1, e.g. 2.0);
+                        0 selects 2.0                                             */
+} ffsrqr_opts;
+
+typedef struct {
+  int64_t l;              /* number of QR steps, min(k+p, m, n)                    */
+  int32_t swaps;          /* SRQR swaps performed                                  */
+  uint32_t flags;         /* FFSRQR_FLAG_* bits                                    */
+  double g2;              /* g2 of the final leading set (1 when rank deficient)   */
+  double alpha;           /* largest residual column norm of the trailing columns  */
+  int64_t jstar;          /* original index of that column (-1 when l == n)        */
+  int64_t numerical_rank; /* l unless RANK_DEFICIENT                               */
+  double min_margin;      /* min over QRCP-on-B steps of (r_max - r_2nd) / r_max   */
+} ffsrqr_info;
+
+/* Default options: FP64, g = 2, max_swaps = 4 l. */
+void ffsrqr_default_opts(ffsrqr_opts* opts);
+
+/* Text of a status code (static storage). */
+const char* ffsrqr_status_string(ffsrqr_status s);
+
+/* Thread-local description of the last failure in this thread ("" if none). */
+const char* ffsrqr_last_error(void);
+
+/*
+ * Workspace size in bytes (written to *bytes, a host pointer) that is enough
+ * for ffsrqr_factor and for every stage entry point on a problem of the
+ * given dimensions.  Pure host computation; needs no device.
+ * Errors: FFSRQR_EINVAL for m, n < 1, k < 1, k > min(m, n), p < 0, a NULL
+ * bytes pointer or an unknown precision.
+ */
+ffsrqr_status ffsrqr_workspace_size(int64_t m, int64_t n, int64_t k, int64_t p,
+                                    const ffsrqr_opts* opts, size_t* bytes);
+
+/*
+ * The whole hot path (Algorithm 9 up to the LQ, with Algorithm 4 inside).
+ *   A      m x n, lda >= m, element type per opts->precision.
+ *   k, p   target rank 1 <= k <= min(m, n) and oversampling p >= 0;
+ *          l = min(k + p, m, n) columns are factored.
+ *   seed   key of the Omega stream: Omega[i, t] = sqrt(-2 ln u1) cos(2 pi u2)
+ *          with (x0, x1, x2, x3) = Philox4x64-10(counter (t, i, 0, 0),
+ *          key (seed, 0)) and u = ((x >> 12) + 0.5) 2^-52 for x0 and x1.
+ *   perm   [n] int64: perm[0:l] the leading columns in order, then the other
+ *          columns in ascending order (Pi).
+ *   Q      m x l (ldq >= m): orthonormal columns, diag(R11) > 0.
+ *   L      l x l (ldl >= l): lower triangular, diag(L) >= 0.
+ *   V      n x l (ldv >= n): V = Pi Qhat1, orthonormal columns; A ~ Q L V^T.
+ *   sigma  [l] double: singular values of L, descending.
+ *   info   host pointer, filled on success (may be NULL).
+ *   work   device workspace of work_bytes >= ffsrqr_workspace_size(...).
+ * The call returns after the stream has completed the solve.
+ */
+ffsrqr_status ffsrqr_factor(const void* A, int64_t m, int64_t n, int64_t lda,
+                            int64_t k, int64_t p, uint64_t seed,
+                            int64_t* perm, void* Q, int64_t ldq, void* L, int64_t ldl,
+                            void* V, int64_t ldv, double* sigma, ffsrqr_info* info,
+                            void* work, size_t work_bytes, const ffsrqr_opts* opts,
+                            ffsrqr_stream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Stage entry points: one per step of the path, on the same conventions.
+ * Each enqueues its kernels on the stream and returns; the outputs are valid
+ * after the stream synchronises.  They let a caller (or a test) run and check
+ * one step at a time.  Their workspace must be at least
+ * ffsrqr_workspace_size(m, n, k, p, opts) for the dimensions involved.
+ * ------------------------------------------------------------------------- */
+
+/*
+ * Omega^T (Algorithm 2, first step): omega_t is m x l, ldo >= m, with
+ * omega_t[t + i*ldo] = Omega[i, t] from the stream documented above.
+ */
+ffsrqr_status ffsrqr_omega(uint64_t seed, int64_t l, int64_t m, void* omega_t, int64_t ldo,
+                           int32_t precision, ffsrqr_stream_t stream);
+
+/*
+ * Sketch (Algorithm 2, "form the initial sample matrix"): B = Omega A with
+ * Omega l x m from seed, B l x n (ldb >= l), and the column norms
+ * anorm2[j] = ||A(:, j)||^2 (FP64 accumulation, n doubles) in the same pass.
+ */
+ffsrqr_status ffsrqr_sketch(const void* A, int64_t m, int64_t n, int64_t lda, uint64_t seed,
+                            int64_t l, void* B, int64_t ldb, double* anorm2,
+                            void* work, size_t work_bytes, int32_t precision,
+                            ffsrqr_stream_t stream);
+
+/*
+ * Partial QRCP on the sketch (Algorithm 1 on B, l steps; l <= rows of B):
+ * at each step the trailing column with the largest residual norm (ties to
+ * the smallest original index) is chosen and a Householder reflector is
+ * applied to the remaining columns.  B (l x n, ldb) is read-only.
+ *   piv      [l] int64: the chosen original column indices, in order.
+ *   margins  [l] double: (r_max - r_second) / r_max at each step (1 when one
+ *            column is left).
+ */
+ffsrqr_status ffsrqr_qrcp(const void* B, int64_t l, int64_t n, int64_t ldb, int64_t* piv,
+                          double* margins, void* work, size_t work_bytes, int32_t precision,
+                          ffsrqr_stream_t stream);
+
+/*
+ * Householder QR without pivoting of the gathered columns A(:, cols[0:c])
+ * (Algorithm 2, QR of the pivoted block, compact WY of Section 2.1), c <= m:
+ *   Q  m x c (ldq >= m), explicit, orthonormal columns;
+ *   R  c x c (ldr >= c), upper triangular with diag(R) >= 0; A(:, cols) = Q R.
+ */
+ffsrqr_status ffsrqr_panel_qr(const void* A, int64_t m, int64_t n, int64_t lda,
+                              const int64_t* cols, int64_t c, void* Q, int64_t ldq,
+                              void* R, int64_t ldr, void* work, size_t work_bytes,
+                              int32_t precision, ffsrqr_stream_t stream);
+
+/*
+ * Projection (partial QR block form, Sections 2.1 and 3.1): W = Q^T A
+ * (c x n, ldw >= c) for every column of A in the original order, and the
+ * residual norms gamma2[j] = anorm2[j] - ||W(:, j)||^2 (FP64).
+ * Q is m x c (ldq >= m).  anorm2 as returned by ffsrqr_sketch.
+ */
+ffsrqr_status ffsrqr_project(const void* Q, int64_t m, int64_t c, int64_t ldq,
+                             const void* A, int64_t n, int64_t lda, void* W, int64_t ldw,
+                             const double* anorm2, double* gamma2, void* work,
+                             size_t work_bytes, int32_t precision, ffsrqr_stream_t stream);
+
+/*
+ * SRQR test (Section 2.2, definitions of R-tilde and g2; Algorithm 4):
+ *   R11    l x l upper triangular (ldr >= l), FP64 or FP32 per precision;
+ *   a      [l] the column R(:, j*) (same element type);
+ *   alpha  the residual norm of column j* (> 0).
+ * Writes rho[0:l] (FP64): rho_i = |alpha| ||row i of R-tilde^{-1}||, so that
+ * g2 = max(1, max_i rho_i) and the swap candidate is argmax_i rho_i.
+ */
+ffsrqr_status ffsrqr_srqr_rho(const void* R11, int64_t l, int64_t ldr, const void* a,
+                              double alpha, double* rho, void* work, size_t work_bytes,
+                              int32_t precision, ffsrqr_stream_t stream);
+
+/*
+ * Flip-flop LQ (Section 3.1): QR without pivoting of R^T, R = [R11 R12]
+ * l x n (ldr >= l) in Pi order: R^T = Qhat1 Rhat11.
+ *   L  l x l (ldl >= l) = Rhat11^T, lower triangular, diag(L) >= 0;
+ *   V  n x l (ldv >= n) = Pi Qhat1: V(perm[i], :) = Qhat1(i, :).
+ */
+ffsrqr_status ffsrqr_lq(const void* R, int64_t l, int64_t n, int64_t ldr, const int64_t* perm,
+                        void* L, int64_t ldl, void* V, int64_t ldv, void* work,
+                        size_t work_bytes, int32_t precision, ffsrqr_stream_t stream);
+
+/*
+ * Singular values of L (l x l, ldl >= l, FP64 or FP32 per precision) by
+ * one-sided Jacobi in FP64 (Algorithm 9 asks for the SVD of the small
+ * factor); sigma[0:l] descending.
+ */
+ffsrqr_status ffsrqr_svd_small(const void* L, int64_t l, int64_t ldl, double* sigma,
+                               void* work, size_t work_bytes, int32_t precision,
+                               ffsrqr_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FFSRQR_H */

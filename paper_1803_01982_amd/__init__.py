@@ -1,0 +1,16 @@
+"""MI355X (gfx950) Flip-Flop SRQR hot path.
+
+Python binding over libffsrqr.so (C ABI: include/ffsrqr.h).  Build the
+library with ``python -m paper_1803_01982_amd.build``; importing works without
+it, and the first call raises ``LibraryMissing`` if it is absent.
+"""
+from ._lib import (FLAG_L_CLAMPED, FLAG_NONFINITE, FLAG_RANK_DEFICIENT, FLAG_SWAPCAP, FLAG_TIMEOUT, FP32, FP64,
+                   FfsrqrError, LibraryMissing, load)
+from .api import (Factorization, empty_fortran, factor, fortran, lq, omega, panel_qr, project, qrcp, sketch,
+                  srqr_rho, svd_small, workspace, workspace_size)
+
+__all__ = [
+    "FLAG_L_CLAMPED", "FLAG_NONFINITE", "FLAG_RANK_DEFICIENT", "FLAG_SWAPCAP", "FLAG_TIMEOUT", "FP32", "FP64",
+    "FfsrqrError", "LibraryMissing", "load", "Factorization", "empty_fortran", "factor", "fortran", "lq", "omega",
+    "panel_qr", "project", "qrcp", "sketch", "srqr_rho", "svd_small", "workspace", "workspace_size",
+]

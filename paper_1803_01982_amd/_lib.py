@@ -1,0 +1,92 @@
+"""ctypes declarations of libffsrqr.so (the C ABI in include/ffsrqr.h).
+
+Loading fails loudly when the library has not been built: there is no
+fallback implementation of any step.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libffsrqr.so")
+
+FFSRQR_OK, FFSRQR_EINVAL, FFSRQR_EWORKSPACE, FFSRQR_EHIP, FFSRQR_ENODEV = range(5)
+FP64, FP32 = 0, 1
+FLAG_RANK_DEFICIENT, FLAG_SWAPCAP, FLAG_NONFINITE, FLAG_L_CLAMPED, FLAG_TIMEOUT = 1, 2, 4, 8, 16
+
+
+class LibraryMissing(RuntimeError):
+    pass
+
+
+class Opts(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("max_swaps", C.c_int32), ("g", C.c_double)]
+
+
+class Info(C.Structure):
+    _fields_ = [("l", C.c_int64), ("swaps", C.c_int32), ("flags", C.c_uint32), ("g2", C.c_double),
+                ("alpha", C.c_double), ("jstar", C.c_int64), ("numerical_rank", C.c_int64),
+                ("min_margin", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_P = C.c_void_p
+_I64 = C.c_int64
+_I32 = C.c_int32
+_SZ = C.c_size_t
+_U64 = C.c_uint64
+_D = C.c_double
+
+SIGNATURES = {
+    "ffsrqr_default_opts": (None, [C.POINTER(Opts)]),
+    "ffsrqr_status_string": (C.c_char_p, [C.c_int]),
+    "ffsrqr_last_error": (C.c_char_p, []),
+    "ffsrqr_workspace_size": (C.c_int, [_I64, _I64, _I64, _I64, C.POINTER(Opts), C.POINTER(_SZ)]),
+    "ffsrqr_factor": (C.c_int, [_P, _I64, _I64, _I64, _I64, _I64, _U64, _P, _P, _I64, _P, _I64, _P, _I64, _P,
+                                C.POINTER(Info), _P, _SZ, C.POINTER(Opts), _P]),
+    "ffsrqr_omega": (C.c_int, [_U64, _I64, _I64, _P, _I64, _I32, _P]),
+    "ffsrqr_sketch": (C.c_int, [_P, _I64, _I64, _I64, _U64, _I64, _P, _I64, _P, _P, _SZ, _I32, _P]),
+    "ffsrqr_qrcp": (C.c_int, [_P, _I64, _I64, _I64, _P, _P, _P, _SZ, _I32, _P]),
+    "ffsrqr_panel_qr": (C.c_int, [_P, _I64, _I64, _I64, _P, _I64, _P, _I64, _P, _I64, _P, _SZ, _I32, _P]),
+    "ffsrqr_project": (C.c_int, [_P, _I64, _I64, _I64, _P, _I64, _I64, _P, _I64, _P, _P, _P, _SZ, _I32, _P]),
+    "ffsrqr_srqr_rho": (C.c_int, [_P, _I64, _I64, _P, _D, _P, _P, _SZ, _I32, _P]),
+    "ffsrqr_lq": (C.c_int, [_P, _I64, _I64, _I64, _P, _P, _I64, _P, _I64, _P, _SZ, _I32, _P]),
+    "ffsrqr_svd_small": (C.c_int, [_P, _I64, _I64, _P, _P, _SZ, _I32, _P]),
+}
+
+_lib = None
+
+
+def load() -> C.CDLL:
+    """Load libffsrqr.so (once) and declare every entry point."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise LibraryMissing(
+            f"{LIB_PATH} is missing: build it with `python -m paper_1803_01982_amd.build` "
+            "(there is no fallback implementation)")
+    lib = C.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class FfsrqrError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        lib = load()
+        msg = lib.ffsrqr_last_error().decode()
+        text = lib.ffsrqr_status_string(status).decode()
+        super().__init__(f"{where}: {text} ({status}): {msg}")
+        self.status = status
+
+
+def check(status: int, where: str) -> None:
+    if status != FFSRQR_OK:
+        raise FfsrqrError(status, where)

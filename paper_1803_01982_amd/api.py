@@ -1,0 +1,209 @@
+"""Python binding of the C ABI: the same names, argument marshalling only.
+
+Matrices are column-major torch tensors on the current HIP device: a (rows x
+cols) tensor with strides (1, ld).  ``fortran(t)`` makes one.  Every step of
+the method runs in libffsrqr.so; torch only allocates device memory and
+provides the current stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+
+import torch
+
+from . import _lib as L
+
+_WORK: dict = {}
+
+
+def fortran(t: torch.Tensor) -> torch.Tensor:
+    """Column-major copy (strides (1, rows)) of a 2-D tensor."""
+    return t.t().contiguous().t()
+
+
+def empty_fortran(rows: int, cols: int, dtype, device) -> torch.Tensor:
+    return torch.empty((cols, rows), dtype=dtype, device=device).t()
+
+
+def _ld(t: torch.Tensor) -> int:
+    if t.dim() != 2:
+        raise ValueError("expected a 2-D tensor")
+    rows, cols = t.shape
+    if t.stride(0) != 1 and rows > 1:
+        raise ValueError("expected a column-major tensor (stride(0) == 1); use fortran()")
+    return max(t.stride(1), rows, 1)
+
+
+def _prec(dtype) -> int:
+    if dtype == torch.float64:
+        return L.FP64
+    if dtype == torch.float32:
+        return L.FP32
+    raise TypeError(f"unsupported dtype {dtype}; use float64 or float32")
+
+
+def _stream(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _ptr(t) -> int:
+    return t.data_ptr() if t is not None else 0
+
+
+def opts(precision=L.FP64, g: float = 2.0, max_swaps: int = -1) -> L.Opts:
+    return L.Opts(precision=precision, max_swaps=max_swaps, g=g)
+
+
+def workspace_size(m: int, n: int, k: int, p: int, precision=L.FP64) -> int:
+    lib = L.load()
+    out = C.c_size_t(0)
+    o = opts(precision)
+    L.check(lib.ffsrqr_workspace_size(m, n, k, p, C.byref(o), C.byref(out)), "ffsrqr_workspace_size")
+    return out.value
+
+
+def workspace(nbytes: int, device) -> torch.Tensor:
+    """A cached device workspace of at least nbytes (grown on demand)."""
+    dev = torch.device(device)
+    key = (dev.type, dev.index)
+    w = _WORK.get(key)
+    if w is None or w.numel() < nbytes:
+        w = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        _WORK[key] = w
+    return w
+
+
+@dataclasses.dataclass
+class Factorization:
+    perm: torch.Tensor
+    Q: torch.Tensor
+    L: torch.Tensor
+    V: torch.Tensor
+    sigma: torch.Tensor
+    info: dict
+
+
+def factor(A: torch.Tensor, k: int, p: int, seed: int = 0, g: float = 2.0, max_swaps: int = -1,
+           work: torch.Tensor | None = None, stream=None) -> Factorization:
+    """ffsrqr_factor: A (m x n, column-major, float64 or float32) -> perm, Q, L, V, sigma, info."""
+    lib = L.load()
+    m, n = A.shape
+    lda = _ld(A)
+    prec = _prec(A.dtype)
+    l = min(k + p, m, n)
+    dev = A.device
+    perm = torch.empty(n, dtype=torch.int64, device=dev)
+    Q = empty_fortran(m, l, A.dtype, dev)
+    Lf = empty_fortran(l, l, A.dtype, dev)
+    V = empty_fortran(n, l, A.dtype, dev)
+    sigma = torch.empty(l, dtype=torch.float64, device=dev)
+    if work is None:
+        work = workspace(workspace_size(m, n, k, p, prec), dev)
+    info = L.Info()
+    o = opts(prec, g, max_swaps)
+    L.check(lib.ffsrqr_factor(_ptr(A), m, n, lda, k, p, seed, _ptr(perm), _ptr(Q), m, _ptr(Lf), l,
+                              _ptr(V), n, _ptr(sigma), C.byref(info), _ptr(work), work.numel(),
+                              C.byref(o), _stream(stream)), "ffsrqr_factor")
+    return Factorization(perm, Q, Lf, V, sigma, info.as_dict())
+
+
+def omega(seed: int, l: int, m: int, dtype=torch.float64, device="cuda", stream=None) -> torch.Tensor:
+    """ffsrqr_omega: Omega^T as an m x l column-major tensor."""
+    lib = L.load()
+    Ot = empty_fortran(m, l, dtype, device)
+    L.check(lib.ffsrqr_omega(seed, l, m, _ptr(Ot), m, _prec(dtype), _stream(stream)), "ffsrqr_omega")
+    return Ot
+
+
+def sketch(A: torch.Tensor, seed: int, l: int, work=None, stream=None):
+    """ffsrqr_sketch: (B = Omega A, anorm2)."""
+    lib = L.load()
+    m, n = A.shape
+    B = empty_fortran(l, n, A.dtype, A.device)
+    an = torch.empty(n, dtype=torch.float64, device=A.device)
+    if work is None:
+        work = workspace(workspace_size(m, n, l, 0, _prec(A.dtype)), A.device)
+    L.check(lib.ffsrqr_sketch(_ptr(A), m, n, _ld(A), seed, l, _ptr(B), l, _ptr(an), _ptr(work), work.numel(),
+                              _prec(A.dtype), _stream(stream)), "ffsrqr_sketch")
+    return B, an
+
+
+def qrcp(B: torch.Tensor, l: int | None = None, work=None, stream=None):
+    """ffsrqr_qrcp: (piv[l], margins[l]) of partial QRCP on B (l x n)."""
+    lib = L.load()
+    rows, n = B.shape
+    l = rows if l is None else l
+    piv = torch.empty(l, dtype=torch.int64, device=B.device)
+    mg = torch.empty(l, dtype=torch.float64, device=B.device)
+    if work is None:
+        work = workspace(workspace_size(max(rows, l), n, l, 0, _prec(B.dtype)), B.device)
+    L.check(lib.ffsrqr_qrcp(_ptr(B), l, n, _ld(B), _ptr(piv), _ptr(mg), _ptr(work), work.numel(),
+                            _prec(B.dtype), _stream(stream)), "ffsrqr_qrcp")
+    return piv, mg
+
+
+def panel_qr(A: torch.Tensor, cols: torch.Tensor, work=None, stream=None):
+    """ffsrqr_panel_qr: explicit (Q, R) of A(:, cols)."""
+    lib = L.load()
+    m, n = A.shape
+    c = cols.numel()
+    Q = empty_fortran(m, c, A.dtype, A.device)
+    R = empty_fortran(c, c, A.dtype, A.device)
+    if work is None:
+        work = workspace(workspace_size(m, n, min(c, m, n), 0, _prec(A.dtype)) + m * c * 8, A.device)
+    L.check(lib.ffsrqr_panel_qr(_ptr(A), m, n, _ld(A), _ptr(cols), c, _ptr(Q), m, _ptr(R), c, _ptr(work),
+                                work.numel(), _prec(A.dtype), _stream(stream)), "ffsrqr_panel_qr")
+    return Q, R
+
+
+def project(Q: torch.Tensor, A: torch.Tensor, anorm2: torch.Tensor, work=None, stream=None):
+    """ffsrqr_project: (W = Q^T A, gamma2)."""
+    lib = L.load()
+    m, c = Q.shape
+    n = A.shape[1]
+    W = empty_fortran(c, n, A.dtype, A.device)
+    g2 = torch.empty(n, dtype=torch.float64, device=A.device)
+    if work is None:
+        work = workspace(workspace_size(m, n, min(c, m, n), 0, _prec(A.dtype)), A.device)
+    L.check(lib.ffsrqr_project(_ptr(Q), m, c, _ld(Q), _ptr(A), n, _ld(A), _ptr(W), c, _ptr(anorm2), _ptr(g2),
+                               _ptr(work), work.numel(), _prec(A.dtype), _stream(stream)), "ffsrqr_project")
+    return W, g2
+
+
+def srqr_rho(R11: torch.Tensor, a: torch.Tensor, alpha: float, work=None, stream=None) -> torch.Tensor:
+    """ffsrqr_srqr_rho: rho[l] of R-tilde = [[R11, a], [0, alpha]]."""
+    lib = L.load()
+    l = R11.shape[0]
+    rho = torch.empty(l, dtype=torch.float64, device=R11.device)
+    if work is None:
+        work = workspace(8 * (l + 1) * l + (1 << 16), R11.device)
+    L.check(lib.ffsrqr_srqr_rho(_ptr(R11), l, _ld(R11), _ptr(a), float(alpha), _ptr(rho), _ptr(work),
+                                work.numel(), _prec(R11.dtype), _stream(stream)), "ffsrqr_srqr_rho")
+    return rho
+
+
+def lq(R: torch.Tensor, perm: torch.Tensor, work=None, stream=None):
+    """ffsrqr_lq: (L, V) with R^T = Qhat1 Rhat11, L = Rhat11^T, V = Pi Qhat1."""
+    lib = L.load()
+    l, n = R.shape
+    Lf = empty_fortran(l, l, R.dtype, R.device)
+    V = empty_fortran(n, l, R.dtype, R.device)
+    if work is None:
+        work = workspace(workspace_size(n, n, l, 0, _prec(R.dtype)) + n * l * 8, R.device)
+    L.check(lib.ffsrqr_lq(_ptr(R), l, n, _ld(R), _ptr(perm), _ptr(Lf), l, _ptr(V), n, _ptr(work), work.numel(),
+                          _prec(R.dtype), _stream(stream)), "ffsrqr_lq")
+    return Lf, V
+
+
+def svd_small(Lm: torch.Tensor, work=None, stream=None) -> torch.Tensor:
+    """ffsrqr_svd_small: singular values of L (descending, float64)."""
+    lib = L.load()
+    l = Lm.shape[0]
+    sig = torch.empty(l, dtype=torch.float64, device=Lm.device)
+    if work is None:
+        work = workspace(8 * (l * l + l) + (1 << 16), Lm.device)
+    L.check(lib.ffsrqr_svd_small(_ptr(Lm), l, _ld(Lm), _ptr(sig), _ptr(work), work.numel(), _prec(Lm.dtype),
+                                 _stream(stream)), "ffsrqr_svd_small")
+    return sig

@@ -1,0 +1,556 @@
+// C ABI of the gfx950 Flip-Flop SRQR library: argument checks, workspace
+// planning, the stage entry points and the whole path.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/ffsrqr.h"
+#include "kernels.hpp"
+
+namespace ffsrqr {
+
+namespace {
+
+thread_local std::string g_last_error;
+
+ffsrqr_status fail(ffsrqr_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+#define FF_HIP(call)                                                                           \
+  do {                                                                                         \
+    hipError_t e_ = (call);                                                                    \
+    if (e_ != hipSuccess)                                                                      \
+      return fail(FFSRQR_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));             \
+  } while (0)
+
+std::mutex g_dev_mu;
+DeviceInfo g_dev[64];
+
+bool valid_precision(int32_t p) { return p == FFSRQR_FP64 || p == FFSRQR_FP32; }
+size_t elem_size(int32_t p) { return p == FFSRQR_FP64 ? sizeof(double) : sizeof(float); }
+
+// Conservative device shape for sizing without touching a device.
+DeviceInfo sizing_device() {
+  DeviceInfo d;
+  d.num_cu = 512;
+  d.lds_max = 0;  // size the global-memory fallbacks too
+  d.coop = true;
+  d.gfx950 = true;
+  return d;
+}
+
+struct Layout {
+  int64_t l;
+  size_t bytes;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Persistent buffers of the whole path followed by one scratch region shared
+// by the stages (they run in stream order).
+template <typename T>
+size_t scratch_bytes(int64_t m, int64_t n, int64_t l, const DeviceInfo& d) {
+  size_t s = 0;
+  s = std::max(s, gemm_tn_scratch<T>(l, n, m, d.num_cu));
+  s = std::max(s, qrcp_scratch<T>(l, n, d));
+  s = std::max(s, tallqr_scratch<T>(m, l, d));
+  s = std::max(s, tallqr_scratch<T>(n, l, d));
+  s = std::max(s, srqr_scratch<T>(m, n, l));
+  s = std::max(s, jacobi_scratch<T>(l, d));
+  return s + 16 * 256;
+}
+
+template <typename T>
+size_t persistent_bytes(int64_t m, int64_t n, int64_t l) {
+  size_t b = 0;
+  b += align256(std::max<size_t>((size_t)m * l, (size_t)m * l) * sizeof(T));  // Omega^T, then the gathered panel
+  b += align256((size_t)l * n * sizeof(T));                                   // B, then R^T
+  b += align256((size_t)l * n * sizeof(T));                                   // W
+  b += align256((size_t)l * l * sizeof(T));                                   // R11
+  b += 2 * align256((size_t)n * sizeof(double));                              // anorm2, gamma2
+  b += 2 * align256((size_t)l * sizeof(double));                              // margins, rho
+  b += align256((size_t)l * sizeof(int64_t));                                 // S
+  b += align256((size_t)n);                                                   // inS
+  b += align256((size_t)((n + 1023) / 1024 + 1) * sizeof(int64_t));           // perm counts
+  b += align256(sizeof(SrqrState)) + align256(64 * sizeof(unsigned));         // state, error word
+  return b + 256;
+}
+
+template <typename T>
+size_t total_bytes(int64_t m, int64_t n, int64_t l, const DeviceInfo& d) {
+  return persistent_bytes<T>(m, n, l) + scratch_bytes<T>(m, n, l, d);
+}
+
+ffsrqr_status get_device(const DeviceInfo** out) {
+  int id = 0;
+  hipError_t e = hipGetDevice(&id);
+  if (e != hipSuccess) return fail(FFSRQR_ENODEV, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  if (id < 0 || id >= 64) return fail(FFSRQR_ENODEV, "device id out of range");
+  std::lock_guard<std::mutex> lk(g_dev_mu);
+  DeviceInfo& d = g_dev[id];
+  if (d.id != id) {
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, id);
+    if (e != hipSuccess) return fail(FFSRQR_ENODEV, std::string("hipGetDeviceProperties: ") + hipGetErrorString(e));
+    d.num_cu = prop.multiProcessorCount;
+    d.lds_max = prop.sharedMemPerBlock;
+    d.coop = prop.cooperativeLaunch != 0;
+    d.gfx950 = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0;
+    d.id = id;
+  }
+  if (!d.gfx950) return fail(FFSRQR_ENODEV, "the current device is not gfx950");
+  if (!d.coop) return fail(FFSRQR_ENODEV, "the current device has no cooperative launch");
+  *out = &d;
+  return FFSRQR_OK;
+}
+
+ffsrqr_status check_dims(int64_t m, int64_t n, int64_t k, int64_t p) {
+  if (m < 1 || n < 1) return fail(FFSRQR_EINVAL, "m and n must be >= 1");
+  if (k < 1 || k > std::min(m, n)) return fail(FFSRQR_EINVAL, "k must satisfy 1 <= k <= min(m, n)");
+  if (p < 0) return fail(FFSRQR_EINVAL, "p must be >= 0");
+  if (m > (int64_t(1) << 31) || n > (int64_t(1) << 31)) return fail(FFSRQR_EINVAL, "m and n must be < 2^31");
+  return FFSRQR_OK;
+}
+
+ffsrqr_opts resolve(const ffsrqr_opts* o, int64_t l) {
+  ffsrqr_opts r;
+  ffsrqr_default_opts(&r);
+  if (o) r = *o;
+  if (r.g == 0.0) r.g = 2.0;
+  if (r.max_swaps < 0) r.max_swaps = (int32_t)std::min<int64_t>(4 * l, INT32_MAX);
+  return r;
+}
+
+// --------------------------------------------------------------------------
+template <typename T>
+ffsrqr_status factor_impl(const T* A, int64_t m, int64_t n, int64_t lda, int64_t k, int64_t p, uint64_t seed,
+                          int64_t* perm, T* Q, int64_t ldq, T* L, int64_t ldl, T* V, int64_t ldv, double* sigma,
+                          ffsrqr_info* info, void* work, size_t work_bytes, const ffsrqr_opts& op,
+                          const DeviceInfo& d, hipStream_t s) {
+  const int64_t l = std::min(k + p, std::min(m, n));
+  uint32_t flags = (l < k + p) ? FFSRQR_FLAG_L_CLAMPED : 0u;
+  const size_t need = total_bytes<T>(m, n, l, d);
+  if (work_bytes < need)
+    return fail(FFSRQR_EWORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+
+  Arena ar{(char*)work, work_bytes, 0};
+  T* region1 = ar.take<T>((size_t)m * l);  // Omega^T, later the gathered panel
+  T* region2 = ar.take<T>((size_t)l * n);  // B, later R^T
+  T* W = ar.take<T>((size_t)l * n);
+  T* R11 = ar.take<T>((size_t)l * l);
+  double* anorm2 = ar.take<double>(n);
+  double* gamma2 = ar.take<double>(n);
+  double* margins = ar.take<double>(l);
+  double* rho = ar.take<double>(l);
+  int64_t* S = ar.take<int64_t>(l);
+  unsigned char* inS = ar.take<unsigned char>(n);
+  int64_t* cnt = ar.take<int64_t>((n + 1023) / 1024 + 1);
+  SrqrState* st = ar.take<SrqrState>(1);
+  unsigned* err = ar.take<unsigned>(64);
+  const size_t scratch_off = ar.used;
+  auto scratch = [&]() { return Arena{(char*)work, work_bytes, scratch_off}; };
+  if (!err) return fail(FFSRQR_EWORKSPACE, "workspace carving failed");
+
+  FF_HIP(zero_words(err, 64, s));
+  // a1: Omega and the sketch (one pass over A, column norms fused)
+  FF_HIP(launch_omega<T>(seed, l, m, region1, m, s));
+  {
+    Arena a = scratch();
+    FF_HIP(gemm_tn<T>(l, n, m, region1, m, A, lda, region2, l, anorm2, a, d.num_cu, s));
+  }
+  // non-finite input: report and stop before any pivoting
+  {
+    Arena a = scratch();
+    FF_HIP(hipMemsetAsync(inS, 0, (size_t)n, s));
+    FF_HIP(srqr_select<T>(anorm2, anorm2, inS, n, A, m, lda, Q, ldq, W, l, R11, l, 0, st, a, s));
+    SrqrState hs;
+    FF_HIP(hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, s));
+    FF_HIP(hipStreamSynchronize(s));
+    if (hs.nonfinite) {
+      flags |= FFSRQR_FLAG_NONFINITE;
+      const double qnan = std::nan("");
+      std::vector<double> nanv((size_t)l, qnan);
+      FF_HIP(hipMemcpyAsync(sigma, nanv.data(), (size_t)l * sizeof(double), hipMemcpyHostToDevice, s));
+      // NaN-fill Q, L, V column by column; perm = identity
+      std::vector<T> col((size_t)std::max(m, n), (T)qnan);
+      for (int64_t j = 0; j < l; ++j) {
+        FF_HIP(hipMemcpyAsync(Q + j * ldq, col.data(), (size_t)m * sizeof(T), hipMemcpyHostToDevice, s));
+        FF_HIP(hipMemcpyAsync(L + j * ldl, col.data(), (size_t)l * sizeof(T), hipMemcpyHostToDevice, s));
+        FF_HIP(hipMemcpyAsync(V + j * ldv, col.data(), (size_t)n * sizeof(T), hipMemcpyHostToDevice, s));
+      }
+      std::vector<int64_t> id((size_t)n);
+      for (int64_t j = 0; j < n; ++j) id[j] = j;
+      FF_HIP(hipMemcpyAsync(perm, id.data(), (size_t)n * sizeof(int64_t), hipMemcpyHostToDevice, s));
+      FF_HIP(hipStreamSynchronize(s));
+      if (info) {
+        std::memset(info, 0, sizeof(*info));
+        info->l = l;
+        info->flags = flags;
+        info->g2 = qnan;
+        info->alpha = qnan;
+        info->jstar = -1;
+      }
+      return FFSRQR_OK;
+    }
+  }
+  // a2: partial QRCP on the sketch -> S
+  {
+    Arena a = scratch();
+    FF_HIP(qrcp<T>(region2, l, n, l, S, margins, a, err, d, s));
+  }
+  std::vector<double> hmarg((size_t)l);
+  FF_HIP(hipMemcpyAsync(hmarg.data(), margins, (size_t)l * sizeof(double), hipMemcpyDeviceToHost, s));
+
+  int32_t swaps = 0;
+  SrqrState hs{};
+  double g2 = 1.0;
+  int64_t numerical_rank = l;
+  for (;;) {
+    // a3: Householder QR of A(:, S); a4: projection and residual norms
+    FF_HIP(build_perm(S, l, n, perm, inS, cnt, s));
+    FF_HIP(gather_cols<T>(A, m, n, lda, perm, l, region1, m, s));
+    {
+      Arena a = scratch();
+      FF_HIP(tall_qr<T>(region1, m, l, m, Q, ldq, nullptr, R11, l, false, a, err, d, s));
+    }
+    {
+      Arena a = scratch();
+      FF_HIP(gemm_tn<T>(l, n, m, Q, ldq, A, lda, W, l, nullptr, a, d.num_cu, s));
+    }
+    FF_HIP(residual_norms<T>(W, l, n, l, anorm2, gamma2, s));
+    // a5: SRQR test
+    {
+      Arena a = scratch();
+      FF_HIP(srqr_select<T>(gamma2, anorm2, inS, n, A, m, lda, Q, ldq, W, l, R11, l, l, st, a, s));
+    }
+    if (l < n) {
+      Arena a = scratch();
+      FF_HIP(srqr_rho<T>(R11, l, W, l, st, 0.0, l, rho, st, a, s));
+    }
+    // a6, a7 (issued before the swap decision is known; redone after a swap)
+    FF_HIP(assemble_rt<T>(R11, l, W, l, perm, l, n, region2, n, s));
+    {
+      Arena a = scratch();
+      FF_HIP(tall_qr<T>(region2, n, l, n, V, ldv, perm, L, ldl, true, a, err, d, s));
+    }
+    {
+      Arena a = scratch();
+      FF_HIP(jacobi_sigma<T>(L, l, ldl, sigma, a, err, d, s));
+    }
+    unsigned herr = 0;
+    FF_HIP(hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, s));
+    FF_HIP(hipMemcpyAsync(&herr, err, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+    FF_HIP(hipStreamSynchronize(s));
+    if (herr) {
+      flags |= FFSRQR_FLAG_TIMEOUT;
+      return fail(FFSRQR_EHIP, "a device-wide wait exceeded its spin limit");
+    }
+    if (l >= n) {
+      g2 = 1.0;
+      hs.jstar = -1;
+      hs.alpha = 0.0;
+      break;
+    }
+    const double tau_r = (double)std::max(m, n) * std::ldexp(1.0, -52) * hs.anorm_max;
+    if (hs.alpha <= tau_r || hs.min_diag <= tau_r) {
+      flags |= FFSRQR_FLAG_RANK_DEFICIENT;
+      std::vector<T> hr((size_t)l * l);
+      FF_HIP(hipMemcpy(hr.data(), R11, hr.size() * sizeof(T), hipMemcpyDeviceToHost));
+      numerical_rank = 0;
+      for (int64_t i = 0; i < l; ++i)
+        if (std::fabs((double)hr[(size_t)i * l + i]) > tau_r) ++numerical_rank;
+      g2 = 1.0;
+      break;
+    }
+    g2 = hs.g2;
+    if (g2 <= op.g) break;
+    if (swaps >= op.max_swaps) {
+      flags |= FFSRQR_FLAG_SWAPCAP;
+      break;
+    }
+    // round-robin swap: S <- (S without S[istar]) followed by jstar
+    std::vector<int64_t> hS((size_t)l);
+    FF_HIP(hipMemcpy(hS.data(), perm, (size_t)l * sizeof(int64_t), hipMemcpyDeviceToHost));
+    if (hs.istar < 0 || hs.istar >= l || hs.jstar < 0 || hs.jstar >= n)
+      return fail(FFSRQR_EHIP, "invalid swap candidates");
+    hS.erase(hS.begin() + hs.istar);
+    hS.push_back(hs.jstar);
+    FF_HIP(hipMemcpyAsync(S, hS.data(), (size_t)l * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    ++swaps;
+  }
+  if (info) {
+    double mm = 1.0;
+    for (double x : hmarg) mm = std::min(mm, x);
+    info->l = l;
+    info->swaps = swaps;
+    info->flags = flags;
+    info->g2 = g2;
+    info->alpha = hs.alpha;
+    info->jstar = hs.jstar;
+    info->numerical_rank = numerical_rank;
+    info->min_margin = mm;
+  }
+  return FFSRQR_OK;
+}
+
+}  // namespace
+}  // namespace ffsrqr
+
+namespace ffsrqr {
+namespace {
+template <typename T>
+ffsrqr_status sketch_impl(const T* A, int64_t m, int64_t n, int64_t lda, uint64_t seed, int64_t l, T* B, int64_t ldb,
+                          double* anorm2, void* work, size_t work_bytes, const DeviceInfo& d, hipStream_t s) {
+  Arena ar{(char*)work, work_bytes, 0};
+  T* Ot = ar.take<T>((size_t)m * l);
+  if (!Ot) return fail(FFSRQR_EWORKSPACE, "workspace too small");
+  FF_HIP(launch_omega<T>(seed, l, m, Ot, m, s));
+  hipError_t e = gemm_tn<T>(l, n, m, Ot, m, A, lda, B, ldb, anorm2, ar, d.num_cu, s);
+  if (e == hipErrorOutOfMemory) return fail(FFSRQR_EWORKSPACE, "workspace too small");
+  FF_HIP(e);
+  return FFSRQR_OK;
+}
+}  // namespace
+}  // namespace ffsrqr
+
+using namespace ffsrqr;
+
+extern "C" {
+
+void ffsrqr_default_opts(ffsrqr_opts* o) {
+  if (!o) return;
+  o->precision = FFSRQR_FP64;
+  o->max_swaps = -1;
+  o->g = 2.0;
+}
+
+const char* ffsrqr_status_string(ffsrqr_status s) {
+  switch (s) {
+    case FFSRQR_OK: return "ok";
+    case FFSRQR_EINVAL: return "invalid argument";
+    case FFSRQR_EWORKSPACE: return "workspace too small";
+    case FFSRQR_EHIP: return "HIP runtime error";
+    case FFSRQR_ENODEV: return "no usable gfx950 device";
+  }
+  return "unknown status";
+}
+
+const char* ffsrqr_last_error(void) { return g_last_error.c_str(); }
+
+ffsrqr_status ffsrqr_workspace_size(int64_t m, int64_t n, int64_t k, int64_t p, const ffsrqr_opts* opts,
+                                    size_t* bytes) {
+  if (!bytes) return fail(FFSRQR_EINVAL, "bytes is NULL");
+  ffsrqr_status st = check_dims(m, n, k, p);
+  if (st != FFSRQR_OK) return st;
+  const int32_t prec = opts ? opts->precision : FFSRQR_FP64;
+  if (!valid_precision(prec)) return fail(FFSRQR_EINVAL, "unknown precision");
+  const int64_t l = std::min(k + p, std::min(m, n));
+  const DeviceInfo d = sizing_device();
+  *bytes = prec == FFSRQR_FP64 ? total_bytes<double>(m, n, l, d) : total_bytes<float>(m, n, l, d);
+  return FFSRQR_OK;
+}
+
+ffsrqr_status ffsrqr_factor(const void* A, int64_t m, int64_t n, int64_t lda, int64_t k, int64_t p, uint64_t seed,
+                            int64_t* perm, void* Q, int64_t ldq, void* L, int64_t ldl, void* V, int64_t ldv,
+                            double* sigma, ffsrqr_info* info, void* work, size_t work_bytes,
+                            const ffsrqr_opts* opts, ffsrqr_stream_t stream) {
+  ffsrqr_status st = check_dims(m, n, k, p);
+  if (st != FFSRQR_OK) return st;
+  const int64_t l = std::min(k + p, std::min(m, n));
+  const ffsrqr_opts op = resolve(opts, l);
+  if (!valid_precision(op.precision)) return fail(FFSRQR_EINVAL, "unknown precision");
+  if (!(op.g > 1.0)) return fail(FFSRQR_EINVAL, "g must be > 1");
+  if (lda < m || ldq < m || ldl < l || ldv < n) return fail(FFSRQR_EINVAL, "leading dimension too small");
+  if (!A || !perm || !Q || !L || !V || !sigma || !work) return fail(FFSRQR_EINVAL, "NULL pointer argument");
+  const DeviceInfo* d = nullptr;
+  st = get_device(&d);
+  if (st != FFSRQR_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if (op.precision == FFSRQR_FP64)
+    return factor_impl<double>((const double*)A, m, n, lda, k, p, seed, perm, (double*)Q, ldq, (double*)L, ldl,
+                               (double*)V, ldv, sigma, info, work, work_bytes, op, *d, s);
+  return factor_impl<float>((const float*)A, m, n, lda, k, p, seed, perm, (float*)Q, ldq, (float*)L, ldl,
+                            (float*)V, ldv, sigma, info, work, work_bytes, op, *d, s);
+}
+
+ffsrqr_status ffsrqr_omega(uint64_t seed, int64_t l, int64_t m, void* omega_t, int64_t ldo, int32_t precision,
+                           ffsrqr_stream_t stream) {
+  if (l < 1 || m < 1 || ldo < m || !omega_t) return fail(FFSRQR_EINVAL, "bad omega arguments");
+  if (!valid_precision(precision)) return fail(FFSRQR_EINVAL, "unknown precision");
+  const DeviceInfo* d = nullptr;
+  ffsrqr_status st = get_device(&d);
+  if (st != FFSRQR_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if (precision == FFSRQR_FP64) FF_HIP(launch_omega<double>(seed, l, m, (double*)omega_t, ldo, s));
+  else FF_HIP(launch_omega<float>(seed, l, m, (float*)omega_t, ldo, s));
+  return FFSRQR_OK;
+}
+
+
+ffsrqr_status ffsrqr_sketch(const void* A, int64_t m, int64_t n, int64_t lda, uint64_t seed, int64_t l, void* B,
+                            int64_t ldb, double* anorm2, void* work, size_t work_bytes, int32_t precision,
+                            ffsrqr_stream_t stream) {
+  if (m < 1 || n < 1 || l < 1 || lda < m || ldb < l || !A || !B || !anorm2 || !work)
+    return fail(FFSRQR_EINVAL, "bad sketch arguments");
+  if (!valid_precision(precision)) return fail(FFSRQR_EINVAL, "unknown precision");
+  const DeviceInfo* d = nullptr;
+  ffsrqr_status st = get_device(&d);
+  if (st != FFSRQR_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if (precision == FFSRQR_FP64)
+    return sketch_impl<double>((const double*)A, m, n, lda, seed, l, (double*)B, ldb, anorm2, work, work_bytes, *d, s);
+  return sketch_impl<float>((const float*)A, m, n, lda, seed, l, (float*)B, ldb, anorm2, work, work_bytes, *d, s);
+}
+
+ffsrqr_status ffsrqr_qrcp(const void* B, int64_t l, int64_t n, int64_t ldb, int64_t* piv, double* margins, void* work,
+                          size_t work_bytes, int32_t precision, ffsrqr_stream_t stream) {
+  if (l < 1 || n < l || ldb < l || !B || !piv || !margins || !work) return fail(FFSRQR_EINVAL, "bad qrcp arguments");
+  if (!valid_precision(precision)) return fail(FFSRQR_EINVAL, "unknown precision");
+  const DeviceInfo* d = nullptr;
+  ffsrqr_status st = get_device(&d);
+  if (st != FFSRQR_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  Arena ar{(char*)work, work_bytes, 0};
+  unsigned* err = ar.take<unsigned>(64);
+  if (!err) return fail(FFSRQR_EWORKSPACE, "workspace too small");
+  FF_HIP(zero_words(err, 64, s));
+  hipError_t e = precision == FFSRQR_FP64
+                     ? qrcp<double>((const double*)B, l, n, ldb, piv, margins, ar, err, *d, s)
+                     : qrcp<float>((const float*)B, l, n, ldb, piv, margins, ar, err, *d, s);
+  if (e == hipErrorOutOfMemory) return fail(FFSRQR_EWORKSPACE, "workspace too small");
+  FF_HIP(e);
+  return FFSRQR_OK;
+}
+
+ffsrqr_status ffsrqr_panel_qr(const void* A, int64_t m, int64_t n, int64_t lda, const int64_t* cols, int64_t c,
+                              void* Q, int64_t ldq, void* R, int64_t ldr, void* work, size_t work_bytes,
+                              int32_t precision, ffsrqr_stream_t stream) {
+  if (m < 1 || n < 1 || c < 1 || c > m || lda < m || ldq < m || ldr < c || !A || !cols || !Q || !R || !work)
+    return fail(FFSRQR_EINVAL, "bad panel_qr arguments");
+  if (!valid_precision(precision)) return fail(FFSRQR_EINVAL, "unknown precision");
+  const DeviceInfo* d = nullptr;
+  ffsrqr_status st = get_device(&d);
+  if (st != FFSRQR_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  Arena ar{(char*)work, work_bytes, 0};
+  unsigned* err = ar.take<unsigned>(64);
+  const size_t es = elem_size(precision);
+  char* P = ar.take<char>((size_t)m * c * es);
+  if (!err || !P) return fail(FFSRQR_EWORKSPACE, "workspace too small");
+  FF_HIP(zero_words(err, 64, s));
+  hipError_t e;
+  if (precision == FFSRQR_FP64) {
+    FF_HIP(gather_cols<double>((const double*)A, m, n, lda, cols, c, (double*)P, m, s));
+    e = tall_qr<double>((double*)P, m, c, m, (double*)Q, ldq, nullptr, (double*)R, ldr, false, ar, err, *d, s);
+  } else {
+    FF_HIP(gather_cols<float>((const float*)A, m, n, lda, cols, c, (float*)P, m, s));
+    e = tall_qr<float>((float*)P, m, c, m, (float*)Q, ldq, nullptr, (float*)R, ldr, false, ar, err, *d, s);
+  }
+  if (e == hipErrorOutOfMemory) return fail(FFSRQR_EWORKSPACE, "workspace too small");
+  FF_HIP(e);
+  return FFSRQR_OK;
+}
+
+ffsrqr_status ffsrqr_project(const void* Q, int64_t m, int64_t c, int64_t ldq, const void* A, int64_t n, int64_t lda,
+                             void* W, int64_t ldw, const double* anorm2, double* gamma2, void* work,
+                             size_t work_bytes, int32_t precision, ffsrqr_stream_t stream) {
+  if (m < 1 || n < 1 || c < 1 || ldq < m || lda < m || ldw < c || !Q || !A || !W || !anorm2 || !gamma2 || !work)
+    return fail(FFSRQR_EINVAL, "bad project arguments");
+  if (!valid_precision(precision)) return fail(FFSRQR_EINVAL, "unknown precision");
+  const DeviceInfo* d = nullptr;
+  ffsrqr_status st = get_device(&d);
+  if (st != FFSRQR_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  Arena ar{(char*)work, work_bytes, 0};
+  hipError_t e;
+  if (precision == FFSRQR_FP64) {
+    e = gemm_tn<double>(c, n, m, (const double*)Q, ldq, (const double*)A, lda, (double*)W, ldw, nullptr, ar,
+                        d->num_cu, s);
+    if (e == hipSuccess) e = residual_norms<double>((const double*)W, c, n, ldw, anorm2, gamma2, s);
+  } else {
+    e = gemm_tn<float>(c, n, m, (const float*)Q, ldq, (const float*)A, lda, (float*)W, ldw, nullptr, ar,
+                       d->num_cu, s);
+    if (e == hipSuccess) e = residual_norms<float>((const float*)W, c, n, ldw, anorm2, gamma2, s);
+  }
+  if (e == hipErrorOutOfMemory) return fail(FFSRQR_EWORKSPACE, "workspace too small");
+  FF_HIP(e);
+  return FFSRQR_OK;
+}
+
+ffsrqr_status ffsrqr_srqr_rho(const void* R11, int64_t l, int64_t ldr, const void* a, double alpha, double* rho,
+                              void* work, size_t work_bytes, int32_t precision, ffsrqr_stream_t stream) {
+  if (l < 1 || ldr < l || !R11 || !a || !rho || !work || !(alpha > 0.0))
+    return fail(FFSRQR_EINVAL, "bad srqr_rho arguments");
+  if (!valid_precision(precision)) return fail(FFSRQR_EINVAL, "unknown precision");
+  const DeviceInfo* d = nullptr;
+  ffsrqr_status st = get_device(&d);
+  if (st != FFSRQR_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  Arena ar{(char*)work, work_bytes, 0};
+  hipError_t e = precision == FFSRQR_FP64
+                     ? srqr_rho<double>((const double*)R11, ldr, (const double*)a, 0, nullptr, alpha, l, rho, nullptr,
+                                        ar, s)
+                     : srqr_rho<float>((const float*)R11, ldr, (const float*)a, 0, nullptr, alpha, l, rho, nullptr,
+                                       ar, s);
+  if (e == hipErrorOutOfMemory) return fail(FFSRQR_EWORKSPACE, "workspace too small");
+  FF_HIP(e);
+  return FFSRQR_OK;
+}
+
+ffsrqr_status ffsrqr_lq(const void* R, int64_t l, int64_t n, int64_t ldr, const int64_t* perm, void* L, int64_t ldl,
+                        void* V, int64_t ldv, void* work, size_t work_bytes, int32_t precision,
+                        ffsrqr_stream_t stream) {
+  if (l < 1 || n < l || ldr < l || ldl < l || ldv < n || !R || !perm || !L || !V || !work)
+    return fail(FFSRQR_EINVAL, "bad lq arguments");
+  if (!valid_precision(precision)) return fail(FFSRQR_EINVAL, "unknown precision");
+  const DeviceInfo* d = nullptr;
+  ffsrqr_status st = get_device(&d);
+  if (st != FFSRQR_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  Arena ar{(char*)work, work_bytes, 0};
+  unsigned* err = ar.take<unsigned>(64);
+  const size_t es = elem_size(precision);
+  char* Rt = ar.take<char>((size_t)n * l * es);
+  if (!err || !Rt) return fail(FFSRQR_EWORKSPACE, "workspace too small");
+  FF_HIP(zero_words(err, 64, s));
+  hipError_t e;
+  if (precision == FFSRQR_FP64) {
+    FF_HIP(assemble_rt<double>((const double*)R, ldr, (const double*)R, ldr, nullptr, l, n, (double*)Rt, n, s));
+    e = tall_qr<double>((double*)Rt, n, l, n, (double*)V, ldv, perm, (double*)L, ldl, true, ar, err, *d, s);
+  } else {
+    FF_HIP(assemble_rt<float>((const float*)R, ldr, (const float*)R, ldr, nullptr, l, n, (float*)Rt, n, s));
+    e = tall_qr<float>((float*)Rt, n, l, n, (float*)V, ldv, perm, (float*)L, ldl, true, ar, err, *d, s);
+  }
+  if (e == hipErrorOutOfMemory) return fail(FFSRQR_EWORKSPACE, "workspace too small");
+  FF_HIP(e);
+  return FFSRQR_OK;
+}
+
+ffsrqr_status ffsrqr_svd_small(const void* L, int64_t l, int64_t ldl, double* sigma, void* work, size_t work_bytes,
+                               int32_t precision, ffsrqr_stream_t stream) {
+  if (l < 1 || ldl < l || !L || !sigma || !work) return fail(FFSRQR_EINVAL, "bad svd_small arguments");
+  if (!valid_precision(precision)) return fail(FFSRQR_EINVAL, "unknown precision");
+  const DeviceInfo* d = nullptr;
+  ffsrqr_status st = get_device(&d);
+  if (st != FFSRQR_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  Arena ar{(char*)work, work_bytes, 0};
+  unsigned* err = ar.take<unsigned>(64);
+  if (!err) return fail(FFSRQR_EWORKSPACE, "workspace too small");
+  FF_HIP(zero_words(err, 64, s));
+  hipError_t e = precision == FFSRQR_FP64
+                     ? jacobi_sigma<double>((const double*)L, l, ldl, sigma, ar, err, *d, s)
+                     : jacobi_sigma<float>((const float*)L, l, ldl, sigma, ar, err, *d, s);
+  if (e == hipErrorOutOfMemory) return fail(FFSRQR_EWORKSPACE, "workspace too small");
+  FF_HIP(e);
+  return FFSRQR_OK;
+}
+
+}  // extern "C"

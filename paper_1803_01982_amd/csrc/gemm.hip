@@ -1,0 +1,177 @@
+// C = X^T Y on MFMA: the sketch B = Omega A (Algorithm 2, sample matrix;
+// X = Omega^T) and the projection W = Q1^T A (partial QR block form,
+// Sections 2.1 and 3.1; X = Q1).  Both operands are column-major and
+// contiguous along the contraction index K = m, so one kernel serves both.
+//
+// Tile 64 x 64 per workgroup (4 waves in 2 x 2, 32 x 32 each as 2 x 2 MFMA
+// 16x16x4 blocks), K step 16, double-buffered LDS with a register prefetch
+// of the next K step.  Split-K over gridDim.z when the output tiles alone
+// cannot fill the chip; partial products are summed in a fixed order.
+// The column norms ||Y(:, j)||^2 are accumulated in FP64 from the LDS tiles
+// by the workgroups of the first row-tile, so the sketch reads A only once.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace ffsrqr {
+
+namespace {
+
+constexpr int BM = 64, BN = 64, BK = 16, PAD = 2, NT = 256;
+
+template <typename T>
+__global__ __launch_bounds__(NT) void gemm_tn_kernel(
+    int64_t M, int64_t N, int64_t K, int64_t kchunk, const T* __restrict__ X, int64_t ldx,
+    const T* __restrict__ Y, int64_t ldy, T* __restrict__ C, int64_t ldc, int64_t cstride,
+    double* __restrict__ colnorm, int64_t nstride) {
+  __shared__ T Xs[2][BK][BM + PAD];
+  __shared__ T Ys[2][BK][BN + PAD];
+  using MF = Mfma<T>;
+  typename MF::acc4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = typename MF::acc4{0, 0, 0, 0};
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wy = wave >> 1, wx = wave & 1;
+  const int64_t m0 = (int64_t)blockIdx.y * BM, n0 = (int64_t)blockIdx.x * BN;
+  const int64_t kb = (int64_t)blockIdx.z * kchunk;
+  const int64_t ke = (kb + kchunk < K) ? kb + kchunk : K;
+  const bool do_norm = colnorm != nullptr && blockIdx.y == 0;
+
+  // loader mapping: 16 consecutive k by 4 columns per wave instruction
+  const int lk = tid % BK, lc = tid / BK;  // lc in 0..15
+  T xr[4], yr[4];
+  auto load = [&](int64_t k0) {
+    const int64_t k = k0 + lk;
+    const bool kin = k < ke;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t mm = m0 + lc + 16 * q, nn = n0 + lc + 16 * q;
+      xr[q] = (kin && mm < M) ? X[mm * ldx + k] : T(0);
+      yr[q] = (kin && nn < N) ? Y[nn * ldy + k] : T(0);
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      Xs[buf][lk][lc + 16 * q] = xr[q];
+      Ys[buf][lk][lc + 16 * q] = yr[q];
+    }
+  };
+
+  double nrm = 0.0;
+  int cur = 0;
+  if (kb < ke) {
+    load(kb);
+    store(0);
+  }
+  __syncthreads();
+  for (int64_t k0 = kb; k0 < ke; k0 += BK) {
+    const bool more = k0 + BK < ke;
+    if (more) load(k0 + BK);
+#pragma unroll
+    for (int k4 = 0; k4 < BK / 4; ++k4) {
+      const int kr = k4 * 4 + (lane >> 4);
+      T a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[i] = Xs[cur][kr][wy * 32 + i * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = Ys[cur][kr][wx * 32 + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = MF::fma(a[i], b[j], acc[i][j]);
+    }
+    if (do_norm && tid < BN) {
+#pragma unroll
+      for (int kk = 0; kk < BK; ++kk) {
+        const double y = (double)Ys[cur][kk][tid];
+        nrm += y * y;
+      }
+    }
+    if (more) store(cur ^ 1);
+    __syncthreads();
+    cur ^= 1;
+  }
+
+  T* Cz = C + (int64_t)blockIdx.z * cstride;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = m0 + wy * 32 + i * 16 + MF::row(lane, r);
+        const int64_t col = n0 + wx * 32 + j * 16 + (lane & 15);
+        if (row < M && col < N) Cz[col * ldc + row] = acc[i][j][r];
+      }
+  if (do_norm && tid < BN && n0 + tid < N) colnorm[(int64_t)blockIdx.z * nstride + n0 + tid] = nrm;
+}
+
+// C = sum_z Cpart_z (fixed order); colnorm likewise.
+template <typename T>
+__global__ void splitk_reduce(int64_t M, int64_t N, int splits, const T* __restrict__ P, T* __restrict__ C,
+                              int64_t ldc, const double* __restrict__ np, double* __restrict__ colnorm) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < M * N) {
+    const int64_t row = idx % M, col = idx / M;
+    T s = 0;
+    for (int z = 0; z < splits; ++z) s += P[(int64_t)z * M * N + idx];
+    C[col * ldc + row] = s;
+  }
+  if (colnorm && idx < N) {
+    double s = 0;
+    for (int z = 0; z < splits; ++z) s += np[(int64_t)z * N + idx];
+    colnorm[idx] = s;
+  }
+}
+
+int pick_splits(int64_t M, int64_t N, int64_t K, int num_cu) {
+  const int64_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
+  int64_t s = 1;
+  const int64_t want = 2 * (int64_t)num_cu;
+  while (tiles * s < want && K / (s * 2) >= 512) s *= 2;
+  return (int)s;
+}
+
+}  // namespace
+
+template <typename T>
+size_t gemm_tn_scratch(int64_t M, int64_t N, int64_t K, int num_cu) {
+  const int s = pick_splits(M, N, K, num_cu);
+  if (s == 1) return 0;
+  return (size_t)s * M * N * sizeof(T) + (size_t)s * N * sizeof(double) + 1024;
+}
+
+template <typename T>
+hipError_t gemm_tn(int64_t M, int64_t N, int64_t K, const T* X, int64_t ldx, const T* Y, int64_t ldy,
+                   T* C, int64_t ldc, double* colnorm, Arena& ar, int num_cu, hipStream_t s) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  const int splits = pick_splits(M, N, K, num_cu);
+  int64_t kchunk = (K + splits - 1) / splits;
+  kchunk = (kchunk + BK - 1) / BK * BK;
+  dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((M + BM - 1) / BM), (unsigned)splits);
+  if (splits == 1) {
+    gemm_tn_kernel<T><<<grid, NT, 0, s>>>(M, N, K, kchunk, X, ldx, Y, ldy, C, ldc, 0, colnorm, 0);
+    return hipGetLastError();
+  }
+  T* part = ar.take<T>((size_t)splits * M * N);
+  double* npart = colnorm ? ar.take<double>((size_t)splits * N) : nullptr;
+  if (!part || (colnorm && !npart)) return hipErrorOutOfMemory;
+  gemm_tn_kernel<T><<<grid, NT, 0, s>>>(M, N, K, kchunk, X, ldx, Y, ldy, part, M, M * N, npart, N);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t total = M * N > N ? M * N : N;
+  splitk_reduce<T><<<(unsigned)((total + 255) / 256), 256, 0, s>>>(M, N, splits, part, C, ldc, npart, colnorm);
+  return hipGetLastError();
+}
+
+template size_t gemm_tn_scratch<double>(int64_t, int64_t, int64_t, int);
+template size_t gemm_tn_scratch<float>(int64_t, int64_t, int64_t, int);
+template hipError_t gemm_tn<double>(int64_t, int64_t, int64_t, const double*, int64_t, const double*, int64_t,
+                                    double*, int64_t, double*, Arena&, int, hipStream_t);
+template hipError_t gemm_tn<float>(int64_t, int64_t, int64_t, const float*, int64_t, const float*, int64_t,
+                                   float*, int64_t, double*, Arena&, int, hipStream_t);
+
+}  // namespace ffsrqr

@@ -1,0 +1,122 @@
+// Internal launchers of the gfx950 Flip-Flop SRQR library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace ffsrqr {
+
+struct DeviceInfo {
+  int id = -1;
+  int num_cu = 0;
+  size_t lds_max = 0;
+  bool coop = false;
+  bool gfx950 = false;
+};
+// Cached properties of the current device.
+const DeviceInfo& device_info(hipError_t* err);
+
+// Workspace carving: bump allocator over the caller's buffer (256-byte aligned).
+struct Arena {
+  char* base;
+  size_t cap;
+  size_t used;
+  template <typename U>
+  U* take(size_t count) {
+    size_t off = (used + 255) & ~size_t(255);
+    used = off + count * sizeof(U);
+    return (base && used <= cap) ? reinterpret_cast<U*>(base + off) : nullptr;
+  }
+};
+
+hipError_t zero_words(unsigned* p, int n, hipStream_t s);
+
+// Omega^T (m x l, ldo): Ot[t + i*ldo] = Omega[i, t] (Philox4x64-10 + Box-Muller).
+template <typename T>
+hipError_t launch_omega(uint64_t seed, int64_t l, int64_t m, T* Ot, int64_t ldo, hipStream_t s);
+
+// C (M x N, ldc) = X^T Y with X K x M (ldx), Y K x N (ldy).  If colnorm is
+// non-null it receives ||Y(:, j)||^2 (FP64).  Scratch comes from the arena.
+template <typename T>
+size_t gemm_tn_scratch(int64_t M, int64_t N, int64_t K, int num_cu);
+template <typename T>
+hipError_t gemm_tn(int64_t M, int64_t N, int64_t K, const T* X, int64_t ldx, const T* Y,
+                   int64_t ldy, T* C, int64_t ldc, double* colnorm, Arena& ar, int num_cu,
+                   hipStream_t s);
+
+// Partial QRCP on B (l x n): piv[0:l], margins[0:l].
+template <typename T>
+size_t qrcp_scratch(int64_t l, int64_t n, const DeviceInfo& d);
+template <typename T>
+hipError_t qrcp(const T* B, int64_t l, int64_t n, int64_t ldb, int64_t* piv, double* margins,
+                Arena& ar, unsigned* err, const DeviceInfo& d, hipStream_t s);
+
+// P (mrows x c) <- A(:, cols[0:c]).
+// Indices outside [0, n) yield NaN columns instead of a read.
+template <typename T>
+hipError_t gather_cols(const T* A, int64_t m, int64_t n, int64_t lda, const int64_t* cols, int64_t c, T* P,
+                       int64_t ldp, hipStream_t s);
+
+// Householder QR of P (mrows x c, in place): explicit Q (row i written to
+// row rowmap[i] of Qout, or row i when rowmap is null) and R (c x c, or its
+// transpose when transpose_r), with diag(R) >= 0.
+template <typename T>
+size_t tallqr_scratch(int64_t mrows, int64_t c, const DeviceInfo& d);
+template <typename T>
+hipError_t tall_qr(T* P, int64_t mrows, int64_t c, int64_t ldp, T* Qout, int64_t ldq,
+                   const int64_t* rowmap, T* R, int64_t ldr, bool transpose_r, Arena& ar,
+                   unsigned* err, const DeviceInfo& d, hipStream_t s);
+
+// Rt (n x l): row i = R11(:, i)^T for i < l, W(:, perm[i])^T for i >= l.
+template <typename T>
+hipError_t assemble_rt(const T* R11, int64_t ldr11, const T* W, int64_t ldw, const int64_t* perm,
+                       int64_t l, int64_t n, T* Rt, int64_t ldrt, hipStream_t s);
+// R (l x n, ldr) in perm order from R11 and W.
+template <typename T>
+hipError_t assemble_r(const T* R11, int64_t ldr11, const T* W, int64_t ldw, const int64_t* perm,
+                      int64_t l, int64_t n, T* R, int64_t ldr, hipStream_t s);
+
+// perm[n] = [S (l entries), the rest ascending]; inS[n] = 1 for members of S.
+// cnt: scratch of ceil(n / 1024) int64.
+hipError_t build_perm(const int64_t* S, int64_t l, int64_t n, int64_t* perm, unsigned char* inS, int64_t* cnt,
+                      hipStream_t s);
+
+// SRQR small stage.  State shared between kernels and read back by the host.
+struct SrqrState {
+  double gamma2_max;   // largest approximate residual^2 over the trailing set
+  int64_t jstar;       // its original index (-1 if none)
+  double anorm_max;    // max_j ||a_j||
+  double alpha;        // exact residual norm of column jstar
+  double min_diag;     // min |R11_ii|
+  double g2;           // max(1, max rho)
+  int64_t istar;       // argmax rho (leading position)
+  unsigned nonfinite;  // A held a NaN/Inf
+  unsigned pad;
+};
+template <typename T>
+hipError_t residual_norms(const T* W, int64_t l, int64_t n, int64_t ldw, const double* anorm2,
+                          double* gamma2, hipStream_t s);
+template <typename T>
+size_t srqr_scratch(int64_t m, int64_t n, int64_t l);
+template <typename T>
+hipError_t srqr_select(const double* gamma2, const double* anorm2, const unsigned char* inS, int64_t n,
+                       const T* A, int64_t m, int64_t lda, const T* Q, int64_t ldq, const T* W,
+                       int64_t ldw, const T* R11, int64_t ldr, int64_t l, SrqrState* st,
+                       Arena& ar, hipStream_t s);
+// rho of R-tilde = [[R11, a], [0, alpha]].  With sel non-null, a is column
+// sel->jstar of the matrix at `a` (column stride a_stride) and alpha is
+// sel->alpha; otherwise a and alpha_host are used as given.  g2 and istar go
+// to st_out when non-null.
+template <typename T>
+hipError_t srqr_rho(const T* R11, int64_t ldr, const T* a, int64_t a_stride, const SrqrState* sel,
+                    double alpha_host, int64_t l, double* rho, SrqrState* st_out, Arena& ar, hipStream_t s);
+
+// Singular values of L (l x l) by block one-sided Jacobi (FP64).
+template <typename T>
+size_t jacobi_scratch(int64_t l, const DeviceInfo& d);
+template <typename T>
+hipError_t jacobi_sigma(const T* L, int64_t l, int64_t ldl, double* sigma, Arena& ar, unsigned* err,
+                        const DeviceInfo& d, hipStream_t s);
+
+}  // namespace ffsrqr

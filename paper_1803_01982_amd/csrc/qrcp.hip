@@ -1,0 +1,235 @@
+// Partial QRCP on the sketch B (Algorithm 1 applied to B for l steps; the
+// pivot search of Algorithm 2).
+//
+// One cooperative launch, one workgroup per CU.  Workgroup g owns a
+// contiguous slice of nc columns of B, kept in LDS (or in a global copy when
+// the slice does not fit) for all l steps.  Step j:
+//   1. each workgroup publishes its best active column (largest residual
+//      norm, ties to the smallest original index), its runner-up norm, and
+//      that column's rows j..l-1;
+//   2. one grid barrier;
+//   3. every workgroup reads the candidates and takes the same winner
+//      (fixed comparison order, so no broadcast is needed), builds the
+//      Householder reflector of the winner's rows j..l-1 (LAPACK xLARFG
+//      convention, FP64), retires the winner and applies the reflector to
+//      its own active columns, recomputing their residual norms from
+//      scratch over rows j+1..l-1 (the same definition as the oracle; no
+//      downdating drift to guard against).
+// Candidate slots are double-buffered by step parity, so one barrier per
+// step suffices.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace ffsrqr {
+
+namespace {
+
+constexpr int NT = 256;
+
+struct QrcpSlots {
+  double* r;      // [2][G]
+  double* r2;     // [2][G]
+  int64_t* idx;   // [2][G]
+  double* col;    // [2][G][l]
+};
+
+__device__ inline int group_size_for(int nc) {
+  int g = 1;
+  while (g * 2 * nc <= NT && g < 64) g *= 2;
+  return g;
+}
+
+template <typename T, bool IN_LDS>
+__global__ __launch_bounds__(NT) void qrcp_kernel(const T* __restrict__ B, int64_t ldb, int l, int64_t n,
+                                                  int nc, T* __restrict__ Bw, QrcpSlots sl,
+                                                  int64_t* __restrict__ piv, double* __restrict__ margins,
+                                                  GridSync gs) {
+  extern __shared__ double smem[];
+  __shared__ double redv[NT / 64];
+  __shared__ int64_t redi[NT / 64];
+  __shared__ double s_bcast[4];
+  __shared__ int64_t s_ibcast[2];
+
+  const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
+  const int64_t c0 = (int64_t)g * nc;
+  const int ncl = (int)((n - c0) < nc ? ((n - c0) > 0 ? (n - c0) : 0) : nc);
+  double* v = smem;            // l
+  double* rloc = v + l;        // nc
+  int* act = (int*)(rloc + nc);  // nc (padded to an even count)
+  T* Bl = IN_LDS ? (T*)(smem + l + nc + (nc + 1) / 2) : Bw + (int64_t)g * nc * l;
+
+  for (int64_t e = tid; e < (int64_t)ncl * l; e += NT) {
+    const int c = (int)(e / l), i = (int)(e % l);
+    Bl[(int64_t)c * l + i] = B[(c0 + c) * ldb + i];
+  }
+  for (int c = tid; c < nc; c += NT) act[c] = c < ncl ? 1 : 0;
+  const int gsz = group_size_for(nc), ngrp = NT / gsz, q = tid % gsz;
+  __syncthreads();
+  for (int c = tid / gsz; c < ncl; c += ngrp) {
+    double s = 0.0;
+    for (int i = q; i < l; i += gsz) {
+      const double b = (double)Bl[(int64_t)c * l + i];
+      s += b * b;
+    }
+    s = group_sum(s, gsz);
+    if (q == 0) rloc[c] = s;
+  }
+  __syncthreads();
+
+  unsigned epoch = 0;
+  for (int j = 0; j < l; ++j) {
+    const int par = j & 1;
+    // ---- 1. local best and runner-up among the active columns
+    ArgMax best{0.0, -1};
+    for (int c = tid; c < ncl; c += NT)
+      if (act[c] && better(rloc[c], c0 + c, best.v, best.i)) best = ArgMax{rloc[c], c0 + c};
+    best = block_argmax(best, redv, redi);
+    ArgMax second{0.0, -1};
+    for (int c = tid; c < ncl; c += NT)
+      if (act[c] && c0 + c != best.i && better(rloc[c], c0 + c, second.v, second.i))
+        second = ArgMax{rloc[c], c0 + c};
+    second = block_argmax(second, redv, redi);
+    if (tid == 0) {
+      sl.r[par * G + g] = best.v;
+      sl.idx[par * G + g] = best.i;
+      sl.r2[par * G + g] = second.i >= 0 ? second.v : -1.0;
+    }
+    if (best.i >= 0) {
+      const int cb = (int)(best.i - c0);
+      double* dst = sl.col + ((int64_t)par * G + g) * l;
+      for (int i = j + tid; i < l; i += NT) dst[i] = (double)Bl[(int64_t)cb * l + i];
+    }
+    // ---- 2. exchange
+    if (!grid_barrier(gs, epoch)) return;
+    // ---- 3. global winner (identical in every workgroup)
+    ArgMax w{0.0, -1};
+    for (int t = tid; t < G; t += NT) {
+      const int64_t it = sl.idx[par * G + t];
+      const double vt = sl.r[par * G + t];
+      if (better(vt, it, w.v, w.i)) w = ArgMax{vt, it};
+    }
+    w = block_argmax(w, redv, redi);
+    const int wg = (int)(w.i / nc);
+    double r2 = -1.0;
+    for (int t = tid; t < G; t += NT) {
+      const double vt = (t == wg) ? sl.r2[par * G + t] : (sl.idx[par * G + t] >= 0 ? sl.r[par * G + t] : -1.0);
+      r2 = vt > r2 ? vt : r2;
+    }
+    {
+      // block max of r2 (fixed order)
+      ArgMax m2{r2, r2 >= 0.0 ? 0 : -1};
+      m2 = block_argmax(m2, redv, redi);
+      r2 = m2.i >= 0 ? m2.v : -1.0;
+    }
+    if (g == 0 && tid == 0) {
+      piv[j] = w.i;
+      double mg;
+      if (n - j <= 1) mg = 1.0;
+      else if (w.v > 0.0) mg = (w.v - (r2 > 0.0 ? r2 : 0.0)) / w.v;
+      else mg = 0.0;
+      margins[j] = mg;
+    }
+    const double* src = sl.col + ((int64_t)par * G + wg) * l;
+    for (int i = j + tid; i < l; i += NT) v[i] = src[i];
+    __syncthreads();
+    double xs = 0.0;
+    for (int i = j + 1 + tid; i < l; i += NT) xs += v[i] * v[i];
+    const double xnorm2 = block_sum(xs, redv);
+    const double x0 = v[j];
+    double tau = 0.0;
+    if (xnorm2 > 0.0) {
+      const double beta = -copysign(sqrt(x0 * x0 + xnorm2), x0);
+      tau = (beta - x0) / beta;
+      const double scale = 1.0 / (x0 - beta);
+      __syncthreads();
+      for (int i = j + 1 + tid; i < l; i += NT) v[i] *= scale;
+      if (tid == 0) v[j] = 1.0;
+    }
+    if (wg == g && tid == 0) act[w.i - c0] = 0;
+    __syncthreads();
+    // ---- update the active local columns, recompute residual norms
+    for (int c = tid / gsz; c < ncl; c += ngrp) {
+      if (!act[c]) continue;
+      T* col = Bl + (int64_t)c * l;
+      if (tau != 0.0) {
+        double s = 0.0;
+        for (int i = j + q; i < l; i += gsz) s += v[i] * (double)col[i];
+        s = group_sum(s, gsz) * tau;
+        for (int i = j + q; i < l; i += gsz) col[i] = (T)((double)col[i] - s * v[i]);
+      }
+      double r = 0.0;
+      for (int i = j + 1 + q; i < l; i += gsz) {
+        const double b = (double)col[i];
+        r += b * b;
+      }
+      r = group_sum(r, gsz);
+      if (q == 0) rloc[c] = r;
+    }
+    __syncthreads();
+  }
+}
+
+void choose(int64_t l, int64_t n, int num_cu, size_t lds_max, size_t tsize, int* nc, int* G, bool* in_lds,
+            size_t* lds) {
+  int64_t c = (n + num_cu - 1) / num_cu;
+  if (c < 1) c = 1;
+  *nc = (int)c;
+  *G = (int)((n + c - 1) / c);
+  const size_t base = (size_t)(l + c + (c + 1) / 2) * sizeof(double);
+  const size_t with = base + (size_t)c * l * tsize;
+  *in_lds = with <= lds_max;
+  *lds = *in_lds ? with : base;
+}
+
+}  // namespace
+
+template <typename T>
+size_t qrcp_scratch(int64_t l, int64_t n, const DeviceInfo& d) {
+  int nc, G;
+  bool in_lds;
+  size_t lds;
+  choose(l, n, d.num_cu, d.lds_max, sizeof(T), &nc, &G, &in_lds, &lds);
+  size_t b = (size_t)2 * G * (3 * sizeof(double) + l * sizeof(double)) + 4 * 256;
+  if (!in_lds) b += (size_t)G * nc * l * sizeof(T) + 256;
+  return b + 512;
+}
+
+template <typename T>
+hipError_t qrcp(const T* B, int64_t l, int64_t n, int64_t ldb, int64_t* piv, double* margins, Arena& ar,
+                unsigned* err, const DeviceInfo& d, hipStream_t s) {
+  if (l <= 0) return hipSuccess;
+  int nc, G;
+  bool in_lds;
+  size_t lds;
+  choose(l, n, d.num_cu, d.lds_max, sizeof(T), &nc, &G, &in_lds, &lds);
+  QrcpSlots sl;
+  sl.r = ar.take<double>(2 * G);
+  sl.r2 = ar.take<double>(2 * G);
+  sl.idx = ar.take<int64_t>(2 * G);
+  sl.col = ar.take<double>((size_t)2 * G * l);
+  unsigned* counter = ar.take<unsigned>(64);
+  T* Bw = in_lds ? nullptr : ar.take<T>((size_t)G * nc * l);
+  if (!sl.r || !sl.r2 || !sl.idx || !sl.col || !counter || (!in_lds && !Bw)) return hipErrorOutOfMemory;
+  hipError_t e = zero_words(counter, 64, s);
+  if (e != hipSuccess) return e;
+  GridSync gs{counter, err, (unsigned)G};
+  int li = (int)l;
+  int64_t ln = n, lldb = ldb;
+  void* args[] = {(void*)&B, (void*)&lldb, (void*)&li, (void*)&ln, (void*)&nc, (void*)&Bw,
+                  (void*)&sl, (void*)&piv, (void*)&margins, (void*)&gs};
+  const void* fn = in_lds ? (const void*)qrcp_kernel<T, true> : (const void*)qrcp_kernel<T, false>;
+  if (lds > 65536) {
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  return hipLaunchCooperativeKernel(fn, dim3(G), dim3(NT), args, (unsigned)lds, s);
+}
+
+template size_t qrcp_scratch<double>(int64_t, int64_t, const DeviceInfo&);
+template size_t qrcp_scratch<float>(int64_t, int64_t, const DeviceInfo&);
+template hipError_t qrcp<double>(const double*, int64_t, int64_t, int64_t, int64_t*, double*, Arena&, unsigned*,
+                                 const DeviceInfo&, hipStream_t);
+template hipError_t qrcp<float>(const float*, int64_t, int64_t, int64_t, int64_t*, double*, Arena&, unsigned*,
+                                const DeviceInfo&, hipStream_t);
+
+}  // namespace ffsrqr

@@ -1,0 +1,378 @@
+// SRQR small stage (Section 2.2, definitions of R-tilde, g1, g2; Algorithm 4)
+// and the bookkeeping around the projection.
+//
+//   residual norms  gamma_j^2 = ||a_j||^2 - ||W(:, j)||^2 in FP64, W = Q1^T A
+//                   (the part of a_j outside span(Q1)); one wave per column.
+//   select          j* = argmax of gamma^2 over the trailing columns (ties to
+//                   the smallest index), then alpha = ||a_j* - Q1 W(:, j*)||
+//                   recomputed exactly in FP64 so that the swap test does not
+//                   depend on the cancellation in the difference of squares.
+//   rho             X = R11^{-1} and z = R11^{-1} a by column-oriented back
+//                   substitution (one workgroup per column, R staged in LDS in
+//                   chunks of 16 columns), then
+//                   rho_i^2 = alpha^2 ||X(i, :)||^2 + z_i^2, the squared norm of
+//                   row i of |alpha| R-tilde^{-1}; g2 = max(1, max_i rho_i).
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace ffsrqr {
+
+namespace {
+
+constexpr int NT = 256;
+
+template <typename T>
+__global__ void resid_kernel(const T* __restrict__ W, int64_t l, int64_t n, int64_t ldw,
+                             const double* __restrict__ anorm2, double* __restrict__ gamma2) {
+  const int lane = threadIdx.x & 63;
+  const int64_t j = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+  if (j >= n) return;
+  double s = 0.0;
+  for (int64_t i = lane; i < l; i += 64) {
+    const double w = (double)W[j * ldw + i];
+    s += w * w;
+  }
+  s = wave_sum(s);
+  if (lane == 0) gamma2[j] = anorm2[j] - s;
+}
+
+// Block partials of (masked argmax gamma2, max anorm2, non-finite).
+__global__ void select_partial(const double* __restrict__ gamma2, const double* __restrict__ anorm2,
+                               const unsigned char* __restrict__ inS, int64_t n, double* pv, int64_t* pi,
+                               double* pa, unsigned* pnf) {
+  __shared__ double rv[NT / 64];
+  __shared__ int64_t ri[NT / 64];
+  ArgMax b{0.0, -1};
+  double amax = 0.0;
+  unsigned nf = 0;
+  for (int64_t j = (int64_t)blockIdx.x * NT + threadIdx.x; j < n; j += (int64_t)gridDim.x * NT) {
+    const double a = anorm2[j];
+    if (!(a <= 1.7976931348623157e308)) nf = 1;  // NaN or Inf
+    else if (a > amax) amax = a;
+    if (!inS[j] && better(gamma2[j], j, b.v, b.i)) b = ArgMax{gamma2[j], j};
+  }
+  b = block_argmax(b, rv, ri);
+  ArgMax am = block_argmax(ArgMax{amax, 0}, rv, ri);
+  ArgMax nfm = block_argmax(ArgMax{(double)nf, 0}, rv, ri);
+  if (threadIdx.x == 0) {
+    pv[blockIdx.x] = b.v;
+    pi[blockIdx.x] = b.i;
+    pa[blockIdx.x] = am.v;
+    pnf[blockIdx.x] = nfm.v > 0.0 ? 1u : 0u;
+  }
+}
+
+template <typename T>
+__global__ void select_final(int nb, const double* pv, const int64_t* pi, const double* pa, const unsigned* pnf,
+                             const T* __restrict__ R11, int64_t ldr, int64_t l, SrqrState* st) {
+  __shared__ double rv[NT / 64];
+  __shared__ int64_t ri[NT / 64];
+  ArgMax b{0.0, -1};
+  double amax = 0.0;
+  unsigned nf = 0;
+  for (int q = threadIdx.x; q < nb; q += NT) {
+    if (better(pv[q], pi[q], b.v, b.i)) b = ArgMax{pv[q], pi[q]};
+    amax = pa[q] > amax ? pa[q] : amax;
+    nf |= pnf[q];
+  }
+  b = block_argmax(b, rv, ri);
+  ArgMax am = block_argmax(ArgMax{amax, 0}, rv, ri);
+  ArgMax nfm = block_argmax(ArgMax{(double)nf, 0}, rv, ri);
+  double dmin = 1.7976931348623157e308;
+  for (int64_t i = threadIdx.x; i < l; i += NT) {
+    const double d = fabs((double)R11[i * ldr + i]);
+    dmin = d < dmin ? d : dmin;
+  }
+  ArgMax dm = block_argmax(ArgMax{-dmin, 0}, rv, ri);
+  if (threadIdx.x == 0) {
+    st->gamma2_max = b.v;
+    st->jstar = b.i;
+    st->anorm_max = sqrt(am.v);
+    st->nonfinite = nfm.v > 0.0 ? 1u : 0u;
+    st->min_diag = -dm.v;
+    st->alpha = 0.0;
+  }
+}
+
+// Partial sums of e_i^2, e = a_j* - Q W(:, j*), over row blocks.
+template <typename T>
+__global__ void alpha_partial(const T* __restrict__ A, int64_t m, int64_t lda, const T* __restrict__ Q,
+                              int64_t ldq, const T* __restrict__ W, int64_t ldw, int64_t l, const SrqrState* st,
+                              double* part) {
+  extern __shared__ double wcol[];
+  __shared__ double red[NT / 64];
+  const int64_t js = st->jstar;
+  if (js < 0) {
+    if (threadIdx.x == 0) part[blockIdx.x] = 0.0;
+    return;
+  }
+  for (int64_t s = threadIdx.x; s < l; s += NT) wcol[s] = (double)W[js * ldw + s];
+  __syncthreads();
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < m; i += (int64_t)gridDim.x * NT) {
+    double e = (double)A[js * lda + i];
+    for (int64_t s = 0; s < l; ++s) e -= (double)Q[s * ldq + i] * wcol[s];
+    acc += e * e;
+  }
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+__global__ void alpha_final(int nb, const double* part, SrqrState* st) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double t = 0.0;
+    for (int q = 0; q < nb; ++q) t += part[q];
+    st->alpha = sqrt(t);
+  }
+}
+
+// Column j of R11^{-1} (j < l), or z = R11^{-1} a (j == l), by back substitution.
+template <typename T>
+__global__ void trinv_kernel(const T* __restrict__ R, int64_t ldr, int64_t l, const T* __restrict__ a_base,
+                             int64_t a_stride, const SrqrState* st, double* __restrict__ X) {
+  extern __shared__ double sm[];
+  constexpr int CH = 16;
+  double* b = sm;              // l
+  double* xo = b + l;          // l
+  double* Rc = xo + l;         // l x CH staging
+  const int64_t j = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int64_t len = (j < l) ? j + 1 : l;
+  const T* a = nullptr;
+  if (j == l) {
+    // st selects the column of W; no trailing column leaves a = 0
+    if (!st) a = a_base;
+    else if (st->jstar >= 0) a = a_base + st->jstar * a_stride;
+  }
+  for (int64_t r = tid; r < l; r += NT) {
+    b[r] = (j < l) ? (r == j ? 1.0 : 0.0) : (a ? (double)a[r] : 0.0);
+    xo[r] = 0.0;
+  }
+  for (int64_t hi = len - 1; hi >= 0; hi -= CH) {
+    const int64_t lo = hi - CH + 1 > 0 ? hi - CH + 1 : 0;
+    const int nc = (int)(hi - lo + 1);
+    __syncthreads();
+    // stage R(0:hi, lo:hi)
+    for (int64_t e = tid; e < (hi + 1) * nc; e += NT) {
+      const int64_t r = e % (hi + 1), c = e / (hi + 1);
+      Rc[c * l + r] = (double)R[(lo + c) * ldr + r];
+    }
+    for (int64_t i = hi; i >= lo; --i) {
+      __syncthreads();
+      const double* col = Rc + (i - lo) * l;
+      const double xi = b[i] / col[i];
+      if (tid == 0) xo[i] = xi;
+      for (int64_t r = tid; r < i; r += NT) b[r] -= xi * col[r];
+    }
+  }
+  __syncthreads();
+  for (int64_t r = tid; r < l; r += NT) X[j * l + r] = xo[r];
+}
+
+// rho_i = sqrt(alpha^2 ||X(i, 0:l)||^2 + X(i, l)^2); g2, istar.
+__global__ void rho_kernel(const double* __restrict__ X, int64_t l, const SrqrState* st_in, double alpha_host,
+                           double* __restrict__ rho, SrqrState* st) {
+  __shared__ double rv[NT / 64];
+  __shared__ int64_t ri[NT / 64];
+  const double alpha = st_in ? st_in->alpha : alpha_host;
+  ArgMax b{0.0, -1};
+  for (int64_t i = threadIdx.x; i < l; i += NT) {
+    double s = 0.0;
+    for (int64_t j = i; j < l; ++j) {
+      const double x = X[j * l + i];
+      s += x * x;
+    }
+    const double z = X[l * l + i];
+    const double r = sqrt(alpha * alpha * s + z * z);
+    rho[i] = r;
+    if (better(r, i, b.v, b.i)) b = ArgMax{r, i};
+  }
+  b = block_argmax(b, rv, ri);
+  if (threadIdx.x == 0 && st) {
+    st->g2 = b.v > 1.0 ? b.v : 1.0;
+    st->istar = b.i;
+  }
+}
+
+// ------------------------------------------------------------------ perm
+__global__ void perm_clear(int64_t n, unsigned char* inS) {
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x)
+    inS[j] = 0;
+}
+__global__ void perm_set(const int64_t* __restrict__ S, int64_t l, int64_t n, unsigned char* inS, int64_t* perm) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < l; k += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = S[k];
+    if (c >= 0 && c < n) inS[c] = 1;
+    perm[k] = c;
+  }
+}
+constexpr int PB = 1024;
+__global__ void perm_count(const unsigned char* __restrict__ inS, int64_t n, int64_t* cnt) {
+  __shared__ double red[PB / 64];
+  const int64_t j = (int64_t)blockIdx.x * PB + threadIdx.x;
+  double c = (j < n && !inS[j]) ? 1.0 : 0.0;
+  c = block_sum(c, red);
+  if (threadIdx.x == 0) cnt[blockIdx.x] = (int64_t)c;
+}
+__global__ void perm_scan(int64_t* cnt, int nb) {
+  if (threadIdx.x == 0) {
+    int64_t run = 0;
+    for (int q = 0; q < nb; ++q) {
+      const int64_t c = cnt[q];
+      cnt[q] = run;
+      run += c;
+    }
+  }
+}
+__global__ void perm_scatter(const unsigned char* __restrict__ inS, int64_t n, int64_t l, const int64_t* cnt,
+                             int64_t* perm) {
+  __shared__ int sc[PB];
+  const int64_t j = (int64_t)blockIdx.x * PB + threadIdx.x;
+  const int f = (j < n && !inS[j]) ? 1 : 0;
+  sc[threadIdx.x] = f;
+  __syncthreads();
+  // inclusive Hillis-Steele scan
+  for (int o = 1; o < PB; o <<= 1) {
+    const int v = threadIdx.x >= o ? sc[threadIdx.x - o] : 0;
+    __syncthreads();
+    sc[threadIdx.x] += v;
+    __syncthreads();
+  }
+  const int64_t dst = l + cnt[blockIdx.x] + sc[threadIdx.x] - 1;
+  if (f && dst < n) perm[dst] = j;
+}
+
+// ------------------------------------------------------------- assembly
+template <typename T>
+__global__ void assemble_rt_kernel(const T* __restrict__ R11, int64_t ldr11, const T* __restrict__ W, int64_t ldw,
+                                   const int64_t* __restrict__ perm, int64_t l, int64_t n, T* __restrict__ Rt,
+                                   int64_t ldrt) {
+  __shared__ T tile[32][33];
+  const int64_t i0 = (int64_t)blockIdx.x * 32, s0 = (int64_t)blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int k = ty; k < 32; k += 8) {
+    const int64_t i = i0 + k, s = s0 + tx;
+    T v = 0;
+    if (i < n && s < l) {
+      if (i < l) v = R11[i * ldr11 + s];
+      else {
+        const int64_t c = perm ? perm[i] : i;
+        v = (c >= 0 && c < n) ? W[c * ldw + s] : T(0);
+      }
+    }
+    tile[k][tx] = v;
+  }
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8) {
+    const int64_t s = s0 + k, i = i0 + tx;
+    if (i < n && s < l) Rt[s * ldrt + i] = tile[tx][k];
+  }
+}
+
+template <typename T>
+__global__ void assemble_r_kernel(const T* __restrict__ R11, int64_t ldr11, const T* __restrict__ W, int64_t ldw,
+                                  const int64_t* __restrict__ perm, int64_t l, int64_t n, T* __restrict__ R,
+                                  int64_t ldr) {
+  const int64_t i = blockIdx.y;
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < l; s += (int64_t)gridDim.x * blockDim.x)
+    R[i * ldr + s] = (i < l) ? R11[i * ldr11 + s] : W[perm[i] * ldw + s];
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t residual_norms(const T* W, int64_t l, int64_t n, int64_t ldw, const double* anorm2, double* gamma2,
+                          hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  resid_kernel<T><<<(unsigned)((n + 3) / 4), 256, 0, s>>>(W, l, n, ldw, anorm2, gamma2);
+  return hipGetLastError();
+}
+
+template <typename T>
+size_t srqr_scratch(int64_t m, int64_t n, int64_t l) {
+  return sizeof(double) * ((size_t)(l + 1) * l + 4 * 1024) + sizeof(int64_t) * 1024 + 4 * 1024 + 8 * 256;
+}
+
+template <typename T>
+hipError_t srqr_select(const double* gamma2, const double* anorm2, const unsigned char* inS, int64_t n, const T* A,
+                       int64_t m, int64_t lda, const T* Q, int64_t ldq, const T* W, int64_t ldw, const T* R11,
+                       int64_t ldr, int64_t l, SrqrState* st, Arena& ar, hipStream_t s) {
+  int nb = (int)((n + NT - 1) / NT);
+  if (nb > 1024) nb = 1024;
+  double* pv = ar.take<double>(1024);
+  int64_t* pi = ar.take<int64_t>(1024);
+  double* pa = ar.take<double>(1024);
+  unsigned* pnf = ar.take<unsigned>(1024);
+  double* part = ar.take<double>(1024);
+  if (!pv || !pi || !pa || !pnf || !part) return hipErrorOutOfMemory;
+  select_partial<<<nb, NT, 0, s>>>(gamma2, anorm2, inS, n, pv, pi, pa, pnf);
+  select_final<T><<<1, NT, 0, s>>>(nb, pv, pi, pa, pnf, R11, ldr, l, st);
+  if (l <= 0) return hipGetLastError();  // only the non-finite / norm scan was wanted
+  int na = (int)((m + NT - 1) / NT);
+  if (na > 512) na = 512;
+  alpha_partial<T><<<na, NT, (size_t)l * sizeof(double), s>>>(A, m, lda, Q, ldq, W, ldw, l, st, part);
+  alpha_final<<<1, 64, 0, s>>>(na, part, st);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t srqr_rho(const T* R11, int64_t ldr, const T* a, int64_t a_stride, const SrqrState* sel,
+                    double alpha_host, int64_t l, double* rho, SrqrState* st_out, Arena& ar, hipStream_t s) {
+  double* X = ar.take<double>((size_t)(l + 1) * l);
+  if (!X) return hipErrorOutOfMemory;
+  const size_t lds = (size_t)(2 * l + 16 * l) * sizeof(double);
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)trinv_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  trinv_kernel<T><<<(unsigned)(l + 1), NT, lds, s>>>(R11, ldr, l, a, a_stride, sel, X);
+  rho_kernel<<<1, NT, 0, s>>>(X, l, sel, alpha_host, rho, st_out);
+  return hipGetLastError();
+}
+
+hipError_t build_perm(const int64_t* S, int64_t l, int64_t n, int64_t* perm, unsigned char* inS, int64_t* cnt,
+                      hipStream_t s) {
+  const int nb = (int)((n + PB - 1) / PB);
+  const unsigned gc = (unsigned)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
+  perm_clear<<<gc, 256, 0, s>>>(n, inS);
+  perm_set<<<(unsigned)((l + 255) / 256), 256, 0, s>>>(S, l, n, inS, perm);
+  perm_count<<<nb, PB, 0, s>>>(inS, n, cnt);
+  perm_scan<<<1, 64, 0, s>>>(cnt, nb);
+  perm_scatter<<<nb, PB, 0, s>>>(inS, n, l, cnt, perm);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t assemble_rt(const T* R11, int64_t ldr11, const T* W, int64_t ldw, const int64_t* perm, int64_t l, int64_t n,
+                       T* Rt, int64_t ldrt, hipStream_t s) {
+  dim3 grid((unsigned)((n + 31) / 32), (unsigned)((l + 31) / 32));
+  assemble_rt_kernel<T><<<grid, 256, 0, s>>>(R11, ldr11, W, ldw, perm, l, n, Rt, ldrt);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t assemble_r(const T* R11, int64_t ldr11, const T* W, int64_t ldw, const int64_t* perm, int64_t l, int64_t n,
+                      T* R, int64_t ldr, hipStream_t s) {
+  dim3 grid((unsigned)((l + 255) / 256), (unsigned)n);
+  assemble_r_kernel<T><<<grid, 256, 0, s>>>(R11, ldr11, W, ldw, perm, l, n, R, ldr);
+  return hipGetLastError();
+}
+
+#define INST(T)                                                                                                   \
+  template hipError_t residual_norms<T>(const T*, int64_t, int64_t, int64_t, const double*, double*, hipStream_t); \
+  template size_t srqr_scratch<T>(int64_t, int64_t, int64_t);                                                       \
+  template hipError_t srqr_select<T>(const double*, const double*, const unsigned char*, int64_t, const T*, int64_t, \
+                                     int64_t, const T*, int64_t, const T*, int64_t, const T*, int64_t, int64_t,      \
+                                     SrqrState*, Arena&, hipStream_t);                                              \
+  template hipError_t srqr_rho<T>(const T*, int64_t, const T*, int64_t, const SrqrState*, double, int64_t, double*, \
+                                  SrqrState*, Arena&, hipStream_t);                                                 \
+  template hipError_t assemble_rt<T>(const T*, int64_t, const T*, int64_t, const int64_t*, int64_t, int64_t, T*,   \
+                                     int64_t, hipStream_t);                                                         \
+  template hipError_t assemble_r<T>(const T*, int64_t, const T*, int64_t, const int64_t*, int64_t, int64_t, T*,    \
+                                    int64_t, hipStream_t);
+INST(double)
+INST(float)
+#undef INST
+
+}  // namespace ffsrqr

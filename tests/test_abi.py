@@ -1,0 +1,126 @@
+"""The C ABI on the CPU: the library loads, exports every entry point that
+include/ffsrqr.h declares, and its host-side logic (argument checks,
+workspace sizing) behaves as documented.  No call here reaches a device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ffsrqr.h")
+LIB = os.path.join(ROOT, "paper_1803_01982_amd", "libffsrqr.so")
+
+
+def declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ffsrqr_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libffsrqr.so is not built (run __graft_entry__.build())")
+    from paper_1803_01982_amd import _lib
+    return _lib.load()
+
+
+def test_header_declares_the_path():
+    names = declared()
+    for n in ("ffsrqr_factor", "ffsrqr_workspace_size", "ffsrqr_omega", "ffsrqr_sketch", "ffsrqr_qrcp",
+              "ffsrqr_panel_qr", "ffsrqr_project", "ffsrqr_srqr_rho", "ffsrqr_lq", "ffsrqr_svd_small"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    raw = C.CDLL(LIB)
+    for name in declared():
+        assert hasattr(raw, name), name
+    from paper_1803_01982_amd import _lib
+    assert set(declared()) == set(_lib.SIGNATURES), "binding and header disagree"
+
+
+def test_status_strings(lib):
+    assert lib.ffsrqr_status_string(0) == b"ok"
+    assert lib.ffsrqr_status_string(1) == b"invalid argument"
+    assert lib.ffsrqr_status_string(99) == b"unknown status"
+
+
+def test_default_opts(lib):
+    from paper_1803_01982_amd import _lib
+    o = _lib.Opts()
+    lib.ffsrqr_default_opts(C.byref(o))
+    assert (o.precision, o.max_swaps, o.g) == (0, -1, 2.0)
+
+
+def test_workspace_size_host_only(lib):
+    from paper_1803_01982_amd import _lib
+    out = C.c_size_t(0)
+    o = _lib.Opts(0, -1, 2.0)
+    assert lib.ffsrqr_workspace_size(1000, 800, 20, 10, C.byref(o), C.byref(out)) == 0
+    small = out.value
+    assert small > 8 * (1000 * 30 + 2 * 30 * 800)      # at least the sketch, W and the panel
+    assert lib.ffsrqr_workspace_size(16384, 8192, 256, 16, C.byref(o), C.byref(out)) == 0
+    assert out.value > small
+    o32 = _lib.Opts(1, -1, 2.0)
+    big64 = out.value
+    assert lib.ffsrqr_workspace_size(16384, 8192, 256, 16, C.byref(o32), C.byref(out)) == 0
+    assert out.value < big64
+
+
+@pytest.mark.parametrize("m,n,k,p", [(0, 10, 1, 0), (10, 0, 1, 0), (10, 10, 0, 0), (10, 10, 11, 0),
+                                     (10, 10, 1, -1)])
+def test_workspace_size_rejects_bad_dims(lib, m, n, k, p):
+    out = C.c_size_t(0)
+    assert lib.ffsrqr_workspace_size(m, n, k, p, None, C.byref(out)) == 1
+    assert lib.ffsrqr_last_error()
+
+
+def test_workspace_size_rejects_bad_precision_and_null(lib):
+    from paper_1803_01982_amd import _lib
+    out = C.c_size_t(0)
+    assert lib.ffsrqr_workspace_size(10, 10, 1, 0, C.byref(_lib.Opts(7, -1, 2.0)), C.byref(out)) == 1
+    assert lib.ffsrqr_workspace_size(10, 10, 1, 0, None, None) == 1
+
+
+def _factor(lib, m=10, n=8, lda=10, k=2, p=1, ldq=10, ldl=3, ldv=8, g=2.0, prec=0, null=None):
+    from paper_1803_01982_amd import _lib
+    fake = C.c_void_p(0x1000)  # never dereferenced: the checks fail first
+    ptrs = {n_: fake for n_ in ("A", "perm", "Q", "L", "V", "sigma", "work")}
+    if null:
+        ptrs[null] = None
+    o = _lib.Opts(prec, -1, g)
+    info = _lib.Info()
+    return lib.ffsrqr_factor(ptrs["A"], m, n, lda, k, p, 0, ptrs["perm"], ptrs["Q"], ldq, ptrs["L"], ldl,
+                             ptrs["V"], ldv, ptrs["sigma"], C.byref(info), ptrs["work"], 1 << 20, C.byref(o),
+                             None)
+
+
+@pytest.mark.parametrize("kw", [dict(m=0), dict(k=0), dict(k=9), dict(p=-2), dict(lda=9), dict(ldq=9),
+                                dict(ldl=2), dict(ldv=7), dict(g=1.0), dict(g=0.5), dict(prec=3),
+                                dict(null="A"), dict(null="Q"), dict(null="sigma"), dict(null="work")])
+def test_factor_argument_checks(lib, kw):
+    assert _factor(lib, **kw) == 1
+    assert lib.ffsrqr_last_error() != b""
+
+
+def test_stage_argument_checks(lib):
+    fake = C.c_void_p(0x1000)
+    assert lib.ffsrqr_omega(0, 0, 10, fake, 10, 0, None) == 1
+    assert lib.ffsrqr_omega(0, 3, 10, fake, 9, 0, None) == 1
+    assert lib.ffsrqr_sketch(fake, 10, 5, 9, 0, 3, fake, 3, fake, fake, 100, 0, None) == 1
+    assert lib.ffsrqr_qrcp(fake, 5, 4, 5, fake, fake, fake, 100, 0, None) == 1          # n < l
+    assert lib.ffsrqr_panel_qr(fake, 10, 5, 10, fake, 11, fake, 10, fake, 11, fake, 100, 0, None) == 1
+    assert lib.ffsrqr_project(fake, 10, 3, 10, fake, 5, 10, fake, 2, fake, fake, fake, 100, 0, None) == 1
+    assert lib.ffsrqr_srqr_rho(fake, 4, 4, fake, 0.0, fake, fake, 100, 0, None) == 1   # alpha must be > 0
+    assert lib.ffsrqr_lq(fake, 4, 3, 4, fake, fake, 4, fake, 3, fake, 100, 0, None) == 1
+    assert lib.ffsrqr_svd_small(fake, 4, 3, fake, fake, 100, 0, None) == 1
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    from paper_1803_01982_amd import _lib
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(_lib.LibraryMissing):
+        _lib.load()
