@@ -226,6 +226,34 @@ ffsrqr_status ffsrqr_svd_small(const void* L, int64_t l, int64_t ldl, double* si
                                void* work, size_t work_bytes, int32_t precision,
                                ffsrqr_stream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * Device-time accounting of ffsrqr_factor, for benchmarks.  When enabled,
+ * ffsrqr_factor records HIP events around each step on the caller's stream
+ * and adds the elapsed times (milliseconds) and launch counts to per-step
+ * accumulators after its final synchronisation.  Steps:
+ * ------------------------------------------------------------------------- */
+enum {
+  FFSRQR_STEP_OMEGA = 0,     /* Omega generation                              */
+  FFSRQR_STEP_SKETCH = 1,    /* sketch GEMM B = Omega A (+ column norms)      */
+  FFSRQR_STEP_CHECK = 2,     /* non-finite scan of the column norms           */
+  FFSRQR_STEP_QRCP = 3,      /* partial QRCP on the sketch                    */
+  FFSRQR_STEP_PANEL = 4,     /* gather + Householder QR of A(:, S)            */
+  FFSRQR_STEP_PROJECT = 5,   /* projection GEMM W = Q1^T A                    */
+  FFSRQR_STEP_RESID = 6,     /* residual norms gamma^2                        */
+  FFSRQR_STEP_SRQR = 7,      /* selection, exact alpha, rho and g2            */
+  FFSRQR_STEP_LQ = 8,        /* R^T assembly + Householder QR of R^T          */
+  FFSRQR_STEP_SVD = 9,       /* one-sided Jacobi singular values of L         */
+  FFSRQR_NUM_STEPS = 10
+};
+
+/* Enable (on != 0) or disable the accounting; either call resets it.
+ * Process-wide; meant for single-threaded benchmark drivers. */
+void ffsrqr_profile_enable(int on);
+
+/* Copy min(nsteps, FFSRQR_NUM_STEPS) accumulators (host arrays) and return
+ * FFSRQR_NUM_STEPS. */
+int ffsrqr_profile_read(double* ms, int64_t* launches, int nsteps);
+
 #ifdef __cplusplus
 }
 #endif

@@ -6,11 +6,11 @@ it, and the first call raises ``LibraryMissing`` if it is absent.
 """
 from ._lib import (FLAG_L_CLAMPED, FLAG_NONFINITE, FLAG_RANK_DEFICIENT, FLAG_SWAPCAP, FLAG_TIMEOUT, FP32, FP64,
                    FfsrqrError, LibraryMissing, load)
-from .api import (Factorization, empty_fortran, factor, fortran, lq, omega, panel_qr, project, qrcp, sketch,
-                  srqr_rho, svd_small, workspace, workspace_size)
+from .api import (Factorization, empty_fortran, factor, fortran, lq, omega, panel_qr, profile_enable, profile_read,
+                  project, qrcp, sketch, srqr_rho, svd_small, workspace, workspace_size)
 
 __all__ = [
     "FLAG_L_CLAMPED", "FLAG_NONFINITE", "FLAG_RANK_DEFICIENT", "FLAG_SWAPCAP", "FLAG_TIMEOUT", "FP32", "FP64",
     "FfsrqrError", "LibraryMissing", "load", "Factorization", "empty_fortran", "factor", "fortran", "lq", "omega",
-    "panel_qr", "project", "qrcp", "sketch", "srqr_rho", "svd_small", "workspace", "workspace_size",
+    "panel_qr", "profile_enable", "profile_read", "project", "qrcp", "sketch", "srqr_rho", "svd_small", "workspace", "workspace_size",
 ]

@@ -207,3 +207,18 @@ def svd_small(Lm: torch.Tensor, work=None, stream=None) -> torch.Tensor:
     L.check(lib.ffsrqr_svd_small(_ptr(Lm), l, _ld(Lm), _ptr(sig), _ptr(work), work.numel(), _prec(Lm.dtype),
                                  _stream(stream)), "ffsrqr_svd_small")
     return sig
+
+
+def profile_enable(on: bool = True) -> None:
+    """Enable (and reset) the per-step device-time accounting of factor()."""
+    L.load().ffsrqr_profile_enable(1 if on else 0)
+
+
+def profile_read() -> dict:
+    """{step: (milliseconds, launches)} accumulated since profile_enable()."""
+    lib = L.load()
+    n = len(L.STEPS)
+    ms = (C.c_double * n)()
+    cnt = (C.c_int64 * n)()
+    lib.ffsrqr_profile_read(ms, cnt, n)
+    return {name: (ms[i], cnt[i]) for i, name in enumerate(L.STEPS)}

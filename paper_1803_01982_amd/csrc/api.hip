@@ -33,6 +33,61 @@ ffsrqr_status fail(ffsrqr_status s, const std::string& msg) {
 std::mutex g_dev_mu;
 DeviceInfo g_dev[64];
 
+// ---------------------------------------------------------------- profiling
+struct Profile {
+  std::mutex mu;
+  bool on = false;
+  double ms[FFSRQR_NUM_STEPS] = {};
+  int64_t launches[FFSRQR_NUM_STEPS] = {};
+} g_prof;
+
+// Events around the steps of one ffsrqr_factor call, on its stream.
+class StepTimer {
+ public:
+  explicit StepTimer(hipStream_t s) : s_(s) {
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    on_ = g_prof.on;
+  }
+  ~StepTimer() {
+    for (auto& r : recs_) {
+      hipEventDestroy(r.a);
+      hipEventDestroy(r.b);
+    }
+  }
+  void begin(int step) {
+    if (!on_) return;
+    Rec r{step, nullptr, nullptr};
+    if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return;
+    hipEventRecord(r.a, s_);
+    recs_.push_back(r);
+  }
+  void end() {
+    if (!on_ || recs_.empty()) return;
+    hipEventRecord(recs_.back().b, s_);
+  }
+  // after the stream has been synchronised
+  void collect() {
+    if (!on_) return;
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    for (auto& r : recs_) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+        g_prof.ms[r.step] += ms;
+        g_prof.launches[r.step] += 1;
+      }
+    }
+  }
+
+ private:
+  struct Rec {
+    int step;
+    hipEvent_t a, b;
+  };
+  hipStream_t s_;
+  bool on_ = false;
+  std::vector<Rec> recs_;
+};
+
 bool valid_precision(int32_t p) { return p == FFSRQR_FP64 || p == FFSRQR_FP32; }
 size_t elem_size(int32_t p) { return p == FFSRQR_FP64 ? sizeof(double) : sizeof(float); }
 
@@ -158,18 +213,25 @@ ffsrqr_status factor_impl(const T* A, int64_t m, int64_t n, int64_t lda, int64_t
   auto scratch = [&]() { return Arena{(char*)work, work_bytes, scratch_off}; };
   if (!err) return fail(FFSRQR_EWORKSPACE, "workspace carving failed");
 
+  StepTimer tm(s);
   FF_HIP(zero_words(err, 64, s));
   // a1: Omega and the sketch (one pass over A, column norms fused)
+  tm.begin(FFSRQR_STEP_OMEGA);
   FF_HIP(launch_omega<T>(seed, l, m, region1, m, s));
+  tm.end();
   {
     Arena a = scratch();
+    tm.begin(FFSRQR_STEP_SKETCH);
     FF_HIP(gemm_tn<T>(l, n, m, region1, m, A, lda, region2, l, anorm2, a, d.num_cu, s));
+    tm.end();
   }
   // non-finite input: report and stop before any pivoting
   {
     Arena a = scratch();
     FF_HIP(hipMemsetAsync(inS, 0, (size_t)n, s));
+    tm.begin(FFSRQR_STEP_CHECK);
     FF_HIP(srqr_select<T>(anorm2, anorm2, inS, n, A, m, lda, Q, ldq, W, l, R11, l, 0, st, a, s));
+    tm.end();
     SrqrState hs;
     FF_HIP(hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, s));
     FF_HIP(hipStreamSynchronize(s));
@@ -203,7 +265,9 @@ ffsrqr_status factor_impl(const T* A, int64_t m, int64_t n, int64_t lda, int64_t
   // a2: partial QRCP on the sketch -> S
   {
     Arena a = scratch();
+    tm.begin(FFSRQR_STEP_QRCP);
     FF_HIP(qrcp<T>(region2, l, n, l, S, margins, a, err, d, s));
+    tm.end();
   }
   std::vector<double> hmarg((size_t)l);
   FF_HIP(hipMemcpyAsync(hmarg.data(), margins, (size_t)l * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -214,18 +278,25 @@ ffsrqr_status factor_impl(const T* A, int64_t m, int64_t n, int64_t lda, int64_t
   int64_t numerical_rank = l;
   for (;;) {
     // a3: Householder QR of A(:, S); a4: projection and residual norms
+    tm.begin(FFSRQR_STEP_PANEL);
     FF_HIP(build_perm(S, l, n, perm, inS, cnt, s));
     FF_HIP(gather_cols<T>(A, m, n, lda, perm, l, region1, m, s));
     {
       Arena a = scratch();
       FF_HIP(tall_qr<T>(region1, m, l, m, Q, ldq, nullptr, R11, l, false, a, err, d, s));
     }
+    tm.end();
     {
       Arena a = scratch();
+      tm.begin(FFSRQR_STEP_PROJECT);
       FF_HIP(gemm_tn<T>(l, n, m, Q, ldq, A, lda, W, l, nullptr, a, d.num_cu, s));
+      tm.end();
     }
+    tm.begin(FFSRQR_STEP_RESID);
     FF_HIP(residual_norms<T>(W, l, n, l, anorm2, gamma2, s));
+    tm.end();
     // a5: SRQR test
+    tm.begin(FFSRQR_STEP_SRQR);
     {
       Arena a = scratch();
       FF_HIP(srqr_select<T>(gamma2, anorm2, inS, n, A, m, lda, Q, ldq, W, l, R11, l, l, st, a, s));
@@ -234,15 +305,20 @@ ffsrqr_status factor_impl(const T* A, int64_t m, int64_t n, int64_t lda, int64_t
       Arena a = scratch();
       FF_HIP(srqr_rho<T>(R11, l, W, l, st, 0.0, l, rho, st, a, s));
     }
+    tm.end();
     // a6, a7 (issued before the swap decision is known; redone after a swap)
+    tm.begin(FFSRQR_STEP_LQ);
     FF_HIP(assemble_rt<T>(R11, l, W, l, perm, l, n, region2, n, s));
     {
       Arena a = scratch();
       FF_HIP(tall_qr<T>(region2, n, l, n, V, ldv, perm, L, ldl, true, a, err, d, s));
     }
+    tm.end();
     {
       Arena a = scratch();
+      tm.begin(FFSRQR_STEP_SVD);
       FF_HIP(jacobi_sigma<T>(L, l, ldl, sigma, a, err, d, s));
+      tm.end();
     }
     unsigned herr = 0;
     FF_HIP(hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, s));
@@ -285,6 +361,7 @@ ffsrqr_status factor_impl(const T* A, int64_t m, int64_t n, int64_t lda, int64_t
     FF_HIP(hipMemcpyAsync(S, hS.data(), (size_t)l * sizeof(int64_t), hipMemcpyHostToDevice, s));
     ++swaps;
   }
+  tm.collect();
   if (info) {
     double mm = 1.0;
     for (double x : hmarg) mm = std::min(mm, x);
@@ -343,6 +420,24 @@ const char* ffsrqr_status_string(ffsrqr_status s) {
 }
 
 const char* ffsrqr_last_error(void) { return g_last_error.c_str(); }
+
+void ffsrqr_profile_enable(int on) {
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  g_prof.on = on != 0;
+  for (int i = 0; i < FFSRQR_NUM_STEPS; ++i) {
+    g_prof.ms[i] = 0.0;
+    g_prof.launches[i] = 0;
+  }
+}
+
+int ffsrqr_profile_read(double* ms, int64_t* launches, int nsteps) {
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  for (int i = 0; i < nsteps && i < FFSRQR_NUM_STEPS; ++i) {
+    if (ms) ms[i] = g_prof.ms[i];
+    if (launches) launches[i] = g_prof.launches[i];
+  }
+  return FFSRQR_NUM_STEPS;
+}
 
 ffsrqr_status ffsrqr_workspace_size(int64_t m, int64_t n, int64_t k, int64_t p, const ffsrqr_opts* opts,
                                     size_t* bytes) {

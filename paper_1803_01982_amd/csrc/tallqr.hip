@@ -109,7 +109,7 @@ __global__ __launch_bounds__(NT) void tallqr_kernel(T* __restrict__ P, int64_t m
   extern __shared__ double smem[];
   __shared__ double red[NB * NB];
   __shared__ double Tl[NB * NB];
-  __shared__ double s_sc[4];
+  __shared__ double taul[NB];
   const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
   const int64_t r0 = (int64_t)g * rb;
   const int nrow = (int)max((int64_t)0, min((int64_t)rb, mrows - r0));
@@ -172,6 +172,7 @@ __global__ __launch_bounds__(NT) void tallqr_kernel(T* __restrict__ P, int64_t m
         tau = (beta - x0) / beta;
         scale = 1.0 / (x0 - beta);
       }
+      if (tid == 0) taul[jt] = tau;
       if (g == 0 && tid == 0) sl.tau[jc] = tau;
       // own rows: p_t -= tau w_t v, w_t = p_t(jc) + scale d_t
       for (int e = tid; e < nrow * NB; e += NT) {
@@ -212,7 +213,7 @@ __global__ __launch_bounds__(NT) void tallqr_kernel(T* __restrict__ P, int64_t m
     if (tid < NB * NB) Tl[tid] = 0.0;
     __syncthreads();
     for (int s = 0; s < pw; ++s) {
-      const double ts = sl.tau[p0 + s];
+      const double ts = taul[s];
       double val = 0.0;
       if (tid < s) {
         for (int q = tid; q < s; ++q) val += Tl[q * NB + tid] * Zl[s * NB + q];
@@ -255,6 +256,8 @@ __global__ __launch_bounds__(NT) void tallqr_kernel(T* __restrict__ P, int64_t m
   }
 
   // --------------------------------------------------- explicit Q, backwards
+  // the T factors written by workgroup 0 at the panel ends must be visible
+  if (!grid_barrier(gs, epoch)) return;
   for (int e = tid; e < nrow * c; e += NT) {
     const int i = e % nrow, j = e / nrow;
     const int64_t gi = r0 + i;
