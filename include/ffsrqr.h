@@ -89,6 +89,8 @@ typedef struct {
   int64_t jstar;          /* original index of that column (-1 when l == n)        */
   int64_t numerical_rank; /* l unless RANK_DEFICIENT                               */
   double min_margin;      /* min over QRCP-on-B steps of (r_max - r_2nd) / r_max   */
+  int32_t jacobi_sweeps;  /* sweeps of the one-sided Jacobi on L                   */
+  int32_t reserved;
 } ffsrqr_info;
 
 /* Default options: FP64, g = 2, max_swaps = 4 l. */

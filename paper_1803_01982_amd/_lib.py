@@ -27,7 +27,7 @@ class Opts(C.Structure):
 class Info(C.Structure):
     _fields_ = [("l", C.c_int64), ("swaps", C.c_int32), ("flags", C.c_uint32), ("g2", C.c_double),
                 ("alpha", C.c_double), ("jstar", C.c_int64), ("numerical_rank", C.c_int64),
-                ("min_margin", C.c_double)]
+                ("min_margin", C.c_double), ("jacobi_sweeps", C.c_int32), ("reserved", C.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -273,6 +273,7 @@ ffsrqr_status factor_impl(const T* A, int64_t m, int64_t n, int64_t lda, int64_t
   FF_HIP(hipMemcpyAsync(hmarg.data(), margins, (size_t)l * sizeof(double), hipMemcpyDeviceToHost, s));
 
   int32_t swaps = 0;
+  int32_t jacobi_sweeps = 0;
   SrqrState hs{};
   double g2 = 1.0;
   int64_t numerical_rank = l;
@@ -283,7 +284,7 @@ ffsrqr_status factor_impl(const T* A, int64_t m, int64_t n, int64_t lda, int64_t
     FF_HIP(gather_cols<T>(A, m, n, lda, perm, l, region1, m, s));
     {
       Arena a = scratch();
-      FF_HIP(tall_qr<T>(region1, m, l, m, Q, ldq, nullptr, R11, l, false, a, err, d, s));
+      FF_HIP(tall_qr<T>(region1, m, l, m, Q, ldq, R11, l, false, a, err, d, s));
     }
     tm.end();
     {
@@ -310,21 +311,25 @@ ffsrqr_status factor_impl(const T* A, int64_t m, int64_t n, int64_t lda, int64_t
     tm.begin(FFSRQR_STEP_LQ);
     FF_HIP(assemble_rt<T>(R11, l, W, l, perm, l, n, region2, n, s));
     {
+      // Qhat1 (n x l) in natural row order goes to W's buffer (W is dead
+      // once R^T is assembled), then V = Pi Qhat1 by a row scatter
       Arena a = scratch();
-      FF_HIP(tall_qr<T>(region2, n, l, n, V, ldv, perm, L, ldl, true, a, err, d, s));
+      FF_HIP(tall_qr<T>(region2, n, l, n, W, n, L, ldl, true, a, err, d, s));
+      FF_HIP(scatter_rows<T>(W, n, l, n, perm, V, ldv, s));
     }
     tm.end();
     {
       Arena a = scratch();
       tm.begin(FFSRQR_STEP_SVD);
-      FF_HIP(jacobi_sigma<T>(L, l, ldl, sigma, a, err, d, s));
+      FF_HIP(jacobi_sigma<T>(L, l, ldl, sigma, a, err, d, s, (int*)(err + 32)));
       tm.end();
     }
-    unsigned herr = 0;
+    unsigned herr[64];
     FF_HIP(hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, s));
-    FF_HIP(hipMemcpyAsync(&herr, err, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+    FF_HIP(hipMemcpyAsync(herr, err, sizeof(herr), hipMemcpyDeviceToHost, s));
     FF_HIP(hipStreamSynchronize(s));
-    if (herr) {
+    jacobi_sweeps = (int32_t)herr[32];
+    if (herr[0]) {
       flags |= FFSRQR_FLAG_TIMEOUT;
       return fail(FFSRQR_EHIP, "a device-wide wait exceeded its spin limit");
     }
@@ -373,6 +378,8 @@ ffsrqr_status factor_impl(const T* A, int64_t m, int64_t n, int64_t lda, int64_t
     info->jstar = hs.jstar;
     info->numerical_rank = numerical_rank;
     info->min_margin = mm;
+    info->jacobi_sweeps = jacobi_sweeps;
+    info->reserved = 0;
   }
   return FFSRQR_OK;
 }
@@ -543,10 +550,10 @@ ffsrqr_status ffsrqr_panel_qr(const void* A, int64_t m, int64_t n, int64_t lda, 
   hipError_t e;
   if (precision == FFSRQR_FP64) {
     FF_HIP(gather_cols<double>((const double*)A, m, n, lda, cols, c, (double*)P, m, s));
-    e = tall_qr<double>((double*)P, m, c, m, (double*)Q, ldq, nullptr, (double*)R, ldr, false, ar, err, *d, s);
+    e = tall_qr<double>((double*)P, m, c, m, (double*)Q, ldq, (double*)R, ldr, false, ar, err, *d, s);
   } else {
     FF_HIP(gather_cols<float>((const float*)A, m, n, lda, cols, c, (float*)P, m, s));
-    e = tall_qr<float>((float*)P, m, c, m, (float*)Q, ldq, nullptr, (float*)R, ldr, false, ar, err, *d, s);
+    e = tall_qr<float>((float*)P, m, c, m, (float*)Q, ldq, (float*)R, ldr, false, ar, err, *d, s);
   }
   if (e == hipErrorOutOfMemory) return fail(FFSRQR_EWORKSPACE, "workspace too small");
   FF_HIP(e);
@@ -613,15 +620,18 @@ ffsrqr_status ffsrqr_lq(const void* R, int64_t l, int64_t n, int64_t ldr, const 
   unsigned* err = ar.take<unsigned>(64);
   const size_t es = elem_size(precision);
   char* Rt = ar.take<char>((size_t)n * l * es);
-  if (!err || !Rt) return fail(FFSRQR_EWORKSPACE, "workspace too small");
+  char* Qh = ar.take<char>((size_t)n * l * es);
+  if (!err || !Rt || !Qh) return fail(FFSRQR_EWORKSPACE, "workspace too small");
   FF_HIP(zero_words(err, 64, s));
   hipError_t e;
   if (precision == FFSRQR_FP64) {
     FF_HIP(assemble_rt<double>((const double*)R, ldr, (const double*)R, ldr, nullptr, l, n, (double*)Rt, n, s));
-    e = tall_qr<double>((double*)Rt, n, l, n, (double*)V, ldv, perm, (double*)L, ldl, true, ar, err, *d, s);
+    e = tall_qr<double>((double*)Rt, n, l, n, (double*)Qh, n, (double*)L, ldl, true, ar, err, *d, s);
+    if (e == hipSuccess) e = scatter_rows<double>((const double*)Qh, n, l, n, perm, (double*)V, ldv, s);
   } else {
     FF_HIP(assemble_rt<float>((const float*)R, ldr, (const float*)R, ldr, nullptr, l, n, (float*)Rt, n, s));
-    e = tall_qr<float>((float*)Rt, n, l, n, (float*)V, ldv, perm, (float*)L, ldl, true, ar, err, *d, s);
+    e = tall_qr<float>((float*)Rt, n, l, n, (float*)Qh, n, (float*)L, ldl, true, ar, err, *d, s);
+    if (e == hipSuccess) e = scatter_rows<float>((const float*)Qh, n, l, n, perm, (float*)V, ldv, s);
   }
   if (e == hipErrorOutOfMemory) return fail(FFSRQR_EWORKSPACE, "workspace too small");
   FF_HIP(e);

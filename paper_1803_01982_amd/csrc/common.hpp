@@ -92,30 +92,50 @@ __device__ inline ArgMax block_argmax(ArgMax a, double* rv, int64_t* ri) {
 }
 
 // ------------------------------------------------------------ grid barrier
-// Device-wide barrier for cooperative (co-resident) launches.  `counter`
-// starts at zero for each launch and only grows: barrier number e completes
-// when it reaches e * nblocks.  The wait is bounded: past the spin limit the
-// block raises `error` and returns false; every block then leaves its loop
-// within one more bounded wait, so the grid always drains.
+// Device-wide barrier for cooperative (co-resident) launches.
+//
+// On gfx950 an agent-scope release is an L2 writeback and an agent-scope
+// acquire an L2 invalidate, and their cost grows with the number of
+// workgroups per XCD, so only one thread per workgroup fences: the
+// workgroup barrier before it completes every wave's stores to L2, and the
+// invalidate after it covers the CU's vector cache for all waves.  Arrival
+// is counted in groups of 16 workgroups, then across groups; the last
+// arrival publishes the new generation, which the others poll with relaxed
+// loads (no cache maintenance per poll).
+//
+// `sync` (kSyncWords words, zeroed before each launch) holds the counters;
+// every wait is bounded: past the spin limit the block raises `error` and
+// returns false, and every other block then leaves within one more bounded
+// wait, so the grid always drains.
+constexpr int kSyncWords = 1024;
+constexpr unsigned kSpinLimit = 1u << 22;
+constexpr unsigned kGroup = 16;
+
 struct GridSync {
-  unsigned* counter;
+  unsigned* sync;   // [0]: arrivals of groups, [32]: generation, [64 + 32 g]: group arrivals
   unsigned* error;
   unsigned nblocks;
 };
 
-constexpr unsigned kSpinLimit = 1u << 22;
-
 __device__ inline bool grid_barrier(const GridSync& gs, unsigned& epoch) {
   __shared__ int s_ok;
-  __threadfence();
   __syncthreads();
   ++epoch;
+  if (gs.nblocks == 1) return true;  // one workgroup: the workgroup barrier suffices
   if (threadIdx.x == 0) {
     int ok = 1;
-    __hip_atomic_fetch_add(gs.counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned target = epoch * gs.nblocks;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const unsigned grp = blockIdx.x / kGroup, ngrp = (gs.nblocks + kGroup - 1) / kGroup;
+    const unsigned gsize = (grp == ngrp - 1) ? gs.nblocks - grp * kGroup : kGroup;
+    const unsigned old = __hip_atomic_fetch_add(gs.sync + 64 + 32 * grp, 1u, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+    if (old == epoch * gsize - 1) {
+      const unsigned o2 = __hip_atomic_fetch_add(gs.sync, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (o2 == epoch * ngrp - 1)
+        __hip_atomic_store(gs.sync + 32, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     unsigned spins = 0;
-    while (__hip_atomic_load(gs.counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    while (__hip_atomic_load(gs.sync + 32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
       __builtin_amdgcn_s_sleep(1);
       if ((++spins & 255u) == 0) {
         if (__hip_atomic_load(gs.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
@@ -126,10 +146,10 @@ __device__ inline bool grid_barrier(const GridSync& gs, unsigned& epoch) {
         }
       }
     }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     s_ok = ok;
   }
   __syncthreads();
-  __threadfence();
   return s_ok != 0;
 }
 

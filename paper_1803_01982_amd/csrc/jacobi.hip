@@ -7,9 +7,10 @@
 // P = 2G blocks of bs columns; a round-robin tournament (circle method) pairs
 // the blocks so that in each of the P-1 rounds of a sweep every block meets
 // one other block.  Workgroup g takes pair g of the round, copies the two
-// blocks into LDS, runs one cyclic pass over every column pair of the union
-// (pairs in parallel rounds, one wave per pair) and writes them back; one
-// grid barrier per round.  A pair (p, q) is rotated when
+// blocks into LDS and rotates the cross pairs (one column of each block);
+// in the first round of a sweep it rotates every pair of the union, which
+// covers the pairs inside each block once per sweep.  Pairs run in parallel
+// rounds, one wave per pair; one grid barrier per round.  A pair (p, q) is rotated when
 // |c_p . c_q| > tol ||c_p|| ||c_q|| (tol = 1e-14), with Rutishauser's
 // formulas; the iteration stops after a sweep with no rotation (at most 60
 // sweeps).  sigma_j = ||c_j||, sorted descending.
@@ -32,9 +33,13 @@ __device__ inline int rr_player(int pos, int r, int P) {
 template <typename T>
 __global__ __launch_bounds__(NT) void jacobi_kernel(const T* __restrict__ L, int l, int64_t ldl, double* __restrict__ M,
                                                     int bs, int P, unsigned* __restrict__ rot,
-                                                    double* __restrict__ sig, GridSync gs) {
+                                                    double* __restrict__ sig, int* __restrict__ sweeps_out,
+                                                    GridSync gs) {
   extern __shared__ double C[];  // 2*bs columns of length l
   __shared__ int s_rot;
+  __shared__ double dn[64];       // squared norms of the 2*bs local columns
+  __shared__ unsigned short sched_full[31 * 16];
+  __shared__ unsigned short sched_cross[16 * 16];
   const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6, nwave = NT / 64;
   unsigned epoch = 0;
@@ -47,40 +52,58 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(const T* __restrict__ L, int
   if (!grid_barrier(gs, epoch)) return;
 
   const int W2 = 2 * bs;
+  // pair schedules of the local columns, built once:
+  //   full: all W2(W2-1)/2 pairs of the union in W2-1 rounds of bs disjoint
+  //         pairs (circle method), used in the first round of every sweep;
+  //   cross: the bs*bs pairs (block a, block b) in bs rounds (p, bs + (p+r) % bs).
+  for (int e = tid; e < (W2 - 1) * bs; e += NT) {
+    const int ir = e / bs, pr = e % bs;
+    const int p = rr_player(pr, ir, W2), q = rr_player(W2 - 1 - pr, ir, W2);
+    sched_full[e] = (unsigned short)((min(p, q) << 8) | max(p, q));
+  }
+  for (int e = tid; e < bs * bs; e += NT) {
+    const int ir = e / bs, p = e % bs;
+    sched_cross[e] = (unsigned short)((p << 8) | (bs + (p + ir) % bs));
+  }
+  __syncthreads();
   int sweep = 0;
   for (sweep = 0; sweep < kMaxSweeps; ++sweep) {
     if (g == 0 && tid == 0) rot[(sweep + 1) % 3] = 0u;
     if (tid == 0) s_rot = 0;
     for (int r = 0; r < P - 1; ++r) {
       // blocks of this workgroup's pair
-      const int pa = rr_player(g == 0 ? 0 : g, r, P);
+      const int pa = rr_player(g, r, P);
       const int pb = rr_player(P - 1 - g, r, P);
       const int ca0 = pa * bs, cb0 = pb * bs;
       const int na = max(0, min(bs, l - ca0)), nbk = max(0, min(bs, l - cb0));
       // local column k < bs -> block a column k, k >= bs -> block b column k - bs
-      for (int e = tid; e < W2 * l; e += NT) {
-        const int k = e / l, row = e % l;
+      for (int k = wave; k < W2; k += nwave) {
         const int gc = k < bs ? (k < na ? ca0 + k : -1) : (k - bs < nbk ? cb0 + k - bs : -1);
-        C[k * l + row] = gc >= 0 ? M[(int64_t)gc * l + row] : 0.0;
+        double a = 0.0;
+        for (int i = lane; i < l; i += 64) {
+          const double x = gc >= 0 ? M[(int64_t)gc * l + i] : 0.0;
+          C[k * l + i] = x;
+          a += x * x;
+        }
+        a = wave_sum(a);
+        if (lane == 0) dn[k] = a;  // fresh squared norms of the local columns
       }
       __syncthreads();
-      // one pass over all pairs of the W2 columns, in W2-1 parallel rounds
-      for (int ir = 0; ir < W2 - 1; ++ir) {
+      // one pass over the scheduled pairs; the norms follow each rotation
+      // (a - t g, b + t g), so each pair needs one dot product
+      const bool full = (r == 0);
+      const int nir = full ? W2 - 1 : bs;
+      const unsigned short* sched = full ? sched_full : sched_cross;
+      for (int ir = 0; ir < nir; ++ir) {
         for (int pr = wave; pr < bs; pr += nwave) {
-          const int p = rr_player(pr, ir, W2), q = rr_player(W2 - 1 - pr, ir, W2);
-          const int lo = p < q ? p : q, hi = p < q ? q : p;
+          const unsigned pq = sched[ir * bs + pr];
+          const int lo = (int)(pq >> 8), hi = (int)(pq & 255u);
           double* cp = C + lo * l;
           double* cq = C + hi * l;
-          double a = 0.0, b = 0.0, gg = 0.0;
-          for (int i = lane; i < l; i += 64) {
-            const double x = cp[i], y = cq[i];
-            a += x * x;
-            b += y * y;
-            gg += x * y;
-          }
-          a = wave_sum(a);
-          b = wave_sum(b);
+          double gg = 0.0;
+          for (int i = lane; i < l; i += 64) gg += cp[i] * cq[i];
           gg = wave_sum(gg);
+          const double a = dn[lo], b = dn[hi];
           if (a == 0.0 || b == 0.0 || fabs(gg) <= kTol * sqrt(a * b)) continue;
           const double zeta = (b - a) / (2.0 * gg);
           const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
@@ -90,14 +113,18 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(const T* __restrict__ L, int
             cp[i] = cs * x - sn * y;
             cq[i] = sn * x + cs * y;
           }
-          if (lane == 0) s_rot = 1;
+          if (lane == 0) {
+            dn[lo] = a - t * gg;
+            dn[hi] = b + t * gg;
+            s_rot = 1;
+          }
         }
         __syncthreads();
       }
-      for (int e = tid; e < W2 * l; e += NT) {
-        const int k = e / l, row = e % l;
+      for (int k = wave; k < W2; k += nwave) {
         const int gc = k < bs ? (k < na ? ca0 + k : -1) : (k - bs < nbk ? cb0 + k - bs : -1);
-        if (gc >= 0) M[(int64_t)gc * l + row] = C[k * l + row];
+        if (gc >= 0)
+          for (int i = lane; i < l; i += 64) M[(int64_t)gc * l + i] = C[k * l + i];
       }
       if (!grid_barrier(gs, epoch)) return;
     }
@@ -106,6 +133,7 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(const T* __restrict__ L, int
     const unsigned any = __hip_atomic_load(&rot[sweep % 3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (!any) break;
   }
+  if (g == 0 && tid == 0 && sweeps_out) *sweeps_out = sweep < kMaxSweeps ? sweep + 1 : kMaxSweeps;
   // column norms
   for (int c = g * nwave + wave; c < l; c += G * nwave) {
     double s = 0.0;
@@ -132,8 +160,8 @@ __global__ void sort_desc(const double* __restrict__ in, int l, double* __restri
 }
 
 void choose(int64_t l, const DeviceInfo& d, int* bs, int* P, size_t* lds) {
-  int b = 16;
-  while (b > 1 && (size_t)2 * b * l * sizeof(double) > d.lds_max - 1024) --b;
+  int b = 16;  // at most 32 local columns (dn has 64 slots)
+  while (b > 1 && (size_t)2 * b * l * sizeof(double) > d.lds_max - 2048) --b;
   if (l < 2 * b) b = (int)((l + 1) / 2 > 0 ? (l + 1) / 2 : 1);
   int p = (int)((l + b - 1) / b);
   if (p < 2) p = 2;
@@ -147,27 +175,27 @@ void choose(int64_t l, const DeviceInfo& d, int* bs, int* P, size_t* lds) {
 
 template <typename T>
 size_t jacobi_scratch(int64_t l, const DeviceInfo& d) {
-  return sizeof(double) * ((size_t)l * l + l) + 64 * sizeof(unsigned) + 8 * 256;
+  return sizeof(double) * ((size_t)l * l + l) + (kSyncWords + 64) * sizeof(unsigned) + 8 * 256;
 }
 
 template <typename T>
 hipError_t jacobi_sigma(const T* L, int64_t l, int64_t ldl, double* sigma, Arena& ar, unsigned* err,
-                        const DeviceInfo& d, hipStream_t s) {
+                        const DeviceInfo& d, hipStream_t s, int* sweeps) {
   if (l <= 0) return hipSuccess;
   int bs, P;
   size_t lds;
   choose(l, d, &bs, &P, &lds);
   double* M = ar.take<double>((size_t)l * l);
   double* sig = ar.take<double>(l);
-  unsigned* ctl = ar.take<unsigned>(64);
+  unsigned* ctl = ar.take<unsigned>(kSyncWords + 64);
   if (!M || !sig || !ctl) return hipErrorOutOfMemory;
-  hipError_t e = zero_words(ctl, 64, s);
+  hipError_t e = zero_words(ctl, kSyncWords + 64, s);
   if (e != hipSuccess) return e;
   GridSync gs{ctl, err, (unsigned)(P / 2)};
-  unsigned* rot = ctl + 16;
+  unsigned* rot = ctl + kSyncWords;
   int li = (int)l;
   void* args[] = {(void*)&L, (void*)&li, (void*)&ldl, (void*)&M, (void*)&bs, (void*)&P, (void*)&rot, (void*)&sig,
-                  (void*)&gs};
+                  (void*)&sweeps, (void*)&gs};
   const void* fn = (const void*)jacobi_kernel<T>;
   if (lds > 65536) {
     e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -182,8 +210,8 @@ hipError_t jacobi_sigma(const T* L, int64_t l, int64_t ldl, double* sigma, Arena
 template size_t jacobi_scratch<double>(int64_t, const DeviceInfo&);
 template size_t jacobi_scratch<float>(int64_t, const DeviceInfo&);
 template hipError_t jacobi_sigma<double>(const double*, int64_t, int64_t, double*, Arena&, unsigned*,
-                                         const DeviceInfo&, hipStream_t);
+                                         const DeviceInfo&, hipStream_t, int*);
 template hipError_t jacobi_sigma<float>(const float*, int64_t, int64_t, double*, Arena&, unsigned*,
-                                        const DeviceInfo&, hipStream_t);
+                                        const DeviceInfo&, hipStream_t, int*);
 
 }  // namespace ffsrqr

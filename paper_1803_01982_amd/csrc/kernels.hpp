@@ -58,15 +58,17 @@ template <typename T>
 hipError_t gather_cols(const T* A, int64_t m, int64_t n, int64_t lda, const int64_t* cols, int64_t c, T* P,
                        int64_t ldp, hipStream_t s);
 
-// Householder QR of P (mrows x c, in place): explicit Q (row i written to
-// row rowmap[i] of Qout, or row i when rowmap is null) and R (c x c, or its
-// transpose when transpose_r), with diag(R) >= 0.
+// Householder QR of P (mrows x c, in place): explicit Q (mrows x c, ldq) and
+// R (c x c, or its transpose when transpose_r), with diag(R) >= 0.
 template <typename T>
 size_t tallqr_scratch(int64_t mrows, int64_t c, const DeviceInfo& d);
 template <typename T>
-hipError_t tall_qr(T* P, int64_t mrows, int64_t c, int64_t ldp, T* Qout, int64_t ldq,
-                   const int64_t* rowmap, T* R, int64_t ldr, bool transpose_r, Arena& ar,
-                   unsigned* err, const DeviceInfo& d, hipStream_t s);
+hipError_t tall_qr(T* P, int64_t mrows, int64_t c, int64_t ldp, T* Qout, int64_t ldq, T* R, int64_t ldr,
+                   bool transpose_r, Arena& ar, unsigned* err, const DeviceInfo& d, hipStream_t s);
+// V(rowmap[i], :) = Q(i, :) for i < mrows (entries outside [0, mrows) skipped).
+template <typename T>
+hipError_t scatter_rows(const T* Q, int64_t mrows, int64_t c, int64_t ldq, const int64_t* rowmap, T* V,
+                        int64_t ldv, hipStream_t s);
 
 // Rt (n x l): row i = R11(:, i)^T for i < l, W(:, perm[i])^T for i >= l.
 template <typename T>
@@ -117,6 +119,6 @@ template <typename T>
 size_t jacobi_scratch(int64_t l, const DeviceInfo& d);
 template <typename T>
 hipError_t jacobi_sigma(const T* L, int64_t l, int64_t ldl, double* sigma, Arena& ar, unsigned* err,
-                        const DeviceInfo& d, hipStream_t s);
+                        const DeviceInfo& d, hipStream_t s, int* sweeps = nullptr);
 
 }  // namespace ffsrqr

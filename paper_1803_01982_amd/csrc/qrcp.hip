@@ -1,7 +1,7 @@
 // Partial QRCP on the sketch B (Algorithm 1 applied to B for l steps; the
 // pivot search of Algorithm 2).
 //
-// One cooperative launch, one workgroup per CU.  Workgroup g owns a
+// One cooperative launch on as few workgroups as LDS allows.  Workgroup g owns a
 // contiguous slice of nc columns of B, kept in LDS (or in a global copy when
 // the slice does not fit) for all l steps.  Step j:
 //   1. each workgroup publishes its best active column (largest residual
@@ -33,6 +33,15 @@ struct QrcpSlots {
   double* col;    // [2][G][l]
 };
 
+// Column stride of the B slices: l rounded up so that it is an odd number of
+// 8-byte words.
+__host__ __device__ inline int ldbl_for(int64_t l, size_t tsize) {
+  if (tsize == 8) return (int)(l | 1);
+  int64_t w = (l + 1) / 2;  // 8-byte words per float column
+  if (!(w & 1)) ++w;
+  return (int)(2 * w);
+}
+
 __device__ inline int group_size_for(int nc) {
   int g = 1;
   while (g * 2 * nc <= NT && g < 64) g *= 2;
@@ -56,11 +65,14 @@ __global__ __launch_bounds__(NT) void qrcp_kernel(const T* __restrict__ B, int64
   double* v = smem;            // l
   double* rloc = v + l;        // nc
   int* act = (int*)(rloc + nc);  // nc (padded to an even count)
-  T* Bl = IN_LDS ? (T*)(smem + l + nc + (nc + 1) / 2) : Bw + (int64_t)g * nc * l;
+  // column slices with an odd stride (in 8-byte words) so that lanes working
+  // on different columns fall in different LDS banks
+  const int ldb_l = ldbl_for(l, sizeof(T));
+  T* Bl = IN_LDS ? (T*)(smem + l + nc + (nc + 1) / 2) : Bw + (int64_t)g * nc * ldb_l;
 
   for (int64_t e = tid; e < (int64_t)ncl * l; e += NT) {
     const int c = (int)(e / l), i = (int)(e % l);
-    Bl[(int64_t)c * l + i] = B[(c0 + c) * ldb + i];
+    Bl[(int64_t)c * ldb_l + i] = B[(c0 + c) * ldb + i];
   }
   for (int c = tid; c < nc; c += NT) act[c] = c < ncl ? 1 : 0;
   const int gsz = group_size_for(nc), ngrp = NT / gsz, q = tid % gsz;
@@ -68,7 +80,7 @@ __global__ __launch_bounds__(NT) void qrcp_kernel(const T* __restrict__ B, int64
   for (int c = tid / gsz; c < ncl; c += ngrp) {
     double s = 0.0;
     for (int i = q; i < l; i += gsz) {
-      const double b = (double)Bl[(int64_t)c * l + i];
+      const double b = (double)Bl[(int64_t)c * ldb_l + i];
       s += b * b;
     }
     s = group_sum(s, gsz);
@@ -97,7 +109,7 @@ __global__ __launch_bounds__(NT) void qrcp_kernel(const T* __restrict__ B, int64
     if (best.i >= 0) {
       const int cb = (int)(best.i - c0);
       double* dst = sl.col + ((int64_t)par * G + g) * l;
-      for (int i = j + tid; i < l; i += NT) dst[i] = (double)Bl[(int64_t)cb * l + i];
+      for (int i = j + tid; i < l; i += NT) dst[i] = (double)Bl[(int64_t)cb * ldb_l + i];
     }
     // ---- 2. exchange
     if (!grid_barrier(gs, epoch)) return;
@@ -150,7 +162,7 @@ __global__ __launch_bounds__(NT) void qrcp_kernel(const T* __restrict__ B, int64
     // ---- update the active local columns, recompute residual norms
     for (int c = tid / gsz; c < ncl; c += ngrp) {
       if (!act[c]) continue;
-      T* col = Bl + (int64_t)c * l;
+      T* col = Bl + (int64_t)c * ldb_l;
       if (tau != 0.0) {
         double s = 0.0;
         for (int i = j + q; i < l; i += gsz) s += v[i] * (double)col[i];
@@ -169,16 +181,27 @@ __global__ __launch_bounds__(NT) void qrcp_kernel(const T* __restrict__ B, int64
   }
 }
 
+// Fewest workgroups whose column slices of B still fit in LDS: the per-step
+// grid barrier costs more with more workgroups, while the work per step is
+// small.  When B does not fit in the LDS of the whole chip, the slices live
+// in a global copy instead and one workgroup per CU is used.
 void choose(int64_t l, int64_t n, int num_cu, size_t lds_max, size_t tsize, int* nc, int* G, bool* in_lds,
             size_t* lds) {
-  int64_t c = (n + num_cu - 1) / num_cu;
+  const size_t fixed = (size_t)l * sizeof(double) + 2048;
+  const size_t per_col = (size_t)ldbl_for(l, tsize) * tsize + sizeof(double) + sizeof(int);
+  int64_t c = lds_max > fixed ? (int64_t)((lds_max - fixed) / per_col) : 0;
+  if (c > n) c = n;
+  if (c >= 1 && (n + c - 1) / c <= num_cu) {
+    *in_lds = true;
+  } else {
+    c = (n + num_cu - 1) / num_cu;
+    *in_lds = false;
+  }
   if (c < 1) c = 1;
   *nc = (int)c;
   *G = (int)((n + c - 1) / c);
   const size_t base = (size_t)(l + c + (c + 1) / 2) * sizeof(double);
-  const size_t with = base + (size_t)c * l * tsize;
-  *in_lds = with <= lds_max;
-  *lds = *in_lds ? with : base;
+  *lds = *in_lds ? base + (size_t)c * ldbl_for(l, tsize) * tsize : base;
 }
 
 }  // namespace
@@ -190,8 +213,8 @@ size_t qrcp_scratch(int64_t l, int64_t n, const DeviceInfo& d) {
   size_t lds;
   choose(l, n, d.num_cu, d.lds_max, sizeof(T), &nc, &G, &in_lds, &lds);
   size_t b = (size_t)2 * G * (3 * sizeof(double) + l * sizeof(double)) + 4 * 256;
-  if (!in_lds) b += (size_t)G * nc * l * sizeof(T) + 256;
-  return b + 512;
+  if (!in_lds) b += (size_t)G * nc * ldbl_for(l, sizeof(T)) * sizeof(T) + 256;
+  return b + kSyncWords * sizeof(unsigned) + 1024;
 }
 
 template <typename T>
@@ -207,10 +230,10 @@ hipError_t qrcp(const T* B, int64_t l, int64_t n, int64_t ldb, int64_t* piv, dou
   sl.r2 = ar.take<double>(2 * G);
   sl.idx = ar.take<int64_t>(2 * G);
   sl.col = ar.take<double>((size_t)2 * G * l);
-  unsigned* counter = ar.take<unsigned>(64);
-  T* Bw = in_lds ? nullptr : ar.take<T>((size_t)G * nc * l);
+  unsigned* counter = ar.take<unsigned>(kSyncWords);
+  T* Bw = in_lds ? nullptr : ar.take<T>((size_t)G * nc * ldbl_for(l, sizeof(T)));
   if (!sl.r || !sl.r2 || !sl.idx || !sl.col || !counter || (!in_lds && !Bw)) return hipErrorOutOfMemory;
-  hipError_t e = zero_words(counter, 64, s);
+  hipError_t e = zero_words(counter, kSyncWords, s);
   if (e != hipSuccess) return e;
   GridSync gs{counter, err, (unsigned)G};
   int li = (int)l;

@@ -19,7 +19,9 @@
 //     own rows.
 // Then Q = H_1 ... H_c [I; 0] is formed backwards panel by panel with the
 // same reduce pattern (Q -= Y (T (Y^T Q))), and signs are normalised so that
-// diag(R) >= 0.  All arithmetic is FP64; P and Q are stored as T.
+// diag(R) >= 0.  The products with Y at the panel ends run on FP64 MFMA
+// (16x16x4) with operands read straight from global memory and LDS.  All
+// arithmetic is FP64; P and Q are stored as T.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -27,15 +29,15 @@ namespace ffsrqr {
 
 namespace {
 
-constexpr int NT = 256, NB = 16, SUB = 128;
+constexpr int NT = 256, NB = 16, NW = NT / 64;
+using MF = Mfma<double>;
 
 struct TqSlots {
   double* dots;   // [2][G][NB]
   double* rowv;   // [2][NB]
-  double* zpart;  // [G][NB * c]
-  double* zred;   // [2][NB * c]
+  double* zpart;  // [G][NB * cz]
+  double* zred;   // [2][NB * cz]
   double* tst;    // [npan][NB * NB]
-  double* tau;    // [c]
 };
 
 // Y(gi, s) of panel p0 given the stored value at (gi, p0 + s).
@@ -44,50 +46,81 @@ __device__ inline double yval(int64_t gi, int64_t p0, int s, double stored) {
   return gi < d ? 0.0 : (gi == d ? 1.0 : stored);
 }
 
-// Partial Z[:, col] = sum over own rows (rows >= p0) of Y(:, s) * X(row, col)
-// for NB x ncol entries; X column col lives at X[col * ldx + row] (global,
-// with an optional row map).  Yl holds Y of the own rows (nrow x NB, in LDS).
-// Result written to out[col * NB + s].
+// out[col * NB + s] = sum over the own rows i of Y(i, s) * X(r0 + i, col),
+// col < ncol, s < NB; X is column-major in global memory (ldx).  One wave
+// per 16-column chunk; MFMA 16x16x4 with A = Y^T from LDS and B = X from
+// global memory, two accumulators to halve the dependency chain.
 template <typename T>
-__device__ void partial_yt_x(const double* Yl, int nrow, int pw, const T* X, int64_t ldx,
-                             const int64_t* rowmap, int64_t mrows, int64_t r0, int ncol, double* stage,
-                             double* out) {
-  const int tid = threadIdx.x;
-  const int s = tid % NB, cc = tid / NB;  // 16 x 16 outputs per chunk
-  for (int col0 = 0; col0 < ncol; col0 += NB) {
-    double acc = 0.0;
-    for (int i0 = 0; i0 < nrow; i0 += SUB) {
-      const int nr = min(SUB, nrow - i0);
-      __syncthreads();
-      for (int e = tid; e < nr * NB; e += NT) {
-        const int i = e % nr, c = e / nr;
-        const int64_t gi = r0 + i0 + i;
-        const int64_t row = rowmap ? rowmap[gi] : gi;
-        stage[i * NB + c] = (col0 + c < ncol && row >= 0 && row < mrows) ? (double)X[(int64_t)(col0 + c) * ldx + row]
-                                                                          : 0.0;
-      }
-      __syncthreads();
-      if (s < pw)
-        for (int i = 0; i < nr; ++i) acc += Yl[(i0 + i) * NB + s] * stage[i * NB + cc];
+__device__ void yt_times_global(const double* Yl, int ldy, int nrow, const T* X, int64_t ldx, int64_t r0, int ncol,
+                                double* out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int s = lane & 15, kq = lane >> 4;
+  for (int col0 = wave * 16; col0 < ncol; col0 += NW * 16) {
+    const int col = col0 + s;
+    const bool cin = col < ncol;
+    const T* xc = X + (int64_t)(cin ? col : 0) * ldx + r0;
+    MF::acc4 a0 = {0, 0, 0, 0}, a1 = {0, 0, 0, 0};
+    int k0 = 0;
+    for (; k0 + 8 <= nrow; k0 += 8) {
+      const int i0 = k0 + kq, i1 = k0 + 4 + kq;
+      const double ya = Yl[s * ldy + i0], yb = Yl[s * ldy + i1];      // A[s][k] = Y(k, s)
+      const double xa = cin ? (double)xc[i0] : 0.0, xb = cin ? (double)xc[i1] : 0.0;  // B[k][col]
+      a0 = MF::fma(ya, xa, a0);
+      a1 = MF::fma(yb, xb, a1);
     }
-    if (s < NB && col0 + cc < ncol) out[(int64_t)(col0 + cc) * NB + s] = (s < pw) ? acc : 0.0;
+    for (; k0 < nrow; k0 += 4) {
+      const int i = k0 + kq;
+      const double ya = i < nrow ? Yl[s * ldy + i] : 0.0;
+      const double xa = (cin && i < nrow) ? (double)xc[i] : 0.0;
+      a0 = MF::fma(ya, xa, a0);
+    }
+    if (cin)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) out[(int64_t)col * NB + MF::row(lane, r)] = a0[r] + a1[r];
   }
 }
 
-// Partial Z for the Gram part: Y^T Y over own rows, written to out[col*NB+s].
-__device__ void partial_gram(const double* Yl, int nrow, int pw, double* out) {
-  const int tid = threadIdx.x;
-  const int s = tid % NB, cc = tid / NB;
-  double acc = 0.0;
-  if (s < pw && cc < pw)
-    for (int i = 0; i < nrow; ++i) acc += Yl[i * NB + s] * Yl[i * NB + cc];
-  out[cc * NB + s] = acc;
+// X(r0 + i, col) -= sum_s Y(i, s) W(s, col) for the own rows i < nrow and
+// col < ncol, W(s, col) = Wl[col * NB + s] in LDS.  16 x 16 tiles per wave,
+// accumulator initialised with the tile of X and A = -Y.
+template <typename T>
+__device__ void sub_y_times(const double* Yl, int ldy, int nrow, const double* Wl, T* X, int64_t ldx, int64_t r0,
+                            int ncol) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lo = lane & 15, kq = lane >> 4;
+  const int ntr = (nrow + 15) / 16, ntc = (ncol + 15) / 16;
+  for (int tile = wave; tile < ntr * ntc; tile += NW) {
+    const int tr = tile % ntr, tc = tile / ntr;
+    const int i0 = tr * 16, c0 = tc * 16;
+    const int col = c0 + lo;
+    const bool cin = col < ncol;
+    T* xc = X + (int64_t)(cin ? col : 0) * ldx + r0;
+    MF::acc4 acc;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = i0 + MF::row(lane, r);
+      acc[r] = (cin && i < nrow) ? (double)xc[i] : 0.0;
+    }
+#pragma unroll
+    for (int k4 = 0; k4 < NB / 4; ++k4) {
+      const int sidx = 4 * k4 + kq;
+      const int ia = i0 + lo;
+      const double a = ia < nrow ? -Yl[sidx * ldy + ia] : 0.0;    // A[row = lo][k = kq]
+      const double b = cin ? Wl[(int64_t)col * NB + sidx] : 0.0;  // B[k = kq][col = lo]
+      acc = MF::fma(a, b, acc);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = i0 + MF::row(lane, r);
+      if (cin && i < nrow) xc[i] = (T)acc[r];
+    }
+  }
 }
 
 // Reduce-scatter of E entries over G partials into zred, then every block
 // copies the whole reduced Z into Zl.  Returns false on a barrier timeout.
-__device__ bool reduce_z(const double* zpart, double* zred, int64_t E, int64_t estride, int G, int g,
-                         double* Zl, const GridSync& gs, unsigned& epoch) {
+__device__ bool reduce_z(const double* zpart, double* zred, int64_t E, int64_t estride, int G, int g, double* Zl,
+                         const GridSync& gs, unsigned& epoch) {
   if (!grid_barrier(gs, epoch)) return false;
   const int64_t e0 = E * g / G, e1 = E * (g + 1) / G;
   for (int64_t e = e0 + threadIdx.x; e < e1; e += NT) {
@@ -103,9 +136,8 @@ __device__ bool reduce_z(const double* zpart, double* zred, int64_t E, int64_t e
 
 template <typename T>
 __global__ __launch_bounds__(NT) void tallqr_kernel(T* __restrict__ P, int64_t mrows, int c, int64_t ldp, int rb,
-                                                    T* __restrict__ Qout, int64_t ldq,
-                                                    const int64_t* __restrict__ rowmap, T* __restrict__ R,
-                                                    int64_t ldr, int transpose_r, TqSlots sl, GridSync gs) {
+                                                    T* __restrict__ Qout, int64_t ldq, T* __restrict__ R, int64_t ldr,
+                                                    int transpose_r, TqSlots sl, GridSync gs) {
   extern __shared__ double smem[];
   __shared__ double red[NB * NB];
   __shared__ double Tl[NB * NB];
@@ -113,9 +145,11 @@ __global__ __launch_bounds__(NT) void tallqr_kernel(T* __restrict__ P, int64_t m
   const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
   const int64_t r0 = (int64_t)g * rb;
   const int nrow = (int)max((int64_t)0, min((int64_t)rb, mrows - r0));
-  double* Yl = smem;                        // rb x NB
-  double* stage = Yl + (int64_t)rb * NB;    // SUB x NB
-  double* Zl = stage + SUB * NB;            // NB x c
+  // LDS: Y panel of the own rows, column-major with an odd leading dimension
+  // so that lanes along rows and lanes along columns both avoid bank conflicts
+  const int ldy = rb | 1;
+  double* Yl = smem;                    // ldy x NB
+  double* Zl = Yl + (int64_t)ldy * NB;  // NB x cz
   const int npan = (c + NB - 1) / NB;
   const int64_t estride = (int64_t)NB * (c > NB ? c : NB);
   unsigned epoch = 0;
@@ -125,20 +159,24 @@ __global__ __launch_bounds__(NT) void tallqr_kernel(T* __restrict__ P, int64_t m
   for (int pi = 0; pi < npan; ++pi) {
     const int p0 = pi * NB, p1 = min(c, p0 + NB), pw = p1 - p0;
     __syncthreads();
-    for (int e = tid; e < nrow * NB; e += NT) {
-      const int i = e % nrow, t = e / nrow;
-      Yl[i * NB + t] = t < pw ? (double)P[(int64_t)(p0 + t) * ldp + r0 + i] : 0.0;
-    }
+    for (int t = 0; t < NB; ++t)
+      for (int i = tid; i < nrow; i += NT)
+        Yl[t * ldy + i] = t < pw ? (double)P[(int64_t)(p0 + t) * ldp + r0 + i] : 0.0;
     __syncthreads();
     for (int jc = p0; jc < p1; ++jc, ++step) {
       const int jt = jc - p0, par = step & 1;
       // partial dots d_t = sum_{own rows > jc} x_i p_t(i), t = jt..pw-1
       {
-        const int t = tid % NB, rs = tid / NB;
+        const int t = tid & (NB - 1), rs = tid / NB;
+        const int istart = (int)max((int64_t)0, (int64_t)jc + 1 - r0);
         double acc = 0.0;
-        if (t >= jt && t < pw)
-          for (int i = rs; i < nrow; i += NT / NB)
-            if (r0 + i > jc) acc += Yl[i * NB + jt] * Yl[i * NB + t];
+        if (t >= jt && t < pw) {
+          const double* xc = Yl + jt * ldy;
+          const double* pc = Yl + t * ldy;
+          int i = istart + rs;
+          for (; i + 16 < nrow; i += 32) acc += xc[i] * pc[i] + xc[i + 16] * pc[i + 16];
+          for (; i < nrow; i += 16) acc += xc[i] * pc[i];
+        }
         red[rs * NB + t] = acc;
         __syncthreads();
         if (tid < NB) {
@@ -146,21 +184,20 @@ __global__ __launch_bounds__(NT) void tallqr_kernel(T* __restrict__ P, int64_t m
           for (int q = 0; q < NT / NB; ++q) sacc += red[q * NB + tid];
           sl.dots[((int64_t)par * G + g) * NB + tid] = sacc;
         }
-        if (jc >= r0 && jc < r0 + nrow && tid < NB)
-          sl.rowv[par * NB + tid] = Yl[(jc - r0) * NB + tid];
+        if (jc >= r0 && jc < r0 + nrow && tid < NB) sl.rowv[par * NB + tid] = Yl[tid * ldy + (jc - r0)];
       }
       if (!grid_barrier(gs, epoch)) return;
       // sum the partials in a fixed order (identical in every workgroup)
       {
-        const int t = tid % NB, gs16 = tid / NB;
+        const int t = tid & (NB - 1), gq = tid / NB;
         double acc = 0.0;
-        for (int q = gs16; q < G; q += NT / NB) acc += sl.dots[((int64_t)par * G + q) * NB + t];
-        red[gs16 * NB + t] = acc;
+        for (int q = gq; q < G; q += NT / NB) acc += sl.dots[((int64_t)par * G + q) * NB + t];
+        red[gq * NB + t] = acc;
         __syncthreads();
         if (tid < NB) {
           double sacc = 0.0;
           for (int q = 0; q < NT / NB; ++q) sacc += red[q * NB + tid];
-          Tl[tid] = sacc;                       // d_t
+          Tl[tid] = sacc;                          // d_t
           Tl[NB + tid] = sl.rowv[par * NB + tid];  // p_t(jc)
         }
         __syncthreads();
@@ -173,44 +210,44 @@ __global__ __launch_bounds__(NT) void tallqr_kernel(T* __restrict__ P, int64_t m
         scale = 1.0 / (x0 - beta);
       }
       if (tid == 0) taul[jt] = tau;
-      if (g == 0 && tid == 0) sl.tau[jc] = tau;
       // own rows: p_t -= tau w_t v, w_t = p_t(jc) + scale d_t
-      for (int e = tid; e < nrow * NB; e += NT) {
-        const int i = e / NB, t = e % NB;
-        const int64_t gi = r0 + i;
-        if (t <= jt || t >= pw || gi < jc) continue;
-        const double wt = Tl[NB + t] + scale * Tl[t];
-        if (gi == jc) Yl[i * NB + t] -= tau * wt;
-        else Yl[i * NB + t] -= tau * wt * (Yl[i * NB + jt] * scale);
+      const int istart = (int)max((int64_t)0, (int64_t)jc - r0);
+      for (int t = jt + 1; t < pw; ++t) {
+        const double twt = tau * (Tl[NB + t] + scale * Tl[t]);
+        for (int i = istart + tid; i < nrow; i += NT) {
+          const double v = (r0 + i == jc) ? 1.0 : Yl[jt * ldy + i] * scale;
+          Yl[t * ldy + i] -= twt * v;
+        }
       }
       __syncthreads();
-      for (int i = tid; i < nrow; i += NT) {
-        const int64_t gi = r0 + i;
-        if (gi == jc) Yl[i * NB + jt] = beta;
-        else if (gi > jc && tau != 0.0) Yl[i * NB + jt] *= scale;
+      for (int i = istart + tid; i < nrow; i += NT) {
+        if (r0 + i == jc) Yl[jt * ldy + i] = beta;
+        else if (tau != 0.0) Yl[jt * ldy + i] *= scale;
       }
       __syncthreads();
     }
     // write the panel back (R above the diagonal, beta on it, v below)
-    for (int e = tid; e < nrow * NB; e += NT) {
-      const int i = e % nrow, t = e / nrow;
-      if (t < pw) P[(int64_t)(p0 + t) * ldp + r0 + i] = (T)Yl[i * NB + t];
-    }
+    for (int t = 0; t < pw; ++t)
+      for (int i = tid; i < nrow; i += NT) P[(int64_t)(p0 + t) * ldp + r0 + i] = (T)Yl[t * ldy + i];
     __syncthreads();
-    // Y of the own rows (rows >= p0 only contribute)
-    for (int e = tid; e < nrow * NB; e += NT) {
-      const int i = e / NB, s = e % NB;
-      Yl[i * NB + s] = s < pw ? yval(r0 + i, p0, s, Yl[i * NB + s]) : 0.0;
-    }
+    // Y of the own rows
+    for (int s = 0; s < NB; ++s)
+      for (int i = tid; i < nrow; i += NT) Yl[s * ldy + i] = s < pw ? yval(r0 + i, p0, s, Yl[s * ldy + i]) : 0.0;
     __syncthreads();
     const int ntr = c - p1;
     double* zp = sl.zpart + (int64_t)g * estride;
-    partial_gram(Yl, nrow, pw, zp);
-    if (ntr > 0) partial_yt_x<T>(Yl, nrow, pw, P + (int64_t)p1 * ldp, ldp, nullptr, mrows, r0, ntr, stage, zp + NB * NB);
+    // Gram part Y^T Y (16 x 16): one output per thread
+    {
+      const int s = tid & (NB - 1), cc = tid / NB;
+      double acc = 0.0;
+      for (int i = 0; i < nrow; ++i) acc += Yl[s * ldy + i] * Yl[cc * ldy + i];
+      zp[cc * NB + s] = acc;
+    }
+    if (ntr > 0) yt_times_global<T>(Yl, ldy, nrow, P + (int64_t)p1 * ldp, ldp, r0, ntr, zp + NB * NB);
     double* zr = sl.zred + (int64_t)(pi & 1) * estride;
     if (!reduce_z(sl.zpart, zr, (int64_t)NB * (NB + ntr), estride, G, g, Zl, gs, epoch)) return;
     // T of the panel: T(s,s) = tau_s, T(0:s, s) = -tau_s T(0:s, 0:s) (Y^T y_s)
-    if (tid < NB * NB) Tl[tid] = 0.0;
+    Tl[tid] = 0.0;
     __syncthreads();
     for (int s = 0; s < pw; ++s) {
       const double ts = taul[s];
@@ -224,7 +261,7 @@ __global__ __launch_bounds__(NT) void tallqr_kernel(T* __restrict__ P, int64_t m
       if (tid == s) Tl[s * NB + s] = ts;
       __syncthreads();
     }
-    if (g == 0 && tid < NB * NB) sl.tst[(int64_t)pi * NB * NB + tid] = Tl[tid];
+    if (g == 0) sl.tst[(int64_t)pi * NB * NB + tid] = Tl[tid];
     // W' = T^T Z_trail (in place, column by column)
     for (int u = tid; u < ntr; u += NT) {
       double z[NB], w[NB];
@@ -233,50 +270,33 @@ __global__ __launch_bounds__(NT) void tallqr_kernel(T* __restrict__ P, int64_t m
 #pragma unroll
       for (int s2 = 0; s2 < NB; ++s2) {
         double a = 0.0;
-#pragma unroll
-        for (int q = 0; q < NB; ++q)
-          if (q <= s2) a += Tl[s2 * NB + q] * z[q];
+        for (int q = 0; q <= s2; ++q) a += Tl[s2 * NB + q] * z[q];
         w[s2] = a;
       }
 #pragma unroll
       for (int q = 0; q < NB; ++q) Zl[(NB + u) * NB + q] = w[q];
     }
     __syncthreads();
-    // P_trail(own rows >= p0) -= Y W'
-    for (int e = tid; e < nrow * ntr; e += NT) {
-      const int i = e % nrow, u = e / nrow;
-      const int64_t gi = r0 + i;
-      if (gi < p0) continue;
-      double a = 0.0;
-#pragma unroll
-      for (int s = 0; s < NB; ++s) a += Yl[i * NB + s] * Zl[(NB + u) * NB + s];
-      T* pp = P + (int64_t)(p1 + u) * ldp + gi;
-      *pp = (T)((double)*pp - a);
-    }
+    // P_trail(own rows) -= Y W'  (rows above p0 have Y = 0)
+    if (ntr > 0) sub_y_times<T>(Yl, ldy, nrow, Zl + NB * NB, P + (int64_t)p1 * ldp, ldp, r0, ntr);
   }
 
   // --------------------------------------------------- explicit Q, backwards
   // the T factors written by workgroup 0 at the panel ends must be visible
   if (!grid_barrier(gs, epoch)) return;
-  for (int e = tid; e < nrow * c; e += NT) {
-    const int i = e % nrow, j = e / nrow;
-    const int64_t gi = r0 + i;
-    const int64_t row = rowmap ? rowmap[gi] : gi;
-    if (row < 0 || row >= mrows) continue;
-    Qout[(int64_t)j * ldq + row] = (T)(gi == j ? 1.0 : 0.0);
-  }
+  for (int j = 0; j < c; ++j)
+    for (int i = tid; i < nrow; i += NT) Qout[(int64_t)j * ldq + r0 + i] = (T)(r0 + i == j ? 1.0 : 0.0);
   for (int pi = npan - 1; pi >= 0; --pi) {
     const int p0 = pi * NB, p1 = min(c, p0 + NB), pw = p1 - p0;
     const int ncol = c - p0;
     __syncthreads();
-    for (int e = tid; e < nrow * NB; e += NT) {
-      const int i = e % nrow, s = e / nrow;
-      Yl[i * NB + s] = s < pw ? yval(r0 + i, p0, s, (double)P[(int64_t)(p0 + s) * ldp + r0 + i]) : 0.0;
-    }
-    if (tid < NB * NB) Tl[tid] = sl.tst[(int64_t)pi * NB * NB + tid];
+    for (int s = 0; s < NB; ++s)
+      for (int i = tid; i < nrow; i += NT)
+        Yl[s * ldy + i] = s < pw ? yval(r0 + i, p0, s, (double)P[(int64_t)(p0 + s) * ldp + r0 + i]) : 0.0;
+    Tl[tid] = sl.tst[(int64_t)pi * NB * NB + tid];
     __syncthreads();
     double* zp = sl.zpart + (int64_t)g * estride;
-    partial_yt_x<T>(Yl, nrow, pw, Qout + (int64_t)p0 * ldq, ldq, rowmap, mrows, r0, ncol, stage, zp);
+    yt_times_global<T>(Yl, ldy, nrow, Qout + (int64_t)p0 * ldq, ldq, r0, ncol, zp);
     double* zr = sl.zred + (int64_t)(pi & 1) * estride;
     if (!reduce_z(sl.zpart, zr, (int64_t)NB * ncol, estride, G, g, Zl, gs, epoch)) return;
     // W2 = T Z (T upper triangular)
@@ -287,27 +307,14 @@ __global__ __launch_bounds__(NT) void tallqr_kernel(T* __restrict__ P, int64_t m
 #pragma unroll
       for (int r = 0; r < NB; ++r) {
         double a = 0.0;
-#pragma unroll
-        for (int q = 0; q < NB; ++q)
-          if (q >= r) a += Tl[q * NB + r] * z[q];
+        for (int q = r; q < NB; ++q) a += Tl[q * NB + r] * z[q];
         w[r] = a;
       }
 #pragma unroll
       for (int q = 0; q < NB; ++q) Zl[u * NB + q] = w[q];
     }
     __syncthreads();
-    for (int e = tid; e < nrow * ncol; e += NT) {
-      const int i = e % nrow, u = e / nrow;
-      const int64_t gi = r0 + i;
-      if (gi < p0) continue;
-      double a = 0.0;
-#pragma unroll
-      for (int s = 0; s < NB; ++s) a += Yl[i * NB + s] * Zl[u * NB + s];
-      const int64_t row = rowmap ? rowmap[gi] : gi;
-      if (row < 0 || row >= mrows) continue;
-      T* qq = Qout + (int64_t)(p0 + u) * ldq + row;
-      *qq = (T)((double)*qq - a);
-    }
+    sub_y_times<T>(Yl, ldy, nrow, Zl, Qout + (int64_t)p0 * ldq, ldq, r0, ncol);
   }
   __syncthreads();
 
@@ -315,30 +322,33 @@ __global__ __launch_bounds__(NT) void tallqr_kernel(T* __restrict__ P, int64_t m
   double* sgn = Zl;  // c entries
   for (int j = tid; j < c; j += NT) sgn[j] = ((double)P[(int64_t)j * ldp + j] < 0.0) ? -1.0 : 1.0;
   __syncthreads();
-  for (int e = tid; e < nrow * c; e += NT) {
-    const int i = e % nrow, j = e / nrow;
-    const int64_t gi = r0 + i;
-    const int64_t row = rowmap ? rowmap[gi] : gi;
-    if (sgn[j] < 0.0 && row >= 0 && row < mrows) {
-      T* qq = Qout + (int64_t)j * ldq + row;
-      *qq = -*qq;
-    }
-    if (gi < c) {
-      const double val = (j >= gi) ? sgn[gi] * (double)P[(int64_t)j * ldp + gi] : 0.0;
-      if (transpose_r) R[(int64_t)gi * ldr + j] = (T)val;
-      else R[(int64_t)j * ldr + gi] = (T)val;
+  for (int j = 0; j < c; ++j) {
+    const bool flip = sgn[j] < 0.0;
+    for (int i = tid; i < nrow; i += NT) {
+      const int64_t gi = r0 + i;
+      if (flip) {
+        T* qq = Qout + (int64_t)j * ldq + gi;
+        *qq = -*qq;
+      }
+      if (gi < c) {
+        const double val = (j >= gi) ? sgn[gi] * (double)P[(int64_t)j * ldp + gi] : 0.0;
+        if (transpose_r) R[gi * ldr + j] = (T)val;
+        else R[(int64_t)j * ldr + gi] = (T)val;
+      }
     }
   }
 }
 
+// Row blocks of about 512 rows: the work per column step is small, so fewer
+// workgroups (cheaper grid barriers) beat more parallelism here.
 void choose(int64_t mrows, int c, int num_cu, int* G, int* rb, size_t* lds) {
-  int64_t g = (mrows + 255) / 256;
+  int64_t g = (mrows + 511) / 512;
   if (g > num_cu) g = num_cu;
   if (g < 1) g = 1;
   int64_t r = (mrows + g - 1) / g;
   *G = (int)((mrows + r - 1) / r);
   *rb = (int)r;
-  *lds = ((size_t)r * NB + SUB * NB + (size_t)NB * (c > NB ? c : NB) + 64) * sizeof(double);
+  *lds = ((size_t)(r | 1) * NB + (size_t)NB * (c > NB ? c : NB) + 64) * sizeof(double);
 }
 
 template <typename T>
@@ -352,6 +362,18 @@ __global__ void gather_kernel(const T* __restrict__ A, int64_t m, int64_t n, int
   }
 }
 
+// V(rowmap[i], :) = Q(i, :)
+template <typename T>
+__global__ void scatter_rows_kernel(const T* __restrict__ Q, int64_t mrows, int64_t c, int64_t ldq,
+                                    const int64_t* __restrict__ rowmap, T* __restrict__ V, int64_t ldv) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t j = blockIdx.y;
+  if (i < mrows && j < c) {
+    const int64_t r = rowmap[i];
+    if (r >= 0 && r < mrows) V[j * ldv + r] = Q[j * ldq + i];
+  }
+}
+
 }  // namespace
 
 template <typename T>
@@ -362,14 +384,13 @@ size_t tallqr_scratch(int64_t mrows, int64_t c, const DeviceInfo& d) {
   const int npan = (int)((c + NB - 1) / NB);
   const size_t cz = c > NB ? c : NB;
   size_t b = sizeof(double) * ((size_t)2 * G * NB + 2 * NB + (size_t)G * NB * cz + (size_t)2 * NB * cz +
-                               (size_t)npan * NB * NB + c);
-  return b + 64 * sizeof(unsigned) + 8 * 256;
+                               (size_t)npan * NB * NB);
+  return b + kSyncWords * sizeof(unsigned) + 8 * 256;
 }
 
 template <typename T>
-hipError_t tall_qr(T* P, int64_t mrows, int64_t c, int64_t ldp, T* Qout, int64_t ldq, const int64_t* rowmap,
-                   T* R, int64_t ldr, bool transpose_r, Arena& ar, unsigned* err, const DeviceInfo& d,
-                   hipStream_t s) {
+hipError_t tall_qr(T* P, int64_t mrows, int64_t c, int64_t ldp, T* Qout, int64_t ldq, T* R, int64_t ldr,
+                   bool transpose_r, Arena& ar, unsigned* err, const DeviceInfo& d, hipStream_t s) {
   if (c <= 0) return hipSuccess;
   if (mrows < c) return hipErrorInvalidValue;
   int G, rb;
@@ -377,22 +398,21 @@ hipError_t tall_qr(T* P, int64_t mrows, int64_t c, int64_t ldp, T* Qout, int64_t
   choose(mrows, (int)c, d.num_cu, &G, &rb, &lds);
   if (lds > d.lds_max) return hipErrorInvalidValue;
   const int npan = (int)((c + NB - 1) / NB);
+  const size_t cz = c > NB ? c : NB;
   TqSlots sl;
   sl.dots = ar.take<double>((size_t)2 * G * NB);
   sl.rowv = ar.take<double>(2 * NB);
-  const size_t cz = c > NB ? c : NB;
   sl.zpart = ar.take<double>((size_t)G * NB * cz);
   sl.zred = ar.take<double>((size_t)2 * NB * cz);
   sl.tst = ar.take<double>((size_t)npan * NB * NB);
-  sl.tau = ar.take<double>(c);
-  unsigned* counter = ar.take<unsigned>(64);
-  if (!sl.dots || !sl.rowv || !sl.zpart || !sl.zred || !sl.tst || !sl.tau || !counter) return hipErrorOutOfMemory;
-  hipError_t e = zero_words(counter, 64, s);
+  unsigned* counter = ar.take<unsigned>(kSyncWords);
+  if (!sl.dots || !sl.rowv || !sl.zpart || !sl.zred || !sl.tst || !counter) return hipErrorOutOfMemory;
+  hipError_t e = zero_words(counter, kSyncWords, s);
   if (e != hipSuccess) return e;
   GridSync gs{counter, err, (unsigned)G};
   int ci = (int)c, tr = transpose_r ? 1 : 0;
   void* args[] = {(void*)&P, (void*)&mrows, (void*)&ci, (void*)&ldp, (void*)&rb, (void*)&Qout, (void*)&ldq,
-                  (void*)&rowmap, (void*)&R, (void*)&ldr, (void*)&tr, (void*)&sl, (void*)&gs};
+                  (void*)&R, (void*)&ldr, (void*)&tr, (void*)&sl, (void*)&gs};
   const void* fn = (const void*)tallqr_kernel<T>;
   if (lds > 65536) {
     e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -410,15 +430,24 @@ hipError_t gather_cols(const T* A, int64_t m, int64_t n, int64_t lda, const int6
   return hipGetLastError();
 }
 
-template size_t tallqr_scratch<double>(int64_t, int64_t, const DeviceInfo&);
-template size_t tallqr_scratch<float>(int64_t, int64_t, const DeviceInfo&);
-template hipError_t tall_qr<double>(double*, int64_t, int64_t, int64_t, double*, int64_t, const int64_t*, double*,
-                                    int64_t, bool, Arena&, unsigned*, const DeviceInfo&, hipStream_t);
-template hipError_t tall_qr<float>(float*, int64_t, int64_t, int64_t, float*, int64_t, const int64_t*, float*,
-                                   int64_t, bool, Arena&, unsigned*, const DeviceInfo&, hipStream_t);
-template hipError_t gather_cols<double>(const double*, int64_t, int64_t, int64_t, const int64_t*, int64_t, double*,
-                                        int64_t, hipStream_t);
-template hipError_t gather_cols<float>(const float*, int64_t, int64_t, int64_t, const int64_t*, int64_t, float*,
-                                       int64_t, hipStream_t);
+template <typename T>
+hipError_t scatter_rows(const T* Q, int64_t mrows, int64_t c, int64_t ldq, const int64_t* rowmap, T* V, int64_t ldv,
+                        hipStream_t s) {
+  if (c <= 0 || mrows <= 0) return hipSuccess;
+  dim3 grid((unsigned)((mrows + 255) / 256), (unsigned)c);
+  scatter_rows_kernel<T><<<grid, 256, 0, s>>>(Q, mrows, c, ldq, rowmap, V, ldv);
+  return hipGetLastError();
+}
+
+#define INST(T)                                                                                                    \
+  template size_t tallqr_scratch<T>(int64_t, int64_t, const DeviceInfo&);                                          \
+  template hipError_t tall_qr<T>(T*, int64_t, int64_t, int64_t, T*, int64_t, T*, int64_t, bool, Arena&, unsigned*, \
+                                 const DeviceInfo&, hipStream_t);                                                  \
+  template hipError_t gather_cols<T>(const T*, int64_t, int64_t, int64_t, const int64_t*, int64_t, T*, int64_t,     \
+                                     hipStream_t);                                                                 \
+  template hipError_t scatter_rows<T>(const T*, int64_t, int64_t, int64_t, const int64_t*, T*, int64_t, hipStream_t);
+INST(double)
+INST(float)
+#undef INST
 
 }  // namespace ffsrqr
