@@ -77,12 +77,17 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(const T* __restrict__ L, int
       const int ca0 = pa * bs, cb0 = pb * bs;
       const int na = max(0, min(bs, l - ca0)), nbk = max(0, min(bs, l - cb0));
       // local column k < bs -> block a column k, k >= bs -> block b column k - bs
-      for (int k = wave; k < W2; k += nwave) {
+      for (int e = tid; e < W2 * l; e += NT) {
+        // all loads of the two blocks in flight together
+        const int k = e / l, i = e - k * l;
         const int gc = k < bs ? (k < na ? ca0 + k : -1) : (k - bs < nbk ? cb0 + k - bs : -1);
+        C[e] = gc >= 0 ? M[(int64_t)gc * l + i] : 0.0;
+      }
+      __syncthreads();
+      for (int k = wave; k < W2; k += nwave) {
         double a = 0.0;
         for (int i = lane; i < l; i += 64) {
-          const double x = gc >= 0 ? M[(int64_t)gc * l + i] : 0.0;
-          C[k * l + i] = x;
+          const double x = C[k * l + i];
           a += x * x;
         }
         a = wave_sum(a);
@@ -104,10 +109,10 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(const T* __restrict__ L, int
           for (int i = lane; i < l; i += 64) gg += cp[i] * cq[i];
           gg = wave_sum(gg);
           const double a = dn[lo], b = dn[hi];
-          if (a == 0.0 || b == 0.0 || fabs(gg) <= kTol * sqrt(a * b)) continue;
+          if (a == 0.0 || b == 0.0 || gg * gg <= (kTol * kTol) * (a * b)) continue;
           const double zeta = (b - a) / (2.0 * gg);
           const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+          const double cs = rsqrt(1.0 + t * t), sn = cs * t;
           for (int i = lane; i < l; i += 64) {
             const double x = cp[i], y = cq[i];
             cp[i] = cs * x - sn * y;

@@ -1,7 +1,8 @@
 // Partial QRCP on the sketch B (Algorithm 1 applied to B for l steps; the
 // pivot search of Algorithm 2).
 //
-// One cooperative launch on as few workgroups as LDS allows.  Workgroup g owns a
+// One cooperative launch on as few 1024-thread workgroups as LDS allows.
+// Workgroup g owns a
 // contiguous slice of nc columns of B, kept in LDS (or in a global copy when
 // the slice does not fit) for all l steps.  Step j:
 //   1. each workgroup publishes its best active column (largest residual
@@ -24,7 +25,7 @@ namespace ffsrqr {
 
 namespace {
 
-constexpr int NT = 256;
+constexpr int NT = 1024;
 
 struct QrcpSlots {
   double* r;      // [2][G]
@@ -40,6 +41,34 @@ __host__ __device__ inline int ldbl_for(int64_t l, size_t tsize) {
   int64_t w = (l + 1) / 2;  // 8-byte words per float column
   if (!(w & 1)) ++w;
   return (int)(2 * w);
+}
+
+// Top-2 of (value, index) pairs: the best pair (largest value, ties to the
+// smallest index) and the largest other value (v2 < 0 when there is none).
+struct Top2 {
+  double v1;
+  int64_t i1;
+  double v2;
+};
+__device__ inline Top2 top2_merge(Top2 a, Top2 b) {
+  if (better(b.v1, b.i1, a.v1, a.i1)) {
+    const Top2 t = a;
+    a = b;
+    b = t;
+  }
+  // a holds the overall best; the runner-up is b's best or either second
+  double v2 = a.v2;
+  if (b.i1 >= 0 && b.v1 > v2) v2 = b.v1;
+  if (b.v2 > v2) v2 = b.v2;
+  return Top2{a.v1, a.i1, v2};
+}
+__device__ inline Top2 wave_top2(Top2 x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    Top2 y{__shfl_xor(x.v1, o, kWave), __shfl_xor(x.i1, o, kWave), __shfl_xor(x.v2, o, kWave)};
+    x = top2_merge(x, y);
+  }
+  return x;
 }
 
 __device__ inline int group_size_for(int nc) {
@@ -91,56 +120,52 @@ __global__ __launch_bounds__(NT) void qrcp_kernel(const T* __restrict__ B, int64
   unsigned epoch = 0;
   for (int j = 0; j < l; ++j) {
     const int par = j & 1;
-    // ---- 1. local best and runner-up among the active columns
-    ArgMax best{0.0, -1};
-    for (int c = tid; c < ncl; c += NT)
-      if (act[c] && better(rloc[c], c0 + c, best.v, best.i)) best = ArgMax{rloc[c], c0 + c};
-    best = block_argmax(best, redv, redi);
-    ArgMax second{0.0, -1};
-    for (int c = tid; c < ncl; c += NT)
-      if (act[c] && c0 + c != best.i && better(rloc[c], c0 + c, second.v, second.i))
-        second = ArgMax{rloc[c], c0 + c};
-    second = block_argmax(second, redv, redi);
-    if (tid == 0) {
-      sl.r[par * G + g] = best.v;
-      sl.idx[par * G + g] = best.i;
-      sl.r2[par * G + g] = second.i >= 0 ? second.v : -1.0;
+    // ---- 1. local best and runner-up among the active columns (wave 0)
+    if (tid < kWave) {
+      Top2 t{0.0, -1, -1.0};
+      for (int c = tid; c < ncl; c += kWave)
+        if (act[c]) t = top2_merge(t, Top2{rloc[c], c0 + c, -1.0});
+      t = wave_top2(t);
+      if (tid == 0) {
+        sl.r[par * G + g] = t.v1;
+        sl.idx[par * G + g] = t.i1;
+        sl.r2[par * G + g] = t.v2;
+        s_ibcast[0] = t.i1;
+      }
     }
-    if (best.i >= 0) {
-      const int cb = (int)(best.i - c0);
-      double* dst = sl.col + ((int64_t)par * G + g) * l;
-      for (int i = j + tid; i < l; i += NT) dst[i] = (double)Bl[(int64_t)cb * ldb_l + i];
+    __syncthreads();
+    {
+      const int64_t bi = s_ibcast[0];
+      if (bi >= 0) {
+        const int cb = (int)(bi - c0);
+        double* dst = sl.col + ((int64_t)par * G + g) * l;
+        for (int i = j + tid; i < l; i += NT) dst[i] = (double)Bl[(int64_t)cb * ldb_l + i];
+      }
     }
     // ---- 2. exchange
     if (!grid_barrier(gs, epoch)) return;
-    // ---- 3. global winner (identical in every workgroup)
-    ArgMax w{0.0, -1};
-    for (int t = tid; t < G; t += NT) {
-      const int64_t it = sl.idx[par * G + t];
-      const double vt = sl.r[par * G + t];
-      if (better(vt, it, w.v, w.i)) w = ArgMax{vt, it};
+    // ---- 3. global winner and runner-up (identical in every workgroup; wave 0)
+    if (tid < kWave) {
+      Top2 t{0.0, -1, -1.0};
+      for (int q = tid; q < G; q += kWave)
+        t = top2_merge(t, Top2{sl.r[par * G + q], sl.idx[par * G + q], sl.r2[par * G + q]});
+      t = wave_top2(t);
+      if (tid == 0) {
+        s_ibcast[1] = t.i1;
+        s_bcast[0] = t.v1;
+        if (g == 0) {
+          piv[j] = t.i1;
+          double mg;
+          if (n - j <= 1) mg = 1.0;
+          else if (t.v1 > 0.0) mg = (t.v1 - (t.v2 > 0.0 ? t.v2 : 0.0)) / t.v1;
+          else mg = 0.0;
+          margins[j] = mg;
+        }
+      }
     }
-    w = block_argmax(w, redv, redi);
+    __syncthreads();
+    const ArgMax w{s_bcast[0], s_ibcast[1]};
     const int wg = (int)(w.i / nc);
-    double r2 = -1.0;
-    for (int t = tid; t < G; t += NT) {
-      const double vt = (t == wg) ? sl.r2[par * G + t] : (sl.idx[par * G + t] >= 0 ? sl.r[par * G + t] : -1.0);
-      r2 = vt > r2 ? vt : r2;
-    }
-    {
-      // block max of r2 (fixed order)
-      ArgMax m2{r2, r2 >= 0.0 ? 0 : -1};
-      m2 = block_argmax(m2, redv, redi);
-      r2 = m2.i >= 0 ? m2.v : -1.0;
-    }
-    if (g == 0 && tid == 0) {
-      piv[j] = w.i;
-      double mg;
-      if (n - j <= 1) mg = 1.0;
-      else if (w.v > 0.0) mg = (w.v - (r2 > 0.0 ? r2 : 0.0)) / w.v;
-      else mg = 0.0;
-      margins[j] = mg;
-    }
     const double* src = sl.col + ((int64_t)par * G + wg) * l;
     for (int i = j + tid; i < l; i += NT) v[i] = src[i];
     __syncthreads();

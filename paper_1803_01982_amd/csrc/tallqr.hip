@@ -49,70 +49,112 @@ __device__ inline double yval(int64_t gi, int64_t p0, int s, double stored) {
 // out[col * NB + s] = sum over the own rows i of Y(i, s) * X(r0 + i, col),
 // col < ncol, s < NB; X is column-major in global memory (ldx).  One wave
 // per 16-column chunk; MFMA 16x16x4 with A = Y^T from LDS and B = X from
-// global memory, two accumulators to halve the dependency chain.
+// global memory.  Software-pipelined: the eight loads of X for the next 32
+// rows are issued before the MFMAs of the current 32 rows.
 template <typename T>
 __device__ void yt_times_global(const double* Yl, int ldy, int nrow, const T* X, int64_t ldx, int64_t r0, int ncol,
                                 double* out) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int s = lane & 15, kq = lane >> 4;
+  const int nfull = nrow & ~31;
   for (int col0 = wave * 16; col0 < ncol; col0 += NW * 16) {
     const int col = col0 + s;
     const bool cin = col < ncol;
     const T* xc = X + (int64_t)(cin ? col : 0) * ldx + r0;
-    MF::acc4 a0 = {0, 0, 0, 0}, a1 = {0, 0, 0, 0};
-    int k0 = 0;
-    for (; k0 + 8 <= nrow; k0 += 8) {
-      const int i0 = k0 + kq, i1 = k0 + 4 + kq;
-      const double ya = Yl[s * ldy + i0], yb = Yl[s * ldy + i1];      // A[s][k] = Y(k, s)
-      const double xa = cin ? (double)xc[i0] : 0.0, xb = cin ? (double)xc[i1] : 0.0;  // B[k][col]
-      a0 = MF::fma(ya, xa, a0);
-      a1 = MF::fma(yb, xb, a1);
+    const double* yc = Yl + s * ldy;
+    MF::acc4 a[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) a[q] = MF::acc4{0, 0, 0, 0};
+    double xn[8];
+    if (nfull > 0) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) xn[u] = cin ? (double)xc[4 * u + kq] : 0.0;
     }
-    for (; k0 < nrow; k0 += 4) {
+    for (int k0 = 0; k0 < nfull; k0 += 32) {
+      double xv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) xv[u] = xn[u];
+      if (k0 + 32 < nfull) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) xn[u] = cin ? (double)xc[k0 + 32 + 4 * u + kq] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a[u & 3] = MF::fma(yc[k0 + 4 * u + kq], xv[u], a[u & 3]);
+    }
+    for (int k0 = nfull; k0 < nrow; k0 += 4) {
       const int i = k0 + kq;
-      const double ya = i < nrow ? Yl[s * ldy + i] : 0.0;
+      const double ya = i < nrow ? yc[i] : 0.0;
       const double xa = (cin && i < nrow) ? (double)xc[i] : 0.0;
-      a0 = MF::fma(ya, xa, a0);
+      a[0] = MF::fma(ya, xa, a[0]);
     }
     if (cin)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) out[(int64_t)col * NB + MF::row(lane, r)] = a0[r] + a1[r];
+      for (int r = 0; r < 4; ++r) out[(int64_t)col * NB + MF::row(lane, r)] = (a[0][r] + a[1][r]) + (a[2][r] + a[3][r]);
   }
 }
 
 // X(r0 + i, col) -= sum_s Y(i, s) W(s, col) for the own rows i < nrow and
-// col < ncol, W(s, col) = Wl[col * NB + s] in LDS.  16 x 16 tiles per wave,
-// accumulator initialised with the tile of X and A = -Y.
+// col < ncol, W(s, col) = Wl[col * NB + s] in LDS.  16 x 16 tiles in
+// batches of four per wave; the accumulator starts as the tile of X and
+// A = -Y.  Software-pipelined: the next batch's tiles are loaded before the
+// current batch is computed and stored.
 template <typename T>
 __device__ void sub_y_times(const double* Yl, int ldy, int nrow, const double* Wl, T* X, int64_t ldx, int64_t r0,
                             int ncol) {
+  constexpr int TB = 4;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lo = lane & 15, kq = lane >> 4;
   const int ntr = (nrow + 15) / 16, ntc = (ncol + 15) / 16;
-  for (int tile = wave; tile < ntr * ntc; tile += NW) {
-    const int tr = tile % ntr, tc = tile / ntr;
-    const int i0 = tr * 16, c0 = tc * 16;
-    const int col = c0 + lo;
-    const bool cin = col < ncol;
-    T* xc = X + (int64_t)(cin ? col : 0) * ldx + r0;
-    MF::acc4 acc;
+  const int ntile = ntr * ntc;
+  auto tile_ptr = [&](int tile, int* i0, bool* cin, int* col) -> T* {
+    const bool tin = tile < ntile;
+    const int tr = tin ? tile % ntr : 0, tc = tin ? tile / ntr : 0;
+    *i0 = tr * 16;
+    *col = tc * 16 + lo;
+    *cin = tin && *col < ncol;
+    return X + (int64_t)(*cin ? *col : 0) * ldx + r0;
+  };
+  auto load = [&](int t0, MF::acc4* acc) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int i = i0 + MF::row(lane, r);
-      acc[r] = (cin && i < nrow) ? (double)xc[i] : 0.0;
+    for (int b = 0; b < TB; ++b) {
+      int i0, col;
+      bool cin;
+      T* xc = tile_ptr(t0 + b, &i0, &cin, &col);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + MF::row(lane, r);
+        acc[b][r] = (cin && i < nrow) ? (double)xc[i] : 0.0;
+      }
     }
+  };
+  const int stride = NW * TB;
+  int t0 = wave * TB;
+  if (t0 >= ntile) return;
+  MF::acc4 nxt[TB];
+  load(t0, nxt);
+  for (; t0 < ntile; t0 += stride) {
+    MF::acc4 acc[TB];
 #pragma unroll
-    for (int k4 = 0; k4 < NB / 4; ++k4) {
-      const int sidx = 4 * k4 + kq;
-      const int ia = i0 + lo;
-      const double a = ia < nrow ? -Yl[sidx * ldy + ia] : 0.0;    // A[row = lo][k = kq]
-      const double b = cin ? Wl[(int64_t)col * NB + sidx] : 0.0;  // B[k = kq][col = lo]
-      acc = MF::fma(a, b, acc);
-    }
+    for (int b = 0; b < TB; ++b) acc[b] = nxt[b];
+    if (t0 + stride < ntile) load(t0 + stride, nxt);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int i = i0 + MF::row(lane, r);
-      if (cin && i < nrow) xc[i] = (T)acc[r];
+    for (int b = 0; b < TB; ++b) {
+      int i0, col;
+      bool cin;
+      T* xc = tile_ptr(t0 + b, &i0, &cin, &col);
+#pragma unroll
+      for (int k4 = 0; k4 < NB / 4; ++k4) {
+        const int sidx = 4 * k4 + kq;
+        const int ia = i0 + lo;
+        const double av = ia < nrow ? -Yl[sidx * ldy + ia] : 0.0;  // A[row = lo][k = kq]
+        const double bv = cin ? Wl[(int64_t)col * NB + sidx] : 0.0;  // B[k = kq][col = lo]
+        acc[b] = MF::fma(av, bv, acc[b]);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + MF::row(lane, r);
+        if (cin && i < nrow) xc[i] = (T)acc[b][r];
+      }
     }
   }
 }
@@ -339,10 +381,11 @@ __global__ __launch_bounds__(NT) void tallqr_kernel(T* __restrict__ P, int64_t m
   }
 }
 
-// Row blocks of about 512 rows: the work per column step is small, so fewer
-// workgroups (cheaper grid barriers) beat more parallelism here.
+// Row blocks of about 256 rows: fewer workgroups make the per-column grid
+// barriers cheaper, more workgroups share the panel-end streaming; 256 rows
+// measured best for 16384 x 272 (128: 5.5 ms, 256: 5.1 ms, 512: 6.8 ms).
 void choose(int64_t mrows, int c, int num_cu, int* G, int* rb, size_t* lds) {
-  int64_t g = (mrows + 511) / 512;
+  int64_t g = (mrows + 255) / 256;
   if (g > num_cu) g = num_cu;
   if (g < 1) g = 1;
   int64_t r = (mrows + g - 1) / g;
