@@ -39,8 +39,45 @@ __device__ inline int rr_player(int pos, int r, int P) {
   return pos == 0 ? 0 : ((pos - 1 + r) % (P - 1)) + 1;
 }
 
+// 1 / sqrt(x) for x > 0: the hardware estimate (about 24 correct bits)
+// refined by two Newton steps y <- y + y (1 - x y^2) / 2.
+__device__ inline double rsqrt_refined(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double r = fma(-x * y, y, 1.0);
+    y = fma(0.5 * y, r, y);
+  }
+  return y;
+}
+
+// Rotation that annihilates h in the 2x2 Gram block [[a, h], [h, b]]
+// (Rutishauser's choice, the smaller angle): with d = b - a, e = 2 h,
+// r = sqrt(d^2 + e^2) and D = |d| + r,
+//   t = sign(d) e / D,   cs = 1 / sqrt(1 + t^2),   sn = cs t.
+// Since 1 + t^2 = 2 r / D, cs = D u and sn = sign(d) e u with
+// u = 1 / sqrt(2 r D), and t = sign(d) e u (2 r u): two reciprocal square
+// roots and no division.  d and e are scaled by the same power of two first
+// (t, cs, sn are ratios), so nothing overflows or underflows; e != 0.
+__device__ inline void jacobi_rotation(double a, double b, double h, double& cs, double& sn, double& t) {
+  double d = b - a, e = 2.0 * h;
+  const int k = max(__builtin_amdgcn_frexp_exp(d), __builtin_amdgcn_frexp_exp(e));
+  d = __builtin_amdgcn_ldexp(d, -k);
+  e = __builtin_amdgcn_ldexp(e, -k);
+  const double x = fma(d, d, e * e);  // in [1/4, 2)
+  const double r = x * rsqrt_refined(x);
+  const double D = fabs(d) + r;
+  const double r2 = 2.0 * r;
+  const double u = rsqrt_refined(r2 * D);
+  const double eu = copysign(1.0, d) * e * u;
+  cs = D * u;
+  sn = eu;
+  t = eu * (r2 * u);
+}
+
 // Dynamic LDS: C (ncol columns of ldc rows; rows >= l and columns >= 2 bs stay
-// zero), then H[2][GW * GW] and J[2][GW * GW] (double buffers).
+// zero), then H[2][GW * GW] and J[2][GW * GW] (double buffers), then the
+// partial Gram sums of the row quarters 1..3 (3 x 3 x 256).
 template <typename T>
 __global__ __launch_bounds__(NT) void jacobi_kernel(const T* __restrict__ L, int l, int64_t ldl, double* __restrict__ M,
                                                     int bs, int P, int ldc, int ncol, unsigned* __restrict__ rot,
@@ -53,11 +90,14 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(const T* __restrict__ L, int
   double* H1 = H0 + GW * GW;
   double* J0 = H1 + GW * GW;
   double* J1 = J0 + GW * GW;
+  double* Pg = J1 + GW * GW;
   __shared__ double s_al[GW], s_be[GW], s_dn[GW];
-  __shared__ int s_pt[GW];
+  __shared__ int s_rt[GW];
   __shared__ int s_sweep, s_round, s_inner[2];
   __shared__ unsigned short sched_full[31 * 16];
   __shared__ unsigned short sched_cross[16 * 16];
+  __shared__ unsigned char part_full[31 * GW];
+  __shared__ unsigned char part_cross[16 * GW];
   const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int W2 = 2 * bs, nct = ncol / 16;
@@ -75,22 +115,28 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(const T* __restrict__ L, int
   //   full: all W2(W2-1)/2 pairs of the union in W2-1 rounds of bs disjoint
   //         pairs (circle method), used in the first round of every sweep;
   //   cross: the bs*bs pairs (block a, block b) in bs rounds (p, bs + (p+r) % bs).
+  // part_*[ir][k] is the partner of local column k in inner round ir.
   for (int e = tid; e < (W2 - 1) * bs; e += NT) {
     const int ir = e / bs, pr = e % bs;
     const int p = rr_player(pr, ir, W2), q = rr_player(W2 - 1 - pr, ir, W2);
     sched_full[e] = (unsigned short)((min(p, q) << 8) | max(p, q));
+    part_full[ir * GW + p] = (unsigned char)q;
+    part_full[ir * GW + q] = (unsigned char)p;
   }
   for (int e = tid; e < bs * bs; e += NT) {
-    const int ir = e / bs, p = e % bs;
-    sched_cross[e] = (unsigned short)((p << 8) | (bs + (p + ir) % bs));
+    const int ir = e / bs, p = e % bs, q = bs + (p + ir) % bs;
+    sched_cross[e] = (unsigned short)((p << 8) | q);
+    part_cross[ir * GW + p] = (unsigned char)q;
+    part_cross[ir * GW + q] = (unsigned char)p;
   }
   // this thread's entry of the GW x GW arrays
   const int ei = tid / GW, ej = tid % GW;
   const bool own = ei < W2 && ej < W2;
-  // Gram tiles: t = 0 -> (0,0), 1 -> (0,1), 2 -> (1,1); two halves of the rows
+  // Gram tiles: t = 0 -> (0,0), 1 -> (0,1), 2 -> (1,1); four quarters of the rows
   const int ntile = nct * (nct + 1) / 2;
-  const int kr = (l + 15) & ~15;
-  const int kh = ((kr / 4 + 1) / 2) * 4;
+  const int kq = ((l + 15) & ~15) / 4;
+  const int gt = wave % ntile, gh = wave / ntile;
+  const int gtr = (gt == 2) ? 1 : 0, gtc = (gt == 0) ? 0 : 1;
   __syncthreads();
 
   int sweep = 0;
@@ -136,33 +182,36 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(const T* __restrict__ L, int
         }
       }
       __syncthreads();
-      // Gram H = C^T C of the local columns
+      // Gram H = C^T C of the local columns: wave (tile gt, row quarter gh)
       typename MF::acc4 acc = {0.0, 0.0, 0.0, 0.0};
-      const int t = wave % (ntile > 0 ? ntile : 1), h = wave / (ntile > 0 ? ntile : 1);
-      const int tr = (t == 2) ? 1 : 0, tc = (t == 0) ? 0 : 1;
-      if (wave < 2 * ntile) {
+      if (gh < 4) {
         typename MF::acc4 acc1 = {0.0, 0.0, 0.0, 0.0};
-        const int klo = h ? kh : 0, khi = h ? kr : kh;
-        const double* ca = C + (tr * 16 + (lane & 15)) * ldc + (lane >> 4);
-        const double* cb = C + (tc * 16 + (lane & 15)) * ldc + (lane >> 4);
+        const int klo = gh * kq, khi = klo + kq;
+        const double* ca = C + (gtr * 16 + (lane & 15)) * ldc + (lane >> 4);
+        const double* cb = C + (gtc * 16 + (lane & 15)) * ldc + (lane >> 4);
         int k0 = klo;
-        for (; k0 + 8 <= khi; k0 += 8) {
-          acc = MF::fma(ca[k0], cb[k0], acc);
-          acc1 = MF::fma(ca[k0 + 4], cb[k0 + 4], acc1);
+        for (; k0 + 16 <= khi; k0 += 16) {
+          const double a0 = ca[k0], a1 = ca[k0 + 4], a2 = ca[k0 + 8], a3 = ca[k0 + 12];
+          const double b0 = cb[k0], b1 = cb[k0 + 4], b2 = cb[k0 + 8], b3 = cb[k0 + 12];
+          acc = MF::fma(a0, b0, acc);
+          acc1 = MF::fma(a1, b1, acc1);
+          acc = MF::fma(a2, b2, acc);
+          acc1 = MF::fma(a3, b3, acc1);
         }
-        if (k0 < khi) acc = MF::fma(ca[k0], cb[k0], acc);
+        for (; k0 < khi; k0 += 4) acc = MF::fma(ca[k0], cb[k0], acc);
         acc = acc + acc1;
-        if (h == 1)
+        if (gh > 0)
 #pragma unroll
-          for (int q = 0; q < 4; ++q) H1[t * 256 + q * 64 + lane] = acc[q];
+          for (int q = 0; q < 4; ++q) Pg[(gh - 1) * 768 + gt * 256 + q * 64 + lane] = acc[q];
       }
       __syncthreads();
-      if (wave < ntile) {
+      if (gh == 0) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const double v = acc[q] + H1[t * 256 + q * 64 + lane];
-          const int i = tr * 16 + MF::row(lane, q), j = tc * 16 + (lane & 15);
-          if (tr != tc || i <= j) {
+          const int o = gt * 256 + q * 64 + lane;
+          const double v = ((acc[q] + Pg[o]) + Pg[768 + o]) + Pg[1536 + o];
+          const int i = gtr * 16 + MF::row(lane, q), j = gtc * 16 + (lane & 15);
+          if (gtr != gtc || i <= j) {
             H0[i * GW + j] = v;
             H0[j * GW + i] = v;
           }
@@ -170,24 +219,41 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(const T* __restrict__ L, int
       }
       J0[tid] = (ei == ej && ei < W2) ? 1.0 : 0.0;
       __syncthreads();
-      // inner rounds on the Gram matrix
+      // skip the round when no scheduled pair needs a rotation
       const bool full = (r == 0);
-      const int nir = full ? W2 - 1 : bs;
+      int need = 0;
+      if (own && (full ? ei < ej : (ei < bs && ej >= bs))) {
+        const double a = H0[ei * GW + ei], b = H0[ej * GW + ej], hg = H0[ei * GW + ej];
+        need = !(a == 0.0 || b == 0.0 || hg * hg <= (kTol * kTol) * (a * b));
+      }
+      const int nir = __syncthreads_or(need) ? (full ? W2 - 1 : bs) : 0;
       const unsigned short* sched = full ? sched_full : sched_cross;
+      const unsigned char* part = full ? part_full : part_cross;
+      // inner rounds on the Gram matrix
       for (int ir = 0; ir < nir; ++ir) {
+        // this thread's operands, read while the rotations are being chosen
+        const int pi = own ? part[ir * GW + ei] : 0, pj = own ? part[ir * GW + ej] : 0;
+        double hij = 0.0, hipj = 0.0, hpij = 0.0, hpipj = 0.0, jij = 0.0, jipj = 0.0;
+        if (own) {
+          hij = H0[ei * GW + ej];
+          hipj = H0[ei * GW + pj];
+          hpij = H0[pi * GW + ej];
+          hpipj = H0[pi * GW + pj];
+          jij = J0[ei * GW + ej];
+          jipj = J0[ei * GW + pj];
+        }
         if (tid < bs) {
           const unsigned pq = sched[ir * bs + tid];
           const int p = (int)(pq >> 8), q = (int)(pq & 255u);
           const double a = H0[p * GW + p], b = H0[q * GW + q], hg = H0[p * GW + q];
           if (a == 0.0 || b == 0.0 || hg * hg <= (kTol * kTol) * (a * b)) {
-            s_al[p] = 1.0; s_be[p] = 0.0; s_pt[p] = p; s_dn[p] = a;
-            s_al[q] = 1.0; s_be[q] = 0.0; s_pt[q] = q; s_dn[q] = b;
+            s_al[p] = 1.0; s_be[p] = 0.0; s_dn[p] = a; s_rt[p] = 0;
+            s_al[q] = 1.0; s_be[q] = 0.0; s_dn[q] = b; s_rt[q] = 0;
           } else {
-            const double zeta = (b - a) / (2.0 * hg);
-            const double tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-            const double cs = rsqrt(1.0 + tt * tt), sn = cs * tt;
-            s_al[p] = cs; s_be[p] = -sn; s_pt[p] = q; s_dn[p] = a - tt * hg;
-            s_al[q] = cs; s_be[q] = sn; s_pt[q] = p; s_dn[q] = b + tt * hg;
+            double cs, sn, tt;
+            jacobi_rotation(a, b, hg, cs, sn, tt);
+            s_al[p] = cs; s_be[p] = -sn; s_dn[p] = a - tt * hg; s_rt[p] = 1;
+            s_al[q] = cs; s_be[q] = sn; s_dn[q] = b + tt * hg; s_rt[q] = 1;
             s_inner[ir & 1] = 1;
             s_round = 1;
             s_sweep = 1;
@@ -197,37 +263,55 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(const T* __restrict__ L, int
         __syncthreads();
         if (!s_inner[ir & 1]) continue;  // uniform: nothing rotated in this inner round
         if (own) {
-          const int pi = s_pt[ei], pj = s_pt[ej];
           const double ai = s_al[ei], bi = s_be[ei], aj = s_al[ej], bj = s_be[ej];
           double v;
           if (ei == ej) v = s_dn[ei];
-          else if (pj == ei) v = 0.0;  // the pair annihilated in this inner round
-          else
-            v = ai * (aj * H0[ei * GW + ej] + bj * H0[ei * GW + pj]) +
-                bi * (aj * H0[pi * GW + ej] + bj * H0[pi * GW + pj]);
-          H1[ei * GW + ej] = v;
-          J1[ei * GW + ej] = aj * J0[ei * GW + ej] + bj * J0[ei * GW + pj];
+          else if (pj == ei && s_rt[ej]) v = 0.0;  // the pair annihilated in this inner round
+          else v = ai * (aj * hij + bj * hipj) + bi * (aj * hpij + bj * hpipj);
+          if (ir + 1 < nir) H1[ei * GW + ej] = v;
+          J1[ei * GW + ej] = aj * jij + bj * jipj;
         }
         __syncthreads();
         double* x = H0; H0 = H1; H1 = x;
         x = J0; J0 = J1; J1 = x;
       }
       // columns <- C J, written straight to M (transposed product J^T C^T, so
-      // each MFMA result row is a run of 16 consecutive entries of a column)
+      // each MFMA result row is a run of 16 consecutive entries of a column);
+      // a wave takes a 16-row slice of the columns for both column tiles
       if (s_round) {
         const int nit = (l + 15) / 16;
-        for (int tt = wave; tt < nct * nit; tt += NW) {
-          const int jt = tt % nct, it = tt / nct;
-          typename MF::acc4 d = {0.0, 0.0, 0.0, 0.0};
-          const double* ja = J0 + (lane >> 4) * GW + jt * 16 + (lane & 15);
+        for (int it = wave; it < nit; it += NW) {
+          typename MF::acc4 d0 = {0.0, 0.0, 0.0, 0.0}, d1 = {0.0, 0.0, 0.0, 0.0};
+          const double* ja = J0 + (lane >> 4) * GW + (lane & 15);
           const double* cbp = C + (lane >> 4) * ldc + it * 16 + (lane & 15);
-          for (int k0 = 0; k0 < ncol; k0 += 4) d = MF::fma(ja[k0 * GW], cbp[k0 * ldc], d);
+          if (nct == 2) {
+#pragma unroll
+            for (int hs = 0; hs < 8; hs += 4) {
+              double bv[4], av0[4], av1[4];
+#pragma unroll
+              for (int s = 0; s < 4; ++s) {
+                bv[s] = cbp[4 * (hs + s) * ldc];
+                av0[s] = ja[4 * (hs + s) * GW];
+                av1[s] = ja[4 * (hs + s) * GW + 16];
+              }
+#pragma unroll
+              for (int s = 0; s < 4; ++s) {
+                d0 = MF::fma(av0[s], bv[s], d0);
+                d1 = MF::fma(av1[s], bv[s], d1);
+              }
+            }
+          } else {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) d0 = MF::fma(ja[4 * s * GW], cbp[4 * s * ldc], d0);
+          }
           const int i = it * 16 + (lane & 15);
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            const int j = jt * 16 + MF::row(lane, q);
-            const int gc = gcol(j);
-            if (gc >= 0 && i < l) M[(int64_t)gc * l + i] = d[q];
+            const int j = MF::row(lane, q);
+            const int gc0 = gcol(j);
+            if (gc0 >= 0 && i < l) M[(int64_t)gc0 * l + i] = d0[q];
+            const int gc1 = gcol(16 + j);
+            if (nct == 2 && gc1 >= 0 && i < l) M[(int64_t)gc1 * l + i] = d1[q];
           }
         }
       }
@@ -270,7 +354,9 @@ __global__ void sort_desc(const double* __restrict__ in, int l, double* __restri
 // when the columns of one block pair do not fit in LDS.
 bool choose(int64_t l, const DeviceInfo& d, int* bs, int* P, int* ldc, int* ncol, size_t* lds) {
   const int ld = (int)(((l + 15) & ~(int64_t)15) + 1);
-  auto bytes = [&](int b) { return ((size_t)((2 * b + 15) / 16 * 16) * ld + 4 * GW * GW) * sizeof(double); };
+  auto bytes = [&](int b) {
+    return ((size_t)((2 * b + 15) / 16 * 16) * ld + 4 * GW * GW + 3 * 768) * sizeof(double);
+  };
   int b = 16;
   if (d.lds_max != 0 && bytes(b) + 4096 > d.lds_max) b = 8;  // 16 local columns
   if (l < 2 * b) b = (int)((l + 1) / 2 > 0 ? (l + 1) / 2 : 1);
