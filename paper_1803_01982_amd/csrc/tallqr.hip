@@ -4,24 +4,27 @@
 //     pivoted block; compact WY representation Q = I - Y T Y^T of Section 2.1);
 //   * the flip-flop step, QR of R^T (n x l) (Section 3.1).
 //
-// One cooperative launch.  Workgroup g owns the row block [g*rb, (g+1)*rb).
-// Columns are processed in panels of NB = 16:
+// One cooperative launch factors the matrix.  Workgroup g owns the row block
+// [g*rb, (g+1)*rb).  Columns are processed in panels of NB = 16:
 //   column step (one grid barrier): every workgroup publishes the partial
 //     dot products of the current column with the remaining panel columns
 //     over its rows (and the owner of the pivot row publishes that row);
 //     after the barrier all workgroups sum the partials in the same fixed
 //     order, build the same reflector (LAPACK xLARFG convention) and update
 //     their own rows of the panel, which stay in LDS for the whole panel;
-//   panel end (two grid barriers): Z = Y^T [Y | P_trail] is reduced
-//     (reduce-scatter, then every workgroup reads the whole Z), each
-//     workgroup forms the panel's T (LAPACK xLARFT, forward, columnwise)
-//     from the Gram part and applies P_trail -= Y (T^T (Y^T P_trail)) to its
-//     own rows.
-// Then Q = H_1 ... H_c [I; 0] is formed backwards panel by panel with the
-// same reduce pattern (Q -= Y (T (Y^T Q))), and signs are normalised so that
-// diag(R) >= 0.  The products with Y at the panel ends run on FP64 MFMA
-// (16x16x4) with operands read straight from global memory and LDS.  All
-// arithmetic is FP64; P and Q are stored as T.
+//   panel end (two grid barriers): Z = Y_p^T [Y_p | P_trail | Y_<p] is
+//     reduced (reduce-scatter, then every workgroup reads the whole Z), each
+//     workgroup forms the panel's T_p (LAPACK xLARFT, forward, columnwise)
+//     from the Gram part and applies P_trail -= Y_p (T_p^T (Y_p^T P_trail))
+//     to its own rows.  The workgroups also extend the T factor of the whole
+//     product H_1 ... H_c = I - Y T Y^T (Section 2.1) by the panel's column
+//     block, T(0:p0, p0:p1) = -T(0:p0, 0:p0) (Y_<p^T Y_p) T_p, each for a
+//     share of its rows.
+// Q = (I - Y T Y^T) [I; 0] = [I; 0] - Y M with M = T Y(0:c, :)^T (upper
+// triangular) is then one product: the cooperative kernel forms M (with the
+// sign normalisation diag(R) >= 0 folded into its columns), and a separate
+// tiled MFMA kernel over the whole chip writes Q.  All arithmetic is FP64;
+// P and Q are stored as T.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -29,15 +32,17 @@ namespace ffsrqr {
 
 namespace {
 
-constexpr int NT = 256, NB = 16, NW = NT / 64;
+constexpr int NT = 256, NB = 16, NW = NT / 64, TROWS = 8;
 using MF = Mfma<double>;
 
 struct TqSlots {
   double* dots;   // [2][G][NB]
   double* rowv;   // [2][NB]
-  double* zpart;  // [G][NB * cz]
-  double* zred;   // [2][NB * cz]
-  double* tst;    // [npan][NB * NB]
+  double* zpart;  // [G][NB * (c + NB)]
+  double* zred;   // [2][NB * (c + NB)]
+  double* tg;     // [c * c]  T of the whole product, row-major (upper triangle)
+  double* mt;     // [c * c]  M = T Y(0:c, :)^T with column signs, row-major
+  double* sgn;    // [c]      sign of diag(R)
 };
 
 // Y(gi, s) of panel p0 given the stored value at (gi, p0 + s).
@@ -161,17 +166,39 @@ __device__ void sub_y_times(const double* Yl, int ldy, int nrow, const double* W
 
 // Reduce-scatter of E entries over G partials into zred, then every block
 // copies the whole reduced Z into Zl.  Returns false on a barrier timeout.
+// The partials of an entry are summed in order q = 0, 1, ..., G-1 in every
+// run; their loads are issued in batches of 16 so that the latency of the
+// memory hierarchy is paid once per batch, not once per load.
 __device__ bool reduce_z(const double* zpart, double* zred, int64_t E, int64_t estride, int G, int g, double* Zl,
                          const GridSync& gs, unsigned& epoch) {
+  constexpr int RB = 16;
   if (!grid_barrier(gs, epoch)) return false;
   const int64_t e0 = E * g / G, e1 = E * (g + 1) / G;
   for (int64_t e = e0 + threadIdx.x; e < e1; e += NT) {
     double t = 0.0;
-    for (int q = 0; q < G; ++q) t += zpart[(int64_t)q * estride + e];
+    for (int q0 = 0; q0 < G; q0 += RB) {
+      double v[RB];
+#pragma unroll
+      for (int u = 0; u < RB; ++u) v[u] = q0 + u < G ? zpart[(int64_t)(q0 + u) * estride + e] : 0.0;
+#pragma unroll
+      for (int u = 0; u < RB; ++u) t += v[u];
+    }
     zred[e] = t;
   }
   if (!grid_barrier(gs, epoch)) return false;
-  for (int64_t e = threadIdx.x; e < E; e += NT) Zl[e] = zred[e];
+  for (int64_t b = 0; b < E; b += (int64_t)NT * RB) {
+    double v[RB];
+#pragma unroll
+    for (int u = 0; u < RB; ++u) {
+      const int64_t e = b + u * NT + threadIdx.x;
+      v[u] = e < E ? zred[e] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < RB; ++u) {
+      const int64_t e = b + u * NT + threadIdx.x;
+      if (e < E) Zl[e] = v[u];
+    }
+  }
   __syncthreads();
   return true;
 }
@@ -184,6 +211,7 @@ __global__ __launch_bounds__(NT) void tallqr_kernel(T* __restrict__ P, int64_t m
   __shared__ double red[NB * NB];
   __shared__ double Tl[NB * NB];
   __shared__ double taul[NB];
+  __shared__ double yv[NB];
   const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
   const int64_t r0 = (int64_t)g * rb;
   const int nrow = (int)max((int64_t)0, min((int64_t)rb, mrows - r0));
@@ -191,9 +219,9 @@ __global__ __launch_bounds__(NT) void tallqr_kernel(T* __restrict__ P, int64_t m
   // so that lanes along rows and lanes along columns both avoid bank conflicts
   const int ldy = rb | 1;
   double* Yl = smem;                    // ldy x NB
-  double* Zl = Yl + (int64_t)ldy * NB;  // NB x cz
+  double* Zl = Yl + (int64_t)ldy * NB;  // NB x (c + NB)
   const int npan = (c + NB - 1) / NB;
-  const int64_t estride = (int64_t)NB * (c > NB ? c : NB);
+  const int64_t estride = (int64_t)NB * (c + NB);
   unsigned epoch = 0;
   int step = 0;
 
@@ -286,8 +314,11 @@ __global__ __launch_bounds__(NT) void tallqr_kernel(T* __restrict__ P, int64_t m
       zp[cc * NB + s] = acc;
     }
     if (ntr > 0) yt_times_global<T>(Yl, ldy, nrow, P + (int64_t)p1 * ldp, ldp, r0, ntr, zp + NB * NB);
+    // Y_<p^T Y_p: Y_p vanishes on the rows above p0, where the stored entries
+    // of the earlier columns are not Householder entries, so P itself serves
+    if (p0 > 0) yt_times_global<T>(Yl, ldy, nrow, P, ldp, r0, p0, zp + NB * (NB + ntr));
     double* zr = sl.zred + (int64_t)(pi & 1) * estride;
-    if (!reduce_z(sl.zpart, zr, (int64_t)NB * (NB + ntr), estride, G, g, Zl, gs, epoch)) return;
+    if (!reduce_z(sl.zpart, zr, (int64_t)NB * (NB + ntr + p0), estride, G, g, Zl, gs, epoch)) return;
     // T of the panel: T(s,s) = tau_s, T(0:s, s) = -tau_s T(0:s, 0:s) (Y^T y_s)
     Tl[tid] = 0.0;
     __syncthreads();
@@ -303,7 +334,60 @@ __global__ __launch_bounds__(NT) void tallqr_kernel(T* __restrict__ P, int64_t m
       if (tid == s) Tl[s * NB + s] = ts;
       __syncthreads();
     }
-    if (g == 0) sl.tst[(int64_t)pi * NB * NB + tid] = Tl[tid];
+    // T of the whole product (row-major tg): the diagonal block T_p
+    // (workgroup 0) and the rows of T(0:p0, p0:p1) = -(T(i, i:p0) S(i:p0,
+    // p0:p1)) T_p shared out by row, S(k, p0 + s) = Zl[NB (NB + ntr) + k NB + s].
+    // The earlier columns of T were written at earlier panel ends, before at
+    // least one barrier.  Rows go through LDS in chunks of TROWS, their
+    // global loads issued together.
+    if (g == 0 && tid < NB * NB) {
+      const int q = tid / NB, s = tid % NB;
+      if (q < pw && s < pw) sl.tg[(int64_t)(p0 + q) * c + p0 + s] = Tl[s * NB + q];
+    }
+    {
+      const double* Sz = Zl + NB * (NB + ntr);
+      double* Ts = Zl + NB * (c + NB);  // TROWS x p0
+      const int ilo = (int)((int64_t)p0 * g / G), ihi = (int)((int64_t)p0 * (g + 1) / G);
+      for (int rc = ilo; rc < ihi; rc += TROWS) {
+        const int nr = min(TROWS, ihi - rc), ne = nr * p0;
+        for (int e0 = 0; e0 < ne; e0 += NT * 9) {
+          double v[9];
+#pragma unroll
+          for (int u = 0; u < 9; ++u) {
+            const int e = e0 + u * NT + tid;
+            const int r = e / p0, k = e - r * p0;
+            v[u] = (e < ne && k >= rc + r) ? sl.tg[(int64_t)(rc + r) * c + k] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < 9; ++u) {
+            const int e = e0 + u * NT + tid;
+            if (e < ne) Ts[e] = v[u];
+          }
+        }
+        __syncthreads();
+        // y(r, s) = sum_k T(rc + r, k) S(k, s): two halves of k per (r, s)
+        {
+          const int half = tid / (TROWS * NB), rs = tid % (TROWS * NB), r = rs / NB, s = rs % NB;
+          double acc = 0.0;
+          if (r < nr) {
+            const int kmid = (rc + r + p0) / 2;
+            const int klo = half ? kmid : rc + r, khi = half ? p0 : kmid;
+            for (int k = klo; k < khi; ++k) acc += Ts[r * p0 + k] * Sz[k * NB + s];
+          }
+          red[tid] = acc;
+        }
+        __syncthreads();
+        if (tid < TROWS * NB) {
+          const int r = tid / NB, s = tid % NB;
+          if (r < nr && s < pw) {
+            double v = 0.0;
+            for (int q = 0; q <= s; ++q) v += (red[r * NB + q] + red[TROWS * NB + r * NB + q]) * Tl[s * NB + q];
+            sl.tg[(int64_t)(rc + r) * c + p0 + s] = -v;
+          }
+        }
+        __syncthreads();
+      }
+    }
     // W' = T^T Z_trail (in place, column by column)
     for (int u = tid; u < ntr; u += NT) {
       double z[NB], w[NB];
@@ -323,62 +407,123 @@ __global__ __launch_bounds__(NT) void tallqr_kernel(T* __restrict__ P, int64_t m
     if (ntr > 0) sub_y_times<T>(Yl, ldy, nrow, Zl + NB * NB, P + (int64_t)p1 * ldp, ldp, r0, ntr);
   }
 
-  // --------------------------------------------------- explicit Q, backwards
-  // the T factors written by workgroup 0 at the panel ends must be visible
+  // ------------------------------------- M = T Y(0:c, :)^T, column signs
+  // every T block and every stored P entry must be visible
   if (!grid_barrier(gs, epoch)) return;
-  for (int j = 0; j < c; ++j)
-    for (int i = tid; i < nrow; i += NT) Qout[(int64_t)j * ldq + r0 + i] = (T)(r0 + i == j ? 1.0 : 0.0);
-  for (int pi = npan - 1; pi >= 0; --pi) {
-    const int p0 = pi * NB, p1 = min(c, p0 + NB), pw = p1 - p0;
-    const int ncol = c - p0;
-    __syncthreads();
-    for (int s = 0; s < NB; ++s)
-      for (int i = tid; i < nrow; i += NT)
-        Yl[s * ldy + i] = s < pw ? yval(r0 + i, p0, s, (double)P[(int64_t)(p0 + s) * ldp + r0 + i]) : 0.0;
-    Tl[tid] = sl.tst[(int64_t)pi * NB * NB + tid];
-    __syncthreads();
-    double* zp = sl.zpart + (int64_t)g * estride;
-    yt_times_global<T>(Yl, ldy, nrow, Qout + (int64_t)p0 * ldq, ldq, r0, ncol, zp);
-    double* zr = sl.zred + (int64_t)(pi & 1) * estride;
-    if (!reduce_z(sl.zpart, zr, (int64_t)NB * ncol, estride, G, g, Zl, gs, epoch)) return;
-    // W2 = T Z (T upper triangular)
-    for (int u = tid; u < ncol; u += NT) {
-      double z[NB], w[NB];
+  {
+    // 16 x 16 tiles of M, one wave each: M(I, J) = sum_{k} T(I, k) Y(J, k)^T,
+    // T(i, k) = 0 for k < i and Y(j, k) = 0 for k > j, so k runs over
+    // [16 I, 16 J + 16); a tile below the diagonal is zero
+    const int lane = tid & 63, wave = tid >> 6;
+    const int nt = (c + 15) / 16;
+    for (int t = g * NW + wave; t < nt * nt; t += G * NW) {
+      const int I = t / nt, J = t % nt;
+      const int i = 16 * I + (lane & 15), j = 16 * J + (lane & 15);
+      const int khi = min(c, 16 * J + 16);
+      MF::acc4 acc = {0, 0, 0, 0};
+      for (int k0 = 16 * I; k0 < khi; k0 += 32) {
+        // eight MFMA steps with their loads issued together
+        double a[8], b[8];
 #pragma unroll
-      for (int q = 0; q < NB; ++q) z[q] = Zl[u * NB + q];
+        for (int u = 0; u < 8; ++u) {
+          const int k = k0 + 4 * u + (lane >> 4);
+          // A(row i, k) = T(i, k); B(k, col j) = Y(j, k)
+          a[u] = (i < c && k < khi && k >= i) ? sl.tg[(int64_t)i * c + k] : 0.0;
+          b[u] = (j < c && k < khi && k <= j) ? (k == j ? 1.0 : (double)P[(int64_t)k * ldp + j]) : 0.0;
+        }
 #pragma unroll
-      for (int r = 0; r < NB; ++r) {
-        double a = 0.0;
-        for (int q = r; q < NB; ++q) a += Tl[q * NB + r] * z[q];
-        w[r] = a;
+        for (int u = 0; u < 8; ++u) acc = MF::fma(a[u], b[u], acc);
       }
+      if (j < c) {
+        const double sj = ((double)P[(int64_t)j * ldp + j] < 0.0) ? -1.0 : 1.0;
 #pragma unroll
-      for (int q = 0; q < NB; ++q) Zl[u * NB + q] = w[q];
+        for (int r = 0; r < 4; ++r) {
+          const int ii = 16 * I + MF::row(lane, r);
+          if (ii < c) sl.mt[(int64_t)ii * c + j] = acc[r] * sj;
+        }
+        if (I == 0 && lane < 16) sl.sgn[j] = sj;
+      }
     }
-    __syncthreads();
-    sub_y_times<T>(Yl, ldy, nrow, Zl, Qout + (int64_t)p0 * ldq, ldq, r0, ncol);
   }
-  __syncthreads();
 
-  // --------------------------------------------------- signs, R output
+  // --------------------------------------------------- R output, diag(R) >= 0
+  if (r0 >= c) return;
   double* sgn = Zl;  // c entries
   for (int j = tid; j < c; j += NT) sgn[j] = ((double)P[(int64_t)j * ldp + j] < 0.0) ? -1.0 : 1.0;
   __syncthreads();
-  for (int j = 0; j < c; ++j) {
-    const bool flip = sgn[j] < 0.0;
-    for (int i = tid; i < nrow; i += NT) {
-      const int64_t gi = r0 + i;
-      if (flip) {
-        T* qq = Qout + (int64_t)j * ldq + gi;
-        *qq = -*qq;
-      }
-      if (gi < c) {
-        const double val = (j >= gi) ? sgn[gi] * (double)P[(int64_t)j * ldp + gi] : 0.0;
-        if (transpose_r) R[gi * ldr + j] = (T)val;
-        else R[(int64_t)j * ldr + gi] = (T)val;
-      }
+  const int rows = (int)min((int64_t)nrow, (int64_t)c - r0);
+  for (int64_t e = tid; e < (int64_t)rows * c; e += NT) {
+    const int i = (int)(e % rows), j = (int)(e / rows);
+    const int64_t gi = r0 + i;
+    const double val = (j >= gi) ? sgn[gi] * (double)P[(int64_t)j * ldp + gi] : 0.0;
+    if (transpose_r) R[gi * ldr + j] = (T)val;
+    else R[(int64_t)j * ldr + gi] = (T)val;
+  }
+}
+
+// Q(i, j) = [i == j] sgn_j - sum_{k <= min(i, j)} Y(i, k) M'(k, j), with
+// M' = M diag(sgn) row-major (mt) and Y the unit lower trapezoidal
+// Householder vectors stored in P.  64 x 64 tiles of Q per workgroup, K in
+// steps of 16 through LDS; the MFMA computes the transposed tile
+// (A = M'^T, B = Y^T) so that each result row is a run of 16 consecutive
+// entries of a column of Q.  Column tiles stop at K = j0 + 64 (M' is upper
+// triangular), row tiles at K = i0 + 64 (Y is lower trapezoidal).
+constexpr int WY_T = 64, WY_K = 16, WY_LD = WY_T + 16;
+
+template <typename T>
+__global__ __launch_bounds__(256) void wy_apply_kernel(const T* __restrict__ P, int64_t mrows, int c, int64_t ldp,
+                                                       const double* __restrict__ mt, const double* __restrict__ sgn,
+                                                       T* __restrict__ Q, int64_t ldq) {
+  __shared__ double Ys[WY_K * WY_LD];  // Ys[k * WY_LD + i] = Y(i0 + i, k0 + k)
+  __shared__ double Ms[WY_K * WY_LD];  // Ms[k * WY_LD + j] = M'(k0 + k, j0 + j)
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t i0 = (int64_t)blockIdx.x * WY_T;
+  const int j0 = blockIdx.y * WY_T;
+  const int wr = wave & 1, wc = wave >> 1;  // 32 x 32 quarter of the tile: rows (i) wr, columns (j) wc
+  int64_t kmax = min((int64_t)c, (int64_t)j0 + WY_T);
+  kmax = min(kmax, i0 + WY_T);
+  MF::acc4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = MF::acc4{0, 0, 0, 0};
+  for (int k0 = 0; k0 < kmax; k0 += WY_K) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = tid + 256 * u, k = e / WY_T, x = e % WY_T;
+      const int64_t gk = k0 + k, gi = i0 + x;
+      double yv = 0.0;
+      if (gk < kmax && gi < mrows) yv = gi < gk ? 0.0 : (gi == gk ? 1.0 : (double)P[gk * ldp + gi]);
+      Ys[k * WY_LD + x] = yv;
+      const int gj = j0 + x;
+      Ms[k * WY_LD + x] = (gk < kmax && gj < c) ? mt[gk * c + gj] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < WY_K; kk += 4) {
+      const int k = kk + (lane >> 4);
+      double av[2], bv[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) av[a] = Ms[k * WY_LD + wc * 32 + a * 16 + (lane & 15)];  // A(j, k)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) bv[b] = Ys[k * WY_LD + wr * 32 + b * 16 + (lane & 15)];  // B(k, i)
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = MF::fma(av[a], bv[b], acc[a][b]);
     }
   }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int j = j0 + wc * 32 + a * 16 + MF::row(lane, r);
+        const int64_t i = i0 + wr * 32 + b * 16 + (lane & 15);
+        if (j < c && i < mrows) Q[(int64_t)j * ldq + i] = (T)((i == j ? sgn[j] : 0.0) - acc[a][b][r]);
+      }
 }
 
 // Row blocks of about 256 rows: fewer workgroups make the per-column grid
@@ -391,7 +536,7 @@ void choose(int64_t mrows, int c, int num_cu, int* G, int* rb, size_t* lds) {
   int64_t r = (mrows + g - 1) / g;
   *G = (int)((mrows + r - 1) / r);
   *rb = (int)r;
-  *lds = ((size_t)(r | 1) * NB + (size_t)NB * (c > NB ? c : NB) + 64) * sizeof(double);
+  *lds = ((size_t)(r | 1) * NB + (size_t)NB * (c + NB) + (size_t)TROWS * c + 64) * sizeof(double);
 }
 
 template <typename T>
@@ -424,10 +569,9 @@ size_t tallqr_scratch(int64_t mrows, int64_t c, const DeviceInfo& d) {
   int G, rb;
   size_t lds;
   choose(mrows, (int)c, d.num_cu, &G, &rb, &lds);
-  const int npan = (int)((c + NB - 1) / NB);
-  const size_t cz = c > NB ? c : NB;
+  const size_t cz = (size_t)c + NB;
   size_t b = sizeof(double) * ((size_t)2 * G * NB + 2 * NB + (size_t)G * NB * cz + (size_t)2 * NB * cz +
-                               (size_t)npan * NB * NB);
+                               (size_t)2 * c * c + c);
   return b + kSyncWords * sizeof(unsigned) + 8 * 256;
 }
 
@@ -440,16 +584,18 @@ hipError_t tall_qr(T* P, int64_t mrows, int64_t c, int64_t ldp, T* Qout, int64_t
   size_t lds;
   choose(mrows, (int)c, d.num_cu, &G, &rb, &lds);
   if (lds > d.lds_max) return hipErrorInvalidValue;
-  const int npan = (int)((c + NB - 1) / NB);
-  const size_t cz = c > NB ? c : NB;
+  const size_t cz = (size_t)c + NB;
   TqSlots sl;
   sl.dots = ar.take<double>((size_t)2 * G * NB);
   sl.rowv = ar.take<double>(2 * NB);
   sl.zpart = ar.take<double>((size_t)G * NB * cz);
   sl.zred = ar.take<double>((size_t)2 * NB * cz);
-  sl.tst = ar.take<double>((size_t)npan * NB * NB);
+  sl.tg = ar.take<double>((size_t)c * c);
+  sl.mt = ar.take<double>((size_t)c * c);
+  sl.sgn = ar.take<double>((size_t)c);
   unsigned* counter = ar.take<unsigned>(kSyncWords);
-  if (!sl.dots || !sl.rowv || !sl.zpart || !sl.zred || !sl.tst || !counter) return hipErrorOutOfMemory;
+  if (!sl.dots || !sl.rowv || !sl.zpart || !sl.zred || !sl.tg || !sl.mt || !sl.sgn || !counter)
+    return hipErrorOutOfMemory;
   hipError_t e = zero_words(counter, kSyncWords, s);
   if (e != hipSuccess) return e;
   GridSync gs{counter, err, (unsigned)G};
@@ -461,7 +607,11 @@ hipError_t tall_qr(T* P, int64_t mrows, int64_t c, int64_t ldp, T* Qout, int64_t
     e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  return hipLaunchCooperativeKernel(fn, dim3(G), dim3(NT), args, (unsigned)lds, s);
+  e = hipLaunchCooperativeKernel(fn, dim3(G), dim3(NT), args, (unsigned)lds, s);
+  if (e != hipSuccess) return e;
+  dim3 grid((unsigned)((mrows + WY_T - 1) / WY_T), (unsigned)((c + WY_T - 1) / WY_T));
+  wy_apply_kernel<T><<<grid, 256, 0, s>>>(P, mrows, ci, ldp, sl.mt, sl.sgn, Qout, ldq);
+  return hipGetLastError();
 }
 
 template <typename T>
