@@ -12,19 +12,23 @@
 //     after the barrier all workgroups sum the partials in the same fixed
 //     order, build the same reflector (LAPACK xLARFG convention) and update
 //     their own rows of the panel, which stay in LDS for the whole panel;
-//   panel end (two grid barriers): Z = Y_p^T [Y_p | P_trail | Y_<p] is
-//     reduced (reduce-scatter, then every workgroup reads the whole Z), each
+//   panel end (two grid barriers): Z = Y_p^T [Y_p | P_trail] is reduced
+//     (reduce-scatter, then every workgroup reads the whole Z), each
 //     workgroup forms the panel's T_p (LAPACK xLARFT, forward, columnwise)
 //     from the Gram part and applies P_trail -= Y_p (T_p^T (Y_p^T P_trail))
-//     to its own rows.  The workgroups also extend the T factor of the whole
-//     product H_1 ... H_c = I - Y T Y^T (Section 2.1) by the panel's column
-//     block, T(0:p0, p0:p1) = -T(0:p0, 0:p0) (Y_<p^T Y_p) T_p, each for a
-//     share of its rows.
-// Q = (I - Y T Y^T) [I; 0] = [I; 0] - Y M with M = T Y(0:c, :)^T (upper
-// triangular) is then one product: the cooperative kernel forms M (with the
-// sign normalisation diag(R) >= 0 folded into its columns), and a separate
-// tiled MFMA kernel over the whole chip writes Q.  All arithmetic is FP64;
-// P and Q are stored as T.
+//     to its own rows.
+// Within a panel the rows of the 16 columns stay in registers.
+//
+// Q = H_1 ... H_c [I; 0] = [I; 0] - Y T Y(0:c, :)^T (compact WY form of the
+// whole product, Section 2.1) is then formed by three tiled kernels over the
+// whole chip instead of panel by panel: S = Y^T Y (split over row chunks,
+// then summed in a fixed order); M = T Y(0:c, :)^T by triangular solves with
+// T^-1 = striu(S) + diag(1/tau) (the identity behind the compact WY form;
+// tau = 0 drops the reflector), one workgroup per column, with the signs
+// that make diag(R) >= 0 folded in; Q = [I; 0] diag(sgn) - Y M.  All
+// arithmetic is FP64; P and Q are stored as T.
+#include <algorithm>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -32,7 +36,7 @@ namespace ffsrqr {
 
 namespace {
 
-constexpr int NT = 256, NB = 16, NW = NT / 64, TROWS = 8;
+constexpr int NT = 256, NB = 16, NW = NT / 64;
 using MF = Mfma<double>;
 
 struct TqSlots {
@@ -40,9 +44,7 @@ struct TqSlots {
   double* rowv;   // [2][NB]
   double* zpart;  // [G][NB * (c + NB)]
   double* zred;   // [2][NB * (c + NB)]
-  double* tg;     // [c * c]  T of the whole product, row-major (upper triangle)
-  double* mt;     // [c * c]  M = T Y(0:c, :)^T with column signs, row-major
-  double* sgn;    // [c]      sign of diag(R)
+  double* taus;   // [c]      tau of every reflector
 };
 
 // Y(gi, s) of panel p0 given the stored value at (gi, p0 + s).
@@ -174,16 +176,27 @@ __device__ bool reduce_z(const double* zpart, double* zred, int64_t E, int64_t e
   constexpr int RB = 16;
   if (!grid_barrier(gs, epoch)) return false;
   const int64_t e0 = E * g / G, e1 = E * (g + 1) / G;
-  for (int64_t e = e0 + threadIdx.x; e < e1; e += NT) {
-    double t = 0.0;
-    for (int q0 = 0; q0 < G; q0 += RB) {
+  const int ne = (int)(e1 - e0), nb = (G + RB - 1) / RB;
+  // (entry, batch of RB partials) items; the batch sums go through LDS (Zl,
+  // overwritten by the gather below) and are added in batch order
+  for (int it0 = 0; it0 < ne * nb; it0 += NT) {
+    const int it = it0 + threadIdx.x;
+    if (it < ne * nb) {
+      const int el = it % ne, q0 = (it / ne) * RB;
       double v[RB];
 #pragma unroll
-      for (int u = 0; u < RB; ++u) v[u] = q0 + u < G ? zpart[(int64_t)(q0 + u) * estride + e] : 0.0;
+      for (int u = 0; u < RB; ++u) v[u] = q0 + u < G ? zpart[(int64_t)(q0 + u) * estride + e0 + el] : 0.0;
+      double t = 0.0;
 #pragma unroll
       for (int u = 0; u < RB; ++u) t += v[u];
+      Zl[it] = t;
     }
-    zred[e] = t;
+  }
+  __syncthreads();
+  for (int el = threadIdx.x; el < ne; el += NT) {
+    double t = 0.0;
+    for (int b = 0; b < nb; ++b) t += Zl[b * ne + el];
+    zred[e0 + el] = t;
   }
   if (!grid_barrier(gs, epoch)) return false;
   for (int64_t b = 0; b < E; b += (int64_t)NT * RB) {
@@ -203,7 +216,7 @@ __device__ bool reduce_z(const double* zpart, double* zred, int64_t E, int64_t e
   return true;
 }
 
-template <typename T>
+template <typename T, int RPT>
 __global__ __launch_bounds__(NT) void tallqr_kernel(T* __restrict__ P, int64_t mrows, int c, int64_t ldp, int rb,
                                                     T* __restrict__ Qout, int64_t ldq, T* __restrict__ R, int64_t ldr,
                                                     int transpose_r, TqSlots sl, GridSync gs) {
@@ -211,7 +224,6 @@ __global__ __launch_bounds__(NT) void tallqr_kernel(T* __restrict__ P, int64_t m
   __shared__ double red[NB * NB];
   __shared__ double Tl[NB * NB];
   __shared__ double taul[NB];
-  __shared__ double yv[NB];
   const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
   const int64_t r0 = (int64_t)g * rb;
   const int nrow = (int)max((int64_t)0, min((int64_t)rb, mrows - r0));
@@ -226,42 +238,113 @@ __global__ __launch_bounds__(NT) void tallqr_kernel(T* __restrict__ P, int64_t m
   int step = 0;
 
   // ------------------------------------------------------------ factorization
+  // Within a panel each thread keeps its rows (i = tid + NT u, u < RPT) of the
+  // 16 panel columns in registers: the column steps touch no LDS except for
+  // the cross-wave part of the reductions.
   for (int pi = 0; pi < npan; ++pi) {
     const int p0 = pi * NB, p1 = min(c, p0 + NB), pw = p1 - p0;
-    __syncthreads();
-    for (int t = 0; t < NB; ++t)
-      for (int i = tid; i < nrow; i += NT)
-        Yl[t * ldy + i] = t < pw ? (double)P[(int64_t)(p0 + t) * ldp + r0 + i] : 0.0;
-    __syncthreads();
-    for (int jc = p0; jc < p1; ++jc, ++step) {
-      const int jt = jc - p0, par = step & 1;
-      // partial dots d_t = sum_{own rows > jc} x_i p_t(i), t = jt..pw-1
+    double y[RPT][NB];
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+      const int i = tid + NT * u;
+#pragma unroll
+      for (int t = 0; t < NB; ++t)
+        y[u][t] = (i < nrow && t < pw) ? (double)P[(int64_t)(p0 + t) * ldp + r0 + i] : 0.0;
+    }
+#pragma unroll
+    for (int jt = 0; jt < NB; ++jt) {
+      if (jt < pw) {
+      const int jc = p0 + jt, par = step & 1;
+      // partial dots over the own rows below jc: d_t = sum x_i p_t(i), t >= jt
       {
-        const int t = tid & (NB - 1), rs = tid / NB;
-        const int istart = (int)max((int64_t)0, (int64_t)jc + 1 - r0);
-        double acc = 0.0;
-        if (t >= jt && t < pw) {
-          const double* xc = Yl + jt * ldy;
-          const double* pc = Yl + t * ldy;
-          int i = istart + rs;
-          for (; i + 16 < nrow; i += 32) acc += xc[i] * pc[i] + xc[i + 16] * pc[i + 16];
-          for (; i < nrow; i += 16) acc += xc[i] * pc[i];
+        double d[NB];
+#pragma unroll
+        for (int t = 0; t < NB; ++t) d[t] = 0.0;
+#pragma unroll
+        for (int u = 0; u < RPT; ++u) {
+          const int i = tid + NT * u;
+          if (i < nrow && r0 + i > jc) {
+            const double x = y[u][jt];
+#pragma unroll
+            for (int t = jt; t < NB; ++t) d[t] += x * y[u][t];
+          }
         }
-        red[rs * NB + t] = acc;
+        // wave sums of the 16 values by halving exchanges: after the steps
+        // over lane bits 5, 4, 3, 2 a lane holds the sum for
+        // t = 8 b5 + 4 b4 + 2 b3 + b2, completed over lane bits 1, 0
+        const int lane = tid & 63, wave = tid >> 6;
+        double h8[8], h4[4], h2[2], h1;
+        {
+          const bool up = lane & 32;
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const double send = up ? d[k] : d[k + 8];
+            const double keep = up ? d[k + 8] : d[k];
+            h8[k] = keep + __shfl_xor(send, 32, kWave);
+          }
+        }
+        {
+          const bool up = lane & 16;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const double send = up ? h8[k] : h8[k + 4];
+            const double keep = up ? h8[k + 4] : h8[k];
+            h4[k] = keep + __shfl_xor(send, 16, kWave);
+          }
+        }
+        {
+          const bool up = lane & 8;
+#pragma unroll
+          for (int k = 0; k < 2; ++k) {
+            const double send = up ? h4[k] : h4[k + 2];
+            const double keep = up ? h4[k + 2] : h4[k];
+            h2[k] = keep + __shfl_xor(send, 8, kWave);
+          }
+        }
+        {
+          const bool up = lane & 4;
+          const double send = up ? h2[0] : h2[1];
+          const double keep = up ? h2[1] : h2[0];
+          h1 = keep + __shfl_xor(send, 4, kWave);
+        }
+        h1 += __shfl_xor(h1, 2, kWave);
+        h1 += __shfl_xor(h1, 1, kWave);
+        if ((lane & 3) == 0) {
+          const int t = ((lane >> 5) & 1) * 8 + ((lane >> 4) & 1) * 4 + ((lane >> 3) & 1) * 2 + ((lane >> 2) & 1);
+          red[wave * NB + t] = h1;
+        }
+        // the owner of row jc publishes that row of the panel
+#pragma unroll
+        for (int u = 0; u < RPT; ++u) {
+          const int i = tid + NT * u;
+          if (i < nrow && r0 + i == jc)
+#pragma unroll
+            for (int t = 0; t < NB; ++t) sl.rowv[par * NB + t] = y[u][t];
+        }
         __syncthreads();
         if (tid < NB) {
           double sacc = 0.0;
-          for (int q = 0; q < NT / NB; ++q) sacc += red[q * NB + tid];
+#pragma unroll
+          for (int q = 0; q < NW; ++q) sacc += red[q * NB + tid];
           sl.dots[((int64_t)par * G + g) * NB + tid] = sacc;
         }
-        if (jc >= r0 && jc < r0 + nrow && tid < NB) sl.rowv[par * NB + tid] = Yl[tid * ldy + (jc - r0)];
       }
       if (!grid_barrier(gs, epoch)) return;
       // sum the partials in a fixed order (identical in every workgroup)
       {
         const int t = tid & (NB - 1), gq = tid / NB;
+        constexpr int QB = 8;
         double acc = 0.0;
-        for (int q = gq; q < G; q += NT / NB) acc += sl.dots[((int64_t)par * G + q) * NB + t];
+        for (int q0 = gq; q0 < G; q0 += QB * (NT / NB)) {
+          double v[QB];
+#pragma unroll
+          for (int u = 0; u < QB; ++u) {
+            const int q = q0 + u * (NT / NB);
+            v[u] = q < G ? sl.dots[((int64_t)par * G + q) * NB + t] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < QB; ++u) acc += v[u];
+        }
         red[gq * NB + t] = acc;
         __syncthreads();
         if (tid < NB) {
@@ -279,30 +362,42 @@ __global__ __launch_bounds__(NT) void tallqr_kernel(T* __restrict__ P, int64_t m
         tau = (beta - x0) / beta;
         scale = 1.0 / (x0 - beta);
       }
-      if (tid == 0) taul[jt] = tau;
-      // own rows: p_t -= tau w_t v, w_t = p_t(jc) + scale d_t
-      const int istart = (int)max((int64_t)0, (int64_t)jc - r0);
-      for (int t = jt + 1; t < pw; ++t) {
-        const double twt = tau * (Tl[NB + t] + scale * Tl[t]);
-        for (int i = istart + tid; i < nrow; i += NT) {
-          const double v = (r0 + i == jc) ? 1.0 : Yl[jt * ldy + i] * scale;
-          Yl[t * ldy + i] -= twt * v;
+      if (tid == 0) {
+        taul[jt] = tau;
+        if (g == 0) sl.taus[jc] = tau;
+      }
+      // own rows: p_t -= tau w_t v, w_t = p_t(jc) + scale d_t, then the
+      // column becomes v (beta on the diagonal)
+      double tw[NB];
+#pragma unroll
+      for (int t = jt + 1; t < NB; ++t) tw[t] = tau * (Tl[NB + t] + scale * Tl[t]);
+#pragma unroll
+      for (int u = 0; u < RPT; ++u) {
+        const int64_t gi = r0 + tid + NT * u;
+        if (tid + NT * u < nrow && gi >= jc) {
+          const double vv = (gi == jc) ? 1.0 : y[u][jt] * scale;
+#pragma unroll
+          for (int t = jt + 1; t < NB; ++t) y[u][t] -= tw[t] * vv;
+          if (gi == jc) y[u][jt] = beta;
+          else if (tau != 0.0) y[u][jt] = vv;
         }
       }
-      __syncthreads();
-      for (int i = istart + tid; i < nrow; i += NT) {
-        if (r0 + i == jc) Yl[jt * ldy + i] = beta;
-        else if (tau != 0.0) Yl[jt * ldy + i] *= scale;
+      ++step;
       }
-      __syncthreads();
     }
-    // write the panel back (R above the diagonal, beta on it, v below)
-    for (int t = 0; t < pw; ++t)
-      for (int i = tid; i < nrow; i += NT) P[(int64_t)(p0 + t) * ldp + r0 + i] = (T)Yl[t * ldy + i];
-    __syncthreads();
-    // Y of the own rows
-    for (int s = 0; s < NB; ++s)
-      for (int i = tid; i < nrow; i += NT) Yl[s * ldy + i] = s < pw ? yval(r0 + i, p0, s, Yl[s * ldy + i]) : 0.0;
+    // write the panel back (R above the diagonal, beta on it, v below) and
+    // keep Y of the own rows in LDS for the panel end
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+      const int i = tid + NT * u;
+      if (i < nrow) {
+#pragma unroll
+        for (int t = 0; t < NB; ++t) {
+          if (t < pw) P[(int64_t)(p0 + t) * ldp + r0 + i] = (T)y[u][t];
+          Yl[t * ldy + i] = t < pw ? yval(r0 + i, p0, t, y[u][t]) : 0.0;
+        }
+      }
+    }
     __syncthreads();
     const int ntr = c - p1;
     double* zp = sl.zpart + (int64_t)g * estride;
@@ -314,11 +409,8 @@ __global__ __launch_bounds__(NT) void tallqr_kernel(T* __restrict__ P, int64_t m
       zp[cc * NB + s] = acc;
     }
     if (ntr > 0) yt_times_global<T>(Yl, ldy, nrow, P + (int64_t)p1 * ldp, ldp, r0, ntr, zp + NB * NB);
-    // Y_<p^T Y_p: Y_p vanishes on the rows above p0, where the stored entries
-    // of the earlier columns are not Householder entries, so P itself serves
-    if (p0 > 0) yt_times_global<T>(Yl, ldy, nrow, P, ldp, r0, p0, zp + NB * (NB + ntr));
     double* zr = sl.zred + (int64_t)(pi & 1) * estride;
-    if (!reduce_z(sl.zpart, zr, (int64_t)NB * (NB + ntr + p0), estride, G, g, Zl, gs, epoch)) return;
+    if (!reduce_z(sl.zpart, zr, (int64_t)NB * (NB + ntr), estride, G, g, Zl, gs, epoch)) return;
     // T of the panel: T(s,s) = tau_s, T(0:s, s) = -tau_s T(0:s, 0:s) (Y^T y_s)
     Tl[tid] = 0.0;
     __syncthreads();
@@ -333,60 +425,6 @@ __global__ __launch_bounds__(NT) void tallqr_kernel(T* __restrict__ P, int64_t m
       if (tid < s) Tl[s * NB + tid] = val;
       if (tid == s) Tl[s * NB + s] = ts;
       __syncthreads();
-    }
-    // T of the whole product (row-major tg): the diagonal block T_p
-    // (workgroup 0) and the rows of T(0:p0, p0:p1) = -(T(i, i:p0) S(i:p0,
-    // p0:p1)) T_p shared out by row, S(k, p0 + s) = Zl[NB (NB + ntr) + k NB + s].
-    // The earlier columns of T were written at earlier panel ends, before at
-    // least one barrier.  Rows go through LDS in chunks of TROWS, their
-    // global loads issued together.
-    if (g == 0 && tid < NB * NB) {
-      const int q = tid / NB, s = tid % NB;
-      if (q < pw && s < pw) sl.tg[(int64_t)(p0 + q) * c + p0 + s] = Tl[s * NB + q];
-    }
-    {
-      const double* Sz = Zl + NB * (NB + ntr);
-      double* Ts = Zl + NB * (c + NB);  // TROWS x p0
-      const int ilo = (int)((int64_t)p0 * g / G), ihi = (int)((int64_t)p0 * (g + 1) / G);
-      for (int rc = ilo; rc < ihi; rc += TROWS) {
-        const int nr = min(TROWS, ihi - rc), ne = nr * p0;
-        for (int e0 = 0; e0 < ne; e0 += NT * 9) {
-          double v[9];
-#pragma unroll
-          for (int u = 0; u < 9; ++u) {
-            const int e = e0 + u * NT + tid;
-            const int r = e / p0, k = e - r * p0;
-            v[u] = (e < ne && k >= rc + r) ? sl.tg[(int64_t)(rc + r) * c + k] : 0.0;
-          }
-#pragma unroll
-          for (int u = 0; u < 9; ++u) {
-            const int e = e0 + u * NT + tid;
-            if (e < ne) Ts[e] = v[u];
-          }
-        }
-        __syncthreads();
-        // y(r, s) = sum_k T(rc + r, k) S(k, s): two halves of k per (r, s)
-        {
-          const int half = tid / (TROWS * NB), rs = tid % (TROWS * NB), r = rs / NB, s = rs % NB;
-          double acc = 0.0;
-          if (r < nr) {
-            const int kmid = (rc + r + p0) / 2;
-            const int klo = half ? kmid : rc + r, khi = half ? p0 : kmid;
-            for (int k = klo; k < khi; ++k) acc += Ts[r * p0 + k] * Sz[k * NB + s];
-          }
-          red[tid] = acc;
-        }
-        __syncthreads();
-        if (tid < TROWS * NB) {
-          const int r = tid / NB, s = tid % NB;
-          if (r < nr && s < pw) {
-            double v = 0.0;
-            for (int q = 0; q <= s; ++q) v += (red[r * NB + q] + red[TROWS * NB + r * NB + q]) * Tl[s * NB + q];
-            sl.tg[(int64_t)(rc + r) * c + p0 + s] = -v;
-          }
-        }
-        __syncthreads();
-      }
     }
     // W' = T^T Z_trail (in place, column by column)
     for (int u = tid; u < ntr; u += NT) {
@@ -407,58 +445,159 @@ __global__ __launch_bounds__(NT) void tallqr_kernel(T* __restrict__ P, int64_t m
     if (ntr > 0) sub_y_times<T>(Yl, ldy, nrow, Zl + NB * NB, P + (int64_t)p1 * ldp, ldp, r0, ntr);
   }
 
-  // ------------------------------------- M = T Y(0:c, :)^T, column signs
-  // every T block and every stored P entry must be visible
-  if (!grid_barrier(gs, epoch)) return;
-  {
-    // 16 x 16 tiles of M, one wave each: M(I, J) = sum_{k} T(I, k) Y(J, k)^T,
-    // T(i, k) = 0 for k < i and Y(j, k) = 0 for k > j, so k runs over
-    // [16 I, 16 J + 16); a tile below the diagonal is zero
-    const int lane = tid & 63, wave = tid >> 6;
-    const int nt = (c + 15) / 16;
-    for (int t = g * NW + wave; t < nt * nt; t += G * NW) {
-      const int I = t / nt, J = t % nt;
-      const int i = 16 * I + (lane & 15), j = 16 * J + (lane & 15);
-      const int khi = min(c, 16 * J + 16);
-      MF::acc4 acc = {0, 0, 0, 0};
-      for (int k0 = 16 * I; k0 < khi; k0 += 32) {
-        // eight MFMA steps with their loads issued together
-        double a[8], b[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int k = k0 + 4 * u + (lane >> 4);
-          // A(row i, k) = T(i, k); B(k, col j) = Y(j, k)
-          a[u] = (i < c && k < khi && k >= i) ? sl.tg[(int64_t)i * c + k] : 0.0;
-          b[u] = (j < c && k < khi && k <= j) ? (k == j ? 1.0 : (double)P[(int64_t)k * ldp + j]) : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) acc = MF::fma(a[u], b[u], acc);
-      }
-      if (j < c) {
-        const double sj = ((double)P[(int64_t)j * ldp + j] < 0.0) ? -1.0 : 1.0;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int ii = 16 * I + MF::row(lane, r);
-          if (ii < c) sl.mt[(int64_t)ii * c + j] = acc[r] * sj;
-        }
-        if (I == 0 && lane < 16) sl.sgn[j] = sj;
-      }
-    }
-  }
-
   // --------------------------------------------------- R output, diag(R) >= 0
+  // (the own rows only: every entry read here was written by this workgroup)
   if (r0 >= c) return;
-  double* sgn = Zl;  // c entries
-  for (int j = tid; j < c; j += NT) sgn[j] = ((double)P[(int64_t)j * ldp + j] < 0.0) ? -1.0 : 1.0;
-  __syncthreads();
   const int rows = (int)min((int64_t)nrow, (int64_t)c - r0);
+  double* sgn = Zl;  // sign of diag(R) for the own rows
+  for (int i = tid; i < rows; i += NT) sgn[i] = ((double)P[(r0 + i) * ldp + r0 + i] < 0.0) ? -1.0 : 1.0;
+  __syncthreads();
   for (int64_t e = tid; e < (int64_t)rows * c; e += NT) {
     const int i = (int)(e % rows), j = (int)(e / rows);
     const int64_t gi = r0 + i;
-    const double val = (j >= gi) ? sgn[gi] * (double)P[(int64_t)j * ldp + gi] : 0.0;
+    const double val = (j >= gi) ? sgn[i] * (double)P[(int64_t)j * ldp + gi] : 0.0;
     if (transpose_r) R[gi * ldr + j] = (T)val;
     else R[(int64_t)j * ldr + gi] = (T)val;
   }
+}
+
+// Y(i, k) of the unit lower trapezoidal Householder block stored in P.
+template <typename T>
+__device__ inline double yload(const T* P, int64_t ldp, int64_t i, int64_t k) {
+  return i < k ? 0.0 : (i == k ? 1.0 : (double)P[k * ldp + i]);
+}
+
+// Partial Gram S = Y^T Y over one chunk of rows for one 64 x 64 tile pair
+// (I <= J) of the c x c result: spart[split][b * c + a] = sum_{i in chunk}
+// Y(i, a) Y(i, b).  Same LDS tiling as the WY product below.
+constexpr int WY_T = 64, WY_K = 16, WY_LD = WY_T + 16;
+
+template <typename T>
+__global__ __launch_bounds__(256) void gram_y_kernel(const T* __restrict__ P, int64_t mrows, int c, int64_t ldp,
+                                                     int64_t chunk, double* __restrict__ spart) {
+  __shared__ double Ya[WY_K * WY_LD];
+  __shared__ double Yb[WY_K * WY_LD];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nt = (c + WY_T - 1) / WY_T;
+  int I = 0, J = 0;
+  for (int pr = blockIdx.x; pr >= 0; ++I) {  // tile pair index -> (I, J), I <= J
+    if (pr < nt - I) {
+      J = I + pr;
+      break;
+    }
+    pr -= nt - I;
+  }
+  const int a0 = I * WY_T, b0 = J * WY_T;
+  const int64_t ilo = (int64_t)blockIdx.y * chunk;
+  // rows above a column carry no Householder entries
+  const int64_t ihi = min(mrows, ilo + chunk);
+  const int wa = wave & 1, wb = wave >> 1;
+  MF::acc4 acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = MF::acc4{0, 0, 0, 0};
+  for (int64_t k0 = ilo; k0 < ihi; k0 += WY_K) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = tid + 256 * u, k = e / WY_T, x = e % WY_T;
+      const int64_t gi = k0 + k;
+      const bool rin = gi < ihi;
+      Ya[k * WY_LD + x] = (rin && a0 + x < c) ? yload(P, ldp, gi, a0 + x) : 0.0;
+      Yb[k * WY_LD + x] = (rin && b0 + x < c) ? yload(P, ldp, gi, b0 + x) : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < WY_K; kk += 4) {
+      const int k = kk + (lane >> 4);
+      double av[2], bv[2];
+#pragma unroll
+      for (int x = 0; x < 2; ++x) av[x] = Yb[k * WY_LD + wb * 32 + x * 16 + (lane & 15)];  // A(b, i)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) bv[y] = Ya[k * WY_LD + wa * 32 + y * 16 + (lane & 15)];  // B(i, a)
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) acc[x][y] = MF::fma(av[x], bv[y], acc[x][y]);
+    }
+  }
+  double* out = spart + (int64_t)blockIdx.y * c * c;
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int b = b0 + wb * 32 + x * 16 + MF::row(lane, r);
+        const int a = a0 + wa * 32 + y * 16 + (lane & 15);
+        if (a < c && b < c) out[(int64_t)b * c + a] = acc[x][y][r];
+      }
+}
+
+// S = sum of the row-chunk partials in split order (upper triangle a <= b).
+__global__ void gram_sum_kernel(const double* __restrict__ spart, int nsplit, int c, double* __restrict__ S) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)c * c) return;
+  const int a = (int)(e % c), b = (int)(e / c);
+  if (a > b) return;
+  double t = 0.0;
+  for (int s = 0; s < nsplit; ++s) t += spart[(int64_t)s * c * c + e];
+  S[e] = t;
+}
+
+// Column j of M' = (T Y(0:c, :)^T) diag(sgn), row-major in mt, by back
+// substitution with U = T^-1 = striu(S) + diag(1/tau): U m = y_j with
+// y_j(k) = Y(j, k) (zero for k > j).  m_k = r_k tau_k, so tau_k = 0 gives
+// m_k = 0 (the reflector is the identity).  One workgroup per column; the
+// thread of row k holds r_k; each step broadcasts m_k through LDS, and the
+// next column of S is loaded while the current one is applied.
+template <typename T>
+__global__ __launch_bounds__(256) void wy_m_kernel(const T* __restrict__ P, int c, int64_t ldp,
+                                                   const double* __restrict__ S, const double* __restrict__ taus,
+                                                   double* __restrict__ mt, double* __restrict__ sgn) {
+  constexpr int RPT = 4;  // rows per thread: c <= 1024
+  __shared__ double s_m[2];
+  const int j = blockIdx.x, tid = threadIdx.x;
+  double r[RPT], scur[RPT];
+#pragma unroll
+  for (int u = 0; u < RPT; ++u) {
+    const int k = tid + 256 * u;
+    r[u] = (k <= j) ? yload(P, ldp, j, k) : 0.0;
+    scur[u] = (k < j) ? S[(int64_t)j * c + k] : 0.0;  // column j of striu(S)
+  }
+  for (int k = j; k >= 0; --k) {
+    // prefetch column k - 1 of striu(S)
+    double snext[RPT];
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+      const int i = tid + 256 * u;
+      snext[u] = (k > 0 && i < k - 1) ? S[(int64_t)(k - 1) * c + i] : 0.0;
+    }
+    if (tid == (k & 255)) {
+      double rk = 0.0;
+#pragma unroll
+      for (int u = 0; u < RPT; ++u)
+        if (u == (k >> 8)) rk = r[u];
+      s_m[k & 1] = rk * taus[k];
+    }
+    __syncthreads();
+    const double mk = s_m[k & 1];
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+      const int i = tid + 256 * u;
+      if (i < k) r[u] -= mk * scur[u];
+      else if (i == k) r[u] = mk;
+      scur[u] = snext[u];
+    }
+  }
+  const double sj = ((double)P[(int64_t)j * ldp + j] < 0.0) ? -1.0 : 1.0;
+#pragma unroll
+  for (int u = 0; u < RPT; ++u) {
+    const int k = tid + 256 * u;
+    if (k < c) mt[(int64_t)k * c + j] = (k <= j) ? r[u] * sj : 0.0;
+  }
+  if (tid == 0) sgn[j] = sj;
 }
 
 // Q(i, j) = [i == j] sgn_j - sum_{k <= min(i, j)} Y(i, k) M'(k, j), with
@@ -468,7 +607,6 @@ __global__ __launch_bounds__(NT) void tallqr_kernel(T* __restrict__ P, int64_t m
 // (A = M'^T, B = Y^T) so that each result row is a run of 16 consecutive
 // entries of a column of Q.  Column tiles stop at K = j0 + 64 (M' is upper
 // triangular), row tiles at K = i0 + 64 (Y is lower trapezoidal).
-constexpr int WY_T = 64, WY_K = 16, WY_LD = WY_T + 16;
 
 template <typename T>
 __global__ __launch_bounds__(256) void wy_apply_kernel(const T* __restrict__ P, int64_t mrows, int c, int64_t ldp,
@@ -536,7 +674,7 @@ void choose(int64_t mrows, int c, int num_cu, int* G, int* rb, size_t* lds) {
   int64_t r = (mrows + g - 1) / g;
   *G = (int)((mrows + r - 1) / r);
   *rb = (int)r;
-  *lds = ((size_t)(r | 1) * NB + (size_t)NB * (c + NB) + (size_t)TROWS * c + 64) * sizeof(double);
+  *lds = ((size_t)(r | 1) * NB + (size_t)NB * (c + NB) + 64) * sizeof(double);
 }
 
 template <typename T>
@@ -564,37 +702,56 @@ __global__ void scatter_rows_kernel(const T* __restrict__ Q, int64_t mrows, int6
 
 }  // namespace
 
+// Row chunks of the Gram S = Y^T Y: enough (chunk, tile pair) workgroups to
+// fill the chip twice, chunks of at least 256 rows, at most 32 partials.
+void gram_split(int64_t mrows, int64_t c, int num_cu, int* nsplit, int64_t* chunk) {
+  const int nt = (int)((c + WY_T - 1) / WY_T), npairs = nt * (nt + 1) / 2;
+  int64_t s = (2 * (int64_t)num_cu + npairs - 1) / npairs;
+  s = std::min<int64_t>(s, std::max<int64_t>(1, mrows / 256));
+  s = std::min<int64_t>(s, 32);
+  int64_t ch = (mrows + s - 1) / s;
+  ch = (ch + WY_K - 1) / WY_K * WY_K;
+  *chunk = ch;
+  *nsplit = (int)((mrows + ch - 1) / ch);
+}
+
 template <typename T>
 size_t tallqr_scratch(int64_t mrows, int64_t c, const DeviceInfo& d) {
-  int G, rb;
+  int G, rb, nsplit;
+  int64_t chunk;
   size_t lds;
   choose(mrows, (int)c, d.num_cu, &G, &rb, &lds);
+  gram_split(mrows, c, d.num_cu, &nsplit, &chunk);
   const size_t cz = (size_t)c + NB;
-  size_t b = sizeof(double) * ((size_t)2 * G * NB + 2 * NB + (size_t)G * NB * cz + (size_t)2 * NB * cz +
-                               (size_t)2 * c * c + c);
-  return b + kSyncWords * sizeof(unsigned) + 8 * 256;
+  size_t b = sizeof(double) * ((size_t)2 * G * NB + 2 * NB + (size_t)G * NB * cz + (size_t)2 * NB * cz + c +
+                               ((size_t)nsplit + 2) * c * c + c);
+  return b + kSyncWords * sizeof(unsigned) + 16 * 256;
 }
 
 template <typename T>
 hipError_t tall_qr(T* P, int64_t mrows, int64_t c, int64_t ldp, T* Qout, int64_t ldq, T* R, int64_t ldr,
                    bool transpose_r, Arena& ar, unsigned* err, const DeviceInfo& d, hipStream_t s) {
   if (c <= 0) return hipSuccess;
-  if (mrows < c) return hipErrorInvalidValue;
-  int G, rb;
+  if (mrows < c || c > 1024) return hipErrorInvalidValue;
+  int G, rb, nsplit;
+  int64_t chunk;
   size_t lds;
   choose(mrows, (int)c, d.num_cu, &G, &rb, &lds);
   if (lds > d.lds_max) return hipErrorInvalidValue;
+  gram_split(mrows, c, d.num_cu, &nsplit, &chunk);
   const size_t cz = (size_t)c + NB;
   TqSlots sl;
   sl.dots = ar.take<double>((size_t)2 * G * NB);
   sl.rowv = ar.take<double>(2 * NB);
   sl.zpart = ar.take<double>((size_t)G * NB * cz);
   sl.zred = ar.take<double>((size_t)2 * NB * cz);
-  sl.tg = ar.take<double>((size_t)c * c);
-  sl.mt = ar.take<double>((size_t)c * c);
-  sl.sgn = ar.take<double>((size_t)c);
+  sl.taus = ar.take<double>((size_t)c);
+  double* spart = ar.take<double>((size_t)nsplit * c * c);
+  double* S = ar.take<double>((size_t)c * c);
+  double* mt = ar.take<double>((size_t)c * c);
+  double* sgn = ar.take<double>((size_t)c);
   unsigned* counter = ar.take<unsigned>(kSyncWords);
-  if (!sl.dots || !sl.rowv || !sl.zpart || !sl.zred || !sl.tg || !sl.mt || !sl.sgn || !counter)
+  if (!sl.dots || !sl.rowv || !sl.zpart || !sl.zred || !sl.taus || !spart || !S || !mt || !sgn || !counter)
     return hipErrorOutOfMemory;
   hipError_t e = zero_words(counter, kSyncWords, s);
   if (e != hipSuccess) return e;
@@ -602,15 +759,24 @@ hipError_t tall_qr(T* P, int64_t mrows, int64_t c, int64_t ldp, T* Qout, int64_t
   int ci = (int)c, tr = transpose_r ? 1 : 0;
   void* args[] = {(void*)&P, (void*)&mrows, (void*)&ci, (void*)&ldp, (void*)&rb, (void*)&Qout, (void*)&ldq,
                   (void*)&R, (void*)&ldr, (void*)&tr, (void*)&sl, (void*)&gs};
-  const void* fn = (const void*)tallqr_kernel<T>;
+  const int rpt = (rb + NT - 1) / NT;  // rows per thread in the column steps
+  const void* fn = rpt <= 1 ? (const void*)tallqr_kernel<T, 1>
+                   : rpt <= 2 ? (const void*)tallqr_kernel<T, 2>
+                   : rpt <= 4 ? (const void*)tallqr_kernel<T, 4> : nullptr;
+  if (!fn) return hipErrorInvalidValue;
   if (lds > 65536) {
     e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
   e = hipLaunchCooperativeKernel(fn, dim3(G), dim3(NT), args, (unsigned)lds, s);
   if (e != hipSuccess) return e;
-  dim3 grid((unsigned)((mrows + WY_T - 1) / WY_T), (unsigned)((c + WY_T - 1) / WY_T));
-  wy_apply_kernel<T><<<grid, 256, 0, s>>>(P, mrows, ci, ldp, sl.mt, sl.sgn, Qout, ldq);
+  const int nt = (ci + WY_T - 1) / WY_T;
+  gram_y_kernel<T><<<dim3((unsigned)(nt * (nt + 1) / 2), (unsigned)nsplit), 256, 0, s>>>(P, mrows, ci, ldp, chunk,
+                                                                                        spart);
+  gram_sum_kernel<<<(unsigned)((c * c + 255) / 256), 256, 0, s>>>(spart, nsplit, ci, S);
+  wy_m_kernel<T><<<(unsigned)c, 256, 0, s>>>(P, ci, ldp, S, sl.taus, mt, sgn);
+  dim3 grid((unsigned)((mrows + WY_T - 1) / WY_T), (unsigned)nt);
+  wy_apply_kernel<T><<<grid, 256, 0, s>>>(P, mrows, ci, ldp, mt, sgn, Qout, ldq);
   return hipGetLastError();
 }
 
