@@ -18,6 +18,8 @@
 //      downdating drift to guard against).
 // Candidate slots are double-buffered by step parity, so one barrier per
 // step suffices.
+#include <algorithm>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -206,6 +208,176 @@ __global__ __launch_bounds__(NT) void qrcp_kernel(const T* __restrict__ B, int64
   }
 }
 
+// Register-resident variant for l <= 16 NR: sixteen threads per column, each
+// holding rows q, q + 16, ... of its column (and of CB columns in all) in
+// registers, so that the update and the norm recomputation of a step touch
+// no LDS except the broadcast reflector.  Per step:
+//   1. every wave merges the top-2 of its four column groups and posts it to
+//      LDS; after one workgroup barrier every wave merges the sixteen posts,
+//      so the owner of the local winner writes its column to the slot without
+//      a further barrier, and wave 0 posts the candidate;
+//   2. one grid barrier;
+//   3. wave 0 merges the candidates (fixed order), reads the winner's rows
+//      j..l-1, builds the reflector (LAPACK xLARFG convention) and
+//      broadcasts it through LDS (one workgroup barrier);
+//   4. every active column is updated and its residual norm over rows
+//      j+1..l-1 recomputed from scratch (sums over the 16 lanes of its group).
+template <typename T, int NR, int CB>
+__global__ __launch_bounds__(NT) void qrcp_reg_kernel(const T* __restrict__ B, int64_t ldb, int l, int64_t n,
+                                                      QrcpSlots sl, int64_t* __restrict__ piv,
+                                                      double* __restrict__ margins, GridSync gs) {
+  constexpr int TPC = 16, CPB = NT / TPC;  // threads per column, columns per batch
+  __shared__ double v[TPC * NR];
+  __shared__ double s_tv1[NT / 64], s_tv2[NT / 64];
+  __shared__ int64_t s_ti1[NT / 64];
+  __shared__ double s_tau;
+  __shared__ int64_t s_win;
+  const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6, q = tid & (TPC - 1), cl = tid / TPC;
+  const int64_t c0 = (int64_t)g * CPB * CB;
+  double x[CB][NR], rn[CB];
+  int64_t col[CB];
+  bool act[CB];
+#pragma unroll
+  for (int b = 0; b < CB; ++b) {
+    col[b] = c0 + (int64_t)b * CPB + cl;
+    act[b] = col[b] < n;
+    double s2 = 0.0;
+#pragma unroll
+    for (int s = 0; s < NR; ++s) {
+      const int i = q + TPC * s;
+      x[b][s] = (act[b] && i < l) ? (double)B[col[b] * ldb + i] : 0.0;
+      s2 += x[b][s] * x[b][s];
+    }
+    rn[b] = group_sum(s2, TPC);
+  }
+  unsigned epoch = 0;
+  for (int j = 0; j < l; ++j) {
+    const int par = j & 1;
+    // ---- 1. local best and runner-up
+    Top2 t{0.0, -1, -1.0};
+#pragma unroll
+    for (int b = 0; b < CB; ++b)
+      if (act[b]) t = top2_merge(t, Top2{rn[b], col[b], -1.0});
+#pragma unroll
+    for (int o = 16; o < 64; o <<= 1) {
+      const Top2 y{__shfl_xor(t.v1, o, kWave), __shfl_xor(t.i1, o, kWave), __shfl_xor(t.v2, o, kWave)};
+      t = top2_merge(t, y);
+    }
+    if (lane == 0) {
+      s_tv1[wave] = t.v1;
+      s_ti1[wave] = t.i1;
+      s_tv2[wave] = t.v2;
+    }
+    __syncthreads();
+    {
+      Top2 u{0.0, -1, -1.0};
+      if (lane < NT / 64) u = Top2{s_tv1[lane], s_ti1[lane], s_tv2[lane]};
+#pragma unroll
+      for (int o = 1; o < NT / 64; o <<= 1) {
+        const Top2 y{__shfl_xor(u.v1, o, kWave), __shfl_xor(u.i1, o, kWave), __shfl_xor(u.v2, o, kWave)};
+        u = top2_merge(u, y);
+      }
+      const int64_t bi = __shfl(u.i1, 0, kWave);
+      if (wave == 0 && lane == 0) {
+        sl.r[par * G + g] = u.v1;
+        sl.idx[par * G + g] = u.i1;
+        sl.r2[par * G + g] = u.v2;
+      }
+      // the owner group of the local winner posts rows j..l-1 of its column
+      double* dst = sl.col + ((int64_t)par * G + g) * l;
+#pragma unroll
+      for (int b = 0; b < CB; ++b)
+        if (bi >= 0 && col[b] == bi)
+#pragma unroll
+          for (int s = 0; s < NR; ++s) {
+            const int i = q + TPC * s;
+            if (i >= j && i < l) dst[i] = x[b][s];
+          }
+    }
+    // ---- 2. exchange
+    if (!grid_barrier(gs, epoch)) return;
+    // ---- 3. global winner, its reflector (wave 0)
+    if (wave == 0) {
+      Top2 u{0.0, -1, -1.0};
+      for (int qq = lane; qq < G; qq += kWave)
+        u = top2_merge(u, Top2{sl.r[par * G + qq], sl.idx[par * G + qq], sl.r2[par * G + qq]});
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const Top2 y{__shfl_xor(u.v1, o, kWave), __shfl_xor(u.i1, o, kWave), __shfl_xor(u.v2, o, kWave)};
+        u = top2_merge(u, y);
+      }
+      const int64_t wi = __shfl(u.i1, 0, kWave);
+      if (lane == 0 && g == 0) {
+        piv[j] = wi;
+        double mg;
+        if (n - j <= 1) mg = 1.0;
+        else if (u.v1 > 0.0) mg = (u.v1 - (u.v2 > 0.0 ? u.v2 : 0.0)) / u.v1;
+        else mg = 0.0;
+        margins[j] = mg;
+      }
+      // the winner's rows j..l-1 (sent by the workgroup that owns it)
+      const int wg = (int)(wi / (CPB * CB));
+      const double* src = sl.col + ((int64_t)par * G + wg) * l;
+      double w[(TPC * NR + 63) / 64];
+      double xs = 0.0;
+#pragma unroll
+      for (int s = 0; s < (TPC * NR + 63) / 64; ++s) {
+        const int i = lane + 64 * s;
+        w[s] = (i >= j && i < l) ? src[i] : 0.0;
+        if (i > j) xs += w[s] * w[s];
+      }
+      const double xnorm2 = wave_sum(xs);
+      const double x0 = __shfl(w[0], j & 63, kWave);  // row j is in register j / 64 of lane j % 64
+      double x0v = x0;
+#pragma unroll
+      for (int s = 1; s < (TPC * NR + 63) / 64; ++s) {
+        const double y = __shfl(w[s], j & 63, kWave);
+        if ((j >> 6) == s) x0v = y;
+      }
+      double tau = 0.0, scale = 0.0;
+      if (xnorm2 > 0.0) {
+        const double beta = -copysign(sqrt(x0v * x0v + xnorm2), x0v);
+        tau = (beta - x0v) / beta;
+        scale = 1.0 / (x0v - beta);
+      }
+#pragma unroll
+      for (int s = 0; s < (TPC * NR + 63) / 64; ++s) {
+        const int i = lane + 64 * s;
+        if (i < TPC * NR) v[i] = (i < j || i >= l) ? 0.0 : (i == j ? 1.0 : (tau != 0.0 ? w[s] * scale : w[s]));
+      }
+      if (lane == 0) {
+        s_tau = tau;
+        s_win = wi;
+      }
+    }
+    __syncthreads();
+    // ---- 4. update the active columns, recompute their residual norms
+    const double tau = s_tau;
+    const int64_t wi = s_win;
+#pragma unroll
+    for (int b = 0; b < CB; ++b) {
+      if (col[b] == wi) act[b] = false;
+      if (!act[b]) continue;
+      if (tau != 0.0) {
+        double dt = 0.0;
+#pragma unroll
+        for (int s = 0; s < NR; ++s) dt += v[q + TPC * s] * x[b][s];
+        const double f = group_sum(dt, TPC) * tau;
+#pragma unroll
+        for (int s = 0; s < NR; ++s) x[b][s] -= f * v[q + TPC * s];
+      }
+      double r = 0.0;
+#pragma unroll
+      for (int s = 0; s < NR; ++s) {
+        const int i = q + TPC * s;
+        if (i > j) r += x[b][s] * x[b][s];
+      }
+      rn[b] = group_sum(r, TPC);
+    }
+  }
+}
+
 // Fewest workgroups whose column slices of B still fit in LDS: the per-step
 // grid barrier costs more with more workgroups, while the work per step is
 // small.  When B does not fit in the LDS of the whole chip, the slices live
@@ -229,16 +401,48 @@ void choose(int64_t l, int64_t n, int num_cu, size_t lds_max, size_t tsize, int*
   *lds = *in_lds ? base + (size_t)c * ldbl_for(l, tsize) * tsize : base;
 }
 
+
+// Register variant: rows per thread NR (l <= 16 NR) and columns per thread
+// CB, fewest workgroups first (cheaper grid barriers); G <= num_cu.
+bool reg_choice(int64_t l, int64_t n, int num_cu, int* NR, int* CB, int* G) {
+  static const int nrs[] = {2, 4, 8, 18};
+  static const int cbs[] = {4, 4, 2, 1};
+  for (int k = 0; k < 4; ++k) {
+    if (l > 16 * nrs[k]) continue;
+    const int64_t per = (int64_t)(NT / 16) * cbs[k];
+    const int64_t g = (n + per - 1) / per;
+    if (g > num_cu) return false;
+    *NR = nrs[k];
+    *CB = cbs[k];
+    *G = (int)g;
+    return true;
+  }
+  return false;
+}
+
+template <typename T>
+const void* reg_kernel(int NR) {
+  switch (NR) {
+    case 2: return (const void*)qrcp_reg_kernel<T, 2, 4>;
+    case 4: return (const void*)qrcp_reg_kernel<T, 4, 4>;
+    case 8: return (const void*)qrcp_reg_kernel<T, 8, 2>;
+    case 18: return (const void*)qrcp_reg_kernel<T, 18, 1>;
+  }
+  return nullptr;
+}
+
 }  // namespace
 
 template <typename T>
 size_t qrcp_scratch(int64_t l, int64_t n, const DeviceInfo& d) {
-  int nc, G;
+  int nc, G, NR, CB, Gr;
   bool in_lds;
   size_t lds;
   choose(l, n, d.num_cu, d.lds_max, sizeof(T), &nc, &G, &in_lds, &lds);
   size_t b = (size_t)2 * G * (3 * sizeof(double) + l * sizeof(double)) + 4 * 256;
   if (!in_lds) b += (size_t)G * nc * ldbl_for(l, sizeof(T)) * sizeof(T) + 256;
+  if (reg_choice(l, n, d.num_cu, &NR, &CB, &Gr))
+    b = std::max(b, (size_t)2 * Gr * (3 * sizeof(double) + l * sizeof(double)) + 4 * 256);
   return b + kSyncWords * sizeof(unsigned) + 1024;
 }
 
@@ -246,6 +450,24 @@ template <typename T>
 hipError_t qrcp(const T* B, int64_t l, int64_t n, int64_t ldb, int64_t* piv, double* margins, Arena& ar,
                 unsigned* err, const DeviceInfo& d, hipStream_t s) {
   if (l <= 0) return hipSuccess;
+  int NR, CB, Gr;
+  if (reg_choice(l, n, d.num_cu, &NR, &CB, &Gr)) {
+    QrcpSlots sl;
+    sl.r = ar.take<double>(2 * Gr);
+    sl.r2 = ar.take<double>(2 * Gr);
+    sl.idx = ar.take<int64_t>(2 * Gr);
+    sl.col = ar.take<double>((size_t)2 * Gr * l);
+    unsigned* counter = ar.take<unsigned>(kSyncWords);
+    if (!sl.r || !sl.r2 || !sl.idx || !sl.col || !counter) return hipErrorOutOfMemory;
+    hipError_t e = zero_words(counter, kSyncWords, s);
+    if (e != hipSuccess) return e;
+    GridSync gs{counter, err, (unsigned)Gr};
+    int li = (int)l;
+    int64_t ln = n, lldb = ldb;
+    void* args[] = {(void*)&B, (void*)&lldb, (void*)&li, (void*)&ln, (void*)&sl, (void*)&piv, (void*)&margins,
+                    (void*)&gs};
+    return hipLaunchCooperativeKernel(reg_kernel<T>(NR), dim3(Gr), dim3(NT), args, 0, s);
+  }
   int nc, G;
   bool in_lds;
   size_t lds;

@@ -546,58 +546,92 @@ __global__ void gram_sum_kernel(const double* __restrict__ spart, int nsplit, in
   S[e] = t;
 }
 
+// Broadcast of lane l's value to the whole wave (l wave-uniform).
+__device__ inline double readlane_d(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 // Column j of M' = (T Y(0:c, :)^T) diag(sgn), row-major in mt, by back
 // substitution with U = T^-1 = striu(S) + diag(1/tau): U m = y_j with
 // y_j(k) = Y(j, k) (zero for k > j).  m_k = r_k tau_k, so tau_k = 0 gives
-// m_k = 0 (the reflector is the identity).  One workgroup per column; the
-// thread of row k holds r_k; each step broadcasts m_k through LDS, and the
-// next column of S is loaded while the current one is applied.
-template <typename T>
-__global__ __launch_bounds__(256) void wy_m_kernel(const T* __restrict__ P, int c, int64_t ldp,
+// m_k = 0 (the reflector is the identity).  One wave per column, lane l
+// holding r_i for the rows i = l + 64 u; m_k is broadcast by a lane read,
+// so the steps need no workgroup barrier.  The columns k of striu(S) come
+// through LDS in blocks of sb, the next block loaded while the current one
+// is used; the four waves of a workgroup (four columns) share the blocks.
+template <typename T, int RPL>
+__global__ __launch_bounds__(256) void wy_m_kernel(const T* __restrict__ P, int c, int64_t ldp, int sb,
                                                    const double* __restrict__ S, const double* __restrict__ taus,
                                                    double* __restrict__ mt, double* __restrict__ sgn) {
-  constexpr int RPT = 4;  // rows per thread: c <= 1024
-  __shared__ double s_m[2];
-  const int j = blockIdx.x, tid = threadIdx.x;
-  double r[RPT], scur[RPT];
+  extern __shared__ double Sb[];  // [2][sb][c]: Sb[buf][kk][i] = S(i, k0 + kk), i < k0 + kk
+  constexpr int PF = 16;          // prefetch registers per thread (sb c <= 256 PF)
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int j = blockIdx.x * 4 + wave;
+  const bool live = j < c;
+  const int jmax = min(c - 1, blockIdx.x * 4 + 3);
+  double r[RPL], tr[RPL];
 #pragma unroll
-  for (int u = 0; u < RPT; ++u) {
-    const int k = tid + 256 * u;
-    r[u] = (k <= j) ? yload(P, ldp, j, k) : 0.0;
-    scur[u] = (k < j) ? S[(int64_t)j * c + k] : 0.0;  // column j of striu(S)
+  for (int u = 0; u < RPL; ++u) {
+    const int i = lane + 64 * u;
+    r[u] = (live && i <= j) ? yload(P, ldp, j, i) : 0.0;
+    tr[u] = i < c ? taus[i] : 0.0;
   }
-  for (int k = j; k >= 0; --k) {
-    // prefetch column k - 1 of striu(S)
-    double snext[RPT];
+  const int nblk = jmax / sb + 1;
+  auto fetch = [&](int K, double* pf) {
 #pragma unroll
-    for (int u = 0; u < RPT; ++u) {
-      const int i = tid + 256 * u;
-      snext[u] = (k > 0 && i < k - 1) ? S[(int64_t)(k - 1) * c + i] : 0.0;
+    for (int x = 0; x < PF; ++x) {
+      const int e = tid + 256 * x, kk = e / c, i = e % c, k = K * sb + kk;
+      pf[x] = (kk < sb && k <= jmax && i < k) ? S[(int64_t)k * c + i] : 0.0;
     }
-    if (tid == (k & 255)) {
-      double rk = 0.0;
+  };
+  auto store = [&](int buf, const double* pf) {
 #pragma unroll
-      for (int u = 0; u < RPT; ++u)
-        if (u == (k >> 8)) rk = r[u];
-      s_m[k & 1] = rk * taus[k];
+    for (int x = 0; x < PF; ++x) {
+      const int e = tid + 256 * x;
+      if (e < sb * c) Sb[(int64_t)buf * sb * c + e] = pf[x];
     }
+  };
+  double pf[PF];
+  fetch(nblk - 1, pf);
+  store((nblk - 1) & 1, pf);
+  __syncthreads();
+  for (int K = nblk - 1; K >= 0; --K) {
+    if (K > 0) fetch(K - 1, pf);
+    const double* sbk = Sb + (int64_t)(K & 1) * sb * c;
+    for (int kk = sb - 1; kk >= 0; --kk) {
+      const int k = K * sb + kk;
+      if (!live || k > j) continue;
+      const int ku = k >> 6, kl = k & 63;
+      double rk = 0.0, tk = 0.0;
+#pragma unroll
+      for (int u = 0; u < RPL; ++u)
+        if (u == ku) {
+          rk = r[u];
+          tk = tr[u];
+        }
+      const double mk = readlane_d(rk, kl) * readlane_d(tk, kl);
+#pragma unroll
+      for (int u = 0; u < RPL; ++u) {
+        if (64 * u > k) break;
+        const int i = lane + 64 * u;
+        if (i < k) r[u] -= mk * sbk[kk * c + i];
+        else if (i == k) r[u] = mk;
+      }
+    }
+    if (K > 0) store((K - 1) & 1, pf);
     __syncthreads();
-    const double mk = s_m[k & 1];
-#pragma unroll
-    for (int u = 0; u < RPT; ++u) {
-      const int i = tid + 256 * u;
-      if (i < k) r[u] -= mk * scur[u];
-      else if (i == k) r[u] = mk;
-      scur[u] = snext[u];
-    }
   }
+  if (!live) return;
   const double sj = ((double)P[(int64_t)j * ldp + j] < 0.0) ? -1.0 : 1.0;
 #pragma unroll
-  for (int u = 0; u < RPT; ++u) {
-    const int k = tid + 256 * u;
+  for (int u = 0; u < RPL; ++u) {
+    const int k = lane + 64 * u;
     if (k < c) mt[(int64_t)k * c + j] = (k <= j) ? r[u] * sj : 0.0;
   }
-  if (tid == 0) sgn[j] = sj;
+  if (lane == 0) sgn[j] = sj;
 }
 
 // Q(i, j) = [i == j] sgn_j - sum_{k <= min(i, j)} Y(i, k) M'(k, j), with
@@ -774,7 +808,15 @@ hipError_t tall_qr(T* P, int64_t mrows, int64_t c, int64_t ldp, T* Qout, int64_t
   gram_y_kernel<T><<<dim3((unsigned)(nt * (nt + 1) / 2), (unsigned)nsplit), 256, 0, s>>>(P, mrows, ci, ldp, chunk,
                                                                                         spart);
   gram_sum_kernel<<<(unsigned)((c * c + 255) / 256), 256, 0, s>>>(spart, nsplit, ci, S);
-  wy_m_kernel<T><<<(unsigned)c, 256, 0, s>>>(P, ci, ldp, S, sl.taus, mt, sgn);
+  int sb = 16;
+  while (sb > 1 && sb * ci > 256 * 16) sb >>= 1;
+  const size_t mlds = (size_t)2 * sb * ci * sizeof(double);
+  const unsigned mgrid = (unsigned)((c + 3) / 4);
+  if (ci <= 64) wy_m_kernel<T, 1><<<mgrid, 256, mlds, s>>>(P, ci, ldp, sb, S, sl.taus, mt, sgn);
+  else if (ci <= 128) wy_m_kernel<T, 2><<<mgrid, 256, mlds, s>>>(P, ci, ldp, sb, S, sl.taus, mt, sgn);
+  else if (ci <= 256) wy_m_kernel<T, 4><<<mgrid, 256, mlds, s>>>(P, ci, ldp, sb, S, sl.taus, mt, sgn);
+  else if (ci <= 512) wy_m_kernel<T, 8><<<mgrid, 256, mlds, s>>>(P, ci, ldp, sb, S, sl.taus, mt, sgn);
+  else wy_m_kernel<T, 16><<<mgrid, 256, mlds, s>>>(P, ci, ldp, sb, S, sl.taus, mt, sgn);
   dim3 grid((unsigned)((mrows + WY_T - 1) / WY_T), (unsigned)nt);
   wy_apply_kernel<T><<<grid, 256, 0, s>>>(P, mrows, ci, ldp, mt, sgn, Qout, ldq);
   return hipGetLastError();

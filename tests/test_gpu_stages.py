@@ -68,8 +68,10 @@ def test_sketch_fp32(ff):
 
 
 # ------------------------------------------------------------------- QRCP
+# register-resident kernel (l <= 288 and few enough columns) and the LDS /
+# global-memory kernel (larger l or n) are both covered
 @pytest.mark.parametrize("l,n,seed", [(30, 800, 1), (30, 1001, 2), (64, 5000, 3), (100, 60000, 4), (8, 8, 5),
-                                      (1, 50, 6)])
+                                      (1, 50, 6), (200, 4000, 7), (272, 8192, 8), (300, 2000, 9)])
 def test_qrcp_pivots_fp64(ff, l, n, seed):
     announce(f"qrcp fp64 l={l} n={n} seed={seed}")
     B = synth.random_matrix(l, n, seed=seed)
