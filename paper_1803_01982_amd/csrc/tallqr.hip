@@ -557,21 +557,23 @@ __device__ inline double readlane_d(double v, int l) {
 // Column j of M' = (T Y(0:c, :)^T) diag(sgn), row-major in mt, by back
 // substitution with U = T^-1 = striu(S) + diag(1/tau): U m = y_j with
 // y_j(k) = Y(j, k) (zero for k > j).  m_k = r_k tau_k, so tau_k = 0 gives
-// m_k = 0 (the reflector is the identity).  One wave per column, lane l
-// holding r_i for the rows i = l + 64 u; m_k is broadcast by a lane read,
-// so the steps need no workgroup barrier.  The columns k of striu(S) come
-// through LDS in blocks of sb, the next block loaded while the current one
-// is used; the four waves of a workgroup (four columns) share the blocks.
+// m_k = 0 (the reflector is the identity).  One wave per column (four per
+// workgroup, one per SIMD), lane l holding r_i for the rows i = l + 64 u;
+// m_k is broadcast by a lane read, so the steps need no workgroup barrier.
+// The columns k of striu(S) come through LDS in blocks of WM_SB, loaded by
+// the whole workgroup with all loads in flight together.
+constexpr int WM_NT = 256, WM_SB = 16;
+
 template <typename T, int RPL>
-__global__ __launch_bounds__(256) void wy_m_kernel(const T* __restrict__ P, int c, int64_t ldp, int sb,
-                                                   const double* __restrict__ S, const double* __restrict__ taus,
-                                                   double* __restrict__ mt, double* __restrict__ sgn) {
-  extern __shared__ double Sb[];  // [2][sb][c]: Sb[buf][kk][i] = S(i, k0 + kk), i < k0 + kk
-  constexpr int PF = 16;          // prefetch registers per thread (sb c <= 256 PF)
+__global__ __launch_bounds__(WM_NT) void wy_m_kernel(const T* __restrict__ P, int c, int64_t ldp,
+                                                     const double* __restrict__ S, const double* __restrict__ taus,
+                                                     double* __restrict__ mt, double* __restrict__ sgn) {
+  extern __shared__ double Sb[];  // [WM_SB][c]: Sb[kk][i] = S(i, K WM_SB + kk), i < K WM_SB + kk
+  constexpr int NWV = WM_NT / 64, FB = 16;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int j = blockIdx.x * 4 + wave;
+  const int j = blockIdx.x * NWV + wave;
   const bool live = j < c;
-  const int jmax = min(c - 1, blockIdx.x * 4 + 3);
+  const int jmax = min(c - 1, blockIdx.x * NWV + NWV - 1);
   double r[RPL], tr[RPL];
 #pragma unroll
   for (int u = 0; u < RPL; ++u) {
@@ -579,31 +581,27 @@ __global__ __launch_bounds__(256) void wy_m_kernel(const T* __restrict__ P, int 
     r[u] = (live && i <= j) ? yload(P, ldp, j, i) : 0.0;
     tr[u] = i < c ? taus[i] : 0.0;
   }
-  const int nblk = jmax / sb + 1;
-  auto fetch = [&](int K, double* pf) {
-#pragma unroll
-    for (int x = 0; x < PF; ++x) {
-      const int e = tid + 256 * x, kk = e / c, i = e % c, k = K * sb + kk;
-      pf[x] = (kk < sb && k <= jmax && i < k) ? S[(int64_t)k * c + i] : 0.0;
-    }
-  };
-  auto store = [&](int buf, const double* pf) {
-#pragma unroll
-    for (int x = 0; x < PF; ++x) {
-      const int e = tid + 256 * x;
-      if (e < sb * c) Sb[(int64_t)buf * sb * c + e] = pf[x];
-    }
-  };
-  double pf[PF];
-  fetch(nblk - 1, pf);
-  store((nblk - 1) & 1, pf);
-  __syncthreads();
+  const int nblk = jmax / WM_SB + 1, ne = WM_SB * c;
   for (int K = nblk - 1; K >= 0; --K) {
-    if (K > 0) fetch(K - 1, pf);
-    const double* sbk = Sb + (int64_t)(K & 1) * sb * c;
-    for (int kk = sb - 1; kk >= 0; --kk) {
-      const int k = K * sb + kk;
-      if (!live || k > j) continue;
+    __syncthreads();  // the previous block is no longer read
+    for (int e0 = 0; e0 < ne; e0 += WM_NT * FB) {
+      double pf[FB];
+#pragma unroll
+      for (int x = 0; x < FB; ++x) {
+        const int e = e0 + tid + WM_NT * x, kk = e / c, i = e - kk * c, k = K * WM_SB + kk;
+        pf[x] = (e < ne && k <= jmax && i < k) ? S[(int64_t)k * c + i] : 0.0;
+      }
+#pragma unroll
+      for (int x = 0; x < FB; ++x) {
+        const int e = e0 + tid + WM_NT * x;
+        if (e < ne) Sb[e] = pf[x];
+      }
+    }
+    __syncthreads();
+    if (!live) continue;
+    for (int kk = WM_SB - 1; kk >= 0; --kk) {
+      const int k = K * WM_SB + kk;
+      if (k > j) continue;
       const int ku = k >> 6, kl = k & 63;
       double rk = 0.0, tk = 0.0;
 #pragma unroll
@@ -613,16 +611,16 @@ __global__ __launch_bounds__(256) void wy_m_kernel(const T* __restrict__ P, int 
           tk = tr[u];
         }
       const double mk = readlane_d(rk, kl) * readlane_d(tk, kl);
+      double sv[RPL];
+#pragma unroll
+      for (int u = 0; u < RPL; ++u) sv[u] = (64 * u <= k) ? Sb[kk * c + min(lane + 64 * u, c - 1)] : 0.0;
 #pragma unroll
       for (int u = 0; u < RPL; ++u) {
-        if (64 * u > k) break;
         const int i = lane + 64 * u;
-        if (i < k) r[u] -= mk * sbk[kk * c + i];
-        else if (i == k) r[u] = mk;
+        const double upd = fma(-mk, sv[u], r[u]);
+        r[u] = i < k ? upd : (i == k ? mk : r[u]);
       }
     }
-    if (K > 0) store((K - 1) & 1, pf);
-    __syncthreads();
   }
   if (!live) return;
   const double sj = ((double)P[(int64_t)j * ldp + j] < 0.0) ? -1.0 : 1.0;
@@ -808,15 +806,22 @@ hipError_t tall_qr(T* P, int64_t mrows, int64_t c, int64_t ldp, T* Qout, int64_t
   gram_y_kernel<T><<<dim3((unsigned)(nt * (nt + 1) / 2), (unsigned)nsplit), 256, 0, s>>>(P, mrows, ci, ldp, chunk,
                                                                                         spart);
   gram_sum_kernel<<<(unsigned)((c * c + 255) / 256), 256, 0, s>>>(spart, nsplit, ci, S);
-  int sb = 16;
-  while (sb > 1 && sb * ci > 256 * 16) sb >>= 1;
-  const size_t mlds = (size_t)2 * sb * ci * sizeof(double);
-  const unsigned mgrid = (unsigned)((c + 3) / 4);
-  if (ci <= 64) wy_m_kernel<T, 1><<<mgrid, 256, mlds, s>>>(P, ci, ldp, sb, S, sl.taus, mt, sgn);
-  else if (ci <= 128) wy_m_kernel<T, 2><<<mgrid, 256, mlds, s>>>(P, ci, ldp, sb, S, sl.taus, mt, sgn);
-  else if (ci <= 256) wy_m_kernel<T, 4><<<mgrid, 256, mlds, s>>>(P, ci, ldp, sb, S, sl.taus, mt, sgn);
-  else if (ci <= 512) wy_m_kernel<T, 8><<<mgrid, 256, mlds, s>>>(P, ci, ldp, sb, S, sl.taus, mt, sgn);
-  else wy_m_kernel<T, 16><<<mgrid, 256, mlds, s>>>(P, ci, ldp, sb, S, sl.taus, mt, sgn);
+  const size_t mlds = (size_t)WM_SB * ci * sizeof(double);
+  const unsigned mgrid = (unsigned)((c + WM_NT / 64 - 1) / (WM_NT / 64));
+  const void* mfn = ci <= 64    ? (const void*)wy_m_kernel<T, 1>
+                    : ci <= 128 ? (const void*)wy_m_kernel<T, 2>
+                    : ci <= 256 ? (const void*)wy_m_kernel<T, 4>
+                    : ci <= 512 ? (const void*)wy_m_kernel<T, 8>
+                                : (const void*)wy_m_kernel<T, 16>;
+  if (mlds > 65536) {
+    e = hipFuncSetAttribute(mfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)mlds);
+    if (e != hipSuccess) return e;
+  }
+  const double* taus_c = sl.taus;
+  const double* S_c = S;
+  void* margs[] = {(void*)&P, (void*)&ci, (void*)&ldp, (void*)&S_c, (void*)&taus_c, (void*)&mt, (void*)&sgn};
+  e = hipLaunchKernel(mfn, dim3(mgrid), dim3(WM_NT), margs, mlds, s);
+  if (e != hipSuccess) return e;
   dim3 grid((unsigned)((mrows + WY_T - 1) / WY_T), (unsigned)nt);
   wy_apply_kernel<T><<<grid, 256, 0, s>>>(P, mrows, ci, ldp, mt, sgn, Qout, ldq);
   return hipGetLastError();
