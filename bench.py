@@ -50,7 +50,9 @@ def timed_solves(ff, torch, A, w, steps, warmup):
 
 def gemm_roofline(prof, w, prec):
     # the sketch (B = Omega A) and the projection (W = Q1^T A) are launches of
-    # the same MFMA GEMM kernel; each performs 2 l m n flops
+    # the same MFMA GEMM (for l <= 288 the tall-tile kernel, K split over two
+    # halves plus the fixed-order sum of the halves, both inside the timed
+    # interval); each performs 2 l m n flops
     ms = prof["sketch"][0] + prof["project"][0]
     n_launch = prof["sketch"][1] + prof["project"][1]
     if n_launch == 0:
@@ -60,7 +62,8 @@ def gemm_roofline(prof, w, prec):
     achieved = flop / avg_s / 1e12
     return {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK[prec], "unit": "TFLOP/s",
             "frac": round(achieved / PEAK[prec], 4), "traffic": None,
-            "kernel": f"gemm_tn_kernel<{'double' if prec == 'fp64' else 'float'}>",
+            "kernel": (f"gemm_tall_kernel<{'double' if prec == 'fp64' else 'float'}, {(w.l + 15) // 16}> + splitk_reduce"
+                       if w.l <= 288 else f"gemm_tn_kernel<{'double' if prec == 'fp64' else 'float'}>"),
             "flop_per_launch": flop, "avg_launch_ms": round(avg_s * 1e3, 4), "launches": n_launch}
 
 

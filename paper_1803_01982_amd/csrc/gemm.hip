@@ -109,6 +109,109 @@ __global__ __launch_bounds__(NT) void gemm_tn_kernel(
   if (do_norm && tid < BN && n0 + tid < N) colnorm[(int64_t)blockIdx.z * nstride + n0 + tid] = nrm;
 }
 
+// Tall-tile variant for M <= 16 MT (the sketch and projection have M = l
+// rows, a few hundred): one workgroup covers all M rows and 64 columns, so
+// no row tile is partly empty and X is streamed once per column block.
+// Four waves, wave w owning columns 16 w .. 16 w + 15 of the block and all
+// MT row tiles (MT accumulators); K step 16, double-buffered LDS with a
+// register prefetch of the next step.
+constexpr int TBN = 64, TPAD = 2;
+
+template <typename T, int MT>
+__global__ __launch_bounds__(NT) void gemm_tall_kernel(
+    int64_t M, int64_t N, int64_t K, int64_t kchunk, const T* __restrict__ X, int64_t ldx,
+    const T* __restrict__ Y, int64_t ldy, T* __restrict__ C, int64_t ldc, int64_t cstride,
+    double* __restrict__ colnorm, int64_t nstride) {
+  constexpr int TBM = 16 * MT;
+  constexpr int XL = (TBM * BK + NT - 1) / NT;  // X elements loaded per thread per K step
+  constexpr int YL = TBN * BK / NT;             // Y elements per thread (4)
+  __shared__ T Xs[2][BK][TBM + TPAD];
+  __shared__ T Ys[2][BK][TBN + TPAD];
+  using MF = Mfma<T>;
+  typename MF::acc4 acc[MT];
+#pragma unroll
+  for (int t = 0; t < MT; ++t) acc[t] = typename MF::acc4{0, 0, 0, 0};
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t n0 = (int64_t)blockIdx.x * TBN;
+  const int64_t kb = (int64_t)blockIdx.z * kchunk;
+  const int64_t ke = (kb + kchunk < K) ? kb + kchunk : K;
+  const bool do_norm = colnorm != nullptr;
+
+  // loader: element e = tid + NT q of a tile is (row e / BK, k e % BK), so
+  // sixteen consecutive threads read one 16-element run along K
+  T xr[XL], yr[YL];
+  auto load = [&](int64_t k0) {
+#pragma unroll
+    for (int q = 0; q < XL; ++q) {
+      const int e = tid + NT * q, row = e / BK;
+      const int64_t k = k0 + (e % BK);
+      xr[q] = (row < TBM && row < M && k < ke) ? X[(int64_t)row * ldx + k] : T(0);
+    }
+#pragma unroll
+    for (int q = 0; q < YL; ++q) {
+      const int e = tid + NT * q, col = e / BK;
+      const int64_t k = k0 + (e % BK), nn = n0 + col;
+      yr[q] = (nn < N && k < ke) ? Y[nn * ldy + k] : T(0);
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < XL; ++q) {
+      const int e = tid + NT * q, row = e / BK;
+      if (row < TBM) Xs[buf][e % BK][row] = xr[q];
+    }
+#pragma unroll
+    for (int q = 0; q < YL; ++q) {
+      const int e = tid + NT * q;
+      Ys[buf][e % BK][e / BK] = yr[q];
+    }
+  };
+
+  double nrm = 0.0;
+  int cur = 0;
+  if (kb < ke) {
+    load(kb);
+    store(0);
+  }
+  __syncthreads();
+  for (int64_t k0 = kb; k0 < ke; k0 += BK) {
+    const bool more = k0 + BK < ke;
+    if (more) load(k0 + BK);
+#pragma unroll
+    for (int k4 = 0; k4 < BK / 4; ++k4) {
+      const int kr = k4 * 4 + (lane >> 4);
+      const T b = Ys[cur][kr][wave * 16 + (lane & 15)];
+      T a[MT];
+#pragma unroll
+      for (int t = 0; t < MT; ++t) a[t] = Xs[cur][kr][t * 16 + (lane & 15)];
+#pragma unroll
+      for (int t = 0; t < MT; ++t) acc[t] = MF::fma(a[t], b, acc[t]);
+    }
+    if (do_norm && tid < TBN) {
+#pragma unroll
+      for (int kk = 0; kk < BK; ++kk) {
+        const double y = (double)Ys[cur][kk][tid];
+        nrm += y * y;
+      }
+    }
+    if (more) store(cur ^ 1);
+    __syncthreads();
+    cur ^= 1;
+  }
+
+  T* Cz = C + (int64_t)blockIdx.z * cstride;
+#pragma unroll
+  for (int t = 0; t < MT; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = t * 16 + MF::row(lane, r);
+      const int64_t col = n0 + wave * 16 + (lane & 15);
+      if (row < M && col < N) Cz[col * ldc + row] = acc[t][r];
+    }
+  if (do_norm && tid < TBN && n0 + tid < N) colnorm[(int64_t)blockIdx.z * nstride + n0 + tid] = nrm;
+}
+
 // C = sum_z Cpart_z (fixed order); colnorm likewise.
 template <typename T>
 __global__ void splitk_reduce(int64_t M, int64_t N, int splits, const T* __restrict__ P, T* __restrict__ C,
@@ -127,12 +230,38 @@ __global__ void splitk_reduce(int64_t M, int64_t N, int splits, const T* __restr
   }
 }
 
+constexpr int TALL_MT = 18;  // the tall-tile kernel serves M <= 16 TALL_MT
+
 int pick_splits(int64_t M, int64_t N, int64_t K, int num_cu) {
-  const int64_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
   int64_t s = 1;
+  if (M <= 16 * TALL_MT) {
+    // one workgroup per CU: as many K splits as needed to cover the chip
+    const int64_t tiles = (N + TBN - 1) / TBN;
+    while (tiles * s < (int64_t)num_cu && K / (s * 2) >= 1024) s *= 2;
+    return (int)s;
+  }
+  const int64_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
   const int64_t want = 2 * (int64_t)num_cu;
   while (tiles * s < want && K / (s * 2) >= 512) s *= 2;
   return (int)s;
+}
+
+template <typename T, int MT>
+void launch_tall(dim3 grid, hipStream_t s, int64_t M, int64_t N, int64_t K, int64_t kchunk, const T* X, int64_t ldx,
+                 const T* Y, int64_t ldy, T* C, int64_t ldc, int64_t cstride, double* colnorm, int64_t nstride) {
+  gemm_tall_kernel<T, MT><<<grid, NT, 0, s>>>(M, N, K, kchunk, X, ldx, Y, ldy, C, ldc, cstride, colnorm, nstride);
+}
+
+template <typename T, int MT = 1>
+void dispatch_tall(int mt, dim3 grid, hipStream_t s, int64_t M, int64_t N, int64_t K, int64_t kchunk, const T* X,
+                   int64_t ldx, const T* Y, int64_t ldy, T* C, int64_t ldc, int64_t cstride, double* colnorm,
+                   int64_t nstride) {
+  if constexpr (MT <= TALL_MT) {
+    if (mt == MT)
+      launch_tall<T, MT>(grid, s, M, N, K, kchunk, X, ldx, Y, ldy, C, ldc, cstride, colnorm, nstride);
+    else
+      dispatch_tall<T, MT + 1>(mt, grid, s, M, N, K, kchunk, X, ldx, Y, ldy, C, ldc, cstride, colnorm, nstride);
+  }
 }
 
 }  // namespace
@@ -151,17 +280,31 @@ hipError_t gemm_tn(int64_t M, int64_t N, int64_t K, const T* X, int64_t ldx, con
   const int splits = pick_splits(M, N, K, num_cu);
   int64_t kchunk = (K + splits - 1) / splits;
   kchunk = (kchunk + BK - 1) / BK * BK;
-  dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((M + BM - 1) / BM), (unsigned)splits);
-  if (splits == 1) {
-    gemm_tn_kernel<T><<<grid, NT, 0, s>>>(M, N, K, kchunk, X, ldx, Y, ldy, C, ldc, 0, colnorm, 0);
-    return hipGetLastError();
+  const bool tall = M <= 16 * TALL_MT;
+  const int mt = (int)((M + 15) / 16);
+  dim3 grid = tall ? dim3((unsigned)((N + TBN - 1) / TBN), 1u, (unsigned)splits)
+                   : dim3((unsigned)((N + BN - 1) / BN), (unsigned)((M + BM - 1) / BM), (unsigned)splits);
+  T* out = C;
+  int64_t ldo = ldc, ostride = 0, nstride = 0;
+  double* nout = colnorm;
+  T* part = nullptr;
+  double* npart = nullptr;
+  if (splits > 1) {
+    part = ar.take<T>((size_t)splits * M * N);
+    npart = colnorm ? ar.take<double>((size_t)splits * N) : nullptr;
+    if (!part || (colnorm && !npart)) return hipErrorOutOfMemory;
+    out = part;
+    ldo = M;
+    ostride = M * N;
+    nout = npart;
+    nstride = N;
   }
-  T* part = ar.take<T>((size_t)splits * M * N);
-  double* npart = colnorm ? ar.take<double>((size_t)splits * N) : nullptr;
-  if (!part || (colnorm && !npart)) return hipErrorOutOfMemory;
-  gemm_tn_kernel<T><<<grid, NT, 0, s>>>(M, N, K, kchunk, X, ldx, Y, ldy, part, M, M * N, npart, N);
+  if (tall)
+    dispatch_tall<T>(mt, grid, s, M, N, K, kchunk, X, ldx, Y, ldy, out, ldo, ostride, nout, nstride);
+  else
+    gemm_tn_kernel<T><<<grid, NT, 0, s>>>(M, N, K, kchunk, X, ldx, Y, ldy, out, ldo, ostride, nout, nstride);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || splits == 1) return e;
   const int64_t total = M * N > N ? M * N : N;
   splitk_reduce<T><<<(unsigned)((total + 255) / 256), 256, 0, s>>>(M, N, splits, part, C, ldc, npart, colnorm);
   return hipGetLastError();

@@ -42,7 +42,10 @@ def test_omega_fp32_is_rounded_fp64(ff):
 
 
 # ----------------------------------------------------------------- sketch
-@pytest.mark.parametrize("m,n,l", [(1000, 800, 30), (1000, 333, 30), (8192, 200, 20), (130, 70, 65)])
+# l <= 288 takes the tall-tile kernel (one row block, K split), larger l the
+# 64 x 64 tiled kernel
+@pytest.mark.parametrize("m,n,l", [(1000, 800, 30), (1000, 333, 30), (8192, 200, 20), (130, 70, 65),
+                                   (16384, 2048, 272), (4096, 700, 300)])
 def test_sketch_fp64(ff, m, n, l):
     announce(f"sketch fp64 m={m} n={n} l={l}")
     A = synth.random_matrix(m, n, seed=m + n)
@@ -138,7 +141,7 @@ def test_panel_qr_fp32(ff):
 
 
 # -------------------------------------------------------------- projection
-@pytest.mark.parametrize("m,n,c", [(1000, 800, 30), (2049, 513, 45)])
+@pytest.mark.parametrize("m,n,c", [(1000, 800, 30), (2049, 513, 45), (3000, 1000, 290)])
 def test_project_fp64(ff, m, n, c):
     announce(f"project fp64 m={m} n={n} c={c}")
     A = synth.random_matrix(m, n, seed=c)
