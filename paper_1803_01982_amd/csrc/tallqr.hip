@@ -239,8 +239,12 @@ __global__ __launch_bounds__(NT) void tallqr_kernel(T* __restrict__ P, int64_t m
 
   // ------------------------------------------------------------ factorization
   // Within a panel each thread keeps its rows (i = tid + NT u, u < RPT) of the
-  // 16 panel columns in registers: the column steps touch no LDS except for
-  // the cross-wave part of the reductions.
+  // remaining panel columns in registers, the current column always in
+  // position 0: after a column step the finished column goes to P and to
+  // LDS and the others shift down one position.  The column steps touch no
+  // LDS except for the cross-wave part of the reductions, and one copy of
+  // the step's code serves all sixteen columns (it stays in the
+  // instruction cache).
   for (int pi = 0; pi < npan; ++pi) {
     const int p0 = pi * NB, p1 = min(c, p0 + NB), pw = p1 - p0;
     double y[RPT][NB];
@@ -251,11 +255,10 @@ __global__ __launch_bounds__(NT) void tallqr_kernel(T* __restrict__ P, int64_t m
       for (int t = 0; t < NB; ++t)
         y[u][t] = (i < nrow && t < pw) ? (double)P[(int64_t)(p0 + t) * ldp + r0 + i] : 0.0;
     }
-#pragma unroll
-    for (int jt = 0; jt < NB; ++jt) {
-      if (jt < pw) {
+    for (int jt = 0; jt < pw; ++jt) {
       const int jc = p0 + jt, par = step & 1;
-      // partial dots over the own rows below jc: d_t = sum x_i p_t(i), t >= jt
+      // partial dots over the own rows below jc: d_s = sum x_i p_s(i), where
+      // position s holds column jc + s
       {
         double d[NB];
 #pragma unroll
@@ -264,9 +267,9 @@ __global__ __launch_bounds__(NT) void tallqr_kernel(T* __restrict__ P, int64_t m
         for (int u = 0; u < RPT; ++u) {
           const int i = tid + NT * u;
           if (i < nrow && r0 + i > jc) {
-            const double x = y[u][jt];
+            const double x = y[u][0];
 #pragma unroll
-            for (int t = jt; t < NB; ++t) d[t] += x * y[u][t];
+            for (int t = 0; t < NB; ++t) d[t] += x * y[u][t];
           }
         }
         // wave sums of the 16 values by halving exchanges: after the steps
@@ -313,7 +316,7 @@ __global__ __launch_bounds__(NT) void tallqr_kernel(T* __restrict__ P, int64_t m
           const int t = ((lane >> 5) & 1) * 8 + ((lane >> 4) & 1) * 4 + ((lane >> 3) & 1) * 2 + ((lane >> 2) & 1);
           red[wave * NB + t] = h1;
         }
-        // the owner of row jc publishes that row of the panel
+        // the owner of row jc publishes that row of the remaining columns
 #pragma unroll
         for (int u = 0; u < RPT; ++u) {
           const int i = tid + NT * u;
@@ -350,12 +353,12 @@ __global__ __launch_bounds__(NT) void tallqr_kernel(T* __restrict__ P, int64_t m
         if (tid < NB) {
           double sacc = 0.0;
           for (int q = 0; q < NT / NB; ++q) sacc += red[q * NB + tid];
-          Tl[tid] = sacc;                          // d_t
-          Tl[NB + tid] = sl.rowv[par * NB + tid];  // p_t(jc)
+          Tl[tid] = sacc;                          // d_s
+          Tl[NB + tid] = sl.rowv[par * NB + tid];  // p_s(jc)
         }
         __syncthreads();
       }
-      const double xnorm2 = Tl[jt], x0 = Tl[NB + jt];
+      const double xnorm2 = Tl[0], x0 = Tl[NB];
       double tau = 0.0, beta = x0, scale = 0.0;
       if (xnorm2 > 0.0) {
         beta = -copysign(sqrt(x0 * x0 + xnorm2), x0);
@@ -366,38 +369,34 @@ __global__ __launch_bounds__(NT) void tallqr_kernel(T* __restrict__ P, int64_t m
         taul[jt] = tau;
         if (g == 0) sl.taus[jc] = tau;
       }
-      // own rows: p_t -= tau w_t v, w_t = p_t(jc) + scale d_t, then the
-      // column becomes v (beta on the diagonal)
+      // own rows: p_s -= tau w_s v, w_s = p_s(jc) + scale d_s; the column
+      // becomes v (beta on the diagonal), is stored, and the rest shift down
       double tw[NB];
 #pragma unroll
-      for (int t = jt + 1; t < NB; ++t) tw[t] = tau * (Tl[NB + t] + scale * Tl[t]);
+      for (int t = 1; t < NB; ++t) tw[t] = tau * (Tl[NB + t] + scale * Tl[t]);
 #pragma unroll
       for (int u = 0; u < RPT; ++u) {
-        const int64_t gi = r0 + tid + NT * u;
-        if (tid + NT * u < nrow && gi >= jc) {
-          const double vv = (gi == jc) ? 1.0 : y[u][jt] * scale;
+        const int i = tid + NT * u;
+        const int64_t gi = r0 + i;
+        if (i < nrow) {
+          if (gi >= jc) {
+            const double vv = (gi == jc) ? 1.0 : y[u][0] * scale;
 #pragma unroll
-          for (int t = jt + 1; t < NB; ++t) y[u][t] -= tw[t] * vv;
-          if (gi == jc) y[u][jt] = beta;
-          else if (tau != 0.0) y[u][jt] = vv;
+            for (int t = 1; t < NB; ++t) y[u][t] -= tw[t] * vv;
+            if (gi == jc) y[u][0] = beta;
+            else if (tau != 0.0) y[u][0] = vv;
+          }
+          P[(int64_t)jc * ldp + gi] = (T)y[u][0];
+          Yl[jt * ldy + i] = yval(gi, p0, jt, y[u][0]);
         }
+#pragma unroll
+        for (int t = 0; t + 1 < NB; ++t) y[u][t] = y[u][t + 1];
+        y[u][NB - 1] = 0.0;
       }
       ++step;
-      }
     }
-    // write the panel back (R above the diagonal, beta on it, v below) and
-    // keep Y of the own rows in LDS for the panel end
-#pragma unroll
-    for (int u = 0; u < RPT; ++u) {
-      const int i = tid + NT * u;
-      if (i < nrow) {
-#pragma unroll
-        for (int t = 0; t < NB; ++t) {
-          if (t < pw) P[(int64_t)(p0 + t) * ldp + r0 + i] = (T)y[u][t];
-          Yl[t * ldy + i] = t < pw ? yval(r0 + i, p0, t, y[u][t]) : 0.0;
-        }
-      }
-    }
+    for (int t = pw; t < NB; ++t)
+      for (int i = tid; i < nrow; i += NT) Yl[t * ldy + i] = 0.0;
     __syncthreads();
     const int ntr = c - p1;
     double* zp = sl.zpart + (int64_t)g * estride;
