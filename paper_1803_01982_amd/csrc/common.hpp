@@ -94,25 +94,30 @@ __device__ inline ArgMax block_argmax(ArgMax a, double* rv, int64_t* ri) {
 // ------------------------------------------------------------ grid barrier
 // Device-wide barrier for cooperative (co-resident) launches.
 //
-// On gfx950 an agent-scope release is an L2 writeback and an agent-scope
-// acquire an L2 invalidate, and their cost grows with the number of
-// workgroups per XCD, so only one thread per workgroup fences: the
-// workgroup barrier before it completes every wave's stores to L2, and the
-// invalidate after it covers the CU's vector cache for all waves.  Arrival
-// is counted in groups of 16 workgroups, then across groups; the last
-// arrival publishes the new generation, which the others poll with relaxed
-// loads (no cache maintenance per poll).
+// Every workgroup announces its arrival by storing the barrier's epoch into
+// a flag of its own (one 128-byte line per workgroup), and wave 0 of every
+// workgroup polls all the flags with relaxed loads, one flag per lane, until
+// each holds at least the epoch.  No atomic read-modify-write is on the
+// critical path: a barrier costs the flag store plus one round of loads.
 //
-// `sync` (kSyncWords words, zeroed before each launch) holds the counters;
-// every wait is bounded: past the spin limit the block raises `error` and
-// returns false, and every other block then leaves within one more bounded
-// wait, so the grid always drains.
-constexpr int kSyncWords = 1024;
+// On gfx950 an agent-scope release is an L2 write-back and an acquire an L2
+// invalidate, so only thread 0 of each workgroup fences: the workgroup
+// barrier before its release orders every wave's earlier accesses, and its
+// acquire (an invalidate of the CU's caches) precedes every wave's later
+// ones through the closing workgroup barrier.  Flags only grow, so a
+// workgroup that is already one barrier ahead still satisfies the test.
+//
+// `sync` (kSyncWords words, zeroed before each launch) holds the flags;
+// every wait is bounded: past the spin limit the workgroup raises `error`
+// and returns false, and every other workgroup then leaves within one more
+// bounded wait, so the grid always drains.
+constexpr int kFlagStride = 32;  // words between the flags of two workgroups
+constexpr int kMaxGridBlocks = 256;
+constexpr int kSyncWords = kFlagStride * kMaxGridBlocks;
 constexpr unsigned kSpinLimit = 1u << 22;
-constexpr unsigned kGroup = 16;
 
 struct GridSync {
-  unsigned* sync;   // [0]: arrivals of groups, [32]: generation, [64 + 32 g]: group arrivals
+  unsigned* sync;   // flag of workgroup q at sync[kFlagStride * q]
   unsigned* error;
   unsigned nblocks;
 };
@@ -122,32 +127,32 @@ __device__ inline bool grid_barrier(const GridSync& gs, unsigned& epoch) {
   __syncthreads();
   ++epoch;
   if (gs.nblocks == 1) return true;  // one workgroup: the workgroup barrier suffices
-  if (threadIdx.x == 0) {
-    int ok = 1;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    const unsigned grp = blockIdx.x / kGroup, ngrp = (gs.nblocks + kGroup - 1) / kGroup;
-    const unsigned gsize = (grp == ngrp - 1) ? gs.nblocks - grp * kGroup : kGroup;
-    const unsigned old = __hip_atomic_fetch_add(gs.sync + 64 + 32 * grp, 1u, __ATOMIC_RELAXED,
-                                                __HIP_MEMORY_SCOPE_AGENT);
-    if (old == epoch * gsize - 1) {
-      const unsigned o2 = __hip_atomic_fetch_add(gs.sync, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (o2 == epoch * ngrp - 1)
-        __hip_atomic_store(gs.sync + 32, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x < kWave) {
+    if (threadIdx.x == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __hip_atomic_store(gs.sync + kFlagStride * blockIdx.x, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+    int ok = 1;
     unsigned spins = 0;
-    while (__hip_atomic_load(gs.sync + 32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
+    for (;;) {
+      bool here = true;
+      for (unsigned q = threadIdx.x; q < gs.nblocks; q += kWave)
+        here = here && __hip_atomic_load(gs.sync + kFlagStride * q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= epoch;
+      if (__all(here)) break;
       __builtin_amdgcn_s_sleep(1);
       if ((++spins & 255u) == 0) {
-        if (__hip_atomic_load(gs.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
-            spins > kSpinLimit) {
-          __hip_atomic_fetch_or(gs.error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const bool bad = __hip_atomic_load(gs.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
+        if (__any(bad) || spins > kSpinLimit) {
+          if (threadIdx.x == 0) __hip_atomic_fetch_or(gs.error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           ok = 0;
           break;
         }
       }
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    s_ok = ok;
+    if (threadIdx.x == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      s_ok = ok;
+    }
   }
   __syncthreads();
   return s_ok != 0;

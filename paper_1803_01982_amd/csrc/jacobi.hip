@@ -391,6 +391,7 @@ hipError_t jacobi_sigma(const T* L, int64_t l, int64_t ldl, double* sigma, Arena
   if (!M || !sig || !ctl) return hipErrorOutOfMemory;
   hipError_t e = zero_words(ctl, kSyncWords + 64, s);
   if (e != hipSuccess) return e;
+  if (P / 2 > kMaxGridBlocks) return hipErrorInvalidValue;
   GridSync gs{ctl, err, (unsigned)(P / 2)};
   unsigned* rot = ctl + kSyncWords;
   int li = (int)l;

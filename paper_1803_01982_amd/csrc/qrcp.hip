@@ -461,6 +461,7 @@ hipError_t qrcp(const T* B, int64_t l, int64_t n, int64_t ldb, int64_t* piv, dou
     if (!sl.r || !sl.r2 || !sl.idx || !sl.col || !counter) return hipErrorOutOfMemory;
     hipError_t e = zero_words(counter, kSyncWords, s);
     if (e != hipSuccess) return e;
+    if (Gr > kMaxGridBlocks) return hipErrorInvalidValue;
     GridSync gs{counter, err, (unsigned)Gr};
     int li = (int)l;
     int64_t ln = n, lldb = ldb;
@@ -482,6 +483,7 @@ hipError_t qrcp(const T* B, int64_t l, int64_t n, int64_t ldb, int64_t* piv, dou
   if (!sl.r || !sl.r2 || !sl.idx || !sl.col || !counter || (!in_lds && !Bw)) return hipErrorOutOfMemory;
   hipError_t e = zero_words(counter, kSyncWords, s);
   if (e != hipSuccess) return e;
+  if (G > kMaxGridBlocks) return hipErrorInvalidValue;
   GridSync gs{counter, err, (unsigned)G};
   int li = (int)l;
   int64_t ln = n, lldb = ldb;

@@ -786,6 +786,7 @@ hipError_t tall_qr(T* P, int64_t mrows, int64_t c, int64_t ldp, T* Qout, int64_t
     return hipErrorOutOfMemory;
   hipError_t e = zero_words(counter, kSyncWords, s);
   if (e != hipSuccess) return e;
+  if (G > kMaxGridBlocks) return hipErrorInvalidValue;
   GridSync gs{counter, err, (unsigned)G};
   int ci = (int)c, tr = transpose_r ? 1 : 0;
   void* args[] = {(void*)&P, (void*)&mrows, (void*)&ci, (void*)&ldp, (void*)&rb, (void*)&Qout, (void*)&ldq,
