@@ -18,9 +18,12 @@
 // sweep.  H is recomputed from the columns at every round, so the rounding
 // of the Gram updates never accumulates beyond one round, and the columns
 // only ever see orthogonal transformations.  A pair is rotated when
-// |h_pq| > tol sqrt(h_pp h_qq) (tol = 1e-14), with Rutishauser's formulas;
-// the iteration stops after a sweep with no rotation (at most 60 sweeps).
-// sigma_j = ||c_j||, sorted descending.
+// |h_pq| > tol sqrt(h_pp h_qq) (tol = 1e-14), with Rutishauser's formulas.
+// The iteration stops after a sweep with no rotation, or after a sweep in
+// which every rotated pair had |h_pq| <= 1e-8 sqrt(h_pp h_qq): in that
+// (quadratically convergent) regime the sweep leaves off-diagonal mass of
+// order 1e-16 relative, far below what a further sweep could change in the
+// singular values (at most 60 sweeps).  sigma_j = ||c_j||, sorted descending.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -32,6 +35,7 @@ constexpr int NT = 1024;
 constexpr int NW = NT / kWave;
 constexpr int GW = 32;  // stride of the Gram and rotation arrays (2 bs <= GW)
 constexpr double kTol = 1e-14;
+constexpr double kSettled = 1e-8;  // a sweep with no larger rotation ends the iteration
 constexpr int kMaxSweeps = 60;
 
 __device__ inline int rr_player(int pos, int r, int P) {
@@ -93,7 +97,8 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(const T* __restrict__ L, int
   double* Pg = J1 + GW * GW;
   __shared__ double s_al[GW], s_be[GW], s_dn[GW];
   __shared__ int s_rt[GW];
-  __shared__ int s_sweep, s_round, s_inner[2];
+  __shared__ int s_sweep;  // a pair with |h_pq| > kSettled sqrt(h_pp h_qq) was rotated this sweep
+  __shared__ int s_round, s_inner[2];
   __shared__ unsigned short sched_full[31 * 16];
   __shared__ unsigned short sched_cross[16 * 16];
   __shared__ unsigned char part_full[31 * GW];
@@ -256,7 +261,7 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(const T* __restrict__ L, int
             s_al[q] = cs; s_be[q] = sn; s_dn[q] = b + tt * hg; s_rt[q] = 1;
             s_inner[ir & 1] = 1;
             s_round = 1;
-            s_sweep = 1;
+            if (hg * hg > (kSettled * kSettled) * (a * b)) s_sweep = 1;
           }
         }
         if (tid == 0) s_inner[(ir + 1) & 1] = 0;
@@ -319,8 +324,8 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(const T* __restrict__ L, int
     }
     if (tid == 0 && s_sweep) __hip_atomic_fetch_or(&rot[sweep % 3], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (!grid_barrier(gs, epoch)) return;
-    const unsigned any = __hip_atomic_load(&rot[sweep % 3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (!any) break;
+    const unsigned big = __hip_atomic_load(&rot[sweep % 3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (!big) break;  // no rotation, or only rotations below kSettled
   }
   if (g == 0 && tid == 0 && sweeps_out) *sweeps_out = sweep < kMaxSweeps ? sweep + 1 : kMaxSweeps;
   // column norms

@@ -695,11 +695,14 @@ __global__ __launch_bounds__(256) void wy_apply_kernel(const T* __restrict__ P, 
       }
 }
 
-// Row blocks of about 256 rows: fewer workgroups make the per-column grid
-// barriers cheaper, more workgroups share the panel-end streaming; 256 rows
-// measured best for 16384 x 272 (128: 5.5 ms, 256: 5.1 ms, 512: 6.8 ms).
+// Row blocks of 128 to 256 rows, aiming at 64 workgroups: more workgroups
+// share the panel-end streaming, fewer keep the per-column grid barriers
+// cheap.  Measured on 16384 x 272 / 8192 x 272: 128-row blocks 3.02 / 2.42
+// ms, 256-row blocks 3.00 / 2.77 ms, 512-row blocks 3.75 / 3.64 ms.
 void choose(int64_t mrows, int c, int num_cu, int* G, int* rb, size_t* lds) {
-  int64_t g = (mrows + 255) / 256;
+  int64_t rows = (mrows + 63) / 64;
+  rows = rows < 128 ? 128 : (rows > 256 ? 256 : rows);
+  int64_t g = (mrows + rows - 1) / rows;
   if (g > num_cu) g = num_cu;
   if (g < 1) g = 1;
   int64_t r = (mrows + g - 1) / g;
