@@ -44,6 +44,34 @@ __device__ inline double group_sum(double v, int g) {
   return v;
 }
 
+// Lane exchanges inside a row of 16 lanes through DPP (no LDS round trip).
+// Partners: xor 1 and xor 2 (quad permutations), i <-> 7 - i inside each
+// half row and i <-> 15 - i inside the row; each pairs lanes that differ in
+// bit 0, 1, 2 or 3 respectively.
+enum : int { kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140 };
+template <int CTRL>
+__device__ inline double dpp_mov(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+template <int CTRL>
+__device__ inline int64_t dpp_mov(int64_t v) {
+  const int lo = __builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(v >> 32), CTRL, 0xF, 0xF, true);
+  return (int64_t)(((uint64_t)(unsigned)hi << 32) | (unsigned)lo);
+}
+// Sum over each row of 16 lanes; every lane of the row gets the same value
+// (each level adds two equal-content partial sums, in either order).
+__device__ inline double row16_sum(double v) {
+  v += dpp_mov<kDppXor1>(v);
+  v += dpp_mov<kDppXor2>(v);
+  v += dpp_mov<kDppHalfMirror>(v);
+  v += dpp_mov<kDppMirror>(v);
+  return v;
+}
+
 // Block-wide sum; `red` is LDS scratch of at least blockDim.x / 64 doubles.
 // Every thread gets the total; the summation order is fixed.
 __device__ inline double block_sum(double v, double* red) {

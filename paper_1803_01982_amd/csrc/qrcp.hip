@@ -73,6 +73,21 @@ __device__ inline Top2 wave_top2(Top2 x) {
   return x;
 }
 
+// Top-2 over each row of 16 lanes through DPP exchanges (the merge is
+// commutative and associative, so every lane of the row ends with the same
+// result).
+template <int CTRL>
+__device__ inline Top2 top2_dpp(Top2 x) {
+  const Top2 y{dpp_mov<CTRL>(x.v1), dpp_mov<CTRL>(x.i1), dpp_mov<CTRL>(x.v2)};
+  return top2_merge(x, y);
+}
+__device__ inline Top2 row16_top2(Top2 x) {
+  x = top2_dpp<kDppXor1>(x);
+  x = top2_dpp<kDppXor2>(x);
+  x = top2_dpp<kDppHalfMirror>(x);
+  return top2_dpp<kDppMirror>(x);
+}
+
 __device__ inline int group_size_for(int nc) {
   int g = 1;
   while (g * 2 * nc <= NT && g < 64) g *= 2;
@@ -249,7 +264,7 @@ __global__ __launch_bounds__(NT) void qrcp_reg_kernel(const T* __restrict__ B, i
       x[b][s] = (act[b] && i < l) ? (double)B[col[b] * ldb + i] : 0.0;
       s2 += x[b][s] * x[b][s];
     }
-    rn[b] = group_sum(s2, TPC);
+    rn[b] = row16_sum(s2);
   }
   unsigned epoch = 0;
   for (int j = 0; j < l; ++j) {
@@ -271,13 +286,10 @@ __global__ __launch_bounds__(NT) void qrcp_reg_kernel(const T* __restrict__ B, i
     }
     __syncthreads();
     {
+      static_assert(NT / 64 == 16, "one post per lane of the first row");
       Top2 u{0.0, -1, -1.0};
       if (lane < NT / 64) u = Top2{s_tv1[lane], s_ti1[lane], s_tv2[lane]};
-#pragma unroll
-      for (int o = 1; o < NT / 64; o <<= 1) {
-        const Top2 y{__shfl_xor(u.v1, o, kWave), __shfl_xor(u.i1, o, kWave), __shfl_xor(u.v2, o, kWave)};
-        u = top2_merge(u, y);
-      }
+      u = row16_top2(u);
       const int64_t bi = __shfl(u.i1, 0, kWave);
       if (wave == 0 && lane == 0) {
         sl.r[par * G + g] = u.v1;
@@ -302,8 +314,9 @@ __global__ __launch_bounds__(NT) void qrcp_reg_kernel(const T* __restrict__ B, i
       Top2 u{0.0, -1, -1.0};
       for (int qq = lane; qq < G; qq += kWave)
         u = top2_merge(u, Top2{sl.r[par * G + qq], sl.idx[par * G + qq], sl.r2[par * G + qq]});
+      u = row16_top2(u);
 #pragma unroll
-      for (int o = 1; o < 64; o <<= 1) {
+      for (int o = 16; o < 64; o <<= 1) {
         const Top2 y{__shfl_xor(u.v1, o, kWave), __shfl_xor(u.i1, o, kWave), __shfl_xor(u.v2, o, kWave)};
         u = top2_merge(u, y);
       }
@@ -363,7 +376,7 @@ __global__ __launch_bounds__(NT) void qrcp_reg_kernel(const T* __restrict__ B, i
         double dt = 0.0;
 #pragma unroll
         for (int s = 0; s < NR; ++s) dt += v[q + TPC * s] * x[b][s];
-        const double f = group_sum(dt, TPC) * tau;
+        const double f = row16_sum(dt) * tau;
 #pragma unroll
         for (int s = 0; s < NR; ++s) x[b][s] -= f * v[q + TPC * s];
       }
@@ -373,7 +386,7 @@ __global__ __launch_bounds__(NT) void qrcp_reg_kernel(const T* __restrict__ B, i
         const int i = q + TPC * s;
         if (i > j) r += x[b][s] * x[b][s];
       }
-      rn[b] = group_sum(r, TPC);
+      rn[b] = row16_sum(r);
     }
   }
 }

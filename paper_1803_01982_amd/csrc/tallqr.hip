@@ -295,23 +295,25 @@ __global__ __launch_bounds__(NT) void tallqr_kernel(T* __restrict__ P, int64_t m
             h4[k] = keep + __shfl_xor(send, 16, kWave);
           }
         }
+        // inside a row of 16 lanes the partner of a lane only has to differ in
+        // the bit of the level (DPP mirrors and quad permutations)
         {
           const bool up = lane & 8;
 #pragma unroll
           for (int k = 0; k < 2; ++k) {
             const double send = up ? h4[k] : h4[k + 2];
             const double keep = up ? h4[k + 2] : h4[k];
-            h2[k] = keep + __shfl_xor(send, 8, kWave);
+            h2[k] = keep + dpp_mov<kDppMirror>(send);
           }
         }
         {
           const bool up = lane & 4;
           const double send = up ? h2[0] : h2[1];
           const double keep = up ? h2[1] : h2[0];
-          h1 = keep + __shfl_xor(send, 4, kWave);
+          h1 = keep + dpp_mov<kDppHalfMirror>(send);
         }
-        h1 += __shfl_xor(h1, 2, kWave);
-        h1 += __shfl_xor(h1, 1, kWave);
+        h1 += dpp_mov<kDppXor2>(h1);
+        h1 += dpp_mov<kDppXor1>(h1);
         if ((lane & 3) == 0) {
           const int t = ((lane >> 5) & 1) * 8 + ((lane >> 4) & 1) * 4 + ((lane >> 3) & 1) * 2 + ((lane >> 2) & 1);
           red[wave * NB + t] = h1;
