@@ -54,16 +54,22 @@ class StepTimer {
       hipEventDestroy(r.b);
     }
   }
-  void begin(int step) {
-    if (!on_) return;
-    Rec r{step, nullptr, nullptr};
-    if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return;
-    hipEventRecord(r.a, s_);
+  // begin() returns a handle for end(); end() without one closes the latest
+  // step.  A step may be issued on another stream (its interval may then
+  // overlap other steps).
+  int begin(int step) { return begin(step, s_); }
+  void end() { end((int)recs_.size() - 1, s_); }
+  int begin(int step, hipStream_t st) {
+    if (!on_) return -1;
+    Rec r{step, nullptr, nullptr, false};
+    if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return -1;
+    hipEventRecord(r.a, st);
     recs_.push_back(r);
+    return (int)recs_.size() - 1;
   }
-  void end() {
-    if (!on_ || recs_.empty()) return;
-    hipEventRecord(recs_.back().b, s_);
+  void end(int h, hipStream_t st) {
+    if (!on_ || h < 0 || h >= (int)recs_.size()) return;
+    if (hipEventRecord(recs_[h].b, st) == hipSuccess) recs_[h].closed = true;
   }
   // after the stream has been synchronised
   void collect() {
@@ -71,7 +77,7 @@ class StepTimer {
     std::lock_guard<std::mutex> lk(g_prof.mu);
     for (auto& r : recs_) {
       float ms = 0.f;
-      if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      if (r.closed && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
         g_prof.ms[r.step] += ms;
         g_prof.launches[r.step] += 1;
       }
@@ -82,6 +88,7 @@ class StepTimer {
   struct Rec {
     int step;
     hipEvent_t a, b;
+    bool closed;
   };
   hipStream_t s_;
   bool on_ = false;
@@ -116,7 +123,7 @@ size_t scratch_bytes(int64_t m, int64_t n, int64_t l, const DeviceInfo& d) {
   s = std::max(s, gemm_tn_scratch<T>(l, n, m, d.num_cu));
   s = std::max(s, qrcp_scratch<T>(l, n, d));
   s = std::max(s, tallqr_scratch<T>(m, l, d));
-  s = std::max(s, tallqr_scratch<T>(n, l, d));
+  s = std::max(s, tallqr_scratch<T>(n, l, d) + jacobi_scratch<T>(l, d));  // a6 and a7 run concurrently
   s = std::max(s, srqr_scratch<T>(m, n, l));
   s = std::max(s, jacobi_scratch<T>(l, d));
   return s + 16 * 256;
@@ -163,6 +170,27 @@ ffsrqr_status get_device(const DeviceInfo** out) {
   if (!d.gfx950) return fail(FFSRQR_ENODEV, "the current device is not gfx950");
   if (!d.coop) return fail(FFSRQR_ENODEV, "the current device has no cooperative launch");
   *out = &d;
+  return FFSRQR_OK;
+}
+
+// A second stream (default priority) with a fork and a join event, one set
+// per host thread and device, so that concurrent calls from different host
+// threads never share them.  Created on first use, kept until exit.
+struct SideStream {
+  hipStream_t stream = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+thread_local SideStream g_side[64];
+
+ffsrqr_status get_side(int id, SideStream** out) {
+  SideStream& ss = g_side[id];
+  if (!ss.stream) {
+    hipError_t e = hipStreamCreateWithFlags(&ss.stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ss.join, hipEventDisableTiming);
+    if (e != hipSuccess) return fail(FFSRQR_EHIP, std::string("side stream: ") + hipGetErrorString(e));
+  }
+  *out = &ss;
   return FFSRQR_OK;
 }
 
@@ -213,6 +241,11 @@ ffsrqr_status factor_impl(const T* A, int64_t m, int64_t n, int64_t lda, int64_t
   auto scratch = [&]() { return Arena{(char*)work, work_bytes, scratch_off}; };
   if (!err) return fail(FFSRQR_EWORKSPACE, "workspace carving failed");
 
+  SideStream* side = nullptr;
+  {
+    const ffsrqr_status sst = get_side(d.id, &side);
+    if (sst != FFSRQR_OK) return sst;
+  }
   StepTimer tm(s);
   FF_HIP(zero_words(err, 64, s));
   // a1: Omega and the sketch (one pass over A, column norms fused)
@@ -308,22 +341,24 @@ ffsrqr_status factor_impl(const T* A, int64_t m, int64_t n, int64_t lda, int64_t
     }
     tm.end();
     // a6, a7 (issued before the swap decision is known; redone after a swap)
-    tm.begin(FFSRQR_STEP_LQ);
+    const int lq_step = tm.begin(FFSRQR_STEP_LQ);
     FF_HIP(assemble_rt<T>(R11, l, W, l, perm, l, n, region2, n, s));
     {
       // Qhat1 (n x l) in natural row order goes to W's buffer (W is dead
-      // once R^T is assembled), then V = Pi Qhat1 by a row scatter
+      // once R^T is assembled), then V = Pi Qhat1 by a row scatter.  As soon
+      // as L is written, a7 (Jacobi on L) runs on the side stream, in
+      // scratch of its own, while Qhat1 is formed.
       Arena a = scratch();
-      FF_HIP(tall_qr<T>(region2, n, l, n, W, n, L, ldl, true, a, err, d, s));
+      FF_HIP(tall_qr<T>(region2, n, l, n, W, n, L, ldl, true, a, err, d, s, side->fork));
+      FF_HIP(hipStreamWaitEvent(side->stream, side->fork, 0));
+      const int svd_step = tm.begin(FFSRQR_STEP_SVD, side->stream);
+      FF_HIP(jacobi_sigma<T>(L, l, ldl, sigma, a, err, d, side->stream, (int*)(err + 32)));
+      tm.end(svd_step, side->stream);
+      FF_HIP(hipEventRecord(side->join, side->stream));
       FF_HIP(scatter_rows<T>(W, n, l, n, perm, V, ldv, s));
     }
-    tm.end();
-    {
-      Arena a = scratch();
-      tm.begin(FFSRQR_STEP_SVD);
-      FF_HIP(jacobi_sigma<T>(L, l, ldl, sigma, a, err, d, s, (int*)(err + 32)));
-      tm.end();
-    }
+    tm.end(lq_step, s);
+    FF_HIP(hipStreamWaitEvent(s, side->join, 0));
     unsigned herr[64];
     FF_HIP(hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, s));
     FF_HIP(hipMemcpyAsync(herr, err, sizeof(herr), hipMemcpyDeviceToHost, s));

@@ -64,7 +64,8 @@ template <typename T>
 size_t tallqr_scratch(int64_t mrows, int64_t c, const DeviceInfo& d);
 template <typename T>
 hipError_t tall_qr(T* P, int64_t mrows, int64_t c, int64_t ldp, T* Qout, int64_t ldq, T* R, int64_t ldr,
-                   bool transpose_r, Arena& ar, unsigned* err, const DeviceInfo& d, hipStream_t s);
+                   bool transpose_r, Arena& ar, unsigned* err, const DeviceInfo& d, hipStream_t s,
+                   hipEvent_t r_ready = nullptr);  // recorded on s once R is written (before Q is formed)
 // V(rowmap[i], :) = Q(i, :) for i < mrows (entries outside [0, mrows) skipped).
 template <typename T>
 hipError_t scatter_rows(const T* Q, int64_t mrows, int64_t c, int64_t ldq, const int64_t* rowmap, T* V,

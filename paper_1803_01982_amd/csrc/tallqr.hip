@@ -766,7 +766,8 @@ size_t tallqr_scratch(int64_t mrows, int64_t c, const DeviceInfo& d) {
 
 template <typename T>
 hipError_t tall_qr(T* P, int64_t mrows, int64_t c, int64_t ldp, T* Qout, int64_t ldq, T* R, int64_t ldr,
-                   bool transpose_r, Arena& ar, unsigned* err, const DeviceInfo& d, hipStream_t s) {
+                   bool transpose_r, Arena& ar, unsigned* err, const DeviceInfo& d, hipStream_t s,
+                   hipEvent_t r_ready) {
   if (c <= 0) return hipSuccess;
   if (mrows < c || c > 1024) return hipErrorInvalidValue;
   int G, rb, nsplit;
@@ -807,6 +808,10 @@ hipError_t tall_qr(T* P, int64_t mrows, int64_t c, int64_t ldp, T* Qout, int64_t
   }
   e = hipLaunchCooperativeKernel(fn, dim3(G), dim3(NT), args, (unsigned)lds, s);
   if (e != hipSuccess) return e;
+  if (r_ready) {
+    e = hipEventRecord(r_ready, s);
+    if (e != hipSuccess) return e;
+  }
   const int nt = (ci + WY_T - 1) / WY_T;
   gram_y_kernel<T><<<dim3((unsigned)(nt * (nt + 1) / 2), (unsigned)nsplit), 256, 0, s>>>(P, mrows, ci, ldp, chunk,
                                                                                         spart);
@@ -853,7 +858,7 @@ hipError_t scatter_rows(const T* Q, int64_t mrows, int64_t c, int64_t ldq, const
 #define INST(T)                                                                                                    \
   template size_t tallqr_scratch<T>(int64_t, int64_t, const DeviceInfo&);                                          \
   template hipError_t tall_qr<T>(T*, int64_t, int64_t, int64_t, T*, int64_t, T*, int64_t, bool, Arena&, unsigned*, \
-                                 const DeviceInfo&, hipStream_t);                                                  \
+                                 const DeviceInfo&, hipStream_t, hipEvent_t);                                                  \
   template hipError_t gather_cols<T>(const T*, int64_t, int64_t, int64_t, const int64_t*, int64_t, T*, int64_t,     \
                                      hipStream_t);                                                                 \
   template hipError_t scatter_rows<T>(const T*, int64_t, int64_t, int64_t, const int64_t*, T*, int64_t, hipStream_t);

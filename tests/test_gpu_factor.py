@@ -159,3 +159,28 @@ def test_repeat_is_deterministic(ff):
     assert np.array_equal(host(a.perm), host(b.perm))
     assert np.array_equal(host(a.sigma), host(b.sigma))
     assert np.array_equal(host(a.Q), host(b.Q))
+
+
+def test_profiled_solve_matches_unprofiled(ff):
+    """Per-step timing (events on the solve's stream and on the side stream
+    that runs the Jacobi step concurrently with the forming of V) leaves the
+    results unchanged and accounts for every step once per solve."""
+    import torch
+    announce("factor small_fp64 with step profiling")
+    A = dev_f(synth.make_workload("small_fp64"))
+    ref = ff.factor(A, 20, 10, 0)
+    ff.profile_enable(True)
+    try:
+        out = ff.factor(A, 20, 10, 0)
+        torch.cuda.synchronize()
+        prof = ff.profile_read()
+    finally:
+        ff.profile_enable(False)
+    assert np.array_equal(host(out.sigma), host(ref.sigma))
+    assert np.array_equal(host(out.V), host(ref.V))
+    for step in ("sketch", "qrcp", "panel", "project", "lq", "svd"):
+        ms, launches = prof[step]
+        assert launches == 1 + out.info["swaps"] and ms > 0.0, (step, prof[step])
+    # a later unprofiled call still works (no stale error left behind)
+    again = ff.factor(A, 20, 10, 0)
+    assert np.array_equal(host(again.sigma), host(ref.sigma))
