@@ -123,7 +123,8 @@ size_t scratch_bytes(int64_t m, int64_t n, int64_t l, const DeviceInfo& d) {
   s = std::max(s, gemm_tn_scratch<T>(l, n, m, d.num_cu));
   s = std::max(s, qrcp_scratch<T>(l, n, d));
   s = std::max(s, tallqr_scratch<T>(m, l, d));
-  s = std::max(s, tallqr_scratch<T>(n, l, d) + jacobi_scratch<T>(l, d));  // a6 and a7 run concurrently
+  // a6 on one stream while a4's residual norms, a5 and a7 run on the other
+  s = std::max(s, align256(tallqr_scratch<T>(n, l, d)) + std::max(srqr_scratch<T>(m, n, l), jacobi_scratch<T>(l, d)));
   s = std::max(s, srqr_scratch<T>(m, n, l));
   s = std::max(s, jacobi_scratch<T>(l, d));
   return s + 16 * 256;
@@ -135,6 +136,7 @@ size_t persistent_bytes(int64_t m, int64_t n, int64_t l) {
   b += align256(std::max<size_t>((size_t)m * l, (size_t)m * l) * sizeof(T));  // Omega^T, then the gathered panel
   b += align256((size_t)l * n * sizeof(T));                                   // B, then R^T
   b += align256((size_t)l * n * sizeof(T));                                   // W
+  b += align256((size_t)n * l * sizeof(T));                                   // Qhat1
   b += align256((size_t)l * l * sizeof(T));                                   // R11
   b += 2 * align256((size_t)n * sizeof(double));                              // anorm2, gamma2
   b += 2 * align256((size_t)l * sizeof(double));                              // margins, rho
@@ -227,6 +229,7 @@ ffsrqr_status factor_impl(const T* A, int64_t m, int64_t n, int64_t lda, int64_t
   T* region1 = ar.take<T>((size_t)m * l);  // Omega^T, later the gathered panel
   T* region2 = ar.take<T>((size_t)l * n);  // B, later R^T
   T* W = ar.take<T>((size_t)l * n);
+  T* Qhat = ar.take<T>((size_t)n * l);
   T* R11 = ar.take<T>((size_t)l * l);
   double* anorm2 = ar.take<double>(n);
   double* gamma2 = ar.take<double>(n);
@@ -326,36 +329,45 @@ ffsrqr_status factor_impl(const T* A, int64_t m, int64_t n, int64_t lda, int64_t
       FF_HIP(gemm_tn<T>(l, n, m, Q, ldq, A, lda, W, l, nullptr, a, d.num_cu, s));
       tm.end();
     }
-    tm.begin(FFSRQR_STEP_RESID);
-    FF_HIP(residual_norms<T>(W, l, n, l, anorm2, gamma2, s));
-    tm.end();
-    // a5: SRQR test
-    tm.begin(FFSRQR_STEP_SRQR);
+    // From here two streams: the side stream runs the SRQR test (a4's
+    // residual norms and a5), then a7 once L exists; the caller's stream
+    // runs a6 (issued before the swap decision is known; redone after a
+    // swap).  They read W and R11 concurrently and write disjoint buffers;
+    // the side stream's scratch is carved after the LQ's.
+    FF_HIP(hipEventRecord(side->fork, s));
+    FF_HIP(hipStreamWaitEvent(side->stream, side->fork, 0));
+    Arena a_main = scratch();
+    Arena a_side{(char*)work, work_bytes, scratch_off + align256(tallqr_scratch<T>(n, l, d))};
     {
-      Arena a = scratch();
-      FF_HIP(srqr_select<T>(gamma2, anorm2, inS, n, A, m, lda, Q, ldq, W, l, R11, l, l, st, a, s));
+      const int h = tm.begin(FFSRQR_STEP_RESID, side->stream);
+      FF_HIP(residual_norms<T>(W, l, n, l, anorm2, gamma2, side->stream));
+      tm.end(h, side->stream);
     }
-    if (l < n) {
-      Arena a = scratch();
-      FF_HIP(srqr_rho<T>(R11, l, W, l, st, 0.0, l, rho, st, a, s));
+    {
+      // a5: SRQR test
+      const int h = tm.begin(FFSRQR_STEP_SRQR, side->stream);
+      Arena a = a_side;
+      FF_HIP(srqr_select<T>(gamma2, anorm2, inS, n, A, m, lda, Q, ldq, W, l, R11, l, l, st, a, side->stream));
+      if (l < n) {
+        Arena a2 = a_side;
+        FF_HIP(srqr_rho<T>(R11, l, W, l, st, 0.0, l, rho, st, a2, side->stream));
+      }
+      tm.end(h, side->stream);
     }
-    tm.end();
-    // a6, a7 (issued before the swap decision is known; redone after a swap)
     const int lq_step = tm.begin(FFSRQR_STEP_LQ);
     FF_HIP(assemble_rt<T>(R11, l, W, l, perm, l, n, region2, n, s));
     {
-      // Qhat1 (n x l) in natural row order goes to W's buffer (W is dead
-      // once R^T is assembled), then V = Pi Qhat1 by a row scatter.  As soon
-      // as L is written, a7 (Jacobi on L) runs on the side stream, in
-      // scratch of its own, while Qhat1 is formed.
-      Arena a = scratch();
-      FF_HIP(tall_qr<T>(region2, n, l, n, W, n, L, ldl, true, a, err, d, s, side->fork));
+      // Qhat1 (n x l) in natural row order, then V = Pi Qhat1 by a row
+      // scatter.  As soon as L is written, a7 (Jacobi on L) runs on the side
+      // stream while Qhat1 is formed.
+      FF_HIP(tall_qr<T>(region2, n, l, n, Qhat, n, L, ldl, true, a_main, err, d, s, side->fork));
       FF_HIP(hipStreamWaitEvent(side->stream, side->fork, 0));
       const int svd_step = tm.begin(FFSRQR_STEP_SVD, side->stream);
+      Arena a = a_side;
       FF_HIP(jacobi_sigma<T>(L, l, ldl, sigma, a, err, d, side->stream, (int*)(err + 32)));
       tm.end(svd_step, side->stream);
       FF_HIP(hipEventRecord(side->join, side->stream));
-      FF_HIP(scatter_rows<T>(W, n, l, n, perm, V, ldv, s));
+      FF_HIP(scatter_rows<T>(Qhat, n, l, n, perm, V, ldv, s));
     }
     tm.end(lq_step, s);
     FF_HIP(hipStreamWaitEvent(s, side->join, 0));
