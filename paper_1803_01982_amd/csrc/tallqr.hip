@@ -561,16 +561,16 @@ __device__ inline double readlane_d(double v, int l) {
 // m_k = 0 (the reflector is the identity).  One wave per column (four per
 // workgroup, one per SIMD), lane l holding r_i for the rows i = l + 64 u;
 // m_k is broadcast by a lane read, so the steps need no workgroup barrier.
-// The columns k of striu(S) come through LDS in blocks of WM_SB, loaded by
-// the whole workgroup with all loads in flight together.
-constexpr int WM_NT = 256, WM_SB = 16;
+// The columns k of striu(S) come through LDS in blocks of sb (32, or 16 for
+// c > 512), loaded by the whole workgroup with all loads in flight together.
+constexpr int WM_NT = 256;
 
 template <typename T, int RPL>
-__global__ __launch_bounds__(WM_NT) void wy_m_kernel(const T* __restrict__ P, int c, int64_t ldp,
+__global__ __launch_bounds__(WM_NT) void wy_m_kernel(const T* __restrict__ P, int c, int64_t ldp, int sb,
                                                      const double* __restrict__ S, const double* __restrict__ taus,
                                                      double* __restrict__ mt, double* __restrict__ sgn) {
-  extern __shared__ double Sb[];  // [WM_SB][c]: Sb[kk][i] = S(i, K WM_SB + kk), i < K WM_SB + kk
-  constexpr int NWV = WM_NT / 64, FB = 16;
+  extern __shared__ double Sb[];  // [sb][c]: Sb[kk][i] = S(i, K sb + kk), i < K sb + kk
+  constexpr int NWV = WM_NT / 64, FB = 40;  // one batch of loads per block for c <= 320
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int j = blockIdx.x * NWV + wave;
   const bool live = j < c;
@@ -582,14 +582,14 @@ __global__ __launch_bounds__(WM_NT) void wy_m_kernel(const T* __restrict__ P, in
     r[u] = (live && i <= j) ? yload(P, ldp, j, i) : 0.0;
     tr[u] = i < c ? taus[i] : 0.0;
   }
-  const int nblk = jmax / WM_SB + 1, ne = WM_SB * c;
+  const int nblk = jmax / sb + 1, ne = sb * c;
   for (int K = nblk - 1; K >= 0; --K) {
     __syncthreads();  // the previous block is no longer read
     for (int e0 = 0; e0 < ne; e0 += WM_NT * FB) {
       double pf[FB];
 #pragma unroll
       for (int x = 0; x < FB; ++x) {
-        const int e = e0 + tid + WM_NT * x, kk = e / c, i = e - kk * c, k = K * WM_SB + kk;
+        const int e = e0 + tid + WM_NT * x, kk = e / c, i = e - kk * c, k = K * sb + kk;
         pf[x] = (e < ne && k <= jmax && i < k) ? S[(int64_t)k * c + i] : 0.0;
       }
 #pragma unroll
@@ -600,8 +600,8 @@ __global__ __launch_bounds__(WM_NT) void wy_m_kernel(const T* __restrict__ P, in
     }
     __syncthreads();
     if (!live) continue;
-    for (int kk = WM_SB - 1; kk >= 0; --kk) {
-      const int k = K * WM_SB + kk;
+    for (int kk = sb - 1; kk >= 0; --kk) {
+      const int k = K * sb + kk;
       if (k > j) continue;
       const int ku = k >> 6, kl = k & 63;
       double rk = 0.0, tk = 0.0;
@@ -612,9 +612,9 @@ __global__ __launch_bounds__(WM_NT) void wy_m_kernel(const T* __restrict__ P, in
           tk = tr[u];
         }
       const double mk = readlane_d(rk, kl) * readlane_d(tk, kl);
-      double sv[RPL];
+      double sv[RPL];  // unconditional (clamped) reads, issued together
 #pragma unroll
-      for (int u = 0; u < RPL; ++u) sv[u] = (64 * u <= k) ? Sb[kk * c + min(lane + 64 * u, c - 1)] : 0.0;
+      for (int u = 0; u < RPL; ++u) sv[u] = Sb[kk * c + min(lane + 64 * u, c - 1)];
 #pragma unroll
       for (int u = 0; u < RPL; ++u) {
         const int i = lane + 64 * u;
@@ -816,7 +816,8 @@ hipError_t tall_qr(T* P, int64_t mrows, int64_t c, int64_t ldp, T* Qout, int64_t
   gram_y_kernel<T><<<dim3((unsigned)(nt * (nt + 1) / 2), (unsigned)nsplit), 256, 0, s>>>(P, mrows, ci, ldp, chunk,
                                                                                         spart);
   gram_sum_kernel<<<(unsigned)((c * c + 255) / 256), 256, 0, s>>>(spart, nsplit, ci, S);
-  const size_t mlds = (size_t)WM_SB * ci * sizeof(double);
+  int msb = ci <= 512 ? 32 : 16;
+  const size_t mlds = (size_t)msb * ci * sizeof(double);
   const unsigned mgrid = (unsigned)((c + WM_NT / 64 - 1) / (WM_NT / 64));
   const void* mfn = ci <= 64    ? (const void*)wy_m_kernel<T, 1>
                     : ci <= 128 ? (const void*)wy_m_kernel<T, 2>
@@ -829,7 +830,7 @@ hipError_t tall_qr(T* P, int64_t mrows, int64_t c, int64_t ldp, T* Qout, int64_t
   }
   const double* taus_c = sl.taus;
   const double* S_c = S;
-  void* margs[] = {(void*)&P, (void*)&ci, (void*)&ldp, (void*)&S_c, (void*)&taus_c, (void*)&mt, (void*)&sgn};
+  void* margs[] = {(void*)&P, (void*)&ci, (void*)&ldp, (void*)&msb, (void*)&S_c, (void*)&taus_c, (void*)&mt, (void*)&sgn};
   e = hipLaunchKernel(mfn, dim3(mgrid), dim3(WM_NT), margs, mlds, s);
   if (e != hipSuccess) return e;
   dim3 grid((unsigned)((mrows + WY_T - 1) / WY_T), (unsigned)nt);
