@@ -48,6 +48,25 @@ def timed_solves(ff, torch, A, w, steps, warmup):
     return out, (t1 - t0), prof
 
 
+def gemm_traffic(w, prec):
+    """HBM bytes per GEMM launch from the committed rocprofv3 counter summary
+    (profiles/gemm_tall_mid_fp64_pmc.json), or None when the summary is for
+    another kernel or workload, or the kernel source has changed since."""
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(here, "profiles", "gemm_tall_mid_fp64_pmc.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+        with open(os.path.join(here, d["source_file"]), "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, KeyError, ValueError):
+        return None
+    if sha != d.get("source_sha256") or prec != "fp64" or w.name != "mid":
+        return None
+    return int(d["bytes_per_launch"])
+
+
 def gemm_roofline(prof, w, prec):
     # the sketch (B = Omega A) and the projection (W = Q1^T A) are launches of
     # the same MFMA GEMM (for l <= 288 the tall-tile kernel, K split over two
@@ -61,7 +80,7 @@ def gemm_roofline(prof, w, prec):
     flop = 2.0 * w.l * w.m * w.n
     achieved = flop / avg_s / 1e12
     return {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK[prec], "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK[prec], 4), "traffic": None,
+            "frac": round(achieved / PEAK[prec], 4), "traffic": gemm_traffic(w, prec),
             "kernel": (f"gemm_tall_kernel<{'double' if prec == 'fp64' else 'float'}, {(w.l + 15) // 16}> + splitk_reduce"
                        if w.l <= 288 else f"gemm_tn_kernel<{'double' if prec == 'fp64' else 'float'}>"),
             "flop_per_launch": flop, "avg_launch_ms": round(avg_s * 1e3, 4), "launches": n_launch}

@@ -111,8 +111,12 @@ def test_swap_cap(ff):
     assert out.info["flags"] & 2
 
 
+# (1500, 1200, 290, 10): l = 300 > 288 takes the general kernels (LDS QRCP,
+# 64 x 64 GEMM tiles); (20000, 3000, 100, 8): row blocks of 256 rows in the
+# panel QR and the register QRCP at l = 108
 @pytest.mark.parametrize("m,n,k,p", [(300, 200, 150, 50), (200, 300, 10, 5), (50, 400, 7, 3), (400, 33, 5, 2),
-                                     (70, 70, 1, 0), (64, 1, 1, 0), (1, 64, 1, 0), (257, 129, 16, 16)])
+                                     (70, 70, 1, 0), (64, 1, 1, 0), (1, 64, 1, 0), (257, 129, 16, 16),
+                                     (1500, 1200, 290, 10), (20000, 3000, 100, 8)])
 def test_shapes(ff, m, n, k, p):
     announce(f"factor shape m={m} n={n} k={k} p={p}")
     r = min(m, n)
