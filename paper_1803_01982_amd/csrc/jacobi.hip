@@ -12,7 +12,9 @@
 // rotates bs disjoint column pairs (p, q) at once, updating H <- R^T H R and
 // the accumulated J <- J R (the annihilated entry set to zero, the two
 // diagonal entries to a - t h and b + t h); finally the columns are replaced
-// by C J (FP64 MFMA) in global memory.  The inner rounds take the cross
+// by C J (FP64 MFMA) in global memory.  Inside a workgroup the inner rounds
+// are pipelined: wave 0 chooses the rotations of round ir + 1 while the
+// other waves apply round ir to H and J.  The inner rounds take the cross
 // pairs (one column of each block); in the first round of a sweep they take
 // every pair of the union, which covers the pairs inside each block once per
 // sweep.  H is recomputed from the columns at every round, so the rounding
@@ -31,9 +33,10 @@ namespace ffsrqr {
 
 namespace {
 
-constexpr int NT = 1024;
+constexpr int NT = 512;
 constexpr int NW = NT / kWave;
-constexpr int GW = 32;  // stride of the Gram and rotation arrays (2 bs <= GW)
+constexpr int GW = 32;  // order of the Gram and rotation arrays (2 bs <= GW)
+constexpr int GS = 40;  // their row stride in LDS (rows land 16 banks apart)
 constexpr double kTol = 1e-14;
 constexpr double kSettled = 1e-8;  // a sweep with no larger rotation ends the iteration
 constexpr int kMaxSweeps = 60;
@@ -41,6 +44,15 @@ constexpr int kMaxSweeps = 60;
 __device__ inline int rr_player(int pos, int r, int P) {
   // circle method: position 0 fixed, positions 1..P-1 rotate by r
   return pos == 0 ? 0 : ((pos - 1 + r) % (P - 1)) + 1;
+}
+
+// Entry (i, j) of R^T H R when column k of R holds alpha_k at row k and
+// beta_k at the row of its partner: ai, bi and aj, bj for columns i and j,
+// hij = H(i, j), hipj = H(i, partner j), hpij = H(partner i, j),
+// hpipj = H(partner i, partner j).
+__device__ inline double rot_entry(double ai, double bi, double aj, double bj, double hij, double hipj, double hpij,
+                                   double hpipj) {
+  return fma(bi, fma(bj, hpipj, aj * hpij), ai * fma(bj, hipj, aj * hij));
 }
 
 // 1 / sqrt(x) for x > 0: the hardware estimate (about 24 correct bits)
@@ -80,8 +92,8 @@ __device__ inline void jacobi_rotation(double a, double b, double h, double& cs,
 }
 
 // Dynamic LDS: C (ncol columns of ldc rows; rows >= l and columns >= 2 bs stay
-// zero), then H[2][GW * GW] and J[2][GW * GW] (double buffers), then the
-// partial Gram sums of the row quarters 1..3 (3 x 3 x 256).
+// zero), then H and J (GW rows of stride GS each), then the partial Gram sums
+// of the row quarters 1..3 (3 x 3 x 256).
 template <typename T>
 __global__ __launch_bounds__(NT) void jacobi_kernel(const T* __restrict__ L, int l, int64_t ldl, double* __restrict__ M,
                                                     int bs, int P, int ldc, int ncol, unsigned* __restrict__ rot,
@@ -91,18 +103,15 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(const T* __restrict__ L, int
   extern __shared__ double smem[];
   double* C = smem;
   double* H0 = C + (size_t)ncol * ldc;
-  double* H1 = H0 + GW * GW;
-  double* J0 = H1 + GW * GW;
-  double* J1 = J0 + GW * GW;
-  double* Pg = J1 + GW * GW;
-  __shared__ double s_al[GW], s_be[GW], s_dn[GW];
-  __shared__ int s_rt[GW];
+  double* H1 = H0 + GW * GS;
+  double* J0 = H1 + GW * GS;
+  double* Pg = J0 + GW * GS;
+  __shared__ double2 s_ab[2][GW];  // (alpha, beta) of column k: c_k <- alpha c_k + beta c_partner
+  __shared__ double s_dn[2][GW];   // the diagonal entry of H for column k after the rotation
   __shared__ int s_sweep;  // a pair with |h_pq| > kSettled sqrt(h_pp h_qq) was rotated this sweep
-  __shared__ int s_round, s_inner[2];
+  __shared__ int s_round;
   __shared__ unsigned short sched_full[31 * 16];
-  __shared__ unsigned short sched_cross[16 * 16];
   __shared__ unsigned char part_full[31 * GW];
-  __shared__ unsigned char part_cross[16 * GW];
   const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int W2 = 2 * bs, nct = ncol / 16;
@@ -112,15 +121,16 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(const T* __restrict__ L, int
     const int64_t r = e % l, c = e / l;
     M[c * l + r] = (double)L[c * ldl + r];
   }
-  for (int e = tid; e < ncol * ldc + 4 * GW * GW; e += NT) smem[e] = 0.0;  // C, H and J
+  for (int e = tid; e < ncol * ldc + 3 * GW * GS; e += NT) smem[e] = 0.0;  // C, H and J
   if (g == 0 && tid < 3) rot[tid] = 0u;
   if (!grid_barrier(gs, epoch)) return;
 
-  // pair schedules of the local columns, built once:
+  // pair schedules of the local columns:
   //   full: all W2(W2-1)/2 pairs of the union in W2-1 rounds of bs disjoint
-  //         pairs (circle method), used in the first round of every sweep;
-  //   cross: the bs*bs pairs (block a, block b) in bs rounds (p, bs + (p+r) % bs).
-  // part_*[ir][k] is the partner of local column k in inner round ir.
+  //         pairs (circle method), used in the first round of every sweep,
+  //         built once as a table;
+  //   cross: the bs*bs pairs (block a, block b) in bs rounds (p, bs + (p+r) % bs),
+  //         computed where they are used.
   for (int e = tid; e < (W2 - 1) * bs; e += NT) {
     const int ir = e / bs, pr = e % bs;
     const int p = rr_player(pr, ir, W2), q = rr_player(W2 - 1 - pr, ir, W2);
@@ -128,20 +138,18 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(const T* __restrict__ L, int
     part_full[ir * GW + p] = (unsigned char)q;
     part_full[ir * GW + q] = (unsigned char)p;
   }
-  for (int e = tid; e < bs * bs; e += NT) {
-    const int ir = e / bs, p = e % bs, q = bs + (p + ir) % bs;
-    sched_cross[e] = (unsigned short)((p << 8) | q);
-    part_cross[ir * GW + p] = (unsigned char)q;
-    part_cross[ir * GW + q] = (unsigned char)p;
-  }
-  // this thread's entry of the GW x GW arrays
-  const int ei = tid / GW, ej = tid % GW;
-  const bool own = ei < W2 && ej < W2;
+  // work of the update waves in the inner rounds: H block (pair hb_p1,
+  // pair hb_p2) for threads 0..bs*bs-1 of waves 1..; J entries of pair jb_pi
+  // in rows jb_r0 + jb_rs t for the threads from 256 on
+  const int ut = tid - kWave;
+  const bool hb_ok = ut >= 0 && ut < bs * bs;
+  const int hb_p1 = hb_ok ? ut / bs : 0, hb_p2 = hb_ok ? ut % bs : 0;
+  const int jt = tid - kWave - 256, jb_rs = (NT - kWave - 256) / bs;
+  const bool jb_ok = jt >= 0 && jt < jb_rs * bs;
+  const int jb_pi = jb_ok ? jt % bs : 0, jb_r0 = jb_ok ? jt / bs : 0;
   // Gram tiles: t = 0 -> (0,0), 1 -> (0,1), 2 -> (1,1); four quarters of the rows
   const int ntile = nct * (nct + 1) / 2;
   const int kq = ((l + 15) & ~15) / 4;
-  const int gt = wave % ntile, gh = wave / ntile;
-  const int gtr = (gt == 2) ? 1 : 0, gtc = (gt == 0) ? 0 : 1;
   __syncthreads();
 
   int sweep = 0;
@@ -158,16 +166,12 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(const T* __restrict__ L, int
       auto gcol = [&](int k) -> int {
         return k < bs ? (k < na ? ca0 + k : -1) : (k < W2 && k - bs < nbk ? cb0 + k - bs : -1);
       };
-      if (tid == 0) {
-        s_round = 0;
-        s_inner[0] = 0;
-        s_inner[1] = 0;
-      }
-      // load: wave w takes local columns w and w + NW, all loads in flight together
+      if (tid == 0) s_round = 0;
+      // load: wave w takes local columns w + kk NW, all loads in flight together
       for (int i0 = 0; i0 < l; i0 += 64 * 8) {
-        double v[2][8];
+        double v[GW / NW][8];
 #pragma unroll
-        for (int kk = 0; kk < 2; ++kk) {
+        for (int kk = 0; kk < GW / NW; ++kk) {
           const int k = wave + kk * NW;
           const int gc = gcol(k);
 #pragma unroll
@@ -177,7 +181,7 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(const T* __restrict__ L, int
           }
         }
 #pragma unroll
-        for (int kk = 0; kk < 2; ++kk) {
+        for (int kk = 0; kk < GW / NW; ++kk) {
           const int k = wave + kk * NW;
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
@@ -187,10 +191,15 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(const T* __restrict__ L, int
         }
       }
       __syncthreads();
-      // Gram H = C^T C of the local columns: wave (tile gt, row quarter gh)
-      typename MF::acc4 acc = {0.0, 0.0, 0.0, 0.0};
-      if (gh < 4) {
-        typename MF::acc4 acc1 = {0.0, 0.0, 0.0, 0.0};
+      // Gram H = C^T C of the local columns: task (tile gt, row quarter gh),
+      // task = gt + 3 gh taken by wave task % NW; the quarter-0 sums stay in
+      // the registers of waves 0..2, the others go through Pg
+      typename MF::acc4 acc0 = {0.0, 0.0, 0.0, 0.0};
+      for (int task = wave; task < 12; task += NW) {
+        const int gt = task % 3, gh = task / 3;
+        if (gt >= ntile) continue;
+        const int gtr = (gt == 2) ? 1 : 0, gtc = (gt == 0) ? 0 : 1;
+        typename MF::acc4 acc = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
         const int klo = gh * kq, khi = klo + kq;
         const double* ca = C + (gtr * 16 + (lane & 15)) * ldc + (lane >> 4);
         const double* cb = C + (gtc * 16 + (lane & 15)) * ldc + (lane >> 4);
@@ -205,81 +214,145 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(const T* __restrict__ L, int
         }
         for (; k0 < khi; k0 += 4) acc = MF::fma(ca[k0], cb[k0], acc);
         acc = acc + acc1;
-        if (gh > 0)
+        if (gh == 0) {
+          acc0 = acc;
+        } else {
 #pragma unroll
           for (int q = 0; q < 4; ++q) Pg[(gh - 1) * 768 + gt * 256 + q * 64 + lane] = acc[q];
+        }
       }
       __syncthreads();
-      if (gh == 0) {
+      if (wave < ntile) {
+        const int gt = wave, gtr = (gt == 2) ? 1 : 0, gtc = (gt == 0) ? 0 : 1;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int o = gt * 256 + q * 64 + lane;
-          const double v = ((acc[q] + Pg[o]) + Pg[768 + o]) + Pg[1536 + o];
+          const double v = ((acc0[q] + Pg[o]) + Pg[768 + o]) + Pg[1536 + o];
           const int i = gtr * 16 + MF::row(lane, q), j = gtc * 16 + (lane & 15);
           if (gtr != gtc || i <= j) {
-            H0[i * GW + j] = v;
-            H0[j * GW + i] = v;
+            H0[i * GS + j] = v;
+            H0[j * GS + i] = v;
           }
         }
       }
-      J0[tid] = (ei == ej && ei < W2) ? 1.0 : 0.0;
+      for (int e = tid; e < GW * GW; e += NT) {
+        const int ei = e / GW, ej = e % GW;
+        J0[ei * GS + ej] = (ei == ej && ei < W2) ? 1.0 : 0.0;
+      }
       __syncthreads();
       // skip the round when no scheduled pair needs a rotation
       const bool full = (r == 0);
       int need = 0;
-      if (own && (full ? ei < ej : (ei < bs && ej >= bs))) {
-        const double a = H0[ei * GW + ei], b = H0[ej * GW + ej], hg = H0[ei * GW + ej];
-        need = !(a == 0.0 || b == 0.0 || hg * hg <= (kTol * kTol) * (a * b));
+      for (int e = tid; e < W2 * W2; e += NT) {
+        const int ei = e / W2, ej = e % W2;
+        if (full ? ei < ej : (ei < bs && ej >= bs)) {
+          const double a = H0[ei * GS + ei], b = H0[ej * GS + ej], hg = H0[ei * GS + ej];
+          need |= !(a == 0.0 || b == 0.0 || hg * hg <= (kTol * kTol) * (a * b)) ? 1 : 0;
+        }
       }
       const int nir = __syncthreads_or(need) ? (full ? W2 - 1 : bs) : 0;
-      const unsigned short* sched = full ? sched_full : sched_cross;
-      const unsigned char* part = full ? part_full : part_cross;
-      // inner rounds on the Gram matrix
-      for (int ir = 0; ir < nir; ++ir) {
-        // this thread's operands, read while the rotations are being chosen
-        const int pi = own ? part[ir * GW + ei] : 0, pj = own ? part[ir * GW + ej] : 0;
-        double hij = 0.0, hipj = 0.0, hpij = 0.0, hpipj = 0.0, jij = 0.0, jipj = 0.0;
-        if (own) {
-          hij = H0[ei * GW + ej];
-          hipj = H0[ei * GW + pj];
-          hpij = H0[pi * GW + ej];
-          hpipj = H0[pi * GW + pj];
-          jij = J0[ei * GW + ej];
-          jipj = J0[ei * GW + pj];
+      // inner rounds on the Gram matrix.  Round ir rotates the scheduled pairs
+      // with (alpha, beta) of every column in s_ab[ir & 1] and the new
+      // diagonal entries in s_dn[ir & 1].  In the iteration of round ir,
+      // waves 1.. apply it to H (from one buffer into the other) and to J,
+      // while wave 0 already chooses the rotations of round ir + 1: of H after
+      // round ir it needs two new diagonal entries and one entry given by the
+      // same expression the update evaluates.  One workgroup barrier per round.
+      auto pair_of = [&](int P, int ir) -> unsigned {
+        if (full) return sched_full[ir * bs + P];
+        int q = P + ir;
+        if (q >= bs) q -= bs;
+        return (unsigned)((P << 8) | (bs + q));
+      };
+      auto partner = [&](int k, int ir) -> int {
+        if (full) return part_full[ir * GW + k];
+        int q = k < bs ? k + ir : k - bs - ir;
+        if (k < bs) return bs + (q >= bs ? q - bs : q);
+        return q < 0 ? q + bs : q;
+      };
+      int rot_acc = 0, big_acc = 0;
+      auto choose_rot = [&](int p, int q, double a, double b, double hg, int buf) {
+        if (a == 0.0 || b == 0.0 || hg * hg <= (kTol * kTol) * (a * b)) {
+          s_ab[buf][p] = make_double2(1.0, 0.0);
+          s_ab[buf][q] = make_double2(1.0, 0.0);
+          s_dn[buf][p] = a;
+          s_dn[buf][q] = b;
+        } else {
+          double cs, sn, tt;
+          jacobi_rotation(a, b, hg, cs, sn, tt);
+          s_ab[buf][p] = make_double2(cs, -sn);
+          s_ab[buf][q] = make_double2(cs, sn);
+          s_dn[buf][p] = a - tt * hg;
+          s_dn[buf][q] = b + tt * hg;
+          rot_acc = 1;
+          if (hg * hg > (kSettled * kSettled) * (a * b)) big_acc = 1;
         }
-        if (tid < bs) {
-          const unsigned pq = sched[ir * bs + tid];
-          const int p = (int)(pq >> 8), q = (int)(pq & 255u);
-          const double a = H0[p * GW + p], b = H0[q * GW + q], hg = H0[p * GW + q];
-          if (a == 0.0 || b == 0.0 || hg * hg <= (kTol * kTol) * (a * b)) {
-            s_al[p] = 1.0; s_be[p] = 0.0; s_dn[p] = a; s_rt[p] = 0;
-            s_al[q] = 1.0; s_be[q] = 0.0; s_dn[q] = b; s_rt[q] = 0;
-          } else {
-            double cs, sn, tt;
-            jacobi_rotation(a, b, hg, cs, sn, tt);
-            s_al[p] = cs; s_be[p] = -sn; s_dn[p] = a - tt * hg; s_rt[p] = 1;
-            s_al[q] = cs; s_be[q] = sn; s_dn[q] = b + tt * hg; s_rt[q] = 1;
-            s_inner[ir & 1] = 1;
-            s_round = 1;
-            if (hg * hg > (kSettled * kSettled) * (a * b)) s_sweep = 1;
+      };
+      if (nir > 0 && wave == 0 && lane < bs) {
+        const unsigned pq = pair_of(lane, 0);
+        const int p = (int)(pq >> 8), q = (int)(pq & 255u);
+        choose_rot(p, q, H0[p * GS + p], H0[q * GS + q], H0[p * GS + q], 0);
+      }
+      __syncthreads();
+      for (int ir = 0; ir < nir; ++ir) {
+        const double* Hc = (ir & 1) ? H1 : H0;
+        double* Hn = (ir & 1) ? H0 : H1;
+        const double2* ab = s_ab[ir & 1];
+        const double* dn = s_dn[ir & 1];
+        const bool last = ir + 1 == nir;
+        if (wave == 0) {
+          if (!last && lane < bs) {
+            const unsigned pq = pair_of(lane, ir + 1);
+            const int p = (int)(pq >> 8), q = (int)(pq & 255u);
+            const int x = partner(p, ir), y = partner(q, ir);
+            const double hpq = Hc[p * GS + q], hpy = Hc[p * GS + y], hxq = Hc[x * GS + q], hxy = Hc[x * GS + y];
+            const double2 fp = ab[p], fq = ab[q];
+            const double hg = rot_entry(fp.x, fp.y, fq.x, fq.y, hpq, hpy, hxq, hxy);
+            choose_rot(p, q, dn[p], dn[q], hg, (ir + 1) & 1);
+          }
+        } else {
+          if (!last && hb_ok) {
+            const unsigned u1 = pair_of(hb_p1, ir), u2 = pair_of(hb_p2, ir);
+            const int p1 = (int)(u1 >> 8), q1 = (int)(u1 & 255u), p2 = (int)(u2 >> 8), q2 = (int)(u2 & 255u);
+            if (hb_p1 == hb_p2) {
+              // the rotated pair itself: new diagonal entries, the annihilated entry
+              const double off = ab[p1].y != 0.0 ? 0.0 : Hc[p1 * GS + q1];
+              Hn[p1 * GS + p1] = dn[p1];
+              Hn[q1 * GS + q1] = dn[q1];
+              Hn[p1 * GS + q1] = off;
+              Hn[q1 * GS + p1] = off;
+            } else {
+              const double h00 = Hc[p1 * GS + p2], h01 = Hc[p1 * GS + q2];
+              const double h10 = Hc[q1 * GS + p2], h11 = Hc[q1 * GS + q2];
+              const double2 f1 = ab[p1], g1 = ab[q1], f2 = ab[p2], g2 = ab[q2];
+              Hn[p1 * GS + p2] = rot_entry(f1.x, f1.y, f2.x, f2.y, h00, h01, h10, h11);
+              Hn[p1 * GS + q2] = rot_entry(f1.x, f1.y, g2.x, g2.y, h01, h00, h11, h10);
+              Hn[q1 * GS + p2] = rot_entry(g1.x, g1.y, f2.x, f2.y, h10, h11, h00, h01);
+              Hn[q1 * GS + q2] = rot_entry(g1.x, g1.y, g2.x, g2.y, h11, h10, h01, h00);
+            }
+          }
+          if (jb_ok) {
+            // J <- J R on rows jb_r0 + jb_rs t, columns of pair jb_pi
+            const unsigned u = pair_of(jb_pi, ir);
+            const int p = (int)(u >> 8), q = (int)(u & 255u);
+            const double2 fp = ab[p], fq = ab[q];
+            for (int i = jb_r0; i < W2; i += jb_rs) {
+              const double jp = J0[i * GS + p], jq = J0[i * GS + q];
+              J0[i * GS + p] = fma(fp.y, jq, fp.x * jp);
+              J0[i * GS + q] = fma(fq.y, jp, fq.x * jq);
+            }
           }
         }
-        if (tid == 0) s_inner[(ir + 1) & 1] = 0;
         __syncthreads();
-        if (!s_inner[ir & 1]) continue;  // uniform: nothing rotated in this inner round
-        if (own) {
-          const double ai = s_al[ei], bi = s_be[ei], aj = s_al[ej], bj = s_be[ej];
-          double v;
-          if (ei == ej) v = s_dn[ei];
-          else if (pj == ei && s_rt[ej]) v = 0.0;  // the pair annihilated in this inner round
-          else v = ai * (aj * hij + bj * hipj) + bi * (aj * hpij + bj * hpipj);
-          if (ir + 1 < nir) H1[ei * GW + ej] = v;
-          J1[ei * GW + ej] = aj * jij + bj * jipj;
-        }
-        __syncthreads();
-        double* x = H0; H0 = H1; H1 = x;
-        x = J0; J0 = J1; J1 = x;
       }
+      if (nir > 0 && wave == 0) {
+        const bool any_rot = __any(rot_acc), any_big = __any(big_acc);
+        if (lane == 0) {
+          s_round = any_rot ? 1 : 0;
+          if (any_big) s_sweep = 1;
+        }
+      }
+      __syncthreads();
       // columns <- C J, written straight to M (transposed product J^T C^T, so
       // each MFMA result row is a run of 16 consecutive entries of a column);
       // a wave takes a 16-row slice of the columns for both column tiles
@@ -287,7 +360,7 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(const T* __restrict__ L, int
         const int nit = (l + 15) / 16;
         for (int it = wave; it < nit; it += NW) {
           typename MF::acc4 d0 = {0.0, 0.0, 0.0, 0.0}, d1 = {0.0, 0.0, 0.0, 0.0};
-          const double* ja = J0 + (lane >> 4) * GW + (lane & 15);
+          const double* ja = J0 + (lane >> 4) * GS + (lane & 15);
           const double* cbp = C + (lane >> 4) * ldc + it * 16 + (lane & 15);
           if (nct == 2) {
 #pragma unroll
@@ -296,8 +369,8 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(const T* __restrict__ L, int
 #pragma unroll
               for (int s = 0; s < 4; ++s) {
                 bv[s] = cbp[4 * (hs + s) * ldc];
-                av0[s] = ja[4 * (hs + s) * GW];
-                av1[s] = ja[4 * (hs + s) * GW + 16];
+                av0[s] = ja[4 * (hs + s) * GS];
+                av1[s] = ja[4 * (hs + s) * GS + 16];
               }
 #pragma unroll
               for (int s = 0; s < 4; ++s) {
@@ -307,7 +380,7 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(const T* __restrict__ L, int
             }
           } else {
 #pragma unroll
-            for (int s = 0; s < 4; ++s) d0 = MF::fma(ja[4 * s * GW], cbp[4 * s * ldc], d0);
+            for (int s = 0; s < 4; ++s) d0 = MF::fma(ja[4 * s * GS], cbp[4 * s * ldc], d0);
           }
           const int i = it * 16 + (lane & 15);
 #pragma unroll
@@ -360,7 +433,7 @@ __global__ void sort_desc(const double* __restrict__ in, int l, double* __restri
 bool choose(int64_t l, const DeviceInfo& d, int* bs, int* P, int* ldc, int* ncol, size_t* lds) {
   const int ld = (int)(((l + 15) & ~(int64_t)15) + 1);
   auto bytes = [&](int b) {
-    return ((size_t)((2 * b + 15) / 16 * 16) * ld + 4 * GW * GW + 3 * 768) * sizeof(double);
+    return ((size_t)((2 * b + 15) / 16 * 16) * ld + 3 * GW * GS + 3 * 768) * sizeof(double);
   };
   int b = 16;
   if (d.lds_max != 0 && bytes(b) + 4096 > d.lds_max) b = 8;  // 16 local columns
