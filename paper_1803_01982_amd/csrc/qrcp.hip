@@ -17,7 +17,8 @@
 //      scratch over rows j+1..l-1 (the same definition as the oracle; no
 //      downdating drift to guard against).
 // Candidate slots are double-buffered by step parity, so one barrier per
-// step suffices.
+// step suffices.  The register-resident variant below (l <= 288) replaces
+// the barrier by write-once slots per step.
 #include <algorithm>
 
 #include "common.hpp"
@@ -226,27 +227,60 @@ __global__ __launch_bounds__(NT) void qrcp_kernel(const T* __restrict__ B, int64
 // Register-resident variant for l <= 16 NR: sixteen threads per column, each
 // holding rows q, q + 16, ... of its column (and of CB columns in all) in
 // registers, so that the update and the norm recomputation of a step touch
-// no LDS except the broadcast reflector.  Per step:
+// no LDS except the broadcast reflector.
+//
+// The workgroups exchange their candidates through slots that exist once per
+// step and workgroup, are filled with kVoid before the launch and are written
+// exactly once (relaxed agent-scope atomics): a slot that no longer holds
+// kVoid holds its final value, so a reader needs neither a grid barrier nor a
+// fence, only a bounded poll.  Per step:
 //   1. every wave merges the top-2 of its four column groups and posts it to
-//      LDS; after one workgroup barrier every wave merges the sixteen posts,
-//      so the owner of the local winner writes its column to the slot without
-//      a further barrier, and wave 0 posts the candidate;
-//   2. one grid barrier;
-//   3. wave 0 merges the candidates (fixed order), reads the winner's rows
-//      j..l-1, builds the reflector (LAPACK xLARFG convention) and
-//      broadcasts it through LDS (one workgroup barrier);
-//   4. every active column is updated and its residual norm over rows
+//      LDS; after one workgroup barrier every wave merges the sixteen posts;
+//      the owner of the local winner writes the column's rows j..l-1 to its
+//      column slot and wave 0 the candidate (best norm, runner-up, index);
+//   2. wave 0 polls the candidate slots of the step until every workgroup's
+//      is there, merges them (fixed order, so every workgroup takes the same
+//      winner), polls the winner's column slot, builds the reflector (LAPACK
+//      xLARFG convention) and broadcasts it through LDS;
+//   3. every active column is updated and its residual norm over rows
 //      j+1..l-1 recomputed from scratch (sums over the 16 lanes of its group).
+// A poll past the spin limit raises `error` and ends the workgroup; the
+// others see the error word within their own bounded polls.
+constexpr uint64_t kVoid = 0xFFF4DEADBEEF0001ull;  // a signalling NaN with a payload
+
+struct QrcpPost {
+  uint64_t* cand;  // [3][l][G]: best norm, runner-up norm, best index
+  uint64_t* col;   // rows j..l-1 of the best column of (j, g) at tri(j) G + g (l - j)
+};
+
+// Rows of the column slots of the steps before j: sum over j' < j of (l - j').
+__device__ inline int64_t tri_rows(int j, int l) { return (int64_t)j * l - (int64_t)j * (j - 1) / 2; }
+
+__device__ inline void post_u64(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline uint64_t peek_u64(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// A double as slot bits; the (NaN) bit pattern kVoid is replaced by the default NaN.
+__device__ inline uint64_t slot_bits(double x) {
+  const uint64_t b = (uint64_t)__double_as_longlong(x);
+  return b == kVoid ? 0x7FF8000000000000ull : b;
+}
+__device__ inline double slot_double(uint64_t b) { return __longlong_as_double((long long)b); }
+
 template <typename T, int NR, int CB>
 __global__ __launch_bounds__(NT) void qrcp_reg_kernel(const T* __restrict__ B, int64_t ldb, int l, int64_t n,
-                                                      QrcpSlots sl, int64_t* __restrict__ piv,
-                                                      double* __restrict__ margins, GridSync gs) {
+                                                      QrcpPost post, int64_t* __restrict__ piv,
+                                                      double* __restrict__ margins, unsigned* __restrict__ error) {
   constexpr int TPC = 16, CPB = NT / TPC;  // threads per column, columns per batch
+  constexpr int GQ = kMaxGridBlocks / kWave;  // candidate slots per lane
   __shared__ double v[TPC * NR];
   __shared__ double s_tv1[NT / 64], s_tv2[NT / 64];
   __shared__ int64_t s_ti1[NT / 64];
   __shared__ double s_tau;
   __shared__ int64_t s_win;
+  __shared__ int s_abort;
   const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6, q = tid & (TPC - 1), cl = tid / TPC;
   const int64_t c0 = (int64_t)g * CPB * CB;
@@ -266,9 +300,8 @@ __global__ __launch_bounds__(NT) void qrcp_reg_kernel(const T* __restrict__ B, i
     }
     rn[b] = row16_sum(s2);
   }
-  unsigned epoch = 0;
+  if (tid == 0) s_abort = 0;
   for (int j = 0; j < l; ++j) {
-    const int par = j & 1;
     // ---- 1. local best and runner-up
     Top2 t{0.0, -1, -1.0};
 #pragma unroll
@@ -285,35 +318,58 @@ __global__ __launch_bounds__(NT) void qrcp_reg_kernel(const T* __restrict__ B, i
       s_tv2[wave] = t.v2;
     }
     __syncthreads();
+    const int64_t tb = tri_rows(j, l) * G;
     {
       static_assert(NT / 64 == 16, "one post per lane of the first row");
       Top2 u{0.0, -1, -1.0};
       if (lane < NT / 64) u = Top2{s_tv1[lane], s_ti1[lane], s_tv2[lane]};
       u = row16_top2(u);
       const int64_t bi = __shfl(u.i1, 0, kWave);
-      if (wave == 0 && lane == 0) {
-        sl.r[par * G + g] = u.v1;
-        sl.idx[par * G + g] = u.i1;
-        sl.r2[par * G + g] = u.v2;
-      }
       // the owner group of the local winner posts rows j..l-1 of its column
-      double* dst = sl.col + ((int64_t)par * G + g) * l;
+      uint64_t* dst = post.col + tb + (int64_t)g * (l - j) - j;
 #pragma unroll
       for (int b = 0; b < CB; ++b)
         if (bi >= 0 && col[b] == bi)
 #pragma unroll
           for (int s = 0; s < NR; ++s) {
             const int i = q + TPC * s;
-            if (i >= j && i < l) dst[i] = x[b][s];
+            if (i >= j && i < l) post_u64(dst + i, slot_bits(x[b][s]));
           }
+      if (wave == 0 && lane == 0) {
+        post_u64(post.cand + (int64_t)j * G + g, slot_bits(u.v1));
+        post_u64(post.cand + ((int64_t)l + j) * G + g, slot_bits(u.v2));
+        post_u64(post.cand + (2 * (int64_t)l + j) * G + g, (uint64_t)u.i1);
+      }
     }
-    // ---- 2. exchange
-    if (!grid_barrier(gs, epoch)) return;
-    // ---- 3. global winner, its reflector (wave 0)
+    // ---- 2. global winner, its reflector (wave 0)
     if (wave == 0) {
       Top2 u{0.0, -1, -1.0};
-      for (int qq = lane; qq < G; qq += kWave)
-        u = top2_merge(u, Top2{sl.r[par * G + qq], sl.idx[par * G + qq], sl.r2[par * G + qq]});
+      bool ok = true;
+      unsigned spins = 0;
+      for (;;) {
+        bool here = true;
+        u = Top2{0.0, -1, -1.0};
+#pragma unroll
+        for (int k = 0; k < GQ; ++k) {
+          const int qq = lane + kWave * k;
+          if (qq < G) {
+            const uint64_t b1 = peek_u64(post.cand + (int64_t)j * G + qq);
+            const uint64_t b2 = peek_u64(post.cand + ((int64_t)l + j) * G + qq);
+            const uint64_t bi = peek_u64(post.cand + (2 * (int64_t)l + j) * G + qq);
+            here = here && b1 != kVoid && b2 != kVoid && bi != kVoid;
+            u = top2_merge(u, Top2{slot_double(b1), (int64_t)bi, slot_double(b2)});
+          }
+        }
+        if (__all(here)) break;
+        __builtin_amdgcn_s_sleep(1);
+        if ((++spins & 255u) == 0) {
+          const bool bad = __hip_atomic_load(error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
+          if (__any(bad) || spins > kSpinLimit) {
+            ok = false;
+            break;
+          }
+        }
+      }
       u = row16_top2(u);
 #pragma unroll
       for (int o = 16; o < 64; o <<= 1) {
@@ -321,7 +377,7 @@ __global__ __launch_bounds__(NT) void qrcp_reg_kernel(const T* __restrict__ B, i
         u = top2_merge(u, y);
       }
       const int64_t wi = __shfl(u.i1, 0, kWave);
-      if (lane == 0 && g == 0) {
+      if (ok && lane == 0 && g == 0) {
         piv[j] = wi;
         double mg;
         if (n - j <= 1) mg = 1.0;
@@ -329,43 +385,69 @@ __global__ __launch_bounds__(NT) void qrcp_reg_kernel(const T* __restrict__ B, i
         else mg = 0.0;
         margins[j] = mg;
       }
-      // the winner's rows j..l-1 (sent by the workgroup that owns it)
-      const int wg = (int)(wi / (CPB * CB));
-      const double* src = sl.col + ((int64_t)par * G + wg) * l;
-      double w[(TPC * NR + 63) / 64];
-      double xs = 0.0;
+      // the winner's rows j..l-1 (posted by the workgroup that owns it)
+      const int wg = ok && wi >= 0 ? (int)(wi / (CPB * CB)) : 0;
+      const uint64_t* src = post.col + tb + (int64_t)wg * (l - j) - j;
+      constexpr int WS = (TPC * NR + 63) / 64;
+      double w[WS];
+      for (spins = 0; ok;) {
+        bool here = true;
 #pragma unroll
-      for (int s = 0; s < (TPC * NR + 63) / 64; ++s) {
-        const int i = lane + 64 * s;
-        w[s] = (i >= j && i < l) ? src[i] : 0.0;
-        if (i > j) xs += w[s] * w[s];
+        for (int s = 0; s < WS; ++s) {
+          const int i = lane + 64 * s;
+          uint64_t bits = 0;
+          if (i >= j && i < l) {
+            bits = peek_u64(src + i);
+            here = here && bits != kVoid;
+          }
+          w[s] = slot_double(bits);
+        }
+        if (__all(here)) break;
+        __builtin_amdgcn_s_sleep(1);
+        if ((++spins & 255u) == 0) {
+          const bool bad = __hip_atomic_load(error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
+          if (__any(bad) || spins > kSpinLimit) ok = false;
+        }
       }
-      const double xnorm2 = wave_sum(xs);
-      const double x0 = __shfl(w[0], j & 63, kWave);  // row j is in register j / 64 of lane j % 64
-      double x0v = x0;
+      if (!ok) {
+        if (lane == 0) {
+          __hip_atomic_fetch_or(error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          s_abort = 1;
+        }
+      } else {
+        double xs = 0.0;
 #pragma unroll
-      for (int s = 1; s < (TPC * NR + 63) / 64; ++s) {
-        const double y = __shfl(w[s], j & 63, kWave);
-        if ((j >> 6) == s) x0v = y;
-      }
-      double tau = 0.0, scale = 0.0;
-      if (xnorm2 > 0.0) {
-        const double beta = -copysign(sqrt(x0v * x0v + xnorm2), x0v);
-        tau = (beta - x0v) / beta;
-        scale = 1.0 / (x0v - beta);
-      }
+        for (int s = 0; s < WS; ++s) {
+          const int i = lane + 64 * s;
+          if (i > j && i < l) xs += w[s] * w[s];
+        }
+        const double xnorm2 = wave_sum(xs);
+        double x0v = __shfl(w[0], j & 63, kWave);  // row j is in register j / 64 of lane j % 64
 #pragma unroll
-      for (int s = 0; s < (TPC * NR + 63) / 64; ++s) {
-        const int i = lane + 64 * s;
-        if (i < TPC * NR) v[i] = (i < j || i >= l) ? 0.0 : (i == j ? 1.0 : (tau != 0.0 ? w[s] * scale : w[s]));
-      }
-      if (lane == 0) {
-        s_tau = tau;
-        s_win = wi;
+        for (int s = 1; s < WS; ++s) {
+          const double y = __shfl(w[s], j & 63, kWave);
+          if ((j >> 6) == s) x0v = y;
+        }
+        double tau = 0.0, scale = 0.0;
+        if (xnorm2 > 0.0) {
+          const double beta = -copysign(sqrt(x0v * x0v + xnorm2), x0v);
+          tau = (beta - x0v) / beta;
+          scale = 1.0 / (x0v - beta);
+        }
+#pragma unroll
+        for (int s = 0; s < WS; ++s) {
+          const int i = lane + 64 * s;
+          if (i < TPC * NR) v[i] = (i < j || i >= l) ? 0.0 : (i == j ? 1.0 : (tau != 0.0 ? w[s] * scale : w[s]));
+        }
+        if (lane == 0) {
+          s_tau = tau;
+          s_win = wi;
+        }
       }
     }
     __syncthreads();
-    // ---- 4. update the active columns, recompute their residual norms
+    if (s_abort) return;
+    // ---- 3. update the active columns, recompute their residual norms
     const double tau = s_tau;
     const int64_t wi = s_win;
 #pragma unroll
@@ -390,6 +472,13 @@ __global__ __launch_bounds__(NT) void qrcp_reg_kernel(const T* __restrict__ B, i
     }
   }
 }
+
+__global__ void fill_u64(uint64_t* __restrict__ p, int64_t n, uint64_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+// Words of the candidate and column slots of the register variant.
+inline size_t post_words(int64_t l, int G) { return (size_t)G * (3 * l + l * (l + 1) / 2); }
 
 // Fewest workgroups whose column slices of B still fit in LDS: the per-step
 // grid barrier costs more with more workgroups, while the work per step is
@@ -454,8 +543,7 @@ size_t qrcp_scratch(int64_t l, int64_t n, const DeviceInfo& d) {
   choose(l, n, d.num_cu, d.lds_max, sizeof(T), &nc, &G, &in_lds, &lds);
   size_t b = (size_t)2 * G * (3 * sizeof(double) + l * sizeof(double)) + 4 * 256;
   if (!in_lds) b += (size_t)G * nc * ldbl_for(l, sizeof(T)) * sizeof(T) + 256;
-  if (reg_choice(l, n, d.num_cu, &NR, &CB, &Gr))
-    b = std::max(b, (size_t)2 * Gr * (3 * sizeof(double) + l * sizeof(double)) + 4 * 256);
+  if (reg_choice(l, n, d.num_cu, &NR, &CB, &Gr)) b = std::max(b, post_words(l, Gr) * sizeof(uint64_t) + 256);
   return b + kSyncWords * sizeof(unsigned) + 1024;
 }
 
@@ -465,21 +553,19 @@ hipError_t qrcp(const T* B, int64_t l, int64_t n, int64_t ldb, int64_t* piv, dou
   if (l <= 0) return hipSuccess;
   int NR, CB, Gr;
   if (reg_choice(l, n, d.num_cu, &NR, &CB, &Gr)) {
-    QrcpSlots sl;
-    sl.r = ar.take<double>(2 * Gr);
-    sl.r2 = ar.take<double>(2 * Gr);
-    sl.idx = ar.take<int64_t>(2 * Gr);
-    sl.col = ar.take<double>((size_t)2 * Gr * l);
-    unsigned* counter = ar.take<unsigned>(kSyncWords);
-    if (!sl.r || !sl.r2 || !sl.idx || !sl.col || !counter) return hipErrorOutOfMemory;
-    hipError_t e = zero_words(counter, kSyncWords, s);
-    if (e != hipSuccess) return e;
     if (Gr > kMaxGridBlocks) return hipErrorInvalidValue;
-    GridSync gs{counter, err, (unsigned)Gr};
+    const size_t words = post_words(l, Gr);
+    QrcpPost post;
+    post.cand = ar.take<uint64_t>(words);
+    if (!post.cand) return hipErrorOutOfMemory;
+    post.col = post.cand + (size_t)3 * l * Gr;
+    fill_u64<<<(unsigned)std::min<size_t>((words + 255) / 256, 4096), 256, 0, s>>>(post.cand, (int64_t)words, kVoid);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     int li = (int)l;
     int64_t ln = n, lldb = ldb;
-    void* args[] = {(void*)&B, (void*)&lldb, (void*)&li, (void*)&ln, (void*)&sl, (void*)&piv, (void*)&margins,
-                    (void*)&gs};
+    void* args[] = {(void*)&B, (void*)&lldb, (void*)&li, (void*)&ln, (void*)&post, (void*)&piv, (void*)&margins,
+                    (void*)&err};
     return hipLaunchCooperativeKernel(reg_kernel<T>(NR), dim3(Gr), dim3(NT), args, 0, s);
   }
   int nc, G;
