@@ -212,6 +212,109 @@ __global__ __launch_bounds__(NT) void gemm_tall_kernel(
   if (do_norm && tid < TBN && n0 + tid < N) colnorm[(int64_t)blockIdx.z * nstride + n0 + tid] = nrm;
 }
 
+// Eight-wave form of the tall-tile kernel: two waves per SIMD, so that the
+// LDS reads of one wave overlap the MFMAs of the other.  Wave w owns
+// columns 16 (w % 4) .. 16 (w % 4) + 15 and the row tiles
+// MA (w / 4) .. MA (w / 4) + MA - 1 (MA = ceil(MT / 2); the rows past M are
+// zero in LDS and never stored).
+constexpr int NT8 = 512;
+
+template <typename T, int MT>
+__global__ __launch_bounds__(NT8) void gemm_tall8_kernel(
+    int64_t M, int64_t N, int64_t K, int64_t kchunk, const T* __restrict__ X, int64_t ldx,
+    const T* __restrict__ Y, int64_t ldy, T* __restrict__ C, int64_t ldc, int64_t cstride,
+    double* __restrict__ colnorm, int64_t nstride) {
+  constexpr int MA = (MT + 1) / 2;
+  constexpr int TBM = 32 * MA;                   // rows held in LDS (a multiple of 32)
+  constexpr int XL = (TBM * BK + NT8 - 1) / NT8;  // X elements loaded per thread per K step
+  constexpr int YL = TBN * BK / NT8;             // Y elements per thread (2)
+  __shared__ T Xs[2][BK][TBM + TPAD];
+  __shared__ T Ys[2][BK][TBN + TPAD];
+  using MF = Mfma<T>;
+  typename MF::acc4 acc[MA];
+#pragma unroll
+  for (int t = 0; t < MA; ++t) acc[t] = typename MF::acc4{0, 0, 0, 0};
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wc = wave & 3, t0 = (wave >> 2) * MA;
+  const int64_t n0 = (int64_t)blockIdx.x * TBN;
+  const int64_t kb = (int64_t)blockIdx.z * kchunk;
+  const int64_t ke = (kb + kchunk < K) ? kb + kchunk : K;
+  const bool do_norm = colnorm != nullptr;
+
+  // loader: element e = tid + NT8 q of a tile is (row e / BK, k e % BK)
+  T xr[XL], yr[YL];
+  auto load = [&](int64_t k0) {
+#pragma unroll
+    for (int q = 0; q < XL; ++q) {
+      const int e = tid + NT8 * q, row = e / BK;
+      const int64_t k = k0 + (e % BK);
+      xr[q] = (row < M && k < ke) ? X[(int64_t)row * ldx + k] : T(0);
+    }
+#pragma unroll
+    for (int q = 0; q < YL; ++q) {
+      const int e = tid + NT8 * q, col = e / BK;
+      const int64_t k = k0 + (e % BK), nn = n0 + col;
+      yr[q] = (nn < N && k < ke) ? Y[nn * ldy + k] : T(0);
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < XL; ++q) {
+      const int e = tid + NT8 * q, row = e / BK;
+      if (row < TBM) Xs[buf][e % BK][row] = xr[q];
+    }
+#pragma unroll
+    for (int q = 0; q < YL; ++q) {
+      const int e = tid + NT8 * q;
+      Ys[buf][e % BK][e / BK] = yr[q];
+    }
+  };
+
+  double nrm = 0.0;
+  int cur = 0;
+  if (kb < ke) {
+    load(kb);
+    store(0);
+  }
+  __syncthreads();
+  for (int64_t k0 = kb; k0 < ke; k0 += BK) {
+    const bool more = k0 + BK < ke;
+    if (more) load(k0 + BK);
+#pragma unroll
+    for (int k4 = 0; k4 < BK / 4; ++k4) {
+      const int kr = k4 * 4 + (lane >> 4);
+      const T b = Ys[cur][kr][wc * 16 + (lane & 15)];
+      T a[MA];
+#pragma unroll
+      for (int t = 0; t < MA; ++t) a[t] = Xs[cur][kr][(t0 + t) * 16 + (lane & 15)];
+#pragma unroll
+      for (int t = 0; t < MA; ++t) acc[t] = MF::fma(a[t], b, acc[t]);
+    }
+    if (do_norm && tid < TBN) {
+#pragma unroll
+      for (int kk = 0; kk < BK; ++kk) {
+        const double y = (double)Ys[cur][kk][tid];
+        nrm += y * y;
+      }
+    }
+    if (more) store(cur ^ 1);
+    __syncthreads();
+    cur ^= 1;
+  }
+
+  T* Cz = C + (int64_t)blockIdx.z * cstride;
+#pragma unroll
+  for (int t = 0; t < MA; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = (t0 + t) * 16 + MF::row(lane, r);
+      const int64_t col = n0 + wc * 16 + (lane & 15);
+      if (row < M && col < N) Cz[col * ldc + row] = acc[t][r];
+    }
+  if (do_norm && tid < TBN && n0 + tid < N) colnorm[(int64_t)blockIdx.z * nstride + n0 + tid] = nrm;
+}
+
 // C = sum_z Cpart_z (fixed order); colnorm likewise.
 template <typename T>
 __global__ void splitk_reduce(int64_t M, int64_t N, int splits, const T* __restrict__ P, T* __restrict__ C,
@@ -249,7 +352,10 @@ int pick_splits(int64_t M, int64_t N, int64_t K, int num_cu) {
 template <typename T, int MT>
 void launch_tall(dim3 grid, hipStream_t s, int64_t M, int64_t N, int64_t K, int64_t kchunk, const T* X, int64_t ldx,
                  const T* Y, int64_t ldy, T* C, int64_t ldc, int64_t cstride, double* colnorm, int64_t nstride) {
-  gemm_tall_kernel<T, MT><<<grid, NT, 0, s>>>(M, N, K, kchunk, X, ldx, Y, ldy, C, ldc, cstride, colnorm, nstride);
+  if (MT >= 8)
+    gemm_tall8_kernel<T, MT><<<grid, NT8, 0, s>>>(M, N, K, kchunk, X, ldx, Y, ldy, C, ldc, cstride, colnorm, nstride);
+  else
+    gemm_tall_kernel<T, MT><<<grid, NT, 0, s>>>(M, N, K, kchunk, X, ldx, Y, ldy, C, ldc, cstride, colnorm, nstride);
 }
 
 template <typename T, int MT = 1>

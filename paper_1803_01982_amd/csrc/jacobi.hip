@@ -264,32 +264,26 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(const T* __restrict__ L, int
         if (q >= bs) q -= bs;
         return (unsigned)((P << 8) | (bs + q));
       };
-      auto partner = [&](int k, int ir) -> int {
-        if (full) return part_full[ir * GW + k];
-        int q = k < bs ? k + ir : k - bs - ir;
-        if (k < bs) return bs + (q >= bs ? q - bs : q);
-        return q < 0 ? q + bs : q;
-      };
       int rot_acc = 0, big_acc = 0;
+      // rotation of the pair (p, q) of lane `lane` (lanes >= bs compute a
+      // copy of pair 0 and store nothing); a, b, hg: H(p,p), H(q,q), H(p,q)
       auto choose_rot = [&](int p, int q, double a, double b, double hg, int buf) {
-        if (a == 0.0 || b == 0.0 || hg * hg <= (kTol * kTol) * (a * b)) {
-          s_ab[buf][p] = make_double2(1.0, 0.0);
-          s_ab[buf][q] = make_double2(1.0, 0.0);
-          s_dn[buf][p] = a;
-          s_dn[buf][q] = b;
-        } else {
-          double cs, sn, tt;
-          jacobi_rotation(a, b, hg, cs, sn, tt);
+        const bool skip = (a == 0.0) | (b == 0.0) | (hg * hg <= (kTol * kTol) * (a * b));
+        double cs = 1.0, sn = 0.0, tt = 0.0;
+        if (!skip) jacobi_rotation(a, b, hg, cs, sn, tt);
+        if (lane < bs) {
           s_ab[buf][p] = make_double2(cs, -sn);
           s_ab[buf][q] = make_double2(cs, sn);
           s_dn[buf][p] = a - tt * hg;
           s_dn[buf][q] = b + tt * hg;
-          rot_acc = 1;
-          if (hg * hg > (kSettled * kSettled) * (a * b)) big_acc = 1;
+          if (!skip) {
+            rot_acc = 1;
+            if (hg * hg > (kSettled * kSettled) * (a * b)) big_acc = 1;
+          }
         }
       };
-      if (nir > 0 && wave == 0 && lane < bs) {
-        const unsigned pq = pair_of(lane, 0);
+      if (nir > 0 && wave == 0) {
+        const unsigned pq = pair_of(lane < bs ? lane : 0, 0);
         const int p = (int)(pq >> 8), q = (int)(pq & 255u);
         choose_rot(p, q, H0[p * GS + p], H0[q * GS + q], H0[p * GS + q], 0);
       }
@@ -301,30 +295,48 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(const T* __restrict__ L, int
         const double* dn = s_dn[ir & 1];
         const bool last = ir + 1 == nir;
         if (wave == 0) {
-          if (!last && lane < bs) {
-            const unsigned pq = pair_of(lane, ir + 1);
-            const int p = (int)(pq >> 8), q = (int)(pq & 255u);
-            const int x = partner(p, ir), y = partner(q, ir);
+          if (!last) {
+            // pair (p, q) of round ir + 1 and the partners x of p, y of q in round ir
+            const int P = lane < bs ? lane : 0;
+            int p, q, x, y;
+            if (full) {
+              const unsigned u = sched_full[(ir + 1) * bs + P];
+              p = (int)(u >> 8);
+              q = (int)(u & 255u);
+              x = part_full[ir * GW + p];
+              y = part_full[ir * GW + q];
+            } else {
+              // cross rounds: p = P, q = bs + (P + ir + 1) % bs, x = bs + (P + ir) % bs,
+              // y = (P + 1) % bs (here ir + 1 < bs)
+              int t1 = P + ir + 1, t0 = P + ir;
+              t1 -= t1 >= bs ? bs : 0;
+              t0 -= t0 >= bs ? bs : 0;
+              p = P;
+              q = bs + t1;
+              x = bs + t0;
+              y = P + 1 == bs ? 0 : P + 1;
+            }
             const double hpq = Hc[p * GS + q], hpy = Hc[p * GS + y], hxq = Hc[x * GS + q], hxy = Hc[x * GS + y];
             const double2 fp = ab[p], fq = ab[q];
+            const double a = dn[p], b = dn[q];
             const double hg = rot_entry(fp.x, fp.y, fq.x, fq.y, hpq, hpy, hxq, hxy);
-            choose_rot(p, q, dn[p], dn[q], hg, (ir + 1) & 1);
+            choose_rot(p, q, a, b, hg, (ir + 1) & 1);
           }
         } else {
           if (!last && hb_ok) {
             const unsigned u1 = pair_of(hb_p1, ir), u2 = pair_of(hb_p2, ir);
             const int p1 = (int)(u1 >> 8), q1 = (int)(u1 & 255u), p2 = (int)(u2 >> 8), q2 = (int)(u2 & 255u);
+            const double h00 = Hc[p1 * GS + p2], h01 = Hc[p1 * GS + q2];
+            const double h10 = Hc[q1 * GS + p2], h11 = Hc[q1 * GS + q2];
+            const double2 f1 = ab[p1], g1 = ab[q1], f2 = ab[p2], g2 = ab[q2];
             if (hb_p1 == hb_p2) {
               // the rotated pair itself: new diagonal entries, the annihilated entry
-              const double off = ab[p1].y != 0.0 ? 0.0 : Hc[p1 * GS + q1];
+              const double off = f1.y != 0.0 ? 0.0 : h01;
               Hn[p1 * GS + p1] = dn[p1];
               Hn[q1 * GS + q1] = dn[q1];
               Hn[p1 * GS + q1] = off;
               Hn[q1 * GS + p1] = off;
             } else {
-              const double h00 = Hc[p1 * GS + p2], h01 = Hc[p1 * GS + q2];
-              const double h10 = Hc[q1 * GS + p2], h11 = Hc[q1 * GS + q2];
-              const double2 f1 = ab[p1], g1 = ab[q1], f2 = ab[p2], g2 = ab[q2];
               Hn[p1 * GS + p2] = rot_entry(f1.x, f1.y, f2.x, f2.y, h00, h01, h10, h11);
               Hn[p1 * GS + q2] = rot_entry(f1.x, f1.y, g2.x, g2.y, h01, h00, h11, h10);
               Hn[q1 * GS + p2] = rot_entry(g1.x, g1.y, f2.x, f2.y, h10, h11, h00, h01);
@@ -332,14 +344,24 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(const T* __restrict__ L, int
             }
           }
           if (jb_ok) {
-            // J <- J R on rows jb_r0 + jb_rs t, columns of pair jb_pi
+            // J <- J R on rows jb_r0 + jb_rs t (jb_rs >= 12, so three rows cover GW)
             const unsigned u = pair_of(jb_pi, ir);
             const int p = (int)(u >> 8), q = (int)(u & 255u);
             const double2 fp = ab[p], fq = ab[q];
-            for (int i = jb_r0; i < W2; i += jb_rs) {
-              const double jp = J0[i * GS + p], jq = J0[i * GS + q];
-              J0[i * GS + p] = fma(fp.y, jq, fp.x * jp);
-              J0[i * GS + q] = fma(fq.y, jp, fq.x * jq);
+            double jp[3], jq[3];
+#pragma unroll
+            for (int t = 0; t < 3; ++t) {
+              const int i = min(jb_r0 + jb_rs * t, W2 - 1);
+              jp[t] = J0[i * GS + p];
+              jq[t] = J0[i * GS + q];
+            }
+#pragma unroll
+            for (int t = 0; t < 3; ++t) {
+              const int i = jb_r0 + jb_rs * t;
+              if (i < W2) {
+                J0[i * GS + p] = fma(fp.y, jq[t], fp.x * jp[t]);
+                J0[i * GS + q] = fma(fq.y, jp[t], fq.x * jq[t]);
+              }
             }
           }
         }

@@ -44,7 +44,10 @@ def test_omega_fp32_is_rounded_fp64(ff):
 # ----------------------------------------------------------------- sketch
 # l <= 288 takes the tall-tile kernel (one row block, K split), larger l the
 # 64 x 64 tiled kernel
+# (eight waves from l > 112 on: odd tile counts leave a zero tile, ragged
+# column blocks and K chunks)
 @pytest.mark.parametrize("m,n,l", [(1000, 800, 30), (1000, 333, 30), (8192, 200, 20), (130, 70, 65),
+                                   (3000, 130, 129), (5000, 517, 150), (2000, 300, 288),
                                    (16384, 2048, 272), (4096, 700, 300)])
 def test_sketch_fp64(ff, m, n, l):
     announce(f"sketch fp64 m={m} n={n} l={l}")
@@ -57,12 +60,13 @@ def test_sketch_fp64(ff, m, n, l):
     assert np.max(np.abs(host(an) - np.sum(A * A, axis=0)) / np.sum(A * A, axis=0)) < 4 * m * EPS
 
 
-def test_sketch_fp32(ff):
+@pytest.mark.parametrize("l", [40, 136])
+def test_sketch_fp32(ff, l):
     import torch
-    announce("sketch fp32 m=2000 n=300 l=40")
+    announce(f"sketch fp32 m=2000 n=300 l={l}")
     A = synth.random_matrix(2000, 300, seed=5).astype(np.float32)
-    B, an = ff.sketch(dev_f(A, torch.float32), 4, 40)
-    Om32 = oracle.omega(4, 40, 2000).astype(np.float32).astype(np.float64)
+    B, an = ff.sketch(dev_f(A, torch.float32), 4, l)
+    Om32 = oracle.omega(4, l, 2000).astype(np.float32).astype(np.float64)
     A64 = A.astype(np.float64)
     Bref = Om32 @ A64
     bound = 4 * 2000 * 2.0 ** -24 * (np.abs(Om32) @ np.abs(A64))
@@ -141,7 +145,7 @@ def test_panel_qr_fp32(ff):
 
 
 # -------------------------------------------------------------- projection
-@pytest.mark.parametrize("m,n,c", [(1000, 800, 30), (2049, 513, 45), (3000, 1000, 290)])
+@pytest.mark.parametrize("m,n,c", [(1000, 800, 30), (2049, 513, 45), (4100, 1100, 200), (3000, 1000, 290)])
 def test_project_fp64(ff, m, n, c):
     announce(f"project fp64 m={m} n={n} c={c}")
     A = synth.random_matrix(m, n, seed=c)
