@@ -81,7 +81,8 @@ def gemm_roofline(prof, w, prec):
     achieved = flop / avg_s / 1e12
     return {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK[prec], "unit": "TFLOP/s",
             "frac": round(achieved / PEAK[prec], 4), "traffic": gemm_traffic(w, prec),
-            "kernel": (f"gemm_tall_kernel<{'double' if prec == 'fp64' else 'float'}, {(w.l + 15) // 16}> + splitk_reduce"
+            "kernel": (f"{'gemm_tall8_kernel' if w.l > 112 else 'gemm_tall_kernel'}"
+                       f"<{'double' if prec == 'fp64' else 'float'}, {(w.l + 15) // 16}> + splitk_reduce"
                        if w.l <= 288 else f"gemm_tn_kernel<{'double' if prec == 'fp64' else 'float'}>"),
             "flop_per_launch": flop, "avg_launch_ms": round(avg_s * 1e3, 4), "launches": n_launch}
 

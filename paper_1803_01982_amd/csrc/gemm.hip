@@ -237,70 +237,84 @@ __global__ __launch_bounds__(NT8) void gemm_tall8_kernel(
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wc = wave & 3, t0 = (wave >> 2) * MA;
+  // the last tile of the second half exists only for even MT (wave-uniform)
+  const bool full_last = t0 + MA <= MT;
   const int64_t n0 = (int64_t)blockIdx.x * TBN;
   const int64_t kb = (int64_t)blockIdx.z * kchunk;
   const int64_t ke = (kb + kchunk < K) ? kb + kchunk : K;
   const bool do_norm = colnorm != nullptr;
 
-  // loader: element e = tid + NT8 q of a tile is (row e / BK, k e % BK)
-  T xr[XL], yr[YL];
-  auto load = [&](int64_t k0) {
+  // loader: element e = tid + NT8 q of a tile is (row e / BK, k e % BK);
+  // two register sets, so the loads of a K step are issued two steps ahead
+  T xr0[XL], yr0[YL], xr1[XL], yr1[YL];
+  // every load is issued (addresses clamped into the operands) and the
+  // values outside the tile are zeroed when stored, so the loads carry no
+  // branches and their completion can be counted exactly
+  auto load = [&](T* xr, T* yr, int64_t k0) {
 #pragma unroll
     for (int q = 0; q < XL; ++q) {
       const int e = tid + NT8 * q, row = e / BK;
       const int64_t k = k0 + (e % BK);
-      xr[q] = (row < M && k < ke) ? X[(int64_t)row * ldx + k] : T(0);
+      xr[q] = X[(int64_t)min(row, (int)M - 1) * ldx + (k < K ? k : K - 1)];
     }
 #pragma unroll
     for (int q = 0; q < YL; ++q) {
       const int e = tid + NT8 * q, col = e / BK;
       const int64_t k = k0 + (e % BK), nn = n0 + col;
-      yr[q] = (nn < N && k < ke) ? Y[nn * ldy + k] : T(0);
+      yr[q] = Y[(nn < N ? nn : N - 1) * ldy + (k < K ? k : K - 1)];
     }
   };
-  auto store = [&](int buf) {
+  auto store = [&](const T* xr, const T* yr, int buf, int64_t k0) {
 #pragma unroll
     for (int q = 0; q < XL; ++q) {
       const int e = tid + NT8 * q, row = e / BK;
-      if (row < TBM) Xs[buf][e % BK][row] = xr[q];
+      if (row < TBM) Xs[buf][e % BK][row] = (row < M && k0 + (e % BK) < ke) ? xr[q] : T(0);
     }
 #pragma unroll
     for (int q = 0; q < YL; ++q) {
       const int e = tid + NT8 * q;
-      Ys[buf][e % BK][e / BK] = yr[q];
+      Ys[buf][e % BK][e / BK] = (n0 + e / BK < N && k0 + (e % BK) < ke) ? yr[q] : T(0);
     }
   };
-
   double nrm = 0.0;
-  int cur = 0;
-  if (kb < ke) {
-    load(kb);
-    store(0);
-  }
-  __syncthreads();
-  for (int64_t k0 = kb; k0 < ke; k0 += BK) {
-    const bool more = k0 + BK < ke;
-    if (more) load(k0 + BK);
+  auto compute = [&](int buf) {
 #pragma unroll
     for (int k4 = 0; k4 < BK / 4; ++k4) {
       const int kr = k4 * 4 + (lane >> 4);
-      const T b = Ys[cur][kr][wc * 16 + (lane & 15)];
+      const T b = Ys[buf][kr][wc * 16 + (lane & 15)];
       T a[MA];
 #pragma unroll
-      for (int t = 0; t < MA; ++t) a[t] = Xs[cur][kr][(t0 + t) * 16 + (lane & 15)];
+      for (int t = 0; t < MA; ++t) a[t] = Xs[buf][kr][(t0 + t) * 16 + (lane & 15)];
 #pragma unroll
-      for (int t = 0; t < MA; ++t) acc[t] = MF::fma(a[t], b, acc[t]);
+      for (int t = 0; t < MA - 1; ++t) acc[t] = MF::fma(a[t], b, acc[t]);
+      if (full_last) acc[MA - 1] = MF::fma(a[MA - 1], b, acc[MA - 1]);
     }
-    if (do_norm && tid < TBN) {
+    if (do_norm && wave >= 4) {
 #pragma unroll
-      for (int kk = 0; kk < BK; ++kk) {
-        const double y = (double)Ys[cur][kk][tid];
+      for (int kk = 0; kk < 4; ++kk) {
+        const double y = (double)Ys[buf][4 * (lane >> 4) + kk][wc * 16 + (lane & 15)];
         nrm += y * y;
       }
     }
-    if (more) store(cur ^ 1);
+  };
+
+  // pairs of K steps: the first reads LDS buffer 0 and prefetches into set 0,
+  // the second buffer 1 and set 1; the loads of a step are two steps ahead
+  load(xr0, yr0, kb);
+  load(xr1, yr1, kb + BK);
+  store(xr0, yr0, 0, kb);
+  load(xr0, yr0, kb + 2 * BK);
+  __syncthreads();
+  for (int64_t k0 = kb; k0 < ke; k0 += 2 * BK) {
+    compute(0);
+    store(xr1, yr1, 1, k0 + BK);
     __syncthreads();
-    cur ^= 1;
+    if (k0 + BK >= ke) break;
+    load(xr1, yr1, k0 + 3 * BK);
+    compute(1);
+    store(xr0, yr0, 0, k0 + 2 * BK);
+    __syncthreads();
+    load(xr0, yr0, k0 + 4 * BK);
   }
 
   T* Cz = C + (int64_t)blockIdx.z * cstride;
@@ -312,7 +326,12 @@ __global__ __launch_bounds__(NT8) void gemm_tall8_kernel(
       const int64_t col = n0 + wc * 16 + (lane & 15);
       if (row < M && col < N) Cz[col * ldc + row] = acc[t][r];
     }
-  if (do_norm && tid < TBN && n0 + tid < N) colnorm[(int64_t)blockIdx.z * nstride + n0 + tid] = nrm;
+  if (do_norm && wave >= 4) {
+    nrm += __shfl_xor(nrm, 16, kWave);
+    nrm += __shfl_xor(nrm, 32, kWave);
+    const int64_t col = n0 + wc * 16 + lane;
+    if (lane < 16 && col < N) colnorm[(int64_t)blockIdx.z * nstride + col] = nrm;
+  }
 }
 
 // C = sum_z Cpart_z (fixed order); colnorm likewise.
