@@ -186,6 +186,28 @@ __device__ inline bool grid_barrier(const GridSync& gs, unsigned& epoch) {
   return s_ok != 0;
 }
 
+// ------------------------------------------------------- write-once slots
+// A slot exists once per exchange (step, column, workgroup), is filled with
+// kVoid before the launch and is written exactly once with a relaxed
+// agent-scope atomic store: a slot that no longer holds kVoid holds its final
+// value, so a reader needs neither a grid barrier nor a fence, only a bounded
+// poll with relaxed agent-scope atomic loads.  Doubles travel as their bits;
+// the bit pattern kVoid (a signalling NaN with a payload, which no arithmetic
+// produces) is replaced by the default NaN before it is posted.
+constexpr uint64_t kVoid = 0xFFF4DEADBEEF0001ull;
+
+__device__ inline void post_u64(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline uint64_t peek_u64(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline uint64_t slot_bits(double x) {
+  const uint64_t b = (uint64_t)__double_as_longlong(x);
+  return b == kVoid ? 0x7FF8000000000000ull : b;
+}
+__device__ inline double slot_double(uint64_t b) { return __longlong_as_double((long long)b); }
+
 // ------------------------------------------------------------ misc kernels
 __global__ void fill_u32(unsigned* p, int n, unsigned v);
 

@@ -31,6 +31,8 @@ struct Arena {
 };
 
 hipError_t zero_words(unsigned* p, int n, hipStream_t s);
+// Fills n 64-bit words with the empty-slot pattern kVoid.
+hipError_t fill_void(uint64_t* p, size_t n, hipStream_t s);
 
 // Omega^T (m x l, ldo): Ot[t + i*ldo] = Omega[i, t] (Philox4x64-10 + Box-Muller).
 template <typename T>

@@ -23,6 +23,17 @@ hipError_t zero_words(unsigned* p, int n, hipStream_t s) {
   return hipGetLastError();
 }
 
+__global__ void fill_u64(uint64_t* __restrict__ p, int64_t n, uint64_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+hipError_t fill_void(uint64_t* p, size_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const size_t blocks = (n + 255) / 256;
+  fill_u64<<<(unsigned)(blocks < 4096 ? blocks : 4096), 256, 0, s>>>(p, (int64_t)n, kVoid);
+  return hipGetLastError();
+}
+
 __device__ inline void philox4x64_10(uint64_t& x0, uint64_t& x1, uint64_t& x2, uint64_t& x3,
                                      uint64_t k0, uint64_t k1) {
   const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;

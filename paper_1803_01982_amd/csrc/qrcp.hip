@@ -246,8 +246,6 @@ __global__ __launch_bounds__(NT) void qrcp_kernel(const T* __restrict__ B, int64
 //      j+1..l-1 recomputed from scratch (sums over the 16 lanes of its group).
 // A poll past the spin limit raises `error` and ends the workgroup; the
 // others see the error word within their own bounded polls.
-constexpr uint64_t kVoid = 0xFFF4DEADBEEF0001ull;  // a signalling NaN with a payload
-
 struct QrcpPost {
   uint64_t* cand;  // [3][l][G]: best norm, runner-up norm, best index
   uint64_t* col;   // rows j..l-1 of the best column of (j, g) at tri(j) G + g (l - j)
@@ -255,19 +253,6 @@ struct QrcpPost {
 
 // Rows of the column slots of the steps before j: sum over j' < j of (l - j').
 __device__ inline int64_t tri_rows(int j, int l) { return (int64_t)j * l - (int64_t)j * (j - 1) / 2; }
-
-__device__ inline void post_u64(uint64_t* p, uint64_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ inline uint64_t peek_u64(const uint64_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-// A double as slot bits; the (NaN) bit pattern kVoid is replaced by the default NaN.
-__device__ inline uint64_t slot_bits(double x) {
-  const uint64_t b = (uint64_t)__double_as_longlong(x);
-  return b == kVoid ? 0x7FF8000000000000ull : b;
-}
-__device__ inline double slot_double(uint64_t b) { return __longlong_as_double((long long)b); }
 
 template <typename T, int NR, int CB>
 __global__ __launch_bounds__(NT) void qrcp_reg_kernel(const T* __restrict__ B, int64_t ldb, int l, int64_t n,
@@ -473,10 +458,6 @@ __global__ __launch_bounds__(NT) void qrcp_reg_kernel(const T* __restrict__ B, i
   }
 }
 
-__global__ void fill_u64(uint64_t* __restrict__ p, int64_t n, uint64_t v) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
-}
-
 // Words of the candidate and column slots of the register variant.
 inline size_t post_words(int64_t l, int G) { return (size_t)G * (3 * l + l * (l + 1) / 2); }
 
@@ -559,8 +540,7 @@ hipError_t qrcp(const T* B, int64_t l, int64_t n, int64_t ldb, int64_t* piv, dou
     post.cand = ar.take<uint64_t>(words);
     if (!post.cand) return hipErrorOutOfMemory;
     post.col = post.cand + (size_t)3 * l * Gr;
-    fill_u64<<<(unsigned)std::min<size_t>((words + 255) / 256, 4096), 256, 0, s>>>(post.cand, (int64_t)words, kVoid);
-    hipError_t e = hipGetLastError();
+    hipError_t e = fill_void(post.cand, words, s);
     if (e != hipSuccess) return e;
     int li = (int)l;
     int64_t ln = n, lldb = ldb;

@@ -6,12 +6,13 @@
 //
 // One cooperative launch factors the matrix.  Workgroup g owns the row block
 // [g*rb, (g+1)*rb).  Columns are processed in panels of NB = 16:
-//   column step (one grid barrier): every workgroup publishes the partial
-//     dot products of the current column with the remaining panel columns
-//     over its rows (and the owner of the pivot row publishes that row);
-//     after the barrier all workgroups sum the partials in the same fixed
-//     order, build the same reflector (LAPACK xLARFG convention) and update
-//     their own rows of the panel, which stay in LDS for the whole panel;
+//   column step (no grid barrier): every workgroup posts the partial dot
+//     products of the current column with the remaining panel columns over
+//     its rows (and the owner of the pivot row posts that row) to write-once
+//     slots of the column; every workgroup polls the slots, sums the
+//     partials in the same fixed order, builds the same reflector (LAPACK
+//     xLARFG convention) and updates its own rows of the panel columns,
+//     which stay in registers for the whole panel;
 //   panel end (two grid barriers): Z = Y_p^T [Y_p | P_trail] is reduced
 //     (reduce-scatter, then every workgroup reads the whole Z), each
 //     workgroup forms the panel's T_p (LAPACK xLARFT, forward, columnwise)
@@ -40,8 +41,8 @@ constexpr int NT = 256, NB = 16, NW = NT / 64;
 using MF = Mfma<double>;
 
 struct TqSlots {
-  double* dots;   // [2][G][NB]
-  double* rowv;   // [2][NB]
+  uint64_t* dots;  // [c][G][NB] write-once: partial dots of column jc over the rows of workgroup g
+  uint64_t* rowv;  // [c][NB]    write-once: row jc of the panel columns (posted by its owner)
   double* zpart;  // [G][NB * (c + NB)]
   double* zred;   // [2][NB * (c + NB)]
   double* taus;   // [c]      tau of every reflector
@@ -56,43 +57,44 @@ __device__ inline double yval(int64_t gi, int64_t p0, int s, double stored) {
 // out[col * NB + s] = sum over the own rows i of Y(i, s) * X(r0 + i, col),
 // col < ncol, s < NB; X is column-major in global memory (ldx).  One wave
 // per 16-column chunk; MFMA 16x16x4 with A = Y^T from LDS and B = X from
-// global memory.  Software-pipelined: the eight loads of X for the next 32
-// rows are issued before the MFMAs of the current 32 rows.
+// global memory.  The rows go in blocks of 32 (eight MFMA K steps) with the
+// loads of the next block in flight during the current one; every load is
+// issued at a clamped address (row < nrow, col < ncol) and rows past nrow
+// get a zero A operand, so no load sits behind a branch.
 template <typename T>
-__device__ void yt_times_global(const double* Yl, int ldy, int nrow, const T* X, int64_t ldx, int64_t r0, int ncol,
-                                double* out) {
+__device__ __forceinline__ void yt_times_global(const double* Yl, int ldy, int nrow, const T* X, int64_t ldx,
+                                                int64_t r0, int ncol, double* out) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int s = lane & 15, kq = lane >> 4;
-  const int nfull = nrow & ~31;
+  const int nblk = (nrow + 31) / 32;
   for (int col0 = wave * 16; col0 < ncol; col0 += NW * 16) {
     const int col = col0 + s;
     const bool cin = col < ncol;
-    const T* xc = X + (int64_t)(cin ? col : 0) * ldx + r0;
+    const T* xc = X + (int64_t)(cin ? col : ncol - 1) * ldx + r0;
     const double* yc = Yl + s * ldy;
     MF::acc4 a[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) a[q] = MF::acc4{0, 0, 0, 0};
-    double xn[8];
-    if (nfull > 0) {
+    double xa[8], xb[8];
+    auto load = [&](double* x, int blk) {
 #pragma unroll
-      for (int u = 0; u < 8; ++u) xn[u] = cin ? (double)xc[4 * u + kq] : 0.0;
-    }
-    for (int k0 = 0; k0 < nfull; k0 += 32) {
-      double xv[8];
+      for (int u = 0; u < 8; ++u) x[u] = (double)xc[min(32 * blk + 4 * u + kq, nrow - 1)];
+    };
+    auto mma = [&](const double* x, int blk) {
 #pragma unroll
-      for (int u = 0; u < 8; ++u) xv[u] = xn[u];
-      if (k0 + 32 < nfull) {
-#pragma unroll
-        for (int u = 0; u < 8; ++u) xn[u] = cin ? (double)xc[k0 + 32 + 4 * u + kq] : 0.0;
+      for (int u = 0; u < 8; ++u) {
+        const int i = 32 * blk + 4 * u + kq;
+        const double ya = i < nrow ? yc[i] : 0.0;
+        a[u & 3] = MF::fma(ya, cin ? x[u] : 0.0, a[u & 3]);
       }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) a[u & 3] = MF::fma(yc[k0 + 4 * u + kq], xv[u], a[u & 3]);
-    }
-    for (int k0 = nfull; k0 < nrow; k0 += 4) {
-      const int i = k0 + kq;
-      const double ya = i < nrow ? yc[i] : 0.0;
-      const double xa = (cin && i < nrow) ? (double)xc[i] : 0.0;
-      a[0] = MF::fma(ya, xa, a[0]);
+    };
+    load(xa, 0);
+    for (int blk = 0; blk < nblk; blk += 2) {
+      load(xb, min(blk + 1, nblk - 1));
+      mma(xa, blk);
+      if (blk + 1 >= nblk) break;
+      load(xa, min(blk + 2, nblk - 1));
+      mma(xb, blk + 1);
     }
     if (cin)
 #pragma unroll
@@ -101,68 +103,61 @@ __device__ void yt_times_global(const double* Yl, int ldy, int nrow, const T* X,
 }
 
 // X(r0 + i, col) -= sum_s Y(i, s) W(s, col) for the own rows i < nrow and
-// col < ncol, W(s, col) = Wl[col * NB + s] in LDS.  16 x 16 tiles in
-// batches of four per wave; the accumulator starts as the tile of X and
-// A = -Y.  Software-pipelined: the next batch's tiles are loaded before the
-// current batch is computed and stored.
+// col < ncol, W(s, col) = Wl[col * NB + s] in LDS.  A wave takes batches of
+// TB row tiles of one 16-column tile; the accumulator starts as the tile of
+// X and A = -Y.  The next batch is loaded while the current one is computed
+// and stored; loads use clamped addresses (no branches), stores are masked.
 template <typename T>
-__device__ void sub_y_times(const double* Yl, int ldy, int nrow, const double* Wl, T* X, int64_t ldx, int64_t r0,
-                            int ncol) {
-  constexpr int TB = 4;
+__device__ __forceinline__ void sub_y_times(const double* Yl, int ldy, int nrow, const double* Wl, T* X, int64_t ldx,
+                                            int64_t r0, int ncol) {
+  constexpr int TB = 8;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lo = lane & 15, kq = lane >> 4;
   const int ntr = (nrow + 15) / 16, ntc = (ncol + 15) / 16;
-  const int ntile = ntr * ntc;
-  auto tile_ptr = [&](int tile, int* i0, bool* cin, int* col) -> T* {
-    const bool tin = tile < ntile;
-    const int tr = tin ? tile % ntr : 0, tc = tin ? tile / ntr : 0;
-    *i0 = tr * 16;
-    *col = tc * 16 + lo;
-    *cin = tin && *col < ncol;
-    return X + (int64_t)(*cin ? *col : 0) * ldx + r0;
+  const int nbt = (ntr + TB - 1) / TB, total = ntc * nbt;
+  if (wave >= total) return;
+  auto load = [&](int k, MF::acc4* acc) {
+    const int tc = k / nbt, tr0 = (k % nbt) * TB;
+    const int col = min(tc * 16 + lo, ncol - 1);
+    const T* xc = X + (int64_t)col * ldx + r0;
+#pragma unroll
+    for (int b = 0; b < TB; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[b][r] = (double)xc[min((tr0 + b) * 16 + MF::row(lane, r), nrow - 1)];
   };
-  auto load = [&](int t0, MF::acc4* acc) {
+  auto work = [&](int k, MF::acc4* acc) {
+    const int tc = k / nbt, tr0 = (k % nbt) * TB;
+    const int col = tc * 16 + lo;
+    const bool cin = col < ncol;
+    double bw[NB / 4];
+#pragma unroll
+    for (int k4 = 0; k4 < NB / 4; ++k4) bw[k4] = cin ? Wl[(int64_t)col * NB + 4 * k4 + kq] : 0.0;
 #pragma unroll
     for (int b = 0; b < TB; ++b) {
-      int i0, col;
-      bool cin;
-      T* xc = tile_ptr(t0 + b, &i0, &cin, &col);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = i0 + MF::row(lane, r);
-        acc[b][r] = (cin && i < nrow) ? (double)xc[i] : 0.0;
-      }
-    }
-  };
-  const int stride = NW * TB;
-  int t0 = wave * TB;
-  if (t0 >= ntile) return;
-  MF::acc4 nxt[TB];
-  load(t0, nxt);
-  for (; t0 < ntile; t0 += stride) {
-    MF::acc4 acc[TB];
-#pragma unroll
-    for (int b = 0; b < TB; ++b) acc[b] = nxt[b];
-    if (t0 + stride < ntile) load(t0 + stride, nxt);
-#pragma unroll
-    for (int b = 0; b < TB; ++b) {
-      int i0, col;
-      bool cin;
-      T* xc = tile_ptr(t0 + b, &i0, &cin, &col);
+      const int ia = (tr0 + b) * 16 + lo;
 #pragma unroll
       for (int k4 = 0; k4 < NB / 4; ++k4) {
-        const int sidx = 4 * k4 + kq;
-        const int ia = i0 + lo;
-        const double av = ia < nrow ? -Yl[sidx * ldy + ia] : 0.0;  // A[row = lo][k = kq]
-        const double bv = cin ? Wl[(int64_t)col * NB + sidx] : 0.0;  // B[k = kq][col = lo]
-        acc[b] = MF::fma(av, bv, acc[b]);
-      }
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = i0 + MF::row(lane, r);
-        if (cin && i < nrow) xc[i] = (T)acc[b][r];
+        const double av = ia < nrow ? -Yl[(4 * k4 + kq) * ldy + ia] : 0.0;  // A[row = lo][k = kq]
+        acc[b] = MF::fma(av, bw[k4], acc[b]);
       }
     }
+    T* xc = X + (int64_t)(cin ? col : 0) * ldx + r0;
+#pragma unroll
+    for (int b = 0; b < TB; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = (tr0 + b) * 16 + MF::row(lane, r);
+        if (cin && i < nrow) xc[i] = (T)acc[b][r];
+      }
+  };
+  MF::acc4 ta[TB], tb[TB];
+  load(wave, ta);
+  for (int k = wave; k < total; k += 2 * NW) {
+    load(min(k + NW, total - 1), tb);
+    work(k, ta);
+    if (k + NW >= total) break;
+    load(min(k + 2 * NW, total - 1), ta);
+    work(k + NW, tb);
   }
 }
 
@@ -235,7 +230,6 @@ __global__ __launch_bounds__(NT) void tallqr_kernel(T* __restrict__ P, int64_t m
   const int npan = (c + NB - 1) / NB;
   const int64_t estride = (int64_t)NB * (c + NB);
   unsigned epoch = 0;
-  int step = 0;
 
   // ------------------------------------------------------------ factorization
   // Within a panel each thread keeps its rows (i = tid + NT u, u < RPT) of the
@@ -256,7 +250,7 @@ __global__ __launch_bounds__(NT) void tallqr_kernel(T* __restrict__ P, int64_t m
         y[u][t] = (i < nrow && t < pw) ? (double)P[(int64_t)(p0 + t) * ldp + r0 + i] : 0.0;
     }
     for (int jt = 0; jt < pw; ++jt) {
-      const int jc = p0 + jt, par = step & 1;
+      const int jc = p0 + jt;
       // partial dots over the own rows below jc: d_s = sum x_i p_s(i), where
       // position s holds column jc + s
       {
@@ -324,39 +318,73 @@ __global__ __launch_bounds__(NT) void tallqr_kernel(T* __restrict__ P, int64_t m
           const int i = tid + NT * u;
           if (i < nrow && r0 + i == jc)
 #pragma unroll
-            for (int t = 0; t < NB; ++t) sl.rowv[par * NB + t] = y[u][t];
+            for (int t = 0; t < NB; ++t) post_u64(sl.rowv + (int64_t)jc * NB + t, slot_bits(y[u][t]));
         }
         __syncthreads();
         if (tid < NB) {
           double sacc = 0.0;
 #pragma unroll
           for (int q = 0; q < NW; ++q) sacc += red[q * NB + tid];
-          sl.dots[((int64_t)par * G + g) * NB + tid] = sacc;
+          post_u64(sl.dots + ((int64_t)jc * G + g) * NB + tid, slot_bits(sacc));
         }
       }
-      if (!grid_barrier(gs, epoch)) return;
-      // sum the partials in a fixed order (identical in every workgroup)
+      // gather the partials of every workgroup (bounded polls of the column's
+      // write-once slots) and sum them in a fixed order, identical in every
+      // workgroup
       {
         const int t = tid & (NB - 1), gq = tid / NB;
         constexpr int QB = 8;
-        double acc = 0.0;
-        for (int q0 = gq; q0 < G; q0 += QB * (NT / NB)) {
+        double acc = 0.0, rv = 0.0;
+        bool ok = true;
+        const uint64_t* dj = sl.dots + (int64_t)jc * G * NB + t;
+        for (int q0 = gq; q0 < G && ok; q0 += QB * (NT / NB)) {
           double v[QB];
+          for (unsigned spins = 0;;) {
+            bool here = true;
 #pragma unroll
-          for (int u = 0; u < QB; ++u) {
-            const int q = q0 + u * (NT / NB);
-            v[u] = q < G ? sl.dots[((int64_t)par * G + q) * NB + t] : 0.0;
+            for (int u = 0; u < QB; ++u) {
+              const int q = q0 + u * (NT / NB);
+              uint64_t b = 0;
+              if (q < G) {
+                b = peek_u64(dj + (int64_t)q * NB);
+                here = here && b != kVoid;
+              }
+              v[u] = slot_double(b);
+            }
+            if (here) break;
+            __builtin_amdgcn_s_sleep(1);
+            if ((++spins & 255u) == 0 &&
+                (__hip_atomic_load(gs.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u || spins > kSpinLimit)) {
+              ok = false;
+              break;
+            }
           }
 #pragma unroll
           for (int u = 0; u < QB; ++u) acc += v[u];
         }
+        if (tid < NB && ok) {
+          for (unsigned spins = 0;;) {
+            const uint64_t b = peek_u64(sl.rowv + (int64_t)jc * NB + tid);
+            if (b != kVoid) {
+              rv = slot_double(b);
+              break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            if ((++spins & 255u) == 0 &&
+                (__hip_atomic_load(gs.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u || spins > kSpinLimit)) {
+              ok = false;
+              break;
+            }
+          }
+        }
+        if (!ok) __hip_atomic_fetch_or(gs.error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         red[gq * NB + t] = acc;
-        __syncthreads();
+        if (__syncthreads_or(!ok)) return;
         if (tid < NB) {
           double sacc = 0.0;
           for (int q = 0; q < NT / NB; ++q) sacc += red[q * NB + tid];
-          Tl[tid] = sacc;                          // d_s
-          Tl[NB + tid] = sl.rowv[par * NB + tid];  // p_s(jc)
+          Tl[tid] = sacc;      // d_s
+          Tl[NB + tid] = rv;   // p_s(jc)
         }
         __syncthreads();
       }
@@ -395,7 +423,6 @@ __global__ __launch_bounds__(NT) void tallqr_kernel(T* __restrict__ P, int64_t m
         for (int t = 0; t + 1 < NB; ++t) y[u][t] = y[u][t + 1];
         y[u][NB - 1] = 0.0;
       }
-      ++step;
     }
     for (int t = pw; t < NB; ++t)
       for (int i = tid; i < nrow; i += NT) Yl[t * ldy + i] = 0.0;
@@ -442,8 +469,10 @@ __global__ __launch_bounds__(NT) void tallqr_kernel(T* __restrict__ P, int64_t m
       for (int q = 0; q < NB; ++q) Zl[(NB + u) * NB + q] = w[q];
     }
     __syncthreads();
-    // P_trail(own rows) -= Y W'  (rows above p0 have Y = 0)
+    // P_trail(own rows) -= Y W'  (rows above p0 have Y = 0); the next panel
+    // reads these rows from other waves
     if (ntr > 0) sub_y_times<T>(Yl, ldy, nrow, Zl + NB * NB, P + (int64_t)p1 * ldp, ldp, r0, ntr);
+    __syncthreads();
   }
 
   // --------------------------------------------------- R output, diag(R) >= 0
@@ -759,7 +788,7 @@ size_t tallqr_scratch(int64_t mrows, int64_t c, const DeviceInfo& d) {
   choose(mrows, (int)c, d.num_cu, &G, &rb, &lds);
   gram_split(mrows, c, d.num_cu, &nsplit, &chunk);
   const size_t cz = (size_t)c + NB;
-  size_t b = sizeof(double) * ((size_t)2 * G * NB + 2 * NB + (size_t)G * NB * cz + (size_t)2 * NB * cz + c +
+  size_t b = sizeof(double) * ((size_t)c * G * NB + (size_t)c * NB + (size_t)G * NB * cz + (size_t)2 * NB * cz + c +
                                ((size_t)nsplit + 2) * c * c + c);
   return b + kSyncWords * sizeof(unsigned) + 16 * 256;
 }
@@ -778,8 +807,8 @@ hipError_t tall_qr(T* P, int64_t mrows, int64_t c, int64_t ldp, T* Qout, int64_t
   gram_split(mrows, c, d.num_cu, &nsplit, &chunk);
   const size_t cz = (size_t)c + NB;
   TqSlots sl;
-  sl.dots = ar.take<double>((size_t)2 * G * NB);
-  sl.rowv = ar.take<double>(2 * NB);
+  sl.dots = ar.take<uint64_t>((size_t)c * G * NB);
+  sl.rowv = ar.take<uint64_t>((size_t)c * NB);
   sl.zpart = ar.take<double>((size_t)G * NB * cz);
   sl.zred = ar.take<double>((size_t)2 * NB * cz);
   sl.taus = ar.take<double>((size_t)c);
@@ -791,6 +820,8 @@ hipError_t tall_qr(T* P, int64_t mrows, int64_t c, int64_t ldp, T* Qout, int64_t
   if (!sl.dots || !sl.rowv || !sl.zpart || !sl.zred || !sl.taus || !spart || !S || !mt || !sgn || !counter)
     return hipErrorOutOfMemory;
   hipError_t e = zero_words(counter, kSyncWords, s);
+  if (e == hipSuccess) e = fill_void(sl.dots, (size_t)c * G * NB, s);
+  if (e == hipSuccess) e = fill_void(sl.rowv, (size_t)c * NB, s);
   if (e != hipSuccess) return e;
   if (G > kMaxGridBlocks) return hipErrorInvalidValue;
   GridSync gs{counter, err, (unsigned)G};
