@@ -439,21 +439,28 @@ __global__ __launch_bounds__(NT) void tallqr_kernel(T* __restrict__ P, int64_t m
     if (ntr > 0) yt_times_global<T>(Yl, ldy, nrow, P + (int64_t)p1 * ldp, ldp, r0, ntr, zp + NB * NB);
     double* zr = sl.zred + (int64_t)(pi & 1) * estride;
     if (!reduce_z(sl.zpart, zr, (int64_t)NB * (NB + ntr), estride, G, g, Zl, gs, epoch)) return;
-    // T of the panel: T(s,s) = tau_s, T(0:s, s) = -tau_s T(0:s, 0:s) (Y^T y_s)
-    Tl[tid] = 0.0;
-    __syncthreads();
-    for (int s = 0; s < pw; ++s) {
-      const double ts = taul[s];
-      double val = 0.0;
-      if (tid < s) {
-        for (int q = tid; q < s; ++q) val += Tl[q * NB + tid] * Zl[s * NB + q];
-        val *= -ts;
+    // T of the panel: T(s,s) = tau_s, T(0:s, s) = -tau_s T(0:s, 0:s) (Y^T y_s),
+    // by wave 0 alone: lane j keeps row j of T in registers (T(j, q) = 0 for
+    // q < j, so the sums over q < s add exact zeros below the row's start)
+    if (tid < kWave) {
+      double trow[NB];
+#pragma unroll
+      for (int q = 0; q < NB; ++q) trow[q] = 0.0;
+#pragma unroll
+      for (int s2 = 0; s2 < NB; ++s2) {
+        if (s2 < pw) {
+          double val = 0.0;
+#pragma unroll
+          for (int q = 0; q < s2; ++q) val += trow[q] * Zl[s2 * NB + q];
+          const double ts = taul[s2];
+          trow[s2] = tid < s2 ? -ts * val : (tid == s2 ? ts : 0.0);
+        }
       }
-      __syncthreads();
-      if (tid < s) Tl[s * NB + tid] = val;
-      if (tid == s) Tl[s * NB + s] = ts;
-      __syncthreads();
+      if (tid < NB)
+#pragma unroll
+        for (int q = 0; q < NB; ++q) Tl[q * NB + tid] = trow[q];
     }
+    __syncthreads();
     // W' = T^T Z_trail (in place, column by column)
     for (int u = tid; u < ntr; u += NT) {
       double z[NB], w[NB];
