@@ -226,7 +226,7 @@ __global__ __launch_bounds__(NT) void tallqr_kernel(T* __restrict__ P, int64_t m
   // so that lanes along rows and lanes along columns both avoid bank conflicts
   const int ldy = rb | 1;
   double* Yl = smem;                    // ldy x NB
-  double* Zl = Yl + (int64_t)ldy * NB;  // NB x (c + NB)
+  double* Zl = Yl + (int64_t)ldy * NB;  // NB x (c + NB), at least 4 NB NB
   const int npan = (c + NB - 1) / NB;
   const int64_t estride = (int64_t)NB * (c + NB);
   unsigned epoch = 0;
@@ -429,12 +429,29 @@ __global__ __launch_bounds__(NT) void tallqr_kernel(T* __restrict__ P, int64_t m
     __syncthreads();
     const int ntr = c - p1;
     double* zp = sl.zpart + (int64_t)g * estride;
-    // Gram part Y^T Y (16 x 16): one output per thread
+    // Gram part Y^T Y (16 x 16) on MFMA: wave w takes the K steps of rows
+    // 4 (w + NW t) .. + 3; the four partial tiles are summed in wave order
     {
+      const int lane = tid & 63, wave = tid >> 6, lo = lane & 15, kq = lane >> 4;
+      MF::acc4 ga = {0.0, 0.0, 0.0, 0.0}, gb = {0.0, 0.0, 0.0, 0.0};
+      const double* yc = Yl + lo * ldy;
+      int i0 = 4 * wave;
+      for (; i0 + 4 * NW < nrow; i0 += 8 * NW) {
+        const int ia = i0 + kq, ib = i0 + 4 * NW + kq;
+        const double va = yc[ia], vb = ib < nrow ? yc[ib] : 0.0;
+        ga = MF::fma(va, va, ga);  // A[s = lo][k] = Y(i, lo) = B[k][s = lo]
+        gb = MF::fma(vb, vb, gb);
+      }
+      if (i0 < nrow) {
+        const double va = i0 + kq < nrow ? yc[i0 + kq] : 0.0;
+        ga = MF::fma(va, va, ga);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Zl[wave * NB * NB + lo * NB + MF::row(lane, r)] = ga[r] + gb[r];
+      __syncthreads();
       const int s = tid & (NB - 1), cc = tid / NB;
-      double acc = 0.0;
-      for (int i = 0; i < nrow; ++i) acc += Yl[s * ldy + i] * Yl[cc * ldy + i];
-      zp[cc * NB + s] = acc;
+      zp[cc * NB + s] = ((Zl[cc * NB + s] + Zl[NB * NB + cc * NB + s]) + Zl[2 * NB * NB + cc * NB + s]) +
+                        Zl[3 * NB * NB + cc * NB + s];
     }
     if (ntr > 0) yt_times_global<T>(Yl, ldy, nrow, P + (int64_t)p1 * ldp, ldp, r0, ntr, zp + NB * NB);
     double* zr = sl.zred + (int64_t)(pi & 1) * estride;
@@ -746,7 +763,9 @@ void choose(int64_t mrows, int c, int num_cu, int* G, int* rb, size_t* lds) {
   int64_t r = (mrows + g - 1) / g;
   *G = (int)((mrows + r - 1) / r);
   *rb = (int)r;
-  *lds = ((size_t)(r | 1) * NB + (size_t)NB * (c + NB) + 64) * sizeof(double);
+  // Zl: Z = Y_p^T [Y_p | P_trail] (NB x (c + NB)), also the four partial
+  // Gram tiles (4 NB NB)
+  *lds = ((size_t)(r | 1) * NB + std::max((size_t)NB * (c + NB), (size_t)4 * NB * NB) + 64) * sizeof(double);
 }
 
 template <typename T>
