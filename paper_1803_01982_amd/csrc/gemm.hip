@@ -213,125 +213,178 @@ __global__ __launch_bounds__(NT) void gemm_tall_kernel(
 }
 
 // Eight-wave form of the tall-tile kernel: two waves per SIMD, so that the
-// LDS reads of one wave overlap the MFMAs of the other.  Wave w owns
-// columns 16 (w % 4) .. 16 (w % 4) + 15 and the row tiles
-// MA (w / 4) .. MA (w / 4) + MA - 1 (MA = ceil(MT / 2); the rows past M are
-// zero in LDS and never stored).
+// LDS traffic of one wave overlaps the MFMAs of the other.  Wave w owns
+// columns 16 (w % 4) .. 16 (w % 4) + 15; waves 0-3 own the row tiles
+// 0 .. MA - 1 and waves 4-7 the tiles MA .. MT - 1 (MA = ceil(MT / 2)).  The
+// two wave groups run separate instantiations of one body, selected by a
+// wave-uniform branch, so neither carries a per-tile predicate; the second
+// group also accumulates the column norms from its B fragments, which cover
+// every K index of its 16 columns once.
+//
+// Within a K step the fragments of the next k4 slice are read while the
+// MFMAs of the current one run; the register set holding the next step's
+// global loads is stored into the other LDS buffer after the first MFMA
+// group and then refilled two steps ahead.  The one barrier per step sits
+// before the last MFMA group, and the next step's first fragments are read
+// behind it.
+//
+// LDS layout.  FP64: element (k, r) of a tile sits in row k at column
+// r ^ k (the swizzle stays inside the 16-row tile) and the row stride is
+// 16 mod 32 elements; then both the transposing stores (16 k by 2 rows per
+// 32 lanes) and the fragment reads (2 k by 16 rows per 32 lanes) touch 32
+// distinct 8-byte bank pairs.  FP32: a row stride of 2 mod 32 elements,
+// which measured best for 4-byte elements.
 constexpr int NT8 = 512;
+
+template <typename T>
+struct Tall8Layout {
+  static constexpr bool swz = sizeof(T) == 8;
+  static constexpr int pad = swz ? 16 : 2;
+};
+
+template <typename T, int MT, int G>
+__device__ __forceinline__ void tall8_body(int64_t M, int64_t N, int64_t K, int64_t kchunk, const T* __restrict__ X,
+                                           int64_t ldx, const T* __restrict__ Y, int64_t ldy, T* __restrict__ C,
+                                           int64_t ldc, int64_t cstride, double* __restrict__ colnorm, int64_t nstride,
+                                           T (*Xs)[BK][32 * ((MT + 1) / 2) + Tall8Layout<T>::pad],
+                                           T (*Ys)[BK][TBN + Tall8Layout<T>::pad]) {
+  constexpr bool SWZ = Tall8Layout<T>::swz;
+  constexpr int PAD = Tall8Layout<T>::pad;
+  constexpr int MA = (MT + 1) / 2;
+  constexpr int TBM = 32 * MA;                  // rows held in LDS (rows >= M are zero)
+  constexpr int NTL = G == 0 ? MA : MT - MA;    // row tiles of this wave group
+  constexpr int T0 = G == 0 ? 0 : MA;
+  constexpr int XL = TBM * BK / NT8;            // X elements per thread per K step (= MA)
+  constexpr int YL = TBN * BK / NT8;            // Y elements per thread (2)
+  constexpr int XB = BK * (TBM + PAD), YB = BK * (TBN + PAD);  // elements per LDS buffer
+  static_assert(BK == 16 && TBM * BK % NT8 == 0 && TBN * BK % NT8 == 0, "loader covers the tiles exactly");
+  using MF = Mfma<T>;
+  typename MF::acc4 acc[NTL];
+#pragma unroll
+  for (int t = 0; t < NTL; ++t) acc[t] = typename MF::acc4{0, 0, 0, 0};
+
+  const int tid = threadIdx.x, lane = tid & 63, wc = (tid >> 6) & 3;
+  const int64_t n0 = (int64_t)blockIdx.x * TBN;
+  const int64_t kb = (int64_t)blockIdx.z * kchunk;
+  const int64_t ke = (kb + kchunk < K) ? kb + kchunk : K;
+
+  // loader: thread tid moves k = tid % 16 of rows tid / 16 + 32 q; every
+  // load is issued at an address clamped into the operand and the values
+  // outside the tile are zeroed when stored, so the loads carry no branches
+  const int sk = tid & 15, sr = tid >> 4;
+  T xr[XL], yr[YL];
+  auto load = [&](int64_t k0) {
+    const int64_t k = k0 + sk < K ? k0 + sk : K - 1;
+#pragma unroll
+    for (int q = 0; q < XL; ++q) xr[q] = X[(int64_t)min(sr + 32 * q, (int)M - 1) * ldx + k];
+#pragma unroll
+    for (int q = 0; q < YL; ++q) {
+      const int64_t nn = n0 + sr + 32 * q;
+      yr[q] = Y[(nn < N ? nn : N - 1) * ldy + k];
+    }
+  };
+  T* const xst = &Xs[0][sk][SWZ ? (sr ^ sk) : sr];
+  T* const yst = &Ys[0][sk][SWZ ? (sr ^ sk) : sr];
+  auto store = [&](int buf, int64_t k0) {
+    const bool kin = k0 + sk < ke;
+#pragma unroll
+    for (int q = 0; q < XL; ++q) xst[buf * XB + 32 * q] = (sr + 32 * q < M && kin) ? xr[q] : T(0);
+#pragma unroll
+    for (int q = 0; q < YL; ++q) yst[buf * YB + 32 * q] = (n0 + sr + 32 * q < N && kin) ? yr[q] : T(0);
+  };
+
+  // fragment reads: lane l holds A[l % 16][l / 16] and B[l / 16][l % 16] of
+  // the k4 slice, one base address per slice (the swizzle depends on k)
+  const int g = lane >> 4, c = lane & 15;
+  const T* xrd[BK / 4];
+  const T* yrd[BK / 4];
+#pragma unroll
+  for (int k4 = 0; k4 < BK / 4; ++k4) {
+    const int kr = 4 * k4 + g, cc = SWZ ? (c ^ kr) : c;
+    xrd[k4] = &Xs[0][kr][T0 * 16 + cc];
+    yrd[k4] = &Ys[0][kr][wc * 16 + cc];
+  }
+  double nrm = 0.0;
+  auto frag = [&](T* a, T& b, int buf, int k4) {
+    b = yrd[k4][buf * YB];
+#pragma unroll
+    for (int t = 0; t < NTL; ++t) a[t] = xrd[k4][buf * XB + 16 * t];
+  };
+  auto mma = [&](const T* a, T b) {
+#pragma unroll
+    for (int t = 0; t < NTL; ++t) acc[t] = MF::fma(a[t], b, acc[t]);
+    if (G == 1) nrm = fma((double)b, (double)b, nrm);
+  };
+
+  // one K step from LDS buffer `buf`; on entry a0/b0 and a1/b1 hold its
+  // first two k4 slices (the scheduling fences keep the phases in order)
+  T a0[NTL], a1[NTL], b0, b1;
+  auto step = [&](int buf, int64_t k0) {
+    mma(a0, b0);
+    store(buf ^ 1, k0 + BK);
+    load(k0 + 2 * BK);
+    __builtin_amdgcn_sched_barrier(0);
+    frag(a0, b0, buf, 2);
+    __builtin_amdgcn_sched_barrier(0);
+    mma(a1, b1);
+    __builtin_amdgcn_sched_barrier(0);
+    frag(a1, b1, buf, 3);
+    __builtin_amdgcn_sched_barrier(0);
+    mma(a0, b0);
+    __builtin_amdgcn_sched_barrier(0);
+    __syncthreads();  // every read of `buf` has returned; the other buffer is complete
+    __builtin_amdgcn_sched_barrier(0);
+    frag(a0, b0, buf ^ 1, 0);
+    __builtin_amdgcn_sched_barrier(0);
+    mma(a1, b1);
+    __builtin_amdgcn_sched_barrier(0);
+    frag(a1, b1, buf ^ 1, 1);
+    __builtin_amdgcn_sched_barrier(0);
+  };
+
+  // an even number of steps: a trailing step past ke multiplies zeros
+  const int64_t npair = (ke - kb + 2 * BK - 1) / (2 * BK);
+  load(kb);
+  store(0, kb);
+  load(kb + BK);
+  __syncthreads();
+  frag(a0, b0, 0, 0);
+  frag(a1, b1, 0, 1);
+  for (int64_t i = 0; i < npair; ++i) {
+    const int64_t k0 = kb + 2 * BK * i;
+    step(0, k0);
+    step(1, k0 + BK);
+  }
+
+  T* Cz = C + (int64_t)blockIdx.z * cstride;
+#pragma unroll
+  for (int t = 0; t < NTL; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = (T0 + t) * 16 + MF::row(lane, r);
+      const int64_t col = n0 + wc * 16 + c;
+      if (row < M && col < N) Cz[col * ldc + row] = acc[t][r];
+    }
+  if (G == 1 && colnorm != nullptr) {
+    nrm += __shfl_xor(nrm, 16, kWave);
+    nrm += __shfl_xor(nrm, 32, kWave);
+    const int64_t col = n0 + wc * 16 + lane;
+    if (lane < 16 && col < N) colnorm[(int64_t)blockIdx.z * nstride + col] = nrm;
+  }
+}
 
 template <typename T, int MT>
 __global__ __launch_bounds__(NT8) void gemm_tall8_kernel(
     int64_t M, int64_t N, int64_t K, int64_t kchunk, const T* __restrict__ X, int64_t ldx,
     const T* __restrict__ Y, int64_t ldy, T* __restrict__ C, int64_t ldc, int64_t cstride,
     double* __restrict__ colnorm, int64_t nstride) {
-  constexpr int MA = (MT + 1) / 2;
-  constexpr int TBM = 32 * MA;                   // rows held in LDS (a multiple of 32)
-  constexpr int XL = (TBM * BK + NT8 - 1) / NT8;  // X elements loaded per thread per K step
-  constexpr int YL = TBN * BK / NT8;             // Y elements per thread (2)
-  __shared__ T Xs[2][BK][TBM + TPAD];
-  __shared__ T Ys[2][BK][TBN + TPAD];
-  using MF = Mfma<T>;
-  typename MF::acc4 acc[MA];
-#pragma unroll
-  for (int t = 0; t < MA; ++t) acc[t] = typename MF::acc4{0, 0, 0, 0};
-
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wc = wave & 3, t0 = (wave >> 2) * MA;
-  // the last tile of the second half exists only for even MT (wave-uniform)
-  const bool full_last = t0 + MA <= MT;
-  const int64_t n0 = (int64_t)blockIdx.x * TBN;
-  const int64_t kb = (int64_t)blockIdx.z * kchunk;
-  const int64_t ke = (kb + kchunk < K) ? kb + kchunk : K;
-  const bool do_norm = colnorm != nullptr;
-
-  // loader: element e = tid + NT8 q of a tile is (row e / BK, k e % BK);
-  // two register sets, so the loads of a K step are issued two steps ahead
-  T xr0[XL], yr0[YL], xr1[XL], yr1[YL];
-  // every load is issued (addresses clamped into the operands) and the
-  // values outside the tile are zeroed when stored, so the loads carry no
-  // branches and their completion can be counted exactly
-  auto load = [&](T* xr, T* yr, int64_t k0) {
-#pragma unroll
-    for (int q = 0; q < XL; ++q) {
-      const int e = tid + NT8 * q, row = e / BK;
-      const int64_t k = k0 + (e % BK);
-      xr[q] = X[(int64_t)min(row, (int)M - 1) * ldx + (k < K ? k : K - 1)];
-    }
-#pragma unroll
-    for (int q = 0; q < YL; ++q) {
-      const int e = tid + NT8 * q, col = e / BK;
-      const int64_t k = k0 + (e % BK), nn = n0 + col;
-      yr[q] = Y[(nn < N ? nn : N - 1) * ldy + (k < K ? k : K - 1)];
-    }
-  };
-  auto store = [&](const T* xr, const T* yr, int buf, int64_t k0) {
-#pragma unroll
-    for (int q = 0; q < XL; ++q) {
-      const int e = tid + NT8 * q, row = e / BK;
-      if (row < TBM) Xs[buf][e % BK][row] = (row < M && k0 + (e % BK) < ke) ? xr[q] : T(0);
-    }
-#pragma unroll
-    for (int q = 0; q < YL; ++q) {
-      const int e = tid + NT8 * q;
-      Ys[buf][e % BK][e / BK] = (n0 + e / BK < N && k0 + (e % BK) < ke) ? yr[q] : T(0);
-    }
-  };
-  double nrm = 0.0;
-  auto compute = [&](int buf) {
-#pragma unroll
-    for (int k4 = 0; k4 < BK / 4; ++k4) {
-      const int kr = k4 * 4 + (lane >> 4);
-      const T b = Ys[buf][kr][wc * 16 + (lane & 15)];
-      T a[MA];
-#pragma unroll
-      for (int t = 0; t < MA; ++t) a[t] = Xs[buf][kr][(t0 + t) * 16 + (lane & 15)];
-#pragma unroll
-      for (int t = 0; t < MA - 1; ++t) acc[t] = MF::fma(a[t], b, acc[t]);
-      if (full_last) acc[MA - 1] = MF::fma(a[MA - 1], b, acc[MA - 1]);
-    }
-    if (do_norm && wave >= 4) {
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        const double y = (double)Ys[buf][4 * (lane >> 4) + kk][wc * 16 + (lane & 15)];
-        nrm += y * y;
-      }
-    }
-  };
-
-  // pairs of K steps: the first reads LDS buffer 0 and prefetches into set 0,
-  // the second buffer 1 and set 1; the loads of a step are two steps ahead
-  load(xr0, yr0, kb);
-  load(xr1, yr1, kb + BK);
-  store(xr0, yr0, 0, kb);
-  load(xr0, yr0, kb + 2 * BK);
-  __syncthreads();
-  for (int64_t k0 = kb; k0 < ke; k0 += 2 * BK) {
-    compute(0);
-    store(xr1, yr1, 1, k0 + BK);
-    __syncthreads();
-    if (k0 + BK >= ke) break;
-    load(xr1, yr1, k0 + 3 * BK);
-    compute(1);
-    store(xr0, yr0, 0, k0 + 2 * BK);
-    __syncthreads();
-    load(xr0, yr0, k0 + 4 * BK);
-  }
-
-  T* Cz = C + (int64_t)blockIdx.z * cstride;
-#pragma unroll
-  for (int t = 0; t < MA; ++t)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int64_t row = (t0 + t) * 16 + MF::row(lane, r);
-      const int64_t col = n0 + wc * 16 + (lane & 15);
-      if (row < M && col < N) Cz[col * ldc + row] = acc[t][r];
-    }
-  if (do_norm && wave >= 4) {
-    nrm += __shfl_xor(nrm, 16, kWave);
-    nrm += __shfl_xor(nrm, 32, kWave);
-    const int64_t col = n0 + wc * 16 + lane;
-    if (lane < 16 && col < N) colnorm[(int64_t)blockIdx.z * nstride + col] = nrm;
-  }
+  constexpr int PAD = Tall8Layout<T>::pad;
+  __shared__ T Xs[2][BK][32 * ((MT + 1) / 2) + PAD];
+  __shared__ T Ys[2][BK][TBN + PAD];
+  if (__builtin_amdgcn_readfirstlane(threadIdx.x >> 8) == 0)
+    tall8_body<T, MT, 0>(M, N, K, kchunk, X, ldx, Y, ldy, C, ldc, cstride, colnorm, nstride, Xs, Ys);
+  else
+    tall8_body<T, MT, 1>(M, N, K, kchunk, X, ldx, Y, ldy, C, ldc, cstride, colnorm, nstride, Xs, Ys);
 }
 
 // C = sum_z Cpart_z (fixed order); colnorm likewise.
@@ -371,7 +424,7 @@ int pick_splits(int64_t M, int64_t N, int64_t K, int num_cu) {
 template <typename T, int MT>
 void launch_tall(dim3 grid, hipStream_t s, int64_t M, int64_t N, int64_t K, int64_t kchunk, const T* X, int64_t ldx,
                  const T* Y, int64_t ldy, T* C, int64_t ldc, int64_t cstride, double* colnorm, int64_t nstride) {
-  if (MT >= 8)
+  if constexpr (MT >= 8)
     gemm_tall8_kernel<T, MT><<<grid, NT8, 0, s>>>(M, N, K, kchunk, X, ldx, Y, ldy, C, ldc, cstride, colnorm, nstride);
   else
     gemm_tall_kernel<T, MT><<<grid, NT, 0, s>>>(M, N, K, kchunk, X, ldx, Y, ldy, C, ldc, cstride, colnorm, nstride);
@@ -402,6 +455,7 @@ template <typename T>
 hipError_t gemm_tn(int64_t M, int64_t N, int64_t K, const T* X, int64_t ldx, const T* Y, int64_t ldy,
                    T* C, int64_t ldc, double* colnorm, Arena& ar, int num_cu, hipStream_t s) {
   if (M <= 0 || N <= 0) return hipSuccess;
+  if (K <= 0) return hipErrorInvalidValue;
   const int splits = pick_splits(M, N, K, num_cu);
   int64_t kchunk = (K + splits - 1) / splits;
   kchunk = (kchunk + BK - 1) / BK * BK;
