@@ -41,8 +41,10 @@ constexpr int NT = 256, NB = 16, NW = NT / 64;
 using MF = Mfma<double>;
 
 struct TqSlots {
-  uint64_t* dots;  // [c][G][NB] write-once: partial dots of column jc over the rows of workgroup g
-  uint64_t* rowv;  // [c][NB]    write-once: row jc of the panel columns (posted by its owner)
+  uint64_t* gram;   // [npan][G][NB * NB] write-once: Gram of the panel's active rows of workgroup g
+  uint64_t* rowv;   // [c][NB] write-once: row jc of its panel's columns at the panel start (posted by its owner)
+  uint64_t* dots;   // [c][G][NB] write-once: partial dots of column jc over the rows of workgroup g
+  uint64_t* rowv2;  // [c][NB] write-once: row jc of the remaining panel columns at column step jc
   double* zpart;  // [G][NB * (c + NB)]
   double* zred;   // [2][NB * (c + NB)]
   double* taus;   // [c]      tau of every reflector
@@ -161,6 +163,43 @@ __device__ __forceinline__ void sub_y_times(const double* Yl, int ldy, int nrow,
   }
 }
 
+// Gram Y^T Y (NB x NB) of the rows i < nrow of the panel in LDS (Yl,
+// column-major, ldy) on MFMA: wave w takes the K steps of rows
+// 4 (w + NW t) .. + 3 and leaves its partial tile, entry (s, t) at
+// part[w NB NB + t NB + s]; the caller sums the NW tiles in wave order.
+__device__ __forceinline__ void gram_tiles(const double* Yl, int ldy, int nrow, double* part) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, lo = lane & 15, kq = lane >> 4;
+  MF::acc4 ga = {0.0, 0.0, 0.0, 0.0}, gb = {0.0, 0.0, 0.0, 0.0};
+  const double* yc = Yl + lo * ldy;
+  int i0 = 4 * wave;
+  for (; i0 + 4 * NW < nrow; i0 += 8 * NW) {
+    const int ia = i0 + kq, ib = i0 + 4 * NW + kq;
+    const double va = yc[ia], vb = ib < nrow ? yc[ib] : 0.0;
+    ga = MF::fma(va, va, ga);  // A[s = lo][k] = Y(i, lo) = B[k][s = lo]
+    gb = MF::fma(vb, vb, gb);
+  }
+  if (i0 < nrow) {
+    const double va = i0 + kq < nrow ? yc[i0 + kq] : 0.0;
+    ga = MF::fma(va, va, ga);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) part[wave * NB * NB + lo * NB + MF::row(lane, r)] = ga[r] + gb[r];
+}
+
+// Broadcast of lane l's value to the whole wave (l wave-uniform).
+__device__ inline double readlane_d(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// A panel column whose remaining squared norm, recovered from the panel's
+// Gram matrix, is below this fraction of its squared norm at the panel start
+// has lost more than four bits to cancellation; it and the rest of the panel
+// go through the exact per-column reductions instead.
+constexpr double kPanelTheta = 1.0 / 16.0;
+
 // Reduce-scatter of E entries over G partials into zred, then every block
 // copies the whole reduced Z into Zl.  Returns false on a barrier timeout.
 // The partials of an entry are summed in order q = 0, 1, ..., G-1 in every
@@ -219,6 +258,7 @@ __global__ __launch_bounds__(NT) void tallqr_kernel(T* __restrict__ P, int64_t m
   __shared__ double red[NB * NB];
   __shared__ double Tl[NB * NB];
   __shared__ double taul[NB];
+  __shared__ int s_jf;  // first panel column left to the per-column reductions
   const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
   const int64_t r0 = (int64_t)g * rb;
   const int nrow = (int)max((int64_t)0, min((int64_t)rb, mrows - r0));
@@ -249,7 +289,181 @@ __global__ __launch_bounds__(NT) void tallqr_kernel(T* __restrict__ P, int64_t m
       for (int t = 0; t < NB; ++t)
         y[u][t] = (i < nrow && t < pw) ? (double)P[(int64_t)(p0 + t) * ldp + r0 + i] : 0.0;
     }
-    for (int jt = 0; jt < pw; ++jt) {
+    // ---- the panel's reflectors from one exchange.  The Gram matrix G of
+    // the panel columns over the active rows (>= p0) is invariant under the
+    // reflectors, and the rows p0 .. p1-1 (block B, the only rows the first
+    // pw reflectors leave above the diagonal) are posted once.  Before
+    // reflector j the dots of column j with the columns s >= j over the rows
+    // below jc are then G(j, s) - sum_{i <= j} B(i, j) B(i, s), with B
+    // already transformed by reflectors 0 .. j-1; every workgroup runs this
+    // recurrence on the same data in the same order (identical reflectors)
+    // and applies the reflectors to its own rows without further exchanges.
+    {
+#pragma unroll
+      for (int u = 0; u < RPT; ++u) {
+        const int i = tid + NT * u;
+        if (i < nrow) {
+          const int64_t gi = r0 + i;
+#pragma unroll
+          for (int t = 0; t < NB; ++t) Yl[t * ldy + i] = gi >= p0 ? y[u][t] : 0.0;
+          if (gi >= p0 && gi < p1)
+#pragma unroll
+            for (int t = 0; t < NB; ++t) post_u64(sl.rowv + gi * NB + t, slot_bits(y[u][t]));
+        }
+      }
+      __syncthreads();
+      gram_tiles(Yl, ldy, nrow, Zl);
+      __syncthreads();
+      {
+        // entry (s, t) posted as the (min, max) sum: G is exactly symmetric
+        const int e = tid, lo = min(e & 15, e >> 4), hi = max(e & 15, e >> 4), o = hi * NB + lo;
+        const double v = ((Zl[o] + Zl[NB * NB + o]) + Zl[2 * NB * NB + o]) + Zl[3 * NB * NB + o];
+        post_u64(sl.gram + ((int64_t)pi * G + g) * NB * NB + e, slot_bits(v));
+      }
+      // every workgroup gathers G (entry e = tid, partials summed in order
+      // q = 0 .. G-1, loads in batches) and B (row e / NB, column e % NB)
+      {
+        constexpr int QB = 32;
+        const uint64_t* gp = sl.gram + (int64_t)pi * G * NB * NB + tid;
+        double acc = 0.0, bv = 0.0;
+        bool ok = true;
+        for (int q0 = 0; q0 < G && ok; q0 += QB) {
+          double v[QB];
+          for (unsigned spins = 0;;) {
+            bool here = true;
+#pragma unroll
+            for (int u = 0; u < QB; ++u) {
+              uint64_t b = 0;
+              if (q0 + u < G) {
+                b = peek_u64(gp + (int64_t)(q0 + u) * NB * NB);
+                here = here && b != kVoid;
+              }
+              v[u] = slot_double(b);
+            }
+            if (here) break;
+            __builtin_amdgcn_s_sleep(1);
+            if ((++spins & 255u) == 0 &&
+                (__hip_atomic_load(gs.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u || spins > kSpinLimit)) {
+              ok = false;
+              break;
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < QB; ++u) acc += v[u];
+        }
+        const int bi = tid >> 4, bt = tid & 15;
+        if (ok && bi < pw) {
+          for (unsigned spins = 0;;) {
+            const uint64_t b = peek_u64(sl.rowv + (int64_t)(p0 + bi) * NB + bt);
+            if (b != kVoid) {
+              bv = slot_double(b);
+              break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            if ((++spins & 255u) == 0 &&
+                (__hip_atomic_load(gs.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u || spins > kSpinLimit)) {
+              ok = false;
+              break;
+            }
+          }
+        }
+        if (!ok) __hip_atomic_fetch_or(gs.error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();  // the partial tiles in Zl are no longer read
+        Zl[tid] = acc;
+        Zl[NB * NB + tid] = bv;
+        if (__syncthreads_or(!ok)) return;
+      }
+      // the recurrence, by wave 0: lane s keeps column s of B in registers;
+      // column j and the diagonal quantities come from lane j
+      if (tid < kWave) {
+        const int s = tid & (NB - 1);
+        double* twl = Zl + 2 * NB * NB;  // tau_j w_j(s), s > j
+        double* scl = twl + NB * NB;     // 1 / (x0 - beta) of reflector j
+        double* bet = scl + NB;          // beta of reflector j
+        double b[NB];
+#pragma unroll
+        for (int i = 0; i < NB; ++i) b[i] = Zl[NB * NB + i * NB + s];
+        int jf = pw;
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          if (j < jf) {
+            double bj[NB];
+#pragma unroll
+            for (int i = 0; i < NB; ++i) bj[i] = readlane_d(b[i], j);
+            double dsum = 0.0;
+#pragma unroll
+            for (int i = 0; i <= j; ++i) dsum = fma(bj[i], b[i], dsum);
+            const double gjs = Zl[j * NB + s];
+            const double d = gjs - dsum;  // dot of columns j and s below row jc
+            const double gjj = readlane_d(gjs, j), xnorm2 = readlane_d(d, j), x0 = bj[j];
+            if (!(fma(x0, x0, xnorm2) >= kPanelTheta * gjj)) {
+              jf = j;
+            } else {
+              double tau = 0.0, beta = x0, scale = 0.0;
+              if (xnorm2 > 0.0) {
+                beta = -copysign(sqrt(fma(x0, x0, xnorm2)), x0);
+                tau = (beta - x0) / beta;
+                scale = 1.0 / (x0 - beta);
+              }
+              const double tw = tau * fma(scale, d, b[j]);
+              if (s > j) {
+#pragma unroll
+                for (int i = j + 1; i < NB; ++i) b[i] = fma(-tw, bj[i] * scale, b[i]);
+                b[j] = b[j] - tw;
+              }
+              if (tid < NB) twl[j * NB + s] = s > j ? tw : 0.0;
+              if (tid == 0) {
+                taul[j] = tau;
+                scl[j] = scale;
+                bet[j] = beta;
+              }
+            }
+          }
+        }
+        if (tid == 0) s_jf = jf;
+      }
+      __syncthreads();
+    }
+    const int jf = s_jf;
+    // own rows: reflectors 0 .. jf-1 (the same arithmetic as on B above)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      if (j < jf) {
+        const int64_t jc = p0 + j;
+        const double* twl = Zl + 2 * NB * NB + j * NB;
+        const double tau = taul[j], scale = Zl[3 * NB * NB + j], beta = Zl[3 * NB * NB + NB + j];
+        double tw[NB];
+#pragma unroll
+        for (int t = j + 1; t < NB; ++t) tw[t] = twl[t];
+#pragma unroll
+        for (int u = 0; u < RPT; ++u) {
+          const int i = tid + NT * u;
+          const int64_t gi = r0 + i;
+          if (i < nrow) {
+            if (gi >= jc) {
+              const double vv = (gi == jc) ? 1.0 : y[u][j] * scale;
+#pragma unroll
+              for (int t = j + 1; t < NB; ++t) y[u][t] = fma(-tw[t], vv, y[u][t]);
+              if (gi == jc) y[u][j] = beta;
+              else if (tau != 0.0) y[u][j] = vv;
+            }
+            P[jc * ldp + gi] = (T)y[u][j];
+            Yl[j * ldy + i] = yval(gi, p0, j, y[u][j]);
+          }
+        }
+        if (tid == 0 && g == 0) sl.taus[jc] = tau;
+      }
+    }
+    // the remaining columns (after a cancellation) one reduction each, the
+    // current column in register position 0
+    for (int k = 0; k < jf && jf < pw; ++k)
+#pragma unroll
+      for (int u = 0; u < RPT; ++u) {
+#pragma unroll
+        for (int t = 0; t + 1 < NB; ++t) y[u][t] = y[u][t + 1];
+        y[u][NB - 1] = 0.0;
+      }
+    for (int jt = jf; jt < pw; ++jt) {
       const int jc = p0 + jt;
       // partial dots over the own rows below jc: d_s = sum x_i p_s(i), where
       // position s holds column jc + s
@@ -318,7 +532,7 @@ __global__ __launch_bounds__(NT) void tallqr_kernel(T* __restrict__ P, int64_t m
           const int i = tid + NT * u;
           if (i < nrow && r0 + i == jc)
 #pragma unroll
-            for (int t = 0; t < NB; ++t) post_u64(sl.rowv + (int64_t)jc * NB + t, slot_bits(y[u][t]));
+            for (int t = 0; t < NB; ++t) post_u64(sl.rowv2 + (int64_t)jc * NB + t, slot_bits(y[u][t]));
         }
         __syncthreads();
         if (tid < NB) {
@@ -364,7 +578,7 @@ __global__ __launch_bounds__(NT) void tallqr_kernel(T* __restrict__ P, int64_t m
         }
         if (tid < NB && ok) {
           for (unsigned spins = 0;;) {
-            const uint64_t b = peek_u64(sl.rowv + (int64_t)jc * NB + tid);
+            const uint64_t b = peek_u64(sl.rowv2 + (int64_t)jc * NB + tid);
             if (b != kVoid) {
               rv = slot_double(b);
               break;
@@ -429,26 +643,10 @@ __global__ __launch_bounds__(NT) void tallqr_kernel(T* __restrict__ P, int64_t m
     __syncthreads();
     const int ntr = c - p1;
     double* zp = sl.zpart + (int64_t)g * estride;
-    // Gram part Y^T Y (16 x 16) on MFMA: wave w takes the K steps of rows
-    // 4 (w + NW t) .. + 3; the four partial tiles are summed in wave order
+    // Gram part Y^T Y (16 x 16) on MFMA, the four partial tiles summed in wave order
+    gram_tiles(Yl, ldy, nrow, Zl);
+    __syncthreads();
     {
-      const int lane = tid & 63, wave = tid >> 6, lo = lane & 15, kq = lane >> 4;
-      MF::acc4 ga = {0.0, 0.0, 0.0, 0.0}, gb = {0.0, 0.0, 0.0, 0.0};
-      const double* yc = Yl + lo * ldy;
-      int i0 = 4 * wave;
-      for (; i0 + 4 * NW < nrow; i0 += 8 * NW) {
-        const int ia = i0 + kq, ib = i0 + 4 * NW + kq;
-        const double va = yc[ia], vb = ib < nrow ? yc[ib] : 0.0;
-        ga = MF::fma(va, va, ga);  // A[s = lo][k] = Y(i, lo) = B[k][s = lo]
-        gb = MF::fma(vb, vb, gb);
-      }
-      if (i0 < nrow) {
-        const double va = i0 + kq < nrow ? yc[i0 + kq] : 0.0;
-        ga = MF::fma(va, va, ga);
-      }
-#pragma unroll
-      for (int r = 0; r < 4; ++r) Zl[wave * NB * NB + lo * NB + MF::row(lane, r)] = ga[r] + gb[r];
-      __syncthreads();
       const int s = tid & (NB - 1), cc = tid / NB;
       zp[cc * NB + s] = ((Zl[cc * NB + s] + Zl[NB * NB + cc * NB + s]) + Zl[2 * NB * NB + cc * NB + s]) +
                         Zl[3 * NB * NB + cc * NB + s];
@@ -600,13 +798,6 @@ __global__ void gram_sum_kernel(const double* __restrict__ spart, int nsplit, in
   S[e] = t;
 }
 
-// Broadcast of lane l's value to the whole wave (l wave-uniform).
-__device__ inline double readlane_d(double v, int l) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)b, l);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
 
 // Column j of M' = (T Y(0:c, :)^T) diag(sgn), row-major in mt, by back
 // substitution with U = T^-1 = striu(S) + diag(1/tau): U m = y_j with
@@ -814,7 +1005,8 @@ size_t tallqr_scratch(int64_t mrows, int64_t c, const DeviceInfo& d) {
   choose(mrows, (int)c, d.num_cu, &G, &rb, &lds);
   gram_split(mrows, c, d.num_cu, &nsplit, &chunk);
   const size_t cz = (size_t)c + NB;
-  size_t b = sizeof(double) * ((size_t)c * G * NB + (size_t)c * NB + (size_t)G * NB * cz + (size_t)2 * NB * cz + c +
+  const size_t npan = ((size_t)c + NB - 1) / NB;
+  size_t b = sizeof(double) * (npan * G * NB * NB + (size_t)c * NB + (size_t)c * G * NB + (size_t)c * NB + (size_t)G * NB * cz + (size_t)2 * NB * cz + c +
                                ((size_t)nsplit + 2) * c * c + c);
   return b + kSyncWords * sizeof(unsigned) + 16 * 256;
 }
@@ -832,9 +1024,12 @@ hipError_t tall_qr(T* P, int64_t mrows, int64_t c, int64_t ldp, T* Qout, int64_t
   if (lds > d.lds_max) return hipErrorInvalidValue;
   gram_split(mrows, c, d.num_cu, &nsplit, &chunk);
   const size_t cz = (size_t)c + NB;
+  const int npan = (int)((c + NB - 1) / NB);
   TqSlots sl;
-  sl.dots = ar.take<uint64_t>((size_t)c * G * NB);
+  sl.gram = ar.take<uint64_t>((size_t)npan * G * NB * NB);
   sl.rowv = ar.take<uint64_t>((size_t)c * NB);
+  sl.dots = ar.take<uint64_t>((size_t)c * G * NB);
+  sl.rowv2 = ar.take<uint64_t>((size_t)c * NB);
   sl.zpart = ar.take<double>((size_t)G * NB * cz);
   sl.zred = ar.take<double>((size_t)2 * NB * cz);
   sl.taus = ar.take<double>((size_t)c);
@@ -843,11 +1038,13 @@ hipError_t tall_qr(T* P, int64_t mrows, int64_t c, int64_t ldp, T* Qout, int64_t
   double* mt = ar.take<double>((size_t)c * c);
   double* sgn = ar.take<double>((size_t)c);
   unsigned* counter = ar.take<unsigned>(kSyncWords);
-  if (!sl.dots || !sl.rowv || !sl.zpart || !sl.zred || !sl.taus || !spart || !S || !mt || !sgn || !counter)
+  if (!sl.gram || !sl.dots || !sl.rowv || !sl.rowv2 || !sl.zpart || !sl.zred || !sl.taus || !spart || !S || !mt || !sgn || !counter)
     return hipErrorOutOfMemory;
   hipError_t e = zero_words(counter, kSyncWords, s);
+  if (e == hipSuccess) e = fill_void(sl.gram, (size_t)npan * G * NB * NB, s);
   if (e == hipSuccess) e = fill_void(sl.dots, (size_t)c * G * NB, s);
   if (e == hipSuccess) e = fill_void(sl.rowv, (size_t)c * NB, s);
+  if (e == hipSuccess) e = fill_void(sl.rowv2, (size_t)c * NB, s);
   if (e != hipSuccess) return e;
   if (G > kMaxGridBlocks) return hipErrorInvalidValue;
   GridSync gs{counter, err, (unsigned)G};

@@ -132,6 +132,38 @@ def test_panel_qr_fp64(ff, m, n, c, seed):
     assert np.allclose(np.tril(R, -1), 0.0) and np.all(np.diag(R) >= 0)
 
 
+# Columns that are (nearly) dependent on earlier ones of their panel: the
+# panel reflectors recovered from the panel's Gram matrix would lose most of
+# such a column's remaining norm to cancellation, so the kernel takes those
+# columns through the exact per-column reductions.  The leading columns are
+# well conditioned and must match the oracle; the whole factorization must
+# be orthogonal and reproduce A(:, cols) to rounding.
+@pytest.mark.parametrize("m,c,bad", [(3000, 40, ((5, 4, 1e-9), (20, 19, 0.0), (33, None, 0.0))),
+                                     (16384, 48, ((1, 0, 1e-7), (17, 3, 1e-12), (40, 39, 1e-5)))])
+def test_panel_qr_dependent_columns_fp64(ff, m, c, bad):
+    import torch
+    announce(f"panel_qr dependent columns fp64 m={m} c={c}")
+    A = synth.random_matrix(m, c, seed=c)
+    noise = synth.random_matrix(m, c, seed=c + 1)
+    for j, k, eps in bad:
+        A[:, j] = 0.0 if k is None else A[:, k] + eps * noise[:, j]
+    cols = np.arange(c)
+    Q, R = ff.panel_qr(dev_f(A), torch.from_numpy(cols).cuda())
+    Q, R = host(Q), host(R)
+    first = min(j for j, _, _ in bad)
+    Qr, Rr = oracle.householder_qr(A)
+    assert np.max(np.abs(Q[:, :first] - Qr[:, :first])) < 1e-11
+    assert np.max(np.abs(R[:first, :] - Rr[:first, :])) < 1e-12 * np.abs(Rr).max()
+    assert np.linalg.norm(Q.T @ Q - np.eye(c)) < 1e-13
+    assert np.linalg.norm(A - Q @ R) < 1e-14 * np.linalg.norm(A)
+    assert np.allclose(np.tril(R, -1), 0.0) and np.all(np.diag(R) >= 0)
+    for j, k, eps in bad:
+        if k is None:
+            assert R[j, j] == 0.0
+        else:
+            assert R[j, j] <= 4 * eps * np.linalg.norm(noise[:, j]) + 1e-12 * np.abs(Rr).max()
+
+
 def test_panel_qr_fp32(ff):
     import torch
     announce("panel_qr fp32 m=3000 c=50")
