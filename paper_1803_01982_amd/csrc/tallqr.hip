@@ -42,6 +42,7 @@ using MF = Mfma<double>;
 
 struct TqSlots {
   uint64_t* gram;   // [npan][G][NB * NB] write-once: Gram of the panel's active rows of workgroup g
+  uint64_t* gram2;  // [npan][ceil(G / 8)][NB * NB] write-once: sums of the Grams of eight workgroups
   uint64_t* rowv;   // [c][NB] write-once: row jc of its panel's columns at the panel start (posted by its owner)
   uint64_t* dots;   // [c][G][NB] write-once: partial dots of column jc over the rows of workgroup g
   uint64_t* rowv2;  // [c][NB] write-once: row jc of the remaining panel columns at column step jc
@@ -194,6 +195,38 @@ __device__ inline double readlane_d(double v, int l) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
+// Sum, in index order, of the n <= 8 write-once slots p[0], p[stride], ...,
+// p[(n - 1) stride] after a bounded poll (all loads of a poll in flight
+// together).  False after a timeout or when the error flag is raised.
+__device__ inline bool poll_sum8(const uint64_t* p, int64_t stride, int n, const unsigned* error, double& sum) {
+  double v[8];
+  for (unsigned spins = 0;;) {
+    bool here = true;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      uint64_t b = 0;
+      if (u < n) {
+        b = peek_u64(p + u * stride);
+        here = here && b != kVoid;
+      }
+      v[u] = slot_double(b);
+    }
+    if (here) break;
+    __builtin_amdgcn_s_sleep(1);
+    if ((++spins & 255u) == 0 &&
+        (__hip_atomic_load(error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u || spins > kSpinLimit))
+      return false;
+  }
+  double s = v[0];
+#pragma unroll
+  for (int u = 1; u < 8; ++u)
+    if (u < n) s += v[u];
+  sum = s;
+  return true;
+}
+
+constexpr int kGramGroup = 8;  // workgroups per first-level Gram sum
+
 // A panel column whose remaining squared norm, recovered from the panel's
 // Gram matrix, is below this fraction of its squared norm at the panel start
 // has lost more than four bits to cancellation; it and the rest of the panel
@@ -320,36 +353,25 @@ __global__ __launch_bounds__(NT) void tallqr_kernel(T* __restrict__ P, int64_t m
         const double v = ((Zl[o] + Zl[NB * NB + o]) + Zl[2 * NB * NB + o]) + Zl[3 * NB * NB + o];
         post_u64(sl.gram + ((int64_t)pi * G + g) * NB * NB + e, slot_bits(v));
       }
-      // every workgroup gathers G (entry e = tid, partials summed in order
-      // q = 0 .. G-1, loads in batches) and B (row e / NB, column e % NB)
+      // G in two levels (entry e = tid): the first workgroup of each group
+      // of kGramGroup sums the group's Grams in workgroup order and posts the
+      // sum; every workgroup sums the group sums in group order.  B: row
+      // e / NB, column e % NB, from its owner.
       {
-        constexpr int QB = 32;
-        const uint64_t* gp = sl.gram + (int64_t)pi * G * NB * NB + tid;
-        double acc = 0.0, bv = 0.0;
+        const int ngrp = (G + kGramGroup - 1) / kGramGroup;
         bool ok = true;
-        for (int q0 = 0; q0 < G && ok; q0 += QB) {
-          double v[QB];
-          for (unsigned spins = 0;;) {
-            bool here = true;
-#pragma unroll
-            for (int u = 0; u < QB; ++u) {
-              uint64_t b = 0;
-              if (q0 + u < G) {
-                b = peek_u64(gp + (int64_t)(q0 + u) * NB * NB);
-                here = here && b != kVoid;
-              }
-              v[u] = slot_double(b);
-            }
-            if (here) break;
-            __builtin_amdgcn_s_sleep(1);
-            if ((++spins & 255u) == 0 &&
-                (__hip_atomic_load(gs.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u || spins > kSpinLimit)) {
-              ok = false;
-              break;
-            }
-          }
-#pragma unroll
-          for (int u = 0; u < QB; ++u) acc += v[u];
+        if (g % kGramGroup == 0) {
+          double s1 = 0.0;
+          ok = poll_sum8(sl.gram + ((int64_t)pi * G + g) * NB * NB + tid, NB * NB, min(kGramGroup, G - g), gs.error,
+                         s1);
+          if (ok) post_u64(sl.gram2 + ((int64_t)pi * ngrp + g / kGramGroup) * NB * NB + tid, slot_bits(s1));
+        }
+        double acc = 0.0, bv = 0.0;
+        for (int k0 = 0; k0 < ngrp && ok; k0 += 8) {
+          double s2 = 0.0;
+          ok = poll_sum8(sl.gram2 + ((int64_t)pi * ngrp + k0) * NB * NB + tid, NB * NB, min(8, ngrp - k0), gs.error,
+                         s2);
+          acc = k0 == 0 ? s2 : acc + s2;
         }
         const int bi = tid >> 4, bt = tid & 15;
         if (ok && bi < pw) {
@@ -1006,7 +1028,8 @@ size_t tallqr_scratch(int64_t mrows, int64_t c, const DeviceInfo& d) {
   gram_split(mrows, c, d.num_cu, &nsplit, &chunk);
   const size_t cz = (size_t)c + NB;
   const size_t npan = ((size_t)c + NB - 1) / NB;
-  size_t b = sizeof(double) * (npan * G * NB * NB + (size_t)c * NB + (size_t)c * G * NB + (size_t)c * NB + (size_t)G * NB * cz + (size_t)2 * NB * cz + c +
+  const size_t ngrp = ((size_t)G + kGramGroup - 1) / kGramGroup;
+  size_t b = sizeof(double) * (npan * G * NB * NB + npan * ngrp * NB * NB + (size_t)c * NB + (size_t)c * G * NB + (size_t)c * NB + (size_t)G * NB * cz + (size_t)2 * NB * cz + c +
                                ((size_t)nsplit + 2) * c * c + c);
   return b + kSyncWords * sizeof(unsigned) + 16 * 256;
 }
@@ -1026,7 +1049,9 @@ hipError_t tall_qr(T* P, int64_t mrows, int64_t c, int64_t ldp, T* Qout, int64_t
   const size_t cz = (size_t)c + NB;
   const int npan = (int)((c + NB - 1) / NB);
   TqSlots sl;
+  const int ngrp = (G + kGramGroup - 1) / kGramGroup;
   sl.gram = ar.take<uint64_t>((size_t)npan * G * NB * NB);
+  sl.gram2 = ar.take<uint64_t>((size_t)npan * ngrp * NB * NB);
   sl.rowv = ar.take<uint64_t>((size_t)c * NB);
   sl.dots = ar.take<uint64_t>((size_t)c * G * NB);
   sl.rowv2 = ar.take<uint64_t>((size_t)c * NB);
@@ -1038,10 +1063,11 @@ hipError_t tall_qr(T* P, int64_t mrows, int64_t c, int64_t ldp, T* Qout, int64_t
   double* mt = ar.take<double>((size_t)c * c);
   double* sgn = ar.take<double>((size_t)c);
   unsigned* counter = ar.take<unsigned>(kSyncWords);
-  if (!sl.gram || !sl.dots || !sl.rowv || !sl.rowv2 || !sl.zpart || !sl.zred || !sl.taus || !spart || !S || !mt || !sgn || !counter)
+  if (!sl.gram || !sl.gram2 || !sl.dots || !sl.rowv || !sl.rowv2 || !sl.zpart || !sl.zred || !sl.taus || !spart || !S || !mt || !sgn || !counter)
     return hipErrorOutOfMemory;
   hipError_t e = zero_words(counter, kSyncWords, s);
   if (e == hipSuccess) e = fill_void(sl.gram, (size_t)npan * G * NB * NB, s);
+  if (e == hipSuccess) e = fill_void(sl.gram2, (size_t)npan * ngrp * NB * NB, s);
   if (e == hipSuccess) e = fill_void(sl.dots, (size_t)c * G * NB, s);
   if (e == hipSuccess) e = fill_void(sl.rowv, (size_t)c * NB, s);
   if (e == hipSuccess) e = fill_void(sl.rowv2, (size_t)c * NB, s);
