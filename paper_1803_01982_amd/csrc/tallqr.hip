@@ -195,15 +195,16 @@ __device__ inline double readlane_d(double v, int l) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-// Sum, in index order, of the n <= 8 write-once slots p[0], p[stride], ...,
+// Sum, in index order, of the n <= N write-once slots p[0], p[stride], ...,
 // p[(n - 1) stride] after a bounded poll (all loads of a poll in flight
 // together).  False after a timeout or when the error flag is raised.
-__device__ inline bool poll_sum8(const uint64_t* p, int64_t stride, int n, const unsigned* error, double& sum) {
-  double v[8];
+template <int N>
+__device__ inline bool poll_sum(const uint64_t* p, int64_t stride, int n, const unsigned* error, double& sum) {
+  double v[N];
   for (unsigned spins = 0;;) {
     bool here = true;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < N; ++u) {
       uint64_t b = 0;
       if (u < n) {
         b = peek_u64(p + u * stride);
@@ -219,13 +220,13 @@ __device__ inline bool poll_sum8(const uint64_t* p, int64_t stride, int n, const
   }
   double s = v[0];
 #pragma unroll
-  for (int u = 1; u < 8; ++u)
+  for (int u = 1; u < N; ++u)
     if (u < n) s += v[u];
   sum = s;
   return true;
 }
 
-constexpr int kGramGroup = 8;  // workgroups per first-level Gram sum
+constexpr int kGramGroup = 16;  // workgroups per first-level Gram sum
 
 // A panel column whose remaining squared norm, recovered from the panel's
 // Gram matrix, is below this fraction of its squared norm at the panel start
@@ -362,15 +363,15 @@ __global__ __launch_bounds__(NT) void tallqr_kernel(T* __restrict__ P, int64_t m
         bool ok = true;
         if (g % kGramGroup == 0) {
           double s1 = 0.0;
-          ok = poll_sum8(sl.gram + ((int64_t)pi * G + g) * NB * NB + tid, NB * NB, min(kGramGroup, G - g), gs.error,
-                         s1);
+          ok = poll_sum<kGramGroup>(sl.gram + ((int64_t)pi * G + g) * NB * NB + tid, NB * NB, min(kGramGroup, G - g),
+                                    gs.error, s1);
           if (ok) post_u64(sl.gram2 + ((int64_t)pi * ngrp + g / kGramGroup) * NB * NB + tid, slot_bits(s1));
         }
         double acc = 0.0, bv = 0.0;
-        for (int k0 = 0; k0 < ngrp && ok; k0 += 8) {
+        for (int k0 = 0; k0 < ngrp && ok; k0 += 16) {
           double s2 = 0.0;
-          ok = poll_sum8(sl.gram2 + ((int64_t)pi * ngrp + k0) * NB * NB + tid, NB * NB, min(8, ngrp - k0), gs.error,
-                         s2);
+          ok = poll_sum<16>(sl.gram2 + ((int64_t)pi * ngrp + k0) * NB * NB + tid, NB * NB, min(16, ngrp - k0), gs.error,
+                            s2);
           acc = k0 == 0 ? s2 : acc + s2;
         }
         const int bi = tid >> 4, bt = tid & 15;
@@ -963,13 +964,14 @@ __global__ __launch_bounds__(256) void wy_apply_kernel(const T* __restrict__ P, 
       }
 }
 
-// Row blocks of 128 to 256 rows, aiming at 64 workgroups: more workgroups
-// share the panel-end streaming, fewer keep the per-column grid barriers
-// cheap.  Measured on 16384 x 272 / 8192 x 272: 128-row blocks 3.02 / 2.42
-// ms, 256-row blocks 3.00 / 2.77 ms, 512-row blocks 3.75 / 3.64 ms.
+// Row blocks of 64 to 256 rows, aiming at 128 workgroups: more workgroups
+// share the streaming trailing updates, fewer keep the panel exchanges and
+// the grid barriers cheap.  Measured on 16384 x 272 / 8192 x 272 (one
+// exchange per panel): 64 workgroups 1.99 / 1.83 ms, 128 workgroups
+// 1.66 / 1.39 ms, 256 workgroups 1.74 ms (16384 rows).
 void choose(int64_t mrows, int c, int num_cu, int* G, int* rb, size_t* lds) {
-  int64_t rows = (mrows + 63) / 64;
-  rows = rows < 128 ? 128 : (rows > 256 ? 256 : rows);
+  int64_t rows = (mrows + 127) / 128;
+  rows = rows < 64 ? 64 : (rows > 256 ? 256 : rows);
   int64_t g = (mrows + rows - 1) / rows;
   if (g > num_cu) g = num_cu;
   if (g < 1) g = 1;
