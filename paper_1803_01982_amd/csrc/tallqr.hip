@@ -46,8 +46,8 @@ struct TqSlots {
   uint64_t* rowv;   // [c][NB] write-once: row jc of its panel's columns at the panel start (posted by its owner)
   uint64_t* dots;   // [c][G][NB] write-once: partial dots of column jc over the rows of workgroup g
   uint64_t* rowv2;  // [c][NB] write-once: row jc of the remaining panel columns at column step jc
-  double* zpart;  // [G][NB * (c + NB)]
-  double* zred;   // [2][NB * (c + NB)]
+  uint64_t* zpart;  // per panel p: [G][E_p] write-once partials of Z = Y_p^T [Y_p | P_trail], E_p = NB (NB + ntr_p)
+  uint64_t* zred;   // per panel p: [E_p] write-once reduced Z
   double* taus;   // [c]      tau of every reflector
 };
 
@@ -57,7 +57,7 @@ __device__ inline double yval(int64_t gi, int64_t p0, int s, double stored) {
   return gi < d ? 0.0 : (gi == d ? 1.0 : stored);
 }
 
-// out[col * NB + s] = sum over the own rows i of Y(i, s) * X(r0 + i, col),
+// Posts out[col * NB + s] = sum over the own rows i of Y(i, s) * X(r0 + i, col),
 // col < ncol, s < NB; X is column-major in global memory (ldx).  One wave
 // per 16-column chunk; MFMA 16x16x4 with A = Y^T from LDS and B = X from
 // global memory.  The rows go in blocks of 32 (eight MFMA K steps) with the
@@ -66,7 +66,7 @@ __device__ inline double yval(int64_t gi, int64_t p0, int s, double stored) {
 // get a zero A operand, so no load sits behind a branch.
 template <typename T>
 __device__ __forceinline__ void yt_times_global(const double* Yl, int ldy, int nrow, const T* X, int64_t ldx,
-                                                int64_t r0, int ncol, double* out) {
+                                                int64_t r0, int ncol, uint64_t* out) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int s = lane & 15, kq = lane >> 4;
   const int nblk = (nrow + 31) / 32;
@@ -101,7 +101,8 @@ __device__ __forceinline__ void yt_times_global(const double* Yl, int ldy, int n
     }
     if (cin)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) out[(int64_t)col * NB + MF::row(lane, r)] = (a[0][r] + a[1][r]) + (a[2][r] + a[3][r]);
+      for (int r = 0; r < 4; ++r)
+        post_u64(out + (int64_t)col * NB + MF::row(lane, r), slot_bits((a[0][r] + a[1][r]) + (a[2][r] + a[3][r])));
   }
 }
 
@@ -226,6 +227,28 @@ __device__ inline bool poll_sum(const uint64_t* p, int64_t stride, int n, const 
   return true;
 }
 
+// The n <= N write-once slots p[0], p[stride], ... into v after a bounded poll.
+template <int N>
+__device__ inline bool poll_vals(const uint64_t* p, int64_t stride, int n, const unsigned* error, double* v) {
+  for (unsigned spins = 0;;) {
+    bool here = true;
+#pragma unroll
+    for (int u = 0; u < N; ++u) {
+      uint64_t b = 0;
+      if (u < n) {
+        b = peek_u64(p + u * stride);
+        here = here && b != kVoid;
+      }
+      v[u] = slot_double(b);
+    }
+    if (here) return true;
+    __builtin_amdgcn_s_sleep(1);
+    if ((++spins & 255u) == 0 &&
+        (__hip_atomic_load(error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u || spins > kSpinLimit))
+      return false;
+  }
+}
+
 constexpr int kGramGroup = 16;  // workgroups per first-level Gram sum
 
 // A panel column whose remaining squared norm, recovered from the panel's
@@ -234,54 +257,44 @@ constexpr int kGramGroup = 16;  // workgroups per first-level Gram sum
 // go through the exact per-column reductions instead.
 constexpr double kPanelTheta = 1.0 / 16.0;
 
-// Reduce-scatter of E entries over G partials into zred, then every block
-// copies the whole reduced Z into Zl.  Returns false on a barrier timeout.
-// The partials of an entry are summed in order q = 0, 1, ..., G-1 in every
-// run; their loads are issued in batches of 16 so that the latency of the
-// memory hierarchy is paid once per batch, not once per load.
-__device__ bool reduce_z(const double* zpart, double* zred, int64_t E, int64_t estride, int G, int g, double* Zl,
-                         const GridSync& gs, unsigned& epoch) {
+// Reduce-scatter of the E entries of Z over the G partials (write-once
+// slots, partial q at zpart[q E]): workgroup g sums the entries
+// [E g / G, E (g + 1) / G) in partial order, in batches of 16 partials whose
+// sums are added in batch order, and posts them to zred; every workgroup
+// then gathers the whole reduced Z into Zl.  No grid barrier: every wait is
+// a bounded poll of the slots it reads.  False after a timeout or an error.
+__device__ bool reduce_z(const uint64_t* zpart, uint64_t* zred, int64_t E, int G, int g, double* Zl,
+                         const unsigned* error) {
   constexpr int RB = 16;
-  if (!grid_barrier(gs, epoch)) return false;
   const int64_t e0 = E * g / G, e1 = E * (g + 1) / G;
   const int ne = (int)(e1 - e0), nb = (G + RB - 1) / RB;
-  // (entry, batch of RB partials) items; the batch sums go through LDS (Zl,
-  // overwritten by the gather below) and are added in batch order
-  for (int it0 = 0; it0 < ne * nb; it0 += NT) {
+  bool ok = true;
+  for (int it0 = 0; it0 < ne * nb && ok; it0 += NT) {
     const int it = it0 + threadIdx.x;
     if (it < ne * nb) {
       const int el = it % ne, q0 = (it / ne) * RB;
-      double v[RB];
-#pragma unroll
-      for (int u = 0; u < RB; ++u) v[u] = q0 + u < G ? zpart[(int64_t)(q0 + u) * estride + e0 + el] : 0.0;
       double t = 0.0;
-#pragma unroll
-      for (int u = 0; u < RB; ++u) t += v[u];
+      ok = poll_sum<RB>(zpart + (int64_t)q0 * E + e0 + el, E, min(RB, G - q0), error, t);
       Zl[it] = t;
     }
   }
-  __syncthreads();
+  if (__syncthreads_or(!ok)) return false;
   for (int el = threadIdx.x; el < ne; el += NT) {
-    double t = 0.0;
-    for (int b = 0; b < nb; ++b) t += Zl[b * ne + el];
-    zred[e0 + el] = t;
+    double t = Zl[el];
+    for (int b = 1; b < nb; ++b) t += Zl[b * ne + el];
+    post_u64(zred + e0 + el, slot_bits(t));
   }
-  if (!grid_barrier(gs, epoch)) return false;
-  for (int64_t b = 0; b < E; b += (int64_t)NT * RB) {
+  __syncthreads();  // Zl is overwritten below
+  for (int64_t b = 0; b < E && ok; b += (int64_t)NT * RB) {
+    const int64_t e = b + threadIdx.x;
+    const int n = e < E ? (int)min((int64_t)RB, (E - e + NT - 1) / NT) : 0;
     double v[RB];
+    if (n > 0) ok = poll_vals<RB>(zred + e, NT, n, error, v);
 #pragma unroll
-    for (int u = 0; u < RB; ++u) {
-      const int64_t e = b + u * NT + threadIdx.x;
-      v[u] = e < E ? zred[e] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < RB; ++u) {
-      const int64_t e = b + u * NT + threadIdx.x;
-      if (e < E) Zl[e] = v[u];
-    }
+    for (int u = 0; u < RB; ++u)
+      if (u < n) Zl[e + (int64_t)u * NT] = v[u];
   }
-  __syncthreads();
-  return true;
+  return !__syncthreads_or(!ok);
 }
 
 template <typename T, int RPT>
@@ -302,8 +315,7 @@ __global__ __launch_bounds__(NT) void tallqr_kernel(T* __restrict__ P, int64_t m
   double* Yl = smem;                    // ldy x NB
   double* Zl = Yl + (int64_t)ldy * NB;  // NB x (c + NB), at least 4 NB NB
   const int npan = (c + NB - 1) / NB;
-  const int64_t estride = (int64_t)NB * (c + NB);
-  unsigned epoch = 0;
+  int64_t zacc = 0;  // entries of Z in the panels before the current one
 
   // ------------------------------------------------------------ factorization
   // Within a panel each thread keeps its rows (i = tid + NT u, u < RPT) of the
@@ -665,18 +677,23 @@ __global__ __launch_bounds__(NT) void tallqr_kernel(T* __restrict__ P, int64_t m
       for (int i = tid; i < nrow; i += NT) Yl[t * ldy + i] = 0.0;
     __syncthreads();
     const int ntr = c - p1;
-    double* zp = sl.zpart + (int64_t)g * estride;
+    const int64_t E = (int64_t)NB * (NB + ntr);
+    uint64_t* zp = sl.zpart + (int64_t)G * zacc + (int64_t)g * E;
     // Gram part Y^T Y (16 x 16) on MFMA, the four partial tiles summed in wave order
     gram_tiles(Yl, ldy, nrow, Zl);
     __syncthreads();
     {
       const int s = tid & (NB - 1), cc = tid / NB;
-      zp[cc * NB + s] = ((Zl[cc * NB + s] + Zl[NB * NB + cc * NB + s]) + Zl[2 * NB * NB + cc * NB + s]) +
-                        Zl[3 * NB * NB + cc * NB + s];
+      post_u64(zp + cc * NB + s,
+               slot_bits(((Zl[cc * NB + s] + Zl[NB * NB + cc * NB + s]) + Zl[2 * NB * NB + cc * NB + s]) +
+                         Zl[3 * NB * NB + cc * NB + s]));
     }
     if (ntr > 0) yt_times_global<T>(Yl, ldy, nrow, P + (int64_t)p1 * ldp, ldp, r0, ntr, zp + NB * NB);
-    double* zr = sl.zred + (int64_t)(pi & 1) * estride;
-    if (!reduce_z(sl.zpart, zr, (int64_t)NB * (NB + ntr), estride, G, g, Zl, gs, epoch)) return;
+    if (!reduce_z(sl.zpart + (int64_t)G * zacc, sl.zred + zacc, E, G, g, Zl, gs.error)) {
+      if (tid == 0) __hip_atomic_fetch_or(gs.error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return;
+    }
+    zacc += E;
     // T of the panel: T(s,s) = tau_s, T(0:s, s) = -tau_s T(0:s, 0:s) (Y^T y_s),
     // by wave 0 alone: lane j keeps row j of T in registers (T(j, q) = 0 for
     // q < j, so the sums over q < s add exact zeros below the row's start)
@@ -1008,6 +1025,13 @@ __global__ void scatter_rows_kernel(const T* __restrict__ Q, int64_t mrows, int6
 
 }  // namespace
 
+// Entries of Z = Y_p^T [Y_p | P_trail] over all panels: NB (NB + ntr_p).
+static size_t z_entries(int64_t c) {
+  size_t t = 0;
+  for (int64_t p1 = NB; p1 - NB < c; p1 += NB) t += (size_t)NB * (NB + (p1 < c ? c - p1 : 0));
+  return t;
+}
+
 // Row chunks of the Gram S = Y^T Y: enough (chunk, tile pair) workgroups to
 // fill the chip twice, chunks of at least 256 rows, at most 32 partials.
 void gram_split(int64_t mrows, int64_t c, int num_cu, int* nsplit, int64_t* chunk) {
@@ -1028,10 +1052,10 @@ size_t tallqr_scratch(int64_t mrows, int64_t c, const DeviceInfo& d) {
   size_t lds;
   choose(mrows, (int)c, d.num_cu, &G, &rb, &lds);
   gram_split(mrows, c, d.num_cu, &nsplit, &chunk);
-  const size_t cz = (size_t)c + NB;
   const size_t npan = ((size_t)c + NB - 1) / NB;
   const size_t ngrp = ((size_t)G + kGramGroup - 1) / kGramGroup;
-  size_t b = sizeof(double) * (npan * G * NB * NB + npan * ngrp * NB * NB + (size_t)c * NB + (size_t)c * G * NB + (size_t)c * NB + (size_t)G * NB * cz + (size_t)2 * NB * cz + c +
+  size_t b = sizeof(double) * (npan * G * NB * NB + npan * ngrp * NB * NB + (size_t)c * NB + (size_t)c * G * NB +
+                               (size_t)c * NB + ((size_t)G + 1) * z_entries(c) + c +
                                ((size_t)nsplit + 2) * c * c + c);
   return b + kSyncWords * sizeof(unsigned) + 16 * 256;
 }
@@ -1048,7 +1072,6 @@ hipError_t tall_qr(T* P, int64_t mrows, int64_t c, int64_t ldp, T* Qout, int64_t
   choose(mrows, (int)c, d.num_cu, &G, &rb, &lds);
   if (lds > d.lds_max) return hipErrorInvalidValue;
   gram_split(mrows, c, d.num_cu, &nsplit, &chunk);
-  const size_t cz = (size_t)c + NB;
   const int npan = (int)((c + NB - 1) / NB);
   TqSlots sl;
   const int ngrp = (G + kGramGroup - 1) / kGramGroup;
@@ -1057,8 +1080,9 @@ hipError_t tall_qr(T* P, int64_t mrows, int64_t c, int64_t ldp, T* Qout, int64_t
   sl.rowv = ar.take<uint64_t>((size_t)c * NB);
   sl.dots = ar.take<uint64_t>((size_t)c * G * NB);
   sl.rowv2 = ar.take<uint64_t>((size_t)c * NB);
-  sl.zpart = ar.take<double>((size_t)G * NB * cz);
-  sl.zred = ar.take<double>((size_t)2 * NB * cz);
+  const size_t zall = z_entries(c);
+  sl.zpart = ar.take<uint64_t>((size_t)G * zall);
+  sl.zred = ar.take<uint64_t>(zall);
   sl.taus = ar.take<double>((size_t)c);
   double* spart = ar.take<double>((size_t)nsplit * c * c);
   double* S = ar.take<double>((size_t)c * c);
@@ -1070,6 +1094,8 @@ hipError_t tall_qr(T* P, int64_t mrows, int64_t c, int64_t ldp, T* Qout, int64_t
   hipError_t e = zero_words(counter, kSyncWords, s);
   if (e == hipSuccess) e = fill_void(sl.gram, (size_t)npan * G * NB * NB, s);
   if (e == hipSuccess) e = fill_void(sl.gram2, (size_t)npan * ngrp * NB * NB, s);
+  if (e == hipSuccess) e = fill_void(sl.zpart, (size_t)G * zall, s);
+  if (e == hipSuccess) e = fill_void(sl.zred, zall, s);
   if (e == hipSuccess) e = fill_void(sl.dots, (size_t)c * G * NB, s);
   if (e == hipSuccess) e = fill_void(sl.rowv, (size_t)c * NB, s);
   if (e == hipSuccess) e = fill_void(sl.rowv2, (size_t)c * NB, s);
