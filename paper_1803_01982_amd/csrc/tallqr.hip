@@ -767,8 +767,9 @@ constexpr int WY_T = 64, WY_K = 16, WY_LD = WY_T + 16;
 template <typename T>
 __global__ __launch_bounds__(256) void gram_y_kernel(const T* __restrict__ P, int64_t mrows, int c, int64_t ldp,
                                                      int64_t chunk, double* __restrict__ spart) {
-  __shared__ double Ya[WY_K * WY_LD];
-  __shared__ double Yb[WY_K * WY_LD];
+  constexpr int GY_LD = WY_T + 1;  // odd stride: the row-wise stores below spread over the banks
+  __shared__ double Ya[WY_K * GY_LD];
+  __shared__ double Yb[WY_K * GY_LD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nt = (c + WY_T - 1) / WY_T;
   int I = 0, J = 0;
@@ -781,7 +782,6 @@ __global__ __launch_bounds__(256) void gram_y_kernel(const T* __restrict__ P, in
   }
   const int a0 = I * WY_T, b0 = J * WY_T;
   const int64_t ilo = (int64_t)blockIdx.y * chunk;
-  // rows above a column carry no Householder entries
   const int64_t ihi = min(mrows, ilo + chunk);
   const int wa = wave & 1, wb = wave >> 1;
   MF::acc4 acc[2][2];
@@ -789,25 +789,38 @@ __global__ __launch_bounds__(256) void gram_y_kernel(const T* __restrict__ P, in
   for (int x = 0; x < 2; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y) acc[x][y] = MF::acc4{0, 0, 0, 0};
+  // loader: element e = tid + 256 u is row k = e % WY_K of column x = e / WY_K,
+  // so sixteen lanes read sixteen consecutive rows of one column
+  double ra[4], rb[4];
+  auto load = [&](int64_t k0) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = tid + 256 * u, k = e & (WY_K - 1), x = e / WY_K;
+      const int64_t gi = k0 + k;
+      const bool rin = gi < ihi;
+      ra[u] = (rin && a0 + x < c) ? yload(P, ldp, gi, a0 + x) : 0.0;
+      rb[u] = (rin && b0 + x < c) ? yload(P, ldp, gi, b0 + x) : 0.0;
+    }
+  };
+  load(ilo);
   for (int64_t k0 = ilo; k0 < ihi; k0 += WY_K) {
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int e = tid + 256 * u, k = e / WY_T, x = e % WY_T;
-      const int64_t gi = k0 + k;
-      const bool rin = gi < ihi;
-      Ya[k * WY_LD + x] = (rin && a0 + x < c) ? yload(P, ldp, gi, a0 + x) : 0.0;
-      Yb[k * WY_LD + x] = (rin && b0 + x < c) ? yload(P, ldp, gi, b0 + x) : 0.0;
+      const int e = tid + 256 * u, k = e & (WY_K - 1), x = e / WY_K;
+      Ya[k * GY_LD + x] = ra[u];
+      Yb[k * GY_LD + x] = rb[u];
     }
     __syncthreads();
+    if (k0 + WY_K < ihi) load(k0 + WY_K);
 #pragma unroll
     for (int kk = 0; kk < WY_K; kk += 4) {
       const int k = kk + (lane >> 4);
       double av[2], bv[2];
 #pragma unroll
-      for (int x = 0; x < 2; ++x) av[x] = Yb[k * WY_LD + wb * 32 + x * 16 + (lane & 15)];  // A(b, i)
+      for (int x = 0; x < 2; ++x) av[x] = Yb[k * GY_LD + wb * 32 + x * 16 + (lane & 15)];  // A(b, i)
 #pragma unroll
-      for (int y = 0; y < 2; ++y) bv[y] = Ya[k * WY_LD + wa * 32 + y * 16 + (lane & 15)];  // B(i, a)
+      for (int y = 0; y < 2; ++y) bv[y] = Ya[k * GY_LD + wa * 32 + y * 16 + (lane & 15)];  // B(i, a)
 #pragma unroll
       for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -917,6 +930,115 @@ __global__ __launch_bounds__(WM_NT) void wy_m_kernel(const T* __restrict__ P, in
   if (lane == 0) sgn[j] = sj;
 }
 
+// The same M' for c <= 512 as a blocked triangular solve: workgroup w
+// takes the sixteen right-hand sides j = 16 w .. 16 w + 15 with all their
+// rows in LDS, and walks the 16-row blocks from the one holding the largest
+// j up to the first.  A block's diagonal part is solved by sixteen lanes of
+// wave 0, lane jj holding the block's rows of column jj in registers (the
+// solve needs no lane exchange); the rows above are then updated at once,
+// r(0:k0, :) -= S(0:k0, block) m(block, :), on FP64 MFMA by all four waves.
+// The S columns of the next block are loaded while the current one is
+// worked on.
+constexpr int WB_NT = 256, WB_LD = 17;  // LDS row stride of the right-hand sides
+
+template <typename T>
+__global__ __launch_bounds__(WB_NT) void wy_m_blocked_kernel(const T* __restrict__ P, int c, int64_t ldp,
+                                                             const double* __restrict__ S,
+                                                             const double* __restrict__ taus,
+                                                             double* __restrict__ mt, double* __restrict__ sgn) {
+  extern __shared__ double smem[];
+  const int c16 = (c + 15) & ~15;
+  double* rl = smem;                         // rl[i * WB_LD + jj]: row i of right-hand side jj
+  double* sb = rl + (int64_t)c16 * WB_LD;    // sb[kk * c16 + i] = S(i, k0 + kk), i < k0 + kk
+  double* tl = sb + (int64_t)16 * c16;       // tau_k, zero past c
+  constexpr int PF = 32;                     // S loads per thread and block (16 c16 <= 256 PF for c <= 512)
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int j0 = blockIdx.x * 16, jn = min(16, c - j0);
+  // thread tid: right-hand side jj = tid % 16, rows tid / 16 + 16 x (all
+  // loads in flight together)
+  const int jj = tid & 15, ir = tid >> 4;
+  for (int k = tid; k < c16; k += WB_NT) tl[k] = k < c ? taus[k] : 0.0;
+  {
+    constexpr int RX = 512 / 16;
+    double v[RX];
+#pragma unroll
+    for (int x = 0; x < RX; ++x) {
+      const int i = ir + 16 * x;
+      v[x] = (jj < jn && i < c) ? yload(P, ldp, j0 + jj, i) : 0.0;
+    }
+#pragma unroll
+    for (int x = 0; x < RX; ++x)
+      if (ir + 16 * x < c16) rl[(ir + 16 * x) * WB_LD + jj] = v[x];
+  }
+  // S(0 : k0 + 16, k0 : k0 + 16) of block kb, element x of thread tid:
+  // column kk = x / 2, row i = tid + WB_NT (x % 2)
+  double pf[PF];
+  auto load_s = [&](int kb) {
+    const int k0 = kb * 16;
+#pragma unroll
+    for (int x = 0; x < PF; ++x) {
+      const int kk = x >> 1, i = tid + WB_NT * (x & 1), k = k0 + kk;
+      pf[x] = (i < k && k < c) ? S[(int64_t)k * c + i] : 0.0;
+    }
+  };
+  auto store_s = [&](int kb) {
+    const int k0 = kb * 16;
+#pragma unroll
+    for (int x = 0; x < PF; ++x) {
+      const int kk = x >> 1, i = tid + WB_NT * (x & 1);
+      if (i < k0 + 16) sb[kk * c16 + i] = pf[x];
+    }
+  };
+  const int nb = (j0 + jn - 1) / 16 + 1;
+  load_s(nb - 1);
+  for (int kb = nb - 1; kb >= 0; --kb) {
+    const int k0 = kb * 16;
+    __syncthreads();  // the previous block no longer reads sb; rl is up to date
+    store_s(kb);
+    if (kb > 0) load_s(kb - 1);
+    __syncthreads();
+    if (wave == 0 && lane < 16) {
+      double rr[16], tk[16];
+#pragma unroll
+      for (int t = 0; t < 16; ++t) {
+        rr[t] = rl[(k0 + t) * WB_LD + lane];
+        tk[t] = tl[k0 + t];
+      }
+#pragma unroll
+      for (int t = 15; t >= 0; --t) {
+        const double m = rr[t] * tk[t];
+        rr[t] = m;
+#pragma unroll
+        for (int i = 0; i < t; ++i) rr[i] = fma(-m, sb[t * c16 + k0 + i], rr[i]);
+      }
+#pragma unroll
+      for (int t = 0; t < 16; ++t) rl[(k0 + t) * WB_LD + lane] = rr[t];
+    }
+    __syncthreads();
+    // rows above: tile rows 16 tt .. 16 tt + 15; A = S(rows, block), B = m(block, :)
+    for (int tt = wave; tt < kb; tt += WB_NT / 64) {
+      MF::acc4 d = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int k4 = 0; k4 < 4; ++k4) {
+        const int kk = 4 * k4 + (lane >> 4);
+        d = MF::fma(sb[kk * c16 + 16 * tt + (lane & 15)], rl[(k0 + kk) * WB_LD + (lane & 15)], d);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * tt + MF::row(lane, r);
+        rl[i * WB_LD + (lane & 15)] -= d[r];
+      }
+    }
+  }
+  __syncthreads();
+  if (jj < jn) {
+    const int j = j0 + jj;
+    const double sj = ((double)P[(int64_t)j * ldp + j] < 0.0) ? -1.0 : 1.0;
+    for (int k = ir; k < c; k += 16) mt[(int64_t)k * c + j] = k <= j ? rl[k * WB_LD + jj] * sj : 0.0;
+    if (ir == 0) sgn[j] = sj;
+  }
+}
+
 // Q(i, j) = [i == j] sgn_j - sum_{k <= min(i, j)} Y(i, k) M'(k, j), with
 // M' = M diag(sgn) row-major (mt) and Y the unit lower trapezoidal
 // Householder vectors stored in P.  64 x 64 tiles of Q per workgroup, K in
@@ -942,19 +1064,31 @@ __global__ __launch_bounds__(256) void wy_apply_kernel(const T* __restrict__ P, 
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = MF::acc4{0, 0, 0, 0};
-  for (int k0 = 0; k0 < kmax; k0 += WY_K) {
-    __syncthreads();
+  // the next K step is loaded into registers while the current one is computed
+  double yr[4], mr[4];
+  auto load = [&](int k0) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int e = tid + 256 * u, k = e / WY_T, x = e % WY_T;
       const int64_t gk = k0 + k, gi = i0 + x;
       double yv = 0.0;
       if (gk < kmax && gi < mrows) yv = gi < gk ? 0.0 : (gi == gk ? 1.0 : (double)P[gk * ldp + gi]);
-      Ys[k * WY_LD + x] = yv;
+      yr[u] = yv;
       const int gj = j0 + x;
-      Ms[k * WY_LD + x] = (gk < kmax && gj < c) ? mt[gk * c + gj] : 0.0;
+      mr[u] = (gk < kmax && gj < c) ? mt[gk * c + gj] : 0.0;
+    }
+  };
+  load(0);
+  for (int k0 = 0; k0 < kmax; k0 += WY_K) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = tid + 256 * u, k = e / WY_T, x = e % WY_T;
+      Ys[k * WY_LD + x] = yr[u];
+      Ms[k * WY_LD + x] = mr[u];
     }
     __syncthreads();
+    if (k0 + WY_K < kmax) load(k0 + WY_K);
 #pragma unroll
     for (int kk = 0; kk < WY_K; kk += 4) {
       const int k = kk + (lane >> 4);
@@ -1124,6 +1258,19 @@ hipError_t tall_qr(T* P, int64_t mrows, int64_t c, int64_t ldp, T* Qout, int64_t
   gram_y_kernel<T><<<dim3((unsigned)(nt * (nt + 1) / 2), (unsigned)nsplit), 256, 0, s>>>(P, mrows, ci, ldp, chunk,
                                                                                         spart);
   gram_sum_kernel<<<(unsigned)((c * c + 255) / 256), 256, 0, s>>>(spart, nsplit, ci, S);
+  if (ci <= 512) {
+    const size_t blds = ((size_t)((ci + 15) & ~15) * (WB_LD + 16 + 1)) * sizeof(double);
+    const void* bfn = (const void*)wy_m_blocked_kernel<T>;
+    if (blds > 65536) {
+      e = hipFuncSetAttribute(bfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)blds);
+      if (e != hipSuccess) return e;
+    }
+    const double* taus_b = sl.taus;
+    const double* S_b = S;
+    void* bargs[] = {(void*)&P, (void*)&ci, (void*)&ldp, (void*)&S_b, (void*)&taus_b, (void*)&mt, (void*)&sgn};
+    e = hipLaunchKernel(bfn, dim3((unsigned)((ci + 15) / 16)), dim3(WB_NT), bargs, blds, s);
+    if (e != hipSuccess) return e;
+  } else {
   int msb = ci <= 512 ? 32 : 16;
   const size_t mlds = (size_t)msb * ci * sizeof(double);
   const unsigned mgrid = (unsigned)((c + WM_NT / 64 - 1) / (WM_NT / 64));
@@ -1141,6 +1288,7 @@ hipError_t tall_qr(T* P, int64_t mrows, int64_t c, int64_t ldp, T* Qout, int64_t
   void* margs[] = {(void*)&P, (void*)&ci, (void*)&ldp, (void*)&msb, (void*)&S_c, (void*)&taus_c, (void*)&mt, (void*)&sgn};
   e = hipLaunchKernel(mfn, dim3(mgrid), dim3(WM_NT), margs, mlds, s);
   if (e != hipSuccess) return e;
+  }
   dim3 grid((unsigned)((mrows + WY_T - 1) / WY_T), (unsigned)nt);
   wy_apply_kernel<T><<<grid, 256, 0, s>>>(P, mrows, ci, ldp, mt, sgn, Qout, ldq);
   return hipGetLastError();
