@@ -108,9 +108,12 @@ __device__ __forceinline__ void yt_times_global(const double* Yl, int ldy, int n
 
 // X(r0 + i, col) -= sum_s Y(i, s) W(s, col) for the own rows i < nrow and
 // col < ncol, W(s, col) = Wl[col * NB + s] in LDS.  A wave takes batches of
-// TB row tiles of one 16-column tile; the accumulator starts as the tile of
-// X and A = -Y.  The next batch is loaded while the current one is computed
-// and stored; loads use clamped addresses (no branches), stores are masked.
+// TB row tiles of one 16-column tile.  The MFMA computes the transposed
+// tile, D(col, i) = X(i, col) - sum_s W(s, col) Y(i, s) (A = W^T, B = -Y^T),
+// so that sixteen lanes hold sixteen consecutive rows of one column: every
+// load and store instruction covers four whole 128-byte runs of X.  The next
+// batch is loaded while the current one is computed and stored; loads use
+// clamped addresses (no branches), stores are masked.
 template <typename T>
 __device__ __forceinline__ void sub_y_times(const double* Yl, int ldy, int nrow, const double* Wl, T* X, int64_t ldx,
                                             int64_t r0, int ncol) {
@@ -122,37 +125,40 @@ __device__ __forceinline__ void sub_y_times(const double* Yl, int ldy, int nrow,
   if (wave >= total) return;
   auto load = [&](int k, MF::acc4* acc) {
     const int tc = k / nbt, tr0 = (k % nbt) * TB;
-    const int col = min(tc * 16 + lo, ncol - 1);
-    const T* xc = X + (int64_t)col * ldx + r0;
 #pragma unroll
-    for (int b = 0; b < TB; ++b)
+    for (int r = 0; r < 4; ++r) {
+      const int col = min(tc * 16 + MF::row(lane, r), ncol - 1);
+      const T* xc = X + (int64_t)col * ldx + r0;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) acc[b][r] = (double)xc[min((tr0 + b) * 16 + MF::row(lane, r), nrow - 1)];
+      for (int b = 0; b < TB; ++b) acc[b][r] = (double)xc[min((tr0 + b) * 16 + lo, nrow - 1)];
+    }
   };
   auto work = [&](int k, MF::acc4* acc) {
     const int tc = k / nbt, tr0 = (k % nbt) * TB;
-    const int col = tc * 16 + lo;
-    const bool cin = col < ncol;
-    double bw[NB / 4];
+    const int wcol = tc * 16 + lo;  // A(m = lo, k = kq) = W(4 k4 + kq, wcol)
+    const bool win = wcol < ncol;
+    double aw[NB / 4];
 #pragma unroll
-    for (int k4 = 0; k4 < NB / 4; ++k4) bw[k4] = cin ? Wl[(int64_t)col * NB + 4 * k4 + kq] : 0.0;
+    for (int k4 = 0; k4 < NB / 4; ++k4) aw[k4] = win ? Wl[(int64_t)wcol * NB + 4 * k4 + kq] : 0.0;
 #pragma unroll
     for (int b = 0; b < TB; ++b) {
-      const int ia = (tr0 + b) * 16 + lo;
+      const int ib = (tr0 + b) * 16 + lo;
 #pragma unroll
       for (int k4 = 0; k4 < NB / 4; ++k4) {
-        const double av = ia < nrow ? -Yl[(4 * k4 + kq) * ldy + ia] : 0.0;  // A[row = lo][k = kq]
-        acc[b] = MF::fma(av, bw[k4], acc[b]);
+        const double bv = ib < nrow ? -Yl[(4 * k4 + kq) * ldy + ib] : 0.0;  // B(k = kq, n = lo)
+        acc[b] = MF::fma(aw[k4], bv, acc[b]);
       }
     }
-    T* xc = X + (int64_t)(cin ? col : 0) * ldx + r0;
 #pragma unroll
-    for (int b = 0; b < TB; ++b)
+    for (int r = 0; r < 4; ++r) {
+      const int col = tc * 16 + MF::row(lane, r);
+      T* xc = X + (int64_t)(col < ncol ? col : 0) * ldx + r0;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = (tr0 + b) * 16 + MF::row(lane, r);
-        if (cin && i < nrow) xc[i] = (T)acc[b][r];
+      for (int b = 0; b < TB; ++b) {
+        const int i = (tr0 + b) * 16 + lo;
+        if (col < ncol && i < nrow) xc[i] = (T)acc[b][r];
       }
+    }
   };
   MF::acc4 ta[TB], tb[TB];
   load(wave, ta);
