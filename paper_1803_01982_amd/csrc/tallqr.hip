@@ -29,6 +29,7 @@
 // that make diag(R) >= 0 folded in; Q = [I; 0] diag(sgn) - Y M.  All
 // arithmetic is FP64; P and Q are stored as T.
 #include <algorithm>
+#include <type_traits>
 
 #include "common.hpp"
 #include "kernels.hpp"
@@ -60,10 +61,11 @@ __device__ inline double yval(int64_t gi, int64_t p0, int s, double stored) {
 // Posts out[col * NB + s] = sum over the own rows i of Y(i, s) * X(r0 + i, col),
 // col < ncol, s < NB; X is column-major in global memory (ldx).  One wave
 // per 16-column chunk; MFMA 16x16x4 with A = Y^T from LDS and B = X from
-// global memory.  The rows go in blocks of 32 (eight MFMA K steps) with the
-// loads of the next block in flight during the current one; every load is
-// issued at a clamped address (row < nrow, col < ncol) and rows past nrow
-// get a zero A operand, so no load sits behind a branch.
+// global memory.  The rows go in groups of four 32-row blocks (32 MFMA K
+// steps; the tail in groups of two and one) whose loads are all in flight
+// together; every load is issued at a clamped address (row < nrow,
+// col < ncol) and rows past nrow get a zero A operand, so no load sits
+// behind a branch.
 template <typename T>
 __device__ __forceinline__ void yt_times_global(const double* Yl, int ldy, int nrow, const T* X, int64_t ldx,
                                                 int64_t r0, int ncol, uint64_t* out) {
@@ -78,27 +80,31 @@ __device__ __forceinline__ void yt_times_global(const double* Yl, int ldy, int n
     MF::acc4 a[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) a[q] = MF::acc4{0, 0, 0, 0};
-    double xa[8], xb[8];
-    auto load = [&](double* x, int blk) {
+    // groups of four (then two, then one) 32-row blocks: all loads of a
+    // group in flight together, no branch inside a group
+    auto group = [&](auto gq, int bg) {
+      constexpr int GQ = decltype(gq)::value;
+      double x[GQ][8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) x[u] = (double)xc[min(32 * blk + 4 * u + kq, nrow - 1)];
-    };
-    auto mma = [&](const double* x, int blk) {
+      for (int q = 0; q < GQ; ++q)
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int i = 32 * blk + 4 * u + kq;
-        const double ya = i < nrow ? yc[i] : 0.0;
-        a[u & 3] = MF::fma(ya, cin ? x[u] : 0.0, a[u & 3]);
-      }
+        for (int u = 0; u < 8; ++u) x[q][u] = (double)xc[min(32 * (bg + q) + 4 * u + kq, nrow - 1)];
+#pragma unroll
+      for (int q = 0; q < GQ; ++q)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int i = 32 * (bg + q) + 4 * u + kq;
+          const double ya = i < nrow ? yc[i] : 0.0;
+          a[u & 3] = MF::fma(ya, cin ? x[q][u] : 0.0, a[u & 3]);
+        }
     };
-    load(xa, 0);
-    for (int blk = 0; blk < nblk; blk += 2) {
-      load(xb, min(blk + 1, nblk - 1));
-      mma(xa, blk);
-      if (blk + 1 >= nblk) break;
-      load(xa, min(blk + 2, nblk - 1));
-      mma(xb, blk + 1);
+    int bg = 0;
+    for (; bg + 4 <= nblk; bg += 4) group(std::integral_constant<int, 4>{}, bg);
+    if (bg + 2 <= nblk) {
+      group(std::integral_constant<int, 2>{}, bg);
+      bg += 2;
     }
+    if (bg < nblk) group(std::integral_constant<int, 1>{}, bg);
     if (cin)
 #pragma unroll
       for (int r = 0; r < 4; ++r)
@@ -291,13 +297,14 @@ __device__ bool reduce_z(const uint64_t* zpart, uint64_t* zred, int64_t E, int G
     post_u64(zred + e0 + el, slot_bits(t));
   }
   __syncthreads();  // Zl is overwritten below
-  for (int64_t b = 0; b < E && ok; b += (int64_t)NT * RB) {
+  constexpr int GB = 24;  // gather batch: E <= 24 NT entries (l <= 368) in one round trip
+  for (int64_t b = 0; b < E && ok; b += (int64_t)NT * GB) {
     const int64_t e = b + threadIdx.x;
-    const int n = e < E ? (int)min((int64_t)RB, (E - e + NT - 1) / NT) : 0;
-    double v[RB];
-    if (n > 0) ok = poll_vals<RB>(zred + e, NT, n, error, v);
+    const int n = e < E ? (int)min((int64_t)GB, (E - e + NT - 1) / NT) : 0;
+    double v[GB];
+    if (n > 0) ok = poll_vals<GB>(zred + e, NT, n, error, v);
 #pragma unroll
-    for (int u = 0; u < RB; ++u)
+    for (int u = 0; u < GB; ++u)
       if (u < n) Zl[e + (int64_t)u * NT] = v[u];
   }
   return !__syncthreads_or(!ok);
