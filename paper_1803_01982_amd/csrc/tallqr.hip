@@ -5,29 +5,35 @@
 //   * the flip-flop step, QR of R^T (n x l) (Section 3.1).
 //
 // One cooperative launch factors the matrix.  Workgroup g owns the row block
-// [g*rb, (g+1)*rb).  Columns are processed in panels of NB = 16:
-//   column step (no grid barrier): every workgroup posts the partial dot
-//     products of the current column with the remaining panel columns over
-//     its rows (and the owner of the pivot row posts that row) to write-once
-//     slots of the column; every workgroup polls the slots, sums the
-//     partials in the same fixed order, builds the same reflector (LAPACK
-//     xLARFG convention) and updates its own rows of the panel columns,
-//     which stay in registers for the whole panel;
-//   panel end (two grid barriers): Z = Y_p^T [Y_p | P_trail] is reduced
-//     (reduce-scatter, then every workgroup reads the whole Z), each
-//     workgroup forms the panel's T_p (LAPACK xLARFT, forward, columnwise)
-//     from the Gram part and applies P_trail -= Y_p (T_p^T (Y_p^T P_trail))
-//     to its own rows.
-// Within a panel the rows of the 16 columns stay in registers.
+// [g*rb, (g+1)*rb); the rows of the current 16-column panel stay in
+// registers.  Workgroups exchange data only through write-once slots (no
+// grid barrier).  Per panel of NB = 16 columns:
+//   reflectors: every workgroup posts the Gram matrix of the panel columns
+//     over its active rows (rows >= p0), and the owners of rows p0 .. p1-1
+//     post those rows (B).  The Grams are summed in a fixed order (two
+//     levels), and every workgroup runs the panel's Householder steps (LAPACK
+//     xLARFG convention) on (G, B) itself: the Gram matrix over the active
+//     rows is invariant under the reflectors, so the dots of column j with
+//     the later columns below row jc are G(j, s) minus the products over the
+//     top rows 0 .. j of B, which the recurrence keeps transformed.  Each
+//     workgroup then applies the reflectors to its own rows.  A column whose
+//     remaining squared norm would be recovered with a cancellation worse
+//     than 1/16 of G(j, j) stops the recurrence; it and the rest of the
+//     panel take one exact reduction per column (partial dots posted to
+//     slots, summed in a fixed order);
+//   panel end: Z = Y_p^T [Y_p | P_trail] is reduce-scattered and gathered
+//     through slots, each workgroup forms the panel's T_p (LAPACK xLARFT,
+//     forward, columnwise) from the Gram part and applies
+//     P_trail -= Y_p (T_p^T (Y_p^T P_trail)) to its own rows.
 //
 // Q = H_1 ... H_c [I; 0] = [I; 0] - Y T Y(0:c, :)^T (compact WY form of the
 // whole product, Section 2.1) is then formed by three tiled kernels over the
 // whole chip instead of panel by panel: S = Y^T Y (split over row chunks,
-// then summed in a fixed order); M = T Y(0:c, :)^T by triangular solves with
-// T^-1 = striu(S) + diag(1/tau) (the identity behind the compact WY form;
-// tau = 0 drops the reflector), one workgroup per column, with the signs
-// that make diag(R) >= 0 folded in; Q = [I; 0] diag(sgn) - Y M.  All
-// arithmetic is FP64; P and Q are stored as T.
+// then summed in a fixed order); M = T Y(0:c, :)^T by blocked back
+// substitution with T^-1 = striu(S) + diag(1/tau) (the identity behind the
+// compact WY form; tau = 0 drops the reflector), with the signs that make
+// diag(R) >= 0 folded in; Q = [I; 0] diag(sgn) - Y M.  All arithmetic is
+// FP64; P and Q are stored as T.
 #include <algorithm>
 #include <type_traits>
 
@@ -1204,7 +1210,7 @@ size_t tallqr_scratch(int64_t mrows, int64_t c, const DeviceInfo& d) {
   size_t b = sizeof(double) * (npan * G * NB * NB + npan * ngrp * NB * NB + (size_t)c * NB + (size_t)c * G * NB +
                                (size_t)c * NB + ((size_t)G + 1) * z_entries(c) + c +
                                ((size_t)nsplit + 2) * c * c + c);
-  return b + kSyncWords * sizeof(unsigned) + 16 * 256;
+  return b + 16 * 256;
 }
 
 template <typename T>
@@ -1235,11 +1241,10 @@ hipError_t tall_qr(T* P, int64_t mrows, int64_t c, int64_t ldp, T* Qout, int64_t
   double* S = ar.take<double>((size_t)c * c);
   double* mt = ar.take<double>((size_t)c * c);
   double* sgn = ar.take<double>((size_t)c);
-  unsigned* counter = ar.take<unsigned>(kSyncWords);
-  if (!sl.gram || !sl.gram2 || !sl.dots || !sl.rowv || !sl.rowv2 || !sl.zpart || !sl.zred || !sl.taus || !spart || !S || !mt || !sgn || !counter)
+  if (!sl.gram || !sl.gram2 || !sl.dots || !sl.rowv || !sl.rowv2 || !sl.zpart || !sl.zred || !sl.taus || !spart ||
+      !S || !mt || !sgn)
     return hipErrorOutOfMemory;
-  hipError_t e = zero_words(counter, kSyncWords, s);
-  if (e == hipSuccess) e = fill_void(sl.gram, (size_t)npan * G * NB * NB, s);
+  hipError_t e = fill_void(sl.gram, (size_t)npan * G * NB * NB, s);
   if (e == hipSuccess) e = fill_void(sl.gram2, (size_t)npan * ngrp * NB * NB, s);
   if (e == hipSuccess) e = fill_void(sl.zpart, (size_t)G * zall, s);
   if (e == hipSuccess) e = fill_void(sl.zred, zall, s);
@@ -1248,7 +1253,7 @@ hipError_t tall_qr(T* P, int64_t mrows, int64_t c, int64_t ldp, T* Qout, int64_t
   if (e == hipSuccess) e = fill_void(sl.rowv2, (size_t)c * NB, s);
   if (e != hipSuccess) return e;
   if (G > kMaxGridBlocks) return hipErrorInvalidValue;
-  GridSync gs{counter, err, (unsigned)G};
+  GridSync gs{nullptr, err, (unsigned)G};  // the kernel only uses the error word (no grid barrier)
   int ci = (int)c, tr = transpose_r ? 1 : 0;
   void* args[] = {(void*)&P, (void*)&mrows, (void*)&ci, (void*)&ldp, (void*)&rb, (void*)&Qout, (void*)&ldq,
                   (void*)&R, (void*)&ldr, (void*)&tr, (void*)&sl, (void*)&gs};
