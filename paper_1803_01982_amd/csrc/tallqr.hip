@@ -1244,13 +1244,9 @@ hipError_t tall_qr(T* P, int64_t mrows, int64_t c, int64_t ldp, T* Qout, int64_t
   if (!sl.gram || !sl.gram2 || !sl.dots || !sl.rowv || !sl.rowv2 || !sl.zpart || !sl.zred || !sl.taus || !spart ||
       !S || !mt || !sgn)
     return hipErrorOutOfMemory;
-  hipError_t e = fill_void(sl.gram, (size_t)npan * G * NB * NB, s);
-  if (e == hipSuccess) e = fill_void(sl.gram2, (size_t)npan * ngrp * NB * NB, s);
-  if (e == hipSuccess) e = fill_void(sl.zpart, (size_t)G * zall, s);
-  if (e == hipSuccess) e = fill_void(sl.zred, zall, s);
-  if (e == hipSuccess) e = fill_void(sl.dots, (size_t)c * G * NB, s);
-  if (e == hipSuccess) e = fill_void(sl.rowv, (size_t)c * NB, s);
-  if (e == hipSuccess) e = fill_void(sl.rowv2, (size_t)c * NB, s);
+  // the slot arrays were carved one after the other (gram .. zred): one fill
+  // covers them and the alignment gaps between them
+  hipError_t e = fill_void(sl.gram, (size_t)(sl.zred + zall - sl.gram), s);
   if (e != hipSuccess) return e;
   if (G > kMaxGridBlocks) return hipErrorInvalidValue;
   GridSync gs{nullptr, err, (unsigned)G};  // the kernel only uses the error word (no grid barrier)

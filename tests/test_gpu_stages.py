@@ -116,8 +116,11 @@ def test_qrcp_orthogonal_columns(ff):
 
 
 # --------------------------------------------------------- Householder QR
+# c = 512 is the widest panel set whose M goes through the blocked back
+# substitution; c = 520 takes the column-per-wave kernel
 @pytest.mark.parametrize("m,n,c,seed", [(1000, 800, 30, 1), (1000, 800, 37, 2), (300, 50, 5, 3),
-                                        (5000, 400, 100, 4), (64, 64, 64, 5), (16384, 300, 17, 6)])
+                                        (5000, 400, 100, 4), (64, 64, 64, 5), (16384, 300, 17, 6),
+                                        (1100, 600, 512, 8), (1300, 600, 520, 9)])
 def test_panel_qr_fp64(ff, m, n, c, seed):
     import torch
     announce(f"panel_qr fp64 m={m} n={n} c={c}")
