@@ -780,7 +780,8 @@ __device__ inline double yload(const T* P, int64_t ldp, int64_t i, int64_t k) {
 
 // Partial Gram S = Y^T Y over one chunk of rows for one 64 x 64 tile pair
 // (I <= J) of the c x c result: spart[split][b * c + a] = sum_{i in chunk}
-// Y(i, a) Y(i, b).  Same LDS tiling as the WY product below.
+// Y(i, a) Y(i, b).  K steps of 16 rows through LDS, loaded along the rows
+// (sixteen lanes on one column) and one step ahead into registers.
 constexpr int WY_T = 64, WY_K = 16, WY_LD = WY_T + 16;
 
 template <typename T>
@@ -1061,7 +1062,8 @@ __global__ __launch_bounds__(WB_NT) void wy_m_blocked_kernel(const T* __restrict
 // Q(i, j) = [i == j] sgn_j - sum_{k <= min(i, j)} Y(i, k) M'(k, j), with
 // M' = M diag(sgn) row-major (mt) and Y the unit lower trapezoidal
 // Householder vectors stored in P.  64 x 64 tiles of Q per workgroup, K in
-// steps of 16 through LDS; the MFMA computes the transposed tile
+// steps of 16 through LDS, the next step loaded into registers while the
+// current one is computed; the MFMA computes the transposed tile
 // (A = M'^T, B = Y^T) so that each result row is a run of 16 consecutive
 // entries of a column of Q.  Column tiles stop at K = j0 + 64 (M' is upper
 // triangular), row tiles at K = i0 + 64 (Y is lower trapezoidal).
