@@ -25,7 +25,9 @@ from .ffsrqr import (
     FLAG_NONFINITE,
     FLAG_RANK_DEFICIENT,
     FLAG_SWAPCAP,
+    Alg9,
     Result,
+    alg9,
     back_substitute,
     factor_leading_set,
     ffsrqr,
@@ -35,7 +37,9 @@ from .ffsrqr import (
     jacobi_svd,
     project,
     qrcp_sketch,
+    residual_margin,
     residual_norms,
+    round_bf16,
     sketch,
     srqr_rho,
     upper_inverse,
@@ -44,8 +48,9 @@ from . import diagnostics
 
 __all__ = [
     "omega", "philox4x64_10", "uniform_open", "FLAG_L_CLAMPED", "FLAG_NONFINITE",
-    "FLAG_RANK_DEFICIENT", "FLAG_SWAPCAP", "Result", "back_substitute",
+    "FLAG_RANK_DEFICIENT", "FLAG_SWAPCAP", "Alg9", "Result", "alg9", "back_substitute",
     "factor_leading_set", "ffsrqr", "flip_flop_lq", "householder", "householder_qr",
-    "jacobi_svd", "project", "qrcp_sketch", "residual_norms", "sketch", "srqr_rho",
+    "jacobi_svd", "project", "qrcp_sketch", "residual_margin", "residual_norms", "round_bf16",
+    "sketch", "srqr_rho",
     "upper_inverse", "diagnostics",
 ]

@@ -11,7 +11,10 @@ blocked, fused or reordered.  All arithmetic is FP64.
 Steps (Feng, Xiao & Gu, "Low-Rank Matrix Approximations with Flip-Flop
 Spectrum-Revealing QR Factorization"):
 
-  sketch       Algorithm 2 (TRQRCP), first two steps: B = Omega A.
+  sketch       Algorithm 2 (TRQRCP), first two steps: B = Omega A; in the
+               "bf16" mode both factors are first rounded to bfloat16 and the
+               exact products are summed in FP64 (the mixed-precision form's
+               definition of the sample matrix).
   qrcp_sketch  Algorithm 1 (Partial QRCP) run for l steps on B; pivots only.
   qr_panel     Householder QR without pivoting of A(:, S) (Algorithm 2, the
                "QR on the pivoted block" step; compact-WY form in Section 2.1),
@@ -24,6 +27,10 @@ Spectrum-Revealing QR Factorization"):
   ffsrqr       Algorithm 4 (SRQR) swap loop around the above, then Section
                3.1: QR without pivoting of (R11 R12)^T, L = Rhat11^T,
                V = Pi Qhat1, and sigma(L) by one-sided Jacobi.
+  alg9         Algorithm 9, last three steps: tmp = A Pi Qhat1 = A V, its thin
+               SVD (Householder QR of tmp, then one-sided Jacobi with vectors
+               on the triangular factor), U = U_tmp(:, 1:k), Sigma_k and
+               V_k = Pi Qhat1 V_tmp(:, 1:k).
 
 Readings of the paper taken here (each is listed with its reason in the
 design notes):
@@ -95,9 +102,34 @@ def omega(seed: int, l: int, m: int) -> np.ndarray:
     return _omega(seed, l, m)
 
 
-def sketch(Omega: np.ndarray, A: np.ndarray) -> np.ndarray:
-    """B = Omega A (Algorithm 2: form the initial sample matrix)."""
-    return Omega @ np.asarray(A, dtype=np.float64)
+def round_bf16(x) -> np.ndarray:
+    """Each FP64 value rounded to the nearest bfloat16 value, ties to even.
+
+    bfloat16 keeps 8 significant bits and the FP32 exponent range, so near
+    x = f 2^e (1/2 <= |f| < 1) its values are spaced 2^(e-8) apart, and
+    2^-133 apart below 2^-126 (subnormals).  The rounding is taken from the
+    FP64 value directly (not through FP32, which could round twice).
+    Finite inputs below the bfloat16 overflow threshold only.
+    """
+    x = np.asarray(x, dtype=np.float64)
+    _, e = np.frexp(x)
+    q = np.ldexp(1.0, np.maximum(e, -125) - 8)
+    return np.rint(x / q) * q
+
+
+def sketch(Omega: np.ndarray, A: np.ndarray, mode: str = "fp64") -> np.ndarray:
+    """B = Omega A (Algorithm 2: form the initial sample matrix).
+
+    mode "fp64": FP64 product.  mode "bf16": B = bf16(Omega) bf16(A), i.e.
+    B_ij = sum_t bf16(Omega_it) bf16(A_tj) with every product exact in FP64
+    (8 x 8 significant bits) and the sum taken in FP64.
+    """
+    A = np.asarray(A, dtype=np.float64)
+    if mode == "fp64":
+        return Omega @ A
+    if mode == "bf16":
+        return round_bf16(Omega) @ round_bf16(A)
+    raise ValueError(f"unknown sketch mode {mode!r}")
 
 
 # ---------------------------------------------------------------------------
@@ -324,10 +356,12 @@ class Result:
     alpha: float            # residual norm of the (l+1)-st column
     jstar: int              # original index of that column
     margins: np.ndarray     # QRCP-on-B margins per step
+    jstar_margin: float     # (gamma_max^2 - gamma_2nd^2) / gamma_max^2 at the final test
     flags: int
     numerical_rank: int
     B: np.ndarray           # sketch (l x n)
     history: list           # [(S, g2, jstar, alpha)] per SRQR test
+    sketch_mode: str = "fp64"
 
 
 def _full_perm(S, n):
@@ -351,9 +385,23 @@ def factor_leading_set(A: np.ndarray, S):
     return perm, Q1, R11, R, W
 
 
+def residual_margin(gam: np.ndarray) -> float:
+    """(gamma_max^2 - gamma_2nd^2) / gamma_max^2 over the trailing columns
+    (1 when there is one column, 0 when the largest is zero)."""
+    if gam.shape[0] < 2:
+        return 1.0
+    g2 = np.sort(gam * gam)
+    return float((g2[-1] - g2[-2]) / g2[-1]) if g2[-1] > 0 else 0.0
+
+
 def ffsrqr(A: np.ndarray, k: int, p: int, seed: int, g: float = 2.0,
-           max_swaps: int | None = None, Omega: np.ndarray | None = None) -> Result:
-    """Flip-Flop SRQR hot path, FP64 (Algorithm 9 up to the LQ, Algorithm 4 inside)."""
+           max_swaps: int | None = None, Omega: np.ndarray | None = None,
+           sketch_mode: str = "fp64") -> Result:
+    """Flip-Flop SRQR hot path, FP64 (Algorithm 9 up to the LQ, Algorithm 4 inside).
+
+    sketch_mode selects the arithmetic of B = Omega A ("fp64" or "bf16", see
+    sketch()); every later step is FP64 on the same A.
+    """
     A = np.asarray(A)
     m, n = A.shape
     if not (1 <= k <= min(m, n)) or p < 0 or not g > 1.0:
@@ -372,14 +420,14 @@ def ffsrqr(A: np.ndarray, k: int, p: int, seed: int, g: float = 2.0,
         return Result(perm=np.arange(n, dtype=np.int64), Q=np.full((m, l), nan),
                       R=np.full((l, n), nan), L=np.full((l, l), nan), V=np.full((n, l), nan),
                       sigma=np.full(l, nan), l=l, swaps=0, g2=nan, alpha=nan, jstar=-1,
-                      margins=np.zeros(l), flags=flags, numerical_rank=0,
-                      B=np.full((l, n), nan), history=[])
+                      margins=np.zeros(l), jstar_margin=0.0, flags=flags, numerical_rank=0,
+                      B=np.full((l, n), nan), history=[], sketch_mode=sketch_mode)
     colnorm = np.sqrt(np.sum(Af * Af, axis=0))
     tau_r = max(m, n) * 2.0 ** -52 * float(colnorm.max())
 
     # a1
     Om = omega(seed, l, m) if Omega is None else Omega
-    B = sketch(Om, Af)
+    B = sketch(Om, Af, sketch_mode)
     # a2
     pivots, margins, _ = qrcp_sketch(B, l)
     S = [int(s) for s in pivots[:l]]
@@ -387,6 +435,7 @@ def ffsrqr(A: np.ndarray, k: int, p: int, seed: int, g: float = 2.0,
     swaps = 0
     history = []
     numerical_rank = l
+    jmargin = 1.0
     while True:
         # a3 + a4
         perm, Q1, R11, R, W = factor_leading_set(Af, S)
@@ -399,6 +448,7 @@ def ffsrqr(A: np.ndarray, k: int, p: int, seed: int, g: float = 2.0,
             jpos = int(cands[np.argmin(trailing[cands])])
             jstar = int(trailing[jpos])
             alpha = float(gmax)
+            jmargin = residual_margin(gam)
             dR = np.abs(np.diag(R11))
             if alpha <= tau_r or dR.min() <= tau_r:
                 flags |= FLAG_RANK_DEFICIENT
@@ -427,5 +477,38 @@ def ffsrqr(A: np.ndarray, k: int, p: int, seed: int, g: float = 2.0,
     # a7
     sigma, _ = jacobi_svd(L)
     return Result(perm=perm, Q=Q1, R=R, L=L, V=V, sigma=sigma, l=l, swaps=swaps,
-                  g2=g2, alpha=alpha, jstar=jstar, margins=margins, flags=flags,
-                  numerical_rank=numerical_rank, B=B, history=history)
+                  g2=g2, alpha=alpha, jstar=jstar, margins=margins, jstar_margin=jmargin,
+                  flags=flags, numerical_rank=numerical_rank, B=B, history=history,
+                  sketch_mode=sketch_mode)
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 9 completion: rank-k approximate SVD from the flip-flop factors
+# ---------------------------------------------------------------------------
+@dataclasses.dataclass
+class Alg9:
+    U: np.ndarray           # m x k, orthonormal columns
+    sigma: np.ndarray       # [k] leading singular values of A Pi Qhat1, descending
+    V: np.ndarray           # n x k, Pi Qhat1 V_tmp(:, 1:k)
+    sigma_all: np.ndarray   # [l] all singular values of tmp
+
+
+def alg9(A: np.ndarray, res: Result, k: int) -> Alg9:
+    """Last three steps of Algorithm 9 on the result of ffsrqr().
+
+    tmp = A Pi Qhat1; since V = Pi Qhat1 this is A V (m x l).  Its thin SVD
+    is taken as tmp = Q_t R_t (Householder QR), R_t V_t = U_R diag(s) (one-
+    sided Jacobi with accumulated rotations), U_tmp = Q_t U_R.  Returns
+    U = U_tmp(:, 1:k), sigma = s(1:k), V_k = V V_t(:, 1:k).  Column signs are
+    normalised so that the largest-magnitude entry of each column of U_k is
+    positive (the SVD fixes the pairs (u_j, v_j) only up to a common sign).
+    """
+    A = np.asarray(A, dtype=np.float64)
+    tmp = A @ res.V
+    Qt, Rt = householder_qr(tmp)
+    s, UR, VR, _ = jacobi_svd(Rt, want_vectors=True)
+    U = Qt @ UR[:, :k]
+    Vk = res.V @ VR[:, :k]
+    idx = np.argmax(np.abs(U), axis=0)
+    sg = np.where(U[idx, np.arange(k)] < 0, -1.0, 1.0)
+    return Alg9(U=U * sg, sigma=s[:k].copy(), V=Vk * sg, sigma_all=s)

@@ -17,6 +17,11 @@ Recipes (all seeded, FP64 arithmetic, optionally rounded to FP32 storage):
     k=20, p=10, sketch seed 0.
   - ``mid``         : m=16384, n=8192, r=1024, sigma_j = exp(-j/50),
     noise 1e-6, k=256, p=16, sketch seed 0.
+  - ``large``       : m=32768, n=16384, r=1024, sigma_j = 1 for j <= 8 and
+    10^(-3 (j - 8) / 1000) for 8 < j <= 1024, noise 1e-5, k=512, p=32
+    (l = 544), sketch seed 0; meant for FP32 storage.
+  - ``large_q``     : the same spectrum and k, p at a quarter of the size
+    (8192 x 4096), small enough for the oracle to run whole.
 """
 from __future__ import annotations
 
@@ -108,12 +113,17 @@ class Workload:
         if self.spectrum == "exp50_r1024":
             j = np.arange(1, 1025, dtype=np.float64)
             return np.exp(-j / 50.0)
+        if self.spectrum == "flat8_decade3_r1024":
+            j = np.arange(1, 1025, dtype=np.float64)
+            return np.where(j <= 8, 1.0, 10.0 ** (-3.0 * (j - 8) / 1000.0))
         raise KeyError(self.spectrum)
 
 
 WORKLOADS = {
     "small_fp64": Workload("small_fp64", 1000, 800, 20, 10, 0, 1, "inv_square", 0.0),
     "mid": Workload("mid", 16384, 8192, 256, 16, 0, 2, "exp50_r1024", 1e-6),
+    "large": Workload("large", 32768, 16384, 512, 32, 0, 3, "flat8_decade3_r1024", 1e-5),
+    "large_q": Workload("large_q", 8192, 4096, 512, 32, 0, 3, "flat8_decade3_r1024", 1e-5),
 }
 
 

@@ -11,6 +11,8 @@ import numpy as np
 import pytest
 
 import oracle
+import test_oracle_alg9 as ALG9
+import test_oracle_bf16 as BF16
 import test_oracle_linalg as LIN
 import test_oracle_path as PATH
 
@@ -50,6 +52,12 @@ def _pins():
         ("bounds", lambda: PATH.test_singular_value_bounds(_small(), "small")),
         ("kahan_swaps", PATH.test_srqr_swaps_kahan),
         ("tight_g", PATH.test_tighter_g_swaps_until_satisfied),
+        ("bf16_brute", BF16.test_round_bf16_matches_exhaustive_search_on_doubles),
+        ("bf16_ties", BF16.test_round_bf16_ties_and_double_rounding),
+        ("bf16_sketch", BF16.test_bf16_sketch_is_the_exactly_rounded_sum_of_exact_products),
+        ("alg9_lapack", ALG9.test_alg9_sigma_matches_lapack_and_factors_are_consistent),
+        ("alg9_full_rank", ALG9.test_alg9_at_full_rank_is_the_svd_of_A),
+        ("jstar_margin", ALG9.test_jstar_margin_on_orthogonal_columns),
     ]
     for name, fn in checks:
         try:
@@ -94,6 +102,16 @@ MUTANTS = [
     ("jacobi_svd", "new_p = c * cp - s * cq", "new_p = c * cp + s * cq"),
     ("jacobi_svd", "zeta = (b - a) / (2.0 * g)", "zeta = (a - b) / (2.0 * g)"),
     ("jacobi_svd", "for q in range(p + 1, n):", "for q in range(p + 2, n):"),
+    # bfloat16 sketch mode
+    ("round_bf16", "return np.rint(x / q) * q", "return np.floor(x / q + 0.5) * q"),
+    ("round_bf16", "np.maximum(e, -125) - 8", "np.maximum(e, -125) - 7"),
+    ("round_bf16", "np.maximum(e, -125) - 8", "e - 8"),
+    ("sketch", "return round_bf16(Omega) @ round_bf16(A)", "return round_bf16(Omega) @ A"),
+    # Algorithm 9 completion and the j* margin
+    ("alg9", "tmp = A @ res.V", "tmp = A @ res.V[:, ::-1] * 1.0 + 0.0 * A @ res.V"),
+    ("alg9", "U = Qt @ UR[:, :k]", "U = Qt[:, :k]"),
+    ("alg9", "Vk = res.V @ VR[:, :k]", "Vk = res.V @ UR[:, :k]"),
+    ("residual_margin", "return float((g2[-1] - g2[-2]) / g2[-1])", "return float((g2[-1] - g2[0]) / g2[-1])"),
 ]
 
 
