@@ -32,15 +32,15 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def timed_solves(ff, torch, A, w, steps, warmup):
+def timed_solves(ff, torch, A, w, steps, warmup, mixed=False):
     for _ in range(warmup):
-        ff.factor(A, w.k, w.p, w.seed)
+        ff.factor(A, w.k, w.p, w.seed, mixed=mixed)
     ff.profile_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     out = None
     for _ in range(steps):
-        out = ff.factor(A, w.k, w.p, w.seed)
+        out = ff.factor(A, w.k, w.p, w.seed, mixed=mixed)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = ff.profile_read()
@@ -67,7 +67,31 @@ def gemm_traffic(w, prec):
     return int(d["bytes_per_launch"])
 
 
+def mixed_roofline(prof, w):
+    # mixed form: the sketch is bound by HBM (A read once in FP32, Omega^T in
+    # BF16, B written in FP32), the split-BF16 projection by BF16 MFMA (three
+    # products of 2 l m n flops each)
+    sk_ms, sk_n = prof["sketch"]
+    pj_ms, pj_n = prof["project"]
+    if sk_n == 0 or pj_n == 0:
+        return None
+    sk_s = sk_ms / sk_n / 1e3
+    pj_s = pj_ms / pj_n / 1e3
+    sk_bytes = 4.0 * w.m * w.n + 2.0 * w.m * w.l + 4.0 * w.l * w.n
+    pj_flop = 3 * 2.0 * w.l * w.m * w.n
+    pj = pj_flop / pj_s / 1e12
+    sk = sk_bytes / sk_s / 1e9
+    return {"bound": "mfma", "achieved": round(pj, 3), "peak": 2500.0, "unit": "TFLOP/s",
+            "frac": round(pj / 2500.0, 4), "traffic": None, "kernel": "gemm_bf16_kernel<3, *> (split-BF16 projection)",
+            "flop_per_launch": pj_flop, "avg_launch_ms": round(pj_s * 1e3, 4), "launches": pj_n,
+            "sketch": {"bound": "hbm", "achieved": round(sk, 1), "peak": 8000.0, "unit": "GB/s",
+                       "frac": round(sk / 8000.0, 4), "bytes_per_launch": sk_bytes,
+                       "avg_launch_ms": round(sk_s * 1e3, 4), "kernel": "gemm_bf16_kernel<1, *> (BF16 sketch)"}}
+
+
 def gemm_roofline(prof, w, prec):
+    if prec == "mixed":
+        return mixed_roofline(prof, w)
     # the sketch (B = Omega A) and the projection (W = Q1^T A) are launches of
     # the same MFMA GEMM (for l <= 288 the tall-tile kernel, K split over two
     # halves plus the fixed-order sum of the halves, both inside the timed
@@ -92,7 +116,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--precision", choices=["fp64", "fp32", "mixed"], default="fp64")
     ap.add_argument("--workload", default="mid")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-second-form", action="store_true")
@@ -120,7 +144,7 @@ def main():
     torch.cuda.synchronize()
 
     log(f"{args.precision}: warmup {args.warmup}, timing {args.steps} solves")
-    out, secs, prof = timed_solves(ff, torch, Ad, w, args.steps, args.warmup)
+    out, secs, prof = timed_solves(ff, torch, Ad, w, args.steps, args.warmup, mixed=args.precision == "mixed")
     value = args.steps / secs
     log(f"{args.precision}: {secs / args.steps * 1e3:.3f} ms per solve")
     stages = {k: {"ms_per_solve": round(v[0] / args.steps, 4), "launches_per_solve": v[1] / args.steps}

@@ -28,9 +28,19 @@
  *  - The caller owns every buffer.  A is read-only.  No entry point allocates
  *    device memory: scratch lives in the caller's workspace.
  *  - precision: FFSRQR_FP64 means double storage and arithmetic everywhere;
- *    FFSRQR_FP32 means float storage of A and of the float outputs (Q, L, V,
- *    B, R, W), FP32 MFMA GEMMs and FP32 Householder panels, FP64 column
- *    norms, residual norms, SRQR test and singular values.
+ *    FFSRQR_FP32 means float storage of A and of the float outputs and
+ *    intermediates (Q, L, V, B, R, W, the panel between its 16-column
+ *    blocks), FP32 MFMA GEMMs (sketch and projection), and FP64 arithmetic
+ *    everywhere else: QRCP on B, the Householder panel steps and their
+ *    trailing updates, column and residual norms, the SRQR test and the
+ *    singular values.  FFSRQR_MIXED has the storage of FFSRQR_FP32 and
+ *    replaces its two GEMMs: the sketch multiplies BF16 operands
+ *    (Omega rounded to bfloat16 from its FP64 value, A rounded from FP32,
+ *    both to nearest even) on MFMA with FP32 accumulation, with the column
+ *    norms summed in FP64 from the FP32 entries; the projection is the
+ *    split-BF16 product Q^T A ~ Qhi^T Ahi + Qhi^T Alo + Qlo^T Ahi
+ *    (x = hi + lo, hi = bf16(x), lo = bf16(x - hi)) with FP32 accumulation.
+ *    Everything after the GEMMs is as in FFSRQR_FP32.
  *  - stream is a hipStream_t (NULL = the default stream).  Stage entry points
  *    only enqueue work; ffsrqr_factor synchronises the stream once per SRQR
  *    test (the swap decision is read back on the host) and on return.
@@ -62,11 +72,11 @@ typedef enum {
   FFSRQR_ENODEV = 4
 } ffsrqr_status;
 
-typedef enum { FFSRQR_FP64 = 0, FFSRQR_FP32 = 1 } ffsrqr_precision;
+typedef enum { FFSRQR_FP64 = 0, FFSRQR_FP32 = 1, FFSRQR_MIXED = 2 } ffsrqr_precision;
 
 /* ffsrqr_info.flags bits */
 enum {
-  FFSRQR_FLAG_RANK_DEFICIENT = 1u, /* alpha or a diagonal of R11 <= max(m,n) eps max_j ||a_j|| */
+  FFSRQR_FLAG_RANK_DEFICIENT = 1u, /* alpha or a diagonal of R11 <= tau_r (below)                */
   FFSRQR_FLAG_SWAPCAP = 2u,        /* the swap loop stopped at max_swaps with g2 > g            */
   FFSRQR_FLAG_NONFINITE = 4u,      /* A holds a NaN or Inf; outputs are NaN                     */
   FFSRQR_FLAG_L_CLAMPED = 8u,      /* k + p > min(m, n); l was clamped to min(m, n)             */
@@ -91,7 +101,19 @@ typedef struct {
   double min_margin;      /* min over QRCP-on-B steps of (r_max - r_2nd) / r_max   */
   int32_t jacobi_sweeps;  /* sweeps of the one-sided Jacobi on L                   */
   int32_t reserved;
+  double jstar_margin;    /* (gamma_j*^2 - g_2nd) / gamma_j*^2: how clearly j* won;
+                             g_2nd bounds every other trailing gamma_j^2 (1 when
+                             l == n or one column trails)                         */
+  int64_t jstar_candidates; /* trailing columns whose residual norm was recomputed
+                               exactly to choose j*                                */
 } ffsrqr_info;
+
+/* Rank tolerance tau_r of the SRQR test: max(m, n) 2^-52 max_j ||a_j|| for
+ * FFSRQR_FP64; 8 sqrt(max(m, n)) 2^-24 max_j ||a_j|| for FFSRQR_FP32 (Q1, the
+ * panel between blocks and W are rounded to float, so exactly dependent
+ * columns leave residuals of order sqrt(l) 2^-24 ||a_j||).  When alpha or a
+ * diagonal entry of R11 is <= tau_r, RANK_DEFICIENT is set, numerical_rank is
+ * the number of |R11_ii| > tau_r, g2 = 1 and no swap is made. */
 
 /* Default options: FP64, g = 2, max_swaps = 4 l. */
 void ffsrqr_default_opts(ffsrqr_opts* opts);
@@ -107,7 +129,13 @@ const char* ffsrqr_last_error(void);
  * for ffsrqr_factor and for every stage entry point on a problem of the
  * given dimensions.  Pure host computation; needs no device.
  * Errors: FFSRQR_EINVAL for m, n < 1, k < 1, k > min(m, n), p < 0, a NULL
- * bytes pointer or an unknown precision.
+ * bytes pointer, an unknown precision, or sizes beyond the supported range:
+ * l = min(k + p, m, n) <= 1024, and the Householder QR of the m x l and
+ * n x l panels must fit a 256-CU gfx950 with 160 KiB of LDS per workgroup
+ * (one row block per workgroup, at most 1024 rows, stored in LDS beside the
+ * panel's exchange tile): m and n at most about 256 min(1024, 1259 - l) rows,
+ * e.g. 252672 at l = 272, 183040 at l = 544, 30080 at l = 1024.
+ * ffsrqr_factor re-checks against the device in use.
  */
 ffsrqr_status ffsrqr_workspace_size(int64_t m, int64_t n, int64_t k, int64_t p,
                                     const ffsrqr_opts* opts, size_t* bytes);
@@ -126,7 +154,12 @@ ffsrqr_status ffsrqr_workspace_size(int64_t m, int64_t n, int64_t k, int64_t p,
  *   L      l x l (ldl >= l): lower triangular, diag(L) >= 0.
  *   V      n x l (ldv >= n): V = Pi Qhat1, orthonormal columns; A ~ Q L V^T.
  *   sigma  [l] double: singular values of L, descending.
- *   info   host pointer, filled on success (may be NULL).
+ *   info   host pointer, filled on success (may be NULL); also filled
+ *          (flags with FFSRQR_FLAG_TIMEOUT) when a device-wide wait ran out
+ *          and FFSRQR_EHIP is returned: the outputs are then incomplete.
+ * Errors as ffsrqr_workspace_size, plus lda < m, ldq < m, ldl < l, ldv < n,
+ * g <= 1 or a NULL output (FFSRQR_EINVAL), all checked before anything is
+ * enqueued.
  *   work   device workspace of work_bytes >= ffsrqr_workspace_size(...).
  * The call returns after the stream has completed the solve.
  */
@@ -156,6 +189,7 @@ ffsrqr_status ffsrqr_omega(uint64_t seed, int64_t l, int64_t m, void* omega_t, i
  * Sketch (Algorithm 2, "form the initial sample matrix"): B = Omega A with
  * Omega l x m from seed, B l x n (ldb >= l), and the column norms
  * anorm2[j] = ||A(:, j)||^2 (FP64 accumulation, n doubles) in the same pass.
+ * FFSRQR_MIXED: A and B float, B = bf16(Omega) bf16(A) with FP32 sums.
  */
 ffsrqr_status ffsrqr_sketch(const void* A, int64_t m, int64_t n, int64_t lda, uint64_t seed,
                             int64_t l, void* B, int64_t ldb, double* anorm2,
@@ -191,6 +225,7 @@ ffsrqr_status ffsrqr_panel_qr(const void* A, int64_t m, int64_t n, int64_t lda,
  * (c x n, ldw >= c) for every column of A in the original order, and the
  * residual norms gamma2[j] = anorm2[j] - ||W(:, j)||^2 (FP64).
  * Q is m x c (ldq >= m).  anorm2 as returned by ffsrqr_sketch.
+ * FFSRQR_MIXED: Q, A and W float, W by the split-BF16 product.
  */
 ffsrqr_status ffsrqr_project(const void* Q, int64_t m, int64_t c, int64_t ldq,
                              const void* A, int64_t n, int64_t lda, void* W, int64_t ldw,

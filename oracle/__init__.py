@@ -37,6 +37,7 @@ from .ffsrqr import (
     jacobi_svd,
     project,
     qrcp_sketch,
+    rank_tolerance,
     residual_margin,
     residual_norms,
     round_bf16,
@@ -50,7 +51,7 @@ __all__ = [
     "omega", "philox4x64_10", "uniform_open", "FLAG_L_CLAMPED", "FLAG_NONFINITE",
     "FLAG_RANK_DEFICIENT", "FLAG_SWAPCAP", "Alg9", "Result", "alg9", "back_substitute",
     "factor_leading_set", "ffsrqr", "flip_flop_lq", "householder", "householder_qr",
-    "jacobi_svd", "project", "qrcp_sketch", "residual_margin", "residual_norms", "round_bf16",
+    "jacobi_svd", "project", "qrcp_sketch", "rank_tolerance", "residual_margin", "residual_norms", "round_bf16",
     "sketch", "srqr_rho",
     "upper_inverse", "diagnostics",
 ]

@@ -394,13 +394,32 @@ def residual_margin(gam: np.ndarray) -> float:
     return float((g2[-1] - g2[-2]) / g2[-1]) if g2[-1] > 0 else 0.0
 
 
+def rank_tolerance(m: int, n: int, max_col_norm: float, storage: str = "fp64") -> float:
+    """tau_r: alpha or |R11_ii| at or below it counts as zero (numerical rank).
+
+    For FP64 data, max(m, n) 2^-52 max_j ||a_j|| (the usual rank-revealing
+    threshold).  When A and the factors are held in FP32, rounding to 2^-24
+    leaves exactly dependent columns with residuals of order
+    sqrt(l) 2^-24 ||a_j||, so the threshold is 8 sqrt(max(m, n)) 2^-24
+    max_j ||a_j||: zero at the storage precision.
+    """
+    mn = float(max(m, n))
+    if storage == "fp64":
+        return mn * 2.0 ** -52 * max_col_norm
+    if storage == "fp32":
+        return 8.0 * math.sqrt(mn) * 2.0 ** -24 * max_col_norm
+    raise ValueError(f"unknown storage {storage!r}")
+
+
 def ffsrqr(A: np.ndarray, k: int, p: int, seed: int, g: float = 2.0,
            max_swaps: int | None = None, Omega: np.ndarray | None = None,
-           sketch_mode: str = "fp64") -> Result:
+           sketch_mode: str = "fp64", storage: str = "fp64") -> Result:
     """Flip-Flop SRQR hot path, FP64 (Algorithm 9 up to the LQ, Algorithm 4 inside).
 
     sketch_mode selects the arithmetic of B = Omega A ("fp64" or "bf16", see
-    sketch()); every later step is FP64 on the same A.
+    sketch()); every later step is FP64 on the same A.  storage names the
+    precision the data is held in ("fp64" or "fp32"); it only sets the rank
+    tolerance (rank_tolerance()).
     """
     A = np.asarray(A)
     m, n = A.shape
@@ -423,7 +442,7 @@ def ffsrqr(A: np.ndarray, k: int, p: int, seed: int, g: float = 2.0,
                       margins=np.zeros(l), jstar_margin=0.0, flags=flags, numerical_rank=0,
                       B=np.full((l, n), nan), history=[], sketch_mode=sketch_mode)
     colnorm = np.sqrt(np.sum(Af * Af, axis=0))
-    tau_r = max(m, n) * 2.0 ** -52 * float(colnorm.max())
+    tau_r = rank_tolerance(m, n, float(colnorm.max()), storage)
 
     # a1
     Om = omega(seed, l, m) if Omega is None else Omega

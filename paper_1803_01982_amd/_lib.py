@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libffsrqr.so")
 
 FFSRQR_OK, FFSRQR_EINVAL, FFSRQR_EWORKSPACE, FFSRQR_EHIP, FFSRQR_ENODEV = range(5)
-FP64, FP32 = 0, 1
+FP64, FP32, MIXED = 0, 1, 2
 FLAG_RANK_DEFICIENT, FLAG_SWAPCAP, FLAG_NONFINITE, FLAG_L_CLAMPED, FLAG_TIMEOUT = 1, 2, 4, 8, 16
 
 
@@ -27,7 +27,8 @@ class Opts(C.Structure):
 class Info(C.Structure):
     _fields_ = [("l", C.c_int64), ("swaps", C.c_int32), ("flags", C.c_uint32), ("g2", C.c_double),
                 ("alpha", C.c_double), ("jstar", C.c_int64), ("numerical_rank", C.c_int64),
-                ("min_margin", C.c_double), ("jacobi_sweeps", C.c_int32), ("reserved", C.c_int32)]
+                ("min_margin", C.c_double), ("jacobi_sweeps", C.c_int32), ("reserved", C.c_int32),
+                ("jstar_margin", C.c_double), ("jstar_candidates", C.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -35,11 +35,13 @@ def _ld(t: torch.Tensor) -> int:
     return max(t.stride(1), rows, 1)
 
 
-def _prec(dtype) -> int:
+def _prec(dtype, mixed: bool = False) -> int:
     if dtype == torch.float64:
+        if mixed:
+            raise TypeError("the mixed form takes float32 data")
         return L.FP64
     if dtype == torch.float32:
-        return L.FP32
+        return L.MIXED if mixed else L.FP32
     raise TypeError(f"unsupported dtype {dtype}; use float64 or float32")
 
 
@@ -86,12 +88,13 @@ class Factorization:
 
 
 def factor(A: torch.Tensor, k: int, p: int, seed: int = 0, g: float = 2.0, max_swaps: int = -1,
-           work: torch.Tensor | None = None, stream=None) -> Factorization:
-    """ffsrqr_factor: A (m x n, column-major, float64 or float32) -> perm, Q, L, V, sigma, info."""
+           work: torch.Tensor | None = None, stream=None, mixed: bool = False) -> Factorization:
+    """ffsrqr_factor: A (m x n, column-major, float64 or float32) -> perm, Q, L, V, sigma, info.
+    mixed=True (float32 A) selects FFSRQR_MIXED (BF16 sketch, split-BF16 projection)."""
     lib = L.load()
     m, n = A.shape
     lda = _ld(A)
-    prec = _prec(A.dtype)
+    prec = _prec(A.dtype, mixed)
     l = min(k + p, m, n)
     dev = A.device
     perm = torch.empty(n, dtype=torch.int64, device=dev)
@@ -117,16 +120,17 @@ def omega(seed: int, l: int, m: int, dtype=torch.float64, device="cuda", stream=
     return Ot
 
 
-def sketch(A: torch.Tensor, seed: int, l: int, work=None, stream=None):
-    """ffsrqr_sketch: (B = Omega A, anorm2)."""
+def sketch(A: torch.Tensor, seed: int, l: int, work=None, stream=None, mixed: bool = False):
+    """ffsrqr_sketch: (B = Omega A, anorm2); mixed=True: BF16 operands, FP32 sums."""
     lib = L.load()
     m, n = A.shape
+    prec = _prec(A.dtype, mixed)
     B = empty_fortran(l, n, A.dtype, A.device)
     an = torch.empty(n, dtype=torch.float64, device=A.device)
     if work is None:
-        work = workspace(workspace_size(m, n, l, 0, _prec(A.dtype)), A.device)
+        work = workspace(workspace_size(m, n, l, 0, prec), A.device)
     L.check(lib.ffsrqr_sketch(_ptr(A), m, n, _ld(A), seed, l, _ptr(B), l, _ptr(an), _ptr(work), work.numel(),
-                              _prec(A.dtype), _stream(stream)), "ffsrqr_sketch")
+                              prec, _stream(stream)), "ffsrqr_sketch")
     return B, an
 
 
@@ -158,17 +162,18 @@ def panel_qr(A: torch.Tensor, cols: torch.Tensor, work=None, stream=None):
     return Q, R
 
 
-def project(Q: torch.Tensor, A: torch.Tensor, anorm2: torch.Tensor, work=None, stream=None):
-    """ffsrqr_project: (W = Q^T A, gamma2)."""
+def project(Q: torch.Tensor, A: torch.Tensor, anorm2: torch.Tensor, work=None, stream=None, mixed: bool = False):
+    """ffsrqr_project: (W = Q^T A, gamma2); mixed=True: the split-BF16 product."""
     lib = L.load()
     m, c = Q.shape
     n = A.shape[1]
+    prec = _prec(A.dtype, mixed)
     W = empty_fortran(c, n, A.dtype, A.device)
     g2 = torch.empty(n, dtype=torch.float64, device=A.device)
     if work is None:
-        work = workspace(workspace_size(m, n, min(c, m, n), 0, _prec(A.dtype)), A.device)
+        work = workspace(workspace_size(m, n, min(c, m, n), 0, prec), A.device)
     L.check(lib.ffsrqr_project(_ptr(Q), m, c, _ld(Q), _ptr(A), n, _ld(A), _ptr(W), c, _ptr(anorm2), _ptr(g2),
-                               _ptr(work), work.numel(), _prec(A.dtype), _stream(stream)), "ffsrqr_project")
+                               _ptr(work), work.numel(), prec, _stream(stream)), "ffsrqr_project")
     return W, g2
 
 

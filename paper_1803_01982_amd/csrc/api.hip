@@ -95,8 +95,11 @@ class StepTimer {
   std::vector<Rec> recs_;
 };
 
-bool valid_precision(int32_t p) { return p == FFSRQR_FP64 || p == FFSRQR_FP32; }
+bool valid_precision(int32_t p) { return p == FFSRQR_FP64 || p == FFSRQR_FP32 || p == FFSRQR_MIXED; }
 size_t elem_size(int32_t p) { return p == FFSRQR_FP64 ? sizeof(double) : sizeof(float); }
+// Rows of the K-major BF16 operand arrays of the mixed form: m rounded up to
+// a multiple of 8 (16-byte fragment loads).
+int64_t bf16_ld(int64_t m) { return (m + 7) / 8 * 8; }
 
 // Conservative device shape for sizing without touching a device.
 DeviceInfo sizing_device() {
@@ -121,6 +124,7 @@ template <typename T>
 size_t scratch_bytes(int64_t m, int64_t n, int64_t l, const DeviceInfo& d) {
   size_t s = 0;
   s = std::max(s, gemm_tn_scratch<T>(l, n, m, d.num_cu));
+  if (sizeof(T) == 4) s = std::max(s, gemm_bf16_scratch(l, n, m, d.num_cu));
   s = std::max(s, qrcp_scratch<T>(l, n, d));
   s = std::max(s, tallqr_scratch<T>(m, l, d));
   // a6 on one stream while a4's residual norms, a5 and a7 run on the other
@@ -133,7 +137,8 @@ size_t scratch_bytes(int64_t m, int64_t n, int64_t l, const DeviceInfo& d) {
 template <typename T>
 size_t persistent_bytes(int64_t m, int64_t n, int64_t l) {
   size_t b = 0;
-  b += align256(std::max<size_t>((size_t)m * l, (size_t)m * l) * sizeof(T));  // Omega^T, then the gathered panel
+  // Omega^T, then the gathered panel, then (mixed form) the BF16 parts of Q
+  b += align256((size_t)(sizeof(T) == 4 ? bf16_ld(m) : m) * l * sizeof(T));
   b += align256((size_t)l * n * sizeof(T));                                   // B, then R^T
   b += align256((size_t)l * n * sizeof(T));                                   // W
   b += align256((size_t)n * l * sizeof(T));                                   // Qhat1
@@ -204,6 +209,49 @@ ffsrqr_status check_dims(int64_t m, int64_t n, int64_t k, int64_t p) {
   return FFSRQR_OK;
 }
 
+// Sizes the path supports on device d: l <= 1024 and the Householder QR of
+// the m x l panel and of the n x l transposed factor fit the device.
+ffsrqr_status check_limits(int64_t m, int64_t n, int64_t l, const DeviceInfo& d) {
+  if (l > 1024) return fail(FFSRQR_EINVAL, "l = min(k + p, m, n) must be <= 1024");
+  if (!tallqr_fits(m, l, d) || !tallqr_fits(n, l, d))
+    return fail(FFSRQR_EINVAL, "m or n too large for the panel QR at this l (rows per workgroup exceed the LDS)");
+  return FFSRQR_OK;
+}
+
+// The device the limits are checked against when no device is at hand: a
+// 256-CU gfx950 with 160 KiB of LDS per workgroup.
+DeviceInfo limits_device() {
+  DeviceInfo d;
+  d.num_cu = 256;
+  d.lds_max = 160 * 1024;
+  d.coop = true;
+  d.gfx950 = true;
+  return d;
+}
+
+// Rank tolerance of the SRQR test (alpha or a diagonal entry of R11 at or
+// below it counts as zero): max(m, n) 2^-52 max_j ||a_j|| for FP64 storage;
+// for FP32 storage, 8 sqrt(max(m, n)) 2^-24 max_j ||a_j||, since Q1, the
+// panel between blocks and W are rounded to FP32 and exactly dependent
+// columns then leave residuals of order sqrt(l) 2^-24 ||a_j||.
+double rank_tol(int64_t m, int64_t n, double anorm_max, bool fp32) {
+  const double mn = (double)std::max(m, n);
+  return fp32 ? 8.0 * std::sqrt(mn) * 0x1p-24 * anorm_max : mn * 0x1p-52 * anorm_max;
+}
+
+// Window of the j* preselection, relative to ||a_j||^2 + ||a_max||^2: the
+// rounding of ||a_j||^2 - ||W(:, j)||^2 grows like (4 sqrt(m) + l) u with u
+// the unit roundoff of W's arithmetic; the split-BF16 projection adds a
+// product error of about 2^-16 per term, i.e. about 2^-16 / sqrt(m) of
+// ||a_j||^2 for sums of m terms of random sign, taken with a factor 64.
+template <typename T>
+double select_window(int64_t m, int64_t l, bool mixed) {
+  const double u = sizeof(T) == 8 ? 0x1p-53 : 0x1p-24;
+  double w = (4.0 * std::sqrt((double)m) + (double)l) * u;
+  if (mixed) w += 64.0 * 0x1p-16 / std::sqrt((double)m);
+  return w;
+}
+
 ffsrqr_opts resolve(const ffsrqr_opts* o, int64_t l) {
   ffsrqr_opts r;
   ffsrqr_default_opts(&r);
@@ -219,6 +267,8 @@ ffsrqr_status factor_impl(const T* A, int64_t m, int64_t n, int64_t lda, int64_t
                           int64_t* perm, T* Q, int64_t ldq, T* L, int64_t ldl, T* V, int64_t ldv, double* sigma,
                           ffsrqr_info* info, void* work, size_t work_bytes, const ffsrqr_opts& op,
                           const DeviceInfo& d, hipStream_t s) {
+  const bool mixed = op.precision == FFSRQR_MIXED;
+  const int64_t mp = bf16_ld(m);
   const int64_t l = std::min(k + p, std::min(m, n));
   uint32_t flags = (l < k + p) ? FFSRQR_FLAG_L_CLAMPED : 0u;
   const size_t need = total_bytes<T>(m, n, l, d);
@@ -226,7 +276,7 @@ ffsrqr_status factor_impl(const T* A, int64_t m, int64_t n, int64_t lda, int64_t
     return fail(FFSRQR_EWORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
 
   Arena ar{(char*)work, work_bytes, 0};
-  T* region1 = ar.take<T>((size_t)m * l);  // Omega^T, later the gathered panel
+  T* region1 = ar.take<T>((size_t)(sizeof(T) == 4 ? mp : m) * l);  // Omega^T, the gathered panel, Q's BF16 parts
   T* region2 = ar.take<T>((size_t)l * n);  // B, later R^T
   T* W = ar.take<T>((size_t)l * n);
   T* Qhat = ar.take<T>((size_t)n * l);
@@ -253,12 +303,17 @@ ffsrqr_status factor_impl(const T* A, int64_t m, int64_t n, int64_t lda, int64_t
   FF_HIP(zero_words(err, 64, s));
   // a1: Omega and the sketch (one pass over A, column norms fused)
   tm.begin(FFSRQR_STEP_OMEGA);
-  FF_HIP(launch_omega<T>(seed, l, m, region1, m, s));
+  if (mixed) FF_HIP(launch_omega<__bf16>(seed, l, m, (__bf16*)region1, mp, s));
+  else FF_HIP(launch_omega<T>(seed, l, m, region1, m, s));
   tm.end();
   {
     Arena a = scratch();
     tm.begin(FFSRQR_STEP_SKETCH);
-    FF_HIP(gemm_tn<T>(l, n, m, region1, m, A, lda, region2, l, anorm2, a, d.num_cu, s));
+    if (mixed)
+      FF_HIP(gemm_bf16(1, l, n, m, (const __bf16*)region1, nullptr, mp, (const float*)A, lda, (float*)region2, l,
+                       anorm2, a, d.num_cu, s));
+    else
+      FF_HIP(gemm_tn<T>(l, n, m, region1, m, A, lda, region2, l, anorm2, a, d.num_cu, s));
     tm.end();
   }
   // non-finite input: report and stop before any pivoting
@@ -294,6 +349,7 @@ ffsrqr_status factor_impl(const T* A, int64_t m, int64_t n, int64_t lda, int64_t
         info->g2 = qnan;
         info->alpha = qnan;
         info->jstar = -1;
+        info->jstar_margin = 0.0;
       }
       return FFSRQR_OK;
     }
@@ -326,7 +382,15 @@ ffsrqr_status factor_impl(const T* A, int64_t m, int64_t n, int64_t lda, int64_t
     {
       Arena a = scratch();
       tm.begin(FFSRQR_STEP_PROJECT);
-      FF_HIP(gemm_tn<T>(l, n, m, Q, ldq, A, lda, W, l, nullptr, a, d.num_cu, s));
+      if (mixed) {
+        // the panel in region1 is no longer read once Q is formed (stream order)
+        __bf16* qh = (__bf16*)region1;
+        __bf16* ql = qh + (size_t)mp * l;
+        FF_HIP(split_bf16((const float*)Q, m, l, ldq, qh, ql, mp, s));
+        FF_HIP(gemm_bf16(3, l, n, m, qh, ql, mp, (const float*)A, lda, (float*)W, l, nullptr, a, d.num_cu, s));
+      } else {
+        FF_HIP(gemm_tn<T>(l, n, m, Q, ldq, A, lda, W, l, nullptr, a, d.num_cu, s));
+      }
       tm.end();
     }
     // From here two streams: the side stream runs the SRQR test (a4's
@@ -347,7 +411,8 @@ ffsrqr_status factor_impl(const T* A, int64_t m, int64_t n, int64_t lda, int64_t
       // a5: SRQR test
       const int h = tm.begin(FFSRQR_STEP_SRQR, side->stream);
       Arena a = a_side;
-      FF_HIP(srqr_select<T>(gamma2, anorm2, inS, n, A, m, lda, Q, ldq, W, l, R11, l, l, st, a, side->stream));
+      FF_HIP(srqr_select<T>(gamma2, anorm2, inS, n, A, m, lda, Q, ldq, W, l, R11, l, l, st, a, side->stream,
+                            select_window<T>(m, l, mixed)));
       if (l < n) {
         Arena a2 = a_side;
         FF_HIP(srqr_rho<T>(R11, l, W, l, st, 0.0, l, rho, st, a2, side->stream));
@@ -377,8 +442,16 @@ ffsrqr_status factor_impl(const T* A, int64_t m, int64_t n, int64_t lda, int64_t
     FF_HIP(hipStreamSynchronize(s));
     jacobi_sweeps = (int32_t)herr[32];
     if (herr[0]) {
-      flags |= FFSRQR_FLAG_TIMEOUT;
-      return fail(FFSRQR_EHIP, "a device-wide wait exceeded its spin limit");
+      // the outputs are incomplete; info says which condition ended the call
+      if (info) {
+        std::memset(info, 0, sizeof(*info));
+        info->l = l;
+        info->flags = flags | FFSRQR_FLAG_TIMEOUT;
+        info->g2 = std::nan("");
+        info->alpha = std::nan("");
+        info->jstar = -1;
+      }
+      return fail(FFSRQR_EHIP, "a device-wide wait exceeded its spin limit; the outputs are incomplete");
     }
     if (l >= n) {
       g2 = 1.0;
@@ -386,7 +459,7 @@ ffsrqr_status factor_impl(const T* A, int64_t m, int64_t n, int64_t lda, int64_t
       hs.alpha = 0.0;
       break;
     }
-    const double tau_r = (double)std::max(m, n) * std::ldexp(1.0, -52) * hs.anorm_max;
+    const double tau_r = rank_tol(m, n, hs.anorm_max, sizeof(T) == 4);
     if (hs.alpha <= tau_r || hs.min_diag <= tau_r) {
       flags |= FFSRQR_FLAG_RANK_DEFICIENT;
       std::vector<T> hr((size_t)l * l);
@@ -427,6 +500,8 @@ ffsrqr_status factor_impl(const T* A, int64_t m, int64_t n, int64_t lda, int64_t
     info->min_margin = mm;
     info->jacobi_sweeps = jacobi_sweeps;
     info->reserved = 0;
+    info->jstar_margin = l < n ? hs.jmargin : 1.0;
+    info->jstar_candidates = l < n ? hs.ncand : 0;
   }
   return FFSRQR_OK;
 }
@@ -436,6 +511,20 @@ ffsrqr_status factor_impl(const T* A, int64_t m, int64_t n, int64_t lda, int64_t
 
 namespace ffsrqr {
 namespace {
+ffsrqr_status sketch_mixed(const float* A, int64_t m, int64_t n, int64_t lda, uint64_t seed, int64_t l, float* B,
+                           int64_t ldb, double* anorm2, void* work, size_t work_bytes, const DeviceInfo& d,
+                           hipStream_t s) {
+  Arena ar{(char*)work, work_bytes, 0};
+  const int64_t mp = bf16_ld(m);
+  __bf16* Ot = ar.take<__bf16>((size_t)mp * l);
+  if (!Ot) return fail(FFSRQR_EWORKSPACE, "workspace too small");
+  FF_HIP(launch_omega<__bf16>(seed, l, m, Ot, mp, s));
+  hipError_t e = gemm_bf16(1, l, n, m, Ot, nullptr, mp, A, lda, B, ldb, anorm2, ar, d.num_cu, s);
+  if (e == hipErrorOutOfMemory) return fail(FFSRQR_EWORKSPACE, "workspace too small");
+  FF_HIP(e);
+  return FFSRQR_OK;
+}
+
 template <typename T>
 ffsrqr_status sketch_impl(const T* A, int64_t m, int64_t n, int64_t lda, uint64_t seed, int64_t l, T* B, int64_t ldb,
                           double* anorm2, void* work, size_t work_bytes, const DeviceInfo& d, hipStream_t s) {
@@ -501,6 +590,8 @@ ffsrqr_status ffsrqr_workspace_size(int64_t m, int64_t n, int64_t k, int64_t p, 
   const int32_t prec = opts ? opts->precision : FFSRQR_FP64;
   if (!valid_precision(prec)) return fail(FFSRQR_EINVAL, "unknown precision");
   const int64_t l = std::min(k + p, std::min(m, n));
+  st = check_limits(m, n, l, limits_device());
+  if (st != FFSRQR_OK) return st;
   const DeviceInfo d = sizing_device();
   *bytes = prec == FFSRQR_FP64 ? total_bytes<double>(m, n, l, d) : total_bytes<float>(m, n, l, d);
   return FFSRQR_OK;
@@ -521,7 +612,10 @@ ffsrqr_status ffsrqr_factor(const void* A, int64_t m, int64_t n, int64_t lda, in
   const DeviceInfo* d = nullptr;
   st = get_device(&d);
   if (st != FFSRQR_OK) return st;
+  st = check_limits(m, n, l, *d);
+  if (st != FFSRQR_OK) return st;
   hipStream_t s = (hipStream_t)stream;
+  if (op.precision == FFSRQR_MIXED && ((uintptr_t)A & 3) != 0) return fail(FFSRQR_EINVAL, "A must be 4-byte aligned");
   if (op.precision == FFSRQR_FP64)
     return factor_impl<double>((const double*)A, m, n, lda, k, p, seed, perm, (double*)Q, ldq, (double*)L, ldl,
                                (double*)V, ldv, sigma, info, work, work_bytes, op, *d, s);
@@ -553,6 +647,8 @@ ffsrqr_status ffsrqr_sketch(const void* A, int64_t m, int64_t n, int64_t lda, ui
   ffsrqr_status st = get_device(&d);
   if (st != FFSRQR_OK) return st;
   hipStream_t s = (hipStream_t)stream;
+  if (precision == FFSRQR_MIXED)
+    return sketch_mixed((const float*)A, m, n, lda, seed, l, (float*)B, ldb, anorm2, work, work_bytes, *d, s);
   if (precision == FFSRQR_FP64)
     return sketch_impl<double>((const double*)A, m, n, lda, seed, l, (double*)B, ldb, anorm2, work, work_bytes, *d, s);
   return sketch_impl<float>((const float*)A, m, n, lda, seed, l, (float*)B, ldb, anorm2, work, work_bytes, *d, s);
@@ -619,7 +715,16 @@ ffsrqr_status ffsrqr_project(const void* Q, int64_t m, int64_t c, int64_t ldq, c
   hipStream_t s = (hipStream_t)stream;
   Arena ar{(char*)work, work_bytes, 0};
   hipError_t e;
-  if (precision == FFSRQR_FP64) {
+  if (precision == FFSRQR_MIXED) {
+    const int64_t mp = bf16_ld(m);
+    __bf16* qh = ar.take<__bf16>((size_t)mp * c);
+    __bf16* ql = ar.take<__bf16>((size_t)mp * c);
+    if (!qh || !ql) return fail(FFSRQR_EWORKSPACE, "workspace too small");
+    e = split_bf16((const float*)Q, m, c, ldq, qh, ql, mp, s);
+    if (e == hipSuccess)
+      e = gemm_bf16(3, c, n, m, qh, ql, mp, (const float*)A, lda, (float*)W, ldw, nullptr, ar, d->num_cu, s);
+    if (e == hipSuccess) e = residual_norms<float>((const float*)W, c, n, ldw, anorm2, gamma2, s);
+  } else if (precision == FFSRQR_FP64) {
     e = gemm_tn<double>(c, n, m, (const double*)Q, ldq, (const double*)A, lda, (double*)W, ldw, nullptr, ar,
                         d->num_cu, s);
     if (e == hipSuccess) e = residual_norms<double>((const double*)W, c, n, ldw, anorm2, gamma2, s);

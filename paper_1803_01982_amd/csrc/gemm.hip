@@ -243,7 +243,7 @@ struct Tall8Layout {
 };
 
 template <typename T, int MT, int G>
-__device__ __forceinline__ void tall8_body(int64_t M, int64_t N, int64_t K, int64_t kchunk, const T* __restrict__ X,
+__device__ __forceinline__ void tall8_body(int64_t n0, int64_t M, int64_t N, int64_t K, int64_t kchunk, const T* __restrict__ X,
                                            int64_t ldx, const T* __restrict__ Y, int64_t ldy, T* __restrict__ C,
                                            int64_t ldc, int64_t cstride, double* __restrict__ colnorm, int64_t nstride,
                                            T (*Xs)[BK][32 * ((MT + 1) / 2) + Tall8Layout<T>::pad],
@@ -264,7 +264,6 @@ __device__ __forceinline__ void tall8_body(int64_t M, int64_t N, int64_t K, int6
   for (int t = 0; t < NTL; ++t) acc[t] = typename MF::acc4{0, 0, 0, 0};
 
   const int tid = threadIdx.x, lane = tid & 63, wc = (tid >> 6) & 3;
-  const int64_t n0 = (int64_t)blockIdx.x * TBN;
   const int64_t kb = (int64_t)blockIdx.z * kchunk;
   const int64_t ke = (kb + kchunk < K) ? kb + kchunk : K;
 
@@ -373,18 +372,37 @@ __device__ __forceinline__ void tall8_body(int64_t M, int64_t N, int64_t K, int6
   }
 }
 
+// More than 16 MT rows (M up to 1152): the rows are split into `groups`
+// groups of 16 MT rows, each a workgroup of its own over the same column
+// block.  Workgroups are dispatched round-robin over the eight XCDs
+// (workgroup b to XCD b % 8), so the groups of one column block take ids
+// eight apart: they share an XCD and its L2, which then serves the second
+// read of their common columns of Y.
 template <typename T, int MT>
 __global__ __launch_bounds__(NT8) void gemm_tall8_kernel(
     int64_t M, int64_t N, int64_t K, int64_t kchunk, const T* __restrict__ X, int64_t ldx,
     const T* __restrict__ Y, int64_t ldy, T* __restrict__ C, int64_t ldc, int64_t cstride,
-    double* __restrict__ colnorm, int64_t nstride) {
+    double* __restrict__ colnorm, int64_t nstride, int groups) {
   constexpr int PAD = Tall8Layout<T>::pad;
   __shared__ T Xs[2][BK][32 * ((MT + 1) / 2) + PAD];
   __shared__ T Ys[2][BK][TBN + PAD];
+  int64_t tile = blockIdx.x;
+  int grp = 0;
+  if (groups > 1) {
+    const int64_t per = 8 * (int64_t)groups;
+    tile = (int64_t)(blockIdx.x / per) * 8 + blockIdx.x % 8;
+    grp = (int)((blockIdx.x % per) / 8);
+  }
+  const int64_t n0 = tile * TBN, r0 = (int64_t)grp * 16 * MT;
+  if (n0 >= N || r0 >= M) return;
+  const int64_t Mg = M - r0 < 16 * MT ? M - r0 : 16 * MT;
+  X += r0 * ldx;
+  C += r0;
+  if (grp != 0) colnorm = nullptr;
   if (__builtin_amdgcn_readfirstlane(threadIdx.x >> 8) == 0)
-    tall8_body<T, MT, 0>(M, N, K, kchunk, X, ldx, Y, ldy, C, ldc, cstride, colnorm, nstride, Xs, Ys);
+    tall8_body<T, MT, 0>(n0, Mg, N, K, kchunk, X, ldx, Y, ldy, C, ldc, cstride, colnorm, nstride, Xs, Ys);
   else
-    tall8_body<T, MT, 1>(M, N, K, kchunk, X, ldx, Y, ldy, C, ldc, cstride, colnorm, nstride, Xs, Ys);
+    tall8_body<T, MT, 1>(n0, Mg, N, K, kchunk, X, ldx, Y, ldy, C, ldc, cstride, colnorm, nstride, Xs, Ys);
 }
 
 // C = sum_z Cpart_z (fixed order); colnorm likewise.
@@ -405,13 +423,30 @@ __global__ void splitk_reduce(int64_t M, int64_t N, int splits, const T* __restr
   }
 }
 
-constexpr int TALL_MT = 18;  // the tall-tile kernel serves M <= 16 TALL_MT
+constexpr int TALL_MT = 18;  // one tall-tile workgroup covers at most 16 TALL_MT rows
+constexpr int TALL_GROUPS = 4;  // row groups of the tall-tile kernel (M <= 1152)
+
+// Row groups and row tiles per group of the tall-tile kernel for M rows
+// (groups == 0: M is too large for it).
+void tall_shape(int64_t M, int* groups, int* mt) {
+  const int64_t g = (M + 16 * TALL_MT - 1) / (16 * TALL_MT);
+  if (g > TALL_GROUPS) {
+    *groups = 0;
+    *mt = 0;
+    return;
+  }
+  const int64_t rows = (M + g - 1) / g;
+  *groups = (int)g;
+  *mt = (int)((rows + 15) / 16);
+}
 
 int pick_splits(int64_t M, int64_t N, int64_t K, int num_cu) {
   int64_t s = 1;
-  if (M <= 16 * TALL_MT) {
+  int groups, mt;
+  tall_shape(M, &groups, &mt);
+  if (groups > 0) {
     // one workgroup per CU: as many K splits as needed to cover the chip
-    const int64_t tiles = (N + TBN - 1) / TBN;
+    const int64_t tiles = (N + TBN - 1) / TBN * groups;
     while (tiles * s < (int64_t)num_cu && K / (s * 2) >= 1024) s *= 2;
     return (int)s;
   }
@@ -423,9 +458,11 @@ int pick_splits(int64_t M, int64_t N, int64_t K, int num_cu) {
 
 template <typename T, int MT>
 void launch_tall(dim3 grid, hipStream_t s, int64_t M, int64_t N, int64_t K, int64_t kchunk, const T* X, int64_t ldx,
-                 const T* Y, int64_t ldy, T* C, int64_t ldc, int64_t cstride, double* colnorm, int64_t nstride) {
+                 const T* Y, int64_t ldy, T* C, int64_t ldc, int64_t cstride, double* colnorm, int64_t nstride,
+                 int groups) {
   if constexpr (MT >= 8)
-    gemm_tall8_kernel<T, MT><<<grid, NT8, 0, s>>>(M, N, K, kchunk, X, ldx, Y, ldy, C, ldc, cstride, colnorm, nstride);
+    gemm_tall8_kernel<T, MT><<<grid, NT8, 0, s>>>(M, N, K, kchunk, X, ldx, Y, ldy, C, ldc, cstride, colnorm, nstride,
+                                                  groups);
   else
     gemm_tall_kernel<T, MT><<<grid, NT, 0, s>>>(M, N, K, kchunk, X, ldx, Y, ldy, C, ldc, cstride, colnorm, nstride);
 }
@@ -433,12 +470,13 @@ void launch_tall(dim3 grid, hipStream_t s, int64_t M, int64_t N, int64_t K, int6
 template <typename T, int MT = 1>
 void dispatch_tall(int mt, dim3 grid, hipStream_t s, int64_t M, int64_t N, int64_t K, int64_t kchunk, const T* X,
                    int64_t ldx, const T* Y, int64_t ldy, T* C, int64_t ldc, int64_t cstride, double* colnorm,
-                   int64_t nstride) {
+                   int64_t nstride, int groups) {
   if constexpr (MT <= TALL_MT) {
     if (mt == MT)
-      launch_tall<T, MT>(grid, s, M, N, K, kchunk, X, ldx, Y, ldy, C, ldc, cstride, colnorm, nstride);
+      launch_tall<T, MT>(grid, s, M, N, K, kchunk, X, ldx, Y, ldy, C, ldc, cstride, colnorm, nstride, groups);
     else
-      dispatch_tall<T, MT + 1>(mt, grid, s, M, N, K, kchunk, X, ldx, Y, ldy, C, ldc, cstride, colnorm, nstride);
+      dispatch_tall<T, MT + 1>(mt, grid, s, M, N, K, kchunk, X, ldx, Y, ldy, C, ldc, cstride, colnorm, nstride,
+                               groups);
   }
 }
 
@@ -459,9 +497,13 @@ hipError_t gemm_tn(int64_t M, int64_t N, int64_t K, const T* X, int64_t ldx, con
   const int splits = pick_splits(M, N, K, num_cu);
   int64_t kchunk = (K + splits - 1) / splits;
   kchunk = (kchunk + BK - 1) / BK * BK;
-  const bool tall = M <= 16 * TALL_MT;
-  const int mt = (int)((M + 15) / 16);
-  dim3 grid = tall ? dim3((unsigned)((N + TBN - 1) / TBN), 1u, (unsigned)splits)
+  int groups, mt;
+  tall_shape(M, &groups, &mt);
+  const bool tall = groups > 0;
+  // groups > 1 only with the eight-wave kernel (mt >= 8 there)
+  const int64_t ntile = (N + TBN - 1) / TBN;
+  const int64_t gx = groups > 1 ? (ntile + 7) / 8 * 8 * groups : ntile;
+  dim3 grid = tall ? dim3((unsigned)gx, 1u, (unsigned)splits)
                    : dim3((unsigned)((N + BN - 1) / BN), (unsigned)((M + BM - 1) / BM), (unsigned)splits);
   T* out = C;
   int64_t ldo = ldc, ostride = 0, nstride = 0;
@@ -479,7 +521,7 @@ hipError_t gemm_tn(int64_t M, int64_t N, int64_t K, const T* X, int64_t ldx, con
     nstride = N;
   }
   if (tall)
-    dispatch_tall<T>(mt, grid, s, M, N, K, kchunk, X, ldx, Y, ldy, out, ldo, ostride, nout, nstride);
+    dispatch_tall<T>(mt, grid, s, M, N, K, kchunk, X, ldx, Y, ldy, out, ldo, ostride, nout, nstride, groups);
   else
     gemm_tn_kernel<T><<<grid, NT, 0, s>>>(M, N, K, kchunk, X, ldx, Y, ldy, out, ldo, ostride, nout, nstride);
   hipError_t e = hipGetLastError();

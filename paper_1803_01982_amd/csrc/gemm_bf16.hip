@@ -1,0 +1,373 @@
+// The mixed-precision form's GEMM passes on BF16 MFMA with FP32 accumulation:
+//
+//   sketch      B = Omega A  (Algorithm 2, sample matrix): one product of
+//               BF16 operands, X = bf16(Omega^T) (rounded from FP64 when
+//               Omega is drawn) and bf16(A) rounded from the FP32 entries of
+//               A in registers; the column norms ||A(:, j)||^2 are summed in
+//               FP64 from the FP32 entries in the same pass.
+//   projection  W = Q1^T A  (partial QR block form, Sections 2.1 and 3.1):
+//               split-BF16, x = hi + lo with hi = bf16(x), lo = bf16(x - hi)
+//               (x - hi is exact in FP32), and
+//                 Q^T A ~ Qhi^T Ahi + Qhi^T Alo + Qlo^T Ahi,
+//               dropping Qlo^T Alo (about 2^-16 of a product), three MFMAs
+//               into one FP32 accumulator.  Q is split once into BF16 arrays
+//               by split_bf16_kernel; A is split in registers.
+//
+// Both operands are K-contiguous (K = m): X is M x K (stored K-major, ldx a
+// multiple of 8 on a 16-byte aligned base), Y is FP32 K x N (ldy; 16-byte
+// loads when its columns are 16-byte aligned, else element loads).  One workgroup of eight waves covers a group of
+// up to 640 rows of C (512 for the three-product form) and a block of 64
+// columns; with one group (the sketch up to l = 640) A is streamed from HBM
+// once.  MFMA 16x16x32 (BF16 in, FP32
+// out): wave w owns the row tiles w, w + 8, w + 16, ... and all four
+// 16-column tiles of the block, so every row tile's X fragment is loaded by
+// exactly one wave, straight from global memory into registers in the MFMA
+// operand layout (16 bytes per lane: eight consecutive k of one row), one K
+// step ahead.  The FP32 columns of A go through LDS once per K step: loaded
+// one step ahead, rounded (and split) into BF16, stored into a double
+// buffer as [column][k] rows of 40 BF16 (80 bytes: the 16 lanes that read
+// one k-slice of 16 columns hit distinct banks), and read by every wave as
+// its B fragments.  One workgroup barrier per K step.
+//
+// Lane layout of v_mfma_f32_16x16x32_bf16 (checked by an in-bounds probe on
+// gfx950): lane l holds A[l % 16][8 (l / 16) + e] and B[8 (l / 16) + e][l % 16]
+// for e = 0..7; result register r of lane l is D[4 (l / 16) + r][l % 16].
+#include <algorithm>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace ffsrqr {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int MB_NT = 512;            // threads per workgroup (eight waves)
+constexpr int MB_BN = 64;             // columns per workgroup
+constexpr int MB_BK = 32;             // K per step (one MFMA)
+constexpr int MB_YS = 40;             // BF16 per LDS row of a Y column (32 + 8 padding)
+constexpr int MB_MAXT = 40;           // row tiles per group (640 rows)
+
+__device__ inline f32x4 mfma_bf16(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// BF16 round to nearest even of an FP32 value (the hardware conversion).
+__device__ inline __bf16 to_bf16(float x) { return (__bf16)x; }
+
+// NP = 1: C = Xhi^T bf16(Y).  NP = 3: C = Xhi^T Yhi + Xhi^T Ylo + Xlo^T Yhi.
+// NTW = row tiles per wave (ceil(MT / 8)).  Xlo is unused for NP = 1.
+template <int NP, int NTW>
+__global__ __launch_bounds__(MB_NT) void gemm_bf16_kernel(
+    int64_t M, int64_t N, int64_t K, int64_t kchunk, const __bf16* __restrict__ Xhi, const __bf16* __restrict__ Xlo,
+    int64_t ldx, const float* __restrict__ Y, int64_t ldy, float* __restrict__ C, int64_t ldc, int64_t cstride,
+    double* __restrict__ colnorm, int64_t nstride, int groups, int rows_per_group) {
+  constexpr int NB = NP == 1 ? 1 : 2;  // BF16 parts of Y held in LDS
+  __shared__ __attribute__((aligned(16))) __bf16 Ys[2][NB][MB_BN * MB_YS];
+  __shared__ double nred[MB_NT];
+
+  // workgroup -> (column block, row group); the groups of one column block
+  // take ids eight apart (same XCD, shared L2 for their common A columns)
+  int64_t tile = blockIdx.x;
+  int grp = 0;
+  if (groups > 1) {
+    const int64_t per = 8 * (int64_t)groups;
+    tile = (int64_t)(blockIdx.x / per) * 8 + blockIdx.x % 8;
+    grp = (int)((blockIdx.x % per) / 8);
+  }
+  const int64_t n0 = tile * MB_BN, r0 = (int64_t)grp * rows_per_group;
+  if (n0 >= N || r0 >= M) return;
+  const int64_t Mg = M - r0 < rows_per_group ? M - r0 : rows_per_group;
+  const int MT = (int)((Mg + 15) / 16);
+  const int64_t kb = (int64_t)blockIdx.z * kchunk;
+  const int64_t ke = (kb + kchunk < K) ? kb + kchunk : K;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int fr = lane & 15, fg = lane >> 4;  // fragment row/column and k-group
+
+  // X fragments: tile t = wave + 8 i, row r0 + 16 t + fr, k = k0 + 8 fg .. +7.
+  // Rows past Mg read row Mg - 1 (their results are discarded); k past ke
+  // is zero-filled.
+  const __bf16* xrow_hi[NTW];
+  const __bf16* xrow_lo[NTW];
+#pragma unroll
+  for (int i = 0; i < NTW; ++i) {
+    int64_t row = (int64_t)16 * (wave + 8 * i) + fr;
+    row = row < Mg ? row : Mg - 1;
+    xrow_hi[i] = Xhi + (r0 + row) * ldx;
+    xrow_lo[i] = NP == 3 ? Xlo + (r0 + row) * ldx : nullptr;
+  }
+  auto load_x = [&](bf16x8* xh, bf16x8* xl, int64_t k0) {
+    const int64_t k = k0 + 8 * fg;
+    const bool full = k + 8 <= ke;
+#pragma unroll
+    for (int i = 0; i < NTW; ++i) {
+      if (full) {
+        xh[i] = *reinterpret_cast<const bf16x8*>(xrow_hi[i] + k);
+        if (NP == 3) xl[i] = *reinterpret_cast<const bf16x8*>(xrow_lo[i] + k);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          xh[i][e] = k + e < ke ? xrow_hi[i][k + e] : (__bf16)0.0f;
+          if (NP == 3) xl[i][e] = k + e < ke ? xrow_lo[i][k + e] : (__bf16)0.0f;
+        }
+      }
+    }
+  };
+
+  // Y loader: thread tid moves four consecutive k (k0 + 4 (tid % 8)) of
+  // column n0 + tid / 8 (16 bytes); columns past N read column N - 1 and k
+  // past ke is zeroed.
+  const int yc = tid >> 3, yk = (tid & 7) * 4;
+  const int64_t ycol = n0 + yc < N ? n0 + yc : N - 1;
+  const float* ysrc = Y + ycol * ldy;
+  const bool ycol_ok = n0 + yc < N;
+  // 16-byte loads need 16-byte aligned columns (ldy % 4 == 0, aligned base)
+  const bool yvec = (ldy & 3) == 0 && (reinterpret_cast<uintptr_t>(Y) & 15) == 0;
+  float yv[4];
+  auto load_y = [&](int64_t k0) {
+    const int64_t k = k0 + yk;
+    if (yvec && k + 4 <= ke) {
+      const float4 v = *reinterpret_cast<const float4*>(ysrc + k);
+      yv[0] = v.x;
+      yv[1] = v.y;
+      yv[2] = v.z;
+      yv[3] = v.w;
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) yv[e] = k + e < ke ? ysrc[k + e] : 0.0f;
+    }
+  };
+  double nrm = 0.0;
+  auto store_y = [&](int buf) {
+    __bf16 hi[4], lo[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const float y = ycol_ok ? yv[e] : 0.0f;
+      hi[e] = to_bf16(y);
+      if (NP == 3) lo[e] = to_bf16(y - (float)hi[e]);
+      nrm = fma((double)y, (double)y, nrm);
+    }
+    __bf16* dst = &Ys[buf][0][yc * MB_YS + yk];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) dst[e] = hi[e];
+    if (NP == 3) {
+      __bf16* dl = &Ys[buf][NB - 1][yc * MB_YS + yk];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) dl[e] = lo[e];
+    }
+  };
+
+  f32x4 acc[NTW][4];
+#pragma unroll
+  for (int i = 0; i < NTW; ++i)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[i][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  // PRE: the next step's X fragments are loaded into a second register set
+  // before the current MFMAs; without it (the three-product form with five
+  // row tiles per wave, where two sets do not fit the 256 VGPRs of a wave)
+  // they are loaded into the same registers right after the MFMAs that read
+  // them, and the other wave of the SIMD covers the latency.
+  constexpr bool PRE = NP == 1 || NTW <= 4;  // always true with the groups chosen below
+  constexpr int NX = PRE ? NTW : 1;
+  bf16x8 xh[NTW], xl[NTW], nh[NX], nl[NX];
+  const int64_t nsteps = (ke - kb + MB_BK - 1) / MB_BK;
+  if (nsteps > 0) {
+    load_y(kb);
+    store_y(0);
+    load_x(xh, xl, kb);
+    load_y(kb + MB_BK);
+  }
+  for (int64_t st = 0; st < nsteps; ++st) {
+    const int64_t k0 = kb + st * MB_BK;
+    const int buf = (int)(st & 1);
+    if (PRE && st + 1 < nsteps) load_x(nh, nl, k0 + MB_BK);
+    __syncthreads();  // Ys[buf] complete; every read of Ys[buf ^ 1] done
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&Ys[buf][0][(16 * c + fr) * MB_YS + 8 * fg]);
+      bf16x8 bl;
+      if (NP == 3) bl = *reinterpret_cast<const bf16x8*>(&Ys[buf][NB - 1][(16 * c + fr) * MB_YS + 8 * fg]);
+#pragma unroll
+      for (int i = 0; i < NTW; ++i) {
+        if (wave + 8 * i < MT) {
+          acc[i][c] = mfma_bf16(xh[i], bh, acc[i][c]);
+          if (NP == 3) {
+            acc[i][c] = mfma_bf16(xh[i], bl, acc[i][c]);
+            acc[i][c] = mfma_bf16(xl[i], bh, acc[i][c]);
+          }
+        }
+      }
+    }
+    if (st + 1 < nsteps) {
+      if (PRE) {
+#pragma unroll
+        for (int i = 0; i < NX; ++i) {
+          xh[i] = nh[i];
+          if (NP == 3) xl[i] = nl[i];
+        }
+      } else {
+        load_x(xh, xl, k0 + MB_BK);
+      }
+      store_y(buf ^ 1);
+      if (st + 2 < nsteps) load_y(k0 + 2 * MB_BK);
+    }
+  }
+
+  float* Cz = C + (int64_t)blockIdx.z * cstride + r0;
+#pragma unroll
+  for (int i = 0; i < NTW; ++i) {
+    const int t = wave + 8 * i;
+    if (t >= MT) continue;
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = 16 * t + 4 * fg + r, col = n0 + 16 * c + fr;
+        if (row < Mg && col < N) Cz[col * ldc + row] = acc[i][c][r];
+      }
+  }
+  if (colnorm != nullptr && grp == 0) {
+    // the eight threads of a column hold disjoint k ranges: fixed-order sum
+    nred[tid] = nrm;
+    __syncthreads();
+    if (tid < MB_BN && n0 + tid < N) {
+      double s = 0.0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) s += nred[tid * 8 + q];
+      colnorm[(int64_t)blockIdx.z * nstride + n0 + tid] = s;
+    }
+  }
+}
+
+// xhi = bf16(x), xlo = bf16(x - xhi) for an M x K column-major FP32 block
+// (ld), written K-major with leading dimension ldo.
+__global__ void split_bf16_kernel(const float* __restrict__ X, int64_t rows, int64_t cols, int64_t ld,
+                                  __bf16* __restrict__ hi, __bf16* __restrict__ lo, int64_t ldo) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t j = blockIdx.y;
+  if (i >= rows || j >= cols) return;
+  const float x = X[j * ld + i];
+  const __bf16 h = to_bf16(x);
+  hi[j * ldo + i] = h;
+  lo[j * ldo + i] = to_bf16(x - (float)h);
+}
+
+__global__ void splitk_reduce_f32(int64_t M, int64_t N, int splits, const float* __restrict__ P,
+                                  float* __restrict__ C, int64_t ldc, const double* __restrict__ np,
+                                  double* __restrict__ colnorm) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < M * N) {
+    const int64_t row = idx % M, col = idx / M;
+    float s = 0.f;
+    for (int z = 0; z < splits; ++z) s += P[(int64_t)z * M * N + idx];
+    C[col * ldc + row] = s;
+  }
+  if (colnorm && idx < N) {
+    double s = 0;
+    for (int z = 0; z < splits; ++z) s += np[(int64_t)z * N + idx];
+    colnorm[idx] = s;
+  }
+}
+
+// Row groups: at most 40 row tiles (640 rows) per group for the one-product
+// form; 32 (512 rows, four tiles per wave) for the three-product form, whose
+// five-tile variant does not fit the 256 VGPRs of a wave.
+void bf16_shape(int nprod, int64_t M, int* groups, int* rows_per_group, int* ntw) {
+  const int maxt = nprod == 1 ? MB_MAXT : 32;
+  const int64_t g = (M + 16 * maxt - 1) / (16 * maxt);
+  const int64_t rows = ((M + g - 1) / g + 15) / 16 * 16;
+  *groups = (int)g;
+  *rows_per_group = (int)rows;
+  *ntw = (int)((rows / 16 + 7) / 8);
+}
+
+int bf16_splits(int nprod, int64_t M, int64_t N, int64_t K, int num_cu) {
+  int groups, rpg, ntw;
+  bf16_shape(nprod, M, &groups, &rpg, &ntw);
+  const int64_t tiles = (N + MB_BN - 1) / MB_BN * groups;
+  int64_t s = 1;
+  while (tiles * s < (int64_t)num_cu && K / (s * 2) >= 2048) s *= 2;
+  return (int)s;
+}
+
+template <int NP, int NTW = 1>
+hipError_t launch_bf16(int ntw, dim3 grid, hipStream_t s, int64_t M, int64_t N, int64_t K, int64_t kchunk,
+                       const __bf16* Xhi, const __bf16* Xlo, int64_t ldx, const float* Y, int64_t ldy, float* C,
+                       int64_t ldc, int64_t cstride, double* colnorm, int64_t nstride, int groups, int rpg) {
+  if constexpr (NTW <= (NP == 1 ? 5 : 4)) {
+    if (ntw == NTW) {
+      gemm_bf16_kernel<NP, NTW><<<grid, MB_NT, 0, s>>>(M, N, K, kchunk, Xhi, Xlo, ldx, Y, ldy, C, ldc, cstride,
+                                                       colnorm, nstride, groups, rpg);
+      return hipGetLastError();
+    }
+    return launch_bf16<NP, NTW + 1>(ntw, grid, s, M, N, K, kchunk, Xhi, Xlo, ldx, Y, ldy, C, ldc, cstride,
+                                    colnorm, nstride, groups, rpg);
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+size_t gemm_bf16_scratch(int64_t M, int64_t N, int64_t K, int num_cu) {
+  const int s = std::max(bf16_splits(1, M, N, K, num_cu), bf16_splits(3, M, N, K, num_cu));
+  if (s == 1) return 0;
+  return (size_t)s * M * N * sizeof(float) + (size_t)s * N * sizeof(double) + 1024;
+}
+
+hipError_t gemm_bf16(int nprod, int64_t M, int64_t N, int64_t K, const __bf16* Xhi, const __bf16* Xlo, int64_t ldx,
+                     const float* Y, int64_t ldy, float* C, int64_t ldc, double* colnorm, Arena& ar, int num_cu,
+                     hipStream_t s) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  if (K <= 0 || (nprod != 1 && nprod != 3) || M > 4 * 16 * MB_MAXT) return hipErrorInvalidValue;
+  // 16-byte X fragment loads: rows of X start on 16-byte boundaries
+  if ((ldx % 8) != 0 || (reinterpret_cast<uintptr_t>(Xhi) & 15) != 0 ||
+      (Xlo != nullptr && (reinterpret_cast<uintptr_t>(Xlo) & 15) != 0))
+    return hipErrorInvalidValue;
+  int groups, rpg, ntw;
+  bf16_shape(nprod, M, &groups, &rpg, &ntw);
+  const int splits = bf16_splits(nprod, M, N, K, num_cu);
+  int64_t kchunk = (K + splits - 1) / splits;
+  kchunk = (kchunk + MB_BK - 1) / MB_BK * MB_BK;
+  const int64_t ntile = (N + MB_BN - 1) / MB_BN;
+  const int64_t gx = groups > 1 ? (ntile + 7) / 8 * 8 * groups : ntile;
+  dim3 grid((unsigned)gx, 1u, (unsigned)splits);
+  float* out = C;
+  int64_t ldo = ldc, ostride = 0, nstride = 0;
+  double* nout = colnorm;
+  float* part = nullptr;
+  double* npart = nullptr;
+  if (splits > 1) {
+    part = ar.take<float>((size_t)splits * M * N);
+    npart = colnorm ? ar.take<double>((size_t)splits * N) : nullptr;
+    if (!part || (colnorm && !npart)) return hipErrorOutOfMemory;
+    out = part;
+    ldo = M;
+    ostride = M * N;
+    nout = npart;
+    nstride = N;
+  }
+  hipError_t e = nprod == 1
+                     ? launch_bf16<1>(ntw, grid, s, M, N, K, kchunk, Xhi, nullptr, ldx, Y, ldy, out, ldo, ostride,
+                                      nout, nstride, groups, rpg)
+                     : launch_bf16<3>(ntw, grid, s, M, N, K, kchunk, Xhi, Xlo, ldx, Y, ldy, out, ldo, ostride,
+                                      nout, nstride, groups, rpg);
+  if (e != hipSuccess || splits == 1) return e;
+  const int64_t total = M * N > N ? M * N : N;
+  splitk_reduce_f32<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(M, N, splits, part, C, ldc, npart, colnorm);
+  return hipGetLastError();
+}
+
+hipError_t split_bf16(const float* X, int64_t rows, int64_t cols, int64_t ld, __bf16* hi, __bf16* lo, int64_t ldo,
+                      hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  dim3 grid((unsigned)((rows + 255) / 256), (unsigned)cols);
+  split_bf16_kernel<<<grid, 256, 0, s>>>(X, rows, cols, ld, hi, lo, ldo);
+  return hipGetLastError();
+}
+
+}  // namespace ffsrqr

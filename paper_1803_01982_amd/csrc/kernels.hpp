@@ -47,6 +47,20 @@ hipError_t gemm_tn(int64_t M, int64_t N, int64_t K, const T* X, int64_t ldx, con
                    int64_t ldy, T* C, int64_t ldc, double* colnorm, Arena& ar, int num_cu,
                    hipStream_t s);
 
+// Mixed form (BF16 MFMA, FP32 accumulation), C (M x N, FP32) = X^T Y with
+// X M x K stored K-major (ldx, a multiple of 8) as BF16 parts and Y FP32
+// K x N (ldy, a multiple of 4).  nprod 1: C = Xhi^T bf16(Y) (the sketch;
+// colnorm, if non-null, gets ||Y(:, j)||^2 in FP64 from the FP32 entries).
+// nprod 3: the split-BF16 product Xhi^T Yhi + Xhi^T Ylo + Xlo^T Yhi.
+size_t gemm_bf16_scratch(int64_t M, int64_t N, int64_t K, int num_cu);
+hipError_t gemm_bf16(int nprod, int64_t M, int64_t N, int64_t K, const __bf16* Xhi, const __bf16* Xlo, int64_t ldx,
+                     const float* Y, int64_t ldy, float* C, int64_t ldc, double* colnorm, Arena& ar, int num_cu,
+                     hipStream_t s);
+// hi = bf16(X), lo = bf16(X - hi) for a rows x cols FP32 block (ld), into
+// K-major arrays with leading dimension ldo.
+hipError_t split_bf16(const float* X, int64_t rows, int64_t cols, int64_t ld, __bf16* hi, __bf16* lo, int64_t ldo,
+                      hipStream_t s);
+
 // Partial QRCP on B (l x n): piv[0:l], margins[0:l].
 template <typename T>
 size_t qrcp_scratch(int64_t l, int64_t n, const DeviceInfo& d);
@@ -62,6 +76,9 @@ hipError_t gather_cols(const T* A, int64_t m, int64_t n, int64_t lda, const int6
 
 // Householder QR of P (mrows x c, in place): explicit Q (mrows x c, ldq) and
 // R (c x c, or its transpose when transpose_r), with diag(R) >= 0.
+// Whether tall_qr supports mrows x c on device d (c <= 1024, the row blocks
+// fit the LDS and the co-resident grid).
+bool tallqr_fits(int64_t mrows, int64_t c, const DeviceInfo& d);
 template <typename T>
 size_t tallqr_scratch(int64_t mrows, int64_t c, const DeviceInfo& d);
 template <typename T>
@@ -98,6 +115,9 @@ struct SrqrState {
   int64_t istar;       // argmax rho (leading position)
   unsigned nonfinite;  // A held a NaN/Inf
   unsigned pad;
+  double jmargin;      // (gamma_j*^2 - next largest) / gamma_j*^2 after the recomputation
+  int64_t ncand;       // trailing columns whose residual was recomputed exactly
+  double ub_noncand;   // largest upper bound of gamma^2 over the other trailing columns
 };
 template <typename T>
 hipError_t residual_norms(const T* W, int64_t l, int64_t n, int64_t ldw, const double* anorm2,
@@ -108,7 +128,7 @@ template <typename T>
 hipError_t srqr_select(const double* gamma2, const double* anorm2, const unsigned char* inS, int64_t n,
                        const T* A, int64_t m, int64_t lda, const T* Q, int64_t ldq, const T* W,
                        int64_t ldw, const T* R11, int64_t ldr, int64_t l, SrqrState* st,
-                       Arena& ar, hipStream_t s);
+                       Arena& ar, hipStream_t s, double win = 0.0);
 // rho of R-tilde = [[R11, a], [0, alpha]].  With sel non-null, a is column
 // sel->jstar of the matrix at `a` (column stride a_stride) and alpha is
 // sel->alpha; otherwise a and alpha_host are used as given.  g2 and istar go

@@ -54,6 +54,28 @@ __device__ inline void philox4x64_10(uint64_t& x0, uint64_t& x1, uint64_t& x2, u
   }
 }
 
+// Nearest bfloat16 value of x, ties to even, taken from the FP64 value
+// directly (no intermediate FP32 rounding): with x = f 2^e, 1/2 <= |f| < 1,
+// bfloat16 keeps 8 significant bits, i.e. a spacing of 2^(e - 8) (2^-133
+// below 2^-126).  Finite x below the bfloat16 overflow threshold.
+__device__ inline __bf16 bf16_from_double(double x) {
+  if (x == 0.0) return (__bf16)0.0f;
+  int e;
+  (void)frexp(x, &e);
+  e = e < -125 ? -125 : e;
+  const double q = ldexp(rint(ldexp(x, 8 - e)), e - 8);  // exact in FP32 and in BF16
+  return (__bf16)(float)q;
+}
+
+template <typename T>
+__device__ inline T omega_value(double z) {
+  return (T)z;
+}
+template <>
+__device__ inline __bf16 omega_value<__bf16>(double z) {
+  return bf16_from_double(z);
+}
+
 template <typename T>
 __global__ void omega_kernel(uint64_t seed, int64_t l, int64_t m, T* __restrict__ Ot, int64_t ldo) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -64,7 +86,7 @@ __global__ void omega_kernel(uint64_t seed, int64_t l, int64_t m, T* __restrict_
   const double u1 = ((double)(x0 >> 12) + 0.5) * 0x1p-52;
   const double u2 = ((double)(x1 >> 12) + 0.5) * 0x1p-52;
   const double z = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
-  Ot[t + i * ldo] = (T)z;
+  Ot[t + i * ldo] = omega_value<T>(z);
 }
 
 template <typename T>
@@ -77,5 +99,6 @@ hipError_t launch_omega(uint64_t seed, int64_t l, int64_t m, T* Ot, int64_t ldo,
 
 template hipError_t launch_omega<double>(uint64_t, int64_t, int64_t, double*, int64_t, hipStream_t);
 template hipError_t launch_omega<float>(uint64_t, int64_t, int64_t, float*, int64_t, hipStream_t);
+template hipError_t launch_omega<__bf16>(uint64_t, int64_t, int64_t, __bf16*, int64_t, hipStream_t);
 
 }  // namespace ffsrqr

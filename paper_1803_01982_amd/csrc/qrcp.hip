@@ -17,7 +17,7 @@
 //      scratch over rows j+1..l-1 (the same definition as the oracle; no
 //      downdating drift to guard against).
 // Candidate slots are double-buffered by step parity, so one barrier per
-// step suffices.  The register-resident variant below (l <= 288) replaces
+// step suffices.  The register-resident variant below (l <= 544) replaces
 // the barrier by write-once slots per step.
 #include <algorithm>
 
@@ -488,9 +488,9 @@ void choose(int64_t l, int64_t n, int num_cu, size_t lds_max, size_t tsize, int*
 // Register variant: rows per thread NR (l <= 16 NR) and columns per thread
 // CB, fewest workgroups first (cheaper grid barriers); G <= num_cu.
 bool reg_choice(int64_t l, int64_t n, int num_cu, int* NR, int* CB, int* G) {
-  static const int nrs[] = {2, 4, 8, 18};
-  static const int cbs[] = {4, 4, 2, 1};
-  for (int k = 0; k < 4; ++k) {
+  static const int nrs[] = {2, 4, 8, 18, 34};
+  static const int cbs[] = {4, 4, 2, 1, 1};
+  for (int k = 0; k < 5; ++k) {
     if (l > 16 * nrs[k]) continue;
     const int64_t per = (int64_t)(NT / 16) * cbs[k];
     const int64_t g = (n + per - 1) / per;
@@ -510,6 +510,7 @@ const void* reg_kernel(int NR) {
     case 4: return (const void*)qrcp_reg_kernel<T, 4, 4>;
     case 8: return (const void*)qrcp_reg_kernel<T, 8, 2>;
     case 18: return (const void*)qrcp_reg_kernel<T, 18, 1>;
+    case 34: return (const void*)qrcp_reg_kernel<T, 34, 1>;
   }
   return nullptr;
 }

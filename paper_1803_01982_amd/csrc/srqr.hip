@@ -3,15 +3,28 @@
 //
 //   residual norms  gamma_j^2 = ||a_j||^2 - ||W(:, j)||^2 in FP64, W = Q1^T A
 //                   (the part of a_j outside span(Q1)); one wave per column.
-//   select          j* = argmax of gamma^2 over the trailing columns (ties to
-//                   the smallest index), then alpha = ||a_j* - Q1 W(:, j*)||
-//                   recomputed exactly in FP64 so that the swap test does not
-//                   depend on the cancellation in the difference of squares.
+//   select          the difference of squares loses the relative accuracy of
+//                   gamma_j^2 when gamma_j << ||a_j|| (an absolute error of
+//                   about c u ||a_j||^2, u the unit roundoff of W's arithmetic),
+//                   so it only preselects: every trailing column whose
+//                   approximate gamma_j^2 lies within the window
+//                   (4 sqrt(m) + l) u (||a_j||^2 + ||a_max||^2) of the largest
+//                   one is a candidate, and each candidate's residual is
+//                   recomputed as ||a_j - Q1 W(:, j)||^2 in FP64 (the error of
+//                   W then enters only to second order, since Q1 dW lies in
+//                   span(Q1), orthogonal to the residual).  j* is the argmax
+//                   of the recomputed values (ties to the smallest index),
+//                   alpha = gamma_j*, and the margin of the choice is
+//                   (gamma_j*^2 - g_2nd) / gamma_j*^2 with g_2nd the largest of
+//                   the other candidates' recomputed values and the upper
+//                   bounds gamma_j^2 + window of the non-candidates.
 //   rho             X = R11^{-1} and z = R11^{-1} a by column-oriented back
 //                   substitution (one workgroup per column, R staged in LDS in
 //                   chunks of 16 columns), then
 //                   rho_i^2 = alpha^2 ||X(i, :)||^2 + z_i^2, the squared norm of
 //                   row i of |alpha| R-tilde^{-1}; g2 = max(1, max_i rho_i).
+#include <cmath>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -94,35 +107,158 @@ __global__ void select_final(int nb, const double* pv, const int64_t* pi, const 
   }
 }
 
-// Partial sums of e_i^2, e = a_j* - Q W(:, j*), over row blocks.
-template <typename T>
-__global__ void alpha_partial(const T* __restrict__ A, int64_t m, int64_t lda, const T* __restrict__ Q,
-                              int64_t ldq, const T* __restrict__ W, int64_t ldw, int64_t l, const SrqrState* st,
-                              double* part) {
-  extern __shared__ double wcol[];
-  __shared__ double red[NT / 64];
-  const int64_t js = st->jstar;
-  if (js < 0) {
-    if (threadIdx.x == 0) part[blockIdx.x] = 0.0;
-    return;
-  }
-  for (int64_t s = threadIdx.x; s < l; s += NT) wcol[s] = (double)W[js * ldw + s];
-  __syncthreads();
-  double acc = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < m; i += (int64_t)gridDim.x * NT) {
-    double e = (double)A[js * lda + i];
-    for (int64_t s = 0; s < l; ++s) e -= (double)Q[s * ldq + i] * wcol[s];
-    acc += e * e;
-  }
-  acc = block_sum(acc, red);
-  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+// ------------------------------------------------------- j* candidates
+// Window of the preselection (see the header): the approximate gamma_j^2 of
+// a trailing column may exceed the true value by at most win (a_j + a_max)
+// where a = ||a||^2, so column j can beat the approximate maximum only when
+// gamma_j^2 >= gmax - win (a_j + a_max).
+__device__ inline bool is_cand(double g, double a, double gmax, double amax2, double win, bool lead) {
+  return !lead && g >= gmax - win * (a + amax2);
 }
 
-__global__ void alpha_final(int nb, const double* part, SrqrState* st) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    double t = 0.0;
-    for (int q = 0; q < nb; ++q) t += part[q];
-    st->alpha = sqrt(t);
+constexpr int CB_N = 1024;  // columns per block of the candidate compaction
+
+// Per block of CB_N columns: the number of candidates and the largest upper
+// bound gamma_j^2 + win a_j over the non-candidates (-1 when there is none).
+__global__ void cand_count(const double* __restrict__ gamma2, const double* __restrict__ anorm2,
+                           const unsigned char* __restrict__ inS, int64_t n, const SrqrState* st, double win,
+                           int64_t* cnt, double* ub) {
+  __shared__ double red[CB_N / 64];
+  __shared__ int64_t ri[CB_N / 64];
+  const int64_t j = (int64_t)blockIdx.x * CB_N + threadIdx.x;
+  const double gmax = st->gamma2_max, amax2 = anorm2[st->jstar >= 0 ? st->jstar : 0];
+  double c = 0.0, u = -1.0;
+  if (j < n && !inS[j]) {
+    if (is_cand(gamma2[j], anorm2[j], gmax, amax2, win, false)) c = 1.0;
+    else u = gamma2[j] + win * anorm2[j];
+  }
+  c = block_sum(c, red);
+  const ArgMax m = block_argmax(ArgMax{u, 0}, red, ri);
+  if (threadIdx.x == 0) {
+    cnt[blockIdx.x] = (int64_t)c;
+    ub[blockIdx.x] = m.v;
+  }
+}
+
+// Exclusive prefix of the block counts (in place); the total and the
+// largest non-candidate bound go to the state.
+__global__ void cand_scan(int64_t* cnt, const double* ub, int nb, SrqrState* st) {
+  if (threadIdx.x == 0) {
+    int64_t run = 0;
+    double u = -1.0;
+    for (int q = 0; q < nb; ++q) {
+      const int64_t c = cnt[q];
+      cnt[q] = run;
+      run += c;
+      u = ub[q] > u ? ub[q] : u;
+    }
+    st->ncand = run;
+    st->ub_noncand = u;
+  }
+}
+
+// list[0:ncand] = the candidates in ascending column order.
+__global__ void cand_scatter(const double* __restrict__ gamma2, const double* __restrict__ anorm2,
+                             const unsigned char* __restrict__ inS, int64_t n, const SrqrState* st, double win,
+                             const int64_t* cnt, int64_t* list) {
+  __shared__ int sc[CB_N];
+  const int64_t j = (int64_t)blockIdx.x * CB_N + threadIdx.x;
+  const double gmax = st->gamma2_max, amax2 = anorm2[st->jstar >= 0 ? st->jstar : 0];
+  const int f = (j < n && is_cand(gamma2[j], anorm2[j], gmax, amax2, win, inS[j] != 0)) ? 1 : 0;
+  sc[threadIdx.x] = f;
+  __syncthreads();
+  for (int o = 1; o < CB_N; o <<= 1) {  // inclusive Hillis-Steele scan
+    const int v = threadIdx.x >= o ? sc[threadIdx.x - o] : 0;
+    __syncthreads();
+    sc[threadIdx.x] += v;
+    __syncthreads();
+  }
+  if (f) list[cnt[blockIdx.x] + sc[threadIdx.x] - 1] = j;
+}
+
+// Row-block partial sums of e_i^2, e = a_c - Q W(:, c), for the candidates
+// c of chunks of CC: blockIdx.x strides over the rows, blockIdx.y over the
+// chunks.  part[t * gridDim.x + blockIdx.x] for candidate t of the list.
+constexpr int CC = 8;
+template <typename T>
+__global__ void cand_exact(const T* __restrict__ A, int64_t m, int64_t lda, const T* __restrict__ Q, int64_t ldq,
+                           const T* __restrict__ W, int64_t ldw, int64_t l, const int64_t* __restrict__ list,
+                           const SrqrState* st, double* __restrict__ part) {
+  extern __shared__ double wl[];  // wl[s * CC + c] = W(s, list[chunk * CC + c])
+  __shared__ double red[NT / 64];
+  const int64_t nc = st->ncand;
+  const int64_t nchunk = (nc + CC - 1) / CC;
+  for (int64_t ch = blockIdx.y; ch < nchunk; ch += gridDim.y) {
+    int64_t col[CC];
+#pragma unroll
+    for (int c = 0; c < CC; ++c) {
+      const int64_t t = ch * CC + c;
+      col[c] = t < nc ? list[t] : -1;
+    }
+    __syncthreads();
+    for (int64_t e = threadIdx.x; e < l * CC; e += NT) {
+      const int c = (int)(e % CC);
+      const int64_t sidx = e / CC;
+      wl[e] = col[c] >= 0 ? (double)W[col[c] * ldw + sidx] : 0.0;
+    }
+    __syncthreads();
+    double acc[CC];
+#pragma unroll
+    for (int c = 0; c < CC; ++c) acc[c] = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < m; i += (int64_t)gridDim.x * NT) {
+      double ev[CC];
+#pragma unroll
+      for (int c = 0; c < CC; ++c) ev[c] = col[c] >= 0 ? (double)A[col[c] * lda + i] : 0.0;
+      for (int64_t sidx = 0; sidx < l; ++sidx) {
+        const double q = (double)Q[sidx * ldq + i];
+#pragma unroll
+        for (int c = 0; c < CC; ++c) ev[c] = fma(-q, wl[sidx * CC + c], ev[c]);
+      }
+#pragma unroll
+      for (int c = 0; c < CC; ++c) acc[c] = fma(ev[c], ev[c], acc[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < CC; ++c) {
+      const double t = block_sum(acc[c], red);
+      if (threadIdx.x == 0 && col[c] >= 0) part[(ch * CC + c) * gridDim.x + blockIdx.x] = t;
+    }
+  }
+}
+
+// j* = argmax of the recomputed gamma^2 (ties to the smallest index),
+// alpha = gamma_j*, and the margin of the choice.
+__global__ void cand_final(const int64_t* __restrict__ list, const double* __restrict__ part, int na,
+                           SrqrState* st) {
+  __shared__ double rv[NT / 64];
+  __shared__ int64_t ri[NT / 64];
+  const int64_t nc = st->ncand;
+  ArgMax b{0.0, -1};
+  for (int64_t t = threadIdx.x; t < nc; t += NT) {
+    double g = 0.0;
+    for (int x = 0; x < na; ++x) g += part[t * na + x];
+    if (better(g, list[t], b.v, b.i)) b = ArgMax{g, list[t]};
+  }
+  const ArgMax top = block_argmax(b, rv, ri);
+  ArgMax s2{-1.0, -1};
+  for (int64_t t = threadIdx.x; t < nc; t += NT) {
+    if (list[t] == top.i) continue;
+    double g = 0.0;
+    for (int x = 0; x < na; ++x) g += part[t * na + x];
+    if (g > s2.v) s2 = ArgMax{g, 0};
+  }
+  const ArgMax second = block_argmax(s2, rv, ri);
+  if (threadIdx.x == 0) {
+    if (top.i < 0) {
+      st->alpha = 0.0;
+      st->jmargin = 1.0;
+      return;
+    }
+    const double g1 = top.v > 0.0 ? top.v : 0.0;
+    const double g2nd = second.v > st->ub_noncand ? second.v : st->ub_noncand;
+    st->jstar = top.i;
+    st->gamma2_max = g1;
+    st->alpha = sqrt(g1);
+    st->jmargin = g1 > 0.0 ? (g2nd < 0.0 ? 1.0 : (g1 - g2nd) / g1) : 0.0;
   }
 }
 
@@ -288,30 +424,49 @@ hipError_t residual_norms(const T* W, int64_t l, int64_t n, int64_t ldw, const d
   return hipGetLastError();
 }
 
+constexpr int kCandRowBlocks = 32;  // row blocks of the candidate recomputation
+
 template <typename T>
 size_t srqr_scratch(int64_t m, int64_t n, int64_t l) {
-  return sizeof(double) * ((size_t)(l + 1) * l + 4 * 1024) + sizeof(int64_t) * 1024 + 4 * 1024 + 8 * 256;
+  const size_t nb = (size_t)(n + CB_N - 1) / CB_N;
+  return sizeof(double) * ((size_t)(l + 1) * l + 4 * 1024) + sizeof(int64_t) * 1024 + 4 * 1024 + 8 * 256 +
+         nb * (sizeof(int64_t) + sizeof(double)) + (size_t)n * sizeof(int64_t) +
+         (size_t)n * kCandRowBlocks * sizeof(double) + 8 * 256;
 }
 
 template <typename T>
 hipError_t srqr_select(const double* gamma2, const double* anorm2, const unsigned char* inS, int64_t n, const T* A,
                        int64_t m, int64_t lda, const T* Q, int64_t ldq, const T* W, int64_t ldw, const T* R11,
-                       int64_t ldr, int64_t l, SrqrState* st, Arena& ar, hipStream_t s) {
+                       int64_t ldr, int64_t l, SrqrState* st, Arena& ar, hipStream_t s, double win) {
   int nb = (int)((n + NT - 1) / NT);
   if (nb > 1024) nb = 1024;
   double* pv = ar.take<double>(1024);
   int64_t* pi = ar.take<int64_t>(1024);
   double* pa = ar.take<double>(1024);
   unsigned* pnf = ar.take<unsigned>(1024);
-  double* part = ar.take<double>(1024);
-  if (!pv || !pi || !pa || !pnf || !part) return hipErrorOutOfMemory;
+  if (!pv || !pi || !pa || !pnf) return hipErrorOutOfMemory;
   select_partial<<<nb, NT, 0, s>>>(gamma2, anorm2, inS, n, pv, pi, pa, pnf);
   select_final<T><<<1, NT, 0, s>>>(nb, pv, pi, pa, pnf, R11, ldr, l, st);
   if (l <= 0) return hipGetLastError();  // only the non-finite / norm scan was wanted
+  const int cb = (int)((n + CB_N - 1) / CB_N);
+  int64_t* cnt = ar.take<int64_t>(cb);
+  double* ub = ar.take<double>(cb);
+  int64_t* list = ar.take<int64_t>(n);
+  double* part = ar.take<double>((size_t)n * kCandRowBlocks);
+  if (!cnt || !ub || !list || !part) return hipErrorOutOfMemory;
+  cand_count<<<cb, CB_N, 0, s>>>(gamma2, anorm2, inS, n, st, win, cnt, ub);
+  cand_scan<<<1, 64, 0, s>>>(cnt, ub, cb, st);
+  cand_scatter<<<cb, CB_N, 0, s>>>(gamma2, anorm2, inS, n, st, win, cnt, list);
   int na = (int)((m + NT - 1) / NT);
-  if (na > 512) na = 512;
-  alpha_partial<T><<<na, NT, (size_t)l * sizeof(double), s>>>(A, m, lda, Q, ldq, W, ldw, l, st, part);
-  alpha_final<<<1, 64, 0, s>>>(na, part, st);
+  if (na > kCandRowBlocks) na = kCandRowBlocks;
+  const size_t lds = (size_t)l * CC * sizeof(double);
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)cand_exact<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  cand_exact<T><<<dim3((unsigned)na, 32u), NT, lds, s>>>(A, m, lda, Q, ldq, W, ldw, l, list, st, part);
+  cand_final<<<1, NT, 0, s>>>(list, part, na, st);
   return hipGetLastError();
 }
 
@@ -364,7 +519,7 @@ hipError_t assemble_r(const T* R11, int64_t ldr11, const T* W, int64_t ldw, cons
   template size_t srqr_scratch<T>(int64_t, int64_t, int64_t);                                                       \
   template hipError_t srqr_select<T>(const double*, const double*, const unsigned char*, int64_t, const T*, int64_t, \
                                      int64_t, const T*, int64_t, const T*, int64_t, const T*, int64_t, int64_t,      \
-                                     SrqrState*, Arena&, hipStream_t);                                              \
+                                     SrqrState*, Arena&, hipStream_t, double);                                      \
   template hipError_t srqr_rho<T>(const T*, int64_t, const T*, int64_t, const SrqrState*, double, int64_t, double*, \
                                   SrqrState*, Arena&, hipStream_t);                                                 \
   template hipError_t assemble_rt<T>(const T*, int64_t, const T*, int64_t, const int64_t*, int64_t, int64_t, T*,   \

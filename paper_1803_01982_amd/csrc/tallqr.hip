@@ -1200,6 +1200,14 @@ void gram_split(int64_t mrows, int64_t c, int num_cu, int* nsplit, int64_t* chun
   *nsplit = (int)((mrows + ch - 1) / ch);
 }
 
+bool tallqr_fits(int64_t mrows, int64_t c, const DeviceInfo& d) {
+  if (c < 1 || c > 1024 || mrows < c) return false;
+  int G, rb;
+  size_t lds;
+  choose(mrows, (int)c, d.num_cu, &G, &rb, &lds);
+  return lds <= d.lds_max && G <= kMaxGridBlocks && (rb + NT - 1) / NT <= 4;
+}
+
 template <typename T>
 size_t tallqr_scratch(int64_t mrows, int64_t c, const DeviceInfo& d) {
   int G, rb, nsplit;

@@ -48,7 +48,8 @@ def test_omega_fp32_is_rounded_fp64(ff):
 # column blocks and K chunks)
 @pytest.mark.parametrize("m,n,l", [(1000, 800, 30), (1000, 333, 30), (8192, 200, 20), (130, 70, 65),
                                    (3000, 130, 129), (5000, 517, 150), (2000, 300, 288),
-                                   (16384, 2048, 272), (4096, 700, 300)])
+                                   (16384, 2048, 272), (4096, 700, 300), (6000, 700, 544), (5000, 700, 600),
+                                   (3000, 1100, 1000)])
 def test_sketch_fp64(ff, m, n, l):
     announce(f"sketch fp64 m={m} n={n} l={l}")
     A = synth.random_matrix(m, n, seed=m + n)
@@ -60,11 +61,12 @@ def test_sketch_fp64(ff, m, n, l):
     assert np.max(np.abs(host(an) - np.sum(A * A, axis=0)) / np.sum(A * A, axis=0)) < 4 * m * EPS
 
 
-@pytest.mark.parametrize("l", [40, 136])
+@pytest.mark.parametrize("l", [40, 136, 544])
 def test_sketch_fp32(ff, l):
     import torch
-    announce(f"sketch fp32 m=2000 n=300 l={l}")
-    A = synth.random_matrix(2000, 300, seed=5).astype(np.float32)
+    n = max(300, l + 100)
+    announce(f"sketch fp32 m=2000 n={n} l={l}")
+    A = synth.random_matrix(2000, n, seed=5).astype(np.float32)
     B, an = ff.sketch(dev_f(A, torch.float32), 4, l)
     Om32 = oracle.omega(4, l, 2000).astype(np.float32).astype(np.float64)
     A64 = A.astype(np.float64)
@@ -74,11 +76,55 @@ def test_sketch_fp32(ff, l):
     assert np.max(np.abs(host(an) - np.sum(A64 * A64, axis=0)) / np.sum(A64 * A64, axis=0)) < 1e-12
 
 
+# Mixed form: B = bf16(Omega) bf16(A) with FP32 sums.  The oracle's bf16
+# sketch is the FP64 sum of the same exact products, so the difference is the
+# FP32 summation error, at most m 2^-24 sum_t |bf16(Omega_it)| |bf16(A_tj)|.
+# l = 544 is one row group of the kernel, l = 700 two; ragged m and n.
+@pytest.mark.parametrize("m,n,l", [(1000, 800, 30), (3001, 517, 136), (8192, 1100, 544), (2000, 900, 700),
+                                   (40000, 64, 16)])
+def test_sketch_mixed(ff, m, n, l):
+    import torch
+    announce(f"sketch mixed m={m} n={n} l={l}")
+    A = synth.random_matrix(m, n, seed=m + 3 * n).astype(np.float32)
+    B, an = ff.sketch(dev_f(A, torch.float32), 6, l, mixed=True)
+    A64 = A.astype(np.float64)
+    Om = oracle.omega(6, l, m)
+    Bref = oracle.sketch(Om, A64, "bf16")
+    bound = m * 2.0 ** -24 * (np.abs(oracle.round_bf16(Om)) @ np.abs(oracle.round_bf16(A64)))
+    err = np.abs(host(B).astype(np.float64) - Bref)
+    print(f"[gpu-case] max err / bound {np.max(err / bound):.3e}", flush=True)
+    assert np.all(err <= bound)
+    an_ref = np.sum(A64 * A64, axis=0)
+    assert np.max(np.abs(host(an) - an_ref) / an_ref) < 1e-12
+
+
+# Split-BF16 projection: each product q a is replaced by
+# qhi ahi + qhi alo + qlo ahi, whose error is at most about 3 2^-18 |q a|
+# (the dropped qlo alo and the two representation remainders), plus the FP32
+# summation error m 2^-24 of the sum of |q a|.
+@pytest.mark.parametrize("m,n,c", [(1000, 800, 30), (4100, 1100, 200), (8192, 700, 544), (2049, 300, 17)])
+def test_project_mixed(ff, m, n, c):
+    import torch
+    announce(f"project mixed m={m} n={n} c={c}")
+    A = synth.random_matrix(m, n, seed=c + 1000).astype(np.float32)
+    Qr, _ = oracle.householder_qr(synth.random_matrix(m, c, seed=c + 1001))
+    Q32 = Qr.astype(np.float32)
+    A64, Q64 = A.astype(np.float64), Q32.astype(np.float64)
+    an = np.sum(A64 * A64, axis=0)
+    W, g2 = ff.project(dev_f(Q32, torch.float32), dev_f(A, torch.float32), torch.from_numpy(an).cuda(), mixed=True)
+    Wr = oracle.project(Q64, A64)
+    bound = (3.0 * 2.0 ** -18 * 1.01 + m * 2.0 ** -24) * (np.abs(Q64.T) @ np.abs(A64))
+    err = np.abs(host(W).astype(np.float64) - Wr)
+    print(f"[gpu-case] max err / bound {np.max(err / bound):.3e}", flush=True)
+    assert np.all(err <= bound)
+
+
 # ------------------------------------------------------------------- QRCP
 # register-resident kernel (l <= 288 and few enough columns) and the LDS /
 # global-memory kernel (larger l or n) are both covered
 @pytest.mark.parametrize("l,n,seed", [(30, 800, 1), (30, 1001, 2), (64, 5000, 3), (100, 60000, 4), (8, 8, 5),
-                                      (1, 50, 6), (200, 4000, 7), (272, 8192, 8), (300, 2000, 9)])
+                                      (1, 50, 6), (200, 4000, 7), (272, 8192, 8), (300, 2000, 9),
+                                      (544, 16384, 10), (400, 3000, 11), (544, 20000, 12)])
 def test_qrcp_pivots_fp64(ff, l, n, seed):
     announce(f"qrcp fp64 l={l} n={n} seed={seed}")
     B = synth.random_matrix(l, n, seed=seed)
@@ -120,7 +166,7 @@ def test_qrcp_orthogonal_columns(ff):
 # substitution; c = 520 takes the column-per-wave kernel
 @pytest.mark.parametrize("m,n,c,seed", [(1000, 800, 30, 1), (1000, 800, 37, 2), (300, 50, 5, 3),
                                         (5000, 400, 100, 4), (64, 64, 64, 5), (16384, 300, 17, 6),
-                                        (1100, 600, 512, 8), (1300, 600, 520, 9)])
+                                        (1100, 600, 512, 8), (1300, 600, 520, 9), (20000, 600, 544, 10)])
 def test_panel_qr_fp64(ff, m, n, c, seed):
     import torch
     announce(f"panel_qr fp64 m={m} n={n} c={c}")
@@ -210,7 +256,7 @@ def test_srqr_rho_fp64(ff, l, seed):
 
 
 # --------------------------------------------------------------- flip-flop
-@pytest.mark.parametrize("l,n,seed", [(30, 800, 1), (37, 500, 2), (5, 5, 3), (64, 3000, 4)])
+@pytest.mark.parametrize("l,n,seed", [(30, 800, 1), (37, 500, 2), (5, 5, 3), (64, 3000, 4), (544, 4000, 5)])
 def test_lq_fp64(ff, l, n, seed):
     import torch
     announce(f"lq fp64 l={l} n={n}")
@@ -226,7 +272,7 @@ def test_lq_fp64(ff, l, n, seed):
 
 # --------------------------------------------------------------- small SVD
 @pytest.mark.parametrize("l,kind", [(30, "qlp"), (2, "gauss"), (31, "gauss"), (100, "graded"), (272, "qlp"),
-                                    (16, "rankdef")])
+                                    (16, "rankdef"), (544, "qlp")])
 def test_svd_small_fp64(ff, l, kind):
     announce(f"svd_small fp64 l={l} kind={kind}")
     rng = np.random.default_rng(l)
@@ -240,9 +286,18 @@ def test_svd_small_fp64(ff, l, kind):
         M = rng.standard_normal((l, l))
     sig = host(ff.svd_small(dev_f(M)))
     ref, _ = oracle.jacobi_svd(M)
-    lap = np.linalg.svd(M, compute_uv=False)
-    # absolute agreement at the FP64 level of sigma_1, relative agreement for
-    # the singular values that FP64 Jacobi resolves to 1e-11 (>= 1e-3 sigma_1)
-    keep = lap > 1e-3 * lap[0]
-    assert np.max(np.abs(sig - ref)) < 1e-13 * ref[0]
-    assert np.max(np.abs(sig[keep] - ref[keep]) / ref[keep]) < 1e-11
+    # Both sides are one-sided Jacobi, whose computed singular values carry a
+    # relative error of at most about l u kappa_s, kappa_s the condition
+    # number of M with its columns scaled to unit norm (Demmel and Veselic):
+    # each sigma_j is compared to that bound, and in absolute terms to
+    # 8 l u sigma_1, the order of the backward error of l sweeps' worth of
+    # plane rotations on each side (u = 2^-53).
+    nrm = np.linalg.norm(M, axis=0)
+    cols = nrm > 0
+    kappa_s = np.linalg.cond(M[:, cols] / nrm[cols]) if np.all(cols) else np.inf
+    assert np.max(np.abs(sig - ref)) < 4.0 * l * EPS * ref[0]
+    if np.isfinite(kappa_s):
+        rel_tol = 8.0 * l * EPS * kappa_s
+        print(f"[gpu-case] kappa_s {kappa_s:.3e}, relative bound {rel_tol:.2e}, worst "
+              f"{np.max(np.abs(sig - ref) / ref):.2e}", flush=True)
+        assert np.all(np.abs(sig - ref) <= rel_tol * ref)

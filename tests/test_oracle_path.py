@@ -196,3 +196,42 @@ def test_result_depends_only_on_leading_set(small):
     s2, _ = oracle.jacobi_svd(L2)
     assert np.max(np.abs(s2 - r.sigma) / r.sigma) < 1e-12
     assert abs(dg.residual_fro(A, Q2, L2, V2) - dg.residual_fro(A, r.Q, r.L, r.V)) < 1e-12
+
+
+def _integer_low_rank(m, n, r, seed):
+    """A = X Y^T with small integer factors: every entry is an integer below
+    2^24, so the matrix is exactly the same in FP32 and FP64 storage and has
+    exact rank r."""
+    rng = np.random.default_rng(seed)
+    X = rng.integers(-2, 3, size=(m, r)).astype(np.float64)
+    Y = rng.integers(-2, 3, size=(n, r)).astype(np.float64)
+    return np.asfortranarray(X @ Y.T)
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+def test_rank_tolerance_finds_exact_integer_rank(storage):
+    """Exactly dependent columns held in either precision: the rule of the
+    storage flags RANK_DEFICIENT and counts the exact rank (r = 20 < l = 30,
+    past the first 16-column block)."""
+    A = _integer_low_rank(200, 150, 20, seed=5)
+    assert np.linalg.matrix_rank(A) == 20
+    r = oracle.ffsrqr(A, 25, 5, seed=0, storage=storage)
+    assert r.flags & oracle.FLAG_RANK_DEFICIENT
+    assert r.numerical_rank == 20
+
+
+def test_rank_tolerance_fp32_keeps_a_conditioned_full_rank_matrix():
+    """sigma_min / sigma_1 = 1e-3 is far above FP32 rounding: not flagged."""
+    A = synth.spectrum_matrix(300, 200, np.logspace(0, -3, 200), seed=6).astype(np.float32)
+    r = oracle.ffsrqr(A.astype(np.float64), 30, 5, seed=0, storage="fp32")
+    assert not r.flags & oracle.FLAG_RANK_DEFICIENT
+    assert r.numerical_rank == r.l
+
+
+def test_rank_tolerance_values():
+    """The two thresholds written out: max(m, n) 2^-52 a_max for FP64 storage and
+    8 sqrt(max(m, n)) 2^-24 a_max for FP32 storage."""
+    assert oracle.rank_tolerance(100, 400, 2.0, "fp64") == 400 * 2.0 ** -52 * 2.0
+    assert oracle.rank_tolerance(400, 100, 2.0, "fp32") == 8 * 20 * 2.0 ** -24 * 2.0
+    with pytest.raises(ValueError):
+        oracle.rank_tolerance(1, 1, 1.0, "bf16")
