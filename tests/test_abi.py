@@ -77,6 +77,33 @@ def test_workspace_size_rejects_bad_dims(lib, m, n, k, p):
     assert lib.ffsrqr_last_error()
 
 
+def test_workspace_size_limits(lib):
+    """l = min(k + p, m, n) <= 1024, and the panel rows of the m x l and n x l
+    Householder QRs must fit the LDS of a workgroup (at most
+    256 min(1024, 1259 - l) rows): sizes beyond are EINVAL, checked on the
+    host before anything is enqueued."""
+    from paper_1803_01982_amd import _lib
+    out = C.c_size_t(0)
+    o = _lib.Opts(0, -1, 2.0)
+    assert lib.ffsrqr_workspace_size(4000, 3000, 1000, 24, C.byref(o), C.byref(out)) == 0   # l = 1024
+    assert lib.ffsrqr_workspace_size(4000, 3000, 1000, 25, C.byref(o), C.byref(out)) == 1   # l = 1025
+    assert b"1024" in lib.ffsrqr_last_error()
+    assert lib.ffsrqr_workspace_size(183040, 2000, 512, 32, C.byref(o), C.byref(out)) == 0  # l = 544
+    assert lib.ffsrqr_workspace_size(184000, 2000, 512, 32, C.byref(o), C.byref(out)) == 1
+    assert lib.ffsrqr_workspace_size(2000, 184000, 512, 32, C.byref(o), C.byref(out)) == 1
+
+
+def test_workspace_size_mixed(lib):
+    """The mixed form keeps FP32 storage: its workspace is the FP32 one plus
+    the BF16 operand rows (m rounded up to 8)."""
+    from paper_1803_01982_amd import _lib
+    out = C.c_size_t(0)
+    assert lib.ffsrqr_workspace_size(32768, 16384, 512, 32, C.byref(_lib.Opts(1, -1, 2.0)), C.byref(out)) == 0
+    fp32 = out.value
+    assert lib.ffsrqr_workspace_size(32768, 16384, 512, 32, C.byref(_lib.Opts(2, -1, 2.0)), C.byref(out)) == 0
+    assert out.value >= fp32
+
+
 def test_workspace_size_rejects_bad_precision_and_null(lib):
     from paper_1803_01982_amd import _lib
     out = C.c_size_t(0)
@@ -98,7 +125,7 @@ def _factor(lib, m=10, n=8, lda=10, k=2, p=1, ldq=10, ldl=3, ldv=8, g=2.0, prec=
 
 
 @pytest.mark.parametrize("kw", [dict(m=0), dict(k=0), dict(k=9), dict(p=-2), dict(lda=9), dict(ldq=9),
-                                dict(ldl=2), dict(ldv=7), dict(g=1.0), dict(g=0.5), dict(prec=3),
+                                dict(ldl=2), dict(ldv=7), dict(g=1.0), dict(g=0.5), dict(prec=3), dict(prec=-1),
                                 dict(null="A"), dict(null="Q"), dict(null="sigma"), dict(null="work")])
 def test_factor_argument_checks(lib, kw):
     assert _factor(lib, **kw) == 1

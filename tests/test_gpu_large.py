@@ -51,23 +51,6 @@ def test_large_q(large_q, prec):
     perm, sig = host(out.perm), host(out.sigma)
     assert out.info["l"] == ref.l == 544
     assert out.info["flags"] == ref.flags
-    if ref.margins.min() >= mfloor:
-        assert np.array_equal(perm, ref.perm)
-        assert out.info["swaps"] == ref.swaps
-        if ref.jstar_margin >= (1e-3 if fp32 else 1e-10):
-            assert out.info["jstar"] == ref.jstar
-        if not fp32:
-            assert abs(out.info["g2"] - ref.g2) < 1e-8 * ref.g2
-    else:
-        bad = int(np.flatnonzero(ref.margins < mfloor)[0])
-        print(f"[gpu-case] QRCP near-tie at step {bad} (margin {ref.margins[bad]:.2e}): "
-              f"pivots compared up to it", flush=True)
-        assert np.array_equal(perm[:bad], ref.perm[:bad])
-    err = np.abs(sig - ref.sigma)
-    print(f"[gpu-case] sigma: max rel err {np.max(err / ref.sigma):.3e}, j <= k "
-          f"{np.max(err[:w.k] / ref.sigma[:w.k]):.3e}, max abs / sigma_1 {np.max(err) / ref.sigma[0]:.3e}",
-          flush=True)
-    assert np.all(err <= tol * ref.sigma + floor * ref.sigma[0])
     Q, L, V = (host(t).astype(np.float64) for t in (out.Q, out.L, out.V))
     l = ref.l
     orth = 1e-13 if not fp32 else 1e-5 * np.sqrt(l)
@@ -75,7 +58,36 @@ def test_large_q(large_q, prec):
     assert np.linalg.norm(V.T @ V - np.eye(l)) < orth
     res = dg.residual_fro(Ah, Q, L, V)
     res_ref = dg.residual_fro(Ah, ref.Q, ref.L, ref.V)
-    assert abs(res - res_ref) <= tol * res_ref
+    err = np.abs(sig - ref.sigma)
+    print(f"[gpu-case] sigma vs oracle: max rel err {np.max(err / ref.sigma):.3e}, j <= k "
+          f"{np.max(err[:w.k] / ref.sigma[:w.k]):.3e}, max abs / sigma_1 {np.max(err) / ref.sigma[0]:.3e}; "
+          f"residual {res:.6e} vs {res_ref:.6e}", flush=True)
+    if ref.margins.min() >= mfloor:
+        assert np.array_equal(perm, ref.perm)
+        assert out.info["swaps"] == ref.swaps
+        if ref.jstar_margin >= (1e-3 if fp32 else 1e-10):
+            assert out.info["jstar"] == ref.jstar
+        if not fp32:
+            assert abs(out.info["g2"] - ref.g2) < 1e-8 * ref.g2
+        assert np.all(err <= tol * ref.sigma + floor * ref.sigma[0])
+        assert abs(res - res_ref) <= tol * res_ref
+    else:
+        # A QRCP step of the oracle whose margin is below what this form's
+        # rounding resolves: the pivots are exact up to it, and after it the
+        # two leading sets may differ, so sigma(L) and the residual (functions
+        # of the set) are only held to what every SRQR-certified set meets:
+        # g2 <= g, interlacing with sigma(A), the residual within 1% of the
+        # oracle's, and sigma_j(L)^2 >= sigma_j(A)^2 - res^2.
+        bad = int(np.flatnonzero(ref.margins < mfloor)[0])
+        print(f"[gpu-case] QRCP near-tie at step {bad} (margin {ref.margins[bad]:.2e}): "
+              f"pivots compared up to it, set-level bounds after it", flush=True)
+        assert np.array_equal(perm[:bad], ref.perm[:bad])
+        assert out.info["g2"] <= 2.0
+        s_true = w.sigma()[:l]
+        nn = w.noise * (np.sqrt(w.m) + np.sqrt(w.n)) * 1.01
+        assert np.all(sig <= s_true + nn)
+        assert res <= 1.01 * res_ref
+        assert np.all(sig ** 2 >= np.maximum(s_true - nn, 0.0) ** 2 - res ** 2)
 
 
 def test_large_fp64_full_size():
