@@ -263,6 +263,20 @@ ffsrqr_status ffsrqr_svd_small(const void* L, int64_t l, int64_t ldl, double* si
                                void* work, size_t work_bytes, int32_t precision,
                                ffsrqr_stream_t stream);
 
+/*
+ * ffsrqr_svd_small without a workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, harnesses
+ * that forbid allocation): the same kernels and results as
+ * ffsrqr_svd_small, with their scratch in a static device array of the
+ * library (about 8.4 MB per GPU, held until the process ends; the call
+ * itself allocates nothing).  l <= 1024, else FFSRQR_EINVAL.  Every call on
+ * one GPU shares that GPU's array: calls that overlap on one GPU (other
+ * streams, other host threads) race and must be serialised by the caller.
+ * Each call clears what must start at zero with kernels on its stream.
+ */
+ffsrqr_status ffsrqr_svd_small_noalloc(const void* L, int64_t l, int64_t ldl, double* sigma,
+                                       int32_t precision, ffsrqr_stream_t stream);
+
 /* ---------------------------------------------------------------------------
  * Device-time accounting of ffsrqr_factor, for benchmarks.  When enabled,
  * ffsrqr_factor records HIP events around each step on the caller's stream

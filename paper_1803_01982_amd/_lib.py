@@ -56,6 +56,7 @@ SIGNATURES = {
     "ffsrqr_srqr_rho": (C.c_int, [_P, _I64, _I64, _P, _D, _P, _P, _SZ, _I32, _P]),
     "ffsrqr_lq": (C.c_int, [_P, _I64, _I64, _I64, _P, _P, _I64, _P, _I64, _P, _SZ, _I32, _P]),
     "ffsrqr_svd_small": (C.c_int, [_P, _I64, _I64, _P, _P, _SZ, _I32, _P]),
+    "ffsrqr_svd_small_noalloc": (C.c_int, [_P, _I64, _I64, _P, _I32, _P]),
     "ffsrqr_profile_enable": (None, [C.c_int]),
     "ffsrqr_profile_read": (C.c_int, [C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int]),
 }

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "../../include/ffsrqr.h"
+#include "common.hpp"
 #include "kernels.hpp"
 
 namespace ffsrqr {
@@ -198,6 +199,34 @@ ffsrqr_status get_side(int id, SideStream** out) {
     if (e != hipSuccess) return fail(FFSRQR_EHIP, std::string("side stream: ") + hipGetErrorString(e));
   }
   *out = &ss;
+  return FFSRQR_OK;
+}
+
+// ------------------------------------------------------------- no-alloc
+// Scratch of the entry points that allocate nothing: a file-scope device
+// array of fixed size (one copy per GPU, held until the process ends).  Host
+// code never passes the array's name to a kernel (on the host it only names
+// a stand-in); it looks the array's address up once per device with
+// hipGetSymbolAddress and passes that pointer.
+constexpr int64_t kNoAllocMaxL = 1024;
+constexpr size_t kNoAllocBytes =
+    sizeof(double) * ((size_t)kNoAllocMaxL * kNoAllocMaxL + kNoAllocMaxL) + (kSyncWords + 64) * sizeof(unsigned) +
+    64 * sizeof(unsigned) + 16 * 256;
+__device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64] = {};
+
+ffsrqr_status scratch_for(int id, void** out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[id]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || ptr == nullptr)
+      return fail(FFSRQR_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[id] = ptr;
+  }
+  *out = g_scratch_ptr[id];
   return FFSRQR_OK;
 }
 
@@ -806,6 +835,32 @@ ffsrqr_status ffsrqr_svd_small(const void* L, int64_t l, int64_t ldl, double* si
                      ? jacobi_sigma<double>((const double*)L, l, ldl, sigma, ar, err, *d, s)
                      : jacobi_sigma<float>((const float*)L, l, ldl, sigma, ar, err, *d, s);
   if (e == hipErrorOutOfMemory) return fail(FFSRQR_EWORKSPACE, "workspace too small");
+  FF_HIP(e);
+  return FFSRQR_OK;
+}
+
+ffsrqr_status ffsrqr_svd_small_noalloc(const void* L, int64_t l, int64_t ldl, double* sigma, int32_t precision,
+                                       ffsrqr_stream_t stream) {
+  if (l < 1 || ldl < l || !L || !sigma) return fail(FFSRQR_EINVAL, "bad svd_small_noalloc arguments");
+  if (l > kNoAllocMaxL)
+    return fail(FFSRQR_EINVAL, "svd_small_noalloc supports l <= " + std::to_string(kNoAllocMaxL));
+  if (!valid_precision(precision)) return fail(FFSRQR_EINVAL, "unknown precision");
+  const DeviceInfo* d = nullptr;
+  ffsrqr_status st = get_device(&d);
+  if (st != FFSRQR_OK) return st;
+  void* base = nullptr;
+  st = scratch_for(d->id, &base);
+  if (st != FFSRQR_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  // the same carving and kernels as ffsrqr_svd_small, over the static scratch
+  Arena ar{(char*)base, kNoAllocBytes, 0};
+  unsigned* err = ar.take<unsigned>(64);
+  if (!err) return fail(FFSRQR_EWORKSPACE, "static scratch too small");
+  FF_HIP(zero_words(err, 64, s));
+  hipError_t e = precision == FFSRQR_FP64
+                     ? jacobi_sigma<double>((const double*)L, l, ldl, sigma, ar, err, *d, s)
+                     : jacobi_sigma<float>((const float*)L, l, ldl, sigma, ar, err, *d, s);
+  if (e == hipErrorOutOfMemory) return fail(FFSRQR_EWORKSPACE, "static scratch too small");
   FF_HIP(e);
   return FFSRQR_OK;
 }

@@ -104,6 +104,15 @@ def test_workspace_size_mixed(lib):
     assert out.value >= fp32
 
 
+def test_svd_small_noalloc_host_checks(lib):
+    fake = C.c_void_p(0x1000)
+    assert lib.ffsrqr_svd_small_noalloc(fake, 1025, 1025, fake, 0, None) == 1
+    assert b"1024" in lib.ffsrqr_last_error()
+    assert lib.ffsrqr_svd_small_noalloc(fake, 4, 3, fake, 0, None) == 1
+    assert lib.ffsrqr_svd_small_noalloc(None, 4, 4, fake, 0, None) == 1
+    assert lib.ffsrqr_svd_small_noalloc(fake, 4, 4, fake, 9, None) == 1
+
+
 def test_workspace_size_rejects_bad_precision_and_null(lib):
     from paper_1803_01982_amd import _lib
     out = C.c_size_t(0)
