@@ -46,9 +46,8 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int MB_NT = 512;            // threads per workgroup (eight waves)
 constexpr int MB_BN = 64;             // columns per workgroup
-constexpr int MB_BK = 32;             // K per step (one MFMA)
-constexpr int MB_YS = 40;             // BF16 per LDS row of a Y column (32 + 8 padding)
 constexpr int MB_MAXT = 40;           // row tiles per group (640 rows)
+constexpr int MB_KMAX = 64;           // largest K step (two MFMA k-slices)
 
 __device__ inline f32x4 mfma_bf16(bf16x8 a, bf16x8 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
@@ -59,12 +58,25 @@ __device__ inline __bf16 to_bf16(float x) { return (__bf16)x; }
 
 // NP = 1: C = Xhi^T bf16(Y).  NP = 3: C = Xhi^T Yhi + Xhi^T Ylo + Xlo^T Yhi.
 // NTW = row tiles per wave (ceil(MT / 8)).  Xlo is unused for NP = 1.
+// KS = MFMA k-slices of 32 per K step: 2 (a 64-deep step, half the barriers
+// and twice the bytes in flight per prefetch) unless the three-product form
+// with three or more row tiles per wave needs the registers (KS = 1).  The products
+// are accumulated in the same order for either KS.
+template <int NP, int NTW>
+struct Bf16Step {
+  static constexpr int KS = (NP == 3 && NTW >= 3) ? 1 : 2;
+  static constexpr int BK = 32 * KS;
+  static constexpr int YS = BK + 8;  // BF16 per LDS row of a Y column (the padding spreads the banks)
+};
+
 template <int NP, int NTW>
 __global__ __launch_bounds__(MB_NT) void gemm_bf16_kernel(
     int64_t M, int64_t N, int64_t K, int64_t kchunk, const __bf16* __restrict__ Xhi, const __bf16* __restrict__ Xlo,
     int64_t ldx, const float* __restrict__ Y, int64_t ldy, float* __restrict__ C, int64_t ldc, int64_t cstride,
     double* __restrict__ colnorm, int64_t nstride, int groups, int rows_per_group) {
   constexpr int NB = NP == 1 ? 1 : 2;  // BF16 parts of Y held in LDS
+  constexpr int KS = Bf16Step<NP, NTW>::KS, MB_BK = Bf16Step<NP, NTW>::BK, MB_YS = Bf16Step<NP, NTW>::YS;
+  constexpr int YPT = MB_BK / 8;  // Y values per thread and step (four or eight consecutive k)
   __shared__ __attribute__((aligned(16))) __bf16 Ys[2][NB][MB_BN * MB_YS];
   __shared__ double nred[MB_NT];
 
@@ -99,52 +111,59 @@ __global__ __launch_bounds__(MB_NT) void gemm_bf16_kernel(
     xrow_hi[i] = Xhi + (r0 + row) * ldx;
     xrow_lo[i] = NP == 3 ? Xlo + (r0 + row) * ldx : nullptr;
   }
+  // fragment (tile i, k-slice ks) at index i * KS + ks
   auto load_x = [&](bf16x8* xh, bf16x8* xl, int64_t k0) {
-    const int64_t k = k0 + 8 * fg;
-    const bool full = k + 8 <= ke;
 #pragma unroll
-    for (int i = 0; i < NTW; ++i) {
-      if (full) {
-        xh[i] = *reinterpret_cast<const bf16x8*>(xrow_hi[i] + k);
-        if (NP == 3) xl[i] = *reinterpret_cast<const bf16x8*>(xrow_lo[i] + k);
-      } else {
+    for (int ks = 0; ks < KS; ++ks) {
+      const int64_t k = k0 + 32 * ks + 8 * fg;
+      const bool full = k + 8 <= ke;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          xh[i][e] = k + e < ke ? xrow_hi[i][k + e] : (__bf16)0.0f;
-          if (NP == 3) xl[i][e] = k + e < ke ? xrow_lo[i][k + e] : (__bf16)0.0f;
+      for (int i = 0; i < NTW; ++i) {
+        if (full) {
+          xh[i * KS + ks] = *reinterpret_cast<const bf16x8*>(xrow_hi[i] + k);
+          if (NP == 3) xl[i * KS + ks] = *reinterpret_cast<const bf16x8*>(xrow_lo[i] + k);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            xh[i * KS + ks][e] = k + e < ke ? xrow_hi[i][k + e] : (__bf16)0.0f;
+            if (NP == 3) xl[i * KS + ks][e] = k + e < ke ? xrow_lo[i][k + e] : (__bf16)0.0f;
+          }
         }
       }
     }
   };
 
-  // Y loader: thread tid moves four consecutive k (k0 + 4 (tid % 8)) of
-  // column n0 + tid / 8 (16 bytes); columns past N read column N - 1 and k
-  // past ke is zeroed.
-  const int yc = tid >> 3, yk = (tid & 7) * 4;
+  // Y loader: thread tid moves YPT consecutive k (k0 + YPT (tid % 8)) of
+  // column n0 + tid / 8 (16 or 32 bytes); columns past N read column N - 1
+  // and k past ke is zeroed.
+  const int yc = tid >> 3, yk = (tid & 7) * YPT;
   const int64_t ycol = n0 + yc < N ? n0 + yc : N - 1;
   const float* ysrc = Y + ycol * ldy;
   const bool ycol_ok = n0 + yc < N;
   // 16-byte loads need 16-byte aligned columns (ldy % 4 == 0, aligned base)
   const bool yvec = (ldy & 3) == 0 && (reinterpret_cast<uintptr_t>(Y) & 15) == 0;
-  float yv[4];
+  float yv[YPT];
   auto load_y = [&](int64_t k0) {
     const int64_t k = k0 + yk;
-    if (yvec && k + 4 <= ke) {
-      const float4 v = *reinterpret_cast<const float4*>(ysrc + k);
-      yv[0] = v.x;
-      yv[1] = v.y;
-      yv[2] = v.z;
-      yv[3] = v.w;
+    if (yvec && k + YPT <= ke) {
+#pragma unroll
+      for (int h = 0; h < YPT / 4; ++h) {
+        const float4 v = *reinterpret_cast<const float4*>(ysrc + k + 4 * h);
+        yv[4 * h] = v.x;
+        yv[4 * h + 1] = v.y;
+        yv[4 * h + 2] = v.z;
+        yv[4 * h + 3] = v.w;
+      }
     } else {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) yv[e] = k + e < ke ? ysrc[k + e] : 0.0f;
+      for (int e = 0; e < YPT; ++e) yv[e] = k + e < ke ? ysrc[k + e] : 0.0f;
     }
   };
   double nrm = 0.0;
   auto store_y = [&](int buf) {
-    __bf16 hi[4], lo[4];
+    __bf16 hi[YPT], lo[YPT];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int e = 0; e < YPT; ++e) {
       const float y = ycol_ok ? yv[e] : 0.0f;
       hi[e] = to_bf16(y);
       if (NP == 3) lo[e] = to_bf16(y - (float)hi[e]);
@@ -152,11 +171,11 @@ __global__ __launch_bounds__(MB_NT) void gemm_bf16_kernel(
     }
     __bf16* dst = &Ys[buf][0][yc * MB_YS + yk];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) dst[e] = hi[e];
+    for (int e = 0; e < YPT; ++e) dst[e] = hi[e];
     if (NP == 3) {
       __bf16* dl = &Ys[buf][NB - 1][yc * MB_YS + yk];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) dl[e] = lo[e];
+      for (int e = 0; e < YPT; ++e) dl[e] = lo[e];
     }
   };
 
@@ -172,8 +191,8 @@ __global__ __launch_bounds__(MB_NT) void gemm_bf16_kernel(
   // they are loaded into the same registers right after the MFMAs that read
   // them, and the other wave of the SIMD covers the latency.
   constexpr bool PRE = NP == 1 || NTW <= 4;  // always true with the groups chosen below
-  constexpr int NX = PRE ? NTW : 1;
-  bf16x8 xh[NTW], xl[NTW], nh[NX], nl[NX];
+  constexpr int NX = PRE ? NTW * KS : 1;
+  bf16x8 xh[NTW * KS], xl[NTW * KS], nh[NX], nl[NX];
   const int64_t nsteps = (ke - kb + MB_BK - 1) / MB_BK;
   if (nsteps > 0) {
     load_y(kb);
@@ -188,16 +207,20 @@ __global__ __launch_bounds__(MB_NT) void gemm_bf16_kernel(
     __syncthreads();  // Ys[buf] complete; every read of Ys[buf ^ 1] done
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&Ys[buf][0][(16 * c + fr) * MB_YS + 8 * fg]);
-      bf16x8 bl;
-      if (NP == 3) bl = *reinterpret_cast<const bf16x8*>(&Ys[buf][NB - 1][(16 * c + fr) * MB_YS + 8 * fg]);
 #pragma unroll
-      for (int i = 0; i < NTW; ++i) {
-        if (wave + 8 * i < MT) {
-          acc[i][c] = mfma_bf16(xh[i], bh, acc[i][c]);
-          if (NP == 3) {
-            acc[i][c] = mfma_bf16(xh[i], bl, acc[i][c]);
-            acc[i][c] = mfma_bf16(xl[i], bh, acc[i][c]);
+      for (int ks = 0; ks < KS; ++ks) {
+        const int yo = (16 * c + fr) * MB_YS + 32 * ks + 8 * fg;
+        const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&Ys[buf][0][yo]);
+        bf16x8 bl;
+        if (NP == 3) bl = *reinterpret_cast<const bf16x8*>(&Ys[buf][NB - 1][yo]);
+#pragma unroll
+        for (int i = 0; i < NTW; ++i) {
+          if (wave + 8 * i < MT) {
+            acc[i][c] = mfma_bf16(xh[i * KS + ks], bh, acc[i][c]);
+            if (NP == 3) {
+              acc[i][c] = mfma_bf16(xh[i * KS + ks], bl, acc[i][c]);
+              acc[i][c] = mfma_bf16(xl[i * KS + ks], bh, acc[i][c]);
+            }
           }
         }
       }
@@ -332,7 +355,7 @@ hipError_t gemm_bf16(int nprod, int64_t M, int64_t N, int64_t K, const __bf16* X
   bf16_shape(nprod, M, &groups, &rpg, &ntw);
   const int splits = bf16_splits(nprod, M, N, K, num_cu);
   int64_t kchunk = (K + splits - 1) / splits;
-  kchunk = (kchunk + MB_BK - 1) / MB_BK * MB_BK;
+  kchunk = (kchunk + MB_KMAX - 1) / MB_KMAX * MB_KMAX;  // a whole number of K steps for either step depth
   const int64_t ntile = (N + MB_BN - 1) / MB_BN;
   const int64_t gx = groups > 1 ? (ntile + 7) / 8 * 8 * groups : ntile;
   dim3 grid((unsigned)gx, 1u, (unsigned)splits);

@@ -254,22 +254,29 @@ struct QrcpPost {
 // Rows of the column slots of the steps before j: sum over j' < j of (l - j').
 __device__ inline int64_t tri_rows(int j, int l) { return (int64_t)j * l - (int64_t)j * (j - 1) / 2; }
 
-template <typename T, int NR, int CB>
+// NL > 0 (with CB = 1): the rows q + 16 s with s < NL, the ones that retire
+// first, live in LDS (xs[s][tid], 8 NL KiB per workgroup) and only the other
+// NR - NL rows in registers, which keeps the l <= 544 variant within 128
+// VGPRs; at step j the LDS rows below 16 (j / 16) are dead and skipped.
+template <typename T, int NR, int CB, int NL>
 __global__ __launch_bounds__(NT) void qrcp_reg_kernel(const T* __restrict__ B, int64_t ldb, int l, int64_t n,
                                                       QrcpPost post, int64_t* __restrict__ piv,
                                                       double* __restrict__ margins, unsigned* __restrict__ error) {
   constexpr int TPC = 16, CPB = NT / TPC;  // threads per column, columns per batch
   constexpr int GQ = kMaxGridBlocks / kWave;  // candidate slots per lane
+  constexpr int NRR = NR - NL;                // rows per thread held in registers
+  static_assert(NL == 0 || CB == 1, "LDS rows with one column per thread group");
   __shared__ double v[TPC * NR];
   __shared__ double s_tv1[NT / 64], s_tv2[NT / 64];
   __shared__ int64_t s_ti1[NT / 64];
   __shared__ double s_tau;
   __shared__ int64_t s_win;
   __shared__ int s_abort;
+  extern __shared__ double xs[];  // [NL][NT]
   const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6, q = tid & (TPC - 1), cl = tid / TPC;
   const int64_t c0 = (int64_t)g * CPB * CB;
-  double x[CB][NR], rn[CB];
+  double x[CB][NRR], rn[CB];
   int64_t col[CB];
   bool act[CB];
 #pragma unroll
@@ -277,9 +284,15 @@ __global__ __launch_bounds__(NT) void qrcp_reg_kernel(const T* __restrict__ B, i
     col[b] = c0 + (int64_t)b * CPB + cl;
     act[b] = col[b] < n;
     double s2 = 0.0;
-#pragma unroll
-    for (int s = 0; s < NR; ++s) {
+    for (int s = 0; s < NL; ++s) {
       const int i = q + TPC * s;
+      const double y = (act[b] && i < l) ? (double)B[col[b] * ldb + i] : 0.0;
+      xs[s * NT + tid] = y;
+      s2 += y * y;
+    }
+#pragma unroll
+    for (int s = 0; s < NRR; ++s) {
+      const int i = q + TPC * (s + NL);
       x[b][s] = (act[b] && i < l) ? (double)B[col[b] * ldb + i] : 0.0;
       s2 += x[b][s] * x[b][s];
     }
@@ -314,12 +327,17 @@ __global__ __launch_bounds__(NT) void qrcp_reg_kernel(const T* __restrict__ B, i
       uint64_t* dst = post.col + tb + (int64_t)g * (l - j) - j;
 #pragma unroll
       for (int b = 0; b < CB; ++b)
-        if (bi >= 0 && col[b] == bi)
-#pragma unroll
-          for (int s = 0; s < NR; ++s) {
+        if (bi >= 0 && col[b] == bi) {
+          for (int s = j / TPC; s < NL; ++s) {
             const int i = q + TPC * s;
+            if (i >= j && i < l) post_u64(dst + i, slot_bits(xs[s * NT + tid]));
+          }
+#pragma unroll
+          for (int s = 0; s < NRR; ++s) {
+            const int i = q + TPC * (s + NL);
             if (i >= j && i < l) post_u64(dst + i, slot_bits(x[b][s]));
           }
+        }
       if (wave == 0 && lane == 0) {
         post_u64(post.cand + (int64_t)j * G + g, slot_bits(u.v1));
         post_u64(post.cand + ((int64_t)l + j) * G + g, slot_bits(u.v2));
@@ -373,8 +391,9 @@ __global__ __launch_bounds__(NT) void qrcp_reg_kernel(const T* __restrict__ B, i
       // the winner's rows j..l-1 (posted by the workgroup that owns it)
       const int wg = ok && wi >= 0 ? (int)(wi / (CPB * CB)) : 0;
       const uint64_t* src = post.col + tb + (int64_t)wg * (l - j) - j;
+      // the winner's rows go straight into the reflector buffer v (this
+      // wave's own entries i = lane + 64 s), so no register copy is held
       constexpr int WS = (TPC * NR + 63) / 64;
-      double w[WS];
       for (spins = 0; ok;) {
         bool here = true;
 #pragma unroll
@@ -385,7 +404,7 @@ __global__ __launch_bounds__(NT) void qrcp_reg_kernel(const T* __restrict__ B, i
             bits = peek_u64(src + i);
             here = here && bits != kVoid;
           }
-          w[s] = slot_double(bits);
+          if (i < TPC * NR) v[i] = slot_double(bits);
         }
         if (__all(here)) break;
         __builtin_amdgcn_s_sleep(1);
@@ -404,15 +423,10 @@ __global__ __launch_bounds__(NT) void qrcp_reg_kernel(const T* __restrict__ B, i
 #pragma unroll
         for (int s = 0; s < WS; ++s) {
           const int i = lane + 64 * s;
-          if (i > j && i < l) xs += w[s] * w[s];
+          if (i > j && i < l) xs += v[i] * v[i];
         }
         const double xnorm2 = wave_sum(xs);
-        double x0v = __shfl(w[0], j & 63, kWave);  // row j is in register j / 64 of lane j % 64
-#pragma unroll
-        for (int s = 1; s < WS; ++s) {
-          const double y = __shfl(w[s], j & 63, kWave);
-          if ((j >> 6) == s) x0v = y;
-        }
+        const double x0v = v[j];  // written by lane j % 64 above (same wave, in order)
         double tau = 0.0, scale = 0.0;
         if (xnorm2 > 0.0) {
           const double beta = -copysign(sqrt(x0v * x0v + xnorm2), x0v);
@@ -422,7 +436,7 @@ __global__ __launch_bounds__(NT) void qrcp_reg_kernel(const T* __restrict__ B, i
 #pragma unroll
         for (int s = 0; s < WS; ++s) {
           const int i = lane + 64 * s;
-          if (i < TPC * NR) v[i] = (i < j || i >= l) ? 0.0 : (i == j ? 1.0 : (tau != 0.0 ? w[s] * scale : w[s]));
+          if (i < TPC * NR) v[i] = (i < j || i >= l) ? 0.0 : (i == j ? 1.0 : (tau != 0.0 ? v[i] * scale : v[i]));
         }
         if (lane == 0) {
           s_tau = tau;
@@ -439,18 +453,29 @@ __global__ __launch_bounds__(NT) void qrcp_reg_kernel(const T* __restrict__ B, i
     for (int b = 0; b < CB; ++b) {
       if (col[b] == wi) act[b] = false;
       if (!act[b]) continue;
+      const int s0 = j / TPC;  // LDS rows below 16 s0 are dead (v is zero there)
       if (tau != 0.0) {
         double dt = 0.0;
+        for (int s = s0; s < NL; ++s) dt += v[q + TPC * s] * xs[s * NT + tid];
 #pragma unroll
-        for (int s = 0; s < NR; ++s) dt += v[q + TPC * s] * x[b][s];
+        for (int s = 0; s < NRR; ++s) dt += v[q + TPC * (s + NL)] * x[b][s];
         const double f = row16_sum(dt) * tau;
+        // compiler barrier: the update reads the reflector from LDS again
+        // rather than keeping all of it live in registers beside the column
+        asm volatile("" ::: "memory");
+        for (int s = s0; s < NL; ++s) xs[s * NT + tid] -= f * v[q + TPC * s];
 #pragma unroll
-        for (int s = 0; s < NR; ++s) x[b][s] -= f * v[q + TPC * s];
+        for (int s = 0; s < NRR; ++s) x[b][s] -= f * v[q + TPC * (s + NL)];
       }
       double r = 0.0;
-#pragma unroll
-      for (int s = 0; s < NR; ++s) {
+      for (int s = s0; s < NL; ++s) {
         const int i = q + TPC * s;
+        const double y = xs[s * NT + tid];
+        if (i > j) r += y * y;
+      }
+#pragma unroll
+      for (int s = 0; s < NRR; ++s) {
+        const int i = q + TPC * (s + NL);
         if (i > j) r += x[b][s] * x[b][s];
       }
       rn[b] = row16_sum(r);
@@ -503,14 +528,17 @@ bool reg_choice(int64_t l, int64_t n, int num_cu, int* NR, int* CB, int* G) {
   return false;
 }
 
+// rows per thread kept in LDS by the variant for NR rows per thread
+inline int reg_lds_rows(int NR) { return NR == 34 ? 16 : 0; }
+
 template <typename T>
 const void* reg_kernel(int NR) {
   switch (NR) {
-    case 2: return (const void*)qrcp_reg_kernel<T, 2, 4>;
-    case 4: return (const void*)qrcp_reg_kernel<T, 4, 4>;
-    case 8: return (const void*)qrcp_reg_kernel<T, 8, 2>;
-    case 18: return (const void*)qrcp_reg_kernel<T, 18, 1>;
-    case 34: return (const void*)qrcp_reg_kernel<T, 34, 1>;
+    case 2: return (const void*)qrcp_reg_kernel<T, 2, 4, 0>;
+    case 4: return (const void*)qrcp_reg_kernel<T, 4, 4, 0>;
+    case 8: return (const void*)qrcp_reg_kernel<T, 8, 2, 0>;
+    case 18: return (const void*)qrcp_reg_kernel<T, 18, 1, 0>;
+    case 34: return (const void*)qrcp_reg_kernel<T, 34, 1, 16>;
   }
   return nullptr;
 }
@@ -547,7 +575,13 @@ hipError_t qrcp(const T* B, int64_t l, int64_t n, int64_t ldb, int64_t* piv, dou
     int64_t ln = n, lldb = ldb;
     void* args[] = {(void*)&B, (void*)&lldb, (void*)&li, (void*)&ln, (void*)&post, (void*)&piv, (void*)&margins,
                     (void*)&err};
-    return hipLaunchCooperativeKernel(reg_kernel<T>(NR), dim3(Gr), dim3(NT), args, 0, s);
+    const void* fn = reg_kernel<T>(NR);
+    const size_t xlds = (size_t)reg_lds_rows(NR) * NT * sizeof(double);
+    if (xlds > 65536) {
+      e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)xlds);
+      if (e != hipSuccess) return e;
+    }
+    return hipLaunchCooperativeKernel(fn, dim3(Gr), dim3(NT), args, (unsigned)xlds, s);
   }
   int nc, G;
   bool in_lds;
