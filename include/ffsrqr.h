@@ -118,6 +118,11 @@ typedef struct {
 /* Default options: FP64, g = 2, max_swaps = 4 l. */
 void ffsrqr_default_opts(ffsrqr_opts* opts);
 
+/* Destroy the second stream and the events that this host thread's calls
+ * created (they are created again by the next call).  For an orderly
+ * shutdown: call it before the HIP runtime is unloaded, e.g. at exit. */
+void ffsrqr_release(void);
+
 /* Text of a status code (static storage). */
 const char* ffsrqr_status_string(ffsrqr_status s);
 
@@ -262,6 +267,30 @@ ffsrqr_status ffsrqr_lq(const void* R, int64_t l, int64_t n, int64_t ldr, const 
 ffsrqr_status ffsrqr_svd_small(const void* L, int64_t l, int64_t ldl, double* sigma,
                                void* work, size_t work_bytes, int32_t precision,
                                ffsrqr_stream_t stream);
+
+/*
+ * Algorithm 9, last steps: the rank-k approximate SVD from the flip-flop
+ * factors (Section 3.1).  With V = Pi Qhat1 (n x l) from ffsrqr_factor:
+ *   tmp = A V (m x l, a third pass over A),
+ *   tmp = U_tmp Sigma V_tmp^T, its thin SVD (Householder QR of tmp, then
+ *         one-sided Jacobi with the rotations accumulated on its l x l
+ *         triangular factor),
+ *   U = U_tmp(:, 1:k) (m x k, ldu >= m), V_k = V V_tmp(:, 1:k) (n x k,
+ *   ldvk >= n), sigma[0:l] = Sigma (descending; sigma[0:k] is Sigma_k),
+ * so that A ~ U diag(sigma[0:k]) V_k^T.  Each pair (U(:, j), V_k(:, j)) is
+ * signed so that the entry of U(:, j) of largest magnitude (the first on
+ * ties) is positive.  A, V, U and V_k have the element type of precision
+ * (FFSRQR_MIXED: float, FP32 GEMMs); everything else as ffsrqr_factor.
+ * 1 <= k <= l <= min(m, n), the size limits of ffsrqr_workspace_size; the
+ * workspace comes from ffsrqr_alg9_workspace_size.  The call returns after
+ * the stream has completed.
+ */
+ffsrqr_status ffsrqr_alg9_workspace_size(int64_t m, int64_t n, int64_t l, int64_t k, int32_t precision,
+                                         size_t* bytes);
+ffsrqr_status ffsrqr_alg9_svd(const void* A, int64_t m, int64_t n, int64_t lda, const void* V, int64_t ldv,
+                              int64_t l, int64_t k, void* U, int64_t ldu, double* sigma, void* Vk,
+                              int64_t ldvk, void* work, size_t work_bytes, int32_t precision,
+                              ffsrqr_stream_t stream);
 
 /*
  * ffsrqr_svd_small without a workspace, for callers that cannot allocate

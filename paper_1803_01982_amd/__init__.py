@@ -5,12 +5,13 @@ library with ``python -m paper_1803_01982_amd.build``; importing works without
 it, and the first call raises ``LibraryMissing`` if it is absent.
 """
 from ._lib import (FLAG_L_CLAMPED, FLAG_NONFINITE, FLAG_RANK_DEFICIENT, FLAG_SWAPCAP, FLAG_TIMEOUT, FP32, FP64,
-                   FfsrqrError, LibraryMissing, load)
-from .api import (Factorization, empty_fortran, factor, fortran, lq, omega, panel_qr, profile_enable, profile_read,
-                  project, qrcp, sketch, srqr_rho, svd_small, workspace, workspace_size)
+                   MIXED, FfsrqrError, LibraryMissing, load)
+from .api import (Alg9Result, Factorization, alg9_svd, empty_fortran, factor, fortran, lq, omega, panel_qr,
+                  profile_enable, profile_read, project, qrcp, sketch, srqr_rho, svd_small, workspace,
+                  workspace_size)
 
 __all__ = [
     "FLAG_L_CLAMPED", "FLAG_NONFINITE", "FLAG_RANK_DEFICIENT", "FLAG_SWAPCAP", "FLAG_TIMEOUT", "FP32", "FP64",
-    "FfsrqrError", "LibraryMissing", "load", "Factorization", "empty_fortran", "factor", "fortran", "lq", "omega",
+    "MIXED", "FfsrqrError", "LibraryMissing", "load", "Alg9Result", "alg9_svd", "Factorization", "empty_fortran", "factor", "fortran", "lq", "omega",
     "panel_qr", "profile_enable", "profile_read", "project", "qrcp", "sketch", "srqr_rho", "svd_small", "workspace", "workspace_size",
 ]

@@ -43,6 +43,7 @@ _D = C.c_double
 
 SIGNATURES = {
     "ffsrqr_default_opts": (None, [C.POINTER(Opts)]),
+    "ffsrqr_release": (None, []),
     "ffsrqr_status_string": (C.c_char_p, [C.c_int]),
     "ffsrqr_last_error": (C.c_char_p, []),
     "ffsrqr_workspace_size": (C.c_int, [_I64, _I64, _I64, _I64, C.POINTER(Opts), C.POINTER(_SZ)]),
@@ -57,6 +58,9 @@ SIGNATURES = {
     "ffsrqr_lq": (C.c_int, [_P, _I64, _I64, _I64, _P, _P, _I64, _P, _I64, _P, _SZ, _I32, _P]),
     "ffsrqr_svd_small": (C.c_int, [_P, _I64, _I64, _P, _P, _SZ, _I32, _P]),
     "ffsrqr_svd_small_noalloc": (C.c_int, [_P, _I64, _I64, _P, _I32, _P]),
+    "ffsrqr_alg9_workspace_size": (C.c_int, [_I64, _I64, _I64, _I64, _I32, C.POINTER(_SZ)]),
+    "ffsrqr_alg9_svd": (C.c_int, [_P, _I64, _I64, _I64, _P, _I64, _I64, _I64, _P, _I64, _P, _P, _I64, _P, _SZ,
+                                  _I32, _P]),
     "ffsrqr_profile_enable": (None, [C.c_int]),
     "ffsrqr_profile_read": (C.c_int, [C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int]),
 }

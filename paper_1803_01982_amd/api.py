@@ -7,8 +7,10 @@ provides the current stream.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import dataclasses
+import threading
 
 import torch
 
@@ -66,15 +68,34 @@ def workspace_size(m: int, n: int, k: int, p: int, precision=L.FP64) -> int:
     return out.value
 
 
-def workspace(nbytes: int, device) -> torch.Tensor:
-    """A cached device workspace of at least nbytes (grown on demand)."""
+def workspace(nbytes: int, device, stream=None) -> torch.Tensor:
+    """A cached device workspace of at least nbytes (grown on demand), one per
+    (device, stream, host thread): calls on one workspace must not overlap, so
+    work on different streams or from different threads never shares one.
+    A buffer that is replaced is first recorded on its stream, so the caching
+    allocator does not hand its memory out while work queued there may still
+    use it."""
     dev = torch.device(device)
-    key = (dev.type, dev.index)
+    s = stream if stream is not None else torch.cuda.current_stream(dev)
+    key = (dev.type, dev.index, s.cuda_stream, threading.get_ident())
     w = _WORK.get(key)
     if w is None or w.numel() < nbytes:
+        if w is not None:
+            w.record_stream(s)
         w = torch.empty(nbytes, dtype=torch.uint8, device=dev)
         _WORK[key] = w
     return w
+
+
+def release() -> None:
+    """Drop the cached workspaces and the library's per-thread streams and
+    events (registered to run at exit, while the HIP runtime is alive)."""
+    _WORK.clear()
+    if L._lib is not None:
+        L._lib.ffsrqr_release()
+
+
+atexit.register(release)
 
 
 @dataclasses.dataclass
@@ -103,7 +124,7 @@ def factor(A: torch.Tensor, k: int, p: int, seed: int = 0, g: float = 2.0, max_s
     V = empty_fortran(n, l, A.dtype, dev)
     sigma = torch.empty(l, dtype=torch.float64, device=dev)
     if work is None:
-        work = workspace(workspace_size(m, n, k, p, prec), dev)
+        work = workspace(workspace_size(m, n, k, p, prec), dev, stream)
     info = L.Info()
     o = opts(prec, g, max_swaps)
     L.check(lib.ffsrqr_factor(_ptr(A), m, n, lda, k, p, seed, _ptr(perm), _ptr(Q), m, _ptr(Lf), l,
@@ -128,7 +149,7 @@ def sketch(A: torch.Tensor, seed: int, l: int, work=None, stream=None, mixed: bo
     B = empty_fortran(l, n, A.dtype, A.device)
     an = torch.empty(n, dtype=torch.float64, device=A.device)
     if work is None:
-        work = workspace(workspace_size(m, n, l, 0, prec), A.device)
+        work = workspace(workspace_size(m, n, l, 0, prec), A.device, stream)
     L.check(lib.ffsrqr_sketch(_ptr(A), m, n, _ld(A), seed, l, _ptr(B), l, _ptr(an), _ptr(work), work.numel(),
                               prec, _stream(stream)), "ffsrqr_sketch")
     return B, an
@@ -142,7 +163,7 @@ def qrcp(B: torch.Tensor, l: int | None = None, work=None, stream=None):
     piv = torch.empty(l, dtype=torch.int64, device=B.device)
     mg = torch.empty(l, dtype=torch.float64, device=B.device)
     if work is None:
-        work = workspace(workspace_size(max(rows, l), n, l, 0, _prec(B.dtype)), B.device)
+        work = workspace(workspace_size(max(rows, l), n, l, 0, _prec(B.dtype)), B.device, stream)
     L.check(lib.ffsrqr_qrcp(_ptr(B), l, n, _ld(B), _ptr(piv), _ptr(mg), _ptr(work), work.numel(),
                             _prec(B.dtype), _stream(stream)), "ffsrqr_qrcp")
     return piv, mg
@@ -156,7 +177,7 @@ def panel_qr(A: torch.Tensor, cols: torch.Tensor, work=None, stream=None):
     Q = empty_fortran(m, c, A.dtype, A.device)
     R = empty_fortran(c, c, A.dtype, A.device)
     if work is None:
-        work = workspace(workspace_size(m, n, min(c, m, n), 0, _prec(A.dtype)) + m * c * 8, A.device)
+        work = workspace(workspace_size(m, n, min(c, m, n), 0, _prec(A.dtype)) + m * c * 8, A.device, stream)
     L.check(lib.ffsrqr_panel_qr(_ptr(A), m, n, _ld(A), _ptr(cols), c, _ptr(Q), m, _ptr(R), c, _ptr(work),
                                 work.numel(), _prec(A.dtype), _stream(stream)), "ffsrqr_panel_qr")
     return Q, R
@@ -171,7 +192,7 @@ def project(Q: torch.Tensor, A: torch.Tensor, anorm2: torch.Tensor, work=None, s
     W = empty_fortran(c, n, A.dtype, A.device)
     g2 = torch.empty(n, dtype=torch.float64, device=A.device)
     if work is None:
-        work = workspace(workspace_size(m, n, min(c, m, n), 0, prec), A.device)
+        work = workspace(workspace_size(m, n, min(c, m, n), 0, prec), A.device, stream)
     L.check(lib.ffsrqr_project(_ptr(Q), m, c, _ld(Q), _ptr(A), n, _ld(A), _ptr(W), c, _ptr(anorm2), _ptr(g2),
                                _ptr(work), work.numel(), prec, _stream(stream)), "ffsrqr_project")
     return W, g2
@@ -183,7 +204,7 @@ def srqr_rho(R11: torch.Tensor, a: torch.Tensor, alpha: float, work=None, stream
     l = R11.shape[0]
     rho = torch.empty(l, dtype=torch.float64, device=R11.device)
     if work is None:
-        work = workspace(8 * (l + 1) * l + (1 << 16), R11.device)
+        work = workspace(8 * (l + 1) * l + (1 << 16), R11.device, stream)
     L.check(lib.ffsrqr_srqr_rho(_ptr(R11), l, _ld(R11), _ptr(a), float(alpha), _ptr(rho), _ptr(work),
                                 work.numel(), _prec(R11.dtype), _stream(stream)), "ffsrqr_srqr_rho")
     return rho
@@ -196,7 +217,7 @@ def lq(R: torch.Tensor, perm: torch.Tensor, work=None, stream=None):
     Lf = empty_fortran(l, l, R.dtype, R.device)
     V = empty_fortran(n, l, R.dtype, R.device)
     if work is None:
-        work = workspace(workspace_size(n, n, l, 0, _prec(R.dtype)) + n * l * 8, R.device)
+        work = workspace(workspace_size(n, n, l, 0, _prec(R.dtype)) + n * l * 8, R.device, stream)
     L.check(lib.ffsrqr_lq(_ptr(R), l, n, _ld(R), _ptr(perm), _ptr(Lf), l, _ptr(V), n, _ptr(work), work.numel(),
                           _prec(R.dtype), _stream(stream)), "ffsrqr_lq")
     return Lf, V
@@ -208,10 +229,35 @@ def svd_small(Lm: torch.Tensor, work=None, stream=None) -> torch.Tensor:
     l = Lm.shape[0]
     sig = torch.empty(l, dtype=torch.float64, device=Lm.device)
     if work is None:
-        work = workspace(8 * (l * l + l) + (1 << 16), Lm.device)
+        work = workspace(workspace_size(l, l, l, 0, _prec(Lm.dtype)), Lm.device, stream)
     L.check(lib.ffsrqr_svd_small(_ptr(Lm), l, _ld(Lm), _ptr(sig), _ptr(work), work.numel(), _prec(Lm.dtype),
                                  _stream(stream)), "ffsrqr_svd_small")
     return sig
+
+
+@dataclasses.dataclass
+class Alg9Result:
+    U: torch.Tensor       # m x k
+    sigma: torch.Tensor   # [l] descending (the first k are Sigma_k)
+    Vk: torch.Tensor      # n x k
+
+
+def alg9_svd(A: torch.Tensor, V: torch.Tensor, k: int, work=None, stream=None, mixed: bool = False) -> Alg9Result:
+    """ffsrqr_alg9_svd: rank-k SVD A ~ U diag(sigma[:k]) Vk^T from V = Pi Qhat1."""
+    lib = L.load()
+    m, n = A.shape
+    l = V.shape[1]
+    prec = _prec(A.dtype, mixed)
+    U = empty_fortran(m, k, A.dtype, A.device)
+    Vk = empty_fortran(n, k, A.dtype, A.device)
+    sigma = torch.empty(l, dtype=torch.float64, device=A.device)
+    if work is None:
+        out = C.c_size_t(0)
+        L.check(lib.ffsrqr_alg9_workspace_size(m, n, l, k, prec, C.byref(out)), "ffsrqr_alg9_workspace_size")
+        work = workspace(out.value, A.device, stream)
+    L.check(lib.ffsrqr_alg9_svd(_ptr(A), m, n, _ld(A), _ptr(V), _ld(V), l, k, _ptr(U), m, _ptr(sigma), _ptr(Vk), n,
+                                _ptr(work), work.numel(), prec, _stream(stream)), "ffsrqr_alg9_svd")
+    return Alg9Result(U, sigma, Vk)
 
 
 def profile_enable(on: bool = True) -> None:

@@ -210,8 +210,8 @@ ffsrqr_status get_side(int id, SideStream** out) {
 // hipGetSymbolAddress and passes that pointer.
 constexpr int64_t kNoAllocMaxL = 1024;
 constexpr size_t kNoAllocBytes =
-    sizeof(double) * ((size_t)kNoAllocMaxL * kNoAllocMaxL + kNoAllocMaxL) + (kSyncWords + 64) * sizeof(unsigned) +
-    64 * sizeof(unsigned) + 16 * 256;
+    sizeof(double) * ((size_t)kNoAllocMaxL * kNoAllocMaxL + kNoAllocMaxL + (size_t)kMaxGridBlocks * 32 * 32) +
+    (kSyncWords + 64) * sizeof(unsigned) + 64 * sizeof(unsigned) + 16 * 256;
 __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
 
 std::mutex g_scratch_mu;
@@ -566,6 +566,99 @@ ffsrqr_status sketch_impl(const T* A, int64_t m, int64_t n, int64_t lda, uint64_
   FF_HIP(e);
   return FFSRQR_OK;
 }
+// Algorithm 9, last steps: workspace carving shared by the sizing and the call.
+template <typename T>
+struct Alg9Layout {
+  T *tt, *P, *Qt, *Rt, *UR, *VR;
+  double* sg;
+  unsigned* err;
+  size_t scratch_off;
+};
+
+template <typename T>
+size_t alg9_scratch(int64_t m, int64_t n, int64_t l, int64_t k, const DeviceInfo& d) {
+  size_t s = 0;
+  s = std::max(s, gemm_tn_scratch<T>(l, m, n, d.num_cu));
+  s = std::max(s, gemm_tn_scratch<T>(k, m, l, d.num_cu));
+  s = std::max(s, gemm_tn_scratch<T>(k, n, l, d.num_cu));
+  s = std::max(s, tallqr_scratch<T>(m, l, d));
+  s = std::max(s, jacobi_scratch<T>(l, d));
+  return s + 16 * 256;
+}
+
+template <typename T>
+bool alg9_carve(Arena& ar, int64_t m, int64_t n, int64_t l, int64_t k, Alg9Layout<T>* o) {
+  o->tt = ar.take<T>(std::max((size_t)l * m, (size_t)k * n));  // tmp^T, then U^T, then V_k^T
+  o->P = ar.take<T>((size_t)m * l);                             // tmp, factored in place
+  o->Qt = ar.take<T>((size_t)m * l);
+  o->Rt = ar.take<T>((size_t)l * l);
+  o->UR = ar.take<T>((size_t)l * l);
+  o->VR = ar.take<T>((size_t)l * l);
+  o->sg = ar.take<double>((size_t)k);
+  o->err = ar.take<unsigned>(64);
+  o->scratch_off = ar.used;
+  return o->err != nullptr;
+}
+
+template <typename T>
+size_t alg9_bytes(int64_t m, int64_t n, int64_t l, int64_t k, const DeviceInfo& d) {
+  Arena ar{nullptr, 0, 0};
+  Alg9Layout<T> o;
+  alg9_carve<T>(ar, m, n, l, k, &o);
+  return ar.used + 256 + alg9_scratch<T>(m, n, l, k, d);
+}
+
+template <typename T>
+ffsrqr_status alg9_impl(const T* A, int64_t m, int64_t n, int64_t lda, const T* V, int64_t ldv, int64_t l, int64_t k,
+                        T* U, int64_t ldu, double* sigma, T* Vk, int64_t ldvk, void* work, size_t work_bytes,
+                        const DeviceInfo& d, hipStream_t s) {
+  const size_t need = alg9_bytes<T>(m, n, l, k, d);
+  if (work_bytes < need) return fail(FFSRQR_EWORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+  Arena ar{(char*)work, work_bytes, 0};
+  Alg9Layout<T> o;
+  if (!alg9_carve<T>(ar, m, n, l, k, &o)) return fail(FFSRQR_EWORKSPACE, "workspace carving failed");
+  auto scratch = [&]() { return Arena{(char*)work, work_bytes, o.scratch_off}; };
+  FF_HIP(zero_words(o.err, 64, s));
+  {
+    // tmp^T = V^T A^T (l x m): the third pass over A (A read by columns)
+    Arena a = scratch();
+    FF_HIP(gemm_tn<T>(l, m, n, V, ldv, A, lda, o.tt, l, nullptr, a, d.num_cu, s, true));
+  }
+  FF_HIP(transpose<T>(o.tt, l, m, l, o.P, m, s));
+  {
+    // thin SVD of tmp: Householder QR, then Jacobi with vectors on R
+    Arena a = scratch();
+    FF_HIP(tall_qr<T>(o.P, m, l, m, o.Qt, m, o.Rt, l, false, a, o.err, d, s));
+  }
+  {
+    Arena a = scratch();
+    FF_HIP(jacobi_svd_vectors<T>(o.Rt, l, l, sigma, o.UR, l, o.VR, l, a, o.err, d, s));
+  }
+  {
+    // U = Qt UR(:, 1:k) and V_k = V VR(:, 1:k), both through their transposes
+    Arena a = scratch();
+    FF_HIP(gemm_tn<T>(k, m, l, o.UR, l, o.Qt, m, o.tt, k, nullptr, a, d.num_cu, s, true));
+    FF_HIP(transpose<T>(o.tt, k, m, k, U, ldu, s));
+    Arena b = scratch();
+    FF_HIP(gemm_tn<T>(k, n, l, o.VR, l, V, ldv, o.tt, k, nullptr, b, d.num_cu, s, true));
+    FF_HIP(transpose<T>(o.tt, k, n, k, Vk, ldvk, s));
+  }
+  FF_HIP(normalize_pair_signs<T>(U, m, ldu, Vk, n, ldvk, k, o.sg, s));
+  unsigned herr = 0;
+  FF_HIP(hipMemcpyAsync(&herr, o.err, sizeof(herr), hipMemcpyDeviceToHost, s));
+  FF_HIP(hipStreamSynchronize(s));
+  if (herr) return fail(FFSRQR_EHIP, "a device-wide wait exceeded its spin limit; the outputs are incomplete");
+  return FFSRQR_OK;
+}
+
+ffsrqr_status alg9_check(int64_t m, int64_t n, int64_t l, int64_t k, int32_t precision, const DeviceInfo& d) {
+  if (m < 1 || n < 1 || l < 1 || l > std::min(m, n) || k < 1 || k > l)
+    return fail(FFSRQR_EINVAL, "need 1 <= k <= l <= min(m, n)");
+  if (precision != FFSRQR_FP64 && precision != FFSRQR_FP32 && precision != FFSRQR_MIXED)
+    return fail(FFSRQR_EINVAL, "unknown precision");
+  return check_limits(m, n, l, d);
+}
+
 }  // namespace
 }  // namespace ffsrqr
 
@@ -592,6 +685,17 @@ const char* ffsrqr_status_string(ffsrqr_status s) {
 }
 
 const char* ffsrqr_last_error(void) { return g_last_error.c_str(); }
+
+void ffsrqr_release(void) {
+  for (int i = 0; i < 64; ++i) {
+    SideStream& ss = g_side[i];
+    if (!ss.stream) continue;
+    (void)hipEventDestroy(ss.fork);
+    (void)hipEventDestroy(ss.join);
+    (void)hipStreamDestroy(ss.stream);
+    ss = SideStream{};
+  }
+}
 
 void ffsrqr_profile_enable(int on) {
   std::lock_guard<std::mutex> lk(g_prof.mu);
@@ -837,6 +941,37 @@ ffsrqr_status ffsrqr_svd_small(const void* L, int64_t l, int64_t ldl, double* si
   if (e == hipErrorOutOfMemory) return fail(FFSRQR_EWORKSPACE, "workspace too small");
   FF_HIP(e);
   return FFSRQR_OK;
+}
+
+ffsrqr_status ffsrqr_alg9_workspace_size(int64_t m, int64_t n, int64_t l, int64_t k, int32_t precision,
+                                         size_t* bytes) {
+  if (!bytes) return fail(FFSRQR_EINVAL, "bytes is NULL");
+  ffsrqr_status st = alg9_check(m, n, l, k, precision, limits_device());
+  if (st != FFSRQR_OK) return st;
+  const DeviceInfo d = sizing_device();
+  *bytes = precision == FFSRQR_FP64 ? alg9_bytes<double>(m, n, l, k, d) : alg9_bytes<float>(m, n, l, k, d);
+  return FFSRQR_OK;
+}
+
+ffsrqr_status ffsrqr_alg9_svd(const void* A, int64_t m, int64_t n, int64_t lda, const void* V, int64_t ldv, int64_t l,
+                              int64_t k, void* U, int64_t ldu, double* sigma, void* Vk, int64_t ldvk, void* work,
+                              size_t work_bytes, int32_t precision, ffsrqr_stream_t stream) {
+  const DeviceInfo lim = limits_device();
+  ffsrqr_status st = alg9_check(m, n, l, k, precision, lim);
+  if (st != FFSRQR_OK) return st;
+  if (lda < m || ldv < n || ldu < m || ldvk < n) return fail(FFSRQR_EINVAL, "leading dimension too small");
+  if (!A || !V || !U || !sigma || !Vk || !work) return fail(FFSRQR_EINVAL, "NULL pointer argument");
+  const DeviceInfo* d = nullptr;
+  st = get_device(&d);
+  if (st != FFSRQR_OK) return st;
+  st = check_limits(m, n, l, *d);
+  if (st != FFSRQR_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if (precision == FFSRQR_FP64)
+    return alg9_impl<double>((const double*)A, m, n, lda, (const double*)V, ldv, l, k, (double*)U, ldu, sigma,
+                             (double*)Vk, ldvk, work, work_bytes, *d, s);
+  return alg9_impl<float>((const float*)A, m, n, lda, (const float*)V, ldv, l, k, (float*)U, ldu, sigma,
+                          (float*)Vk, ldvk, work, work_bytes, *d, s);
 }
 
 ffsrqr_status ffsrqr_svd_small_noalloc(const void* L, int64_t l, int64_t ldl, double* sigma, int32_t precision,

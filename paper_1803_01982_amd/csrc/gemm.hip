@@ -242,7 +242,7 @@ struct Tall8Layout {
   static constexpr int pad = swz ? 16 : 2;
 };
 
-template <typename T, int MT, int G>
+template <typename T, int MT, int G, bool YN>
 __device__ __forceinline__ void tall8_body(int64_t n0, int64_t M, int64_t N, int64_t K, int64_t kchunk, const T* __restrict__ X,
                                            int64_t ldx, const T* __restrict__ Y, int64_t ldy, T* __restrict__ C,
                                            int64_t ldc, int64_t cstride, double* __restrict__ colnorm, int64_t nstride,
@@ -269,8 +269,12 @@ __device__ __forceinline__ void tall8_body(int64_t n0, int64_t M, int64_t N, int
 
   // loader: thread tid moves k = tid % 16 of rows tid / 16 + 32 q; every
   // load is issued at an address clamped into the operand and the values
-  // outside the tile are zeroed when stored, so the loads carry no branches
+  // outside the tile are zeroed when stored, so the loads carry no branches.
+  // YN (Y stored with the columns contiguous, element (k, j) at k ldy + j):
+  // thread tid moves column tid % 64 of k = tid / 64 + 8 q instead, so that
+  // a wave reads 64 consecutive columns.
   const int sk = tid & 15, sr = tid >> 4;
+  const int yk = tid >> 6, yc = tid & 63;
   T xr[XL], yr[YL];
   auto load = [&](int64_t k0) {
     const int64_t k = k0 + sk < K ? k0 + sk : K - 1;
@@ -278,8 +282,14 @@ __device__ __forceinline__ void tall8_body(int64_t n0, int64_t M, int64_t N, int
     for (int q = 0; q < XL; ++q) xr[q] = X[(int64_t)min(sr + 32 * q, (int)M - 1) * ldx + k];
 #pragma unroll
     for (int q = 0; q < YL; ++q) {
-      const int64_t nn = n0 + sr + 32 * q;
-      yr[q] = Y[(nn < N ? nn : N - 1) * ldy + k];
+      if (YN) {
+        const int64_t kk = k0 + yk + 8 * q < K ? k0 + yk + 8 * q : K - 1;
+        const int64_t nn = n0 + yc < N ? n0 + yc : N - 1;
+        yr[q] = Y[kk * ldy + nn];
+      } else {
+        const int64_t nn = n0 + sr + 32 * q;
+        yr[q] = Y[(nn < N ? nn : N - 1) * ldy + k];
+      }
     }
   };
   T* const xst = &Xs[0][sk][SWZ ? (sr ^ sk) : sr];
@@ -289,7 +299,14 @@ __device__ __forceinline__ void tall8_body(int64_t n0, int64_t M, int64_t N, int
 #pragma unroll
     for (int q = 0; q < XL; ++q) xst[buf * XB + 32 * q] = (sr + 32 * q < M && kin) ? xr[q] : T(0);
 #pragma unroll
-    for (int q = 0; q < YL; ++q) yst[buf * YB + 32 * q] = (n0 + sr + 32 * q < N && kin) ? yr[q] : T(0);
+    for (int q = 0; q < YL; ++q) {
+      if (YN) {
+        const int kl = yk + 8 * q;
+        Ys[buf][kl][SWZ ? (yc ^ kl) : yc] = (n0 + yc < N && k0 + kl < ke) ? yr[q] : T(0);
+      } else {
+        yst[buf * YB + 32 * q] = (n0 + sr + 32 * q < N && kin) ? yr[q] : T(0);
+      }
+    }
   };
 
   // fragment reads: lane l holds A[l % 16][l / 16] and B[l / 16][l % 16] of
@@ -378,7 +395,7 @@ __device__ __forceinline__ void tall8_body(int64_t n0, int64_t M, int64_t N, int
 // (workgroup b to XCD b % 8), so the groups of one column block take ids
 // eight apart: they share an XCD and its L2, which then serves the second
 // read of their common columns of Y.
-template <typename T, int MT>
+template <typename T, int MT, bool YN>
 __global__ __launch_bounds__(NT8) void gemm_tall8_kernel(
     int64_t M, int64_t N, int64_t K, int64_t kchunk, const T* __restrict__ X, int64_t ldx,
     const T* __restrict__ Y, int64_t ldy, T* __restrict__ C, int64_t ldc, int64_t cstride,
@@ -400,9 +417,9 @@ __global__ __launch_bounds__(NT8) void gemm_tall8_kernel(
   C += r0;
   if (grp != 0) colnorm = nullptr;
   if (__builtin_amdgcn_readfirstlane(threadIdx.x >> 8) == 0)
-    tall8_body<T, MT, 0>(n0, Mg, N, K, kchunk, X, ldx, Y, ldy, C, ldc, cstride, colnorm, nstride, Xs, Ys);
+    tall8_body<T, MT, 0, YN>(n0, Mg, N, K, kchunk, X, ldx, Y, ldy, C, ldc, cstride, colnorm, nstride, Xs, Ys);
   else
-    tall8_body<T, MT, 1>(n0, Mg, N, K, kchunk, X, ldx, Y, ldy, C, ldc, cstride, colnorm, nstride, Xs, Ys);
+    tall8_body<T, MT, 1, YN>(n0, Mg, N, K, kchunk, X, ldx, Y, ldy, C, ldc, cstride, colnorm, nstride, Xs, Ys);
 }
 
 // C = sum_z Cpart_z (fixed order); colnorm likewise.
@@ -456,27 +473,27 @@ int pick_splits(int64_t M, int64_t N, int64_t K, int num_cu) {
   return (int)s;
 }
 
-template <typename T, int MT>
+template <typename T, int MT, bool YN>
 void launch_tall(dim3 grid, hipStream_t s, int64_t M, int64_t N, int64_t K, int64_t kchunk, const T* X, int64_t ldx,
                  const T* Y, int64_t ldy, T* C, int64_t ldc, int64_t cstride, double* colnorm, int64_t nstride,
                  int groups) {
   if constexpr (MT >= 8)
-    gemm_tall8_kernel<T, MT><<<grid, NT8, 0, s>>>(M, N, K, kchunk, X, ldx, Y, ldy, C, ldc, cstride, colnorm, nstride,
-                                                  groups);
-  else
+    gemm_tall8_kernel<T, MT, YN><<<grid, NT8, 0, s>>>(M, N, K, kchunk, X, ldx, Y, ldy, C, ldc, cstride, colnorm,
+                                                      nstride, groups);
+  else if constexpr (!YN)
     gemm_tall_kernel<T, MT><<<grid, NT, 0, s>>>(M, N, K, kchunk, X, ldx, Y, ldy, C, ldc, cstride, colnorm, nstride);
 }
 
-template <typename T, int MT = 1>
+template <typename T, bool YN, int MT = 1>
 void dispatch_tall(int mt, dim3 grid, hipStream_t s, int64_t M, int64_t N, int64_t K, int64_t kchunk, const T* X,
                    int64_t ldx, const T* Y, int64_t ldy, T* C, int64_t ldc, int64_t cstride, double* colnorm,
                    int64_t nstride, int groups) {
   if constexpr (MT <= TALL_MT) {
     if (mt == MT)
-      launch_tall<T, MT>(grid, s, M, N, K, kchunk, X, ldx, Y, ldy, C, ldc, cstride, colnorm, nstride, groups);
+      launch_tall<T, MT, YN>(grid, s, M, N, K, kchunk, X, ldx, Y, ldy, C, ldc, cstride, colnorm, nstride, groups);
     else
-      dispatch_tall<T, MT + 1>(mt, grid, s, M, N, K, kchunk, X, ldx, Y, ldy, C, ldc, cstride, colnorm, nstride,
-                               groups);
+      dispatch_tall<T, YN, MT + 1>(mt, grid, s, M, N, K, kchunk, X, ldx, Y, ldy, C, ldc, cstride, colnorm, nstride,
+                                   groups);
   }
 }
 
@@ -491,7 +508,7 @@ size_t gemm_tn_scratch(int64_t M, int64_t N, int64_t K, int num_cu) {
 
 template <typename T>
 hipError_t gemm_tn(int64_t M, int64_t N, int64_t K, const T* X, int64_t ldx, const T* Y, int64_t ldy,
-                   T* C, int64_t ldc, double* colnorm, Arena& ar, int num_cu, hipStream_t s) {
+                   T* C, int64_t ldc, double* colnorm, Arena& ar, int num_cu, hipStream_t s, bool y_ncontig) {
   if (M <= 0 || N <= 0) return hipSuccess;
   if (K <= 0) return hipErrorInvalidValue;
   const int splits = pick_splits(M, N, K, num_cu);
@@ -499,6 +516,12 @@ hipError_t gemm_tn(int64_t M, int64_t N, int64_t K, const T* X, int64_t ldx, con
   kchunk = (kchunk + BK - 1) / BK * BK;
   int groups, mt;
   tall_shape(M, &groups, &mt);
+  if (y_ncontig) {
+    // only the eight-wave kernel reads Y by columns (rows past M are computed
+    // and dropped)
+    if (groups == 0) return hipErrorInvalidValue;
+    mt = mt < 8 ? 8 : mt;
+  }
   const bool tall = groups > 0;
   // groups > 1 only with the eight-wave kernel (mt >= 8 there)
   const int64_t ntile = (N + TBN - 1) / TBN;
@@ -520,8 +543,10 @@ hipError_t gemm_tn(int64_t M, int64_t N, int64_t K, const T* X, int64_t ldx, con
     nout = npart;
     nstride = N;
   }
-  if (tall)
-    dispatch_tall<T>(mt, grid, s, M, N, K, kchunk, X, ldx, Y, ldy, out, ldo, ostride, nout, nstride, groups);
+  if (tall && y_ncontig)
+    dispatch_tall<T, true>(mt, grid, s, M, N, K, kchunk, X, ldx, Y, ldy, out, ldo, ostride, nout, nstride, groups);
+  else if (tall)
+    dispatch_tall<T, false>(mt, grid, s, M, N, K, kchunk, X, ldx, Y, ldy, out, ldo, ostride, nout, nstride, groups);
   else
     gemm_tn_kernel<T><<<grid, NT, 0, s>>>(M, N, K, kchunk, X, ldx, Y, ldy, out, ldo, ostride, nout, nstride);
   hipError_t e = hipGetLastError();
@@ -534,8 +559,8 @@ hipError_t gemm_tn(int64_t M, int64_t N, int64_t K, const T* X, int64_t ldx, con
 template size_t gemm_tn_scratch<double>(int64_t, int64_t, int64_t, int);
 template size_t gemm_tn_scratch<float>(int64_t, int64_t, int64_t, int);
 template hipError_t gemm_tn<double>(int64_t, int64_t, int64_t, const double*, int64_t, const double*, int64_t,
-                                    double*, int64_t, double*, Arena&, int, hipStream_t);
+                                    double*, int64_t, double*, Arena&, int, hipStream_t, bool);
 template hipError_t gemm_tn<float>(int64_t, int64_t, int64_t, const float*, int64_t, const float*, int64_t,
-                                   float*, int64_t, double*, Arena&, int, hipStream_t);
+                                   float*, int64_t, double*, Arena&, int, hipStream_t, bool);
 
 }  // namespace ffsrqr

@@ -91,12 +91,26 @@ __device__ inline void jacobi_rotation(double a, double b, double h, double& cs,
   t = eu * (r2 * u);
 }
 
-// Dynamic LDS: C (ncol columns of ldc rows; rows >= l and columns >= 2 bs stay
+// Dynamic LDS: C (ncol columns of ldc = ch + 1 rows: the ch rows of the local
+// columns that this workgroup owns; rows past l and columns >= 2 bs stay
 // zero), then H and J (GW rows of stride GS each), then the partial Gram sums
-// of the row quarters 1..3 (3 x 3 x 256).
-template <typename T>
+// of the row quarters 1..3 (3 x 3 x 256).  When the l rows of a block pair do
+// not fit the LDS of one workgroup, rg workgroups share the pair, each with
+// ch rows: each computes the Gram matrix of its rows, the partial Gram
+// matrices are exchanged through xbuf (one more grid barrier per round) and
+// summed in a fixed order, so every workgroup of the pair takes the same
+// rotations and applies them to its own rows.
+//
+// With vectors (lpad > 0), M holds ldm = lpad + l rows: L in rows 0..l-1,
+// zeros up to lpad (a multiple of ch) and the identity in rows lpad ..
+// lpad + l - 1.  The Gram matrices take the rows below lpad only, the
+// rotations every row, so that after the sweeps M = [L V; 0; V] with
+// L V = U diag(sigma): the right singular vectors accumulate in the last l
+// rows (one-sided Jacobi on the stacked matrix).
+template <typename T, bool MULTI>
 __global__ __launch_bounds__(NT) void jacobi_kernel(const T* __restrict__ L, int l, int64_t ldl, double* __restrict__ M,
-                                                    int bs, int P, int ldc, int ncol, unsigned* __restrict__ rot,
+                                                    int ldm, int lpad, int bs, int P, int ldc, int ncol, int ch,
+                                                    int rg, double* __restrict__ xbuf, unsigned* __restrict__ rot,
                                                     double* __restrict__ sig, int* __restrict__ sweeps_out,
                                                     GridSync gs) {
   typedef Mfma<double> MF;
@@ -117,10 +131,11 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(const T* __restrict__ L, int
   const int W2 = 2 * bs, nct = ncol / 16;
   unsigned epoch = 0;
 
-  for (int64_t e = (int64_t)g * NT + tid; e < (int64_t)l * l; e += (int64_t)G * NT) {
-    const int64_t r = e % l, c = e / l;
-    M[c * l + r] = (double)L[c * ldl + r];
+  for (int64_t e = (int64_t)g * NT + tid; e < (int64_t)ldm * l; e += (int64_t)G * NT) {
+    const int64_t r = e % ldm, c = e / ldm;
+    M[c * ldm + r] = r < l ? (double)L[c * ldl + r] : (lpad > 0 && r - lpad == c ? 1.0 : 0.0);
   }
+  const int rows_gram = lpad > 0 ? lpad : l;  // rows that enter the Gram matrices
   for (int e = tid; e < ncol * ldc + 3 * GW * GS; e += NT) smem[e] = 0.0;  // C, H and J
   if (g == 0 && tid < 3) rot[tid] = 0u;
   if (!grid_barrier(gs, epoch)) return;
@@ -149,7 +164,9 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(const T* __restrict__ L, int
   const int jb_pi = jb_ok ? jt % bs : 0, jb_r0 = jb_ok ? jt / bs : 0;
   // Gram tiles: t = 0 -> (0,0), 1 -> (0,1), 2 -> (1,1); four quarters of the rows
   const int ntile = nct * (nct + 1) / 2;
-  const int kq = ((l + 15) & ~15) / 4;
+  const int kq = ch / 4;                        // rows of a quarter of the owned rows (ch is a multiple of 16)
+  const int pair = MULTI ? g / rg : g;          // block pair of this workgroup in every round
+  const int r0 = MULTI ? (g % rg) * ch : 0;     // its first row (MULTI: rg > 1 workgroups per pair)
   __syncthreads();
 
   int sweep = 0;
@@ -158,8 +175,8 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(const T* __restrict__ L, int
     if (tid == 0) s_sweep = 0;
     for (int r = 0; r < P - 1; ++r) {
       // blocks of this workgroup's pair
-      const int pa = rr_player(g, r, P);
-      const int pb = rr_player(P - 1 - g, r, P);
+      const int pa = rr_player(pair, r, P);
+      const int pb = rr_player(P - 1 - pair, r, P);
       const int ca0 = pa * bs, cb0 = pb * bs;
       const int na = max(0, min(bs, l - ca0)), nbk = max(0, min(bs, l - cb0));
       // local column k < bs -> block a column k, k >= bs -> block b column k - bs
@@ -167,58 +184,75 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(const T* __restrict__ L, int
         return k < bs ? (k < na ? ca0 + k : -1) : (k < W2 && k - bs < nbk ? cb0 + k - bs : -1);
       };
       if (tid == 0) s_round = 0;
-      // load: wave w takes local columns w + kk NW, all loads in flight together
-      for (int i0 = 0; i0 < l; i0 += 64 * 8) {
-        double v[GW / NW][8];
+      // load rows r0 .. r0 + ch - 1 of the local columns into C (zero past
+      // l): wave w takes local columns w + kk NW, all loads in flight together
+      auto load_chunk = [&](int r0) {
+        for (int i0 = 0; i0 < ch; i0 += 64 * 8) {
+          double v[GW / NW][8];
 #pragma unroll
-        for (int kk = 0; kk < GW / NW; ++kk) {
-          const int k = wave + kk * NW;
-          const int gc = gcol(k);
+          for (int kk = 0; kk < GW / NW; ++kk) {
+            const int k = wave + kk * NW;
+            const int gc = gcol(k);
 #pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            const int i = i0 + u * 64 + lane;
-            v[kk][u] = (gc >= 0 && i < l) ? M[(int64_t)gc * l + i] : 0.0;
+            for (int u = 0; u < 8; ++u) {
+              const int i = i0 + u * 64 + lane;
+              v[kk][u] = (gc >= 0 && i < ch && r0 + i < ldm) ? M[(int64_t)gc * ldm + r0 + i] : 0.0;
+            }
+          }
+#pragma unroll
+          for (int kk = 0; kk < GW / NW; ++kk) {
+            const int k = wave + kk * NW;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              const int i = i0 + u * 64 + lane;
+              if (k < W2 && i < ch) C[k * ldc + i] = v[kk][u];
+            }
           }
         }
+      };
+      // Gram H = C^T C of the local columns: task (tile gt, row quarter gh),
+      // task = gt + 3 gh taken by wave task % NW (at most two per wave, their
+      // sums kept in registers over the chunks); the quarter-0 sums stay in
+      // the registers of waves 0..2, the others go through Pg
+      typename MF::acc4 acct[2] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+      {
+        load_chunk(r0);
+        __syncthreads();
 #pragma unroll
-        for (int kk = 0; kk < GW / NW; ++kk) {
-          const int k = wave + kk * NW;
-#pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            const int i = i0 + u * 64 + lane;
-            if (k < W2 && i < l) C[k * ldc + i] = v[kk][u];
+        for (int ti = 0; ti < 2; ++ti) {
+          const int task = wave + ti * NW;
+          const int gt = task % 3, gh = task / 3;
+          if (task >= 12 || gt >= ntile) continue;
+          if (r0 >= rows_gram) continue;  // rows of the accumulated vectors: no Gram contribution
+          const int gtr = (gt == 2) ? 1 : 0, gtc = (gt == 0) ? 0 : 1;
+          typename MF::acc4 acc = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+          const int klo = gh * kq, khi = klo + kq;
+          const double* ca = C + (gtr * 16 + (lane & 15)) * ldc + (lane >> 4);
+          const double* cb = C + (gtc * 16 + (lane & 15)) * ldc + (lane >> 4);
+          int k0 = klo;
+          for (; k0 + 16 <= khi; k0 += 16) {
+            const double a0 = ca[k0], a1 = ca[k0 + 4], a2 = ca[k0 + 8], a3 = ca[k0 + 12];
+            const double b0 = cb[k0], b1 = cb[k0 + 4], b2 = cb[k0 + 8], b3 = cb[k0 + 12];
+            acc = MF::fma(a0, b0, acc);
+            acc1 = MF::fma(a1, b1, acc1);
+            acc = MF::fma(a2, b2, acc);
+            acc1 = MF::fma(a3, b3, acc1);
           }
+          for (; k0 < khi; k0 += 4) acc = MF::fma(ca[k0], cb[k0], acc);
+          acct[ti] = acc + acc1;
         }
       }
-      __syncthreads();
-      // Gram H = C^T C of the local columns: task (tile gt, row quarter gh),
-      // task = gt + 3 gh taken by wave task % NW; the quarter-0 sums stay in
-      // the registers of waves 0..2, the others go through Pg
       typename MF::acc4 acc0 = {0.0, 0.0, 0.0, 0.0};
-      for (int task = wave; task < 12; task += NW) {
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti) {
+        const int task = wave + ti * NW;
         const int gt = task % 3, gh = task / 3;
-        if (gt >= ntile) continue;
-        const int gtr = (gt == 2) ? 1 : 0, gtc = (gt == 0) ? 0 : 1;
-        typename MF::acc4 acc = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-        const int klo = gh * kq, khi = klo + kq;
-        const double* ca = C + (gtr * 16 + (lane & 15)) * ldc + (lane >> 4);
-        const double* cb = C + (gtc * 16 + (lane & 15)) * ldc + (lane >> 4);
-        int k0 = klo;
-        for (; k0 + 16 <= khi; k0 += 16) {
-          const double a0 = ca[k0], a1 = ca[k0 + 4], a2 = ca[k0 + 8], a3 = ca[k0 + 12];
-          const double b0 = cb[k0], b1 = cb[k0 + 4], b2 = cb[k0 + 8], b3 = cb[k0 + 12];
-          acc = MF::fma(a0, b0, acc);
-          acc1 = MF::fma(a1, b1, acc1);
-          acc = MF::fma(a2, b2, acc);
-          acc1 = MF::fma(a3, b3, acc1);
-        }
-        for (; k0 < khi; k0 += 4) acc = MF::fma(ca[k0], cb[k0], acc);
-        acc = acc + acc1;
+        if (task >= 12 || gt >= ntile) continue;
         if (gh == 0) {
-          acc0 = acc;
+          acc0 = acct[ti];
         } else {
 #pragma unroll
-          for (int q = 0; q < 4; ++q) Pg[(gh - 1) * 768 + gt * 256 + q * 64 + lane] = acc[q];
+          for (int q = 0; q < 4; ++q) Pg[(gh - 1) * 768 + gt * 256 + q * 64 + lane] = acct[ti][q];
         }
       }
       __syncthreads();
@@ -233,6 +267,19 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(const T* __restrict__ L, int
             H0[i * GS + j] = v;
             H0[j * GS + i] = v;
           }
+        }
+      }
+      if (MULTI) {
+        // partial Gram matrices of the rg workgroups of the pair: post, one
+        // grid barrier, and every workgroup sums all of them in the same
+        // order (its own read back from memory like the others)
+        __syncthreads();
+        for (int e = tid; e < GW * GW; e += NT) xbuf[(int64_t)g * GW * GW + e] = H0[(e / GW) * GS + e % GW];
+        if (!grid_barrier(gs, epoch)) return;
+        for (int e = tid; e < GW * GW; e += NT) {
+          double v = 0.0;
+          for (int h = 0; h < rg; ++h) v += xbuf[((int64_t)pair * rg + h) * GW * GW + e];
+          H0[(e / GW) * GS + e % GW] = v;
         }
       }
       for (int e = tid; e < GW * GW; e += NT) {
@@ -377,9 +424,9 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(const T* __restrict__ L, int
       __syncthreads();
       // columns <- C J, written straight to M (transposed product J^T C^T, so
       // each MFMA result row is a run of 16 consecutive entries of a column);
-      // a wave takes a 16-row slice of the columns for both column tiles
+      // a wave takes a 16-row slice of the owned rows for both column tiles
       if (s_round) {
-        const int nit = (l + 15) / 16;
+        const int nit = (min(ch, ldm - r0) + 15) / 16;
         for (int it = wave; it < nit; it += NW) {
           typename MF::acc4 d0 = {0.0, 0.0, 0.0, 0.0}, d1 = {0.0, 0.0, 0.0, 0.0};
           const double* ja = J0 + (lane >> 4) * GS + (lane & 15);
@@ -404,14 +451,14 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(const T* __restrict__ L, int
 #pragma unroll
             for (int s = 0; s < 4; ++s) d0 = MF::fma(ja[4 * s * GS], cbp[4 * s * ldc], d0);
           }
-          const int i = it * 16 + (lane & 15);
+          const int i = r0 + it * 16 + (lane & 15);
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const int j = MF::row(lane, q);
             const int gc0 = gcol(j);
-            if (gc0 >= 0 && i < l) M[(int64_t)gc0 * l + i] = d0[q];
+            if (gc0 >= 0 && i < ldm) M[(int64_t)gc0 * ldm + i] = d0[q];
             const int gc1 = gcol(16 + j);
-            if (nct == 2 && gc1 >= 0 && i < l) M[(int64_t)gc1 * l + i] = d1[q];
+            if (nct == 2 && gc1 >= 0 && i < ldm) M[(int64_t)gc1 * ldm + i] = d1[q];
           }
         }
       }
@@ -427,7 +474,7 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(const T* __restrict__ L, int
   for (int c = g * NW + wave; c < l; c += G * NW) {
     double s = 0.0;
     for (int i = lane; i < l; i += 64) {
-      const double x = M[(int64_t)c * l + i];
+      const double x = M[(int64_t)c * ldm + i];
       s += x * x;
     }
     s = wave_sum(s);
@@ -448,64 +495,135 @@ __global__ void sort_desc(const double* __restrict__ in, int l, double* __restri
   }
 }
 
-// Block size bs <= 16 (2 bs local columns <= GW); C holds the local columns
-// padded to ncol = 16 or 32 columns of ldc = roundup(l, 16) + 1 rows (an odd
-// stride spreads the MFMA operand reads over the LDS banks).  Returns false
-// when the columns of one block pair do not fit in LDS.
-bool choose(int64_t l, const DeviceInfo& d, int* bs, int* P, int* ldc, int* ncol, size_t* lds) {
-  const int ld = (int)(((l + 15) & ~(int64_t)15) + 1);
-  auto bytes = [&](int b) {
-    return ((size_t)((2 * b + 15) / 16 * 16) * ld + 3 * GW * GS + 3 * 768) * sizeof(double);
-  };
+// Block size bs <= 16 (2 bs local columns <= GW); C holds ch rows (a
+// multiple of 16) of the local columns padded to ncol = 16 or 32 columns, with
+// ldc = ch + 1 (an odd stride spreads the MFMA operand reads over the LDS
+// banks).  ch covers all l rows when they fit the LDS (up to 416 rows with
+// 160 KiB), else the rows are split over the fewest workgroups per block pair
+// (*rg) whose equal shares fit.  Returns false when not even 16 rows fit.
+bool choose(int64_t l, const DeviceInfo& d, int* bs, int* P, int* ldc, int* ncol, int* ch, int* rg, size_t* lds) {
   int b = 16;
-  if (d.lds_max != 0 && bytes(b) + 4096 > d.lds_max) b = 8;  // 16 local columns
   if (l < 2 * b) b = (int)((l + 1) / 2 > 0 ? (l + 1) / 2 : 1);
+  const int nc = (2 * b + 15) / 16 * 16;
+  auto bytes = [&](int rows) { return ((size_t)nc * (rows + 1) + 3 * GW * GS + 3 * 768) * sizeof(double); };
+  const int l16 = (int)((l + 15) & ~(int64_t)15);
+  int chunks = 1, rows = l16;
+  while (d.lds_max != 0 && bytes(rows) + 4096 > d.lds_max && rows > 16) {
+    ++chunks;
+    rows = ((l16 + chunks - 1) / chunks + 15) & ~15;
+  }
   int p = (int)((l + b - 1) / b);
   if (p < 2) p = 2;
   if (p & 1) ++p;
   *bs = b;
   *P = p;
-  *ldc = ld;
-  *ncol = (2 * b + 15) / 16 * 16;
-  *lds = bytes(b);
+  *rg = chunks;
+  *ch = rows;
+  *ldc = rows + 1;
+  *ncol = nc;
+  *lds = bytes(rows);
   return d.lds_max == 0 || *lds + 4096 <= d.lds_max;
+}
+
+// Output of the vector form: column c of M has rank(c) among the column
+// norms (descending, ties by index); sigma[rank] = its norm,
+// U(:, rank) = M(0:l, c) / sigma (zero when sigma is zero),
+// V(:, rank) = M(lpad:lpad+l, c).  One workgroup per column.
+template <typename T>
+__global__ void svd_vectors_out(const double* __restrict__ M, int l, int ldm, int lpad, const double* __restrict__ sg,
+                                double* __restrict__ sigma, T* __restrict__ U, int64_t ldu, T* __restrict__ V,
+                                int64_t ldv) {
+  __shared__ int s_rank;
+  const int c = blockIdx.x;
+  if (threadIdx.x == 0) {
+    const double v = sg[c];
+    int rank = 0;
+    for (int i = 0; i < l; ++i) {
+      const double u = sg[i];
+      rank += (u > v || (u == v && i < c)) ? 1 : 0;
+    }
+    s_rank = rank;
+    sigma[rank] = v;
+  }
+  __syncthreads();
+  const int rk = s_rank;
+  const double sv = sg[c];
+  const double inv = sv > 0.0 ? 1.0 / sv : 0.0;
+  for (int i = threadIdx.x; i < l; i += blockDim.x) {
+    U[(int64_t)rk * ldu + i] = (T)(M[(int64_t)c * ldm + i] * inv);
+    V[(int64_t)rk * ldv + i] = (T)M[(int64_t)c * ldm + lpad + i];
+  }
+}
+
+// Rows of the stacked matrix of the vector form for block rows of ch.
+void vec_rows(int64_t l, int ch, int* lpad, int* ldm, int* rg) {
+  const int rg0 = (int)((l + ch - 1) / ch);
+  *lpad = rg0 * ch;
+  *ldm = *lpad + (int)l;
+  *rg = 2 * rg0;
 }
 
 }  // namespace
 
 template <typename T>
 size_t jacobi_scratch(int64_t l, const DeviceInfo& d) {
-  return sizeof(double) * ((size_t)l * l + l) + (kSyncWords + 64) * sizeof(unsigned) + 8 * 256;
+  // the stacked M of the vector form (at most (2 l + 416) x l), sigma, the
+  // partial-Gram exchange (at most kMaxGridBlocks workgroups of GW x GW) and
+  // the barrier flags
+  return sizeof(double) * ((size_t)(2 * l + 432) * l + l + (size_t)kMaxGridBlocks * GW * GW) +
+         (kSyncWords + 64) * sizeof(unsigned) + 8 * 256;
 }
 
+namespace {
 template <typename T>
-hipError_t jacobi_sigma(const T* L, int64_t l, int64_t ldl, double* sigma, Arena& ar, unsigned* err,
-                        const DeviceInfo& d, hipStream_t s, int* sweeps) {
+hipError_t jacobi_launch(const T* L, int64_t l, int64_t ldl, bool vectors, double* sigma, T* U, int64_t ldu, T* V,
+                         int64_t ldv, Arena& ar, unsigned* err, const DeviceInfo& d, hipStream_t s, int* sweeps) {
   if (l <= 0) return hipSuccess;
-  int bs, P, ldc, ncol;
+  int bs, P, ldc, ncol, ch, rg;
   size_t lds;
-  if (!choose(l, d, &bs, &P, &ldc, &ncol, &lds)) return hipErrorInvalidValue;
-  double* M = ar.take<double>((size_t)l * l);
+  if (!choose(l, d, &bs, &P, &ldc, &ncol, &ch, &rg, &lds)) return hipErrorInvalidValue;
+  int lpad = 0, ldm = (int)l;
+  if (vectors) vec_rows(l, ch, &lpad, &ldm, &rg);
+  const int nwg = P / 2 * rg;  // workgroups: rg per block pair
+  if (nwg > kMaxGridBlocks) return hipErrorInvalidValue;
+  double* M = ar.take<double>((size_t)ldm * l);
   double* sig = ar.take<double>(l);
+  double* xbuf = ar.take<double>((size_t)nwg * GW * GW);
   unsigned* ctl = ar.take<unsigned>(kSyncWords + 64);
-  if (!M || !sig || !ctl) return hipErrorOutOfMemory;
+  if (!M || !sig || !xbuf || !ctl) return hipErrorOutOfMemory;
   hipError_t e = zero_words(ctl, kSyncWords + 64, s);
   if (e != hipSuccess) return e;
-  if (P / 2 > kMaxGridBlocks) return hipErrorInvalidValue;
-  GridSync gs{ctl, err, (unsigned)(P / 2)};
+  GridSync gs{ctl, err, (unsigned)nwg};
   unsigned* rot = ctl + kSyncWords;
   int li = (int)l;
-  void* args[] = {(void*)&L,    (void*)&li,  (void*)&ldl, (void*)&M,   (void*)&bs,     (void*)&P, (void*)&ldc,
-                  (void*)&ncol, (void*)&rot, (void*)&sig, (void*)&sweeps, (void*)&gs};
-  const void* fn = (const void*)jacobi_kernel<T>;
+  void* args[] = {(void*)&L,    (void*)&li,  (void*)&ldl,  (void*)&M,   (void*)&ldm,  (void*)&lpad,
+                  (void*)&bs,   (void*)&P,   (void*)&ldc,  (void*)&ncol, (void*)&ch,  (void*)&rg,
+                  (void*)&xbuf, (void*)&rot, (void*)&sig,  (void*)&sweeps, (void*)&gs};
+  const void* fn = rg > 1 ? (const void*)jacobi_kernel<T, true> : (const void*)jacobi_kernel<T, false>;
   if (lds > 65536) {
     e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  e = hipLaunchCooperativeKernel(fn, dim3(P / 2), dim3(NT), args, (unsigned)lds, s);
+  e = hipLaunchCooperativeKernel(fn, dim3(nwg), dim3(NT), args, (unsigned)lds, s);
   if (e != hipSuccess) return e;
-  sort_desc<<<1, 1024, 0, s>>>(sig, li, sigma);
+  if (vectors)
+    svd_vectors_out<T><<<(unsigned)l, 256, 0, s>>>(M, li, ldm, lpad, sig, sigma, U, ldu, V, ldv);
+  else
+    sort_desc<<<1, 1024, 0, s>>>(sig, li, sigma);
   return hipGetLastError();
+}
+}  // namespace
+
+template <typename T>
+hipError_t jacobi_sigma(const T* L, int64_t l, int64_t ldl, double* sigma, Arena& ar, unsigned* err,
+                        const DeviceInfo& d, hipStream_t s, int* sweeps) {
+  return jacobi_launch<T>(L, l, ldl, false, sigma, nullptr, 0, nullptr, 0, ar, err, d, s, sweeps);
+}
+
+template <typename T>
+hipError_t jacobi_svd_vectors(const T* L, int64_t l, int64_t ldl, double* sigma, T* U, int64_t ldu, T* V, int64_t ldv,
+                              Arena& ar, unsigned* err, const DeviceInfo& d, hipStream_t s, int* sweeps) {
+  return jacobi_launch<T>(L, l, ldl, true, sigma, U, ldu, V, ldv, ar, err, d, s, sweeps);
 }
 
 template size_t jacobi_scratch<double>(int64_t, const DeviceInfo&);
@@ -514,5 +632,9 @@ template hipError_t jacobi_sigma<double>(const double*, int64_t, int64_t, double
                                          const DeviceInfo&, hipStream_t, int*);
 template hipError_t jacobi_sigma<float>(const float*, int64_t, int64_t, double*, Arena&, unsigned*,
                                         const DeviceInfo&, hipStream_t, int*);
+template hipError_t jacobi_svd_vectors<double>(const double*, int64_t, int64_t, double*, double*, int64_t, double*,
+                                               int64_t, Arena&, unsigned*, const DeviceInfo&, hipStream_t, int*);
+template hipError_t jacobi_svd_vectors<float>(const float*, int64_t, int64_t, double*, float*, int64_t, float*,
+                                              int64_t, Arena&, unsigned*, const DeviceInfo&, hipStream_t, int*);
 
 }  // namespace ffsrqr

@@ -42,10 +42,13 @@ hipError_t launch_omega(uint64_t seed, int64_t l, int64_t m, T* Ot, int64_t ldo,
 // non-null it receives ||Y(:, j)||^2 (FP64).  Scratch comes from the arena.
 template <typename T>
 size_t gemm_tn_scratch(int64_t M, int64_t N, int64_t K, int num_cu);
+// y_ncontig: Y is stored with its columns contiguous instead (element
+// (k, j) at Y[k ldy + j]), i.e. C = X^T Z^T for a column-major Z (N x K,
+// ldy); M <= 1152 in that case.
 template <typename T>
 hipError_t gemm_tn(int64_t M, int64_t N, int64_t K, const T* X, int64_t ldx, const T* Y,
                    int64_t ldy, T* C, int64_t ldc, double* colnorm, Arena& ar, int num_cu,
-                   hipStream_t s);
+                   hipStream_t s, bool y_ncontig = false);
 
 // Mixed form (BF16 MFMA, FP32 accumulation), C (M x N, FP32) = X^T Y with
 // X M x K stored K-major (ldx, a multiple of 8) as BF16 parts and Y FP32
@@ -143,5 +146,22 @@ size_t jacobi_scratch(int64_t l, const DeviceInfo& d);
 template <typename T>
 hipError_t jacobi_sigma(const T* L, int64_t l, int64_t ldl, double* sigma, Arena& ar, unsigned* err,
                         const DeviceInfo& d, hipStream_t s, int* sweeps = nullptr);
+// Singular values and vectors of L (l x l): L V = U diag(sigma), sigma
+// descending (ties by index), U and V l x l (ldu, ldv >= l) in T; the same
+// Jacobi iteration with the rotations accumulated in stacked rows.
+template <typename T>
+hipError_t jacobi_svd_vectors(const T* L, int64_t l, int64_t ldl, double* sigma, T* U, int64_t ldu, T* V,
+                              int64_t ldv, Arena& ar, unsigned* err, const DeviceInfo& d, hipStream_t s,
+                              int* sweeps = nullptr);
+
+// B (cols x rows, ldb) = A^T for A rows x cols (lda).
+template <typename T>
+hipError_t transpose(const T* A, int64_t rows, int64_t cols, int64_t lda, T* B, int64_t ldb, hipStream_t s);
+// For j < k: flip U(:, j) (m rows) and V(:, j) (n rows) together when the
+// entry of U(:, j) of largest magnitude (the first on ties) is negative; sg
+// is k doubles of scratch.
+template <typename T>
+hipError_t normalize_pair_signs(T* U, int64_t m, int64_t ldu, T* V, int64_t n, int64_t ldv, int64_t k, double* sg,
+                                hipStream_t s);
 
 }  // namespace ffsrqr

@@ -271,6 +271,24 @@ def test_lq_fp64(ff, l, n, seed):
 
 
 # --------------------------------------------------------------- small SVD
+# l = 700 and 1000: the block pairs' rows are split over two and three
+# workgroups (their partial Gram matrices exchanged every round); the
+# reference is LAPACK's SVD on a well-conditioned factor (kappa ~ 1e2, where
+# its singular values are accurate to a few u relative as well)
+@pytest.mark.parametrize("l", [700, 1000])
+def test_svd_small_row_split_fp64(ff, l):
+    announce(f"svd_small fp64 l={l} (row-split block pairs)")
+    rng = np.random.default_rng(l)
+    M = np.tril(rng.standard_normal((l, l))) * 0.02 + np.diag(np.linspace(1.0, 0.01, l))
+    sig = host(ff.svd_small(dev_f(M)))
+    ref = np.linalg.svd(M, compute_uv=False)
+    nrm = np.linalg.norm(M, axis=0)
+    kappa_s = np.linalg.cond(M / nrm)
+    rel_tol = 8.0 * l * EPS * kappa_s
+    print(f"[gpu-case] kappa_s {kappa_s:.3e}, bound {rel_tol:.2e}, worst {np.max(np.abs(sig - ref) / ref):.2e}",
+          flush=True)
+    assert np.all(np.abs(sig - ref) <= rel_tol * ref)
+
 @pytest.mark.parametrize("l,kind", [(30, "qlp"), (2, "gauss"), (31, "gauss"), (100, "graded"), (272, "qlp"),
                                     (16, "rankdef"), (544, "qlp")])
 def test_svd_small_fp64(ff, l, kind):
