@@ -107,11 +107,13 @@ def roofline(prof, w, prec):
         return {"bound": "mfma", "achieved": round(pj, 2), "peak": PEAK["bf16"], "unit": "TFLOP/s",
                 "frac": round(pj / PEAK["bf16"], 4),
                 "traffic": traffic_from_profile("gemm_bf16_split_large_pmc", "paper_1803_01982_amd/csrc/gemm_bf16.hip"),
-                "kernel": "gemm_bf16_kernel<3, 4> (split-BF16 projection, with split_bf16_kernel)",
+                "kernel": ("gemm_bf16_xl_kernel<3, 17, 2> (split-BF16 projection; the timed interval also holds "
+                           "split_bf16_kernel and splitk_reduce_f32)"),
                 "flop_per_launch": pj_flop, "avg_launch_ms": round(pj_s * 1e3, 4), "launches": int(pj_n),
                 "sketch": {"bound": "hbm", "achieved": round(sk, 1), "peak": HBM_PEAK, "unit": "GB/s",
                            "frac": round(sk / HBM_PEAK, 4), "bytes_per_launch": sk_bytes,
-                           "avg_launch_ms": round(sk_s * 1e3, 4), "kernel": "gemm_bf16_kernel<1, 5> (BF16 sketch)"}}
+                           "avg_launch_ms": round(sk_s * 1e3, 4), "kernel": ("gemm_bf16_xl_kernel<1, 17, 2> (BF16 sketch; the timed interval also "
+                                      "holds splitk_reduce_f32)")}}
     avg_s = (sk_ms + pj_ms) / (sk_n + pj_n) / 1e3
     achieved = flop / avg_s / 1e12
     kern = "gemm_tall8_kernel" if w.l > 112 else "gemm_tall_kernel"

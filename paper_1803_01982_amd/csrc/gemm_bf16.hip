@@ -14,25 +14,31 @@
 //               by split_bf16_kernel; A is split in registers.
 //
 // Both operands are K-contiguous (K = m): X is M x K (stored K-major, ldx a
-// multiple of 8 on a 16-byte aligned base), Y is FP32 K x N (ldy; 16-byte
-// loads when its columns are 16-byte aligned, else element loads).  One workgroup of eight waves covers a group of
-// up to 640 rows of C (512 for the three-product form) and a block of 64
-// columns; with one group (the sketch up to l = 640) A is streamed from HBM
-// once.  MFMA 16x16x32 (BF16 in, FP32
-// out): wave w owns the row tiles w, w + 8, w + 16, ... and all four
-// 16-column tiles of the block, so every row tile's X fragment is loaded by
-// exactly one wave, straight from global memory into registers in the MFMA
-// operand layout (16 bytes per lane: eight consecutive k of one row), one K
-// step ahead.  The FP32 columns of A go through LDS once per K step: loaded
-// one step ahead, rounded (and split) into BF16, stored into a double
-// buffer as [column][k] rows of 40 BF16 (80 bytes: the 16 lanes that read
-// one k-slice of 16 columns hit distinct banks), and read by every wave as
-// its B fragments.  One workgroup barrier per K step.
+// multiple of 8 on a 16-byte aligned base), Y is FP32 K x N (ldy).  Two
+// kernel forms:
+//   wide-column (gemm_bf16_xl_kernel, when K is a multiple of 64 and the
+//     columns of Y are 16-byte aligned): X through LDS by direct global ->
+//     LDS loads, each wave owning 32 columns of Y for every row of its
+//     group, straight from global memory into registers;
+//   narrow (gemm_bf16_kernel, any K and alignment): one workgroup of eight
+//     waves covers a group of up to 640 rows of C (512 for the
+//     three-product form) and a block of 64 columns; wave w owns the row
+//     tiles w, w + 8, ... and all four 16-column tiles of the block, its X
+//     fragments loaded straight from global memory into registers (16 bytes
+//     per lane: eight consecutive k of one row) one K step ahead, while the
+//     FP32 columns of Y go through LDS once per K step (loaded one step
+//     ahead, rounded or split into BF16, stored as [column][k] rows of 40
+//     BF16 so that the 16 lanes reading one k-slice of 16 columns hit
+//     distinct banks) and are read by every wave as its B fragments.
+// Both use MFMA 16x16x32 (BF16 in, FP32 out) and one workgroup barrier per K
+// step, and split K when the grid would not cover the chip (partial sums
+// added in a fixed order).
 //
 // Lane layout of v_mfma_f32_16x16x32_bf16 (checked by an in-bounds probe on
 // gfx950): lane l holds A[l % 16][8 (l / 16) + e] and B[8 (l / 16) + e][l % 16]
 // for e = 0..7; result register r of lane l is D[4 (l / 16) + r][l % 16].
 #include <algorithm>
+#include <type_traits>
 
 #include "common.hpp"
 #include "kernels.hpp"
@@ -266,6 +272,242 @@ __global__ __launch_bounds__(MB_NT) void gemm_bf16_kernel(
   }
 }
 
+// ---------------------------------------------------------------------------
+// Wide-column form.  The rows of X (all MTG row tiles of a group) go through
+// LDS, the columns of Y straight into registers:
+//   - X: per 64-deep K step, MTG x NPART x 2 MFMA operand fragments of 1 KB,
+//     each moved by one direct global -> LDS load instruction
+//     (global_load_lds_dwordx4) in which lane l fetches the 16 bytes it will
+//     later read back as its operand: row 16 t + l % 16, k = 8 (l / 16) ..
+//     + 7 of the slice.  LDS then holds every fragment in operand order,
+//     read back with one conflict-free 16-byte read per lane.  Two stage
+//     buffers (two distinct LDS arrays, so the compiler can tell that the
+//     loads into one do not alias the reads of the other), loaded one step
+//     ahead.
+//   - Y: wave w owns NC 16-column tiles (the workgroup 128 NC columns) for
+//     every row tile of the group, so a Y value is needed by one wave only:
+//     each lane loads the eight consecutive k of its column that form its B
+//     operand (two 16-byte loads per k-slice), one step ahead, and rounds
+//     (splits) them to BF16 in registers.
+// One wait for this wave's loads and one workgroup barrier per K step; the
+// loads of step s + 1 are issued right after that barrier, before the
+// MFMAs of step s (a scheduling barrier keeps that order).  The products of
+// one accumulator run in the same order as in the narrow form above.
+constexpr int XL_NT = 512;
+constexpr int XL_BK = 64;
+constexpr int XL_FRAG = 1024;  // bytes of one operand fragment: 64 lanes x 16 bytes
+
+template <int NP, int MTG, int NC>
+struct XlShape {
+  static constexpr int NPART = NP == 1 ? 1 : 2;
+  static constexpr int NF = MTG * NPART * 2;  // fragments per K step
+  static constexpr int FPW = (NF + 7) / 8;    // fragments loaded per wave
+  static constexpr int STAGE = NF * XL_FRAG;  // LDS bytes per K step
+  static constexpr int BN = 8 * 16 * NC;      // columns per workgroup
+};
+
+// One direct global -> LDS load: 16 bytes per lane from src to
+// dst + 16 lane (dst the same for the whole wave).
+__device__ __forceinline__ void xl_issue(const __bf16* src, unsigned char* dst) {
+  __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
+}
+
+// Scheduling groups for the MFMAs of one k-slice: the reads of the first
+// two row tiles, then per tile its MFMAs with the RPT reads of the tile two
+// ahead placed between them.
+template <int T, int MTG, int RPT, int MPT>
+__device__ __forceinline__ void xl_sched() {
+  if constexpr (T == 0) __builtin_amdgcn_sched_group_barrier(0x100, MTG > 1 ? 2 * RPT : RPT, 0);
+  if constexpr (T < MTG) {
+    constexpr int R = T + 2 < MTG ? RPT : 0;
+    constexpr int M0 = (MPT + 1) / 2, M1 = MPT - M0;
+    constexpr int R0 = (R + 1) / 2, R1 = R - R0;
+    __builtin_amdgcn_sched_group_barrier(0x008, M0, 0);
+    if constexpr (R0 > 0) __builtin_amdgcn_sched_group_barrier(0x100, R0, 0);
+    if constexpr (M1 > 0) __builtin_amdgcn_sched_group_barrier(0x008, M1, 0);
+    if constexpr (R1 > 0) __builtin_amdgcn_sched_group_barrier(0x100, R1, 0);
+    xl_sched<T + 1, MTG, RPT, MPT>();
+  }
+}
+
+template <int NP, int MTG, int NC>
+__global__ __launch_bounds__(XL_NT) void gemm_bf16_xl_kernel(
+    int64_t M, int64_t N, int64_t K, int64_t kchunk, const __bf16* __restrict__ Xhi, const __bf16* __restrict__ Xlo,
+    int64_t ldx, const float* __restrict__ Y, int64_t ldy, float* __restrict__ C, int64_t ldc, int64_t cstride,
+    double* __restrict__ colnorm, int64_t nstride, int groups, int rows_per_group) {
+  typedef XlShape<NP, MTG, NC> S;
+  constexpr int NPART = S::NPART, NF = S::NF, FPW = S::FPW;
+  __shared__ __attribute__((aligned(16))) unsigned char xs0[S::STAGE];
+  __shared__ __attribute__((aligned(16))) unsigned char xs1[S::STAGE];
+
+  int64_t tile = blockIdx.x;
+  int grp = 0;
+  if (groups > 1) {
+    const int64_t per = 8 * (int64_t)groups;
+    tile = (int64_t)(blockIdx.x / per) * 8 + blockIdx.x % 8;
+    grp = (int)((blockIdx.x % per) / 8);
+  }
+  const int64_t n0 = tile * S::BN, r0 = (int64_t)grp * rows_per_group;
+  if (n0 >= N || r0 >= M) return;
+  const int64_t Mg = M - r0 < rows_per_group ? M - r0 : rows_per_group;
+  const int MT = (int)((Mg + 15) / 16);
+  const int64_t kb = (int64_t)blockIdx.z * kchunk;
+  const int64_t ke = (kb + kchunk < K) ? kb + kchunk : K;
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: keeps fragment indices scalar
+  const int fr = lane & 15, fg = lane >> 4;
+
+  // fragment f = (t NPART + p) 2 + s (row tile t, part p, k-slice s) is
+  // loaded by wave f % 8.  Lane (fr, fg) of it reads row 16 t + fr,
+  // k = 32 s + 8 fg ..: a per-lane offset plus a uniform one, except in a
+  // tile that crosses Mg, whose rows past Mg read row Mg - 1 (results
+  // discarded).
+  const int64_t lane_off = (int64_t)fr * ldx + 8 * fg;
+  auto issue_x = [&](unsigned char* buf, int64_t k0) __attribute__((always_inline)) {
+#pragma unroll
+    for (int i = 0; i < FPW; ++i) {
+      const int f = wave + 8 * i;
+      if (f < NF) {
+        const int t = f / (2 * NPART), s = f & 1;
+        const __bf16* part = ((f / 2) % NPART) ? Xlo : Xhi;
+        const __bf16* src;
+        if (16 * t + 16 <= Mg) {
+          src = part + (r0 + 16 * t) * ldx + 32 * s + k0 + lane_off;
+        } else {
+          const int64_t row = 16 * t + fr < Mg ? 16 * t + fr : Mg - 1;
+          src = part + (r0 + row) * ldx + 32 * s + 8 * fg + k0;
+        }
+        xl_issue(src, buf + f * XL_FRAG);
+      }
+    }
+  };
+
+  // Y: column n0 + 16 (NC wave + c) + fr (clamped to N - 1), k = k0 + 32 s + 8 fg
+  const float* ycol[NC];
+  bool yok[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const int64_t col = n0 + 16 * (NC * wave + c) + fr;
+    yok[c] = col < N;
+    ycol[c] = Y + (col < N ? col : N - 1) * ldy + 8 * fg;
+  }
+  float yr[NC][2][8];
+  auto load_y = [&](int s, int64_t k0) __attribute__((always_inline)) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const float* p = ycol[c] + k0 + 32 * s;
+      const float4 a = *reinterpret_cast<const float4*>(p);
+      const float4 b = *reinterpret_cast<const float4*>(p + 4);
+      yr[c][s][0] = a.x; yr[c][s][1] = a.y; yr[c][s][2] = a.z; yr[c][s][3] = a.w;
+      yr[c][s][4] = b.x; yr[c][s][5] = b.y; yr[c][s][6] = b.z; yr[c][s][7] = b.w;
+    }
+  };
+
+  f32x4 acc[MTG][NC];
+#pragma unroll
+  for (int t = 0; t < MTG; ++t)
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[t][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+  double nrm[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) nrm[c] = 0.0;
+
+  const int64_t nsteps = (ke - kb) / XL_BK;  // K and the chunk are whole steps
+
+  // one K step on stage `cur`, loading step st + 1 into `nxt`.  The two
+  // k-slices run one after the other: slice s of Y is rounded to BF16 and
+  // its registers reloaded with slice s of the next step before the MFMAs
+  // of slice s over all row tiles.
+  auto step = [&](const unsigned char* cur, unsigned char* nxt, int64_t st) __attribute__((always_inline)) {
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's loads of step st have landed
+    __syncthreads();                     // every wave's loads of step st; every read of nxt done
+    const bool more = st + 1 < nsteps;
+    const int64_t k1 = kb + (st + 1) * XL_BK;
+    const unsigned char* xb = cur + 16 * lane;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      bf16x8 yh[NC], yl[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const float y = yok[c] ? yr[c][s][e] : 0.0f;
+          const __bf16 h = to_bf16(y);
+          yh[c][e] = h;
+          if (NP == 3) yl[c][e] = to_bf16(y - (float)h);
+          if (NP == 1) nrm[c] = fma((double)y, (double)y, nrm[c]);
+        }
+      if (more) {
+        if (s == 0) issue_x(nxt, k1);
+        load_y(s, k1);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      // operand reads run two row tiles ahead of the MFMAs (a ring of three
+      // register sets); the interleave is pinned for the scheduler below
+      bf16x8 xh[3], xl[3];
+      auto rd = [&](int t) __attribute__((always_inline)) {
+        xh[t % 3] = *reinterpret_cast<const bf16x8*>(xb + ((t * NPART) * 2 + s) * XL_FRAG);
+        if (NP == 3) xl[t % 3] = *reinterpret_cast<const bf16x8*>(xb + ((t * NPART + 1) * 2 + s) * XL_FRAG);
+      };
+      rd(0);
+      if (MTG > 1) rd(1);
+#pragma unroll
+      for (int t = 0; t < MTG; ++t) {
+        if (t + 2 < MTG) rd(t + 2);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          acc[t][c] = mfma_bf16(xh[t % 3], yh[c], acc[t][c]);
+          if (NP == 3) {
+            acc[t][c] = mfma_bf16(xh[t % 3], yl[c], acc[t][c]);
+            acc[t][c] = mfma_bf16(xl[t % 3], yh[c], acc[t][c]);
+          }
+        }
+      }
+      xl_sched<0, MTG, NPART, NP * NC>();
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  };
+
+  if (nsteps > 0) {
+    issue_x(xs0, kb);
+    load_y(0, kb);
+    load_y(1, kb);
+  }
+  for (int64_t st = 0; st < nsteps; st += 2) {
+    step(xs0, xs1, st);
+    if (st + 1 < nsteps) step(xs1, xs0, st + 1);
+  }
+
+  float* Cz = C + (int64_t)blockIdx.z * cstride + r0;
+#pragma unroll
+  for (int t = 0; t < MTG; ++t) {
+    if (t >= MT) continue;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const int64_t col = n0 + 16 * (NC * wave + c) + fr;
+      if (col >= N) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = 16 * t + 4 * fg + r;
+        if (row < Mg) Cz[col * ldc + row] = acc[t][c][r];
+      }
+    }
+  }
+  if (NP == 1 && colnorm != nullptr && grp == 0) {
+    // the four lanes of a column (k groups fg) hold disjoint k: pairwise sums
+    // in a fixed pairing, the same value on every lane
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      double v = nrm[c];
+      v += __shfl_xor(v, 16);
+      v += __shfl_xor(v, 32);
+      const int64_t col = n0 + 16 * (NC * wave + c) + fr;
+      if (fg == 0 && col < N) colnorm[(int64_t)blockIdx.z * nstride + col] = v;
+    }
+  }
+}
+
 // xhi = bf16(x), xlo = bf16(x - xhi) for an M x K column-major FP32 block
 // (ld), written K-major with leading dimension ldo.
 __global__ void split_bf16_kernel(const float* __restrict__ X, int64_t rows, int64_t cols, int64_t ld,
@@ -334,10 +576,61 @@ hipError_t launch_bf16(int ntw, dim3 grid, hipStream_t s, int64_t M, int64_t N, 
   }
 }
 
+// Wide-column launch: NP products, MTG row tiles per group, NC column tiles
+// per wave; K split into `splits` chunks of whole 64-deep steps.
+template <int NP, int MTG, int NC>
+hipError_t launch_xl(int64_t M, int64_t N, int64_t K, int splits, const __bf16* Xhi, const __bf16* Xlo, int64_t ldx,
+                     const float* Y, int64_t ldy, float* out, int64_t ldo, int64_t ostride, double* nout,
+                     int64_t nstride, int groups, int rpg, hipStream_t s) {
+  typedef XlShape<NP, MTG, NC> S;
+  int64_t kchunk = (K + splits - 1) / splits;
+  kchunk = (kchunk + XL_BK - 1) / XL_BK * XL_BK;
+  const int64_t ntile = (N + S::BN - 1) / S::BN;
+  const int64_t gx = groups > 1 ? (ntile + 7) / 8 * 8 * groups : ntile;
+  gemm_bf16_xl_kernel<NP, MTG, NC><<<dim3((unsigned)gx, 1u, (unsigned)splits), XL_NT, 0, s>>>(
+      M, N, K, kchunk, Xhi, Xlo, ldx, Y, ldy, out, ldo, ostride, nout, nstride, groups, rpg);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+namespace {
+
+// Plan of the wide-column form: K a whole number of 64-deep steps and Y in
+// 16-byte aligned columns (its loads are unconditional 16-byte loads); row
+// groups of at most 17 tiles, or one group of at most eight for small M;
+// K split until the grid covers the chip.
+struct XlPlan {
+  bool ok;
+  int mtg, groups, rpg, splits;
+};
+
+XlPlan xl_plan(int64_t M, int64_t N, int64_t K, bool y_aligned, int num_cu) {
+  XlPlan p{false, 0, 0, 0, 1};
+  if (K % XL_BK != 0 || !y_aligned) return p;
+  const int64_t T = (M + 15) / 16;
+  if (T <= 8) {
+    p.mtg = 8;
+    p.groups = 1;
+  } else {
+    p.mtg = 17;
+    p.groups = (int)((T + 16) / 17);
+  }
+  p.rpg = (int)((T + p.groups - 1) / p.groups * 16);
+  const int64_t tiles = (N + XlShape<1, 17, 2>::BN - 1) / XlShape<1, 17, 2>::BN * p.groups;
+  int64_t sp = 1;
+  while (tiles * sp < (int64_t)num_cu && K / (sp * 2) >= 2048) sp *= 2;
+  p.splits = (int)sp;
+  p.ok = true;
+  return p;
+}
+
 }  // namespace
 
 size_t gemm_bf16_scratch(int64_t M, int64_t N, int64_t K, int num_cu) {
-  const int s = std::max(bf16_splits(1, M, N, K, num_cu), bf16_splits(3, M, N, K, num_cu));
+  int s = std::max(bf16_splits(1, M, N, K, num_cu), bf16_splits(3, M, N, K, num_cu));
+  const XlPlan xp = xl_plan(M, N, K, true, num_cu);
+  if (xp.ok) s = std::max(s, xp.splits);
   if (s == 1) return 0;
   return (size_t)s * M * N * sizeof(float) + (size_t)s * N * sizeof(double) + 1024;
 }
@@ -351,14 +644,11 @@ hipError_t gemm_bf16(int nprod, int64_t M, int64_t N, int64_t K, const __bf16* X
   if ((ldx % 8) != 0 || (reinterpret_cast<uintptr_t>(Xhi) & 15) != 0 ||
       (Xlo != nullptr && (reinterpret_cast<uintptr_t>(Xlo) & 15) != 0))
     return hipErrorInvalidValue;
+  const bool y_aligned = (ldy & 3) == 0 && (reinterpret_cast<uintptr_t>(Y) & 15) == 0;
+  const XlPlan xp = xl_plan(M, N, K, y_aligned, num_cu);
   int groups, rpg, ntw;
   bf16_shape(nprod, M, &groups, &rpg, &ntw);
-  const int splits = bf16_splits(nprod, M, N, K, num_cu);
-  int64_t kchunk = (K + splits - 1) / splits;
-  kchunk = (kchunk + MB_KMAX - 1) / MB_KMAX * MB_KMAX;  // a whole number of K steps for either step depth
-  const int64_t ntile = (N + MB_BN - 1) / MB_BN;
-  const int64_t gx = groups > 1 ? (ntile + 7) / 8 * 8 * groups : ntile;
-  dim3 grid((unsigned)gx, 1u, (unsigned)splits);
+  const int splits = xp.ok ? xp.splits : bf16_splits(nprod, M, N, K, num_cu);
   float* out = C;
   int64_t ldo = ldc, ostride = 0, nstride = 0;
   double* nout = colnorm;
@@ -374,11 +664,29 @@ hipError_t gemm_bf16(int nprod, int64_t M, int64_t N, int64_t K, const __bf16* X
     nout = npart;
     nstride = N;
   }
-  hipError_t e = nprod == 1
-                     ? launch_bf16<1>(ntw, grid, s, M, N, K, kchunk, Xhi, nullptr, ldx, Y, ldy, out, ldo, ostride,
-                                      nout, nstride, groups, rpg)
-                     : launch_bf16<3>(ntw, grid, s, M, N, K, kchunk, Xhi, Xlo, ldx, Y, ldy, out, ldo, ostride,
-                                      nout, nstride, groups, rpg);
+  hipError_t e;
+  if (xp.ok) {
+    if (nprod == 1)
+      e = xp.mtg == 8 ? launch_xl<1, 8, 2>(M, N, K, splits, Xhi, nullptr, ldx, Y, ldy, out, ldo, ostride, nout,
+                                           nstride, xp.groups, xp.rpg, s)
+                      : launch_xl<1, 17, 2>(M, N, K, splits, Xhi, nullptr, ldx, Y, ldy, out, ldo, ostride, nout,
+                                            nstride, xp.groups, xp.rpg, s);
+    else
+      e = xp.mtg == 8 ? launch_xl<3, 8, 2>(M, N, K, splits, Xhi, Xlo, ldx, Y, ldy, out, ldo, ostride, nout,
+                                           nstride, xp.groups, xp.rpg, s)
+                      : launch_xl<3, 17, 2>(M, N, K, splits, Xhi, Xlo, ldx, Y, ldy, out, ldo, ostride, nout,
+                                            nstride, xp.groups, xp.rpg, s);
+  } else {
+    int64_t kchunk = (K + splits - 1) / splits;
+    kchunk = (kchunk + MB_KMAX - 1) / MB_KMAX * MB_KMAX;  // a whole number of K steps for either step depth
+    const int64_t ntile = (N + MB_BN - 1) / MB_BN;
+    const int64_t gx = groups > 1 ? (ntile + 7) / 8 * 8 * groups : ntile;
+    dim3 grid((unsigned)gx, 1u, (unsigned)splits);
+    e = nprod == 1 ? launch_bf16<1>(ntw, grid, s, M, N, K, kchunk, Xhi, nullptr, ldx, Y, ldy, out, ldo, ostride,
+                                    nout, nstride, groups, rpg)
+                   : launch_bf16<3>(ntw, grid, s, M, N, K, kchunk, Xhi, Xlo, ldx, Y, ldy, out, ldo, ostride, nout,
+                                    nstride, groups, rpg);
+  }
   if (e != hipSuccess || splits == 1) return e;
   const int64_t total = M * N > N ? M * N : N;
   splitk_reduce_f32<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(M, N, splits, part, C, ldc, npart, colnorm);

@@ -79,9 +79,12 @@ def test_sketch_fp32(ff, l):
 # Mixed form: B = bf16(Omega) bf16(A) with FP32 sums.  The oracle's bf16
 # sketch is the FP64 sum of the same exact products, so the difference is the
 # FP32 summation error, at most m 2^-24 sum_t |bf16(Omega_it)| |bf16(A_tj)|.
-# l = 544 is one row group of the kernel, l = 700 two; ragged m and n.
+# m a multiple of 64 takes the wide-column kernel (row groups of up to 17
+# tiles: l = 544 two, l = 700 three, l = 300 two with a partial last tile;
+# l <= 128 one group of up to eight), other m the narrow kernel (l = 544 one
+# row group, l = 700 two); ragged n.
 @pytest.mark.parametrize("m,n,l", [(1000, 800, 30), (3001, 517, 136), (8192, 1100, 544), (2000, 900, 700),
-                                   (40000, 64, 16)])
+                                   (40000, 64, 16), (4096, 1000, 300), (2048, 700, 700), (16384, 300, 64)])
 def test_sketch_mixed(ff, m, n, l):
     import torch
     announce(f"sketch mixed m={m} n={n} l={l}")
@@ -102,7 +105,8 @@ def test_sketch_mixed(ff, m, n, l):
 # qhi ahi + qhi alo + qlo ahi, whose error is at most about 3 2^-18 |q a|
 # (the dropped qlo alo and the two representation remainders), plus the FP32
 # summation error m 2^-24 of the sum of |q a|.
-@pytest.mark.parametrize("m,n,c", [(1000, 800, 30), (4100, 1100, 200), (8192, 700, 544), (2049, 300, 17)])
+@pytest.mark.parametrize("m,n,c", [(1000, 800, 30), (4100, 1100, 200), (8192, 700, 544), (2049, 300, 17),
+                                   (6400, 1500, 300), (8192, 300, 100), (16384, 2000, 1000)])
 def test_project_mixed(ff, m, n, c):
     import torch
     announce(f"project mixed m={m} n={n} c={c}")
