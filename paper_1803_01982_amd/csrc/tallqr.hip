@@ -950,7 +950,7 @@ __global__ __launch_bounds__(WM_NT) void wy_m_kernel(const T* __restrict__ P, in
   if (lane == 0) sgn[j] = sj;
 }
 
-// The same M' for c <= 512 as a blocked triangular solve: workgroup w
+// The same M' for c <= 592 as a blocked triangular solve: workgroup w
 // takes the sixteen right-hand sides j = 16 w .. 16 w + 15 with all their
 // rows in LDS, and walks the 16-row blocks from the one holding the largest
 // j up to the first.  A block's diagonal part is solved by sixteen lanes of
@@ -959,9 +959,12 @@ __global__ __launch_bounds__(WM_NT) void wy_m_kernel(const T* __restrict__ P, in
 // r(0:k0, :) -= S(0:k0, block) m(block, :), on FP64 MFMA by all four waves.
 // The S columns of the next block are loaded while the current one is
 // worked on.
+// RS = 256-row slots per column (2 for c <= 512, 3 up to the 592 rows whose
+// 34 c16 doubles still fit the LDS).
 constexpr int WB_NT = 256, WB_LD = 17;  // LDS row stride of the right-hand sides
+constexpr int WB_MAXC = 592;
 
-template <typename T>
+template <typename T, int RS>
 __global__ __launch_bounds__(WB_NT) void wy_m_blocked_kernel(const T* __restrict__ P, int c, int64_t ldp,
                                                              const double* __restrict__ S,
                                                              const double* __restrict__ taus,
@@ -971,7 +974,7 @@ __global__ __launch_bounds__(WB_NT) void wy_m_blocked_kernel(const T* __restrict
   double* rl = smem;                         // rl[i * WB_LD + jj]: row i of right-hand side jj
   double* sb = rl + (int64_t)c16 * WB_LD;    // sb[kk * c16 + i] = S(i, k0 + kk), i < k0 + kk
   double* tl = sb + (int64_t)16 * c16;       // tau_k, zero past c
-  constexpr int PF = 32;                     // S loads per thread and block (16 c16 <= 256 PF for c <= 512)
+  constexpr int PF = 16 * RS;                // S loads per thread and block (16 c16 <= 256 PF)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int j0 = blockIdx.x * 16, jn = min(16, c - j0);
   // thread tid: right-hand side jj = tid % 16, rows tid / 16 + 16 x (all
@@ -979,7 +982,7 @@ __global__ __launch_bounds__(WB_NT) void wy_m_blocked_kernel(const T* __restrict
   const int jj = tid & 15, ir = tid >> 4;
   for (int k = tid; k < c16; k += WB_NT) tl[k] = k < c ? taus[k] : 0.0;
   {
-    constexpr int RX = 512 / 16;
+    constexpr int RX = 256 * RS / 16;
     double v[RX];
 #pragma unroll
     for (int x = 0; x < RX; ++x) {
@@ -991,13 +994,13 @@ __global__ __launch_bounds__(WB_NT) void wy_m_blocked_kernel(const T* __restrict
       if (ir + 16 * x < c16) rl[(ir + 16 * x) * WB_LD + jj] = v[x];
   }
   // S(0 : k0 + 16, k0 : k0 + 16) of block kb, element x of thread tid:
-  // column kk = x / 2, row i = tid + WB_NT (x % 2)
+  // column kk = x / RS, row i = tid + WB_NT (x % RS)
   double pf[PF];
   auto load_s = [&](int kb) {
     const int k0 = kb * 16;
 #pragma unroll
     for (int x = 0; x < PF; ++x) {
-      const int kk = x >> 1, i = tid + WB_NT * (x & 1), k = k0 + kk;
+      const int kk = x / RS, i = tid + WB_NT * (x % RS), k = k0 + kk;
       pf[x] = (i < k && k < c) ? S[(int64_t)k * c + i] : 0.0;
     }
   };
@@ -1005,7 +1008,7 @@ __global__ __launch_bounds__(WB_NT) void wy_m_blocked_kernel(const T* __restrict
     const int k0 = kb * 16;
 #pragma unroll
     for (int x = 0; x < PF; ++x) {
-      const int kk = x >> 1, i = tid + WB_NT * (x & 1);
+      const int kk = x / RS, i = tid + WB_NT * (x % RS);
       if (i < k0 + 16) sb[kk * c16 + i] = pf[x];
     }
   };
@@ -1137,13 +1140,16 @@ __global__ __launch_bounds__(256) void wy_apply_kernel(const T* __restrict__ P, 
 }
 
 // Row blocks of 64 to 256 rows, aiming at 128 workgroups: more workgroups
-// share the streaming trailing updates, fewer keep the panel exchanges and
-// the grid barriers cheap.  Measured on 16384 x 272 / 8192 x 272 (one
-// exchange per panel): 64 workgroups 1.99 / 1.83 ms, 128 workgroups
-// 1.66 / 1.39 ms, 256 workgroups 1.74 ms (16384 rows).
+// share the streaming trailing updates, fewer keep the panel exchanges
+// cheap.  Measured on 16384 x 272 / 8192 x 272: 64 workgroups 1.99 / 1.83
+// ms, 128 workgroups 1.66 / 1.39 ms, 256 workgroups 1.74 ms (16384 rows).
+// From 32768 rows on the trailing updates dominate and the row blocks stay
+// at 128 rows up to one workgroup per CU (32768 x 544: 256 workgroups 4.79
+// ms, 128 workgroups 5.71 ms; 16384 x 544: 4.01 and 4.00 ms).
 void choose(int64_t mrows, int c, int num_cu, int* G, int* rb, size_t* lds) {
   int64_t rows = (mrows + 127) / 128;
   rows = rows < 64 ? 64 : (rows > 256 ? 256 : rows);
+  if (mrows >= 32768) rows = std::max<int64_t>(128, (mrows + num_cu - 1) / num_cu);
   int64_t g = (mrows + rows - 1) / rows;
   if (g > num_cu) g = num_cu;
   if (g < 1) g = 1;
@@ -1282,9 +1288,9 @@ hipError_t tall_qr(T* P, int64_t mrows, int64_t c, int64_t ldp, T* Qout, int64_t
   gram_y_kernel<T><<<dim3((unsigned)(nt * (nt + 1) / 2), (unsigned)nsplit), 256, 0, s>>>(P, mrows, ci, ldp, chunk,
                                                                                         spart);
   gram_sum_kernel<<<(unsigned)((c * c + 255) / 256), 256, 0, s>>>(spart, nsplit, ci, S);
-  if (ci <= 512) {
-    const size_t blds = ((size_t)((ci + 15) & ~15) * (WB_LD + 16 + 1)) * sizeof(double);
-    const void* bfn = (const void*)wy_m_blocked_kernel<T>;
+  const size_t blds = ((size_t)((ci + 15) & ~15) * (WB_LD + 16 + 1)) * sizeof(double);
+  if (ci <= WB_MAXC && (d.lds_max == 0 || blds <= d.lds_max)) {
+    const void* bfn = ci <= 512 ? (const void*)wy_m_blocked_kernel<T, 2> : (const void*)wy_m_blocked_kernel<T, 3>;
     if (blds > 65536) {
       e = hipFuncSetAttribute(bfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)blds);
       if (e != hipSuccess) return e;

@@ -166,11 +166,15 @@ def test_qrcp_orthogonal_columns(ff):
 
 
 # --------------------------------------------------------- Householder QR
-# c = 512 is the widest panel set whose M goes through the blocked back
-# substitution; c = 520 takes the column-per-wave kernel
+# M goes through the blocked back substitution with two 256-row slots per
+# column up to c = 512, three up to c = 592 (c = 520, 544), and through the
+# column-per-wave kernel beyond (c = 600); from 32768 rows on the row blocks
+# are 128 rows (256 workgroups), 40000 rows gives blocks of 157 rows with a
+# short last one
 @pytest.mark.parametrize("m,n,c,seed", [(1000, 800, 30, 1), (1000, 800, 37, 2), (300, 50, 5, 3),
                                         (5000, 400, 100, 4), (64, 64, 64, 5), (16384, 300, 17, 6),
-                                        (1100, 600, 512, 8), (1300, 600, 520, 9), (20000, 600, 544, 10)])
+                                        (1100, 600, 512, 8), (1300, 600, 520, 9), (20000, 600, 544, 10),
+                                        (32768, 600, 544, 11), (40000, 300, 100, 12), (2000, 700, 600, 13)])
 def test_panel_qr_fp64(ff, m, n, c, seed):
     import torch
     announce(f"panel_qr fp64 m={m} n={n} c={c}")
@@ -192,7 +196,8 @@ def test_panel_qr_fp64(ff, m, n, c, seed):
 # well conditioned and must match the oracle; the whole factorization must
 # be orthogonal and reproduce A(:, cols) to rounding.
 @pytest.mark.parametrize("m,c,bad", [(3000, 40, ((5, 4, 1e-9), (20, 19, 0.0), (33, None, 0.0))),
-                                     (16384, 48, ((1, 0, 1e-7), (17, 3, 1e-12), (40, 39, 1e-5)))])
+                                     (16384, 48, ((1, 0, 1e-7), (17, 3, 1e-12), (40, 39, 1e-5))),
+                                     (32768, 40, ((3, 2, 1e-8), (18, None, 0.0), (35, 34, 1e-11)))])
 def test_panel_qr_dependent_columns_fp64(ff, m, c, bad):
     import torch
     announce(f"panel_qr dependent columns fp64 m={m} c={c}")
