@@ -166,6 +166,14 @@ ffsrqr_status ffsrqr_workspace_size(int64_t m, int64_t n, int64_t k, int64_t p,
  * g <= 1 or a NULL output (FFSRQR_EINVAL), all checked before anything is
  * enqueued.
  *   work   device workspace of work_bytes >= ffsrqr_workspace_size(...).
+ * A swap of Algorithm 4 (leading position i* out, trailing column j* in as
+ * the last leading column) updates the factorization in place: plane
+ * rotations restore the triangle of R11 after its column i* is removed and
+ * act on the columns of Q1 and the rows of W = Q1^T A; the new column of Q1
+ * comes from two Gram-Schmidt passes against the others, and the new row of
+ * W from one pass over A.  The LQ and the singular values are computed for
+ * the first leading set (concurrently with the first SRQR test) and, when
+ * swaps follow, once more for the final one.
  * The call returns after the stream has completed the solve.
  */
 ffsrqr_status ffsrqr_factor(const void* A, int64_t m, int64_t n, int64_t lda,
@@ -323,7 +331,8 @@ enum {
   FFSRQR_STEP_SRQR = 7,      /* selection, exact alpha, rho and g2            */
   FFSRQR_STEP_LQ = 8,        /* R^T assembly + Householder QR of R^T          */
   FFSRQR_STEP_SVD = 9,       /* one-sided Jacobi singular values of L         */
-  FFSRQR_NUM_STEPS = 10
+  FFSRQR_STEP_SWAP = 10,     /* one SRQR swap: update of Q, R11, W            */
+  FFSRQR_NUM_STEPS = 11
 };
 
 /* Enable (on != 0) or disable the accounting; either call resets it.

@@ -65,7 +65,7 @@ SIGNATURES = {
     "ffsrqr_profile_read": (C.c_int, [C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int]),
 }
 
-STEPS = ["omega", "sketch", "check", "qrcp", "panel", "project", "resid", "srqr", "lq", "svd"]
+STEPS = ["omega", "sketch", "check", "qrcp", "panel", "project", "resid", "srqr", "lq", "svd", "swap"]
 
 _lib = None
 

@@ -132,6 +132,7 @@ size_t scratch_bytes(int64_t m, int64_t n, int64_t l, const DeviceInfo& d) {
   s = std::max(s, align256(tallqr_scratch<T>(n, l, d)) + std::max(srqr_scratch<T>(m, n, l), jacobi_scratch<T>(l, d)));
   s = std::max(s, srqr_scratch<T>(m, n, l));
   s = std::max(s, jacobi_scratch<T>(l, d));
+  s = std::max(s, swap_scratch<T>(m, l));
   return s + 16 * 256;
 }
 
@@ -398,46 +399,91 @@ ffsrqr_status factor_impl(const T* A, int64_t m, int64_t n, int64_t lda, int64_t
   SrqrState hs{};
   double g2 = 1.0;
   int64_t numerical_rank = l;
-  for (;;) {
-    // a3: Householder QR of A(:, S); a4: projection and residual norms
-    tm.begin(FFSRQR_STEP_PANEL);
-    FF_HIP(build_perm(S, l, n, perm, inS, cnt, s));
-    FF_HIP(gather_cols<T>(A, m, n, lda, perm, l, region1, m, s));
-    {
-      Arena a = scratch();
-      FF_HIP(tall_qr<T>(region1, m, l, m, Q, ldq, R11, l, false, a, err, d, s));
+  // a6 and a7 for the current leading set: the LQ on the caller's stream;
+  // as soon as its cooperative kernel has written L, the Jacobi step on the
+  // side stream while the caller's stream forms Qhat1 (into a buffer of its
+  // own) and V.  Their scratch is carved after the LQ's.
+  Arena a_main = scratch();
+  Arena a_side{(char*)work, work_bytes, scratch_off + align256(tallqr_scratch<T>(n, l, d))};
+  auto issue_lq = [&]() -> ffsrqr_status {
+    const int lq_step = tm.begin(FFSRQR_STEP_LQ);
+    FF_HIP(assemble_rt<T>(R11, l, W, l, perm, l, n, region2, n, s));
+    Arena am = a_main;
+    FF_HIP(tall_qr<T>(region2, n, l, n, Qhat, n, L, ldl, true, am, err, d, s, side->fork));
+    FF_HIP(hipStreamWaitEvent(side->stream, side->fork, 0));
+    const int svd_step = tm.begin(FFSRQR_STEP_SVD, side->stream);
+    Arena a = a_side;
+    FF_HIP(jacobi_sigma<T>(L, l, ldl, sigma, a, err, d, side->stream, (int*)(err + 32)));
+    tm.end(svd_step, side->stream);
+    FF_HIP(hipEventRecord(side->join, side->stream));
+    FF_HIP(scatter_rows<T>(Qhat, n, l, n, perm, V, ldv, s));
+    tm.end(lq_step, s);
+    FF_HIP(hipStreamWaitEvent(s, side->join, 0));
+    return FFSRQR_OK;
+  };
+  // device-wide waits that ran out of their spin limit end the call
+  auto timed_out = [&]() -> ffsrqr_status {
+    if (info) {
+      std::memset(info, 0, sizeof(*info));
+      info->l = l;
+      info->flags = flags | FFSRQR_FLAG_TIMEOUT;
+      info->g2 = std::nan("");
+      info->alpha = std::nan("");
+      info->jstar = -1;
     }
-    tm.end();
-    {
-      Arena a = scratch();
-      tm.begin(FFSRQR_STEP_PROJECT);
-      if (mixed) {
-        // the panel in region1 is no longer read once Q is formed (stream order)
-        __bf16* qh = (__bf16*)region1;
-        __bf16* ql = qh + (size_t)mp * l;
-        FF_HIP(split_bf16((const float*)Q, m, l, ldq, qh, ql, mp, s));
-        FF_HIP(gemm_bf16(3, l, n, m, qh, ql, mp, (const float*)A, lda, (float*)W, l, nullptr, a, d.num_cu, s));
-      } else {
-        FF_HIP(gemm_tn<T>(l, n, m, Q, ldq, A, lda, W, l, nullptr, a, d.num_cu, s));
+    return fail(FFSRQR_EHIP, "a device-wide wait exceeded its spin limit; the outputs are incomplete");
+  };
+  bool lq_current = false;  // L, V, sigma belong to the current leading set
+  unsigned herr[64];
+  std::vector<int64_t> hS;
+  for (int iter = 0;; ++iter) {
+    if (iter == 0) {
+      // a3: Householder QR of A(:, S); a4: projection
+      tm.begin(FFSRQR_STEP_PANEL);
+      FF_HIP(build_perm(S, l, n, perm, inS, cnt, s));
+      FF_HIP(gather_cols<T>(A, m, n, lda, perm, l, region1, m, s));
+      {
+        Arena a = scratch();
+        FF_HIP(tall_qr<T>(region1, m, l, m, Q, ldq, R11, l, false, a, err, d, s));
       }
       tm.end();
+      {
+        Arena a = scratch();
+        tm.begin(FFSRQR_STEP_PROJECT);
+        if (mixed) {
+          // the panel in region1 is no longer read once Q is formed (stream order)
+          __bf16* qh = (__bf16*)region1;
+          __bf16* ql = qh + (size_t)mp * l;
+          FF_HIP(split_bf16((const float*)Q, m, l, ldq, qh, ql, mp, s));
+          FF_HIP(gemm_bf16(3, l, n, m, qh, ql, mp, (const float*)A, lda, (float*)W, l, nullptr, a, d.num_cu, s));
+        } else {
+          FF_HIP(gemm_tn<T>(l, n, m, Q, ldq, A, lda, W, l, nullptr, a, d.num_cu, s));
+        }
+        tm.end();
+      }
+    } else {
+      // Algorithm 4's swap as an update of Q, R11 and W (rotations, one new
+      // column, one pass over A for the new row); S was updated on the host
+      tm.begin(FFSRQR_STEP_SWAP);
+      {
+        Arena a = scratch();
+        FF_HIP(srqr_swap_update<T>(A, m, n, lda, Q, ldq, W, l, R11, l, l, hs.istar, hs.jstar, a, s));
+      }
+      FF_HIP(build_perm(S, l, n, perm, inS, cnt, s));
+      tm.end();
     }
-    // From here two streams: the side stream runs the SRQR test (a4's
-    // residual norms and a5), then a7 once L exists; the caller's stream
-    // runs a6 (issued before the swap decision is known; redone after a
-    // swap).  They read W and R11 concurrently and write disjoint buffers;
-    // the side stream's scratch is carved after the LQ's.
+    // The side stream runs a4's residual norms and the SRQR test (a5); in
+    // the first test the caller's stream runs a6 meanwhile (issued before the
+    // swap decision is known: it is the result unless a swap follows).  They
+    // read W and R11 concurrently and write disjoint buffers.
     FF_HIP(hipEventRecord(side->fork, s));
     FF_HIP(hipStreamWaitEvent(side->stream, side->fork, 0));
-    Arena a_main = scratch();
-    Arena a_side{(char*)work, work_bytes, scratch_off + align256(tallqr_scratch<T>(n, l, d))};
     {
       const int h = tm.begin(FFSRQR_STEP_RESID, side->stream);
       FF_HIP(residual_norms<T>(W, l, n, l, anorm2, gamma2, side->stream));
       tm.end(h, side->stream);
     }
     {
-      // a5: SRQR test
       const int h = tm.begin(FFSRQR_STEP_SRQR, side->stream);
       Arena a = a_side;
       FF_HIP(srqr_select<T>(gamma2, anorm2, inS, n, A, m, lda, Q, ldq, W, l, R11, l, l, st, a, side->stream,
@@ -448,40 +494,20 @@ ffsrqr_status factor_impl(const T* A, int64_t m, int64_t n, int64_t lda, int64_t
       }
       tm.end(h, side->stream);
     }
-    const int lq_step = tm.begin(FFSRQR_STEP_LQ);
-    FF_HIP(assemble_rt<T>(R11, l, W, l, perm, l, n, region2, n, s));
-    {
-      // Qhat1 (n x l) in natural row order, then V = Pi Qhat1 by a row
-      // scatter.  As soon as L is written, a7 (Jacobi on L) runs on the side
-      // stream while Qhat1 is formed.
-      FF_HIP(tall_qr<T>(region2, n, l, n, Qhat, n, L, ldl, true, a_main, err, d, s, side->fork));
-      FF_HIP(hipStreamWaitEvent(side->stream, side->fork, 0));
-      const int svd_step = tm.begin(FFSRQR_STEP_SVD, side->stream);
-      Arena a = a_side;
-      FF_HIP(jacobi_sigma<T>(L, l, ldl, sigma, a, err, d, side->stream, (int*)(err + 32)));
-      tm.end(svd_step, side->stream);
+    if (iter == 0) {
+      const ffsrqr_status lst = issue_lq();  // joins the side stream
+      if (lst != FFSRQR_OK) return lst;
+      lq_current = true;
+    } else {
       FF_HIP(hipEventRecord(side->join, side->stream));
-      FF_HIP(scatter_rows<T>(Qhat, n, l, n, perm, V, ldv, s));
+      FF_HIP(hipStreamWaitEvent(s, side->join, 0));
+      lq_current = false;
     }
-    tm.end(lq_step, s);
-    FF_HIP(hipStreamWaitEvent(s, side->join, 0));
-    unsigned herr[64];
     FF_HIP(hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, s));
     FF_HIP(hipMemcpyAsync(herr, err, sizeof(herr), hipMemcpyDeviceToHost, s));
     FF_HIP(hipStreamSynchronize(s));
-    jacobi_sweeps = (int32_t)herr[32];
-    if (herr[0]) {
-      // the outputs are incomplete; info says which condition ended the call
-      if (info) {
-        std::memset(info, 0, sizeof(*info));
-        info->l = l;
-        info->flags = flags | FFSRQR_FLAG_TIMEOUT;
-        info->g2 = std::nan("");
-        info->alpha = std::nan("");
-        info->jstar = -1;
-      }
-      return fail(FFSRQR_EHIP, "a device-wide wait exceeded its spin limit; the outputs are incomplete");
-    }
+    if (herr[0]) return timed_out();
+    if (lq_current) jacobi_sweeps = (int32_t)herr[32];
     if (l >= n) {
       g2 = 1.0;
       hs.jstar = -1;
@@ -506,14 +532,25 @@ ffsrqr_status factor_impl(const T* A, int64_t m, int64_t n, int64_t lda, int64_t
       break;
     }
     // round-robin swap: S <- (S without S[istar]) followed by jstar
-    std::vector<int64_t> hS((size_t)l);
-    FF_HIP(hipMemcpy(hS.data(), perm, (size_t)l * sizeof(int64_t), hipMemcpyDeviceToHost));
     if (hs.istar < 0 || hs.istar >= l || hs.jstar < 0 || hs.jstar >= n)
       return fail(FFSRQR_EHIP, "invalid swap candidates");
+    if (hS.empty()) {
+      hS.resize((size_t)l);
+      FF_HIP(hipMemcpy(hS.data(), S, (size_t)l * sizeof(int64_t), hipMemcpyDeviceToHost));
+    }
     hS.erase(hS.begin() + hs.istar);
     hS.push_back(hs.jstar);
     FF_HIP(hipMemcpyAsync(S, hS.data(), (size_t)l * sizeof(int64_t), hipMemcpyHostToDevice, s));
     ++swaps;
+  }
+  if (!lq_current) {
+    // the leading set changed after the first LQ: a6 and a7 once more
+    const ffsrqr_status lst = issue_lq();
+    if (lst != FFSRQR_OK) return lst;
+    FF_HIP(hipMemcpyAsync(herr, err, sizeof(herr), hipMemcpyDeviceToHost, s));
+    FF_HIP(hipStreamSynchronize(s));
+    if (herr[0]) return timed_out();
+    jacobi_sweeps = (int32_t)herr[32];
   }
   tm.collect();
   if (info) {
@@ -583,6 +620,7 @@ size_t alg9_scratch(int64_t m, int64_t n, int64_t l, int64_t k, const DeviceInfo
   s = std::max(s, gemm_tn_scratch<T>(k, n, l, d.num_cu));
   s = std::max(s, tallqr_scratch<T>(m, l, d));
   s = std::max(s, jacobi_scratch<T>(l, d));
+  s = std::max(s, swap_scratch<T>(m, l));
   return s + 16 * 256;
 }
 

@@ -140,6 +140,16 @@ template <typename T>
 hipError_t srqr_rho(const T* R11, int64_t ldr, const T* a, int64_t a_stride, const SrqrState* sel,
                     double alpha_host, int64_t l, double* rho, SrqrState* st_out, Arena& ar, hipStream_t s);
 
+// One swap of Algorithm 4 as an update in place of A(:, S) = Q R11 and
+// W = Q^T A: leading position istar leaves, trailing column jstar becomes
+// the last leading column (rotations on R11, W and Q, one new column of Q by
+// two Gram-Schmidt passes, one new row of W by a pass over A).
+template <typename T>
+size_t swap_scratch(int64_t m, int64_t l);
+template <typename T>
+hipError_t srqr_swap_update(const T* A, int64_t m, int64_t n, int64_t lda, T* Q, int64_t ldq, T* W, int64_t ldw,
+                            T* R11, int64_t ldr, int64_t l, int64_t istar, int64_t jstar, Arena& ar, hipStream_t s);
+
 // Singular values of L (l x l) by block one-sided Jacobi (FP64).
 template <typename T>
 size_t jacobi_scratch(int64_t l, const DeviceInfo& d);

@@ -177,6 +177,74 @@ def test_swap_cap_fp32(ff):
     assert out.info["flags"] & 2
 
 
+def slow_decay(m, n, seed, decay):
+    """U diag(decay^j) V^T with U, V from the QR of seeded Gaussians: a
+    spectrum flat enough that with g just above 1 nearly every SRQR test
+    asks for a swap."""
+    rng = np.random.default_rng(seed)
+    U, _ = np.linalg.qr(rng.standard_normal((m, n)))
+    V, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    return (U * decay ** np.arange(n)) @ V.T
+
+
+@pytest.mark.parametrize("form", ["fp64", "fp32", "mixed"])
+@pytest.mark.parametrize("case", [(600, 300, 30, 6, 0.97, 6), (400, 200, 40, 0, 0.99, 6), (500, 260, 20, 4, 0.9, 6)])
+def test_forced_swaps(ff, form, case):
+    """Several swaps in a row, each an in-place update of Q, R11 and W
+    (rotations, a new column, a pass over A), against the oracle, which
+    factors every new leading set from scratch: the same swaps and
+    pivots, and the final factors within the form's bound."""
+    import torch
+    m, n, k, p, decay, cap = case
+    announce(f"factor forced swaps {form} {m}x{n} k={k} p={p} decay={decay} max_swaps={cap}")
+    A = slow_decay(m, n, 11, decay)
+    if form == "fp64":
+        out, ref = compare(ff, A, k, p, 0, g=1.0 + 1e-6, max_swaps=cap)
+    else:
+        out, ref = compare(ff, A, k, p, 0, g=1.0 + 1e-6, max_swaps=cap, dtype=torch.float32, tol=FP32_TOL,
+                           margin_floor=1e-5, mixed=form == "mixed")
+    print(f"[gpu-case] swaps oracle {ref.swaps} gpu {out.info['swaps']}", flush=True)
+    assert ref.swaps >= 2
+    assert out.info["swaps"] == ref.swaps
+
+
+def test_swap_update_matches_fresh_qr_mid(ff):
+    """At the mid workload's size (16384 x 8192, l = 272): two forced swaps;
+    the updated Q must equal the Householder QR of the final leading set
+    A(:, perm[:l]) computed from scratch (the thin QR with a positive
+    diagonal is unique; the difference is bounded by the conditioning of
+    A(:, S) times the rounding of either side), and the per-swap device time
+    is reported."""
+    import torch
+    w = synth.WORKLOADS["mid"]
+    announce("factor mid fp64 with two forced swaps vs a fresh QR of the final set")
+    A = dev_f(synth.make_workload("mid"))
+    ff.profile_enable(True)
+    try:
+        out = ff.factor(A, w.k, w.p, w.seed, g=1.0 + 1e-9, max_swaps=2)
+        torch.cuda.synchronize()
+        prof = ff.profile_read()
+    finally:
+        ff.profile_enable(False)
+    info = out.info
+    assert info["swaps"] == 2 and info["flags"] & 2
+    ms, cnt = prof["swap"]
+    assert cnt == 2
+    print(f"[gpu-case] swap update: {1000.0 * ms / cnt:.1f} us per swap "
+          f"(panel {prof['panel'][0]:.3f} ms, projection {prof['project'][0]:.3f} ms once)", flush=True)
+    l = info["l"]
+    cols = out.perm[:l].clone()
+    Qf, Rf = ff.panel_qr(A, cols)
+    Qu = host(out.Q)
+    Qfh = host(Qf)
+    S = host(A)[:, host(cols)]
+    kappa = np.linalg.cond(S)
+    d = np.abs(Qu - Qfh).max()
+    print(f"[gpu-case] cond(A(:, S)) {kappa:.3e}, max |Q_update - Q_fresh| {d:.3e}", flush=True)
+    assert d <= 1e-13 * kappa * np.sqrt(l)
+    assert np.linalg.norm(Qu.T @ Qu - np.eye(l)) < 1e-12
+
+
 # Mixed form against the oracle in its bf16 sketch mode on the same FP32
 # bytes: the sample matrices differ only by the FP32 summation of the GPU
 # (relative about sqrt(m) 2^-24), so pivots are compared where the QRCP
