@@ -305,7 +305,7 @@ ffsrqr_status ffsrqr_alg9_svd(const void* A, int64_t m, int64_t n, int64_t lda, 
  * device memory (code under HIP graph capture, serving loops, harnesses
  * that forbid allocation): the same kernels and results as
  * ffsrqr_svd_small, with their scratch in a static device array of the
- * library (about 8.4 MB per GPU, held until the process ends; the call
+ * library (about 12.6 MB per GPU, held until the process ends; the call
  * itself allocates nothing).  l <= 1024, else FFSRQR_EINVAL.  Every call on
  * one GPU shares that GPU's array: calls that overlap on one GPU (other
  * streams, other host threads) race and must be serialised by the caller.

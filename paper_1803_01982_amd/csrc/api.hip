@@ -211,7 +211,7 @@ ffsrqr_status get_side(int id, SideStream** out) {
 // hipGetSymbolAddress and passes that pointer.
 constexpr int64_t kNoAllocMaxL = 1024;
 constexpr size_t kNoAllocBytes =
-    sizeof(double) * ((size_t)kNoAllocMaxL * kNoAllocMaxL + kNoAllocMaxL + (size_t)kMaxGridBlocks * 32 * 32) +
+    sizeof(double) * ((size_t)kNoAllocMaxL * kNoAllocMaxL + kNoAllocMaxL + (size_t)2 * kMaxGridBlocks * 32 * 32) +
     (kSyncWords + 64) * sizeof(unsigned) + 64 * sizeof(unsigned) + 16 * 256;
 __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
 

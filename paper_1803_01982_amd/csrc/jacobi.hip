@@ -45,6 +45,56 @@ __device__ inline int rr_player(int pos, int r, int P) {
   // circle method: position 0 fixed, positions 1..P-1 rotate by r
   return pos == 0 ? 0 : ((pos - 1 + r) % (P - 1)) + 1;
 }
+// The block pair that holds block x in round r (pair g holds positions g
+// and P - 1 - g).
+__device__ inline int rr_pair_of(int x, int r, int P) {
+  const int pos = x == 0 ? 0 : ((x - 1 - r) % (P - 1) + (P - 1)) % (P - 1) + 1;
+  return pos < P / 2 ? pos : P - 1 - pos;
+}
+
+// Barrier over part of the grid: this workgroup posts its flag (the count
+// of barriers passed, which advances identically in every workgroup, so the
+// flags of grid_barrier serve here too) and waits only for the workgroups
+// in [a0, a0 + na) and [a1, a1 + nb), the ones whose writes it reads next.
+// The same release/acquire fences and bounded wait as grid_barrier.
+__device__ inline bool subset_barrier(const GridSync& gs, unsigned& epoch, int a0, int na, int a1, int nb) {
+  __shared__ int s_ok;
+  __syncthreads();
+  ++epoch;
+  if (gs.nblocks == 1) return true;
+  if (threadIdx.x < kWave) {
+    if (threadIdx.x == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __hip_atomic_store(gs.sync + kFlagStride * blockIdx.x, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    int ok = 1;
+    unsigned spins = 0;
+    const int nt = na + nb;
+    for (;;) {
+      bool here = true;
+      for (int t = threadIdx.x; t < nt; t += kWave) {
+        const int q = t < na ? a0 + t : a1 + (t - na);
+        here = here && __hip_atomic_load(gs.sync + kFlagStride * q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= epoch;
+      }
+      if (__all(here)) break;
+      __builtin_amdgcn_s_sleep(1);
+      if ((++spins & 255u) == 0) {
+        const bool bad = __hip_atomic_load(gs.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
+        if (__any(bad) || spins > kSpinLimit) {
+          if (threadIdx.x == 0) __hip_atomic_fetch_or(gs.error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ok = 0;
+          break;
+        }
+      }
+    }
+    if (threadIdx.x == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      s_ok = ok;
+    }
+  }
+  __syncthreads();
+  return s_ok != 0;
+}
 
 // Entry (i, j) of R^T H R when column k of R holds alpha_k at row k and
 // beta_k at the row of its partner: ai, bi and aj, bj for columns i and j,
@@ -97,9 +147,15 @@ __device__ inline void jacobi_rotation(double a, double b, double h, double& cs,
 // of the row quarters 1..3 (3 x 3 x 256).  When the l rows of a block pair do
 // not fit the LDS of one workgroup, rg workgroups share the pair, each with
 // ch rows: each computes the Gram matrix of its rows, the partial Gram
-// matrices are exchanged through xbuf (one more grid barrier per round) and
-// summed in a fixed order, so every workgroup of the pair takes the same
-// rotations and applies them to its own rows.
+// matrices are exchanged through xbuf (two buffers by round parity; a
+// barrier among the rg workgroups of the pair only) and summed in a fixed
+// order, so every workgroup of the pair takes the same rotations and
+// applies them to its own rows.
+//
+// Between rounds a workgroup waits only for the workgroups that wrote the
+// two blocks it takes next (the pairs that held them in the round just
+// ended), not for the whole grid; every sweep ends at a grid barrier, where
+// the decision to go on is taken.
 //
 // With vectors (lpad > 0), M holds ldm = lpad + l rows: L in rows 0..l-1,
 // zeros up to lpad (a multiple of ch) and the identity in rows lpad ..
@@ -274,11 +330,12 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(const T* __restrict__ L, int
         // grid barrier, and every workgroup sums all of them in the same
         // order (its own read back from memory like the others)
         __syncthreads();
-        for (int e = tid; e < GW * GW; e += NT) xbuf[(int64_t)g * GW * GW + e] = H0[(e / GW) * GS + e % GW];
-        if (!grid_barrier(gs, epoch)) return;
+        double* xb = xbuf + (int64_t)(r & 1) * G * GW * GW;
+        for (int e = tid; e < GW * GW; e += NT) xb[(int64_t)g * GW * GW + e] = H0[(e / GW) * GS + e % GW];
+        if (!subset_barrier(gs, epoch, pair * rg, rg, 0, 0)) return;
         for (int e = tid; e < GW * GW; e += NT) {
           double v = 0.0;
-          for (int h = 0; h < rg; ++h) v += xbuf[((int64_t)pair * rg + h) * GW * GW + e];
+          for (int h = 0; h < rg; ++h) v += xb[((int64_t)pair * rg + h) * GW * GW + e];
           H0[(e / GW) * GS + e % GW] = v;
         }
       }
@@ -462,7 +519,14 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(const T* __restrict__ L, int
           }
         }
       }
-      if (!grid_barrier(gs, epoch)) return;
+      if (r + 1 < P - 1) {
+        // the next round's blocks: wait only for the workgroups that wrote
+        // them in this round (the sweep's last round ends at the grid
+        // barrier below instead)
+        const int qa = rr_pair_of(rr_player(pair, r + 1, P), r, P);
+        const int qb = rr_pair_of(rr_player(P - 1 - pair, r + 1, P), r, P);
+        if (!subset_barrier(gs, epoch, qa * rg, rg, qb * rg, rg)) return;
+      }
     }
     if (tid == 0 && s_sweep) __hip_atomic_fetch_or(&rot[sweep % 3], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (!grid_barrier(gs, epoch)) return;
@@ -568,9 +632,10 @@ void vec_rows(int64_t l, int ch, int* lpad, int* ldm, int* rg) {
 template <typename T>
 size_t jacobi_scratch(int64_t l, const DeviceInfo& d) {
   // the stacked M of the vector form (at most (2 l + 416) x l), sigma, the
-  // partial-Gram exchange (at most kMaxGridBlocks workgroups of GW x GW) and
+  // partial-Gram exchange (two buffers of at most kMaxGridBlocks workgroups
+  // of GW x GW) and
   // the barrier flags
-  return sizeof(double) * ((size_t)(2 * l + 432) * l + l + (size_t)kMaxGridBlocks * GW * GW) +
+  return sizeof(double) * ((size_t)(2 * l + 432) * l + l + (size_t)2 * kMaxGridBlocks * GW * GW) +
          (kSyncWords + 64) * sizeof(unsigned) + 8 * 256;
 }
 
@@ -588,7 +653,7 @@ hipError_t jacobi_launch(const T* L, int64_t l, int64_t ldl, bool vectors, doubl
   if (nwg > kMaxGridBlocks) return hipErrorInvalidValue;
   double* M = ar.take<double>((size_t)ldm * l);
   double* sig = ar.take<double>(l);
-  double* xbuf = ar.take<double>((size_t)nwg * GW * GW);
+  double* xbuf = ar.take<double>((size_t)2 * nwg * GW * GW);
   unsigned* ctl = ar.take<unsigned>(kSyncWords + 64);
   if (!M || !sig || !xbuf || !ctl) return hipErrorOutOfMemory;
   hipError_t e = zero_words(ctl, kSyncWords + 64, s);
