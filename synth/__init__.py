@@ -22,6 +22,8 @@ Recipes (all seeded, FP64 arithmetic, optionally rounded to FP32 storage):
     (l = 544), sketch seed 0; meant for FP32 storage.
   - ``large_q``     : the same spectrum and k, p at a quarter of the size
     (8192 x 4096), small enough for the oracle to run whole.
+  - ``large_s``     : the same at an eighth of the size (4096 x 2048), the
+    bounded sample on which the benchmark times the oracle.
 """
 from __future__ import annotations
 
@@ -124,6 +126,7 @@ WORKLOADS = {
     "mid": Workload("mid", 16384, 8192, 256, 16, 0, 2, "exp50_r1024", 1e-6),
     "large": Workload("large", 32768, 16384, 512, 32, 0, 3, "flat8_decade3_r1024", 1e-5),
     "large_q": Workload("large_q", 8192, 4096, 512, 32, 0, 3, "flat8_decade3_r1024", 1e-5),
+    "large_s": Workload("large_s", 4096, 2048, 512, 32, 0, 3, "flat8_decade3_r1024", 1e-5),
 }
 
 
