@@ -22,10 +22,14 @@
 // only ever see orthogonal transformations.  A pair is rotated when
 // |h_pq| > tol sqrt(h_pp h_qq) (tol = 1e-14), with Rutishauser's formulas.
 // The iteration stops after a sweep with no rotation, or after a sweep in
-// which every rotated pair had |h_pq| <= 1e-8 sqrt(h_pp h_qq): in that
-// (quadratically convergent) regime the sweep leaves off-diagonal mass of
-// order 1e-16 relative, far below what a further sweep could change in the
-// singular values (at most 60 sweeps).  sigma_j = ||c_j||, sorted descending.
+// which every rotated pair had |h_pq| <= s sqrt(h_pp h_qq) (at most 60
+// sweeps).  In that quadratically convergent regime the cosines left after
+// the sweep are of order s^2 times a modest factor (about 50 at l = 544),
+// and sigma_j = ||c_j|| (sorted descending) is off by at most that much,
+// relatively.  s = 1e-8 (leftover of order 1e-16) for FP64 data and for the
+// vector form; for FP32 data without vectors s = 1e-4, whose leftover (of
+// order 1e-7) lies below the rounding already carried by L's FP32 entries:
+// the sweep after it could not change sigma beyond that rounding.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -38,7 +42,8 @@ constexpr int NW = NT / kWave;
 constexpr int GW = 32;  // order of the Gram and rotation arrays (2 bs <= GW)
 constexpr int GS = 40;  // their row stride in LDS (rows land 16 banks apart)
 constexpr double kTol = 1e-14;
-constexpr double kSettled = 1e-8;  // a sweep with no larger rotation ends the iteration
+constexpr double kSettled = 1e-8;    // a sweep with no larger rotation ends the iteration
+constexpr double kSettled32 = 1e-4;  // the same for FP32 data, singular values only
 constexpr int kMaxSweeps = 60;
 
 __device__ inline int rr_player(int pos, int r, int P) {
@@ -168,7 +173,7 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(const T* __restrict__ L, int
                                                     int ldm, int lpad, int bs, int P, int ldc, int ncol, int ch,
                                                     int rg, double* __restrict__ xbuf, unsigned* __restrict__ rot,
                                                     double* __restrict__ sig, int* __restrict__ sweeps_out,
-                                                    GridSync gs) {
+                                                    double settled, GridSync gs) {
   typedef Mfma<double> MF;
   extern __shared__ double smem[];
   double* C = smem;
@@ -178,7 +183,7 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(const T* __restrict__ L, int
   double* Pg = J0 + GW * GS;
   __shared__ double2 s_ab[2][GW];  // (alpha, beta) of column k: c_k <- alpha c_k + beta c_partner
   __shared__ double s_dn[2][GW];   // the diagonal entry of H for column k after the rotation
-  __shared__ int s_sweep;  // a pair with |h_pq| > kSettled sqrt(h_pp h_qq) was rotated this sweep
+  __shared__ int s_sweep;  // a pair with |h_pq| > settled sqrt(h_pp h_qq) was rotated this sweep
   __shared__ int s_round;
   __shared__ unsigned short sched_full[31 * 16];
   __shared__ unsigned char part_full[31 * GW];
@@ -382,7 +387,7 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(const T* __restrict__ L, int
           s_dn[buf][q] = b + tt * hg;
           if (!skip) {
             rot_acc = 1;
-            if (hg * hg > (kSettled * kSettled) * (a * b)) big_acc = 1;
+            if (hg * hg > (settled * settled) * (a * b)) big_acc = 1;
           }
         }
       };
@@ -531,7 +536,7 @@ __global__ __launch_bounds__(NT) void jacobi_kernel(const T* __restrict__ L, int
     if (tid == 0 && s_sweep) __hip_atomic_fetch_or(&rot[sweep % 3], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (!grid_barrier(gs, epoch)) return;
     const unsigned big = __hip_atomic_load(&rot[sweep % 3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (!big) break;  // no rotation, or only rotations below kSettled
+    if (!big) break;  // no rotation, or only rotations below the settled level
   }
   if (g == 0 && tid == 0 && sweeps_out) *sweeps_out = sweep < kMaxSweeps ? sweep + 1 : kMaxSweeps;
   // column norms
@@ -661,9 +666,10 @@ hipError_t jacobi_launch(const T* L, int64_t l, int64_t ldl, bool vectors, doubl
   GridSync gs{ctl, err, (unsigned)nwg};
   unsigned* rot = ctl + kSyncWords;
   int li = (int)l;
+  double settled = (vectors || sizeof(T) == 8) ? kSettled : kSettled32;
   void* args[] = {(void*)&L,    (void*)&li,  (void*)&ldl,  (void*)&M,   (void*)&ldm,  (void*)&lpad,
                   (void*)&bs,   (void*)&P,   (void*)&ldc,  (void*)&ncol, (void*)&ch,  (void*)&rg,
-                  (void*)&xbuf, (void*)&rot, (void*)&sig,  (void*)&sweeps, (void*)&gs};
+                  (void*)&xbuf, (void*)&rot, (void*)&sig,  (void*)&sweeps, (void*)&settled, (void*)&gs};
   const void* fn = rg > 1 ? (const void*)jacobi_kernel<T, true> : (const void*)jacobi_kernel<T, false>;
   if (lds > 65536) {
     e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

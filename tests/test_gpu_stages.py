@@ -298,6 +298,38 @@ def test_svd_small_row_split_fp64(ff, l):
           flush=True)
     assert np.all(np.abs(sig - ref) <= rel_tol * ref)
 
+# FP32 data: the iteration stops after a sweep whose rotations all had
+# cosines <= 1e-4; the singular values then differ from the oracle's (Jacobi
+# run until nothing rotates, on the same FP32 values, in FP64) by second-order
+# terms.  Well-conditioned factors (kappa_s small), where relative
+# differences are meaningful: "diag", a dominant decaying diagonal under a
+# small random lower triangle, and "cluster", eight equal singular values
+# then a decay, through the LQ of U diag(s) V^T (the shape of the flip-flop
+# factor).  The FP32 forms' tolerance is 1e-4; the bound here is 1e-6.
+@pytest.mark.parametrize("l,kind", [(272, "diag"), (544, "diag"), (544, "cluster"), (64, "cluster")])
+def test_svd_small_fp32_stop(ff, l, kind):
+    import torch
+    announce(f"svd_small fp32 l={l} kind={kind}")
+    rng = np.random.default_rng(l + 7)
+    if kind == "diag":
+        M = np.tril(rng.standard_normal((l, l))) * 0.02 + np.diag(np.linspace(1.0, 0.01, l))
+    else:
+        j = np.arange(1, l + 1)
+        s = np.where(j <= 8, 1.0, 10.0 ** (-3.0 * (j - 8) / 1000.0))
+        U, _ = np.linalg.qr(rng.standard_normal((l, l)))
+        V, _ = np.linalg.qr(rng.standard_normal((2 * l, l)))
+        X = (U * s) @ V.T
+        M = np.linalg.qr(X.T, mode="r").T
+    M32 = M.astype(np.float32)
+    sig = host(ff.svd_small(dev_f(M32, torch.float32)))
+    ref, _ = oracle.jacobi_svd(M32.astype(np.float64))
+    nrm = np.linalg.norm(M32.astype(np.float64), axis=0)
+    kappa_s = np.linalg.cond(M32 / nrm)
+    worst = np.max(np.abs(sig - ref) / ref)
+    print(f"[gpu-case] kappa_s {kappa_s:.2e}, worst relative difference {worst:.2e}", flush=True)
+    assert worst < 1e-6
+
+
 @pytest.mark.parametrize("l,kind", [(30, "qlp"), (2, "gauss"), (31, "gauss"), (100, "graded"), (272, "qlp"),
                                     (16, "rankdef"), (544, "qlp")])
 def test_svd_small_fp64(ff, l, kind):
