@@ -24,6 +24,9 @@ Recipes (all seeded, FP64 arithmetic, optionally rounded to FP32 storage):
     (8192 x 4096), small enough for the oracle to run whole.
   - ``large_s``     : the same at an eighth of the size (4096 x 2048), the
     bounded sample on which the benchmark times the oracle.
+* ``tucker_tensor``: a Tucker tensor (N(0,1) core times orthonormal
+  factors) plus Gaussian noise, for the ST-HOSVD driver; the 400^3 tensor
+  of core 40^3 and noise 1e-3 stands for the tensor workload.
 """
 from __future__ import annotations
 
@@ -37,6 +40,7 @@ __all__ = [
     "separated_columns_matrix",
     "random_matrix",
     "make_workload",
+    "tucker_tensor",
 ]
 
 
@@ -128,6 +132,20 @@ WORKLOADS = {
     "large_q": Workload("large_q", 8192, 4096, 512, 32, 0, 3, "flat8_decade3_r1024", 1e-5),
     "large_s": Workload("large_s", 4096, 2048, 512, 32, 0, 3, "flat8_decade3_r1024", 1e-5),
 }
+
+
+def tucker_tensor(dims, ranks, seed: int, noise: float = 0.0, dtype=np.float64) -> np.ndarray:
+    """X = G x_1 U_1 x_2 U_2 ... + noise*E: a core G (ranks, i.i.d. N(0,1))
+    times orthonormal factors U_j (dims[j] x ranks[j]), plus i.i.d. Gaussian
+    noise; Fortran order (the first index runs fastest)."""
+    d = len(dims)
+    X = _rng(seed, 10).standard_normal(tuple(ranks))
+    for j in range(d):
+        U = _orthonormal(dims[j], ranks[j], _rng(seed, 11 + j))
+        X = np.moveaxis(np.tensordot(U, X, axes=([1], [j])), 0, j)
+    if noise:
+        X = X + noise * _rng(seed, 20).standard_normal(tuple(dims))
+    return np.asfortranarray(X.astype(dtype, copy=False))
 
 
 def make_workload(name: str, dtype=np.float64) -> np.ndarray:
