@@ -301,6 +301,40 @@ ffsrqr_status ffsrqr_alg9_svd(const void* A, int64_t m, int64_t n, int64_t lda, 
                               ffsrqr_stream_t stream);
 
 /*
+ * ST-HOSVD with Flip-Flop SRQR as the rank-k SVD (Section 2, tensor
+ * notation and the ST-HOSVD algorithm; Section 4, the tensor experiment).
+ *   X      tensor of order d (1 <= d <= 8) with dimensions dims[0:d] (host
+ *          array), Fortran order (the first index runs fastest), element
+ *          type of opts->precision (FFSRQR_MIXED: float).  Read-only.
+ *   ranks  host array, 1 <= ranks[j] <= dims[j]: the Tucker rank.
+ *   order  host array, the processing order (a permutation of 0..d-1), or
+ *          NULL for 0, 1, .., d-1.
+ *   p, seed  oversampling and Omega key of every mode's factorization.
+ * For each mode r in the processing order: the mode-r unfolding G_(r) of the
+ * current tensor (n_r rows; column c = the Fortran-order linear index of
+ * the other indices in order) is factored by ffsrqr_factor's path (target
+ * rank ranks[r], oversampling p, the options in opts) and completed by
+ * Algorithm 9 to G_(r) ~ U_r Sigma V^T; U_r is written to U[r]
+ * (dims[r] x ranks[r], ldu[r] >= dims[r]; U and ldu are host arrays of
+ * device pointers and leading dimensions), and the tensor is reduced to
+ * G_(r) <- U_r^T G_(r) (the mode-r product with U_r^T).  core receives the
+ * final tensor (ranks[0] x .. x ranks[d-1], Fortran order), so that
+ * X ~ core x_1 U_0 x_2 U_1 .. x_d U_{d-1}.
+ * Errors: FFSRQR_EINVAL for an order outside 1..8, a rank outside
+ * 1..dims[j], an order that is not a permutation, a NULL pointer, or a step
+ * whose unfolding breaks the limits of ffsrqr_workspace_size (its message
+ * names the mode); the workspace comes from ffsrqr_st_hosvd_workspace_size.
+ * The call returns after the stream has completed.
+ */
+ffsrqr_status ffsrqr_st_hosvd_workspace_size(int32_t d, const int64_t* dims, const int64_t* ranks,
+                                             const int32_t* order, int64_t p, const ffsrqr_opts* opts,
+                                             size_t* bytes);
+ffsrqr_status ffsrqr_st_hosvd(const void* X, int32_t d, const int64_t* dims, const int64_t* ranks,
+                              const int32_t* order, int64_t p, uint64_t seed, void* core, void* const* U,
+                              const int64_t* ldu, void* work, size_t work_bytes, const ffsrqr_opts* opts,
+                              ffsrqr_stream_t stream);
+
+/*
  * ffsrqr_svd_small without a workspace, for callers that cannot allocate
  * device memory (code under HIP graph capture, serving loops, harnesses
  * that forbid allocation): the same kernels and results as

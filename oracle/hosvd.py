@@ -13,9 +13,11 @@ Conventions (the paper's definitions, written out):
   * The mode-n product Y = X x_n U (U k x I_n) sums x over i_n against
     u_{j, i_n}; equivalently Y_(n) = U X_(n) (the identity the paper states).
   * ST-HOSVD: G <- X; for each mode r in the processing order, a rank-k_r
-    approximate SVD of G_(r) ~ U Sigma V^T, U_r <- U, and G_(r) <- U_r^T G_(r)
-    ("applying U_r^T to G").  The rank-k_r SVD is Flip-Flop SRQR with
-    oversampling p followed by Algorithm 9's completion (ffsrqr, alg9).
+    approximate SVD of G_(r) ~ U Sigma V^T, U_r <- U, and G_(r) <- U_r^T G_(r),
+    the mode-r product with U_r^T (the paper equates this with
+    Sigma V^T, which holds for an exact SVD only).  The rank-k_r SVD is
+    Flip-Flop SRQR with oversampling p followed by Algorithm 9's completion
+    (ffsrqr, alg9).
 """
 from __future__ import annotations
 

@@ -61,6 +61,10 @@ SIGNATURES = {
     "ffsrqr_alg9_workspace_size": (C.c_int, [_I64, _I64, _I64, _I64, _I32, C.POINTER(_SZ)]),
     "ffsrqr_alg9_svd": (C.c_int, [_P, _I64, _I64, _I64, _P, _I64, _I64, _I64, _P, _I64, _P, _P, _I64, _P, _SZ,
                                   _I32, _P]),
+    "ffsrqr_st_hosvd_workspace_size": (C.c_int, [_I32, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I32), _I64,
+                                                 C.POINTER(Opts), C.POINTER(_SZ)]),
+    "ffsrqr_st_hosvd": (C.c_int, [_P, _I32, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I32), _I64, _U64, _P,
+                                  C.POINTER(_P), C.POINTER(_I64), _P, _SZ, C.POINTER(Opts), _P]),
     "ffsrqr_profile_enable": (None, [C.c_int]),
     "ffsrqr_profile_read": (C.c_int, [C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int]),
 }

@@ -260,6 +260,57 @@ def alg9_svd(A: torch.Tensor, V: torch.Tensor, k: int, work=None, stream=None, m
     return Alg9Result(U, sigma, Vk)
 
 
+def fortran_nd(t: torch.Tensor) -> torch.Tensor:
+    """Fortran-order copy (the first index runs fastest) of a tensor."""
+    rev = tuple(range(t.dim() - 1, -1, -1))
+    return t.permute(rev).contiguous().permute(rev)
+
+
+def empty_fortran_nd(shape, dtype, device) -> torch.Tensor:
+    rev = tuple(range(len(shape) - 1, -1, -1))
+    return torch.empty(tuple(shape[::-1]), dtype=dtype, device=device).permute(rev)
+
+
+@dataclasses.dataclass
+class TuckerResult:
+    core: torch.Tensor    # ranks[0] x .. x ranks[d-1], Fortran order
+    U: list               # U[n]: dims[n] x ranks[n], column-major
+
+
+def st_hosvd(X: torch.Tensor, ranks, p: int, seed: int = 0, order=None, mixed: bool = False, work=None,
+             stream=None) -> TuckerResult:
+    """ffsrqr_st_hosvd: Tucker decomposition X ~ core x_1 U[0] .. x_d U[d-1]
+    by ST-HOSVD with Flip-Flop SRQR (plus Algorithm 9) as each mode's rank-k
+    SVD.  X must be in Fortran order (fortran_nd)."""
+    lib = L.load()
+    d = X.dim()
+    dims = [int(x) for x in X.shape]
+    step = 1
+    for j in range(d):
+        if X.stride(j) != step and dims[j] > 1:
+            raise ValueError("expected a Fortran-order tensor; use fortran_nd()")
+        step *= dims[j]
+    ranks = [int(r) for r in ranks]
+    if len(ranks) != d:
+        raise ValueError("one rank per mode")
+    prec = _prec(X.dtype, mixed)
+    i64 = C.c_int64 * d
+    dims_c, ranks_c = i64(*dims), i64(*ranks)
+    order_c = (C.c_int32 * d)(*[int(o) for o in order]) if order is not None else None
+    o = opts(prec)
+    if work is None:
+        out = C.c_size_t(0)
+        L.check(lib.ffsrqr_st_hosvd_workspace_size(d, dims_c, ranks_c, order_c, p, C.byref(o), C.byref(out)),
+                "ffsrqr_st_hosvd_workspace_size")
+        work = workspace(out.value, X.device, stream)
+    core = empty_fortran_nd(ranks, X.dtype, X.device)
+    Us = [empty_fortran(dims[j], ranks[j], X.dtype, X.device) for j in range(d)]
+    u_c = (C.c_void_p * d)(*[u.data_ptr() for u in Us])
+    L.check(lib.ffsrqr_st_hosvd(_ptr(X), d, dims_c, ranks_c, order_c, p, seed, _ptr(core), u_c, i64(*dims),
+                                _ptr(work), work.numel(), C.byref(o), _stream(stream)), "ffsrqr_st_hosvd")
+    return TuckerResult(core, Us)
+
+
 def profile_enable(on: bool = True) -> None:
     """Enable (and reset) the per-step device-time accounting of factor()."""
     L.load().ffsrqr_profile_enable(1 if on else 0)

@@ -689,6 +689,139 @@ ffsrqr_status alg9_impl(const T* A, int64_t m, int64_t n, int64_t lda, const T* 
   return FFSRQR_OK;
 }
 
+// ----------------------------------------------------------------- ST-HOSVD
+// The ST-HOSVD loop (Section 2, the ST-HOSVD algorithm) with Flip-Flop SRQR
+// and Algorithm 9's completion as the rank-k SVD of each unfolding.  Step j
+// processes mode r = order[j]: its unfolding G_(r) is m x n with m = the
+// current n_r and n = the product of the other current dimensions (the
+// modes already processed reduced to their ranks); l = min(k_r + p, m, n).
+struct HosvdPlan {
+  int d = 0;
+  int64_t dims[kMaxTensorOrder] = {}, ranks[kMaxTensorOrder] = {};
+  int order[kMaxTensorOrder] = {};
+  int64_t m[kMaxTensorOrder] = {}, n[kMaxTensorOrder] = {}, l[kMaxTensorOrder] = {};
+  int64_t total = 0, m_max = 0, n_max = 0, l_max = 0, k_max = 0;
+};
+
+ffsrqr_status hosvd_plan(int32_t d, const int64_t* dims, const int64_t* ranks, const int32_t* order, int64_t p,
+                         const DeviceInfo& dev, HosvdPlan* pl) {
+  if (d < 1 || d > kMaxTensorOrder) return fail(FFSRQR_EINVAL, "tensor order must be between 1 and 8");
+  if (!dims || !ranks) return fail(FFSRQR_EINVAL, "NULL dims or ranks");
+  if (p < 0) return fail(FFSRQR_EINVAL, "p must be >= 0");
+  pl->d = d;
+  pl->total = 1;
+  bool seen[kMaxTensorOrder] = {};
+  for (int j = 0; j < d; ++j) {
+    if (dims[j] < 1 || ranks[j] < 1 || ranks[j] > dims[j])
+      return fail(FFSRQR_EINVAL, "need 1 <= ranks[j] <= dims[j] for every mode");
+    if (pl->total > (int64_t(1) << 40) / dims[j]) return fail(FFSRQR_EINVAL, "tensor too large");
+    pl->total *= dims[j];
+    pl->dims[j] = dims[j];
+    pl->ranks[j] = ranks[j];
+    const int o = order ? order[j] : j;
+    if (o < 0 || o >= d || seen[o]) return fail(FFSRQR_EINVAL, "order must be a permutation of 0..d-1");
+    seen[o] = true;
+    pl->order[j] = o;
+  }
+  int64_t cur[kMaxTensorOrder];
+  int64_t size = pl->total;
+  for (int j = 0; j < d; ++j) cur[j] = dims[j];
+  for (int j = 0; j < d; ++j) {
+    const int r = pl->order[j];
+    const int64_t m = cur[r], n = size / m, k = ranks[r];
+    ffsrqr_status st = check_dims(m, n, k, p);
+    if (st != FFSRQR_OK) return fail(FFSRQR_EINVAL, "mode " + std::to_string(r) + ": " + ffsrqr_last_error());
+    const int64_t l = std::min(k + p, std::min(m, n));
+    st = check_limits(m, n, l, dev);
+    if (st != FFSRQR_OK) return fail(FFSRQR_EINVAL, "mode " + std::to_string(r) + ": " + ffsrqr_last_error());
+    pl->m[j] = m;
+    pl->n[j] = n;
+    pl->l[j] = l;
+    pl->m_max = std::max(pl->m_max, m);
+    pl->n_max = std::max(pl->n_max, n);
+    pl->l_max = std::max(pl->l_max, l);
+    pl->k_max = std::max(pl->k_max, k);
+    size = size / m * k;
+    cur[r] = k;
+  }
+  return FFSRQR_OK;
+}
+
+// Two tensor buffers (each the input's size), the factor outputs of the
+// largest step, then one region shared by the steps' workspaces.
+template <typename T>
+size_t hosvd_fixed_bytes(const HosvdPlan& pl) {
+  return 2 * align256((size_t)pl.total * sizeof(T)) + align256((size_t)pl.n_max * sizeof(int64_t)) +
+         align256((size_t)pl.m_max * pl.l_max * sizeof(T)) + align256((size_t)pl.l_max * pl.l_max * sizeof(T)) +
+         align256((size_t)pl.n_max * pl.l_max * sizeof(T)) + align256((size_t)pl.l_max * sizeof(double)) +
+         align256((size_t)pl.n_max * pl.k_max * sizeof(T)) + 256;
+}
+template <typename T>
+size_t hosvd_bytes(const HosvdPlan& pl, const DeviceInfo& d) {
+  size_t w = 0;
+  for (int j = 0; j < pl.d; ++j) {
+    const int64_t m = pl.m[j], n = pl.n[j], l = pl.l[j], k = pl.ranks[pl.order[j]];
+    w = std::max(w, total_bytes<T>(m, n, l, d));
+    w = std::max(w, alg9_bytes<T>(m, n, l, k, d));
+    w = std::max(w, gemm_tn_scratch<T>(k, n, m, d.num_cu) + 256);
+  }
+  return hosvd_fixed_bytes<T>(pl) + w + 1024;
+}
+
+template <typename T>
+ffsrqr_status hosvd_impl(const T* X, const HosvdPlan& pl, int64_t p, uint64_t seed, T* core, T* const* U,
+                         const int64_t* ldu, void* work, size_t work_bytes, const ffsrqr_opts* opts,
+                         const DeviceInfo& d, hipStream_t s) {
+  const size_t need = hosvd_bytes<T>(pl, d);
+  if (work_bytes < need) return fail(FFSRQR_EWORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+  Arena ar{(char*)work, work_bytes, 0};
+  T* buf[2] = {ar.take<T>((size_t)pl.total), ar.take<T>((size_t)pl.total)};
+  int64_t* perm = ar.take<int64_t>((size_t)pl.n_max);
+  T* Q = ar.take<T>((size_t)pl.m_max * pl.l_max);
+  T* L = ar.take<T>((size_t)pl.l_max * pl.l_max);
+  T* V = ar.take<T>((size_t)pl.n_max * pl.l_max);
+  double* sigma = ar.take<double>((size_t)pl.l_max);
+  T* Vk = ar.take<T>((size_t)pl.n_max * pl.k_max);
+  if (!buf[0] || !buf[1] || !perm || !Q || !L || !V || !sigma || !Vk)
+    return fail(FFSRQR_EWORKSPACE, "workspace carving failed");
+  const size_t off = align256(ar.used);
+  char* fwork = (char*)work + off;
+  const size_t fbytes = work_bytes - off;
+  int64_t cur[kMaxTensorOrder];
+  for (int j = 0; j < pl.d; ++j) cur[j] = pl.dims[j];
+  const T* G = X;  // the current tensor, held as its mode-gmode unfolding
+  int gmode = 0, nb = 0;
+  for (int j = 0; j < pl.d; ++j) {
+    const int r = pl.order[j];
+    const int64_t m = pl.m[j], n = pl.n[j], l = pl.l[j], k = pl.ranks[r];
+    const T* Gr = G;
+    if (gmode != r) {
+      FF_HIP(reunfold<T>(G, gmode, buf[nb], r, pl.d, cur, s));
+      Gr = buf[nb];
+      nb ^= 1;
+    }
+    // rank-k_r SVD of G_(r): Flip-Flop SRQR, then Algorithm 9's completion
+    const ffsrqr_opts op = resolve(opts, l);
+    ffsrqr_status st = factor_impl<T>(Gr, m, n, m, k, p, seed, perm, Q, m, L, l, V, n, sigma, nullptr, fwork, fbytes,
+                                      op, d, s);
+    if (st != FFSRQR_OK) return st;
+    st = alg9_impl<T>(Gr, m, n, m, V, n, l, k, U[r], ldu[r], sigma, Vk, n, fwork, fbytes, d, s);
+    if (st != FFSRQR_OK) return st;
+    // G_(r) <- U_r^T G_(r), the mode-r unfolding of the reduced tensor
+    T* W = buf[nb];
+    nb ^= 1;
+    Arena a{fwork, fbytes, 0};
+    FF_HIP(gemm_tn<T>(k, n, m, U[r], ldu[r], Gr, m, W, k, nullptr, a, d.num_cu, s));
+    cur[r] = k;
+    G = W;
+    gmode = r;
+  }
+  // the core in Fortran order, i.e. its mode-0 unfolding
+  FF_HIP(reunfold<T>(G, gmode, core, 0, pl.d, cur, s));
+  FF_HIP(hipStreamSynchronize(s));
+  return FFSRQR_OK;
+}
+
 ffsrqr_status alg9_check(int64_t m, int64_t n, int64_t l, int64_t k, int32_t precision, const DeviceInfo& d) {
   if (m < 1 || n < 1 || l < 1 || l > std::min(m, n) || k < 1 || k > l)
     return fail(FFSRQR_EINVAL, "need 1 <= k <= l <= min(m, n)");
@@ -1010,6 +1143,45 @@ ffsrqr_status ffsrqr_alg9_svd(const void* A, int64_t m, int64_t n, int64_t lda, 
                              (double*)Vk, ldvk, work, work_bytes, *d, s);
   return alg9_impl<float>((const float*)A, m, n, lda, (const float*)V, ldv, l, k, (float*)U, ldu, sigma,
                           (float*)Vk, ldvk, work, work_bytes, *d, s);
+}
+
+ffsrqr_status ffsrqr_st_hosvd_workspace_size(int32_t d, const int64_t* dims, const int64_t* ranks,
+                                             const int32_t* order, int64_t p, const ffsrqr_opts* opts,
+                                             size_t* bytes) {
+  if (!bytes) return fail(FFSRQR_EINVAL, "bytes is NULL");
+  const int32_t prec = opts ? opts->precision : FFSRQR_FP64;
+  if (!valid_precision(prec)) return fail(FFSRQR_EINVAL, "unknown precision");
+  HosvdPlan pl;
+  ffsrqr_status st = hosvd_plan(d, dims, ranks, order, p, limits_device(), &pl);
+  if (st != FFSRQR_OK) return st;
+  const DeviceInfo dv = sizing_device();
+  *bytes = prec == FFSRQR_FP64 ? hosvd_bytes<double>(pl, dv) : hosvd_bytes<float>(pl, dv);
+  return FFSRQR_OK;
+}
+
+ffsrqr_status ffsrqr_st_hosvd(const void* X, int32_t d, const int64_t* dims, const int64_t* ranks,
+                              const int32_t* order, int64_t p, uint64_t seed, void* core, void* const* U,
+                              const int64_t* ldu, void* work, size_t work_bytes, const ffsrqr_opts* opts,
+                              ffsrqr_stream_t stream) {
+  const int32_t prec = opts ? opts->precision : FFSRQR_FP64;
+  if (!valid_precision(prec)) return fail(FFSRQR_EINVAL, "unknown precision");
+  if (opts && !(opts->g == 0.0 || opts->g > 1.0)) return fail(FFSRQR_EINVAL, "g must be > 1");
+  if (!X || !core || !U || !ldu || !work) return fail(FFSRQR_EINVAL, "NULL pointer argument");
+  const DeviceInfo* dv = nullptr;
+  ffsrqr_status st = get_device(&dv);
+  if (st != FFSRQR_OK) return st;
+  HosvdPlan pl;
+  st = hosvd_plan(d, dims, ranks, order, p, *dv, &pl);
+  if (st != FFSRQR_OK) return st;
+  for (int j = 0; j < d; ++j)
+    if (!U[j] || ldu[j] < dims[j]) return fail(FFSRQR_EINVAL, "U[j] NULL or ldu[j] < dims[j]");
+  if (prec == FFSRQR_MIXED && ((uintptr_t)X & 3) != 0) return fail(FFSRQR_EINVAL, "X must be 4-byte aligned");
+  hipStream_t s = (hipStream_t)stream;
+  if (prec == FFSRQR_FP64)
+    return hosvd_impl<double>((const double*)X, pl, p, seed, (double*)core, (double* const*)U, ldu, work, work_bytes,
+                              opts, *dv, s);
+  return hosvd_impl<float>((const float*)X, pl, p, seed, (float*)core, (float* const*)U, ldu, work, work_bytes, opts,
+                           *dv, s);
 }
 
 ffsrqr_status ffsrqr_svd_small_noalloc(const void* L, int64_t l, int64_t ldl, double* sigma, int32_t precision,

@@ -150,6 +150,15 @@ template <typename T>
 hipError_t srqr_swap_update(const T* A, int64_t m, int64_t n, int64_t lda, T* Q, int64_t ldq, T* W, int64_t ldw,
                             T* R11, int64_t ldr, int64_t l, int64_t istar, int64_t jstar, Arena& ar, hipStream_t s);
 
+// Tensors (the ST-HOSVD driver), order at most kMaxTensorOrder.  The mode-a
+// unfolding holds entry (i_0..i_{d-1}) at i_a + n_a c_a, c_a the
+// Fortran-order linear index of the other indices in order (the mode-0
+// unfolding is the tensor in Fortran order).  reunfold copies a tensor from
+// its mode-a unfolding to its mode-b unfolding (a == b: a plain copy).
+constexpr int kMaxTensorOrder = 8;
+template <typename T>
+hipError_t reunfold(const T* src, int a, T* dst, int b, int d, const int64_t* dims, hipStream_t s);
+
 // Singular values of L (l x l) by block one-sided Jacobi (FP64).
 template <typename T>
 size_t jacobi_scratch(int64_t l, const DeviceInfo& d);

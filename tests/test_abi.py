@@ -160,3 +160,28 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(_lib.LibraryMissing):
         _lib.load()
+
+
+def test_st_hosvd_workspace_size_host_only(lib):
+    """The ST-HOSVD sizing call plans every mode on the host: a 400^3 tensor
+    of Tucker rank 40^3 needs its two tensor buffers (2 x 256 MB FP32) plus
+    the largest mode's factorization; invalid ranks, orders and tensor
+    orders are rejected."""
+    from paper_1803_01982_amd import _lib
+    i64 = C.c_int64 * 3
+    out = C.c_size_t(0)
+    o = _lib.Opts(1, -1, 2.0)
+    assert lib.ffsrqr_st_hosvd_workspace_size(3, i64(400, 400, 400), i64(40, 40, 40), None, 10, C.byref(o),
+                                              C.byref(out)) == 0
+    assert out.value > 2 * 4 * 400 ** 3
+    order = (C.c_int32 * 3)(2, 0, 1)
+    assert lib.ffsrqr_st_hosvd_workspace_size(3, i64(400, 400, 400), i64(40, 40, 40), order, 10, C.byref(o),
+                                              C.byref(out)) == 0
+    bad_order = (C.c_int32 * 3)(0, 0, 1)
+    assert lib.ffsrqr_st_hosvd_workspace_size(3, i64(40, 40, 40), i64(4, 4, 4), bad_order, 2, None,
+                                              C.byref(out)) == 1
+    assert lib.ffsrqr_st_hosvd_workspace_size(3, i64(40, 40, 40), i64(4, 41, 4), None, 2, None, C.byref(out)) == 1
+    assert lib.ffsrqr_st_hosvd_workspace_size(0, i64(40, 40, 40), i64(4, 4, 4), None, 2, None, C.byref(out)) == 1
+    assert lib.ffsrqr_st_hosvd_workspace_size(9, (C.c_int64 * 9)(*[2] * 9), (C.c_int64 * 9)(*[1] * 9), None, 0,
+                                              None, C.byref(out)) == 1
+    assert lib.ffsrqr_last_error()
