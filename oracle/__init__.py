@@ -47,6 +47,7 @@ from .ffsrqr import (
 )
 from . import diagnostics
 from . import hosvd
+from . import ialm
 
 __all__ = [
     "omega", "philox4x64_10", "uniform_open", "FLAG_L_CLAMPED", "FLAG_NONFINITE",
@@ -54,5 +55,5 @@ __all__ = [
     "factor_leading_set", "ffsrqr", "flip_flop_lq", "householder", "householder_qr",
     "jacobi_svd", "project", "qrcp_sketch", "rank_tolerance", "residual_margin", "residual_norms", "round_bf16",
     "sketch", "srqr_rho",
-    "upper_inverse", "diagnostics", "hosvd",
+    "upper_inverse", "diagnostics", "hosvd", "ialm",
 ]

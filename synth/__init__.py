@@ -27,6 +27,9 @@ Recipes (all seeded, FP64 arithmetic, optionally rounded to FP32 storage):
 * ``tucker_tensor``: a Tucker tensor (N(0,1) core times orthonormal
   factors) plus Gaussian noise, for the ST-HOSVD driver; the 400^3 tensor
   of core 40^3 and noise 1e-3 stands for the tensor workload.
+* ``rpca_problem``: low rank plus sparse, M = X_L X_R^T + E*, for the
+  robust PCA driver (rank 0.1 m and 5% corrupted entries in the paper's
+  experiment).
 """
 from __future__ import annotations
 
@@ -41,6 +44,7 @@ __all__ = [
     "random_matrix",
     "make_workload",
     "tucker_tensor",
+    "rpca_problem",
 ]
 
 
@@ -146,6 +150,23 @@ def tucker_tensor(dims, ranks, seed: int, noise: float = 0.0, dtype=np.float64) 
     if noise:
         X = X + noise * _rng(seed, 20).standard_normal(tuple(dims))
     return np.asfortranarray(X.astype(dtype, copy=False))
+
+
+def rpca_problem(m: int, n: int, rank: int, frac: float, seed: int, amp: float = 500.0):
+    """M = X* + E*: X* = X_L X_R^T with X_L (m x rank) and X_R (n x rank)
+    i.i.d. N(0,1); E* with round(frac m n) nonzeros at distinct uniformly
+    random positions, each uniform on [-amp, amp] (the robust PCA test
+    matrices of the paper's experiment).  Returns (M, X*, E*), Fortran order."""
+    xl = _rng(seed, 30).standard_normal((m, rank))
+    xr = _rng(seed, 31).standard_normal((n, rank))
+    X = np.asfortranarray(xl @ xr.T)
+    rng = _rng(seed, 32)
+    nnz = int(round(frac * m * n))
+    pos = rng.choice(m * n, size=nnz, replace=False)
+    E = np.zeros(m * n)
+    E[pos] = rng.uniform(-amp, amp, size=nnz)
+    E = np.asfortranarray(E.reshape((m, n), order="F"))
+    return np.asfortranarray(X + E), X, E
 
 
 def make_workload(name: str, dtype=np.float64) -> np.ndarray:
