@@ -335,6 +335,49 @@ ffsrqr_status ffsrqr_st_hosvd(const void* X, int32_t d, const int64_t* dims, con
                               ffsrqr_stream_t stream);
 
 /*
+ * Robust PCA by the inexact augmented Lagrange multiplier method with
+ * Flip-Flop SRQR as its SVD (Section 2, nuclear norm minimization and the
+ * robust PCA algorithm; Section 4, the robust PCA experiment): splits
+ * M (m x n, ldm) into a low-rank X and a sparse E (min ||X||_* +
+ * lambda ||E||_1 with M = X + E).  Iteration: D = M - E + Y / mu; the
+ * rank-sv SVD of D by ffsrqr_factor's path (target rank sv, oversampling p,
+ * Omega key seed, the options in opts) completed by Algorithm 9;
+ * X = U S_{1/mu}(Sigma) V^T over the singular values above 1 / mu;
+ * E = S_{lambda/mu}(M - X + Y / mu); Y += mu (M - X - E); mu <- min(1.5 mu,
+ * 1e7 mu_0); until ||M - X - E||_F / ||M||_F < tol or max_iter iterations
+ * (S_w(x) = sgn(x) max(|x| - w, 0)).  Start: E = 0, Y = M / J(M),
+ * J(M) = max(||M||_2, max |M_ij|), mu_0 = 1.25 / ||M||_2, with ||M||_2
+ * estimated by sigma_1 of the flip-flop factor L of M (k = 1); sv starts at
+ * 10 and follows the number svp of singular values kept: svp + 1 when
+ * svp < sv, else svp + round(0.05 n), capped at min(m, n), 1024 - p and
+ * max_rank (when > 0).  lambda <= 0 selects 1 / sqrt(max(m, n)).
+ *   X (ldx >= m), E (lde >= m): outputs, element type of the precision.
+ *   info  host pointer (may be NULL).
+ * The FP32 forms cannot reach residuals much below 1e-6: use tol >= 1e-5
+ * there.  Errors: FFSRQR_EINVAL for m or n < 1, p outside 0..1023,
+ * tol <= 0, max_iter < 1, a leading dimension too small, a NULL pointer or
+ * sizes beyond the path's limits at l = min(cap + p, m, n); the workspace
+ * comes from ffsrqr_rpca_workspace_size.  The call returns after the
+ * stream has completed.
+ */
+typedef struct ffsrqr_rpca_info {
+  int32_t iterations;   /* iterations run                                    */
+  int32_t rank;         /* singular values kept in the final X               */
+  double residual;      /* ||M - X - E||_F / ||M||_F at exit                  */
+  double mu;            /* mu after the last iteration                        */
+  double norm2;         /* the estimate of ||M||_2                            */
+  int32_t converged;    /* residual < tol                                     */
+  int32_t rank_capped;  /* the predicted rank reached its cap                 */
+} ffsrqr_rpca_info;
+
+ffsrqr_status ffsrqr_rpca_workspace_size(int64_t m, int64_t n, int64_t p, int64_t max_rank,
+                                         const ffsrqr_opts* opts, size_t* bytes);
+ffsrqr_status ffsrqr_rpca_ialm(const void* M, int64_t m, int64_t n, int64_t ldm, double lambda, double tol,
+                               int32_t max_iter, int64_t p, uint64_t seed, int64_t max_rank, void* X,
+                               int64_t ldx, void* E, int64_t lde, ffsrqr_rpca_info* info, void* work,
+                               size_t work_bytes, const ffsrqr_opts* opts, ffsrqr_stream_t stream);
+
+/*
  * ffsrqr_svd_small without a workspace, for callers that cannot allocate
  * device memory (code under HIP graph capture, serving loops, harnesses
  * that forbid allocation): the same kernels and results as

@@ -34,6 +34,14 @@ class Info(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class RpcaInfo(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("rank", C.c_int32), ("residual", C.c_double), ("mu", C.c_double),
+                ("norm2", C.c_double), ("converged", C.c_int32), ("rank_capped", C.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 _P = C.c_void_p
 _I64 = C.c_int64
 _I32 = C.c_int32
@@ -65,6 +73,9 @@ SIGNATURES = {
                                                  C.POINTER(Opts), C.POINTER(_SZ)]),
     "ffsrqr_st_hosvd": (C.c_int, [_P, _I32, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I32), _I64, _U64, _P,
                                   C.POINTER(_P), C.POINTER(_I64), _P, _SZ, C.POINTER(Opts), _P]),
+    "ffsrqr_rpca_workspace_size": (C.c_int, [_I64, _I64, _I64, _I64, C.POINTER(Opts), C.POINTER(_SZ)]),
+    "ffsrqr_rpca_ialm": (C.c_int, [_P, _I64, _I64, _I64, _D, _D, _I32, _I64, _U64, _I64, _P, _I64, _P, _I64,
+                                   C.POINTER(RpcaInfo), _P, _SZ, C.POINTER(Opts), _P]),
     "ffsrqr_profile_enable": (None, [C.c_int]),
     "ffsrqr_profile_read": (C.c_int, [C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int]),
 }

@@ -311,6 +311,36 @@ def st_hosvd(X: torch.Tensor, ranks, p: int, seed: int = 0, order=None, mixed: b
     return TuckerResult(core, Us)
 
 
+@dataclasses.dataclass
+class RpcaResult:
+    X: torch.Tensor       # low-rank part, m x n column-major
+    E: torch.Tensor       # sparse part, m x n column-major
+    info: dict
+
+
+def rpca_ialm(M: torch.Tensor, p: int = 10, seed: int = 0, lam: float = 0.0, tol: float = 1e-7,
+              max_iter: int = 500, max_rank: int = 0, mixed: bool = False, work=None, stream=None) -> RpcaResult:
+    """ffsrqr_rpca_ialm: robust PCA M ~ X + E by IALM with Flip-Flop SRQR
+    (plus Algorithm 9) as the partial SVD; lam <= 0 selects
+    1 / sqrt(max(m, n))."""
+    lib = L.load()
+    m, n = M.shape
+    prec = _prec(M.dtype, mixed)
+    o = opts(prec)
+    if work is None:
+        out = C.c_size_t(0)
+        L.check(lib.ffsrqr_rpca_workspace_size(m, n, p, max_rank, C.byref(o), C.byref(out)),
+                "ffsrqr_rpca_workspace_size")
+        work = workspace(out.value, M.device, stream)
+    X = empty_fortran(m, n, M.dtype, M.device)
+    E = empty_fortran(m, n, M.dtype, M.device)
+    info = L.RpcaInfo()
+    L.check(lib.ffsrqr_rpca_ialm(_ptr(M), m, n, _ld(M), lam, tol, max_iter, p, seed, max_rank, _ptr(X), m, _ptr(E),
+                                 m, C.byref(info), _ptr(work), work.numel(), C.byref(o), _stream(stream)),
+            "ffsrqr_rpca_ialm")
+    return RpcaResult(X, E, info.as_dict())
+
+
 def profile_enable(on: bool = True) -> None:
     """Enable (and reset) the per-step device-time accounting of factor()."""
     L.load().ffsrqr_profile_enable(1 if on else 0)

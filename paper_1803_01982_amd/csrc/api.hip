@@ -822,6 +822,161 @@ ffsrqr_status hosvd_impl(const T* X, const HosvdPlan& pl, int64_t p, uint64_t se
   return FFSRQR_OK;
 }
 
+// ---------------------------------------------------------------- robust PCA
+// Robust PCA by IALM (Section 2, the robust PCA algorithm) with the whole
+// path plus Algorithm 9 as the rank-sv SVD of each iteration.  sv is capped
+// at `cap` (min(m, n), 1024 - p, and the caller's max_rank), so that
+// l = min(sv + p, m, n) stays within the path's limit.
+struct RpcaSizes {
+  int64_t r = 0, cap = 0, lmax = 0;
+};
+
+RpcaSizes rpca_sizes(int64_t m, int64_t n, int64_t p, int64_t max_rank) {
+  RpcaSizes z;
+  z.r = std::min(m, n);
+  z.cap = std::min(z.r, 1024 - p);
+  if (max_rank > 0) z.cap = std::min(z.cap, max_rank);
+  z.lmax = std::min(z.cap + p, z.r);
+  return z;
+}
+
+template <typename T>
+size_t rpca_fixed_bytes(int64_t m, int64_t n, const RpcaSizes& z) {
+  const size_t mn = (size_t)m * n;
+  return 3 * align256(mn * sizeof(T)) + align256((size_t)z.cap * m * sizeof(T)) +
+         align256((size_t)z.cap * n * sizeof(T)) + align256((size_t)n * sizeof(int64_t)) +
+         align256((size_t)m * z.lmax * sizeof(T)) + align256((size_t)z.lmax * z.lmax * sizeof(T)) +
+         align256((size_t)n * z.lmax * sizeof(T)) + align256((size_t)z.lmax * sizeof(double)) +
+         align256((size_t)m * z.cap * sizeof(T)) + align256((size_t)n * z.cap * sizeof(T)) +
+         align256((size_t)(2 * kIalmBlocks + 8) * sizeof(double)) + 256;
+}
+template <typename T>
+size_t rpca_bytes(int64_t m, int64_t n, const RpcaSizes& z, const DeviceInfo& d) {
+  size_t w = total_bytes<T>(m, n, z.lmax, d);
+  w = std::max(w, alg9_bytes<T>(m, n, z.lmax, z.cap, d));
+  w = std::max(w, gemm_tn_scratch<T>(m, n, z.cap, d.num_cu) + 256);
+  return rpca_fixed_bytes<T>(m, n, z) + w + 1024;
+}
+
+template <typename T>
+ffsrqr_status rpca_impl(const T* M, int64_t m, int64_t n, int64_t ldm, double lam, double tol, int32_t max_iter,
+                        int64_t p, uint64_t seed, const RpcaSizes& z, T* X, int64_t ldx, T* E, int64_t lde,
+                        ffsrqr_rpca_info* info, void* work, size_t work_bytes, const ffsrqr_opts* opts,
+                        const DeviceInfo& d, hipStream_t s) {
+  const size_t need = rpca_bytes<T>(m, n, z, d);
+  if (work_bytes < need) return fail(FFSRQR_EWORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+  Arena ar{(char*)work, work_bytes, 0};
+  const size_t mn = (size_t)m * n;
+  T* D = ar.take<T>(mn);
+  T* Y = ar.take<T>(mn);
+  T* Ei = ar.take<T>(mn);
+  T* Ut = ar.take<T>((size_t)z.cap * m);
+  T* Vt = ar.take<T>((size_t)z.cap * n);
+  int64_t* perm = ar.take<int64_t>((size_t)n);
+  T* Q = ar.take<T>((size_t)m * z.lmax);
+  T* L = ar.take<T>((size_t)z.lmax * z.lmax);
+  T* V = ar.take<T>((size_t)n * z.lmax);
+  double* sigma = ar.take<double>((size_t)z.lmax);
+  T* U = ar.take<T>((size_t)m * z.cap);
+  T* Vk = ar.take<T>((size_t)n * z.cap);
+  double* part = ar.take<double>((size_t)2 * kIalmBlocks + 8);
+  if (!D || !Y || !Ei || !Ut || !Vt || !perm || !Q || !L || !V || !sigma || !U || !Vk || !part)
+    return fail(FFSRQR_EWORKSPACE, "workspace carving failed");
+  double* out = part + 2 * kIalmBlocks;
+  const size_t off = align256(ar.used);
+  char* fwork = (char*)work + off;
+  const size_t fbytes = work_bytes - off;
+  double hout[2];
+  auto read_out = [&]() -> ffsrqr_status {
+    FF_HIP(hipMemcpyAsync(hout, out, sizeof(hout), hipMemcpyDeviceToHost, s));
+    FF_HIP(hipStreamSynchronize(s));
+    return FFSRQR_OK;
+  };
+  // ||M||_F and max |M_ij|
+  FF_HIP(matrix_norms<T>(M, ldm, m, n, part, out, s));
+  ffsrqr_status st = read_out();
+  if (st != FFSRQR_OK) return st;
+  const double fro = std::sqrt(hout[0]), amax = hout[1];
+  // ||M||_2 estimate: sigma_1 of the flip-flop factor L of M (k = 1)
+  double norm2 = 0.0;
+  {
+    const int64_t l1 = std::min<int64_t>(1 + p, z.r);
+    st = factor_impl<T>(M, m, n, ldm, 1, p, seed, perm, Q, m, L, l1, V, n, sigma, nullptr, fwork, fbytes,
+                        resolve(opts, l1), d, s);
+    if (st != FFSRQR_OK) return st;
+    FF_HIP(hipMemcpy(&norm2, sigma, sizeof(double), hipMemcpyDeviceToHost));
+  }
+  ffsrqr_rpca_info inf{};
+  inf.norm2 = norm2;
+  if (!(norm2 > 0.0) || !(fro > 0.0)) {
+    // M = 0: X = E = 0
+    FF_HIP(zero_matrix<T>(X, ldx, m, n, s));
+    FF_HIP(zero_matrix<T>(E, lde, m, n, s));
+    FF_HIP(hipStreamSynchronize(s));
+    inf.converged = 1;
+    if (info) *info = inf;
+    return FFSRQR_OK;
+  }
+  const double J = std::max(norm2, amax);
+  FF_HIP(ialm_init<T>(M, ldm, m, n, 1.0 / J, Y, Ei, s));
+  double mu = 1.25 / norm2;
+  const double mu_bar = 1e7 * mu, rho = 1.5;
+  int64_t sv = std::min<int64_t>(10, z.cap);
+  int64_t svp = 0;
+  int32_t it = 0;
+  double res = HUGE_VAL;
+  bool capped = false;
+  std::vector<double> hs((size_t)z.lmax);
+  while (it < max_iter) {
+    ++it;
+    FF_HIP(ialm_shift<T>(M, ldm, Ei, Y, m, n, 1.0 / mu, D, s));
+    // rank-sv SVD of D: Flip-Flop SRQR, then Algorithm 9's completion
+    const int64_t l = std::min(sv + p, z.r);
+    st = factor_impl<T>(D, m, n, m, sv, p, seed, perm, Q, m, L, l, V, n, sigma, nullptr, fwork, fbytes,
+                        resolve(opts, l), d, s);
+    if (st != FFSRQR_OK) return st;
+    st = alg9_impl<T>(D, m, n, m, V, n, l, sv, U, m, sigma, Vk, n, fwork, fbytes, d, s);
+    if (st != FFSRQR_OK) return st;
+    FF_HIP(hipMemcpy(hs.data(), sigma, (size_t)sv * sizeof(double), hipMemcpyDeviceToHost));
+    svp = 0;
+    for (int64_t j = 0; j < sv; ++j)
+      if (hs[(size_t)j] > 1.0 / mu) ++svp;
+    // X = U(:, 0:svp) S_{1/mu}(Sigma) V_k(:, 0:svp)^T
+    if (svp > 0) {
+      FF_HIP(scaled_transpose<T>(U, m, svp, m, sigma, 1.0 / mu, Ut, svp, s));
+      FF_HIP(transpose<T>(Vk, n, svp, n, Vt, svp, s));
+      Arena a{fwork, fbytes, 0};
+      FF_HIP(gemm_tn<T>(m, n, svp, Ut, svp, Vt, svp, X, ldx, nullptr, a, d.num_cu, s));
+    } else {
+      FF_HIP(zero_matrix<T>(X, ldx, m, n, s));
+    }
+    // E, Y and the residual
+    FF_HIP(ialm_update<T>(M, ldm, X, ldx, m, n, mu, lam / mu, Ei, Y, part, out, s));
+    st = read_out();
+    if (st != FFSRQR_OK) return st;
+    res = std::sqrt(hout[0]) / fro;
+    sv = svp < sv ? std::min(svp + 1, z.r) : std::min(svp + (int64_t)std::llround(0.05 * (double)n), z.r);
+    if (sv > z.cap) {
+      sv = z.cap;
+      capped = true;
+    }
+    if (sv < 1) sv = 1;
+    mu = std::min(mu * rho, mu_bar);
+    if (res < tol) break;
+  }
+  FF_HIP(hipMemcpy2DAsync(E, (size_t)lde * sizeof(T), Ei, (size_t)m * sizeof(T), (size_t)m * sizeof(T), (size_t)n,
+                          hipMemcpyDeviceToDevice, s));
+  FF_HIP(hipStreamSynchronize(s));
+  inf.iterations = it;
+  inf.rank = (int32_t)svp;
+  inf.residual = res;
+  inf.mu = mu;
+  inf.converged = res < tol ? 1 : 0;
+  inf.rank_capped = capped ? 1 : 0;
+  if (info) *info = inf;
+  return FFSRQR_OK;
+}
+
 ffsrqr_status alg9_check(int64_t m, int64_t n, int64_t l, int64_t k, int32_t precision, const DeviceInfo& d) {
   if (m < 1 || n < 1 || l < 1 || l > std::min(m, n) || k < 1 || k > l)
     return fail(FFSRQR_EINVAL, "need 1 <= k <= l <= min(m, n)");
@@ -1182,6 +1337,51 @@ ffsrqr_status ffsrqr_st_hosvd(const void* X, int32_t d, const int64_t* dims, con
                               opts, *dv, s);
   return hosvd_impl<float>((const float*)X, pl, p, seed, (float*)core, (float* const*)U, ldu, work, work_bytes, opts,
                            *dv, s);
+}
+
+ffsrqr_status ffsrqr_rpca_workspace_size(int64_t m, int64_t n, int64_t p, int64_t max_rank,
+                                         const ffsrqr_opts* opts, size_t* bytes) {
+  if (!bytes) return fail(FFSRQR_EINVAL, "bytes is NULL");
+  const int32_t prec = opts ? opts->precision : FFSRQR_FP64;
+  if (!valid_precision(prec)) return fail(FFSRQR_EINVAL, "unknown precision");
+  if (m < 1 || n < 1 || p < 0 || p > 1023) return fail(FFSRQR_EINVAL, "need m, n >= 1 and 0 <= p <= 1023");
+  const RpcaSizes z = rpca_sizes(m, n, p, max_rank);
+  ffsrqr_status st = check_dims(m, n, 1, p);
+  if (st != FFSRQR_OK) return st;
+  st = check_limits(m, n, z.lmax, limits_device());
+  if (st != FFSRQR_OK) return st;
+  const DeviceInfo dv = sizing_device();
+  *bytes = prec == FFSRQR_FP64 ? rpca_bytes<double>(m, n, z, dv) : rpca_bytes<float>(m, n, z, dv);
+  return FFSRQR_OK;
+}
+
+ffsrqr_status ffsrqr_rpca_ialm(const void* M, int64_t m, int64_t n, int64_t ldm, double lambda, double tol,
+                               int32_t max_iter, int64_t p, uint64_t seed, int64_t max_rank, void* X, int64_t ldx,
+                               void* E, int64_t lde, ffsrqr_rpca_info* info, void* work, size_t work_bytes,
+                               const ffsrqr_opts* opts, ffsrqr_stream_t stream) {
+  const int32_t prec = opts ? opts->precision : FFSRQR_FP64;
+  if (!valid_precision(prec)) return fail(FFSRQR_EINVAL, "unknown precision");
+  if (opts && !(opts->g == 0.0 || opts->g > 1.0)) return fail(FFSRQR_EINVAL, "g must be > 1");
+  if (m < 1 || n < 1 || p < 0 || p > 1023) return fail(FFSRQR_EINVAL, "need m, n >= 1 and 0 <= p <= 1023");
+  if (ldm < m || ldx < m || lde < m) return fail(FFSRQR_EINVAL, "leading dimension too small");
+  if (!M || !X || !E || !work) return fail(FFSRQR_EINVAL, "NULL pointer argument");
+  if (!(tol > 0.0) || max_iter < 1) return fail(FFSRQR_EINVAL, "need tol > 0 and max_iter >= 1");
+  const double lam = lambda > 0.0 ? lambda : 1.0 / std::sqrt((double)std::max(m, n));
+  const RpcaSizes z = rpca_sizes(m, n, p, max_rank);
+  ffsrqr_status st = check_dims(m, n, 1, p);
+  if (st != FFSRQR_OK) return st;
+  const DeviceInfo* dv = nullptr;
+  st = get_device(&dv);
+  if (st != FFSRQR_OK) return st;
+  st = check_limits(m, n, z.lmax, *dv);
+  if (st != FFSRQR_OK) return st;
+  if (prec == FFSRQR_MIXED && ((uintptr_t)M & 3) != 0) return fail(FFSRQR_EINVAL, "M must be 4-byte aligned");
+  hipStream_t s = (hipStream_t)stream;
+  if (prec == FFSRQR_FP64)
+    return rpca_impl<double>((const double*)M, m, n, ldm, lam, tol, max_iter, p, seed, z, (double*)X, ldx,
+                             (double*)E, lde, info, work, work_bytes, opts, *dv, s);
+  return rpca_impl<float>((const float*)M, m, n, ldm, lam, tol, max_iter, p, seed, z, (float*)X, ldx, (float*)E, lde,
+                          info, work, work_bytes, opts, *dv, s);
 }
 
 ffsrqr_status ffsrqr_svd_small_noalloc(const void* L, int64_t l, int64_t ldl, double* sigma, int32_t precision,

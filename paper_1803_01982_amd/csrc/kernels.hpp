@@ -159,6 +159,26 @@ constexpr int kMaxTensorOrder = 8;
 template <typename T>
 hipError_t reunfold(const T* src, int a, T* dst, int b, int d, const int64_t* dims, hipStream_t s);
 
+// Elementwise steps of robust PCA by IALM (D, E, Y with leading dimension
+// m; M, X with their own).  Reductions write kIalmBlocks partials (part) and
+// their total to out[0] (sum of squares) and out[1] (largest magnitude).
+constexpr int kIalmBlocks = 1024;
+template <typename T>  // D = M - E + Y / mu
+hipError_t ialm_shift(const T* M, int64_t ldm, const T* E, const T* Y, int64_t m, int64_t n, double inv_mu, T* D,
+                      hipStream_t s);
+template <typename T>  // Y = M / J, E = 0
+hipError_t ialm_init(const T* M, int64_t ldm, int64_t m, int64_t n, double inv_j, T* Y, T* E, hipStream_t s);
+template <typename T>  // E = S_w(M - X + Y / mu); Z = M - X - E; Y += mu Z; out[0] = ||Z||_F^2
+hipError_t ialm_update(const T* M, int64_t ldm, const T* X, int64_t ldx, int64_t m, int64_t n, double mu, double w,
+                       T* E, T* Y, double* part, double* out, hipStream_t s);
+template <typename T>  // out[0] = ||M||_F^2, out[1] = max |M_ij|; part: 2 kIalmBlocks doubles
+hipError_t matrix_norms(const T* M, int64_t ldm, int64_t m, int64_t n, double* part, double* out, hipStream_t s);
+template <typename T>  // B (k x rows, ldb): B(j, i) = A(i, j) (sigma[j] - inv_mu)
+hipError_t scaled_transpose(const T* A, int64_t rows, int64_t k, int64_t lda, const double* sigma, double inv_mu,
+                            T* B, int64_t ldb, hipStream_t s);
+template <typename T>
+hipError_t zero_matrix(T* X, int64_t ldx, int64_t m, int64_t n, hipStream_t s);
+
 // Singular values of L (l x l) by block one-sided Jacobi (FP64).
 template <typename T>
 size_t jacobi_scratch(int64_t l, const DeviceInfo& d);

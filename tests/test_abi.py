@@ -185,3 +185,15 @@ def test_st_hosvd_workspace_size_host_only(lib):
     assert lib.ffsrqr_st_hosvd_workspace_size(9, (C.c_int64 * 9)(*[2] * 9), (C.c_int64 * 9)(*[1] * 9), None, 0,
                                               None, C.byref(out)) == 1
     assert lib.ffsrqr_last_error()
+
+
+def test_rpca_workspace_size_host_only(lib):
+    out = C.c_size_t(0)
+    assert lib.ffsrqr_rpca_workspace_size(1000, 1000, 10, 0, None, C.byref(out)) == 0
+    assert out.value > 3 * 8 * 1000 * 1000
+    small = out.value
+    assert lib.ffsrqr_rpca_workspace_size(1000, 1000, 10, 150, None, C.byref(out)) == 0
+    assert out.value < small
+    assert lib.ffsrqr_rpca_workspace_size(0, 10, 10, 0, None, C.byref(out)) == 1
+    assert lib.ffsrqr_rpca_workspace_size(10, 10, 1024, 0, None, C.byref(out)) == 1
+    assert lib.ffsrqr_last_error()
