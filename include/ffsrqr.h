@@ -335,6 +335,41 @@ ffsrqr_status ffsrqr_st_hosvd(const void* X, int32_t d, const int64_t* dims, con
                               ffsrqr_stream_t stream);
 
 /*
+ * Many independent problems in one call (for the batched shapes: tensor
+ * unfoldings, the rank-k SVDs of singular value thresholding).  Each
+ * ffsrqr_problem carries the arguments of one ffsrqr_factor call (device
+ * pointers for A and the outputs, host pointer for info, which may be NULL);
+ * opts applies to all (its precision fixes the element type).  The problems
+ * run one after another on `stream` through one workspace of
+ * ffsrqr_batched_workspace_size bytes (enough for the largest problem);
+ * their cooperative stages could not run side by side on one device anyway,
+ * since cooperative launches are serialised.  Errors: FFSRQR_EINVAL for
+ * count < 1, a NULL probs, or any problem that ffsrqr_factor would reject
+ * (checked for all problems before any work is enqueued; the message names
+ * the problem); a failure while running stops the batch and is returned.
+ * The call returns after the stream has completed every problem.
+ */
+typedef struct ffsrqr_problem {
+  const void* A;
+  int64_t m, n, lda, k, p;
+  uint64_t seed;
+  int64_t* perm;
+  void* Q;
+  int64_t ldq;
+  void* L;
+  int64_t ldl;
+  void* V;
+  int64_t ldv;
+  double* sigma;
+  ffsrqr_info* info;
+} ffsrqr_problem;
+
+ffsrqr_status ffsrqr_batched_workspace_size(int32_t count, const ffsrqr_problem* probs, const ffsrqr_opts* opts,
+                                            size_t* bytes);
+ffsrqr_status ffsrqr_factor_batched(int32_t count, const ffsrqr_problem* probs, void* work, size_t work_bytes,
+                                    const ffsrqr_opts* opts, ffsrqr_stream_t stream);
+
+/*
  * Robust PCA by the inexact augmented Lagrange multiplier method with
  * Flip-Flop SRQR as its SVD (Section 2, nuclear norm minimization and the
  * robust PCA algorithm; Section 4, the robust PCA experiment): splits

@@ -34,6 +34,13 @@ class Info(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class Problem(C.Structure):
+    _fields_ = [("A", C.c_void_p), ("m", C.c_int64), ("n", C.c_int64), ("lda", C.c_int64), ("k", C.c_int64),
+                ("p", C.c_int64), ("seed", C.c_uint64), ("perm", C.c_void_p), ("Q", C.c_void_p),
+                ("ldq", C.c_int64), ("L", C.c_void_p), ("ldl", C.c_int64), ("V", C.c_void_p),
+                ("ldv", C.c_int64), ("sigma", C.c_void_p), ("info", C.POINTER(Info))]
+
+
 class RpcaInfo(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("rank", C.c_int32), ("residual", C.c_double), ("mu", C.c_double),
                 ("norm2", C.c_double), ("converged", C.c_int32), ("rank_capped", C.c_int32)]
@@ -73,6 +80,8 @@ SIGNATURES = {
                                                  C.POINTER(Opts), C.POINTER(_SZ)]),
     "ffsrqr_st_hosvd": (C.c_int, [_P, _I32, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I32), _I64, _U64, _P,
                                   C.POINTER(_P), C.POINTER(_I64), _P, _SZ, C.POINTER(Opts), _P]),
+    "ffsrqr_batched_workspace_size": (C.c_int, [_I32, C.POINTER(Problem), C.POINTER(Opts), C.POINTER(_SZ)]),
+    "ffsrqr_factor_batched": (C.c_int, [_I32, C.POINTER(Problem), _P, _SZ, C.POINTER(Opts), _P]),
     "ffsrqr_rpca_workspace_size": (C.c_int, [_I64, _I64, _I64, _I64, C.POINTER(Opts), C.POINTER(_SZ)]),
     "ffsrqr_rpca_ialm": (C.c_int, [_P, _I64, _I64, _I64, _D, _D, _I32, _I64, _U64, _I64, _P, _I64, _P, _I64,
                                    C.POINTER(RpcaInfo), _P, _SZ, C.POINTER(Opts), _P]),

@@ -311,6 +311,44 @@ def st_hosvd(X: torch.Tensor, ranks, p: int, seed: int = 0, order=None, mixed: b
     return TuckerResult(core, Us)
 
 
+def factor_batched(As, ks, ps, seeds=None, g: float = 2.0, max_swaps: int = -1, mixed: bool = False, work=None,
+                   stream=None) -> list:
+    """ffsrqr_factor_batched: one call over many problems (column-major A's
+    of one dtype); returns one Factorization per problem."""
+    lib = L.load()
+    cnt = len(As)
+    seeds = [0] * cnt if seeds is None else list(seeds)
+    prec = _prec(As[0].dtype, mixed)
+    o = opts(prec, g, max_swaps)
+    probs = (L.Problem * cnt)()
+    outs, infos = [], []
+    for i, A in enumerate(As):
+        if A.dtype != As[0].dtype:
+            raise TypeError("one dtype for the whole batch")
+        m, n = A.shape
+        k, p = int(ks[i]), int(ps[i])
+        l = min(k + p, m, n)
+        dev = A.device
+        f = Factorization(torch.empty(n, dtype=torch.int64, device=dev), empty_fortran(m, l, A.dtype, dev),
+                          empty_fortran(l, l, A.dtype, dev), empty_fortran(n, l, A.dtype, dev),
+                          torch.empty(l, dtype=torch.float64, device=dev), {})
+        info = L.Info()
+        infos.append(info)
+        outs.append(f)
+        probs[i] = L.Problem(_ptr(A), m, n, _ld(A), k, p, int(seeds[i]), _ptr(f.perm), _ptr(f.Q), m, _ptr(f.L), l,
+                             _ptr(f.V), n, _ptr(f.sigma), C.pointer(info))
+    if work is None:
+        out = C.c_size_t(0)
+        L.check(lib.ffsrqr_batched_workspace_size(cnt, probs, C.byref(o), C.byref(out)),
+                "ffsrqr_batched_workspace_size")
+        work = workspace(out.value, As[0].device, stream)
+    L.check(lib.ffsrqr_factor_batched(cnt, probs, _ptr(work), work.numel(), C.byref(o), _stream(stream)),
+            "ffsrqr_factor_batched")
+    for f, info in zip(outs, infos):
+        f.info.update(info.as_dict())
+    return outs
+
+
 @dataclasses.dataclass
 class RpcaResult:
     X: torch.Tensor       # low-rank part, m x n column-major

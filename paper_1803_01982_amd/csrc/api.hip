@@ -1339,6 +1339,49 @@ ffsrqr_status ffsrqr_st_hosvd(const void* X, int32_t d, const int64_t* dims, con
                            *dv, s);
 }
 
+ffsrqr_status ffsrqr_batched_workspace_size(int32_t count, const ffsrqr_problem* probs, const ffsrqr_opts* opts,
+                                            size_t* bytes) {
+  if (!bytes || !probs || count < 1) return fail(FFSRQR_EINVAL, "need count >= 1, probs and bytes");
+  size_t best = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    size_t b = 0;
+    const ffsrqr_problem& q = probs[i];
+    ffsrqr_status st = ffsrqr_workspace_size(q.m, q.n, q.k, q.p, opts, &b);
+    if (st != FFSRQR_OK) return fail(st, "problem " + std::to_string(i) + ": " + ffsrqr_last_error());
+    best = std::max(best, b);
+  }
+  *bytes = best;
+  return FFSRQR_OK;
+}
+
+ffsrqr_status ffsrqr_factor_batched(int32_t count, const ffsrqr_problem* probs, void* work, size_t work_bytes,
+                                    const ffsrqr_opts* opts, ffsrqr_stream_t stream) {
+  if (!probs || count < 1) return fail(FFSRQR_EINVAL, "need count >= 1 and probs");
+  if (!work) return fail(FFSRQR_EINVAL, "NULL pointer argument");
+  // every problem is checked before any work is enqueued
+  for (int32_t i = 0; i < count; ++i) {
+    const ffsrqr_problem& q = probs[i];
+    ffsrqr_status st = check_dims(q.m, q.n, q.k, q.p);
+    if (st != FFSRQR_OK) return fail(st, "problem " + std::to_string(i) + ": " + ffsrqr_last_error());
+    const int64_t l = std::min(q.k + q.p, std::min(q.m, q.n));
+    if (q.lda < q.m || q.ldq < q.m || q.ldl < l || q.ldv < q.n)
+      return fail(FFSRQR_EINVAL, "problem " + std::to_string(i) + ": leading dimension too small");
+    if (!q.A || !q.perm || !q.Q || !q.L || !q.V || !q.sigma)
+      return fail(FFSRQR_EINVAL, "problem " + std::to_string(i) + ": NULL pointer argument");
+    size_t b = 0;
+    st = ffsrqr_workspace_size(q.m, q.n, q.k, q.p, opts, &b);
+    if (st != FFSRQR_OK) return fail(st, "problem " + std::to_string(i) + ": " + ffsrqr_last_error());
+    if (b > work_bytes) return fail(FFSRQR_EWORKSPACE, "problem " + std::to_string(i) + ": workspace too small");
+  }
+  for (int32_t i = 0; i < count; ++i) {
+    const ffsrqr_problem& q = probs[i];
+    ffsrqr_status st = ffsrqr_factor(q.A, q.m, q.n, q.lda, q.k, q.p, q.seed, q.perm, q.Q, q.ldq, q.L, q.ldl, q.V,
+                                     q.ldv, q.sigma, q.info, work, work_bytes, opts, stream);
+    if (st != FFSRQR_OK) return fail(st, "problem " + std::to_string(i) + ": " + ffsrqr_last_error());
+  }
+  return FFSRQR_OK;
+}
+
 ffsrqr_status ffsrqr_rpca_workspace_size(int64_t m, int64_t n, int64_t p, int64_t max_rank,
                                          const ffsrqr_opts* opts, size_t* bytes) {
   if (!bytes) return fail(FFSRQR_EINVAL, "bytes is NULL");

@@ -30,6 +30,9 @@ Recipes (all seeded, FP64 arithmetic, optionally rounded to FP32 storage):
 * ``rpca_problem``: low rank plus sparse, M = X_L X_R^T + E*, for the
   robust PCA driver (rank 0.1 m and 5% corrupted entries in the paper's
   experiment).
+* ``batch_problems``: many independent problems of mixed shapes (m, n
+  uniform on [500, 4000], sigma_j = j^-1.5, k uniform on [10, 100]) for the
+  batched entry point.
 """
 from __future__ import annotations
 
@@ -45,6 +48,7 @@ __all__ = [
     "make_workload",
     "tucker_tensor",
     "rpca_problem",
+    "batch_problems",
 ]
 
 
@@ -167,6 +171,21 @@ def rpca_problem(m: int, n: int, rank: int, frac: float, seed: int, amp: float =
     E[pos] = rng.uniform(-amp, amp, size=nnz)
     E = np.asfortranarray(E.reshape((m, n), order="F"))
     return np.asfortranarray(X + E), X, E
+
+
+def batch_problems(count: int, seed: int, rmax: int = 512):
+    """`count` problems with m, n uniform on [500, 4000], sigma_j = j^-1.5
+    (j <= min(m, n, rmax); the spectrum is cut there, where it is below
+    1e-4 of sigma_1) and k uniform on [10, 100]: [(A, k)], A Fortran order."""
+    rng = _rng(seed, 40)
+    out = []
+    for i in range(count):
+        m, n = (int(x) for x in rng.integers(500, 4001, size=2))
+        k = int(rng.integers(10, 101))
+        r = min(m, n, rmax)
+        sig = np.arange(1, r + 1, dtype=np.float64) ** -1.5
+        out.append((spectrum_matrix(m, n, sig, seed * 1000 + i), k))
+    return out
 
 
 def make_workload(name: str, dtype=np.float64) -> np.ndarray:

@@ -197,3 +197,22 @@ def test_rpca_workspace_size_host_only(lib):
     assert lib.ffsrqr_rpca_workspace_size(0, 10, 10, 0, None, C.byref(out)) == 1
     assert lib.ffsrqr_rpca_workspace_size(10, 10, 1024, 0, None, C.byref(out)) == 1
     assert lib.ffsrqr_last_error()
+
+
+def test_batched_host_checks(lib):
+    from paper_1803_01982_amd import _lib
+    out = C.c_size_t(0)
+    probs = (_lib.Problem * 2)()
+    probs[0] = _lib.Problem(None, 1000, 800, 1000, 20, 10, 0, None, None, 1000, None, 30, None, 800, None, None)
+    probs[1] = _lib.Problem(None, 600, 900, 600, 40, 10, 0, None, None, 600, None, 50, None, 900, None, None)
+    assert lib.ffsrqr_batched_workspace_size(2, probs, None, C.byref(out)) == 0
+    one = C.c_size_t(0)
+    assert lib.ffsrqr_workspace_size(1000, 800, 20, 10, None, C.byref(one)) == 0
+    assert out.value >= one.value
+    assert lib.ffsrqr_batched_workspace_size(0, probs, None, C.byref(out)) == 1
+    probs[1].k = 0
+    assert lib.ffsrqr_batched_workspace_size(2, probs, None, C.byref(out)) == 1
+    assert b"problem 1" in lib.ffsrqr_last_error()
+    # NULL device pointers are rejected before anything runs (no device needed)
+    probs[1].k = 40
+    assert lib.ffsrqr_factor_batched(2, probs, C.c_void_p(1), 1 << 30, None, None) == 1
