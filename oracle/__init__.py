@@ -43,6 +43,7 @@ from .ffsrqr import (
     round_bf16,
     sketch,
     srqr_rho,
+    trqrcp_pivots,
     upper_inverse,
 )
 from . import diagnostics
@@ -54,6 +55,6 @@ __all__ = [
     "FLAG_RANK_DEFICIENT", "FLAG_SWAPCAP", "Alg9", "Result", "alg9", "back_substitute",
     "factor_leading_set", "ffsrqr", "flip_flop_lq", "householder", "householder_qr",
     "jacobi_svd", "project", "qrcp_sketch", "rank_tolerance", "residual_margin", "residual_norms", "round_bf16",
-    "sketch", "srqr_rho",
+    "sketch", "srqr_rho", "trqrcp_pivots",
     "upper_inverse", "diagnostics", "hosvd", "ialm",
 ]

@@ -173,6 +173,56 @@ def qrcp_sketch(B: np.ndarray, l: int):
 
 
 # ---------------------------------------------------------------------------
+# a2 (blocked): Algorithm 2, truncated randomized QRCP with the sample update
+# ---------------------------------------------------------------------------
+def trqrcp_pivots(A: np.ndarray, l: int, b: int, p: int, seed: int, sketch_mode: str = "fp64",
+                  trace: list | None = None):
+    """Algorithm 2's pivot selection, l pivots in blocks of b.
+
+    The sample B = Omega A has rows = min(b + p, m) rows (Omega from the same
+    Philox stream: the first rows of the l-row Omega).  For each block of
+    bj = min(b, l - j) pivots: partial QRCP (Algorithm 1) on the sample's
+    columns not yet chosen gives the block's pivots; the chosen columns'
+    residual after the previous blocks, A(:, piv) - Q Q^T A(:, piv), is
+    factored (Householder QR, Q_b R11); R12 = Q_b^T A(:, rest); and the sample
+    is updated, B(:, rest) <- B(:, rest) - B(:, piv) R11^{-1} R12, which is
+    Omega times the new residual of the remaining columns.  Returns (S, margins)
+    with S the l pivots in order and margins the QRCP margins of the steps
+    that chose them.  With trace a list, (Q, B, rest) after each block is
+    appended to it.
+    """
+    A = np.asarray(A, dtype=np.float64)
+    m, n = A.shape
+    rows = min(b + p, m)
+    B = sketch(omega(seed, rows, m), A, sketch_mode)
+    active = list(range(n))
+    S: list = []
+    margins: list = []
+    Q = np.zeros((m, 0))
+    while len(S) < l:
+        bj = min(b, l - len(S))
+        perm, mg, _ = qrcp_sketch(B[:, active], bj)
+        piv = [active[int(i)] for i in perm[:bj]]
+        margins.extend(float(x) for x in mg[:bj])
+        P = A[:, piv]
+        for _ in range(2):  # the residual after the previous blocks (two projections)
+            P = P - Q @ (Q.T @ P)
+        Qb, R11 = householder_qr(P)
+        chosen = set(piv)
+        rest = [c for c in active if c not in chosen]
+        if rest:
+            R12 = Qb.T @ A[:, rest]
+            X = np.column_stack([back_substitute(R11, R12[:, t]) for t in range(len(rest))])
+            B[:, rest] = B[:, rest] - B[:, piv] @ X
+        Q = np.hstack([Q, Qb])
+        S.extend(piv)
+        active = rest
+        if trace is not None:
+            trace.append((Q.copy(), B.copy(), list(rest)))
+    return S, np.asarray(margins)
+
+
+# ---------------------------------------------------------------------------
 # a3: Householder QR (no pivoting) of a tall panel, explicit Q1
 # ---------------------------------------------------------------------------
 def householder_qr(P: np.ndarray):
@@ -413,7 +463,7 @@ def rank_tolerance(m: int, n: int, max_col_norm: float, storage: str = "fp64") -
 
 def ffsrqr(A: np.ndarray, k: int, p: int, seed: int, g: float = 2.0,
            max_swaps: int | None = None, Omega: np.ndarray | None = None,
-           sketch_mode: str = "fp64", storage: str = "fp64") -> Result:
+           sketch_mode: str = "fp64", storage: str = "fp64", block: int = 0) -> Result:
     """Flip-Flop SRQR hot path, FP64 (Algorithm 9 up to the LQ, Algorithm 4 inside).
 
     sketch_mode selects the arithmetic of B = Omega A ("fp64" or "bf16", see
@@ -444,12 +494,18 @@ def ffsrqr(A: np.ndarray, k: int, p: int, seed: int, g: float = 2.0,
     colnorm = np.sqrt(np.sum(Af * Af, axis=0))
     tau_r = rank_tolerance(m, n, float(colnorm.max()), storage)
 
-    # a1
-    Om = omega(seed, l, m) if Omega is None else Omega
-    B = sketch(Om, Af, sketch_mode)
-    # a2
-    pivots, margins, _ = qrcp_sketch(B, l)
-    S = [int(s) for s in pivots[:l]]
+    if block > 0:
+        # a1 + a2 blocked: Algorithm 2 with a (block + p)-row sample
+        S, margins = trqrcp_pivots(Af, l, block, p, seed, sketch_mode)
+        S = [int(s) for s in S]
+        B = None
+    else:
+        # a1
+        Om = omega(seed, l, m) if Omega is None else Omega
+        B = sketch(Om, Af, sketch_mode)
+        # a2
+        pivots, margins, _ = qrcp_sketch(B, l)
+        S = [int(s) for s in pivots[:l]]
 
     swaps = 0
     history = []
