@@ -88,6 +88,13 @@ typedef struct {
   int32_t max_swaps; /* cap of the SRQR swap loop; < 0 selects the default 4*l     */
   double g;          /* SRQR tolerance for g2 (Section 2.2: g > 1, e.g. 2.0);
                         0 selects 2.0                                             */
+  int32_t block;     /* 0: the l pivots from one partial QRCP on an l-row sketch;
+                        1..64: Algorithm 2's blocked selection (TRQRCP): blocks
+                        of min(block, k) pivots, each from partial QRCP on a
+                        min(block + p, m)-row sample of the columns in play,
+                        the sample updated after each block (needs
+                        n - l + 1 >= min(block + p, m))                          */
+  int32_t reserved;  /* 0                                                         */
 } ffsrqr_opts;
 
 typedef struct {

@@ -495,8 +495,8 @@ def ffsrqr(A: np.ndarray, k: int, p: int, seed: int, g: float = 2.0,
     tau_r = rank_tolerance(m, n, float(colnorm.max()), storage)
 
     if block > 0:
-        # a1 + a2 blocked: Algorithm 2 with a (block + p)-row sample
-        S, margins = trqrcp_pivots(Af, l, block, p, seed, sketch_mode)
+        # a1 + a2 blocked: Algorithm 2 with a (b + p)-row sample, b = min(block, k)
+        S, margins = trqrcp_pivots(Af, l, min(block, k), p, seed, sketch_mode)
         S = [int(s) for s in S]
         B = None
     else:

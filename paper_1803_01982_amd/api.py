@@ -56,14 +56,14 @@ def _ptr(t) -> int:
     return t.data_ptr() if t is not None else 0
 
 
-def opts(precision=L.FP64, g: float = 2.0, max_swaps: int = -1) -> L.Opts:
-    return L.Opts(precision=precision, max_swaps=max_swaps, g=g)
+def opts(precision=L.FP64, g: float = 2.0, max_swaps: int = -1, block: int = 0) -> L.Opts:
+    return L.Opts(precision=precision, max_swaps=max_swaps, g=g, block=block, reserved=0)
 
 
-def workspace_size(m: int, n: int, k: int, p: int, precision=L.FP64) -> int:
+def workspace_size(m: int, n: int, k: int, p: int, precision=L.FP64, block: int = 0) -> int:
     lib = L.load()
     out = C.c_size_t(0)
-    o = opts(precision)
+    o = opts(precision, block=block)
     L.check(lib.ffsrqr_workspace_size(m, n, k, p, C.byref(o), C.byref(out)), "ffsrqr_workspace_size")
     return out.value
 
@@ -109,7 +109,7 @@ class Factorization:
 
 
 def factor(A: torch.Tensor, k: int, p: int, seed: int = 0, g: float = 2.0, max_swaps: int = -1,
-           work: torch.Tensor | None = None, stream=None, mixed: bool = False) -> Factorization:
+           work: torch.Tensor | None = None, stream=None, mixed: bool = False, block: int = 0) -> Factorization:
     """ffsrqr_factor: A (m x n, column-major, float64 or float32) -> perm, Q, L, V, sigma, info.
     mixed=True (float32 A) selects FFSRQR_MIXED (BF16 sketch, split-BF16 projection)."""
     lib = L.load()
@@ -124,9 +124,9 @@ def factor(A: torch.Tensor, k: int, p: int, seed: int = 0, g: float = 2.0, max_s
     V = empty_fortran(n, l, A.dtype, dev)
     sigma = torch.empty(l, dtype=torch.float64, device=dev)
     if work is None:
-        work = workspace(workspace_size(m, n, k, p, prec), dev, stream)
+        work = workspace(workspace_size(m, n, k, p, prec, block), dev, stream)
     info = L.Info()
-    o = opts(prec, g, max_swaps)
+    o = opts(prec, g, max_swaps, block)
     L.check(lib.ffsrqr_factor(_ptr(A), m, n, lda, k, p, seed, _ptr(perm), _ptr(Q), m, _ptr(Lf), l,
                               _ptr(V), n, _ptr(sigma), C.byref(info), _ptr(work), work.numel(),
                               C.byref(o), _stream(stream)), "ffsrqr_factor")

@@ -122,8 +122,9 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // Persistent buffers of the whole path followed by one scratch region shared
 // by the stages (they run in stream order).
 template <typename T>
-size_t scratch_bytes(int64_t m, int64_t n, int64_t l, const DeviceInfo& d) {
+size_t scratch_bytes(int64_t m, int64_t n, int64_t l, const DeviceInfo& d, int64_t block = 0, int64_t p = 0) {
   size_t s = 0;
+  if (block > 0) s = std::max(s, trqrcp_scratch<T>(m, n, l, block, p, d));
   s = std::max(s, gemm_tn_scratch<T>(l, n, m, d.num_cu));
   if (sizeof(T) == 4) s = std::max(s, gemm_bf16_scratch(l, n, m, d.num_cu));
   s = std::max(s, qrcp_scratch<T>(l, n, d));
@@ -155,8 +156,8 @@ size_t persistent_bytes(int64_t m, int64_t n, int64_t l) {
 }
 
 template <typename T>
-size_t total_bytes(int64_t m, int64_t n, int64_t l, const DeviceInfo& d) {
-  return persistent_bytes<T>(m, n, l) + scratch_bytes<T>(m, n, l, d);
+size_t total_bytes(int64_t m, int64_t n, int64_t l, const DeviceInfo& d, int64_t block = 0, int64_t p = 0) {
+  return persistent_bytes<T>(m, n, l) + scratch_bytes<T>(m, n, l, d, block, p);
 }
 
 ffsrqr_status get_device(const DeviceInfo** out) {
@@ -248,6 +249,18 @@ ffsrqr_status check_limits(int64_t m, int64_t n, int64_t l, const DeviceInfo& d)
   return FFSRQR_OK;
 }
 
+// The blocked selection (opts.block > 0): blocks of at most 64 pivots, and
+// enough columns that the sample of the columns in play never has fewer
+// columns than rows (n - l + 1 >= min(block + p, m)).
+ffsrqr_status check_block(int64_t m, int64_t n, int64_t k, int64_t p, int64_t l, int32_t block) {
+  if (block < 0 || block > 64) return fail(FFSRQR_EINVAL, "block must be 0 (one block) or 1..64");
+  if (block == 0) return FFSRQR_OK;
+  const int64_t b = std::min<int64_t>(block, k);
+  if (n - l + 1 < trqrcp_rows(m, b, p))
+    return fail(FFSRQR_EINVAL, "blocked selection needs n - l + 1 >= min(block + p, m)");
+  return FFSRQR_OK;
+}
+
 // The device the limits are checked against when no device is at hand: a
 // 256-CU gfx950 with 160 KiB of LDS per workgroup.
 DeviceInfo limits_device() {
@@ -301,7 +314,8 @@ ffsrqr_status factor_impl(const T* A, int64_t m, int64_t n, int64_t lda, int64_t
   const int64_t mp = bf16_ld(m);
   const int64_t l = std::min(k + p, std::min(m, n));
   uint32_t flags = (l < k + p) ? FFSRQR_FLAG_L_CLAMPED : 0u;
-  const size_t need = total_bytes<T>(m, n, l, d);
+  const int64_t blk0 = op.block > 0 ? std::min<int64_t>(op.block, k) : 0;
+  const size_t need = total_bytes<T>(m, n, l, d, blk0, p);
   if (work_bytes < need)
     return fail(FFSRQR_EWORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
 
@@ -331,19 +345,23 @@ ffsrqr_status factor_impl(const T* A, int64_t m, int64_t n, int64_t lda, int64_t
   }
   StepTimer tm(s);
   FF_HIP(zero_words(err, 64, s));
-  // a1: Omega and the sketch (one pass over A, column norms fused)
+  // a1: Omega and the sketch (one pass over A, column norms fused); with
+  // the blocked selection (Algorithm 2's blocks) the sample has
+  // min(block + p, m) rows instead of l
+  const int64_t blk = op.block > 0 ? std::min<int64_t>(op.block, k) : 0;
+  const int64_t srows = blk > 0 ? trqrcp_rows(m, blk, p) : l;
   tm.begin(FFSRQR_STEP_OMEGA);
-  if (mixed) FF_HIP(launch_omega<__bf16>(seed, l, m, (__bf16*)region1, mp, s));
-  else FF_HIP(launch_omega<T>(seed, l, m, region1, m, s));
+  if (mixed) FF_HIP(launch_omega<__bf16>(seed, srows, m, (__bf16*)region1, mp, s));
+  else FF_HIP(launch_omega<T>(seed, srows, m, region1, m, s));
   tm.end();
   {
     Arena a = scratch();
     tm.begin(FFSRQR_STEP_SKETCH);
     if (mixed)
-      FF_HIP(gemm_bf16(1, l, n, m, (const __bf16*)region1, nullptr, mp, (const float*)A, lda, (float*)region2, l,
-                       anorm2, a, d.num_cu, s));
+      FF_HIP(gemm_bf16(1, srows, n, m, (const __bf16*)region1, nullptr, mp, (const float*)A, lda, (float*)region2,
+                       srows, anorm2, a, d.num_cu, s));
     else
-      FF_HIP(gemm_tn<T>(l, n, m, region1, m, A, lda, region2, l, anorm2, a, d.num_cu, s));
+      FF_HIP(gemm_tn<T>(srows, n, m, region1, m, A, lda, region2, srows, anorm2, a, d.num_cu, s));
     tm.end();
   }
   // non-finite input: report and stop before any pivoting
@@ -384,11 +402,17 @@ ffsrqr_status factor_impl(const T* A, int64_t m, int64_t n, int64_t lda, int64_t
       return FFSRQR_OK;
     }
   }
-  // a2: partial QRCP on the sketch -> S
+  // a2: partial QRCP on the sketch -> S (or Algorithm 2's blocks of it)
   {
     Arena a = scratch();
     tm.begin(FFSRQR_STEP_QRCP);
-    FF_HIP(qrcp<T>(region2, l, n, l, S, margins, a, err, d, s));
+    if (blk > 0) {
+      const hipError_t e = trqrcp_select<T>(A, m, n, lda, l, blk, p, region2, S, margins, a, err, d, s);
+      if (e == hipErrorInvalidValue) return fail(FFSRQR_EHIP, "blocked pivot selection: invalid pivot");
+      FF_HIP(e);
+    } else {
+      FF_HIP(qrcp<T>(region2, l, n, l, S, margins, a, err, d, s));
+    }
     tm.end();
   }
   std::vector<double> hmarg((size_t)l);
@@ -997,6 +1021,8 @@ void ffsrqr_default_opts(ffsrqr_opts* o) {
   o->precision = FFSRQR_FP64;
   o->max_swaps = -1;
   o->g = 2.0;
+  o->block = 0;
+  o->reserved = 0;
 }
 
 const char* ffsrqr_status_string(ffsrqr_status s) {
@@ -1052,7 +1078,12 @@ ffsrqr_status ffsrqr_workspace_size(int64_t m, int64_t n, int64_t k, int64_t p, 
   st = check_limits(m, n, l, limits_device());
   if (st != FFSRQR_OK) return st;
   const DeviceInfo d = sizing_device();
-  *bytes = prec == FFSRQR_FP64 ? total_bytes<double>(m, n, l, d) : total_bytes<float>(m, n, l, d);
+  const int64_t blk = opts && opts->block > 0 ? std::min<int64_t>(opts->block, k) : 0;
+  if (opts && opts->block != 0) {
+    st = check_block(m, n, k, p, l, opts->block);
+    if (st != FFSRQR_OK) return st;
+  }
+  *bytes = prec == FFSRQR_FP64 ? total_bytes<double>(m, n, l, d, blk, p) : total_bytes<float>(m, n, l, d, blk, p);
   return FFSRQR_OK;
 }
 
@@ -1068,6 +1099,8 @@ ffsrqr_status ffsrqr_factor(const void* A, int64_t m, int64_t n, int64_t lda, in
   if (!(op.g > 1.0)) return fail(FFSRQR_EINVAL, "g must be > 1");
   if (lda < m || ldq < m || ldl < l || ldv < n) return fail(FFSRQR_EINVAL, "leading dimension too small");
   if (!A || !perm || !Q || !L || !V || !sigma || !work) return fail(FFSRQR_EINVAL, "NULL pointer argument");
+  st = check_block(m, n, k, p, l, op.block);
+  if (st != FFSRQR_OK) return st;
   const DeviceInfo* d = nullptr;
   st = get_device(&d);
   if (st != FFSRQR_OK) return st;

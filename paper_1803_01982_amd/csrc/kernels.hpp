@@ -140,6 +140,19 @@ template <typename T>
 hipError_t srqr_rho(const T* R11, int64_t ldr, const T* a, int64_t a_stride, const SrqrState* sel,
                     double alpha_host, int64_t l, double* rho, SrqrState* st_out, Arena& ar, hipStream_t s);
 
+// Algorithm 2's blocked pivot selection: l pivots S (and their QRCP
+// margins) in blocks of b <= 64 from the sample B (rows x n, ldb = rows,
+// rows = trqrcp_rows(m, b, p) = min(b + p, m), formed by the caller and
+// updated in place); needs n - l + 1 >= rows.  Synchronises the stream.
+int64_t trqrcp_rows(int64_t m, int64_t b, int64_t p);
+size_t trqrcp_lds(int64_t b, int64_t rows);
+template <typename T>
+size_t trqrcp_scratch(int64_t m, int64_t n, int64_t l, int64_t b, int64_t p, const DeviceInfo& d);
+template <typename T>
+hipError_t trqrcp_select(const T* A, int64_t m, int64_t n, int64_t lda, int64_t l, int64_t b, int64_t p, T* B,
+                         int64_t* S, double* margins, Arena& ar, unsigned* err, const DeviceInfo& d,
+                         hipStream_t s);
+
 // One swap of Algorithm 4 as an update in place of A(:, S) = Q R11 and
 // W = Q^T A: leading position istar leaves, trailing column jstar becomes
 // the last leading column (rotations on R11, W and Q, one new column of Q by

@@ -216,3 +216,17 @@ def test_batched_host_checks(lib):
     # NULL device pointers are rejected before anything runs (no device needed)
     probs[1].k = 40
     assert lib.ffsrqr_factor_batched(2, probs, C.c_void_p(1), 1 << 30, None, None) == 1
+
+
+def test_block_option_checks(lib):
+    from paper_1803_01982_amd import _lib
+    out = C.c_size_t(0)
+    o = _lib.Opts(0, -1, 2.0, 32, 0)
+    assert lib.ffsrqr_workspace_size(16384, 8192, 256, 16, C.byref(o), C.byref(out)) == 0
+    big = out.value
+    assert lib.ffsrqr_workspace_size(16384, 8192, 256, 16, C.byref(_lib.Opts(0, -1, 2.0)), C.byref(out)) == 0
+    assert big >= out.value
+    assert lib.ffsrqr_workspace_size(100, 80, 20, 10, C.byref(_lib.Opts(0, -1, 2.0, 65, 0)), C.byref(out)) == 1
+    # n - l + 1 < block + p: too few columns for the blocked sample
+    assert lib.ffsrqr_workspace_size(100, 40, 20, 10, C.byref(_lib.Opts(0, -1, 2.0, 16, 0)), C.byref(out)) == 1
+    assert b"blocked" in lib.ffsrqr_last_error()
