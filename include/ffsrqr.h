@@ -26,7 +26,8 @@
  *    anorm2, gamma2, sigma and work are DEVICE pointers (hipMalloc'd memory
  *    of the current device); info and bytes are HOST pointers.
  *  - The caller owns every buffer.  A is read-only.  No entry point allocates
- *    device memory: scratch lives in the caller's workspace.
+ *    device memory (scratch lives in the caller's workspace), except
+ *    ffsrqr_server_create, which allocates the server's pool once.
  *  - precision: FFSRQR_FP64 means double storage and arithmetic everywhere;
  *    FFSRQR_FP32 means float storage of A and of the float outputs and
  *    intermediates (Q, L, V, B, R, W, the panel between its 16-column
@@ -69,7 +70,8 @@ typedef enum {
   FFSRQR_EINVAL = 1,
   FFSRQR_EWORKSPACE = 2,
   FFSRQR_EHIP = 3,
-  FFSRQR_ENODEV = 4
+  FFSRQR_ENODEV = 4,
+  FFSRQR_EBUSY = 5 /* a server request ended unrun: the server was destroyed first */
 } ffsrqr_status;
 
 typedef enum { FFSRQR_FP64 = 0, FFSRQR_FP32 = 1, FFSRQR_MIXED = 2 } ffsrqr_precision;
@@ -375,6 +377,40 @@ ffsrqr_status ffsrqr_batched_workspace_size(int32_t count, const ffsrqr_problem*
                                             size_t* bytes);
 ffsrqr_status ffsrqr_factor_batched(int32_t count, const ffsrqr_problem* probs, void* work, size_t work_bytes,
                                     const ffsrqr_opts* opts, ffsrqr_stream_t stream);
+
+/*
+ * Serving: a request loop over the path (continuous batching).  A server
+ * owns one device allocation of cfg->hbm_budget bytes (made by
+ * ffsrqr_server_create on the current device) and cfg->slots worker threads
+ * (1..16), each with its own stream.  ffsrqr_submit queues a request (an
+ * ffsrqr_problem: A and the outputs are device pointers the caller owns and
+ * keeps alive until the request is done; its info field is ignored) and
+ * returns a ticket; requests are admitted in arrival order as soon as a
+ * slot is free and the request's workspace (ffsrqr_workspace_size with the
+ * server's precision) fits the free part of the budget, so requests that
+ * arrive while others run join them as slots and memory free up.  Each runs
+ * ffsrqr_factor with cfg->precision and default options.  ffsrqr_poll sets
+ * *done; once done, it returns the request's status and its info (host
+ * pointer, may be NULL) and forgets the ticket.  ffsrqr_server_destroy
+ * waits for the running requests, ends the queued ones unrun (their status
+ * FFSRQR_EBUSY) and frees the pool.
+ * Errors: create returns NULL for a NULL cfg, a budget below 1 MiB, slots
+ * outside 1..16, an unknown precision or a failed allocation; submit returns
+ * what ffsrqr_workspace_size returns for the problem, FFSRQR_EWORKSPACE when
+ * its workspace exceeds the budget, FFSRQR_EBUSY once the server is being
+ * destroyed; poll returns FFSRQR_EINVAL for an unknown ticket.
+ */
+typedef struct ffsrqr_server_cfg {
+  size_t hbm_budget;  /* bytes of the device pool                               */
+  int32_t slots;      /* worker threads (requests running at once), 1..16        */
+  int32_t precision;  /* ffsrqr_precision of every request                       */
+} ffsrqr_server_cfg;
+typedef struct ffsrqr_server ffsrqr_server;
+
+ffsrqr_server* ffsrqr_server_create(const ffsrqr_server_cfg* cfg);
+ffsrqr_status ffsrqr_submit(ffsrqr_server* server, const ffsrqr_problem* prob, uint64_t* ticket);
+ffsrqr_status ffsrqr_poll(ffsrqr_server* server, uint64_t ticket, ffsrqr_info* out, int32_t* done);
+void ffsrqr_server_destroy(ffsrqr_server* server);
 
 /*
  * Robust PCA by the inexact augmented Lagrange multiplier method with

@@ -42,6 +42,10 @@ class Problem(C.Structure):
                 ("ldv", C.c_int64), ("sigma", C.c_void_p), ("info", C.POINTER(Info))]
 
 
+class ServerCfg(C.Structure):
+    _fields_ = [("hbm_budget", C.c_size_t), ("slots", C.c_int32), ("precision", C.c_int32)]
+
+
 class RpcaInfo(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("rank", C.c_int32), ("residual", C.c_double), ("mu", C.c_double),
                 ("norm2", C.c_double), ("converged", C.c_int32), ("rank_capped", C.c_int32)]
@@ -83,6 +87,10 @@ SIGNATURES = {
                                   C.POINTER(_P), C.POINTER(_I64), _P, _SZ, C.POINTER(Opts), _P]),
     "ffsrqr_batched_workspace_size": (C.c_int, [_I32, C.POINTER(Problem), C.POINTER(Opts), C.POINTER(_SZ)]),
     "ffsrqr_factor_batched": (C.c_int, [_I32, C.POINTER(Problem), _P, _SZ, C.POINTER(Opts), _P]),
+    "ffsrqr_server_create": (C.c_void_p, [C.POINTER(ServerCfg)]),
+    "ffsrqr_submit": (C.c_int, [_P, C.POINTER(Problem), C.POINTER(_U64)]),
+    "ffsrqr_poll": (C.c_int, [_P, _U64, C.POINTER(Info), C.POINTER(_I32)]),
+    "ffsrqr_server_destroy": (None, [_P]),
     "ffsrqr_rpca_workspace_size": (C.c_int, [_I64, _I64, _I64, _I64, C.POINTER(Opts), C.POINTER(_SZ)]),
     "ffsrqr_rpca_ialm": (C.c_int, [_P, _I64, _I64, _I64, _D, _D, _I32, _I64, _U64, _I64, _P, _I64, _P, _I64,
                                    C.POINTER(RpcaInfo), _P, _SZ, C.POINTER(Opts), _P]),

@@ -349,6 +349,61 @@ def factor_batched(As, ks, ps, seeds=None, g: float = 2.0, max_swaps: int = -1, 
     return outs
 
 
+class Server:
+    """ffsrqr_server_*: a serving loop (continuous batching) over the path.
+    submit() allocates the request's outputs on A's device and keeps them
+    (and A) alive until poll() reports the request done; A must be ready on
+    the device (its producing stream synchronised) when it is submitted."""
+
+    def __init__(self, budget_bytes: int, slots: int = 4, precision=L.FP32):
+        self._lib = L.load()
+        cfg = L.ServerCfg(int(budget_bytes), int(slots), int(precision))
+        self._h = self._lib.ffsrqr_server_create(C.byref(cfg))
+        if not self._h:
+            raise L.FfsrqrError(1, "ffsrqr_server_create (configuration or device allocation)")
+        self._live = {}
+
+    def submit(self, A: torch.Tensor, k: int, p: int, seed: int = 0) -> int:
+        m, n = A.shape
+        l = min(k + p, m, n)
+        dev = A.device
+        f = Factorization(torch.empty(n, dtype=torch.int64, device=dev), empty_fortran(m, l, A.dtype, dev),
+                          empty_fortran(l, l, A.dtype, dev), empty_fortran(n, l, A.dtype, dev),
+                          torch.empty(l, dtype=torch.float64, device=dev), {})
+        torch.cuda.current_stream(dev).synchronize()  # outputs allocated, A ready
+        prob = L.Problem(_ptr(A), m, n, _ld(A), k, p, seed, _ptr(f.perm), _ptr(f.Q), m, _ptr(f.L), l, _ptr(f.V), n,
+                         _ptr(f.sigma), None)
+        t = C.c_uint64(0)
+        L.check(self._lib.ffsrqr_submit(self._h, C.byref(prob), C.byref(t)), "ffsrqr_submit")
+        self._live[t.value] = (A, f)
+        return t.value
+
+    def poll(self, ticket: int):
+        """(done, Factorization or None); a done ticket is forgotten."""
+        info = L.Info()
+        done = C.c_int32(0)
+        st = self._lib.ffsrqr_poll(self._h, ticket, C.byref(info), C.byref(done))
+        if not done.value:
+            L.check(st, "ffsrqr_poll")
+            return False, None
+        A, f = self._live.pop(ticket)
+        L.check(st, "ffsrqr_poll")
+        f.info.update(info.as_dict())
+        return True, f
+
+    def close(self) -> None:
+        if self._h:
+            self._lib.ffsrqr_server_destroy(self._h)
+            self._h = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 @dataclasses.dataclass
 class RpcaResult:
     X: torch.Tensor       # low-rank part, m x n column-major

@@ -1032,6 +1032,7 @@ const char* ffsrqr_status_string(ffsrqr_status s) {
     case FFSRQR_EWORKSPACE: return "workspace too small";
     case FFSRQR_EHIP: return "HIP runtime error";
     case FFSRQR_ENODEV: return "no usable gfx950 device";
+    case FFSRQR_EBUSY: return "request ended unrun";
   }
   return "unknown status";
 }

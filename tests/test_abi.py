@@ -230,3 +230,15 @@ def test_block_option_checks(lib):
     # n - l + 1 < block + p: too few columns for the blocked sample
     assert lib.ffsrqr_workspace_size(100, 40, 20, 10, C.byref(_lib.Opts(0, -1, 2.0, 16, 0)), C.byref(out)) == 1
     assert b"blocked" in lib.ffsrqr_last_error()
+
+
+def test_server_rejects_bad_config(lib):
+    from paper_1803_01982_amd import _lib
+    assert not lib.ffsrqr_server_create(None)
+    assert not lib.ffsrqr_server_create(C.byref(_lib.ServerCfg(1 << 30, 0, 1)))
+    assert not lib.ffsrqr_server_create(C.byref(_lib.ServerCfg(1 << 30, 17, 1)))
+    assert not lib.ffsrqr_server_create(C.byref(_lib.ServerCfg(1 << 10, 2, 1)))
+    assert not lib.ffsrqr_server_create(C.byref(_lib.ServerCfg(1 << 30, 2, 9)))
+    t = C.c_uint64(0)
+    assert lib.ffsrqr_submit(None, None, C.byref(t)) == 1
+    lib.ffsrqr_server_destroy(None)
