@@ -32,9 +32,11 @@ from .ffsrqr import (
     factor_leading_set,
     ffsrqr,
     flip_flop_lq,
+    g2_probe_estimate,
     householder,
     householder_qr,
     jacobi_svd,
+    probe_omega,
     project,
     qrcp_sketch,
     rank_tolerance,
@@ -53,8 +55,8 @@ from . import ialm
 __all__ = [
     "omega", "philox4x64_10", "uniform_open", "FLAG_L_CLAMPED", "FLAG_NONFINITE",
     "FLAG_RANK_DEFICIENT", "FLAG_SWAPCAP", "Alg9", "Result", "alg9", "back_substitute",
-    "factor_leading_set", "ffsrqr", "flip_flop_lq", "householder", "householder_qr",
-    "jacobi_svd", "project", "qrcp_sketch", "rank_tolerance", "residual_margin", "residual_norms", "round_bf16",
+    "factor_leading_set", "ffsrqr", "flip_flop_lq", "g2_probe_estimate", "householder",
+    "householder_qr", "jacobi_svd", "probe_omega", "project", "qrcp_sketch", "rank_tolerance", "residual_margin", "residual_norms", "round_bf16",
     "sketch", "srqr_rho", "trqrcp_pivots",
     "upper_inverse", "diagnostics", "hosvd", "ialm",
 ]

@@ -23,7 +23,12 @@ Spectrum-Revealing QR Factorization"):
                factorization (Section 2.1, block form; Section 3.1, partial
                QRCP on A to l steps).
   srqr_rho     g2 of Section 2.2 (definitions of R-tilde, g1, g2), computed
-               exactly (no random probe).
+               exactly.
+  g2_probe_estimate
+               Algorithm 4's randomized estimate of the same quantity: the
+               column norms of Omega_q R-tilde^{-T} scaled by |alpha| / sqrt(d),
+               Omega_q a fresh d x (l+1) Gaussian probe per test (an option of
+               ffsrqr; the exact g2 is the default).
   ffsrqr       Algorithm 4 (SRQR) swap loop around the above, then Section
                3.1: QR without pivoting of (R11 R12)^T, L = Rhat11^T,
                V = Pi Qhat1, and sigma(L) by one-sided Jacobi.
@@ -40,7 +45,13 @@ design notes):
     downdating), ties go to the smallest original column index.
   * Residual norms gamma_j of the trailing columns are exact,
     ||(I - Q1 Q1^T) a_j||, not the sketch estimate of Algorithm 4.
-  * g2 is exact: |alpha| * max row norm of R-tilde^{-1}.
+  * g2 is exact by default: |alpha| * max row norm of R-tilde^{-1}.  With
+    g2_probe = d > 0 it is Algorithm 4's estimate instead: the q-th test of a
+    solve (q = 1, 2, ...) draws Omega_q (d x (l+1)) from the Philox stream q,
+    g2 is the largest estimated column norm over all l+1 positions and i* its
+    argmax; when i* is position l+1 the round-robin rotation is the identity
+    and the next test only draws a fresh probe.  The swap cap counts these
+    identity rotations too.
   * A swap (Algorithm 4's round-robin rotation) replaces S[i*] by j*: the new
     ordered leading set is S without S[i*], followed by j*.  The factorization
     of the new set is recomputed from scratch instead of Givens updates; thin
@@ -319,6 +330,29 @@ def srqr_rho(R11: np.ndarray, a: np.ndarray, alpha: float) -> np.ndarray:
     return abs(alpha) * np.sqrt(np.sum(X * X, axis=1))
 
 
+def probe_omega(seed: int, q: int, d: int, l: int) -> np.ndarray:
+    """The q-th probe (q >= 1) of a solve: d x (l+1) N(0,1), Philox stream q."""
+    if q < 1:
+        raise ValueError("probe streams start at 1 (stream 0 is the sketch)")
+    return _omega(seed, d, l + 1, stream=q)
+
+
+def g2_probe_estimate(R11: np.ndarray, a: np.ndarray, alpha: float, Om: np.ndarray) -> np.ndarray:
+    """Algorithm 4's estimate of g2 (Section 2.2; Algorithm 4, the g2 step):
+    est_i = |alpha| / sqrt(d) * (i-th column 2-norm of Om R-tilde^{-T}),
+    i = 1..l+1, for a d x (l+1) probe Om with N(0,1) entries.  Since
+    E ||Om x||^2 = d ||x||^2, est_i^2 is an unbiased estimate of rho_i^2
+    (srqr_rho); g2 ~ max_i est_i."""
+    l = R11.shape[0]
+    d = Om.shape[0]
+    Rt = np.zeros((l + 1, l + 1))
+    Rt[:l, :l] = R11
+    Rt[:l, l] = a
+    Rt[l, l] = alpha
+    Y = Om @ upper_inverse(Rt).T
+    return abs(alpha) / math.sqrt(d) * np.sqrt(np.sum(Y * Y, axis=0))
+
+
 # ---------------------------------------------------------------------------
 # a6: flip-flop LQ and right factor
 # ---------------------------------------------------------------------------
@@ -412,6 +446,7 @@ class Result:
     B: np.ndarray           # sketch (l x n)
     history: list           # [(S, g2, jstar, alpha)] per SRQR test
     sketch_mode: str = "fp64"
+    probes: int = 0         # random probes drawn (0: exact g2)
 
 
 def _full_perm(S, n):
@@ -463,17 +498,19 @@ def rank_tolerance(m: int, n: int, max_col_norm: float, storage: str = "fp64") -
 
 def ffsrqr(A: np.ndarray, k: int, p: int, seed: int, g: float = 2.0,
            max_swaps: int | None = None, Omega: np.ndarray | None = None,
-           sketch_mode: str = "fp64", storage: str = "fp64", block: int = 0) -> Result:
+           sketch_mode: str = "fp64", storage: str = "fp64", block: int = 0,
+           g2_probe: int = 0) -> Result:
     """Flip-Flop SRQR hot path, FP64 (Algorithm 9 up to the LQ, Algorithm 4 inside).
 
     sketch_mode selects the arithmetic of B = Omega A ("fp64" or "bf16", see
     sketch()); every later step is FP64 on the same A.  storage names the
     precision the data is held in ("fp64" or "fp32"); it only sets the rank
-    tolerance (rank_tolerance()).
+    tolerance (rank_tolerance()).  g2_probe = d > 0 replaces the exact g2 by
+    Algorithm 4's d-row random estimate (g2_probe_estimate, probe_omega).
     """
     A = np.asarray(A)
     m, n = A.shape
-    if not (1 <= k <= min(m, n)) or p < 0 or not g > 1.0:
+    if not (1 <= k <= min(m, n)) or p < 0 or not g > 1.0 or g2_probe < 0:
         raise ValueError("bad arguments")
     flags = 0
     l = min(k + p, m, n)
@@ -508,6 +545,8 @@ def ffsrqr(A: np.ndarray, k: int, p: int, seed: int, g: float = 2.0,
         S = [int(s) for s in pivots[:l]]
 
     swaps = 0
+    rotations = 0   # loop iterations: the swaps plus identity rotations of the probe
+    q = 0           # SRQR tests so far (the probe stream of the next one is q + 1)
     history = []
     numerical_rank = l
     jmargin = 1.0
@@ -531,17 +570,25 @@ def ffsrqr(A: np.ndarray, k: int, p: int, seed: int, g: float = 2.0,
                 g2 = 1.0
                 history.append((list(S), g2, jstar, alpha))
                 break
-            rho = srqr_rho(R11, W[:, jstar], alpha)
-            g2 = float(rho.max())
+            q += 1
+            if g2_probe > 0:
+                est = g2_probe_estimate(R11, W[:, jstar], alpha, probe_omega(seed, q, g2_probe, l))
+                g2 = float(est.max())
+                istar = int(np.argmax(est))       # 0..l; l is the (l+1)-st position
+            else:
+                rho = srqr_rho(R11, W[:, jstar], alpha)
+                g2 = float(rho.max())
+                istar = int(np.argmax(rho[:l]))
             history.append((list(S), g2, jstar, alpha))
             if g2 <= g:
                 break
-            if swaps >= max_swaps:
+            if rotations >= max_swaps:
                 flags |= FLAG_SWAPCAP
                 break
-            istar = int(np.argmax(rho[:l]))
-            S = S[:istar] + S[istar + 1:] + [jstar]
-            swaps += 1
+            rotations += 1
+            if istar < l:
+                S = S[:istar] + S[istar + 1:] + [jstar]
+                swaps += 1
         else:
             jstar, alpha, g2 = -1, 0.0, 1.0
             history.append((list(S), g2, jstar, alpha))
@@ -554,7 +601,7 @@ def ffsrqr(A: np.ndarray, k: int, p: int, seed: int, g: float = 2.0,
     return Result(perm=perm, Q=Q1, R=R, L=L, V=V, sigma=sigma, l=l, swaps=swaps,
                   g2=g2, alpha=alpha, jstar=jstar, margins=margins, jstar_margin=jmargin,
                   flags=flags, numerical_rank=numerical_rank, B=B, history=history,
-                  sketch_mode=sketch_mode)
+                  sketch_mode=sketch_mode, probes=q if g2_probe > 0 else 0)
 
 
 # ---------------------------------------------------------------------------

@@ -15,7 +15,9 @@ of one published counter-based generator:
 Omega stream definition (shared by both sides, written independently):
   key      = (seed, 0)
   entry    Omega[i, t], 0 <= i < l (row), 0 <= t < m (column)
-  counter  = (t, i, 0, 0)  ->  output words x0..x3 = Philox4x64-10(counter, key)
+  counter  = (t, i, s, 0)  ->  output words x0..x3 = Philox4x64-10(counter, key)
+           s = 0 for the sketch's Omega; s = q >= 1 for the q-th random probe
+           of the SRQR test (a d x (l+1) matrix, Algorithm 4's g2 estimate)
   u1 = ((x0 >> 12) + 0.5) * 2^-52,  u2 = ((x1 >> 12) + 0.5) * 2^-52
            (exact in FP64, both in [2^-53, 1 - 2^-53], so inside (0, 1))
   Omega[i, t] = sqrt(-2 ln u1) * cos((2 pi) * u2)   in FP64; x2, x3 unused.
@@ -78,12 +80,15 @@ def uniform_open(x: np.ndarray) -> np.ndarray:
     return ((x >> np.uint64(12)).astype(np.float64) + 0.5) * (2.0 ** -52)
 
 
-def omega(seed: int, l: int, m: int) -> np.ndarray:
-    """Omega (l x m), FP64, entry (i, t) from counter (t, i, 0, 0), key (seed, 0)."""
+def omega(seed: int, l: int, m: int, stream: int = 0) -> np.ndarray:
+    """Omega (l x m), FP64, entry (i, t) from counter (t, i, stream, 0), key
+    (seed, 0).  Stream 0 is the sketch's Omega; stream q >= 1 is the q-th
+    random probe of the SRQR test's g2 estimate (d x (l+1))."""
     t = np.arange(m, dtype=np.uint64)[None, :].repeat(l, axis=0)
     i = np.arange(l, dtype=np.uint64)[:, None].repeat(m, axis=1)
     z = np.zeros_like(t)
-    x0, x1, _, _ = philox4x64_10(t, i, z, z, np.uint64(seed), np.uint64(0))
+    c2 = np.full_like(t, np.uint64(stream))
+    x0, x1, _, _ = philox4x64_10(t, i, c2, z, np.uint64(seed), np.uint64(0))
     u1 = uniform_open(x0)
     u2 = uniform_open(x1)
     return np.sqrt(-2.0 * np.log(u1)) * np.cos((2.0 * np.pi) * u2)

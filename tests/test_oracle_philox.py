@@ -32,6 +32,9 @@ def test_philox_words_match_numpy(seed):
     rng = np.random.default_rng(seed % 1000)
     ctrs = [(0, 0, 0, 0), (1, 0, 0, 0), (0, 5, 0, 0), (MASK, 3, 0, 0)]
     ctrs += [(int(rng.integers(0, 1 << 40)), int(rng.integers(0, 1 << 20)), 0, 0) for _ in range(20)]
+    # the probe streams of the SRQR test: stream q >= 1 in the third word
+    ctrs += [(int(rng.integers(0, 1 << 12)), int(rng.integers(0, 64)), int(rng.integers(1, 1 << 16)), 0)
+             for _ in range(10)]
     for c in ctrs:
         mine = oracle.philox4x64_10(*[np.array([v], dtype=np.uint64) for v in c],
                                     np.uint64(seed), np.uint64(0))
