@@ -96,7 +96,14 @@ typedef struct {
                         min(block + p, m)-row sample of the columns in play,
                         the sample updated after each block (needs
                         n - l + 1 >= min(block + p, m))                          */
-  int32_t reserved;  /* 0                                                         */
+  int32_t g2_probe;  /* 0: the SRQR test's g2 is exact (|alpha| times the largest
+                        row norm of R-tilde^{-1}); d in 1..64: Algorithm 4's
+                        randomized estimate, |alpha| / sqrt(d) times the largest
+                        column norm of P_q R-tilde^{-T}, with a fresh d x (l+1)
+                        Gaussian probe P_q for the q-th test of the call
+                        (ffsrqr_srqr_probe).  When the argmax is the (l+1)-st
+                        position the rotation is the identity and the next test
+                        draws P_{q+1}; max_swaps counts these too.               */
 } ffsrqr_opts;
 
 typedef struct {
@@ -109,7 +116,7 @@ typedef struct {
   int64_t numerical_rank; /* l unless RANK_DEFICIENT                               */
   double min_margin;      /* min over QRCP-on-B steps of (r_max - r_2nd) / r_max   */
   int32_t jacobi_sweeps;  /* sweeps of the one-sided Jacobi on L                   */
-  int32_t reserved;
+  int32_t probes;         /* SRQR tests that drew a random probe (0 when g2 is exact) */
   double jstar_margin;    /* (gamma_j*^2 - g_2nd) / gamma_j*^2: how clearly j* won;
                              g_2nd bounds every other trailing gamma_j^2 (1 when
                              l == n or one column trails)                         */
@@ -267,6 +274,24 @@ ffsrqr_status ffsrqr_srqr_rho(const void* R11, int64_t l, int64_t ldr, const voi
                               int32_t precision, ffsrqr_stream_t stream);
 
 /*
+ * Randomized g2 estimate of the SRQR test (Algorithm 4, the g2 step;
+ * Section 2.2, definition of g2).  R11, a, alpha as for ffsrqr_srqr_rho;
+ * d in 1..64 rows of the probe, q >= 1 its stream.  The probe P (d x (l+1))
+ * has entry (t, i) = sqrt(-2 ln u1) cos(2 pi u2), u_j = ((x_j >> 12) + 0.5)
+ * 2^-52 from words x0, x1 of Philox4x64-10 with counter (i, t, q, 0) and
+ * key (seed, 0) (stream 0 is Omega's, ffsrqr_omega).  Writes est[0:l+1]
+ * (FP64, device): est_i = |alpha| / sqrt(d) * ||column i of P R-tilde^{-T}||,
+ * an estimate of rho_i whose square is unbiased; est_l = ||P(:, l)|| /
+ * sqrt(d).  work: device scratch of at least 8 ((d + 1) l + d (l + 1)) + 512
+ * bytes (the probe and the d + 1 triangular solves).  FFSRQR_EINVAL for
+ * d outside 1..64, q = 0 or alpha <= 0.
+ */
+ffsrqr_status ffsrqr_srqr_probe(const void* R11, int64_t l, int64_t ldr, const void* a,
+                                double alpha, int32_t d, uint64_t seed, uint64_t q,
+                                double* est, void* work, size_t work_bytes,
+                                int32_t precision, ffsrqr_stream_t stream);
+
+/*
  * Flip-flop LQ (Section 3.1): QR without pivoting of R^T, R = [R11 R12]
  * l x n (ldr >= l) in Pi order: R^T = Qhat1 Rhat11.
  *   L  l x l (ldl >= l) = Rhat11^T, lower triangular, diag(L) >= 0;
@@ -322,7 +347,8 @@ ffsrqr_status ffsrqr_alg9_svd(const void* A, int64_t m, int64_t n, int64_t lda, 
  * For each mode r in the processing order: the mode-r unfolding G_(r) of the
  * current tensor (n_r rows; column c = the Fortran-order linear index of
  * the other indices in order) is factored by ffsrqr_factor's path (target
- * rank ranks[r], oversampling p, the options in opts) and completed by
+ * rank ranks[r], oversampling p, the options in opts; opts->block must be 0:
+ * the one-block selection) and completed by
  * Algorithm 9 to G_(r) ~ U_r Sigma V^T; U_r is written to U[r]
  * (dims[r] x ranks[r], ldu[r] >= dims[r]; U and ldu are host arrays of
  * device pointers and leading dimensions), and the tensor is reduced to
@@ -419,7 +445,8 @@ void ffsrqr_server_destroy(ffsrqr_server* server);
  * M (m x n, ldm) into a low-rank X and a sparse E (min ||X||_* +
  * lambda ||E||_1 with M = X + E).  Iteration: D = M - E + Y / mu; the
  * rank-sv SVD of D by ffsrqr_factor's path (target rank sv, oversampling p,
- * Omega key seed, the options in opts) completed by Algorithm 9;
+ * Omega key seed, the options in opts; opts->block must be 0) completed by
+ * Algorithm 9;
  * X = U S_{1/mu}(Sigma) V^T over the singular values above 1 / mu;
  * E = S_{lambda/mu}(M - X + Y / mu); Y += mu (M - X - E); mu <- min(1.5 mu,
  * 1e7 mu_0); until ||M - X - E||_F / ||M||_F < tol or max_iter iterations

@@ -22,13 +22,13 @@ class LibraryMissing(RuntimeError):
 
 class Opts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("max_swaps", C.c_int32), ("g", C.c_double), ("block", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("g2_probe", C.c_int32)]
 
 
 class Info(C.Structure):
     _fields_ = [("l", C.c_int64), ("swaps", C.c_int32), ("flags", C.c_uint32), ("g2", C.c_double),
                 ("alpha", C.c_double), ("jstar", C.c_int64), ("numerical_rank", C.c_int64),
-                ("min_margin", C.c_double), ("jacobi_sweeps", C.c_int32), ("reserved", C.c_int32),
+                ("min_margin", C.c_double), ("jacobi_sweeps", C.c_int32), ("probes", C.c_int32),
                 ("jstar_margin", C.c_double), ("jstar_candidates", C.c_int64)]
 
     def as_dict(self):
@@ -75,6 +75,7 @@ SIGNATURES = {
     "ffsrqr_panel_qr": (C.c_int, [_P, _I64, _I64, _I64, _P, _I64, _P, _I64, _P, _I64, _P, _SZ, _I32, _P]),
     "ffsrqr_project": (C.c_int, [_P, _I64, _I64, _I64, _P, _I64, _I64, _P, _I64, _P, _P, _P, _SZ, _I32, _P]),
     "ffsrqr_srqr_rho": (C.c_int, [_P, _I64, _I64, _P, _D, _P, _P, _SZ, _I32, _P]),
+    "ffsrqr_srqr_probe": (C.c_int, [_P, _I64, _I64, _P, _D, _I32, _U64, _U64, _P, _P, _SZ, _I32, _P]),
     "ffsrqr_lq": (C.c_int, [_P, _I64, _I64, _I64, _P, _P, _I64, _P, _I64, _P, _SZ, _I32, _P]),
     "ffsrqr_svd_small": (C.c_int, [_P, _I64, _I64, _P, _P, _SZ, _I32, _P]),
     "ffsrqr_svd_small_noalloc": (C.c_int, [_P, _I64, _I64, _P, _I32, _P]),

@@ -56,8 +56,8 @@ def _ptr(t) -> int:
     return t.data_ptr() if t is not None else 0
 
 
-def opts(precision=L.FP64, g: float = 2.0, max_swaps: int = -1, block: int = 0) -> L.Opts:
-    return L.Opts(precision=precision, max_swaps=max_swaps, g=g, block=block, reserved=0)
+def opts(precision=L.FP64, g: float = 2.0, max_swaps: int = -1, block: int = 0, g2_probe: int = 0) -> L.Opts:
+    return L.Opts(precision=precision, max_swaps=max_swaps, g=g, block=block, g2_probe=g2_probe)
 
 
 def workspace_size(m: int, n: int, k: int, p: int, precision=L.FP64, block: int = 0) -> int:
@@ -109,9 +109,11 @@ class Factorization:
 
 
 def factor(A: torch.Tensor, k: int, p: int, seed: int = 0, g: float = 2.0, max_swaps: int = -1,
-           work: torch.Tensor | None = None, stream=None, mixed: bool = False, block: int = 0) -> Factorization:
+           work: torch.Tensor | None = None, stream=None, mixed: bool = False, block: int = 0,
+           g2_probe: int = 0) -> Factorization:
     """ffsrqr_factor: A (m x n, column-major, float64 or float32) -> perm, Q, L, V, sigma, info.
-    mixed=True (float32 A) selects FFSRQR_MIXED (BF16 sketch, split-BF16 projection)."""
+    mixed=True (float32 A) selects FFSRQR_MIXED (BF16 sketch, split-BF16 projection);
+    block > 0 Algorithm 2's blocked selection; g2_probe = d > 0 the d-row random g2 estimate."""
     lib = L.load()
     m, n = A.shape
     lda = _ld(A)
@@ -126,7 +128,7 @@ def factor(A: torch.Tensor, k: int, p: int, seed: int = 0, g: float = 2.0, max_s
     if work is None:
         work = workspace(workspace_size(m, n, k, p, prec, block), dev, stream)
     info = L.Info()
-    o = opts(prec, g, max_swaps, block)
+    o = opts(prec, g, max_swaps, block, g2_probe)
     L.check(lib.ffsrqr_factor(_ptr(A), m, n, lda, k, p, seed, _ptr(perm), _ptr(Q), m, _ptr(Lf), l,
                               _ptr(V), n, _ptr(sigma), C.byref(info), _ptr(work), work.numel(),
                               C.byref(o), _stream(stream)), "ffsrqr_factor")
@@ -208,6 +210,20 @@ def srqr_rho(R11: torch.Tensor, a: torch.Tensor, alpha: float, work=None, stream
     L.check(lib.ffsrqr_srqr_rho(_ptr(R11), l, _ld(R11), _ptr(a), float(alpha), _ptr(rho), _ptr(work),
                                 work.numel(), _prec(R11.dtype), _stream(stream)), "ffsrqr_srqr_rho")
     return rho
+
+
+def srqr_probe(R11: torch.Tensor, a: torch.Tensor, alpha: float, d: int, seed: int, q: int, work=None,
+               stream=None) -> torch.Tensor:
+    """ffsrqr_srqr_probe: est[l+1], the randomized g2 estimate with the q-th d-row probe."""
+    lib = L.load()
+    l = R11.shape[0]
+    est = torch.empty(l + 1, dtype=torch.float64, device=R11.device)
+    if work is None:
+        work = workspace(8 * ((d + 1) * l + d * (l + 1)) + (1 << 16), R11.device, stream)
+    L.check(lib.ffsrqr_srqr_probe(_ptr(R11), l, _ld(R11), _ptr(a), float(alpha), int(d), int(seed), int(q),
+                                  _ptr(est), _ptr(work), work.numel(), _prec(R11.dtype), _stream(stream)),
+            "ffsrqr_srqr_probe")
+    return est
 
 
 def lq(R: torch.Tensor, perm: torch.Tensor, work=None, stream=None):

@@ -261,6 +261,17 @@ ffsrqr_status check_block(int64_t m, int64_t n, int64_t k, int64_t p, int64_t l,
   return FFSRQR_OK;
 }
 
+// The tensor and robust PCA drivers run the one-block selection: their
+// per-step ranks (and, for robust PCA, the rank of every iteration) change
+// the sample's shape, so opts.block is refused there.
+ffsrqr_status check_driver_opts(const ffsrqr_opts* o) {
+  if (!o) return FFSRQR_OK;
+  if (o->block != 0)
+    return fail(FFSRQR_EINVAL, "opts.block is for ffsrqr_factor and ffsrqr_factor_batched; the drivers need 0");
+  if (o->g2_probe < 0 || o->g2_probe > kMaxProbe) return fail(FFSRQR_EINVAL, "g2_probe must be 0 (exact) or 1..64");
+  return FFSRQR_OK;
+}
+
 // The device the limits are checked against when no device is at hand: a
 // 256-CU gfx950 with 160 KiB of LDS per workgroup.
 DeviceInfo limits_device() {
@@ -315,6 +326,7 @@ ffsrqr_status factor_impl(const T* A, int64_t m, int64_t n, int64_t lda, int64_t
   const int64_t l = std::min(k + p, std::min(m, n));
   uint32_t flags = (l < k + p) ? FFSRQR_FLAG_L_CLAMPED : 0u;
   const int64_t blk0 = op.block > 0 ? std::min<int64_t>(op.block, k) : 0;
+  if (op.g2_probe < 0 || op.g2_probe > kMaxProbe) return fail(FFSRQR_EINVAL, "g2_probe must be 0 (exact) or 1..64");
   const size_t need = total_bytes<T>(m, n, l, d, blk0, p);
   if (work_bytes < need)
     return fail(FFSRQR_EWORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
@@ -328,7 +340,7 @@ ffsrqr_status factor_impl(const T* A, int64_t m, int64_t n, int64_t lda, int64_t
   double* anorm2 = ar.take<double>(n);
   double* gamma2 = ar.take<double>(n);
   double* margins = ar.take<double>(l);
-  double* rho = ar.take<double>(l);
+  double* rho = ar.take<double>(l + 1);
   int64_t* S = ar.take<int64_t>(l);
   unsigned char* inS = ar.take<unsigned char>(n);
   int64_t* cnt = ar.take<int64_t>((n + 1023) / 1024 + 1);
@@ -419,6 +431,9 @@ ffsrqr_status factor_impl(const T* A, int64_t m, int64_t n, int64_t lda, int64_t
   FF_HIP(hipMemcpyAsync(hmarg.data(), margins, (size_t)l * sizeof(double), hipMemcpyDeviceToHost, s));
 
   int32_t swaps = 0;
+  int32_t rotations = 0;  // swap-loop iterations: swaps and the probe's identity rotations
+  uint64_t probe_q = 0;   // SRQR tests so far; the q-th draws the probe of stream q
+  const bool probe = op.g2_probe > 0;
   int32_t jacobi_sweeps = 0;
   SrqrState hs{};
   double g2 = 1.0;
@@ -514,7 +529,15 @@ ffsrqr_status factor_impl(const T* A, int64_t m, int64_t n, int64_t lda, int64_t
                             select_window<T>(m, l, mixed)));
       if (l < n) {
         Arena a2 = a_side;
-        FF_HIP(srqr_rho<T>(R11, l, W, l, st, 0.0, l, rho, st, a2, side->stream));
+        ++probe_q;
+        if (probe) {
+          const hipError_t e = srqr_probe<T>(R11, l, W, l, st, 0.0, l, op.g2_probe, seed, probe_q, rho, st, a2,
+                                             side->stream);
+          if (e == hipErrorInvalidValue) return fail(FFSRQR_EINVAL, "bad g2 probe");
+          FF_HIP(e);
+        } else {
+          FF_HIP(srqr_rho<T>(R11, l, W, l, st, 0.0, l, rho, st, a2, side->stream));
+        }
       }
       tm.end(h, side->stream);
     }
@@ -549,12 +572,34 @@ ffsrqr_status factor_impl(const T* A, int64_t m, int64_t n, int64_t lda, int64_t
       g2 = 1.0;
       break;
     }
-    g2 = hs.g2;
-    if (g2 <= op.g) break;
-    if (swaps >= op.max_swaps) {
-      flags |= FFSRQR_FLAG_SWAPCAP;
-      break;
+    // Algorithm 4's loop test.  With the random probe the argmax may be the
+    // (l+1)-st position itself: that rotation is the identity, the leading
+    // set and its factors stay, and the next test only draws a fresh probe.
+    bool done = false;
+    for (;;) {
+      g2 = hs.g2;
+      if (g2 <= op.g) {
+        done = true;
+        break;
+      }
+      if (rotations >= op.max_swaps) {
+        flags |= FFSRQR_FLAG_SWAPCAP;
+        done = true;
+        break;
+      }
+      ++rotations;
+      if (!(probe && hs.istar == l)) break;
+      ++probe_q;
+      tm.begin(FFSRQR_STEP_SRQR);
+      {
+        Arena a2 = a_side;
+        FF_HIP(srqr_probe<T>(R11, l, W, l, st, 0.0, l, op.g2_probe, seed, probe_q, rho, st, a2, s));
+      }
+      tm.end();
+      FF_HIP(hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, s));
+      FF_HIP(hipStreamSynchronize(s));
     }
+    if (done) break;
     // round-robin swap: S <- (S without S[istar]) followed by jstar
     if (hs.istar < 0 || hs.istar >= l || hs.jstar < 0 || hs.jstar >= n)
       return fail(FFSRQR_EHIP, "invalid swap candidates");
@@ -589,7 +634,7 @@ ffsrqr_status factor_impl(const T* A, int64_t m, int64_t n, int64_t lda, int64_t
     info->numerical_rank = numerical_rank;
     info->min_margin = mm;
     info->jacobi_sweeps = jacobi_sweeps;
-    info->reserved = 0;
+    info->probes = probe ? (int32_t)probe_q : 0;
     info->jstar_margin = l < n ? hs.jmargin : 1.0;
     info->jstar_candidates = l < n ? hs.ncand : 0;
   }
@@ -1022,7 +1067,7 @@ void ffsrqr_default_opts(ffsrqr_opts* o) {
   o->max_swaps = -1;
   o->g = 2.0;
   o->block = 0;
-  o->reserved = 0;
+  o->g2_probe = 0;
 }
 
 const char* ffsrqr_status_string(ffsrqr_status s) {
@@ -1080,6 +1125,8 @@ ffsrqr_status ffsrqr_workspace_size(int64_t m, int64_t n, int64_t k, int64_t p, 
   if (st != FFSRQR_OK) return st;
   const DeviceInfo d = sizing_device();
   const int64_t blk = opts && opts->block > 0 ? std::min<int64_t>(opts->block, k) : 0;
+  if (opts && (opts->g2_probe < 0 || opts->g2_probe > kMaxProbe))
+    return fail(FFSRQR_EINVAL, "g2_probe must be 0 (exact) or 1..64");
   if (opts && opts->block != 0) {
     st = check_block(m, n, k, p, l, opts->block);
     if (st != FFSRQR_OK) return st;
@@ -1251,6 +1298,27 @@ ffsrqr_status ffsrqr_srqr_rho(const void* R11, int64_t l, int64_t ldr, const voi
   return FFSRQR_OK;
 }
 
+ffsrqr_status ffsrqr_srqr_probe(const void* R11, int64_t l, int64_t ldr, const void* a, double alpha, int32_t d,
+                                uint64_t seed, uint64_t q, double* est, void* work, size_t work_bytes,
+                                int32_t precision, ffsrqr_stream_t stream) {
+  if (l < 1 || ldr < l || !R11 || !a || !est || !work || !(alpha > 0.0) || d < 1 || d > kMaxProbe || q < 1)
+    return fail(FFSRQR_EINVAL, "bad srqr_probe arguments");
+  if (!valid_precision(precision)) return fail(FFSRQR_EINVAL, "unknown precision");
+  const DeviceInfo* dev = nullptr;
+  ffsrqr_status st = get_device(&dev);
+  if (st != FFSRQR_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  Arena ar{(char*)work, work_bytes, 0};
+  hipError_t e = precision == FFSRQR_FP64
+                     ? srqr_probe<double>((const double*)R11, ldr, (const double*)a, 0, nullptr, alpha, l, d, seed, q,
+                                          est, nullptr, ar, s)
+                     : srqr_probe<float>((const float*)R11, ldr, (const float*)a, 0, nullptr, alpha, l, d, seed, q,
+                                         est, nullptr, ar, s);
+  if (e == hipErrorOutOfMemory) return fail(FFSRQR_EWORKSPACE, "workspace too small");
+  FF_HIP(e);
+  return FFSRQR_OK;
+}
+
 ffsrqr_status ffsrqr_lq(const void* R, int64_t l, int64_t n, int64_t ldr, const int64_t* perm, void* L, int64_t ldl,
                         void* V, int64_t ldv, void* work, size_t work_bytes, int32_t precision,
                         ffsrqr_stream_t stream) {
@@ -1340,8 +1408,10 @@ ffsrqr_status ffsrqr_st_hosvd_workspace_size(int32_t d, const int64_t* dims, con
   if (!bytes) return fail(FFSRQR_EINVAL, "bytes is NULL");
   const int32_t prec = opts ? opts->precision : FFSRQR_FP64;
   if (!valid_precision(prec)) return fail(FFSRQR_EINVAL, "unknown precision");
+  ffsrqr_status st = check_driver_opts(opts);
+  if (st != FFSRQR_OK) return st;
   HosvdPlan pl;
-  ffsrqr_status st = hosvd_plan(d, dims, ranks, order, p, limits_device(), &pl);
+  st = hosvd_plan(d, dims, ranks, order, p, limits_device(), &pl);
   if (st != FFSRQR_OK) return st;
   const DeviceInfo dv = sizing_device();
   *bytes = prec == FFSRQR_FP64 ? hosvd_bytes<double>(pl, dv) : hosvd_bytes<float>(pl, dv);
@@ -1356,8 +1426,10 @@ ffsrqr_status ffsrqr_st_hosvd(const void* X, int32_t d, const int64_t* dims, con
   if (!valid_precision(prec)) return fail(FFSRQR_EINVAL, "unknown precision");
   if (opts && !(opts->g == 0.0 || opts->g > 1.0)) return fail(FFSRQR_EINVAL, "g must be > 1");
   if (!X || !core || !U || !ldu || !work) return fail(FFSRQR_EINVAL, "NULL pointer argument");
+  ffsrqr_status st = check_driver_opts(opts);
+  if (st != FFSRQR_OK) return st;
   const DeviceInfo* dv = nullptr;
-  ffsrqr_status st = get_device(&dv);
+  st = get_device(&dv);
   if (st != FFSRQR_OK) return st;
   HosvdPlan pl;
   st = hosvd_plan(d, dims, ranks, order, p, *dv, &pl);
@@ -1425,6 +1497,8 @@ ffsrqr_status ffsrqr_rpca_workspace_size(int64_t m, int64_t n, int64_t p, int64_
   const RpcaSizes z = rpca_sizes(m, n, p, max_rank);
   ffsrqr_status st = check_dims(m, n, 1, p);
   if (st != FFSRQR_OK) return st;
+  st = check_driver_opts(opts);
+  if (st != FFSRQR_OK) return st;
   st = check_limits(m, n, z.lmax, limits_device());
   if (st != FFSRQR_OK) return st;
   const DeviceInfo dv = sizing_device();
@@ -1446,6 +1520,8 @@ ffsrqr_status ffsrqr_rpca_ialm(const void* M, int64_t m, int64_t n, int64_t ldm,
   const double lam = lambda > 0.0 ? lambda : 1.0 / std::sqrt((double)std::max(m, n));
   const RpcaSizes z = rpca_sizes(m, n, p, max_rank);
   ffsrqr_status st = check_dims(m, n, 1, p);
+  if (st != FFSRQR_OK) return st;
+  st = check_driver_opts(opts);
   if (st != FFSRQR_OK) return st;
   const DeviceInfo* dv = nullptr;
   st = get_device(&dv);

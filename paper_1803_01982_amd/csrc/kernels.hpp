@@ -37,6 +37,11 @@ hipError_t fill_void(uint64_t* p, size_t n, hipStream_t s);
 // Omega^T (m x l, ldo): Ot[t + i*ldo] = Omega[i, t] (Philox4x64-10 + Box-Muller).
 template <typename T>
 hipError_t launch_omega(uint64_t seed, int64_t l, int64_t m, T* Ot, int64_t ldo, hipStream_t s);
+// The q-th random probe (q >= 1) of the SRQR test, d x c, FP64:
+// P[t * c + i] from counter (i, t, q, 0), key (seed, 0).
+hipError_t launch_probe(uint64_t seed, uint64_t q, int64_t d, int64_t c, double* P, hipStream_t s);
+// Largest probe height d of the randomized g2 estimate.
+constexpr int32_t kMaxProbe = 64;
 
 // C (M x N, ldc) = X^T Y with X K x M (ldx), Y K x N (ldy).  If colnorm is
 // non-null it receives ||Y(:, j)||^2 (FP64).  Scratch comes from the arena.
@@ -139,6 +144,14 @@ hipError_t srqr_select(const double* gamma2, const double* anorm2, const unsigne
 template <typename T>
 hipError_t srqr_rho(const T* R11, int64_t ldr, const T* a, int64_t a_stride, const SrqrState* sel,
                     double alpha_host, int64_t l, double* rho, SrqrState* st_out, Arena& ar, hipStream_t s);
+// Algorithm 4's randomized g2 estimate with the q-th d-row probe:
+// est[0:l+1], est_i = |alpha| / sqrt(d) * ||column i of P R-tilde^{-T}||;
+// st_out->g2 = max_i est_i, st_out->istar = its argmax in 0..l (l: the
+// (l+1)-st position, whose round-robin rotation is the identity).
+template <typename T>
+hipError_t srqr_probe(const T* R11, int64_t ldr, const T* a, int64_t a_stride, const SrqrState* sel,
+                      double alpha_host, int64_t l, int32_t d, uint64_t seed, uint64_t q, double* est,
+                      SrqrState* st_out, Arena& ar, hipStream_t s);
 
 // Algorithm 2's blocked pivot selection: l pivots S (and their QRCP
 // margins) in blocks of b <= 64 from the sample B (rows x n, ldb = rows,

@@ -1,4 +1,5 @@
-// Gaussian test matrix Omega (Algorithm 2, first step) and small fill kernels.
+// Gaussian test matrix Omega (Algorithm 2, first step), the random probes of
+// the SRQR test's g2 estimate (Algorithm 4) and small fill kernels.
 //
 // Omega[i, t] comes from one Philox4x64-10 block (Salmon, Moraes, Dror, Shaw,
 // SC'11) with counter (t, i, 0, 0) and key (seed, 0), mapped to N(0,1) by the
@@ -6,7 +7,9 @@
 //   u = ((x >> 12) + 0.5) * 2^-52   (exact, inside (0, 1))
 //   Omega[i, t] = sqrt(-2 ln u1) * cos(2 pi u2)
 // Stored transposed (m x l) so that the sketch GEMM reads both operands along
-// the contraction index.
+// the contraction index.  The q-th probe (q >= 1) of a solve, d x c, takes
+// entry (t, i) from counter (i, t, q, 0) with the same key and map: the third
+// counter word keeps the probe streams apart from Omega's.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -67,6 +70,13 @@ __device__ inline __bf16 bf16_from_double(double x) {
   return (__bf16)(float)q;
 }
 
+// N(0,1) from the first two words of a Philox block (Box-Muller)
+__device__ inline double gauss_of(uint64_t x0, uint64_t x1) {
+  const double u1 = ((double)(x0 >> 12) + 0.5) * 0x1p-52;
+  const double u2 = ((double)(x1 >> 12) + 0.5) * 0x1p-52;
+  return sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+}
+
 template <typename T>
 __device__ inline T omega_value(double z) {
   return (T)z;
@@ -83,10 +93,24 @@ __global__ void omega_kernel(uint64_t seed, int64_t l, int64_t m, T* __restrict_
   if (t >= m || i >= l) return;
   uint64_t x0 = (uint64_t)t, x1 = (uint64_t)i, x2 = 0, x3 = 0;
   philox4x64_10(x0, x1, x2, x3, seed, 0ull);
-  const double u1 = ((double)(x0 >> 12) + 0.5) * 0x1p-52;
-  const double u2 = ((double)(x1 >> 12) + 0.5) * 0x1p-52;
-  const double z = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
-  Ot[t + i * ldo] = omega_value<T>(z);
+  Ot[t + i * ldo] = omega_value<T>(gauss_of(x0, x1));
+}
+
+// P[t * c + i], t < d, i < c: the q-th probe, FP64
+__global__ void probe_kernel(uint64_t seed, uint64_t q, int64_t d, int64_t c, double* __restrict__ P) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t t = blockIdx.y;
+  if (i >= c || t >= d) return;
+  uint64_t x0 = (uint64_t)i, x1 = (uint64_t)t, x2 = q, x3 = 0;
+  philox4x64_10(x0, x1, x2, x3, seed, 0ull);
+  P[t * c + i] = gauss_of(x0, x1);
+}
+
+hipError_t launch_probe(uint64_t seed, uint64_t q, int64_t d, int64_t c, double* P, hipStream_t s) {
+  if (d <= 0 || c <= 0) return hipSuccess;
+  dim3 grid((unsigned)((c + 255) / 256), (unsigned)d);
+  probe_kernel<<<grid, 256, 0, s>>>(seed, q, d, c, P);
+  return hipGetLastError();
 }
 
 template <typename T>

@@ -23,6 +23,16 @@
 //                   chunks of 16 columns), then
 //                   rho_i^2 = alpha^2 ||X(i, :)||^2 + z_i^2, the squared norm of
 //                   row i of |alpha| R-tilde^{-1}; g2 = max(1, max_i rho_i).
+//   probe           Algorithm 4's randomized estimate: the q-th probe P
+//                   (d x (l+1), Philox stream q) split as [P1 p2], then
+//                   Y = R11^{-1} P1^T and z = R11^{-1} a by the same back
+//                   substitution (d + 1 columns instead of l + 1), and
+//                   est_i = ||alpha Y(i, :) - z_i p2^T|| / sqrt(d) (i < l),
+//                   est_l = ||p2|| / sqrt(d): row i of R-tilde^{-1} P^T
+//                   scaled by |alpha| / sqrt(d), i.e. column i of
+//                   P R-tilde^{-T}.  g2 = max_i est_i over all l + 1
+//                   positions, i* its argmax (ties to the smaller index).
+#include <algorithm>
 #include <cmath>
 
 #include "common.hpp"
@@ -262,10 +272,13 @@ __global__ void cand_final(const int64_t* __restrict__ list, const double* __res
   }
 }
 
-// Column j of R11^{-1} (j < l), or z = R11^{-1} a (j == l), by back substitution.
+// Back substitution with R11, one right-hand side per workgroup j:
+// j < ncol: e_j (rhs null; column j of R11^{-1}, length j + 1) or row j of
+// rhs (stride rstride, length l); j == ncol: z = R11^{-1} a.
 template <typename T>
 __global__ void trinv_kernel(const T* __restrict__ R, int64_t ldr, int64_t l, const T* __restrict__ a_base,
-                             int64_t a_stride, const SrqrState* st, double* __restrict__ X) {
+                             int64_t a_stride, const SrqrState* st, const double* __restrict__ rhs,
+                             int64_t rstride, int64_t ncol, double* __restrict__ X) {
   extern __shared__ double sm[];
   constexpr int CH = 16;
   double* b = sm;              // l
@@ -273,15 +286,18 @@ __global__ void trinv_kernel(const T* __restrict__ R, int64_t ldr, int64_t l, co
   double* Rc = xo + l;         // l x CH staging
   const int64_t j = blockIdx.x;
   const int tid = threadIdx.x;
-  const int64_t len = (j < l) ? j + 1 : l;
+  const int64_t len = (j < ncol && !rhs) ? j + 1 : l;
   const T* a = nullptr;
-  if (j == l) {
+  if (j == ncol) {
     // st selects the column of W; no trailing column leaves a = 0
     if (!st) a = a_base;
     else if (st->jstar >= 0) a = a_base + st->jstar * a_stride;
   }
   for (int64_t r = tid; r < l; r += NT) {
-    b[r] = (j < l) ? (r == j ? 1.0 : 0.0) : (a ? (double)a[r] : 0.0);
+    double v;
+    if (j < ncol) v = rhs ? rhs[j * rstride + r] : (r == j ? 1.0 : 0.0);
+    else v = a ? (double)a[r] : 0.0;
+    b[r] = v;
     xo[r] = 0.0;
   }
   for (int64_t hi = len - 1; hi >= 0; hi -= CH) {
@@ -326,6 +342,41 @@ __global__ void rho_kernel(const double* __restrict__ X, int64_t l, const SrqrSt
   b = block_argmax(b, rv, ri);
   if (threadIdx.x == 0 && st) {
     st->g2 = b.v > 1.0 ? b.v : 1.0;
+    st->istar = b.i;
+  }
+}
+
+// est_i from Y = R11^{-1} P1^T (column t at X + t l), z = R11^{-1} a (at
+// X + d l) and p2 = P(:, l); g2 and istar over positions 0..l.
+__global__ void probe_rho_kernel(const double* __restrict__ X, int64_t l, int d, const double* __restrict__ P,
+                                 const SrqrState* st_in, double alpha_host, double* __restrict__ est,
+                                 SrqrState* st) {
+  __shared__ double rv[NT / 64];
+  __shared__ int64_t ri[NT / 64];
+  const double alpha = st_in ? st_in->alpha : alpha_host;
+  const double inv_d = 1.0 / (double)d;
+  ArgMax b{0.0, -1};
+  for (int64_t i = threadIdx.x; i <= l; i += NT) {
+    double s = 0.0;
+    if (i < l) {
+      const double z = X[(int64_t)d * l + i];
+      for (int t = 0; t < d; ++t) {
+        const double v = alpha * X[(int64_t)t * l + i] - z * P[(int64_t)t * (l + 1) + l];
+        s += v * v;
+      }
+    } else {
+      for (int t = 0; t < d; ++t) {
+        const double v = P[(int64_t)t * (l + 1) + l];
+        s += v * v;
+      }
+    }
+    const double r = sqrt(s * inv_d);
+    est[i] = r;
+    if (better(r, i, b.v, b.i)) b = ArgMax{r, i};
+  }
+  b = block_argmax(b, rv, ri);
+  if (threadIdx.x == 0 && st) {
+    st->g2 = b.v;
     st->istar = b.i;
   }
 }
@@ -429,7 +480,9 @@ constexpr int kCandRowBlocks = 32;  // row blocks of the candidate recomputation
 template <typename T>
 size_t srqr_scratch(int64_t m, int64_t n, int64_t l) {
   const size_t nb = (size_t)(n + CB_N - 1) / CB_N;
-  return sizeof(double) * ((size_t)(l + 1) * l + 4 * 1024) + sizeof(int64_t) * 1024 + 4 * 1024 + 8 * 256 +
+  // the exact rho's R11^{-1} and z, or the largest probe with its solves
+  const size_t xs = std::max((size_t)(l + 1) * l, (size_t)(kMaxProbe + 1) * l + (size_t)kMaxProbe * (l + 1) + 32);
+  return sizeof(double) * (xs + 4 * 1024) + sizeof(int64_t) * 1024 + 4 * 1024 + 8 * 256 +
          nb * (sizeof(int64_t) + sizeof(double)) + (size_t)n * sizeof(int64_t) +
          (size_t)n * kCandRowBlocks * sizeof(double) + 8 * 256;
 }
@@ -481,8 +534,29 @@ hipError_t srqr_rho(const T* R11, int64_t ldr, const T* a, int64_t a_stride, con
                                        (int)lds);
     if (e != hipSuccess) return e;
   }
-  trinv_kernel<T><<<(unsigned)(l + 1), NT, lds, s>>>(R11, ldr, l, a, a_stride, sel, X);
+  trinv_kernel<T><<<(unsigned)(l + 1), NT, lds, s>>>(R11, ldr, l, a, a_stride, sel, nullptr, 0, l, X);
   rho_kernel<<<1, NT, 0, s>>>(X, l, sel, alpha_host, rho, st_out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t srqr_probe(const T* R11, int64_t ldr, const T* a, int64_t a_stride, const SrqrState* sel,
+                      double alpha_host, int64_t l, int32_t d, uint64_t seed, uint64_t q, double* est,
+                      SrqrState* st_out, Arena& ar, hipStream_t s) {
+  if (d < 1 || d > kMaxProbe || q < 1) return hipErrorInvalidValue;
+  double* P = ar.take<double>((size_t)d * (l + 1));
+  double* X = ar.take<double>((size_t)(d + 1) * l);
+  if (!P || !X) return hipErrorOutOfMemory;
+  const size_t lds = (size_t)(2 * l + 16 * l) * sizeof(double);
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)trinv_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipError_t e = launch_probe(seed, q, d, l + 1, P, s);
+  if (e != hipSuccess) return e;
+  trinv_kernel<T><<<(unsigned)(d + 1), NT, lds, s>>>(R11, ldr, l, a, a_stride, sel, P, l + 1, d, X);
+  probe_rho_kernel<<<1, NT, 0, s>>>(X, l, d, P, sel, alpha_host, est, st_out);
   return hipGetLastError();
 }
 
@@ -522,6 +596,8 @@ hipError_t assemble_r(const T* R11, int64_t ldr11, const T* W, int64_t ldw, cons
                                      SrqrState*, Arena&, hipStream_t, double);                                      \
   template hipError_t srqr_rho<T>(const T*, int64_t, const T*, int64_t, const SrqrState*, double, int64_t, double*, \
                                   SrqrState*, Arena&, hipStream_t);                                                 \
+  template hipError_t srqr_probe<T>(const T*, int64_t, const T*, int64_t, const SrqrState*, double, int64_t,        \
+                                    int32_t, uint64_t, uint64_t, double*, SrqrState*, Arena&, hipStream_t);        \
   template hipError_t assemble_rt<T>(const T*, int64_t, const T*, int64_t, const int64_t*, int64_t, int64_t, T*,   \
                                      int64_t, hipStream_t);                                                         \
   template hipError_t assemble_r<T>(const T*, int64_t, const T*, int64_t, const int64_t*, int64_t, int64_t, T*,    \

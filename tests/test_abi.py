@@ -29,7 +29,8 @@ def lib():
 def test_header_declares_the_path():
     names = declared()
     for n in ("ffsrqr_factor", "ffsrqr_workspace_size", "ffsrqr_omega", "ffsrqr_sketch", "ffsrqr_qrcp",
-              "ffsrqr_panel_qr", "ffsrqr_project", "ffsrqr_srqr_rho", "ffsrqr_lq", "ffsrqr_svd_small"):
+              "ffsrqr_panel_qr", "ffsrqr_project", "ffsrqr_srqr_rho", "ffsrqr_srqr_probe", "ffsrqr_lq",
+              "ffsrqr_svd_small"):
         assert n in names
 
 
@@ -230,6 +231,40 @@ def test_block_option_checks(lib):
     # n - l + 1 < block + p: too few columns for the blocked sample
     assert lib.ffsrqr_workspace_size(100, 40, 20, 10, C.byref(_lib.Opts(0, -1, 2.0, 16, 0)), C.byref(out)) == 1
     assert b"blocked" in lib.ffsrqr_last_error()
+
+
+def test_probe_option_checks(lib):
+    from paper_1803_01982_amd import _lib
+    o = _lib.Opts()
+    lib.ffsrqr_default_opts(C.byref(o))
+    assert o.g2_probe == 0
+    out = C.c_size_t(0)
+    for d, want in ((0, 0), (1, 0), (64, 0), (-1, 1), (65, 1)):
+        rc = lib.ffsrqr_workspace_size(1000, 800, 20, 10, C.byref(_lib.Opts(0, -1, 2.0, 0, d)), C.byref(out))
+        assert rc == want, d
+    assert b"g2_probe" in lib.ffsrqr_last_error()
+    # the per-step entry point checks its arguments before touching a device
+    f = lib.ffsrqr_srqr_probe
+    one = C.c_void_p(256)
+    assert f(one, 8, 8, one, 1.0, 0, 1, 1, one, one, 1 << 20, 0, None) == 1    # d = 0
+    assert f(one, 8, 8, one, 1.0, 65, 1, 1, one, one, 1 << 20, 0, None) == 1   # d > 64
+    assert f(one, 8, 8, one, 1.0, 4, 1, 0, one, one, 1 << 20, 0, None) == 1    # q = 0 is Omega's stream
+    assert f(one, 8, 8, one, 0.0, 4, 1, 1, one, one, 1 << 20, 0, None) == 1    # alpha must be > 0
+    assert f(one, 8, 4, one, 1.0, 4, 1, 1, one, one, 1 << 20, 0, None) == 1    # ldr < l
+
+
+def test_drivers_refuse_the_blocked_selection(lib):
+    from paper_1803_01982_amd import _lib
+    out = C.c_size_t(0)
+    blocked = _lib.Opts(0, -1, 2.0, 16, 0)
+    probed = _lib.Opts(0, -1, 2.0, 0, 8)
+    assert lib.ffsrqr_rpca_workspace_size(500, 400, 10, 0, C.byref(blocked), C.byref(out)) == 1
+    assert b"opts.block" in lib.ffsrqr_last_error()
+    assert lib.ffsrqr_rpca_workspace_size(500, 400, 10, 0, C.byref(probed), C.byref(out)) == 0
+    I64 = C.c_int64 * 3
+    dims, ranks = I64(40, 30, 20), I64(5, 5, 5)
+    assert lib.ffsrqr_st_hosvd_workspace_size(3, dims, ranks, None, 4, C.byref(blocked), C.byref(out)) == 1
+    assert lib.ffsrqr_st_hosvd_workspace_size(3, dims, ranks, None, 4, C.byref(probed), C.byref(out)) == 0
 
 
 def test_server_rejects_bad_config(lib):
