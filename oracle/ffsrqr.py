@@ -44,7 +44,16 @@ design notes):
   * Column norms on B are recomputed from scratch at every step (no
     downdating), ties go to the smallest original column index.
   * Residual norms gamma_j of the trailing columns are exact,
-    ||(I - Q1 Q1^T) a_j||, not the sketch estimate of Algorithm 4.
+    ||(I - Q1 Q1^T) a_j||, by default.  With est_norms (blocked selection
+    only, where the sample is kept up to date) they are Algorithm 4's
+    estimates instead: r_i = ||B(:, i)||^2 / (sample rows) from the sample
+    after the last block's update, j* = argmax r_i, alpha the exact residual
+    norm of column j*; before each test r_i -= (row l+1 of R of [S, j*])_i^2;
+    after a swap r_i += (row l+1 of R of [S', i*])_i^2 for the trailing
+    columns and r_{i*} = R_{l+1,l+1}^2 (the squared rows of the retriangularised
+    R, taken here from a fresh QR of the same ordered columns: the thin QR is
+    unique up to row signs); after an identity rotation r_{j*} = alpha^2 and
+    the other estimates return to their values before the downdate.
   * g2 is exact by default: |alpha| * max row norm of R-tilde^{-1}.  With
     g2_probe = d > 0 it is Algorithm 4's estimate instead: the q-th test of a
     solve (q = 1, 2, ...) draws Omega_q (d x (l+1)) from the Philox stream q,
@@ -330,6 +339,15 @@ def srqr_rho(R11: np.ndarray, a: np.ndarray, alpha: float) -> np.ndarray:
     return abs(alpha) * np.sqrt(np.sum(X * X, axis=1))
 
 
+def row_l1(A: np.ndarray, S, j: int) -> np.ndarray:
+    """Row l+1 of R in the QR of A(:, S + [j]) over all columns of A:
+    q^T A with q the last column of the Householder Q of those l+1 columns
+    (the part of a_j outside span(A(:, S)), normalised; its squares are the
+    norm downdates of Algorithm 4)."""
+    Qx, _ = householder_qr(np.asarray(A[:, list(S) + [j]], dtype=np.float64))
+    return Qx[:, -1] @ A
+
+
 def probe_omega(seed: int, q: int, d: int, l: int) -> np.ndarray:
     """The q-th probe (q >= 1) of a solve: d x (l+1) N(0,1), Philox stream q."""
     if q < 1:
@@ -447,6 +465,7 @@ class Result:
     history: list           # [(S, g2, jstar, alpha)] per SRQR test
     sketch_mode: str = "fp64"
     probes: int = 0         # random probes drawn (0: exact g2)
+    norm_estimates: np.ndarray | None = None  # est_norms: r_i w.r.t. the final leading set
 
 
 def _full_perm(S, n):
@@ -499,7 +518,7 @@ def rank_tolerance(m: int, n: int, max_col_norm: float, storage: str = "fp64") -
 def ffsrqr(A: np.ndarray, k: int, p: int, seed: int, g: float = 2.0,
            max_swaps: int | None = None, Omega: np.ndarray | None = None,
            sketch_mode: str = "fp64", storage: str = "fp64", block: int = 0,
-           g2_probe: int = 0) -> Result:
+           g2_probe: int = 0, est_norms: bool = False) -> Result:
     """Flip-Flop SRQR hot path, FP64 (Algorithm 9 up to the LQ, Algorithm 4 inside).
 
     sketch_mode selects the arithmetic of B = Omega A ("fp64" or "bf16", see
@@ -507,11 +526,15 @@ def ffsrqr(A: np.ndarray, k: int, p: int, seed: int, g: float = 2.0,
     precision the data is held in ("fp64" or "fp32"); it only sets the rank
     tolerance (rank_tolerance()).  g2_probe = d > 0 replaces the exact g2 by
     Algorithm 4's d-row random estimate (g2_probe_estimate, probe_omega).
+    est_norms (needs block > 0) replaces the exact residual norms that pick
+    j* by Algorithm 4's sample estimates (row_l1, and the module notes).
     """
     A = np.asarray(A)
     m, n = A.shape
     if not (1 <= k <= min(m, n)) or p < 0 or not g > 1.0 or g2_probe < 0:
         raise ValueError("bad arguments")
+    if est_norms and block <= 0:
+        raise ValueError("the sample-estimated residual norms need the blocked selection")
     flags = 0
     l = min(k + p, m, n)
     if l < k + p:
@@ -533,9 +556,15 @@ def ffsrqr(A: np.ndarray, k: int, p: int, seed: int, g: float = 2.0,
 
     if block > 0:
         # a1 + a2 blocked: Algorithm 2 with a (b + p)-row sample, b = min(block, k)
-        S, margins = trqrcp_pivots(Af, l, min(block, k), p, seed, sketch_mode)
+        trace = [] if est_norms else None
+        S, margins = trqrcp_pivots(Af, l, min(block, k), p, seed, sketch_mode, trace=trace)
         S = [int(s) for s in S]
         B = None
+        if est_norms:
+            # Algorithm 4: squared column norms of the updated sample over its
+            # row count estimate the squared residual norms of A's columns
+            Bs = trace[-1][1]
+            r = np.sum(Bs * Bs, axis=0) / Bs.shape[0]
     else:
         # a1
         Om = omega(seed, l, m) if Omega is None else Omega
@@ -545,6 +574,7 @@ def ffsrqr(A: np.ndarray, k: int, p: int, seed: int, g: float = 2.0,
         S = [int(s) for s in pivots[:l]]
 
     swaps = 0
+    est_out = None
     rotations = 0   # loop iterations: the swaps plus identity rotations of the probe
     q = 0           # SRQR tests so far (the probe stream of the next one is q + 1)
     history = []
@@ -556,13 +586,24 @@ def ffsrqr(A: np.ndarray, k: int, p: int, seed: int, g: float = 2.0,
         # a5
         if l < n:
             trailing = perm[l:]
-            gam = residual_norms(Af, Q1, W, trailing)
-            gmax = gam.max()
-            cands = np.flatnonzero(gam == gmax)
-            jpos = int(cands[np.argmin(trailing[cands])])
-            jstar = int(trailing[jpos])
-            alpha = float(gmax)
-            jmargin = residual_margin(gam)
+            if est_norms:
+                rt = r[trailing]
+                cands = np.flatnonzero(rt == rt.max())
+                jstar = int(trailing[int(cands[np.argmin(trailing[cands])])])
+                alpha = float(residual_norms(Af, Q1, W, [jstar])[0])
+                jmargin = residual_margin(np.sqrt(np.maximum(rt, 0.0)))
+                # the one-step QR of column j* and the downdate of the estimates
+                r_before = r.copy()
+                est_out = r_before
+                r = r - row_l1(Af, S, jstar) ** 2
+            else:
+                gam = residual_norms(Af, Q1, W, trailing)
+                gmax = gam.max()
+                cands = np.flatnonzero(gam == gmax)
+                jpos = int(cands[np.argmin(trailing[cands])])
+                jstar = int(trailing[jpos])
+                alpha = float(gmax)
+                jmargin = residual_margin(gam)
             dR = np.abs(np.diag(R11))
             if alpha <= tau_r or dR.min() <= tau_r:
                 flags |= FLAG_RANK_DEFICIENT
@@ -587,8 +628,19 @@ def ffsrqr(A: np.ndarray, k: int, p: int, seed: int, g: float = 2.0,
                 break
             rotations += 1
             if istar < l:
+                removed = S[istar]
                 S = S[:istar] + S[istar + 1:] + [jstar]
                 swaps += 1
+                if est_norms:
+                    # the removed column at position l+1 of the new order: its
+                    # row of R restores the estimates; r of it is exact
+                    row = row_l1(Af, S, removed)
+                    r = r + row ** 2
+                    r[removed] = row[removed] ** 2
+            elif est_norms:
+                # the identity rotation: j* back at position l+1, r_{j*} exact
+                r = r_before
+                r[jstar] = alpha * alpha
         else:
             jstar, alpha, g2 = -1, 0.0, 1.0
             history.append((list(S), g2, jstar, alpha))
@@ -601,7 +653,8 @@ def ffsrqr(A: np.ndarray, k: int, p: int, seed: int, g: float = 2.0,
     return Result(perm=perm, Q=Q1, R=R, L=L, V=V, sigma=sigma, l=l, swaps=swaps,
                   g2=g2, alpha=alpha, jstar=jstar, margins=margins, jstar_margin=jmargin,
                   flags=flags, numerical_rank=numerical_rank, B=B, history=history,
-                  sketch_mode=sketch_mode, probes=q if g2_probe > 0 else 0)
+                  sketch_mode=sketch_mode, probes=q if g2_probe > 0 else 0,
+                  norm_estimates=est_out)
 
 
 # ---------------------------------------------------------------------------
