@@ -466,6 +466,10 @@ class Result:
     sketch_mode: str = "fp64"
     probes: int = 0         # random probes drawn (0: exact g2)
     norm_estimates: np.ndarray | None = None  # est_norms: r_i w.r.t. the final leading set
+    test_margins: list = dataclasses.field(default_factory=list)
+    # per SRQR test: (relative gap of the two largest squared residual norms
+    # or estimates that pick j*, relative gap of the two largest values that
+    # pick i*)
 
 
 def _full_perm(S, n):
@@ -577,6 +581,7 @@ def ffsrqr(A: np.ndarray, k: int, p: int, seed: int, g: float = 2.0,
     est_out = None
     rotations = 0   # loop iterations: the swaps plus identity rotations of the probe
     q = 0           # SRQR tests so far (the probe stream of the next one is q + 1)
+    test_margins = []
     history = []
     numerical_rank = l
     jmargin = 1.0
@@ -621,6 +626,9 @@ def ffsrqr(A: np.ndarray, k: int, p: int, seed: int, g: float = 2.0,
                 g2 = float(rho.max())
                 istar = int(np.argmax(rho[:l]))
             history.append((list(S), g2, jstar, alpha))
+            cand_i = np.sort(est if g2_probe > 0 else rho[:l])
+            imargin = float((cand_i[-1] - cand_i[-2]) / cand_i[-1]) if cand_i.size > 1 and cand_i[-1] > 0 else 1.0
+            test_margins.append((jmargin, imargin))
             if g2 <= g:
                 break
             if rotations >= max_swaps:
@@ -654,7 +662,7 @@ def ffsrqr(A: np.ndarray, k: int, p: int, seed: int, g: float = 2.0,
                   g2=g2, alpha=alpha, jstar=jstar, margins=margins, jstar_margin=jmargin,
                   flags=flags, numerical_rank=numerical_rank, B=B, history=history,
                   sketch_mode=sketch_mode, probes=q if g2_probe > 0 else 0,
-                  norm_estimates=est_out)
+                  norm_estimates=est_out, test_margins=test_margins)
 
 
 # ---------------------------------------------------------------------------

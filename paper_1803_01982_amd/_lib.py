@@ -22,7 +22,7 @@ class LibraryMissing(RuntimeError):
 
 class Opts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("max_swaps", C.c_int32), ("g", C.c_double), ("block", C.c_int32),
-                ("g2_probe", C.c_int32)]
+                ("g2_probe", C.c_int32), ("est_norms", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Info(C.Structure):

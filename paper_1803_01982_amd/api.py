@@ -56,8 +56,10 @@ def _ptr(t) -> int:
     return t.data_ptr() if t is not None else 0
 
 
-def opts(precision=L.FP64, g: float = 2.0, max_swaps: int = -1, block: int = 0, g2_probe: int = 0) -> L.Opts:
-    return L.Opts(precision=precision, max_swaps=max_swaps, g=g, block=block, g2_probe=g2_probe)
+def opts(precision=L.FP64, g: float = 2.0, max_swaps: int = -1, block: int = 0, g2_probe: int = 0,
+         est_norms: bool = False) -> L.Opts:
+    return L.Opts(precision=precision, max_swaps=max_swaps, g=g, block=block, g2_probe=g2_probe,
+                  est_norms=1 if est_norms else 0, reserved=0)
 
 
 def workspace_size(m: int, n: int, k: int, p: int, precision=L.FP64, block: int = 0) -> int:
@@ -110,10 +112,11 @@ class Factorization:
 
 def factor(A: torch.Tensor, k: int, p: int, seed: int = 0, g: float = 2.0, max_swaps: int = -1,
            work: torch.Tensor | None = None, stream=None, mixed: bool = False, block: int = 0,
-           g2_probe: int = 0) -> Factorization:
+           g2_probe: int = 0, est_norms: bool = False) -> Factorization:
     """ffsrqr_factor: A (m x n, column-major, float64 or float32) -> perm, Q, L, V, sigma, info.
     mixed=True (float32 A) selects FFSRQR_MIXED (BF16 sketch, split-BF16 projection);
-    block > 0 Algorithm 2's blocked selection; g2_probe = d > 0 the d-row random g2 estimate."""
+    block > 0 Algorithm 2's blocked selection; g2_probe = d > 0 the d-row random g2 estimate;
+    est_norms (with block > 0) Algorithm 4's sample-estimated residual norms."""
     lib = L.load()
     m, n = A.shape
     lda = _ld(A)
@@ -128,7 +131,7 @@ def factor(A: torch.Tensor, k: int, p: int, seed: int = 0, g: float = 2.0, max_s
     if work is None:
         work = workspace(workspace_size(m, n, k, p, prec, block), dev, stream)
     info = L.Info()
-    o = opts(prec, g, max_swaps, block, g2_probe)
+    o = opts(prec, g, max_swaps, block, g2_probe, est_norms)
     L.check(lib.ffsrqr_factor(_ptr(A), m, n, lda, k, p, seed, _ptr(perm), _ptr(Q), m, _ptr(Lf), l,
                               _ptr(V), n, _ptr(sigma), C.byref(info), _ptr(work), work.numel(),
                               C.byref(o), _stream(stream)), "ffsrqr_factor")

@@ -146,7 +146,7 @@ size_t persistent_bytes(int64_t m, int64_t n, int64_t l) {
   b += align256((size_t)l * n * sizeof(T));                                   // W
   b += align256((size_t)n * l * sizeof(T));                                   // Qhat1
   b += align256((size_t)l * l * sizeof(T));                                   // R11
-  b += 2 * align256((size_t)n * sizeof(double));                              // anorm2, gamma2
+  b += 3 * align256((size_t)n * sizeof(double));                              // anorm2, gamma2, estimates
   b += 2 * align256((size_t)l * sizeof(double));                              // margins, rho
   b += align256((size_t)l * sizeof(int64_t));                                 // S
   b += align256((size_t)n);                                                   // inS
@@ -269,6 +269,7 @@ ffsrqr_status check_driver_opts(const ffsrqr_opts* o) {
   if (o->block != 0)
     return fail(FFSRQR_EINVAL, "opts.block is for ffsrqr_factor and ffsrqr_factor_batched; the drivers need 0");
   if (o->g2_probe < 0 || o->g2_probe > kMaxProbe) return fail(FFSRQR_EINVAL, "g2_probe must be 0 (exact) or 1..64");
+  if (o->est_norms != 0) return fail(FFSRQR_EINVAL, "est_norms needs the blocked selection, which the drivers do not run");
   return FFSRQR_OK;
 }
 
@@ -327,6 +328,9 @@ ffsrqr_status factor_impl(const T* A, int64_t m, int64_t n, int64_t lda, int64_t
   uint32_t flags = (l < k + p) ? FFSRQR_FLAG_L_CLAMPED : 0u;
   const int64_t blk0 = op.block > 0 ? std::min<int64_t>(op.block, k) : 0;
   if (op.g2_probe < 0 || op.g2_probe > kMaxProbe) return fail(FFSRQR_EINVAL, "g2_probe must be 0 (exact) or 1..64");
+  if (op.est_norms != 0 && (op.est_norms != 1 || op.block <= 0))
+    return fail(FFSRQR_EINVAL, "est_norms must be 0, or 1 with the blocked selection (block > 0)");
+  const bool est_mode = op.est_norms == 1;
   const size_t need = total_bytes<T>(m, n, l, d, blk0, p);
   if (work_bytes < need)
     return fail(FFSRQR_EWORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
@@ -339,6 +343,7 @@ ffsrqr_status factor_impl(const T* A, int64_t m, int64_t n, int64_t lda, int64_t
   T* R11 = ar.take<T>((size_t)l * l);
   double* anorm2 = ar.take<double>(n);
   double* gamma2 = ar.take<double>(n);
+  double* est = ar.take<double>(n);
   double* margins = ar.take<double>(l);
   double* rho = ar.take<double>(l + 1);
   int64_t* S = ar.take<int64_t>(l);
@@ -419,9 +424,11 @@ ffsrqr_status factor_impl(const T* A, int64_t m, int64_t n, int64_t lda, int64_t
     Arena a = scratch();
     tm.begin(FFSRQR_STEP_QRCP);
     if (blk > 0) {
-      const hipError_t e = trqrcp_select<T>(A, m, n, lda, l, blk, p, region2, S, margins, a, err, d, s);
+      const hipError_t e = trqrcp_select<T>(A, m, n, lda, l, blk, p, region2, S, margins, a, err, d, s, est_mode);
       if (e == hipErrorInvalidValue) return fail(FFSRQR_EHIP, "blocked pivot selection: invalid pivot");
       FF_HIP(e);
+      // Algorithm 4's residual norm estimates from the sample after the last block
+      if (est_mode) FF_HIP(sample_norms<T>(region2, srows, n, est, s));
     } else {
       FF_HIP(qrcp<T>(region2, l, n, l, S, margins, a, err, d, s));
     }
@@ -473,6 +480,8 @@ ffsrqr_status factor_impl(const T* A, int64_t m, int64_t n, int64_t lda, int64_t
     return fail(FFSRQR_EHIP, "a device-wide wait exceeded its spin limit; the outputs are incomplete");
   };
   bool lq_current = false;  // L, V, sigma belong to the current leading set
+  bool redo = false;        // the next test runs on the same leading set (estimates: identity rotation)
+  int64_t removed_col = -1; // original index of the column the next swap removes
   unsigned herr[64];
   std::vector<int64_t> hS;
   for (int iter = 0;; ++iter) {
@@ -500,13 +509,14 @@ ffsrqr_status factor_impl(const T* A, int64_t m, int64_t n, int64_t lda, int64_t
         }
         tm.end();
       }
-    } else {
+    } else if (!redo) {
       // Algorithm 4's swap as an update of Q, R11 and W (rotations, one new
       // column, one pass over A for the new row); S was updated on the host
       tm.begin(FFSRQR_STEP_SWAP);
       {
         Arena a = scratch();
-        FF_HIP(srqr_swap_update<T>(A, m, n, lda, Q, ldq, W, l, R11, l, l, hs.istar, hs.jstar, a, s));
+        FF_HIP(srqr_swap_update<T>(A, m, n, lda, Q, ldq, W, l, R11, l, l, hs.istar, hs.jstar, a, s,
+                                   est_mode ? est : nullptr, removed_col));
       }
       FF_HIP(build_perm(S, l, n, perm, inS, cnt, s));
       tm.end();
@@ -519,14 +529,16 @@ ffsrqr_status factor_impl(const T* A, int64_t m, int64_t n, int64_t lda, int64_t
     FF_HIP(hipStreamWaitEvent(side->stream, side->fork, 0));
     {
       const int h = tm.begin(FFSRQR_STEP_RESID, side->stream);
-      FF_HIP(residual_norms<T>(W, l, n, l, anorm2, gamma2, side->stream));
+      if (!est_mode) FF_HIP(residual_norms<T>(W, l, n, l, anorm2, gamma2, side->stream));
       tm.end(h, side->stream);
     }
     {
       const int h = tm.begin(FFSRQR_STEP_SRQR, side->stream);
       Arena a = a_side;
-      FF_HIP(srqr_select<T>(gamma2, anorm2, inS, n, A, m, lda, Q, ldq, W, l, R11, l, l, st, a, side->stream,
-                            select_window<T>(m, l, mixed)));
+      // with the estimates j* is their argmax (a zero window: only exact
+      // ties are candidates) and alpha its exact residual norm
+      FF_HIP(srqr_select<T>(est_mode ? est : gamma2, anorm2, inS, n, A, m, lda, Q, ldq, W, l, R11, l, l, st, a,
+                            side->stream, est_mode ? 0.0 : select_window<T>(m, l, mixed)));
       if (l < n) {
         Arena a2 = a_side;
         ++probe_q;
@@ -548,8 +560,9 @@ ffsrqr_status factor_impl(const T* A, int64_t m, int64_t n, int64_t lda, int64_t
     } else {
       FF_HIP(hipEventRecord(side->join, side->stream));
       FF_HIP(hipStreamWaitEvent(s, side->join, 0));
-      lq_current = false;
+      if (!redo) lq_current = false;
     }
+    redo = false;
     FF_HIP(hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, s));
     FF_HIP(hipMemcpyAsync(herr, err, sizeof(herr), hipMemcpyDeviceToHost, s));
     FF_HIP(hipStreamSynchronize(s));
@@ -589,6 +602,13 @@ ffsrqr_status factor_impl(const T* A, int64_t m, int64_t n, int64_t lda, int64_t
       }
       ++rotations;
       if (!(probe && hs.istar == l)) break;
+      if (est_mode) {
+        // j* returns to the (l+1)-st position with its exact residual norm:
+        // the selection runs again on the same leading set
+        FF_HIP(est_reset_jstar(est, st, s));
+        redo = true;
+        break;
+      }
       ++probe_q;
       tm.begin(FFSRQR_STEP_SRQR);
       {
@@ -600,6 +620,7 @@ ffsrqr_status factor_impl(const T* A, int64_t m, int64_t n, int64_t lda, int64_t
       FF_HIP(hipStreamSynchronize(s));
     }
     if (done) break;
+    if (redo) continue;
     // round-robin swap: S <- (S without S[istar]) followed by jstar
     if (hs.istar < 0 || hs.istar >= l || hs.jstar < 0 || hs.jstar >= n)
       return fail(FFSRQR_EHIP, "invalid swap candidates");
@@ -607,6 +628,7 @@ ffsrqr_status factor_impl(const T* A, int64_t m, int64_t n, int64_t lda, int64_t
       hS.resize((size_t)l);
       FF_HIP(hipMemcpy(hS.data(), S, (size_t)l * sizeof(int64_t), hipMemcpyDeviceToHost));
     }
+    removed_col = hS[(size_t)hs.istar];
     hS.erase(hS.begin() + hs.istar);
     hS.push_back(hs.jstar);
     FF_HIP(hipMemcpyAsync(S, hS.data(), (size_t)l * sizeof(int64_t), hipMemcpyHostToDevice, s));
@@ -1068,6 +1090,8 @@ void ffsrqr_default_opts(ffsrqr_opts* o) {
   o->g = 2.0;
   o->block = 0;
   o->g2_probe = 0;
+  o->est_norms = 0;
+  o->reserved = 0;
 }
 
 const char* ffsrqr_status_string(ffsrqr_status s) {
@@ -1127,6 +1151,8 @@ ffsrqr_status ffsrqr_workspace_size(int64_t m, int64_t n, int64_t k, int64_t p, 
   const int64_t blk = opts && opts->block > 0 ? std::min<int64_t>(opts->block, k) : 0;
   if (opts && (opts->g2_probe < 0 || opts->g2_probe > kMaxProbe))
     return fail(FFSRQR_EINVAL, "g2_probe must be 0 (exact) or 1..64");
+  if (opts && opts->est_norms != 0 && (opts->est_norms != 1 || opts->block <= 0))
+    return fail(FFSRQR_EINVAL, "est_norms must be 0, or 1 with the blocked selection (block > 0)");
   if (opts && opts->block != 0) {
     st = check_block(m, n, k, p, l, opts->block);
     if (st != FFSRQR_OK) return st;

@@ -164,7 +164,13 @@ size_t trqrcp_scratch(int64_t m, int64_t n, int64_t l, int64_t b, int64_t p, con
 template <typename T>
 hipError_t trqrcp_select(const T* A, int64_t m, int64_t n, int64_t lda, int64_t l, int64_t b, int64_t p, T* B,
                          int64_t* S, double* margins, Arena& ar, unsigned* err, const DeviceInfo& d,
-                         hipStream_t s);
+                         hipStream_t s, bool final_update = false);
+// Algorithm 4's residual norm estimates from the updated sample:
+// r[c] = ||B(:, c)||^2 / rows (B rows x n, ldb = rows).
+template <typename T>
+hipError_t sample_norms(const T* B, int64_t rows, int64_t n, double* r, hipStream_t s);
+// est[st->jstar] = st->alpha^2 (the estimate of j* after an identity rotation)
+hipError_t est_reset_jstar(double* est, const SrqrState* st, hipStream_t s);
 
 // One swap of Algorithm 4 as an update in place of A(:, S) = Q R11 and
 // W = Q^T A: leading position istar leaves, trailing column jstar becomes
@@ -173,8 +179,15 @@ hipError_t trqrcp_select(const T* A, int64_t m, int64_t n, int64_t lda, int64_t 
 template <typename T>
 size_t swap_scratch(int64_t m, int64_t l);
 template <typename T>
+// With est non-null the residual norm estimates follow the swap:
+// est[c] += W_rot(l-1, c)^2 - W_new(l-1, c)^2, the exact change of c's
+// squared residual norm (W_rot: W after the rotations, whose last row belongs
+// to the removed column's direction; W_new: with the new last row), and
+// est[icol] (the removed column, original index) starts from 0, so that it
+// ends exact.
 hipError_t srqr_swap_update(const T* A, int64_t m, int64_t n, int64_t lda, T* Q, int64_t ldq, T* W, int64_t ldw,
-                            T* R11, int64_t ldr, int64_t l, int64_t istar, int64_t jstar, Arena& ar, hipStream_t s);
+                            T* R11, int64_t ldr, int64_t l, int64_t istar, int64_t jstar, Arena& ar, hipStream_t s,
+                            double* est = nullptr, int64_t icol = -1);
 
 // Tensors (the ST-HOSVD driver), order at most kMaxTensorOrder.  The mode-a
 // unfolding holds entry (i_0..i_{d-1}) at i_a + n_a c_a, c_a the

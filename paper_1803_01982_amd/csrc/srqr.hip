@@ -381,6 +381,10 @@ __global__ void probe_rho_kernel(const double* __restrict__ X, int64_t l, int d,
   }
 }
 
+__global__ void est_reset_kernel(double* est, const SrqrState* st) {
+  if (threadIdx.x == 0 && st->jstar >= 0) est[st->jstar] = st->alpha * st->alpha;
+}
+
 // ------------------------------------------------------------------ perm
 __global__ void perm_clear(int64_t n, unsigned char* inS) {
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x)
@@ -557,6 +561,11 @@ hipError_t srqr_probe(const T* R11, int64_t ldr, const T* a, int64_t a_stride, c
   if (e != hipSuccess) return e;
   trinv_kernel<T><<<(unsigned)(d + 1), NT, lds, s>>>(R11, ldr, l, a, a_stride, sel, P, l + 1, d, X);
   probe_rho_kernel<<<1, NT, 0, s>>>(X, l, d, P, sel, alpha_host, est, st_out);
+  return hipGetLastError();
+}
+
+hipError_t est_reset_jstar(double* est, const SrqrState* st, hipStream_t s) {
+  est_reset_kernel<<<1, 64, 0, s>>>(est, st);
   return hipGetLastError();
 }
 

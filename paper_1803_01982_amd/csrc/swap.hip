@@ -29,6 +29,7 @@
 // Arithmetic is FP64 throughout, on T (FP32 or FP64) storage.  Work per
 // swap: about 2(l - istar)(m + n) flops for the rotations, 6 m l for the
 // new column and 2 m n for the new row (the pass over A).
+#include <algorithm>
 #include <cmath>
 
 #include "common.hpp"
@@ -179,6 +180,18 @@ __global__ void swap_rotate_kernel(T* __restrict__ X, int64_t nvec, int64_t vs, 
   x[(int64_t)(l - 1) * es] = (T)run;
 }
 
+// est[c] += sign W(l-1, c)^2 over all columns; with sign > 0, est[icol]
+// starts from 0.
+template <typename T>
+__global__ void est_row_kernel(const T* __restrict__ W, int64_t ldw, int l, int64_t n, double* __restrict__ est,
+                               int64_t icol, double sign) {
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
+    const double w = (double)W[c * ldw + l - 1];
+    const double base = (c == icol) ? 0.0 : est[c];
+    est[c] = fma(sign * w, w, base);
+  }
+}
+
 // v = a_jstar - Q(:, 0:l-2) w(0:l-2), w = W(:, jstar); one thread per row.
 template <typename T>
 __global__ void swap_resid_kernel(const T* __restrict__ A, int64_t lda, int64_t jstar, const T* __restrict__ Q,
@@ -285,9 +298,12 @@ size_t swap_scratch(int64_t m, int64_t l) {
 
 template <typename T>
 hipError_t srqr_swap_update(const T* A, int64_t m, int64_t n, int64_t lda, T* Q, int64_t ldq, T* W, int64_t ldw,
-                            T* R11, int64_t ldr, int64_t l, int64_t istar, int64_t jstar, Arena& ar, hipStream_t s) {
+                            T* R11, int64_t ldr, int64_t l, int64_t istar, int64_t jstar, Arena& ar, hipStream_t s,
+                            double* est, int64_t icol) {
   if (l < 1 || istar < 0 || istar >= l || jstar < 0 || jstar >= n || m < 1 || l > INT32_MAX / 2)
     return hipErrorInvalidValue;
+  if (est && (icol < 0 || icol >= n)) return hipErrorInvalidValue;
+  const unsigned eb = (unsigned)std::min<int64_t>((n + NT - 1) / NT, 4096);
   const int li = (int)l, is = (int)istar;
   T* Rn = ar.take<T>((size_t)l * l);
   double* cs = ar.take<double>(2 * (size_t)l);
@@ -313,6 +329,8 @@ hipError_t srqr_swap_update(const T* A, int64_t m, int64_t n, int64_t lda, T* Q,
       swap_rotate_kernel<T><<<(unsigned)((m + NT - 1) / NT), NT, 0, s>>>(Q, m, 1, ldq, li, is, cs);
     }
   }
+  // the rotated last row belongs to the removed column's direction
+  if (est) est_row_kernel<T><<<eb, NT, 0, s>>>(W, ldw, li, n, est, icol, 1.0);
   // 2. the new last column of Q and R11
   swap_resid_kernel<T><<<(unsigned)nb, NT, lds_c, s>>>(A, lda, jstar, Q, ldq, W, ldw, m, li, v);
   if (l > 1) swap_proj_kernel<T><<<(unsigned)(l - 1), NT, 0, s>>>(Q, ldq, m, v, c);
@@ -326,13 +344,14 @@ hipError_t srqr_swap_update(const T* A, int64_t m, int64_t n, int64_t lda, T* Q,
   swap_qcol_kernel<T><<<(unsigned)nb, NT, 0, s>>>(v, rho, m, li, Q, ldq);
   // 3. row l-1 of W: the pass over A
   swap_row_kernel<T><<<(unsigned)((n + RCOLS - 1) / RCOLS), NT, 0, s>>>(A, lda, m, n, Q, ldq, li, W, ldw);
+  if (est) est_row_kernel<T><<<eb, NT, 0, s>>>(W, ldw, li, n, est, -1, -1.0);
   return hipGetLastError();
 }
 
 #define INST(T)                                                                                                     \
   template size_t swap_scratch<T>(int64_t, int64_t);                                                                \
   template hipError_t srqr_swap_update<T>(const T*, int64_t, int64_t, int64_t, T*, int64_t, T*, int64_t, T*, int64_t, \
-                                          int64_t, int64_t, int64_t, Arena&, hipStream_t);
+                                          int64_t, int64_t, int64_t, Arena&, hipStream_t, double*, int64_t);
 INST(double)
 INST(float)
 #undef INST

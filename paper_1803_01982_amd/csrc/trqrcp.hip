@@ -14,7 +14,10 @@
 //      Omega applied to their new residual.
 // The blocks' basis only steers the pivot choice: the path then factors the
 // chosen columns from scratch (the thin QR with a positive diagonal is
-// unique, so it is the factorization Algorithm 2 accumulates).
+// unique, so it is the factorization Algorithm 2 accumulates).  With
+// final_update the last block updates the sample too, so that B(:, c) is
+// Omega times the residual of column c after all l pivots: Algorithm 4's
+// residual norm estimates are ||B(:, c)||^2 / rows (sample_norms).
 #include <numeric>
 #include <vector>
 
@@ -26,6 +29,20 @@ namespace ffsrqr {
 namespace {
 
 constexpr int NT = 256;
+
+// r[c] = ||B(:, c)||^2 / rows (FP64), one thread per column
+template <typename T>
+__global__ void sample_norms_kernel(const T* __restrict__ B, int64_t rows, int64_t n, double* __restrict__ r) {
+  const int64_t c = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (c >= n) return;
+  const T* b = B + c * rows;
+  double acc = 0.0;
+  for (int64_t i = 0; i < rows; ++i) {
+    const double v = (double)b[i];
+    acc = fma(v, v, acc);
+  }
+  r[c] = acc / (double)rows;
+}
 
 template <typename T>
 __global__ void sub_kernel(T* __restrict__ P, const T* __restrict__ D, int64_t total) {
@@ -113,7 +130,7 @@ size_t trqrcp_scratch(int64_t m, int64_t n, int64_t l, int64_t b, int64_t p, con
 template <typename T>
 hipError_t trqrcp_select(const T* A, int64_t m, int64_t n, int64_t lda, int64_t l, int64_t b, int64_t p, T* B,
                          int64_t* S, double* margins, Arena& ar, unsigned* err, const DeviceInfo& d,
-                         hipStream_t s) {
+                         hipStream_t s, bool final_update) {
   const int64_t rows = trqrcp_rows(m, b, p);
   if (b < 1 || b > 64 || l < 1 || n - l + 1 < rows) return hipErrorInvalidValue;
   TrqLayout<T> o;
@@ -187,7 +204,7 @@ hipError_t trqrcp_select(const T* A, int64_t m, int64_t n, int64_t lda, int64_t 
     if ((e = transpose<T>(Qb, m, bj, m, o.QT + j, l, s)) != hipSuccess) return e;
     // 3. R12 and the sample update of the remaining columns
     const int64_t nr = (int64_t)rest.size();
-    if (nr > 0 && j + bj < l) {
+    if (nr > 0 && (j + bj < l || final_update)) {
       if ((e = hipMemcpyAsync(o.rest, rest.data(), (size_t)nr * sizeof(int64_t), hipMemcpyHostToDevice, s)) !=
           hipSuccess)
         return e;
@@ -211,10 +228,19 @@ hipError_t trqrcp_select(const T* A, int64_t m, int64_t n, int64_t lda, int64_t 
   return hipStreamSynchronize(s);
 }
 
+template <typename T>
+hipError_t sample_norms(const T* B, int64_t rows, int64_t n, double* r, hipStream_t s) {
+  if (n <= 0 || rows <= 0) return hipSuccess;
+  sample_norms_kernel<T><<<(unsigned)((n + NT - 1) / NT), NT, 0, s>>>(B, rows, n, r);
+  return hipGetLastError();
+}
+
 #define INST(T)                                                                                                   \
   template size_t trqrcp_scratch<T>(int64_t, int64_t, int64_t, int64_t, int64_t, const DeviceInfo&);             \
   template hipError_t trqrcp_select<T>(const T*, int64_t, int64_t, int64_t, int64_t, int64_t, int64_t, T*,       \
-                                       int64_t*, double*, Arena&, unsigned*, const DeviceInfo&, hipStream_t);
+                                       int64_t*, double*, Arena&, unsigned*, const DeviceInfo&, hipStream_t,    \
+                                       bool);                                                                    \
+  template hipError_t sample_norms<T>(const T*, int64_t, int64_t, double*, hipStream_t);
 INST(double)
 INST(float)
 #undef INST

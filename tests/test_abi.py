@@ -253,6 +253,18 @@ def test_probe_option_checks(lib):
     assert f(one, 8, 4, one, 1.0, 4, 1, 1, one, one, 1 << 20, 0, None) == 1    # ldr < l
 
 
+def test_est_norms_option_checks(lib):
+    from paper_1803_01982_amd import _lib
+    out = C.c_size_t(0)
+    ws = lib.ffsrqr_workspace_size
+    assert ws(1000, 800, 20, 10, C.byref(_lib.Opts(0, -1, 2.0, 16, 0, 1)), C.byref(out)) == 0
+    assert ws(1000, 800, 20, 10, C.byref(_lib.Opts(0, -1, 2.0, 0, 0, 1)), C.byref(out)) == 1   # needs block
+    assert b"est_norms" in lib.ffsrqr_last_error()
+    assert ws(1000, 800, 20, 10, C.byref(_lib.Opts(0, -1, 2.0, 16, 0, 2)), C.byref(out)) == 1
+    est = _lib.Opts(0, -1, 2.0, 0, 0, 1)
+    assert lib.ffsrqr_rpca_workspace_size(500, 400, 10, 0, C.byref(est), C.byref(out)) == 1
+
+
 def test_drivers_refuse_the_blocked_selection(lib):
     from paper_1803_01982_amd import _lib
     out = C.c_size_t(0)
