@@ -331,14 +331,14 @@ def st_hosvd(X: torch.Tensor, ranks, p: int, seed: int = 0, order=None, mixed: b
 
 
 def factor_batched(As, ks, ps, seeds=None, g: float = 2.0, max_swaps: int = -1, mixed: bool = False, work=None,
-                   stream=None) -> list:
+                   stream=None, g2_probe: int = 0) -> list:
     """ffsrqr_factor_batched: one call over many problems (column-major A's
     of one dtype); returns one Factorization per problem."""
     lib = L.load()
     cnt = len(As)
     seeds = [0] * cnt if seeds is None else list(seeds)
     prec = _prec(As[0].dtype, mixed)
-    o = opts(prec, g, max_swaps)
+    o = opts(prec, g, max_swaps, g2_probe=g2_probe)
     probs = (L.Problem * cnt)()
     outs, infos = [], []
     for i, A in enumerate(As):

@@ -64,3 +64,22 @@ def test_batched_sample_against_oracle(ff, batch, idx):
     A, k = batch[order[idx]]
     announce(f"batch problem {order[idx]}: {A.shape[0]}x{A.shape[1]} k={k} fp32 vs oracle")
     compare(ff, A, k, 10, 0, dtype=torch.float32, tol=FP32_TOL, margin_floor=1e-5)
+
+
+def test_batched_with_probe_equals_single_calls(ff, batch):
+    """The options reach every problem of a batch: with the random g2 probe
+    (d = 8) the first 16 problems give the same results as single calls with
+    the same option (the probe streams restart with each problem)."""
+    import torch
+    announce("factor_batched 16 problems, fp32, p=10, g2_probe=8")
+    sub = batch[:16]
+    As = [dev_f(A, torch.float32) for A, _ in sub]
+    ks = [k for _, k in sub]
+    outs = ff.factor_batched(As, ks, [10] * len(As), g2_probe=8)
+    singles = [ff.factor(A, k, 10, g2_probe=8) for A, k in zip(As, ks)]
+    torch.cuda.synchronize()
+    for i, (b, s) in enumerate(zip(outs, singles)):
+        assert b.info["probes"] >= 1 and b.info["probes"] == s.info["probes"], i
+        assert np.array_equal(host(b.perm), host(s.perm)), i
+        assert np.array_equal(host(b.sigma), host(s.sigma)), i
+        assert b.info["swaps"] == s.info["swaps"] and b.info["g2"] == s.info["g2"], i
