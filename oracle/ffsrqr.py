@@ -44,10 +44,11 @@ design notes):
   * Column norms on B are recomputed from scratch at every step (no
     downdating), ties go to the smallest original column index.
   * Residual norms gamma_j of the trailing columns are exact,
-    ||(I - Q1 Q1^T) a_j||, by default.  With est_norms (blocked selection
-    only, where the sample is kept up to date) they are Algorithm 4's
-    estimates instead: r_i = ||B(:, i)||^2 / (sample rows) from the sample
-    after the last block's update, j* = argmax r_i, alpha the exact residual
+    ||(I - Q1 Q1^T) a_j||, by default.  With est_norms they are Algorithm
+    4's estimates instead: r_i = ||B(:, i)||^2 / (sample rows) from the
+    sample after the last block's update (for the one-block selection, the
+    update of Algorithm 2 with all l pivots as the block, B(:, rest) -=
+    B(:, S) R11^{-1} R12), j* = argmax r_i, alpha the exact residual
     norm of column j*; before each test r_i -= (row l+1 of R of [S, j*])_i^2;
     after a swap r_i += (row l+1 of R of [S', i*])_i^2 for the trailing
     columns and r_{i*} = R_{l+1,l+1}^2 (the squared rows of the retriangularised
@@ -339,6 +340,21 @@ def srqr_rho(R11: np.ndarray, a: np.ndarray, alpha: float) -> np.ndarray:
     return abs(alpha) * np.sqrt(np.sum(X * X, axis=1))
 
 
+def sample_update(A: np.ndarray, B: np.ndarray, S) -> np.ndarray:
+    """Algorithm 2's sample update with the pivots S as one block: B(:, c) -
+    B(:, S) R11^{-1} R12(:, c) for the columns c outside S (zero columns at
+    S), R11 and R12 from the QR of A(:, S); equal to Omega times the residual
+    of column c when B = Omega A."""
+    S = list(S)
+    perm, Q1, R11, R, W = factor_leading_set(A, S)
+    out = np.zeros_like(B, dtype=np.float64)
+    chosen = set(S)
+    for c in range(A.shape[1]):
+        if c not in chosen:
+            out[:, c] = B[:, c] - B[:, S] @ back_substitute(R11, W[:, c])
+    return out
+
+
 def row_l1(A: np.ndarray, S, j: int) -> np.ndarray:
     """Row l+1 of R in the QR of A(:, S + [j]) over all columns of A:
     q^T A with q the last column of the Householder Q of those l+1 columns
@@ -530,15 +546,13 @@ def ffsrqr(A: np.ndarray, k: int, p: int, seed: int, g: float = 2.0,
     precision the data is held in ("fp64" or "fp32"); it only sets the rank
     tolerance (rank_tolerance()).  g2_probe = d > 0 replaces the exact g2 by
     Algorithm 4's d-row random estimate (g2_probe_estimate, probe_omega).
-    est_norms (needs block > 0) replaces the exact residual norms that pick
-    j* by Algorithm 4's sample estimates (row_l1, and the module notes).
+    est_norms replaces the exact residual norms that pick j* by Algorithm
+    4's sample estimates (sample_update, row_l1, and the module notes).
     """
     A = np.asarray(A)
     m, n = A.shape
     if not (1 <= k <= min(m, n)) or p < 0 or not g > 1.0 or g2_probe < 0:
         raise ValueError("bad arguments")
-    if est_norms and block <= 0:
-        raise ValueError("the sample-estimated residual norms need the blocked selection")
     flags = 0
     l = min(k + p, m, n)
     if l < k + p:
@@ -576,6 +590,9 @@ def ffsrqr(A: np.ndarray, k: int, p: int, seed: int, g: float = 2.0,
         # a2
         pivots, margins, _ = qrcp_sketch(B, l)
         S = [int(s) for s in pivots[:l]]
+        if est_norms:
+            Bu = sample_update(Af, B, S)
+            r = np.sum(Bu * Bu, axis=0) / B.shape[0]
 
     swaps = 0
     est_out = None

@@ -11,6 +11,8 @@ norm estimate and its downdates and updates; Algorithm 2, the sample update).
   r_i - ||(I - P_S) a_i||^2 equals r_i(initial) - ||(I - P_S0) a_i||^2 for a
   column never in the leading set, and is zero for a column that left it
   (its estimate is reset to an exact R entry).
+* The same holds for the one-block selection, whose sample update takes
+  all l pivots as one block.
 * With enough sample rows the estimates pick the same j* as exact norms on
   a matrix with well separated residual norms.
 """
@@ -96,7 +98,41 @@ def test_estimates_agree_with_exact_norms_on_separated_columns():
     assert abs(ex.alpha - es.alpha) <= 1e-12 * ex.alpha
 
 
-def test_estimates_need_the_blocked_selection():
-    A = synth.random_matrix(50, 40, seed=1)
-    with pytest.raises(ValueError):
-        oracle.ffsrqr(A, 5, 2, 0, est_norms=True)
+def test_one_block_sample_update_is_omega_times_the_residual():
+    # the one-block selection: an l-row sample, all l pivots as the block
+    A = synth.spectrum_matrix(200, 150, 0.95 ** np.arange(150), seed=4, noise=1e-9)
+    l, seed = 30, 9
+    Om = oracle.omega(seed, l, A.shape[0])
+    B = Om @ A
+    piv, _, _ = oracle.qrcp_sketch(B, l)
+    S = [int(s) for s in piv[:l]]
+    from oracle.ffsrqr import sample_update
+    Bu = sample_update(A, B, S)
+    rest = [c for c in range(A.shape[1]) if c not in set(S)]
+    Q, _ = np.linalg.qr(A[:, S])
+    ref = Om @ (A[:, rest] - Q @ (Q.T @ A[:, rest]))
+    assert np.max(np.abs(Bu[:, rest] - ref)) <= 1e-10 * np.max(np.abs(ref))
+    assert np.all(Bu[:, S] == 0.0)
+
+
+def test_one_block_estimates_carry_their_errors_through_the_swaps():
+    A = synth.spectrum_matrix(300, 200, 0.97 ** np.arange(200), seed=5, noise=1e-8)
+    k, p, seed = 20, 6, 1
+    res = oracle.ffsrqr(A, k, p, seed, g=1.05, est_norms=True, max_swaps=12)
+    l = res.l
+    S0 = res.history[0][0]
+    B = oracle.sketch(oracle.omega(seed, l, A.shape[0]), A)
+    from oracle.ffsrqr import sample_update
+    Bu = sample_update(A, B, S0)
+    r0 = np.sum(Bu * Bu, axis=0) / l
+    S = list(res.perm[:l])
+    ever = set()
+    for h in res.history:
+        ever |= set(h[0])
+    trailing = [c for c in range(A.shape[1]) if c not in set(S)]
+    never = [c for c in trailing if c not in ever]
+    scale = float(np.max(np.sum(A * A, axis=0)))
+    e_fin = res.norm_estimates[never] - _resid2(A, S, never)
+    e_ini = r0[never] - _resid2(A, S0, never)
+    assert res.swaps >= 1
+    assert np.max(np.abs(e_fin - e_ini)) <= 1e-12 * scale
