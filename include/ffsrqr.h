@@ -104,10 +104,13 @@ typedef struct {
                         (ffsrqr_srqr_probe).  When the argmax is the (l+1)-st
                         position the rotation is the identity and the next test
                         draws P_{q+1}; max_swaps counts these too.               */
-  int32_t est_norms; /* 0: j* is chosen by exact residual norms; 1 (needs block
-                        > 0): by Algorithm 4's estimates r_i = ||B(:, i)||^2 /
-                        rows from the sample after the last block's update,
-                        kept through the swaps by the exact changes of the
+  int32_t est_norms; /* 0: j* is chosen by exact residual norms; 1: by
+                        Algorithm 4's estimates r_i = ||B(:, i)||^2 / rows
+                        from the sample after the last block's update (block
+                        0: the l-row sketch updated with all l pivots as one
+                        block, B(:, rest) -= B(:, S) R11^{-1} R12, which needs
+                        an l x n product more workspace), kept through the
+                        swaps by the exact changes of the
                         squared residual norms (the rows of R that leave and
                         enter); alpha stays the exact residual norm of j*, and
                         after an identity rotation r_{j*} = alpha^2.  Not for

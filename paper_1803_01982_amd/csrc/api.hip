@@ -122,9 +122,11 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // Persistent buffers of the whole path followed by one scratch region shared
 // by the stages (they run in stream order).
 template <typename T>
-size_t scratch_bytes(int64_t m, int64_t n, int64_t l, const DeviceInfo& d, int64_t block = 0, int64_t p = 0) {
+size_t scratch_bytes(int64_t m, int64_t n, int64_t l, const DeviceInfo& d, int64_t block = 0, int64_t p = 0,
+                     bool est = false) {
   size_t s = 0;
   if (block > 0) s = std::max(s, trqrcp_scratch<T>(m, n, l, block, p, d));
+  if (est && block <= 0) s = std::max(s, one_block_estimates_scratch<T>(l, n, d));
   s = std::max(s, gemm_tn_scratch<T>(l, n, m, d.num_cu));
   if (sizeof(T) == 4) s = std::max(s, gemm_bf16_scratch(l, n, m, d.num_cu));
   s = std::max(s, qrcp_scratch<T>(l, n, d));
@@ -156,8 +158,9 @@ size_t persistent_bytes(int64_t m, int64_t n, int64_t l) {
 }
 
 template <typename T>
-size_t total_bytes(int64_t m, int64_t n, int64_t l, const DeviceInfo& d, int64_t block = 0, int64_t p = 0) {
-  return persistent_bytes<T>(m, n, l) + scratch_bytes<T>(m, n, l, d, block, p);
+size_t total_bytes(int64_t m, int64_t n, int64_t l, const DeviceInfo& d, int64_t block = 0, int64_t p = 0,
+                   bool est = false) {
+  return persistent_bytes<T>(m, n, l) + scratch_bytes<T>(m, n, l, d, block, p, est);
 }
 
 ffsrqr_status get_device(const DeviceInfo** out) {
@@ -269,7 +272,7 @@ ffsrqr_status check_driver_opts(const ffsrqr_opts* o) {
   if (o->block != 0)
     return fail(FFSRQR_EINVAL, "opts.block is for ffsrqr_factor and ffsrqr_factor_batched; the drivers need 0");
   if (o->g2_probe < 0 || o->g2_probe > kMaxProbe) return fail(FFSRQR_EINVAL, "g2_probe must be 0 (exact) or 1..64");
-  if (o->est_norms != 0) return fail(FFSRQR_EINVAL, "est_norms needs the blocked selection, which the drivers do not run");
+  if (o->est_norms != 0) return fail(FFSRQR_EINVAL, "est_norms is for ffsrqr_factor and ffsrqr_factor_batched");
   return FFSRQR_OK;
 }
 
@@ -328,10 +331,9 @@ ffsrqr_status factor_impl(const T* A, int64_t m, int64_t n, int64_t lda, int64_t
   uint32_t flags = (l < k + p) ? FFSRQR_FLAG_L_CLAMPED : 0u;
   const int64_t blk0 = op.block > 0 ? std::min<int64_t>(op.block, k) : 0;
   if (op.g2_probe < 0 || op.g2_probe > kMaxProbe) return fail(FFSRQR_EINVAL, "g2_probe must be 0 (exact) or 1..64");
-  if (op.est_norms != 0 && (op.est_norms != 1 || op.block <= 0))
-    return fail(FFSRQR_EINVAL, "est_norms must be 0, or 1 with the blocked selection (block > 0)");
+  if (op.est_norms != 0 && op.est_norms != 1) return fail(FFSRQR_EINVAL, "est_norms must be 0 or 1");
   const bool est_mode = op.est_norms == 1;
-  const size_t need = total_bytes<T>(m, n, l, d, blk0, p);
+  const size_t need = total_bytes<T>(m, n, l, d, blk0, p, est_mode);
   if (work_bytes < need)
     return fail(FFSRQR_EWORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
 
@@ -508,6 +510,12 @@ ffsrqr_status factor_impl(const T* A, int64_t m, int64_t n, int64_t lda, int64_t
           FF_HIP(gemm_tn<T>(l, n, m, Q, ldq, A, lda, W, l, nullptr, a, d.num_cu, s));
         }
         tm.end();
+      }
+      if (est_mode && blk == 0 && l < n) {
+        // Algorithm 4's estimates for the one-block selection: the l-row
+        // sketch (still in region2) updated with all l pivots as one block
+        Arena a = scratch();
+        FF_HIP(one_block_estimates<T>(region2, l, n, S, R11, l, W, l, est, a, d, s));
       }
     } else if (!redo) {
       // Algorithm 4's swap as an update of Q, R11 and W (rotations, one new
@@ -1151,13 +1159,14 @@ ffsrqr_status ffsrqr_workspace_size(int64_t m, int64_t n, int64_t k, int64_t p, 
   const int64_t blk = opts && opts->block > 0 ? std::min<int64_t>(opts->block, k) : 0;
   if (opts && (opts->g2_probe < 0 || opts->g2_probe > kMaxProbe))
     return fail(FFSRQR_EINVAL, "g2_probe must be 0 (exact) or 1..64");
-  if (opts && opts->est_norms != 0 && (opts->est_norms != 1 || opts->block <= 0))
-    return fail(FFSRQR_EINVAL, "est_norms must be 0, or 1 with the blocked selection (block > 0)");
+  if (opts && opts->est_norms != 0 && opts->est_norms != 1) return fail(FFSRQR_EINVAL, "est_norms must be 0 or 1");
   if (opts && opts->block != 0) {
     st = check_block(m, n, k, p, l, opts->block);
     if (st != FFSRQR_OK) return st;
   }
-  *bytes = prec == FFSRQR_FP64 ? total_bytes<double>(m, n, l, d, blk, p) : total_bytes<float>(m, n, l, d, blk, p);
+  const bool est = opts && opts->est_norms == 1;
+  *bytes = prec == FFSRQR_FP64 ? total_bytes<double>(m, n, l, d, blk, p, est)
+                               : total_bytes<float>(m, n, l, d, blk, p, est);
   return FFSRQR_OK;
 }
 

@@ -44,6 +44,37 @@ __global__ void sample_norms_kernel(const T* __restrict__ B, int64_t rows, int64
   r[c] = acc / (double)rows;
 }
 
+// Row i of G = B(:, S) R11^{-1} (l x l) by forward substitution on the row
+// vector (g R11 = B(i, S)), FP64, written as column i of Gt (Gt = G^T):
+// g_j = b_j / R11(j, j), then b_k -= g_j R11(j, k) for k > j.
+template <typename T>
+__global__ void right_trsm_kernel(const T* __restrict__ B, int64_t ldb, const int64_t* __restrict__ S, int64_t l,
+                                  const T* __restrict__ R11, int64_t ldr, T* __restrict__ Gt) {
+  extern __shared__ double bsh[];  // l
+  const int64_t i = blockIdx.x;
+  for (int64_t j = threadIdx.x; j < l; j += NT) bsh[j] = (double)B[S[j] * ldb + i];
+  for (int64_t j = 0; j < l; ++j) {
+    __syncthreads();
+    const double g = bsh[j] / (double)R11[j * ldr + j];
+    for (int64_t k = j + 1 + threadIdx.x; k < l; k += NT) bsh[k] = fma(-g, (double)R11[k * ldr + j], bsh[k]);
+    if (threadIdx.x == 0) Gt[i * l + j] = (T)g;
+  }
+}
+
+// r[c] = ||B(:, c) - C(:, c)||^2 / rows (FP64), one thread per column
+template <typename T>
+__global__ void sample_resid_kernel(const T* __restrict__ B, const T* __restrict__ Cm, int64_t rows, int64_t n,
+                                    double* __restrict__ r) {
+  const int64_t c = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (c >= n) return;
+  double acc = 0.0;
+  for (int64_t i = 0; i < rows; ++i) {
+    const double v = (double)B[c * rows + i] - (double)Cm[c * rows + i];
+    acc = fma(v, v, acc);
+  }
+  r[c] = acc / (double)rows;
+}
+
 template <typename T>
 __global__ void sub_kernel(T* __restrict__ P, const T* __restrict__ D, int64_t total) {
   for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT)
@@ -235,7 +266,38 @@ hipError_t sample_norms(const T* B, int64_t rows, int64_t n, double* r, hipStrea
   return hipGetLastError();
 }
 
+template <typename T>
+size_t one_block_estimates_scratch(int64_t l, int64_t n, const DeviceInfo& d) {
+  auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
+  return up((size_t)l * l * sizeof(T)) + up((size_t)l * n * sizeof(T)) + gemm_tn_scratch<T>(l, n, l, d.num_cu) + 1024;
+}
+
+template <typename T>
+hipError_t one_block_estimates(const T* B, int64_t l, int64_t n, const int64_t* S, const T* R11, int64_t ldr,
+                               const T* W, int64_t ldw, double* r, Arena& ar, const DeviceInfo& d, hipStream_t s) {
+  if (l < 1 || n < 1) return hipSuccess;
+  T* Gt = ar.take<T>((size_t)l * l);
+  T* Cm = ar.take<T>((size_t)l * n);
+  if (!Gt || !Cm) return hipErrorOutOfMemory;
+  const size_t lds = (size_t)l * sizeof(double);
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)right_trsm_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  right_trsm_kernel<T><<<(unsigned)l, NT, lds, s>>>(B, l, S, l, R11, ldr, Gt);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // C = G W, the sample of the projection of every column onto span(A(:, S))
+  if ((e = gemm_tn<T>(l, n, l, Gt, l, W, ldw, Cm, l, nullptr, ar, d.num_cu, s)) != hipSuccess) return e;
+  sample_resid_kernel<T><<<(unsigned)((n + NT - 1) / NT), NT, 0, s>>>(B, Cm, l, n, r);
+  return hipGetLastError();
+}
+
 #define INST(T)                                                                                                   \
+  template size_t one_block_estimates_scratch<T>(int64_t, int64_t, const DeviceInfo&);                           \
+  template hipError_t one_block_estimates<T>(const T*, int64_t, int64_t, const int64_t*, const T*, int64_t,       \
+                                             const T*, int64_t, double*, Arena&, const DeviceInfo&, hipStream_t); \
   template size_t trqrcp_scratch<T>(int64_t, int64_t, int64_t, int64_t, int64_t, const DeviceInfo&);             \
   template hipError_t trqrcp_select<T>(const T*, int64_t, int64_t, int64_t, int64_t, int64_t, int64_t, T*,       \
                                        int64_t*, double*, Arena&, unsigned*, const DeviceInfo&, hipStream_t,    \

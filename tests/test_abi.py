@@ -258,9 +258,13 @@ def test_est_norms_option_checks(lib):
     out = C.c_size_t(0)
     ws = lib.ffsrqr_workspace_size
     assert ws(1000, 800, 20, 10, C.byref(_lib.Opts(0, -1, 2.0, 16, 0, 1)), C.byref(out)) == 0
-    assert ws(1000, 800, 20, 10, C.byref(_lib.Opts(0, -1, 2.0, 0, 0, 1)), C.byref(out)) == 1   # needs block
-    assert b"est_norms" in lib.ffsrqr_last_error()
+    # the one-block selection: its sample update needs an l x n product in scratch
+    assert ws(1000, 800, 20, 10, C.byref(_lib.Opts(0, -1, 2.0, 0, 0, 0)), C.byref(out)) == 0
+    plain = out.value
+    assert ws(1000, 800, 20, 10, C.byref(_lib.Opts(0, -1, 2.0, 0, 0, 1)), C.byref(out)) == 0
+    assert out.value >= plain
     assert ws(1000, 800, 20, 10, C.byref(_lib.Opts(0, -1, 2.0, 16, 0, 2)), C.byref(out)) == 1
+    assert b"est_norms" in lib.ffsrqr_last_error()
     est = _lib.Opts(0, -1, 2.0, 0, 0, 1)
     assert lib.ffsrqr_rpca_workspace_size(500, 400, 10, 0, C.byref(est), C.byref(out)) == 1
 

@@ -1,12 +1,13 @@
-"""GPU parity of Algorithm 4's sample-estimated residual norms (opts.est_norms
-with the blocked selection) against the oracle on the same bytes:
+"""GPU parity of Algorithm 4's sample-estimated residual norms (opts.est_norms,
+with the blocked selection and with the one-block one) against the oracle on
+the same bytes:
 
 * whole solves with the same tests, swaps, identity rotations, pivots, j*,
   exact alpha and g2 as the oracle where each of the oracle's decisions is
   clear of its threshold (the two largest estimates, the two largest rho or
   probe values, g2 against g) by 1e-8 relative (FP64) or 1e-3 (FP32
   storage), and the final sigma within the form's bound;
-* the 8192 x 4096, l = 544 workload in the mixed form: the estimate-driven
+* the 8192 x 4096, l = 544 workload in the mixed form, both selections: the estimate-driven
   solve runs through the same kernels as the exact one; alpha is the exact
   residual norm of the chosen column (checked on the host against the
   returned Q), and when neither run swaps the factors are bit-identical.
@@ -43,6 +44,10 @@ CASES = {
     # m, n, decay, matrix seed, k, p, seed, g, block, g2_probe, max_swaps
     "swaps": (300, 200, 0.97, 5, 20, 6, 1, 1.05, 8, 0, 12),
     "identity_rotation": (60, 40, 0.9, 3, 6, 2, 1, 1.05, 4, 1, 30),
+    # the one-block selection (block 0): the l-row sketch updated with all
+    # l pivots as one block
+    "one_block_swaps": (300, 200, 0.97, 5, 20, 6, 1, 1.05, 0, 0, 12),
+    "one_block_identity": (60, 40, 0.9, 3, 6, 2, 1, 1.05, 0, 1, 30),
 }
 
 
@@ -70,7 +75,7 @@ def test_est_norms_factor_matches_oracle(ff, case, form):
           f"gpu: swaps {info['swaps']}, probes {info['probes']}; clear {ok}", flush=True)
     if form == "fp64":
         assert ok, "the FP64 cases are chosen to decide clearly"
-        assert ref.swaps >= 1 if case == "swaps" else idle >= 1
+        assert ref.swaps >= 1 if "swaps" in case else idle >= 1
     if ok:
         assert info["swaps"] == ref.swaps and info["flags"] == ref.flags
         assert info["probes"] == (ref.probes if d > 0 else 0)
@@ -84,18 +89,19 @@ def test_est_norms_factor_matches_oracle(ff, case, form):
         assert np.all(np.abs(sig - ref.sigma) <= tol * ref.sigma + floor * ref.sigma[0])
 
 
-def test_est_norms_l544_mixed(ff):
+@pytest.mark.parametrize("block", [32, 0])
+def test_est_norms_l544_mixed(ff, block):
     import torch
     w = synth.WORKLOADS["large_q"]
     announce(f"generate large_q {w.m}x{w.n}")
     A = dev_f(synth.make_workload("large_q"), torch.float32)
     res = {}
     for est in (False, True):
-        announce(f"factor large_q mixed block=32 est_norms={est}")
-        out = ff.factor(A, w.k, w.p, w.seed, mixed=True, block=32, est_norms=est)
+        announce(f"factor large_q mixed block={block} est_norms={est}")
+        out = ff.factor(A, w.k, w.p, w.seed, mixed=True, block=block, est_norms=est)
         torch.cuda.synchronize()
         res[est] = out
-        print(f"[gpu-case] est_norms={est}: swaps {out.info['swaps']}, jstar {out.info['jstar']}, "
+        print(f"[gpu-case] block={block} est_norms={est}: swaps {out.info['swaps']}, jstar {out.info['jstar']}, "
               f"alpha {out.info['alpha']:.6e}, g2 {out.info['g2']:.4f}", flush=True)
     info = res[True].info
     j = int(info["jstar"])
