@@ -62,10 +62,11 @@ def opts(precision=L.FP64, g: float = 2.0, max_swaps: int = -1, block: int = 0, 
                   est_norms=1 if est_norms else 0, reserved=0)
 
 
-def workspace_size(m: int, n: int, k: int, p: int, precision=L.FP64, block: int = 0) -> int:
+def workspace_size(m: int, n: int, k: int, p: int, precision=L.FP64, block: int = 0,
+                   est_norms: bool = False) -> int:
     lib = L.load()
     out = C.c_size_t(0)
-    o = opts(precision, block=block)
+    o = opts(precision, block=block, est_norms=est_norms)
     L.check(lib.ffsrqr_workspace_size(m, n, k, p, C.byref(o), C.byref(out)), "ffsrqr_workspace_size")
     return out.value
 
@@ -129,7 +130,7 @@ def factor(A: torch.Tensor, k: int, p: int, seed: int = 0, g: float = 2.0, max_s
     V = empty_fortran(n, l, A.dtype, dev)
     sigma = torch.empty(l, dtype=torch.float64, device=dev)
     if work is None:
-        work = workspace(workspace_size(m, n, k, p, prec, block), dev, stream)
+        work = workspace(workspace_size(m, n, k, p, prec, block, est_norms), dev, stream)
     info = L.Info()
     o = opts(prec, g, max_swaps, block, g2_probe, est_norms)
     L.check(lib.ffsrqr_factor(_ptr(A), m, n, lda, k, p, seed, _ptr(perm), _ptr(Q), m, _ptr(Lf), l,

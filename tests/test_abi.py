@@ -269,6 +269,16 @@ def test_est_norms_option_checks(lib):
     assert lib.ffsrqr_rpca_workspace_size(500, 400, 10, 0, C.byref(est), C.byref(out)) == 1
 
 
+def test_python_workspace_size_follows_the_options(lib):
+    # the binding sizes the workspace of a call with the options the call uses
+    from paper_1803_01982_amd import _lib, api
+    out = C.c_size_t(0)
+    for block, est in ((0, False), (0, True), (16, False), (16, True)):
+        o = _lib.Opts(0, -1, 2.0, block, 0, 1 if est else 0)
+        assert lib.ffsrqr_workspace_size(2000, 1500, 40, 10, C.byref(o), C.byref(out)) == 0
+        assert api.workspace_size(2000, 1500, 40, 10, block=block, est_norms=est) == out.value
+
+
 def test_drivers_refuse_the_blocked_selection(lib):
     from paper_1803_01982_amd import _lib
     out = C.c_size_t(0)
