@@ -43,19 +43,20 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def timed_solves(ff, torch, A, w, steps, warmup, mixed=False):
+def timed_solves(ff, torch, A, w, steps, warmup, mixed=False, **opts):
     """Warm up, then time `steps` solves one by one (each call returns after
     the stream is done).  Returns (last output, per-solve seconds, step
-    accounting accumulated over the timed solves)."""
+    accounting accumulated over the timed solves).  opts: options of the
+    SRQR test and the pivot selection (block, g2_probe, est_norms)."""
     for _ in range(warmup):
-        ff.factor(A, w.k, w.p, w.seed, mixed=mixed)
+        ff.factor(A, w.k, w.p, w.seed, mixed=mixed, **opts)
     torch.cuda.synchronize()
     ff.profile_enable(True)
     times = []
     out = None
     for _ in range(steps):
         t0 = time.perf_counter()
-        out = ff.factor(A, w.k, w.p, w.seed, mixed=mixed)
+        out = ff.factor(A, w.k, w.p, w.seed, mixed=mixed, **opts)
         times.append(time.perf_counter() - t0)
     torch.cuda.synchronize()
     prof = ff.profile_read()
@@ -216,6 +217,10 @@ def main():
                     help="median of 3 oracle runs plus a 1-thread run (several minutes)")
     ap.add_argument("--no-second-form", action="store_true")
     ap.add_argument("--no-mid", action="store_true")
+    # options of the first form (the defaults are the headline configuration)
+    ap.add_argument("--block", type=int, default=0, help="Algorithm 2's blocked selection, block size")
+    ap.add_argument("--g2-probe", type=int, default=0, help="Algorithm 4's random g2 estimate, probe rows")
+    ap.add_argument("--est-norms", action="store_true", help="Algorithm 4's sample-estimated residual norms")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -241,7 +246,8 @@ def main():
     torch.cuda.synchronize()
 
     log(f"{prec}: warmup {args.warmup}, timing {args.steps} solves")
-    out, times, prof = timed_solves(ff, torch, Ad, w, args.steps, args.warmup, mixed=prec == "mixed")
+    sopts = {"block": args.block, "g2_probe": args.g2_probe, "est_norms": args.est_norms}
+    out, times, prof = timed_solves(ff, torch, Ad, w, args.steps, args.warmup, mixed=prec == "mixed", **sopts)
     secs = float(np.sum(times))
     log(f"{prec}: {secs / args.steps * 1e3:.3f} ms per solve")
     del Ad
@@ -274,6 +280,9 @@ def main():
         "info": {k: out.info[k] for k in ("l", "swaps", "flags", "g2", "jstar", "jstar_margin", "min_margin",
                                           "jacobi_sweeps")},
     }
+    if args.block or args.g2_probe or args.est_norms:
+        result["config"]["srqr_options"] = sopts
+        result["info"]["probes"] = out.info["probes"]
     sig_gpu = out.sigma.cpu().numpy()
     perm_gpu = out.perm.cpu().numpy()
     result["accuracy"] = {"sigma_rel_err_vs_prescribed_spectrum_j<=k":
