@@ -126,7 +126,8 @@ size_t scratch_bytes(int64_t m, int64_t n, int64_t l, const DeviceInfo& d, int64
                      bool est = false) {
   size_t s = 0;
   if (block > 0) s = std::max(s, trqrcp_scratch<T>(m, n, l, block, p, d));
-  if (est && block <= 0) s = std::max(s, one_block_estimates_scratch<T>(l, n, d));
+  // the one-block estimates run on the side stream, next to a6 on the other
+  if (est && block <= 0) s = std::max(s, align256(tallqr_scratch<T>(n, l, d)) + one_block_estimates_scratch<T>(l, n, d));
   s = std::max(s, gemm_tn_scratch<T>(l, n, m, d.num_cu));
   if (sizeof(T) == 4) s = std::max(s, gemm_bf16_scratch(l, n, m, d.num_cu));
   s = std::max(s, qrcp_scratch<T>(l, n, d));
@@ -483,6 +484,9 @@ ffsrqr_status factor_impl(const T* A, int64_t m, int64_t n, int64_t lda, int64_t
   };
   bool lq_current = false;  // L, V, sigma belong to the current leading set
   bool redo = false;        // the next test runs on the same leading set (estimates: identity rotation)
+  T* ob_Bc = nullptr;       // one-block estimates: the copied sketch and B(:, S), pending on the side stream
+  T* ob_Bs = nullptr;
+  Arena ob_arena = a_side;
   int64_t removed_col = -1; // original index of the column the next swap removes
   unsigned herr[64];
   std::vector<int64_t> hS;
@@ -513,9 +517,12 @@ ffsrqr_status factor_impl(const T* A, int64_t m, int64_t n, int64_t lda, int64_t
       }
       if (est_mode && blk == 0 && l < n) {
         // Algorithm 4's estimates for the one-block selection: the l-row
-        // sketch (still in region2) updated with all l pivots as one block
-        Arena a = scratch();
-        FF_HIP(one_block_estimates<T>(region2, l, n, S, R11, l, W, l, est, a, d, s));
+        // sketch (still in region2, which a6 reuses) is copied to the side
+        // stream's scratch here, and updated there with all l pivots as one
+        // block before the SRQR test
+        Arena a = a_side;
+        FF_HIP(one_block_stage<T>(region2, l, n, S, &ob_Bc, &ob_Bs, a, s));
+        ob_arena = a;
       }
     } else if (!redo) {
       // Algorithm 4's swap as an update of Q, R11 and W (rotations, one new
@@ -538,6 +545,11 @@ ffsrqr_status factor_impl(const T* A, int64_t m, int64_t n, int64_t lda, int64_t
     {
       const int h = tm.begin(FFSRQR_STEP_RESID, side->stream);
       if (!est_mode) FF_HIP(residual_norms<T>(W, l, n, l, anorm2, gamma2, side->stream));
+      if (ob_Bc) {
+        Arena a = ob_arena;
+        FF_HIP(one_block_estimates<T>(ob_Bc, ob_Bs, l, n, R11, l, W, l, est, a, d, side->stream));
+        ob_Bc = nullptr;
+      }
       tm.end(h, side->stream);
     }
     {

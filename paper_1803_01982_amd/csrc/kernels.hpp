@@ -172,11 +172,17 @@ hipError_t sample_norms(const T* B, int64_t rows, int64_t n, double* r, hipStrea
 // The estimates for the one-block selection: r[c] = ||B(:, c) - G W(:, c)||^2
 // / l with G = B(:, S) R11^{-1}, i.e. the sample update of Algorithm 2 with
 // all l pivots as one block (B l x n, ldb = l; W = Q1^T A, l x n).
+// one_block_stage copies B (Bc) and gathers B(:, S) (Bs) from the arena, so
+// that the rest can run while B's buffer is reused; one_block_estimates then
+// forms r from them.
 template <typename T>
 size_t one_block_estimates_scratch(int64_t l, int64_t n, const DeviceInfo& d);
 template <typename T>
-hipError_t one_block_estimates(const T* B, int64_t l, int64_t n, const int64_t* S, const T* R11, int64_t ldr,
-                               const T* W, int64_t ldw, double* r, Arena& ar, const DeviceInfo& d, hipStream_t s);
+hipError_t one_block_stage(const T* B, int64_t l, int64_t n, const int64_t* S, T** Bc, T** Bs, Arena& ar,
+                           hipStream_t s);
+template <typename T>
+hipError_t one_block_estimates(const T* Bc, const T* Bs, int64_t l, int64_t n, const T* R11, int64_t ldr, const T* W,
+                               int64_t ldw, double* r, Arena& ar, const DeviceInfo& d, hipStream_t s);
 // est[st->jstar] = st->alpha^2 (the estimate of j* after an identity rotation)
 hipError_t est_reset_jstar(double* est, const SrqrState* st, hipStream_t s);
 

@@ -44,15 +44,15 @@ __global__ void sample_norms_kernel(const T* __restrict__ B, int64_t rows, int64
   r[c] = acc / (double)rows;
 }
 
-// Row i of G = B(:, S) R11^{-1} (l x l) by forward substitution on the row
-// vector (g R11 = B(i, S)), FP64, written as column i of Gt (Gt = G^T):
-// g_j = b_j / R11(j, j), then b_k -= g_j R11(j, k) for k > j.
+// Row i of G = Bs R11^{-1} (l x l, Bs = B(:, S)) by forward substitution on
+// the row vector (g R11 = Bs(i, :)), FP64, written as column i of Gt
+// (Gt = G^T): g_j = b_j / R11(j, j), then b_k -= g_j R11(j, k) for k > j.
 template <typename T>
-__global__ void right_trsm_kernel(const T* __restrict__ B, int64_t ldb, const int64_t* __restrict__ S, int64_t l,
-                                  const T* __restrict__ R11, int64_t ldr, T* __restrict__ Gt) {
+__global__ void right_trsm_kernel(const T* __restrict__ Bs, int64_t l, const T* __restrict__ R11, int64_t ldr,
+                                  T* __restrict__ Gt) {
   extern __shared__ double bsh[];  // l
   const int64_t i = blockIdx.x;
-  for (int64_t j = threadIdx.x; j < l; j += NT) bsh[j] = (double)B[S[j] * ldb + i];
+  for (int64_t j = threadIdx.x; j < l; j += NT) bsh[j] = (double)Bs[j * l + i];
   for (int64_t j = 0; j < l; ++j) {
     __syncthreads();
     const double g = bsh[j] / (double)R11[j * ldr + j];
@@ -61,18 +61,22 @@ __global__ void right_trsm_kernel(const T* __restrict__ B, int64_t ldb, const in
   }
 }
 
-// r[c] = ||B(:, c) - C(:, c)||^2 / rows (FP64), one thread per column
+// r[c] = ||B(:, c) - C(:, c)||^2 / rows (FP64), one wave per column
+// (the lanes read the column's contiguous rows, then a fixed-order wave sum)
 template <typename T>
 __global__ void sample_resid_kernel(const T* __restrict__ B, const T* __restrict__ Cm, int64_t rows, int64_t n,
                                     double* __restrict__ r) {
-  const int64_t c = (int64_t)blockIdx.x * NT + threadIdx.x;
+  const int64_t c = (int64_t)blockIdx.x * (NT / kWave) + threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
   if (c >= n) return;
   double acc = 0.0;
-  for (int64_t i = 0; i < rows; ++i) {
+  for (int64_t i = lane; i < rows; i += kWave) {
     const double v = (double)B[c * rows + i] - (double)Cm[c * rows + i];
     acc = fma(v, v, acc);
   }
-  r[c] = acc / (double)rows;
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
+  if (lane == 0) r[c] = acc / (double)rows;
 }
 
 template <typename T>
@@ -269,12 +273,24 @@ hipError_t sample_norms(const T* B, int64_t rows, int64_t n, double* r, hipStrea
 template <typename T>
 size_t one_block_estimates_scratch(int64_t l, int64_t n, const DeviceInfo& d) {
   auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
-  return up((size_t)l * l * sizeof(T)) + up((size_t)l * n * sizeof(T)) + gemm_tn_scratch<T>(l, n, l, d.num_cu) + 1024;
+  return 2 * up((size_t)l * l * sizeof(T)) + 2 * up((size_t)l * n * sizeof(T)) +
+         gemm_tn_scratch<T>(l, n, l, d.num_cu) + 1024;
 }
 
 template <typename T>
-hipError_t one_block_estimates(const T* B, int64_t l, int64_t n, const int64_t* S, const T* R11, int64_t ldr,
-                               const T* W, int64_t ldw, double* r, Arena& ar, const DeviceInfo& d, hipStream_t s) {
+hipError_t one_block_stage(const T* B, int64_t l, int64_t n, const int64_t* S, T** Bc, T** Bs, Arena& ar,
+                           hipStream_t s) {
+  *Bc = ar.take<T>((size_t)l * n);
+  *Bs = ar.take<T>((size_t)l * l);
+  if (!*Bc || !*Bs) return hipErrorOutOfMemory;
+  hipError_t e = hipMemcpyAsync(*Bc, B, (size_t)l * n * sizeof(T), hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return e;
+  return gather_cols<T>(B, l, n, l, S, l, *Bs, l, s);
+}
+
+template <typename T>
+hipError_t one_block_estimates(const T* Bc, const T* Bs, int64_t l, int64_t n, const T* R11, int64_t ldr, const T* W,
+                               int64_t ldw, double* r, Arena& ar, const DeviceInfo& d, hipStream_t s) {
   if (l < 1 || n < 1) return hipSuccess;
   T* Gt = ar.take<T>((size_t)l * l);
   T* Cm = ar.take<T>((size_t)l * n);
@@ -285,19 +301,21 @@ hipError_t one_block_estimates(const T* B, int64_t l, int64_t n, const int64_t* 
                                        (int)lds);
     if (e != hipSuccess) return e;
   }
-  right_trsm_kernel<T><<<(unsigned)l, NT, lds, s>>>(B, l, S, l, R11, ldr, Gt);
+  right_trsm_kernel<T><<<(unsigned)l, NT, lds, s>>>(Bs, l, R11, ldr, Gt);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   // C = G W, the sample of the projection of every column onto span(A(:, S))
   if ((e = gemm_tn<T>(l, n, l, Gt, l, W, ldw, Cm, l, nullptr, ar, d.num_cu, s)) != hipSuccess) return e;
-  sample_resid_kernel<T><<<(unsigned)((n + NT - 1) / NT), NT, 0, s>>>(B, Cm, l, n, r);
+  constexpr int CPB = NT / kWave;  // columns per block
+  sample_resid_kernel<T><<<(unsigned)((n + CPB - 1) / CPB), NT, 0, s>>>(Bc, Cm, l, n, r);
   return hipGetLastError();
 }
 
 #define INST(T)                                                                                                   \
   template size_t one_block_estimates_scratch<T>(int64_t, int64_t, const DeviceInfo&);                           \
-  template hipError_t one_block_estimates<T>(const T*, int64_t, int64_t, const int64_t*, const T*, int64_t,       \
-                                             const T*, int64_t, double*, Arena&, const DeviceInfo&, hipStream_t); \
+  template hipError_t one_block_stage<T>(const T*, int64_t, int64_t, const int64_t*, T**, T**, Arena&, hipStream_t); \
+  template hipError_t one_block_estimates<T>(const T*, const T*, int64_t, int64_t, const T*, int64_t, const T*,     \
+                                             int64_t, double*, Arena&, const DeviceInfo&, hipStream_t);             \
   template size_t trqrcp_scratch<T>(int64_t, int64_t, int64_t, int64_t, int64_t, const DeviceInfo&);             \
   template hipError_t trqrcp_select<T>(const T*, int64_t, int64_t, int64_t, int64_t, int64_t, int64_t, T*,       \
                                        int64_t*, double*, Arena&, unsigned*, const DeviceInfo&, hipStream_t,    \
