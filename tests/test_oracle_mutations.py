@@ -13,8 +13,10 @@ import pytest
 import oracle
 import test_oracle_alg9 as ALG9
 import test_oracle_bf16 as BF16
+import test_oracle_est_norms as EST
 import test_oracle_linalg as LIN
 import test_oracle_path as PATH
+import test_oracle_probe as PROBE
 
 MOD = sys.modules["oracle.ffsrqr"]
 
@@ -33,6 +35,14 @@ def _small():
     w = synth.WORKLOADS["small_fp64"]
     A = synth.make_workload("small_fp64")
     return w, A, oracle.ffsrqr(A, w.k, w.p, w.seed)
+
+
+def _kahan_state():
+    """The state of the probe pins' fixture: an SRQR test on a Kahan matrix."""
+    A = np.vstack([PROBE.kahan(48), np.zeros((6, 48))])
+    r = oracle.ffsrqr(A, 20, 0, seed=0, max_swaps=0)
+    S = list(r.perm[:20])
+    return A, S, PROBE._test_state(A, S)
 
 
 def _pins():
@@ -58,6 +68,16 @@ def _pins():
         ("alg9_lapack", ALG9.test_alg9_sigma_matches_lapack_and_factors_are_consistent),
         ("alg9_full_rank", ALG9.test_alg9_at_full_rank_is_the_svd_of_A),
         ("jstar_margin", ALG9.test_jstar_margin_on_orthogonal_columns),
+        # Algorithm 4's random g2 estimate and sample-estimated residual norms
+        ("probe_stream", PROBE.test_probe_stream_is_standard_normal_and_apart_from_the_sketch),
+        ("probe_orthogonal", lambda: [PROBE.test_orthogonal_probe_gives_the_exact_rho(l) for l in (1, 7, 20)]),
+        ("est_sample", lambda: EST.test_final_sample_is_omega_times_the_residual(4, 2)),
+        ("est_one_block_sample", EST.test_one_block_sample_update_is_omega_times_the_residual),
+        ("est_carry", EST.test_estimate_errors_are_carried_exactly_through_the_swaps),
+        ("est_carry_one_block", EST.test_one_block_estimates_carry_their_errors_through_the_swaps),
+        ("probe_loop", PROBE.test_probe_loop_swaps_follow_the_determinant_identity),
+        ("probe_identity", PROBE.test_identity_rotation_draws_a_fresh_probe_and_counts_toward_the_cap),
+        ("probe_unbiased", lambda: PROBE.test_probe_estimate_is_unbiased_over_the_probe_streams(_kahan_state())),
     ]
     for name, fn in checks:
         try:
@@ -112,6 +132,19 @@ MUTANTS = [
     ("alg9", "U = Qt @ UR[:, :k]", "U = Qt[:, :k]"),
     ("alg9", "Vk = res.V @ VR[:, :k]", "Vk = res.V @ UR[:, :k]"),
     ("residual_margin", "return float((g2[-1] - g2[-2]) / g2[-1])", "return float((g2[-1] - g2[0]) / g2[-1])"),
+    # the random g2 estimate
+    ("g2_probe_estimate", "return abs(alpha) / math.sqrt(d) *", "return abs(alpha) / d *"),
+    ("g2_probe_estimate", "Y = Om @ upper_inverse(Rt).T", "Y = Om @ upper_inverse(Rt)"),
+    ("g2_probe_estimate", "Rt[:l, l] = a", "Rt[:l, l] = 0.0 * a"),
+    ("probe_omega", "return _omega(seed, d, l + 1, stream=q)", "return _omega(seed, d, l + 1, stream=q - 1)"),
+    ("ffsrqr", "istar = int(np.argmax(est))", "istar = int(np.argmax(est[:l]))"),
+    # the sample-estimated residual norms
+    ("trqrcp_pivots", "B[:, rest] = B[:, rest] - B[:, piv] @ X", "B[:, rest] = B[:, rest] - 0.0 * (B[:, piv] @ X)"),
+    ("sample_update", "out[:, c] = B[:, c] - B[:, S] @ back_substitute(R11, W[:, c])",
+     "out[:, c] = B[:, c] + B[:, S] @ back_substitute(R11, W[:, c])"),
+    ("row_l1", "return Qx[:, -1] @ A", "return Qx[:, 0] @ A"),
+    ("ffsrqr", "r = r - row_l1(Af, S, jstar) ** 2", "r = r + row_l1(Af, S, jstar) ** 2"),
+    ("ffsrqr", "r[removed] = row[removed] ** 2", "r[removed] = r[removed]"),
 ]
 
 
