@@ -157,3 +157,29 @@ def test_jacobi_matches_lapack_svd(shape, kind):
     r = int(keep.sum())
     assert np.linalg.norm(M @ V[:, :r] - U[:, :r] * sig[:r]) < 1e-13 * ref[0]
     assert np.linalg.norm(V.T @ V - np.eye(shape[1])) < 1e-13
+
+
+@pytest.mark.parametrize("rows,n,l,seed", [(40, 300, 40, 1), (25, 120, 20, 2), (60, 61, 60, 3)])
+def test_qrcp_margins_match_projection_residuals(rows, n, l, seed):
+    """Independent pin of the QRCP margins: at step j the trailing column
+    norms of partial QRCP are the squared residuals of the unchosen columns of
+    B against the span of the j chosen ones, computed here by LAPACK QR of
+    B(:, chosen) and a projection; the step's pivot is their argmax and its
+    margin (r_max - r_2nd) / r_max."""
+    rng = np.random.default_rng(seed)
+    B = rng.standard_normal((rows, n)) * rng.uniform(0.5, 2.0, size=n)
+    perm, margins, _ = oracle.qrcp_sketch(B, l)
+    for j in range(l):
+        chosen = list(perm[:j])
+        rest = [c for c in range(n) if c not in set(chosen)]
+        X = B[:, rest]
+        if chosen:
+            Q, _ = np.linalg.qr(B[:, chosen])
+            X = X - Q @ (Q.T @ X)
+            X = X - Q @ (Q.T @ X)
+        r = np.sum(X * X, axis=0)
+        order = np.argsort(-r, kind="stable")
+        assert rest[order[0]] == perm[j]
+        if len(rest) > 1:
+            ref = (r[order[0]] - r[order[1]]) / r[order[0]]
+            assert abs(margins[j] - ref) <= 1e-9 * max(ref, 1e-3), (j, margins[j], ref)

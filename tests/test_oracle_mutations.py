@@ -53,6 +53,7 @@ def _pins():
         ("qr_lapack", lambda: [LIN.test_householder_qr_matches_lapack(s) for s in ((50, 13), (300, 40))]),
         ("qrcp_dgeqp3", lambda: LIN.test_qrcp_pivots_match_dgeqp3(3, (20, 300), 20)),
         ("qrcp_ties", LIN.test_qrcp_ties_go_to_smallest_index),
+        ("qrcp_margins", lambda: LIN.test_qrcp_margins_match_projection_residuals(25, 120, 20, 2)),
         ("rho_closed_form", LIN.test_srqr_rho_matches_block_inverse_closed_form),
         ("backsub", LIN.test_upper_inverse_and_back_substitution),
         ("jacobi_2x2", LIN.test_jacobi_2x2_closed_form),
@@ -98,6 +99,8 @@ MUTANTS = [
     ("qrcp_sketch", "s = int(cands[np.argmin(perm[j + cands])])", "s = int(cands[np.argmax(perm[j + cands])])"),
     ("qrcp_sketch", "B[j:, j + 1:] -= tau * np.outer(v, w)", "B[j:, j + 1:] -= np.outer(v, w)"),
     ("qrcp_sketch", "perm[[j, j + s]] = perm[[j + s, j]]", "perm[[j, j + s]] = perm[[j, j + s]]"),
+    ("qrcp_sketch", "margins[j] = (rmax - rest.max()) / rmax", "margins[j] = (rmax - rest.min()) / rmax"),
+    ("qrcp_sketch", "margins[j] = (rmax - rest.max()) / rmax", "margins[j] = (rmax - rest.max()) / rest.max()"),
     # Householder QR of the panel
     ("householder_qr", "W[j:, j + 1:] -= tau * np.outer(v, v @ W[j:, j + 1:])",
      "W[j:, j + 1:] -= 0.5 * tau * np.outer(v, v @ W[j:, j + 1:])"),
